@@ -1,0 +1,278 @@
+"""FP64 CPU oracle for the Gaussian-primitive path tracer -- TEST INFRASTRUCTURE.
+
+This package is the plain, slow reference the GPU library is checked against.
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import it.  It shares no code with the HIP library and never
+calls it; the product path must not import it.
+
+The arithmetic lives in ``ugp_oracle.c`` (double precision, libm, pthreads);
+this module only compiles it with gcc and marshals numpy arrays through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ugp_oracle.c")
+_LIB = os.path.join(_HERE, "liborc.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle into ``oracle/liborc.so`` (gcc, -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
+               "-Wno-unused-parameter", "-D_GNU_SOURCE", _SRC, "-o", tmp, "-lm", "-lpthread"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Camera(C.Structure):
+    _fields_ = [("origin", C.c_double * 3), ("target", C.c_double * 3), ("up", C.c_double * 3),
+                ("vfov_deg", C.c_double), ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("spp", C.c_int32), ("max_depth", C.c_int32), ("seed", C.c_uint64),
+                ("sample_offset", C.c_int64), ("env_radiance", C.c_double * 3),
+                ("mis_mode", C.c_int32)]
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct)) if a is not None else None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        vp = C.c_void_p
+        L.orc_scene_create.argtypes = [C.c_int64] + [vp] * 8 + [C.c_double, C.POINTER(vp)]
+        L.orc_scene_destroy.argtypes = [vp]
+        L.orc_scene_build_bvh.argtypes = [vp]
+        L.orc_cutoff_radius.argtypes = [vp]
+        L.orc_cutoff_radius.restype = C.c_double
+        L.orc_prim_frame.argtypes = [vp, C.c_int64, vp, vp, vp, vp]
+        L.orc_chord.argtypes = [vp, C.c_int64, vp, vp]
+        L.orc_ray_integral.argtypes = [vp, C.c_int64, vp, C.c_double, C.c_double]
+        L.orc_ray_integral.restype = C.c_double
+        L.orc_transmittance.argtypes = [vp, C.c_int64, vp, vp, C.c_int, vp, vp]
+        L.orc_saturation.argtypes = [vp, C.c_int64, vp, vp, C.c_int, vp]
+        L.orc_sample_collision.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_int, vp, vp, vp, vp, vp]
+        L.orc_emitter_query.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_int, vp]
+        L.orc_phase_eval.argtypes = [C.c_int, vp, C.c_double, vp, vp, vp, vp, vp]
+        L.orc_phase_sample.argtypes = [C.c_int, vp, C.c_double, vp, vp, C.c_double, C.c_double,
+                                       vp, vp, vp]
+        L.orc_render.argtypes = [vp, C.POINTER(_Camera), C.POINTER(_Params), C.c_int64, vp,
+                                 C.c_int, vp, vp]
+        L.orc_render.restype = C.c_int64
+        L.orc_path_radiance.argtypes = [vp, C.POINTER(_Camera), C.POINTER(_Params), C.c_uint32,
+                                        C.c_uint32, vp]
+        L.orc_philox4x32_10.argtypes = [vp, vp, vp]
+        L.orc_philox4x64_10.argtypes = [vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _addr(a):
+    return None if a is None else a.ctypes.data
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_addr(c), _addr(k), _addr(out))
+    return out
+
+
+def philox4x64_10(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    lib().orc_philox4x64_10(_addr(c), _addr(k), _addr(out))
+    return out
+
+
+def _rays(rays):
+    r = np.ascontiguousarray(rays, dtype=np.float32)
+    assert r.ndim == 2 and r.shape[1] == 8
+    return r
+
+
+def _excl(exclude, n):
+    if exclude is None:
+        return None
+    e = np.ascontiguousarray(exclude, dtype=np.int32)
+    assert e.shape == (n,)
+    return e
+
+
+class Scene:
+    """A scene held by the oracle (widened to float64 inside)."""
+
+    def __init__(self, scene: dict, eps: float = 0.01, bvh: bool = True):
+        self._keep = {}
+        n = int(np.asarray(scene["mean"]).shape[0])
+        fields = [("mean", np.float32, 3), ("scale", np.float32, 3), ("rotation", np.float32, 4),
+                  ("density", np.float32, 1), ("albedo", np.float32, 3),
+                  ("roughness", np.float32, 1), ("emission", np.float32, 3),
+                  ("material", np.int32, 1)]
+        ptrs = []
+        for name, dt, w in fields:
+            a = np.ascontiguousarray(scene[name], dtype=dt).reshape(n, w) if n else np.zeros((0, w), dt)
+            self._keep[name] = a
+            ptrs.append(_addr(a) if n else None)
+        h = C.c_void_p()
+        rc = lib().orc_scene_create(n, *ptrs, float(eps), C.byref(h))
+        if rc != 0:
+            raise ValueError("oracle rejected the scene")
+        self.h = h
+        self.n = n
+        self.use_bvh = 0
+        if bvh:
+            lib().orc_scene_build_bvh(self.h)
+            self.use_bvh = 1
+
+    def __del__(self):
+        try:
+            lib().orc_scene_destroy(self.h)
+        except Exception:
+            pass
+
+    @property
+    def cutoff_radius(self) -> float:
+        return lib().orc_cutoff_radius(self.h)
+
+    def prim_frame(self, k: int):
+        M = np.zeros(9); n = np.zeros(3); lo = np.zeros(3); hi = np.zeros(3)
+        lib().orc_prim_frame(self.h, int(k), _addr(M), _addr(n), _addr(lo), _addr(hi))
+        return M.reshape(3, 3), n, lo, hi
+
+    def chord(self, k: int, ray):
+        r = np.ascontiguousarray(ray, dtype=np.float32).reshape(8)
+        out = np.zeros(2)
+        hit = lib().orc_chord(self.h, int(k), _addr(r), _addr(out))
+        return (float(out[0]), float(out[1])) if hit else None
+
+    def ray_integral(self, k: int, ray, x: float, y: float) -> float:
+        r = np.ascontiguousarray(ray, dtype=np.float64).reshape(8)
+        return lib().orc_ray_integral(self.h, int(k), _addr(r), float(x), float(y))
+
+    def transmittance(self, rays, exclude=None, use_bvh=None):
+        r = _rays(rays)
+        n = r.shape[0]
+        e = _excl(exclude, n)
+        F = np.zeros(n); T = np.zeros(n)
+        ub = self.use_bvh if use_bvh is None else int(use_bvh)
+        lib().orc_transmittance(self.h, n, _addr(r), _addr(e), ub, _addr(F), _addr(T))
+        return F, T
+
+    def saturation(self, rays, exclude=None, use_bvh=None):
+        r = _rays(rays)
+        n = r.shape[0]
+        e = _excl(exclude, n)
+        t = np.zeros(n)
+        ub = self.use_bvh if use_bvh is None else int(use_bvh)
+        lib().orc_saturation(self.h, n, _addr(r), _addr(e), ub, _addr(t))
+        return t
+
+    def sample_collision(self, rays, u, exclude=None, use_bvh=None):
+        r = _rays(rays)
+        n = r.shape[0]
+        e = _excl(exclude, n)
+        uu = np.ascontiguousarray(u, dtype=np.float64)
+        assert uu.shape == (n,)
+        prim = np.zeros(n, dtype=np.int32)
+        t = np.zeros(n); F = np.zeros(n); ts = np.zeros(n); mg = np.zeros(n)
+        ub = self.use_bvh if use_bvh is None else int(use_bvh)
+        lib().orc_sample_collision(self.h, n, _addr(r), _addr(e), _addr(uu), ub, _addr(prim),
+                                   _addr(t), _addr(F), _addr(ts), _addr(mg))
+        return {"prim": prim, "t": t, "F": F, "tsat": ts, "margin": mg}
+
+    def emitter_query(self, rays, target, exclude=None, use_bvh=None):
+        r = _rays(rays)
+        n = r.shape[0]
+        e = _excl(exclude, n)
+        tg = np.ascontiguousarray(target, dtype=np.int32)
+        L = np.zeros(n)
+        ub = self.use_bvh if use_bvh is None else int(use_bvh)
+        lib().orc_emitter_query(self.h, n, _addr(r), _addr(e), _addr(tg), ub, _addr(L))
+        return L
+
+    def render(self, cam: dict, params: dict, pixels=None, nthreads: int | None = None):
+        c = make_camera(cam)
+        p = make_params(params)
+        W, H = int(cam["width"]), int(cam["height"])
+        if pixels is None:
+            npix, pp = W * H, None
+        else:
+            pp = np.ascontiguousarray(pixels, dtype=np.int64)
+            npix = pp.shape[0]
+        s = np.zeros((npix, 3)); s2 = np.zeros((npix, 3))
+        nt = nthreads or os.cpu_count() or 1
+        rays = lib().orc_render(self.h, C.byref(c), C.byref(p), npix, _addr(pp), int(nt),
+                                _addr(s), _addr(s2))
+        return s, s2, int(rays)
+
+    def path_radiance(self, cam: dict, params: dict, pixel: int, sample: int):
+        c = make_camera(cam)
+        p = make_params(params)
+        L = np.zeros(3)
+        lib().orc_path_radiance(self.h, C.byref(c), C.byref(p), int(pixel), int(sample), _addr(L))
+        return L
+
+
+def make_camera(cam: dict) -> _Camera:
+    c = _Camera()
+    for i in range(3):
+        c.origin[i] = float(cam["origin"][i])
+        c.target[i] = float(cam["target"][i])
+        c.up[i] = float(cam["up"][i])
+    c.vfov_deg = float(cam["vfov_deg"])
+    c.width = int(cam["width"])
+    c.height = int(cam["height"])
+    return c
+
+
+def make_params(p: dict) -> _Params:
+    q = _Params()
+    q.spp = int(p.get("spp", 1))
+    q.max_depth = int(p.get("max_depth", 4))
+    q.seed = int(p.get("seed", 0))
+    q.sample_offset = int(p.get("sample_offset", 0))
+    env = p.get("env_radiance", (0.0, 0.0, 0.0))
+    for i in range(3):
+        q.env_radiance[i] = float(env[i])
+    q.mis_mode = int(p.get("mis_mode", 0))
+    return q
+
+
+def phase_eval(mat, albedo, rough, normal, wo, wi):
+    a = np.ascontiguousarray(albedo, dtype=np.float64)
+    n = np.ascontiguousarray(normal, dtype=np.float64)
+    o = np.ascontiguousarray(wo, dtype=np.float64)
+    i = np.ascontiguousarray(wi, dtype=np.float64)
+    f = np.zeros(3)
+    pdf = np.zeros(1)
+    lib().orc_phase_eval(int(mat), _addr(a), float(rough), _addr(n), _addr(o), _addr(i), _addr(f),
+                         _addr(pdf))
+    return f, float(pdf[0])
+
+
+def phase_sample(mat, albedo, rough, normal, wo, u1, u2):
+    a = np.ascontiguousarray(albedo, dtype=np.float64)
+    n = np.ascontiguousarray(normal, dtype=np.float64)
+    o = np.ascontiguousarray(wo, dtype=np.float64)
+    wi = np.zeros(3); w = np.zeros(3); pdf = np.zeros(1)
+    lib().orc_phase_sample(int(mat), _addr(a), float(rough), _addr(n), _addr(o), float(u1),
+                           float(u2), _addr(wi), _addr(w), _addr(pdf))
+    return wi, w, float(pdf[0])

@@ -1,0 +1,1003 @@
+/*
+ * ugp_oracle.c -- FP64 CPU oracle for Monte Carlo path tracing of scenes made of
+ * linear-transmittance Gaussian primitives.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the slow, plain reference that the GPU
+ * library is checked against.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load it.  It shares no source, header, table
+ * or helper with the HIP library, and it never calls it.
+ *
+ * Source: "Unified Gaussian Primitives for Scene Representation and Rendering"
+ * (arXiv 2406.09733).  Each routine names the section / equation it follows.
+ * Where the paper is silent or garbled the adopted reading is stated inline.
+ *
+ * Everything is double precision.  Inputs arrive as the same float32 values the
+ * GPU receives and are widened exactly.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "ugp_oracle.h"
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10 and Philox4x64-10 counter-based generators, written from the */
+/* definition in Salmon, Moraes, Dror and Shaw, "Parallel random numbers: as  */
+/* easy as 1, 2, 3" (SC'11): N rounds of (multiply-hi/lo S-box, word          */
+/* permutation, xor with a round key), the key bumped by a Weyl sequence      */
+/* between rounds.                                                            */
+/* ------------------------------------------------------------------------- */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += W0; k1 += W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+    uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        unsigned __int128 p0 = (unsigned __int128)M0 * c0;
+        unsigned __int128 p1 = (unsigned __int128)M1 * c2;
+        uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        uint64_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += W0; k1 += W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Four uniforms in [0,1) from one counter: the top 24 bits of each word. */
+static void rng4(uint64_t seed, uint32_t pixel, uint32_t sample, uint32_t vertex, uint32_t group,
+                 double u[4]) {
+    uint32_t ctr[4] = {pixel, sample, vertex, group};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t x[4];
+    orc_philox4x32_10(ctr, key, x);
+    for (int i = 0; i < 4; ++i) u[i] = (double)(x[i] >> 8) * (1.0 / 16777216.0);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Small vector helpers.                                                      */
+/* ------------------------------------------------------------------------- */
+static double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static void cross3(const double a[3], const double b[3], double c[3]) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+static void normalize3(double a[3]) {
+    double l = sqrt(dot3(a, a));
+    a[0] /= l; a[1] /= l; a[2] /= l;
+}
+
+/* Orthonormal basis (b1, b2, n) around a unit vector n: Duff, Burgess,
+ * Christensen, Hery, Kensler, Liani, Villemin, "Building an Orthonormal Basis,
+ * Revisited" (JCGT 2017). */
+static void onb(const double n[3], double b1[3], double b2[3]) {
+    double sign = n[2] >= 0.0 ? 1.0 : -1.0;
+    double a = -1.0 / (sign + n[2]);
+    double b = n[0] * n[1] * a;
+    b1[0] = 1.0 + sign * n[0] * n[0] * a; b1[1] = sign * b; b1[2] = -sign * n[0];
+    b2[0] = b; b2[1] = sign + n[1] * n[1] * a; b2[2] = -n[1];
+}
+
+/* ------------------------------------------------------------------------- */
+/* Scene: the primitives of Sec. 3.1 / Sec. 4 with the cut-off of            */
+/* eq. (cutoff_threshold).                                                    */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t left, right; /* children (internal) or -1 */
+    int32_t first, count; /* primitive range in perm (leaf) */
+    double lo[3], hi[3];
+} onode;
+
+struct orc_scene {
+    int64_t n;
+    double r;      /* Mahalanobis radius of the cut-off ellipsoid */
+    double *mu;    /* [n][3] mean */
+    double *M;     /* [n][9] row-major S^-1 R^T: world offset -> unit-Gaussian frame */
+    double *d;     /* [n] peak density G(mu) */
+    double *nrm;   /* [n][3] R e_argmin(s): the facet normal of the delta NDF */
+    double *alb;   /* [n][3] */
+    double *rough; /* [n] */
+    double *emis;  /* [n][3] */
+    int32_t *mat;  /* [n] 0 Lambert, 1 GGX */
+    double *lo, *hi;  /* [n][3] axis-aligned box of the cut-off ellipsoid */
+    double *rsph;  /* [n] radius of the bounding sphere, r * max(s) */
+    int64_t *emitters;
+    int64_t n_emit;
+    /* acceleration structure: a plain median-split BVH, used only to find the
+       candidate set; results are independent of it (checked against brute force) */
+    onode *nodes;
+    int64_t n_nodes;
+    int64_t *perm;
+};
+
+/* Primitive set-up (Sec. 3.1, eq. covariance_decomposition): unit quaternion
+ * (w,x,y,z) -> rotation R; Sigma = (R S)(R S)^T, so the map that sends the
+ * Gaussian to the unit isotropic one is M = S^-1 R^T.  The cut-off ellipsoid of
+ * eq. (cutoff_threshold) is |M (x - mu)| = r with r = sqrt(-2 ln eps). */
+int orc_scene_create(int64_t n, const float *mean, const float *scale, const float *rotation,
+                     const float *density, const float *albedo, const float *roughness,
+                     const float *emission, const int32_t *material, double eps,
+                     orc_scene **out) {
+    if (n < 0 || !out || !(eps > 0.0 && eps < 1.0)) return 1;
+    orc_scene *S = (orc_scene *)calloc(1, sizeof(orc_scene));
+    S->n = n;
+    S->r = sqrt(-2.0 * log(eps));
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    S->mu = (double *)malloc(sizeof(double) * 3 * nn);
+    S->M = (double *)malloc(sizeof(double) * 9 * nn);
+    S->d = (double *)malloc(sizeof(double) * nn);
+    S->nrm = (double *)malloc(sizeof(double) * 3 * nn);
+    S->alb = (double *)malloc(sizeof(double) * 3 * nn);
+    S->rough = (double *)malloc(sizeof(double) * nn);
+    S->emis = (double *)malloc(sizeof(double) * 3 * nn);
+    S->mat = (int32_t *)malloc(sizeof(int32_t) * nn);
+    S->lo = (double *)malloc(sizeof(double) * 3 * nn);
+    S->hi = (double *)malloc(sizeof(double) * 3 * nn);
+    S->rsph = (double *)malloc(sizeof(double) * nn);
+    S->emitters = (int64_t *)malloc(sizeof(int64_t) * nn);
+    S->n_emit = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        double qw = rotation[4 * k + 0], qx = rotation[4 * k + 1], qy = rotation[4 * k + 2],
+               qz = rotation[4 * k + 3];
+        double ql = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+        qw /= ql; qx /= ql; qy /= ql; qz /= ql;
+        double R[3][3] = {
+            {1.0 - 2.0 * (qy * qy + qz * qz), 2.0 * (qx * qy - qw * qz), 2.0 * (qx * qz + qw * qy)},
+            {2.0 * (qx * qy + qw * qz), 1.0 - 2.0 * (qx * qx + qz * qz), 2.0 * (qy * qz - qw * qx)},
+            {2.0 * (qx * qz - qw * qy), 2.0 * (qy * qz + qw * qx), 1.0 - 2.0 * (qx * qx + qy * qy)}};
+        double s[3] = {scale[3 * k + 0], scale[3 * k + 1], scale[3 * k + 2]};
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) S->M[9 * k + 3 * i + j] = R[j][i] / s[i];
+        int m = 0;
+        if (s[1] < s[m]) m = 1;
+        if (s[2] < s[m]) m = 2;
+        for (int j = 0; j < 3; ++j) S->nrm[3 * k + j] = R[j][m];
+        double smax = fmax(s[0], fmax(s[1], s[2]));
+        S->rsph[k] = S->r * smax;
+        for (int j = 0; j < 3; ++j) {
+            double h2 = 0.0;
+            for (int i = 0; i < 3; ++i) h2 += (R[j][i] * s[i]) * (R[j][i] * s[i]);
+            double h = S->r * sqrt(h2);
+            S->mu[3 * k + j] = mean[3 * k + j];
+            /* a relative 1e-12 widening keeps the box conservative under rounding */
+            S->lo[3 * k + j] = mean[3 * k + j] - h * (1.0 + 1e-12) - 1e-300;
+            S->hi[3 * k + j] = mean[3 * k + j] + h * (1.0 + 1e-12) + 1e-300;
+            S->alb[3 * k + j] = albedo[3 * k + j];
+            S->emis[3 * k + j] = emission[3 * k + j];
+        }
+        S->d[k] = density[k];
+        S->rough[k] = roughness[k];
+        S->mat[k] = material[k];
+        if (S->emis[3 * k] > 0.0 || S->emis[3 * k + 1] > 0.0 || S->emis[3 * k + 2] > 0.0)
+            S->emitters[S->n_emit++] = k;
+    }
+    *out = S;
+    return 0;
+}
+
+void orc_scene_destroy(orc_scene *S) {
+    if (!S) return;
+    free(S->mu); free(S->M); free(S->d); free(S->nrm); free(S->alb); free(S->rough);
+    free(S->emis); free(S->mat); free(S->lo); free(S->hi); free(S->rsph); free(S->emitters);
+    free(S->nodes); free(S->perm);
+    free(S);
+}
+
+double orc_cutoff_radius(const orc_scene *S) { return S->r; }
+
+void orc_prim_frame(const orc_scene *S, int64_t k, double M[9], double normal[3], double lo[3],
+                    double hi[3]) {
+    for (int i = 0; i < 9; ++i) M[i] = S->M[9 * k + i];
+    for (int i = 0; i < 3; ++i) {
+        normal[i] = S->nrm[3 * k + i];
+        lo[i] = S->lo[3 * k + i];
+        hi[i] = S->hi[3 * k + i];
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Ray / primitive: chord of the cut-off ellipsoid and the ray integral.      */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int64_t k;
+    double a, b;   /* chord clipped to [t0, t1] */
+    double tc;     /* parameter of the closest approach in the unit frame */
+    double A;      /* |M w|^2 */
+    double rho2;   /* squared distance of closest approach in the unit frame */
+} ohit;
+
+/* Chord of the cut-off ellipsoid (Sec. 4.1, eq. cutoff_threshold): in the unit
+ * frame o' = M(o - mu), w' = M w, the ray point is o' + t w' and the ellipsoid
+ * is |.| = r.  Closest approach t_c = -(o'.w')/A with A = w'.w', squared
+ * distance rho^2 = |o' x w'|^2 / A; the chord is t_c -/+ sqrt((r^2-rho^2)/A). */
+static int ray_prim(const orc_scene *S, int64_t k, const double o[3], const double w[3], double t0,
+                    double t1, ohit *h) {
+    const double *M = S->M + 9 * k, *mu = S->mu + 3 * k;
+    double dlt[3] = {o[0] - mu[0], o[1] - mu[1], o[2] - mu[2]};
+    double op[3], wp[3];
+    for (int i = 0; i < 3; ++i) {
+        op[i] = M[3 * i] * dlt[0] + M[3 * i + 1] * dlt[1] + M[3 * i + 2] * dlt[2];
+        wp[i] = M[3 * i] * w[0] + M[3 * i + 1] * w[1] + M[3 * i + 2] * w[2];
+    }
+    double A = dot3(wp, wp);
+    if (!(A > 0.0)) return 0;
+    double cr[3];
+    cross3(op, wp, cr);
+    double rho2 = dot3(cr, cr) / A;
+    double r2 = S->r * S->r;
+    if (!(rho2 < r2)) return 0;
+    double tc = -dot3(op, wp) / A;
+    double half = sqrt((r2 - rho2) / A);
+    double a = fmax(t0, tc - half), b = fmin(t1, tc + half);
+    if (!(a < b)) return 0;
+    h->k = k; h->a = a; h->b = b; h->tc = tc; h->A = A; h->rho2 = rho2;
+    return 1;
+}
+
+/* Ray integral I(x, y) = int_x^y G(o + t w) dt, closed form of App. A with its
+ * garbled square corrected: the exponent is -(A/2)(t - t_c)^2 - rho^2/2, so
+ * I = d sqrt(pi/(2A)) exp(-rho^2/2) [erf(tau_y) - erf(tau_x)],
+ * tau_t = sqrt(A/2)(t - t_c).  x and y lie inside the chord, where the
+ * truncated kernel equals the Gaussian.  The difference of erf is taken as a
+ * difference of erfc when both arguments have the same sign, to avoid
+ * cancellation in the tails. */
+static double seg_integral(const orc_scene *S, const ohit *h, double x, double y) {
+    if (!(x < y)) return 0.0;
+    double s = sqrt(0.5 * h->A);
+    double tx = s * (x - h->tc), ty = s * (y - h->tc);
+    double diff;
+    if (tx >= 0.0) diff = erfc(tx) - erfc(ty);
+    else if (ty <= 0.0) diff = erfc(-ty) - erfc(-tx);
+    else diff = erf(ty) - erf(tx);
+    return S->d[h->k] * sqrt(M_PI / (2.0 * h->A)) * exp(-0.5 * h->rho2) * diff;
+}
+
+/* Kernel value G(o + t w) inside the chord: d exp(-(A (t-t_c)^2 + rho^2)/2). */
+static double kernel_at(const orc_scene *S, const ohit *h, double t) {
+    double q = h->A * (t - h->tc) * (t - h->tc) + h->rho2;
+    return S->d[h->k] * exp(-0.5 * q);
+}
+
+int orc_chord(const orc_scene *S, int64_t k, const float ray[8], double out[2]) {
+    double o[3] = {ray[0], ray[1], ray[2]}, w[3] = {ray[3], ray[4], ray[5]};
+    ohit h;
+    if (!ray_prim(S, k, o, w, ray[6], ray[7], &h)) return 0;
+    out[0] = h.a;
+    out[1] = h.b;
+    return 1;
+}
+
+double orc_ray_integral(const orc_scene *S, int64_t k, const double ray[8], double x, double y) {
+    ohit h;
+    if (!ray_prim(S, k, ray, ray + 3, ray[6], ray[7], &h)) return 0.0;
+    double a = fmax(x, h.a), b = fmin(y, h.b);
+    return seg_integral(S, &h, a, b);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Candidate gathering: brute force, or a median-split BVH over the boxes.    */
+/* Either way the result is the set H = {k != exclude : a_k < b_k}.           */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    ohit *v;
+    int64_t n, cap;
+} hitvec;
+
+static void hv_push(hitvec *hv, const ohit *h) {
+    if (hv->n == hv->cap) {
+        hv->cap = hv->cap ? 2 * hv->cap : 64;
+        hv->v = (ohit *)realloc(hv->v, sizeof(ohit) * (size_t)hv->cap);
+    }
+    hv->v[hv->n++] = *h;
+}
+
+static int box_hit(const double lo[3], const double hi[3], const double o[3], const double w[3],
+                   double t0, double t1) {
+    for (int i = 0; i < 3; ++i) {
+        if (w[i] != 0.0) {
+            double ta = (lo[i] - o[i]) / w[i], tb = (hi[i] - o[i]) / w[i];
+            if (ta > tb) { double tmp = ta; ta = tb; tb = tmp; }
+            if (ta > t0) t0 = ta;
+            if (tb < t1) t1 = tb;
+        } else if (o[i] < lo[i] || o[i] > hi[i]) {
+            return 0;
+        }
+    }
+    return t0 <= t1;
+}
+
+typedef struct {
+    const orc_scene *S;
+    int axis;
+} sortctx;
+
+static double centroid(const orc_scene *S, int64_t k, int axis) {
+    return 0.5 * (S->lo[3 * k + axis] + S->hi[3 * k + axis]);
+}
+
+/* quickselect on perm[first..last) so that element nth is in sorted place */
+static void select_nth(const orc_scene *S, int64_t *p, int64_t first, int64_t last, int64_t nth,
+                       int axis) {
+    while (last - first > 1) {
+        int64_t mid = first + (last - first) / 2;
+        double pivot = centroid(S, p[mid], axis);
+        int64_t i = first, j = last - 1;
+        while (i <= j) {
+            while (centroid(S, p[i], axis) < pivot) ++i;
+            while (centroid(S, p[j], axis) > pivot) --j;
+            if (i <= j) {
+                int64_t t = p[i]; p[i] = p[j]; p[j] = t;
+                ++i; --j;
+            }
+        }
+        if (nth <= j) last = j + 1;
+        else if (nth >= i) first = i;
+        else return;
+    }
+}
+
+int orc_scene_build_bvh(orc_scene *S) {
+    free(S->nodes); free(S->perm);
+    int64_t n = S->n;
+    S->perm = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) S->perm[i] = i;
+    int64_t cap = 2 * (n > 0 ? n : 1);
+    S->nodes = (onode *)malloc(sizeof(onode) * (size_t)cap);
+    S->n_nodes = 0;
+    if (n == 0) return 0;
+    /* explicit work stack of (node, first, count) */
+    typedef struct { int64_t node, first, count; } job;
+    job *stack = (job *)malloc(sizeof(job) * 128);
+    int sp = 0;
+    S->n_nodes = 1;
+    stack[sp++] = (job){0, 0, n};
+    while (sp) {
+        job jb = stack[--sp];
+        onode *nd = &S->nodes[jb.node];
+        for (int i = 0; i < 3; ++i) { nd->lo[i] = INFINITY; nd->hi[i] = -INFINITY; }
+        double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int64_t i = jb.first; i < jb.first + jb.count; ++i) {
+            int64_t k = S->perm[i];
+            for (int a = 0; a < 3; ++a) {
+                nd->lo[a] = fmin(nd->lo[a], S->lo[3 * k + a]);
+                nd->hi[a] = fmax(nd->hi[a], S->hi[3 * k + a]);
+                double c = centroid(S, k, a);
+                clo[a] = fmin(clo[a], c);
+                chi[a] = fmax(chi[a], c);
+            }
+        }
+        if (jb.count <= 4) {
+            nd->left = nd->right = -1;
+            nd->first = (int32_t)jb.first;
+            nd->count = (int32_t)jb.count;
+            continue;
+        }
+        int axis = 0;
+        for (int a = 1; a < 3; ++a)
+            if (chi[a] - clo[a] > chi[axis] - clo[axis]) axis = a;
+        int64_t half = jb.count / 2;
+        select_nth(S, S->perm, jb.first, jb.first + jb.count, jb.first + half, axis);
+        int64_t l = S->n_nodes++, r = S->n_nodes++;
+        nd->left = (int32_t)l;
+        nd->right = (int32_t)r;
+        nd->first = 0;
+        nd->count = 0;
+        stack[sp++] = (job){l, jb.first, half};
+        stack[sp++] = (job){r, jb.first + half, jb.count - half};
+    }
+    free(stack);
+    return 0;
+}
+
+static void gather(const orc_scene *S, const double o[3], const double w[3], double t0, double t1,
+                   int64_t exclude, int use_bvh, hitvec *out) {
+    out->n = 0;
+    ohit h;
+    if (!use_bvh || !S->nodes || S->n_nodes == 0) {
+        for (int64_t k = 0; k < S->n; ++k)
+            if (k != exclude && ray_prim(S, k, o, w, t0, t1, &h)) hv_push(out, &h);
+        return;
+    }
+    int64_t stack[128];
+    int sp = 0;
+    stack[sp++] = 0;
+    while (sp) {
+        const onode *nd = &S->nodes[stack[--sp]];
+        if (!box_hit(nd->lo, nd->hi, o, w, t0, t1)) continue;
+        if (nd->left < 0) {
+            for (int32_t i = nd->first; i < nd->first + nd->count; ++i) {
+                int64_t k = S->perm[i];
+                if (k != exclude && ray_prim(S, k, o, w, t0, t1, &h)) hv_push(out, &h);
+            }
+        } else {
+            stack[sp++] = nd->left;
+            stack[sp++] = nd->right;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Transmittance (Sec. 4, eq. transmittance): F = 1/2 sum_k I_k(a_k, b_k) over */
+/* the clipped chords, T = max(0, 1 - F).  Order independent.                 */
+/* ------------------------------------------------------------------------- */
+static double accumulated_F(const orc_scene *S, const hitvec *H) {
+    double F = 0.0;
+    for (int64_t i = 0; i < H->n; ++i) F += seg_integral(S, &H->v[i], H->v[i].a, H->v[i].b);
+    return 0.5 * F;
+}
+
+/* F(t) = 1/2 sum_k I_k(a_k, min(b_k, t)), the free-flight CDF before clamping */
+static double F_at(const orc_scene *S, const hitvec *H, double t) {
+    double F = 0.0;
+    for (int64_t i = 0; i < H->n; ++i)
+        if (H->v[i].a < t) F += seg_integral(S, &H->v[i], H->v[i].a, fmin(H->v[i].b, t));
+    return 0.5 * F;
+}
+
+/* dF/dt = 1/2 sum of the kernels active at t (eq. free_flight_pdf) */
+static double dF_at(const orc_scene *S, const hitvec *H, double t) {
+    double g = 0.0;
+    for (int64_t i = 0; i < H->n; ++i)
+        if (H->v[i].a < t && t < H->v[i].b) g += kernel_at(S, &H->v[i], t);
+    return 0.5 * g;
+}
+
+static int cmp_double(const void *a, const void *b) {
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+/* Saturating distance (Sec. 4, below eq. free_flight_pdf; Sec. 4.1 eq.
+ * sampling_overlaps with u = 1): the smallest t with F(t) = 1.  F is
+ * continuous and non-decreasing; the chord end points split [t0, t1] into
+ * pieces on which the active set is fixed.  The first end point with F >= 1
+ * brackets the root, F is strictly increasing inside, and a bisection-guarded
+ * Newton iteration with dF/dt = 1/2 sum G_k converges to full precision. */
+static double solve_tsat(const orc_scene *S, const hitvec *H, double t0) {
+    int64_t m = 2 * H->n;
+    double *bp = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+    for (int64_t i = 0; i < H->n; ++i) { bp[2 * i] = H->v[i].a; bp[2 * i + 1] = H->v[i].b; }
+    qsort(bp, (size_t)m, sizeof(double), cmp_double);
+    double lo = t0, hi = t0;
+    for (int64_t i = 0; i < m; ++i) {
+        if (bp[i] <= lo) continue;
+        if (F_at(S, H, bp[i]) >= 1.0) { hi = bp[i]; break; }
+        lo = bp[i];
+    }
+    free(bp);
+    if (!(hi > lo)) return hi;
+    double t = 0.5 * (lo + hi);
+    for (int it = 0; it < 300; ++it) {
+        double f = F_at(S, H, t) - 1.0;
+        if (f >= 0.0) hi = t; else lo = t;
+        double g = dF_at(S, H, t);
+        double tn = (g > 0.0) ? t - f / g : 0.5 * (lo + hi);
+        if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+        if (fabs(tn - t) <= 1e-16 * fmax(1.0, fabs(t)) || hi - lo <= 4e-16 * fmax(1.0, fabs(hi))) {
+            t = tn;
+            break;
+        }
+        t = tn;
+    }
+    return t;
+}
+
+void orc_transmittance(const orc_scene *S, int64_t n, const float *rays, const int32_t *exclude,
+                       int use_bvh, double *F_out, double *T_out) {
+    hitvec H = {0};
+    for (int64_t i = 0; i < n; ++i) {
+        const float *r = rays + 8 * i;
+        double o[3] = {r[0], r[1], r[2]}, w[3] = {r[3], r[4], r[5]};
+        gather(S, o, w, r[6], r[7], exclude ? exclude[i] : -1, use_bvh, &H);
+        double F = accumulated_F(S, &H);
+        if (F_out) F_out[i] = F;
+        if (T_out) T_out[i] = fmax(0.0, 1.0 - F);
+    }
+    free(H.v);
+}
+
+void orc_saturation(const orc_scene *S, int64_t n, const float *rays, const int32_t *exclude,
+                    int use_bvh, double *tsat_out) {
+    hitvec H = {0};
+    for (int64_t i = 0; i < n; ++i) {
+        const float *r = rays + 8 * i;
+        double o[3] = {r[0], r[1], r[2]}, w[3] = {r[3], r[4], r[5]};
+        gather(S, o, w, r[6], r[7], exclude ? exclude[i] : -1, use_bvh, &H);
+        double F = accumulated_F(S, &H);
+        tsat_out[i] = (F < 1.0) ? (double)r[7] : solve_tsat(S, &H, r[6]);
+    }
+    free(H.v);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Free-flight (primitive) sampling, Sec. 5.2.                                */
+/* The paper samples primitive k with probability equal to its share of the   */
+/* free-flight pdf up to the saturating distance:                             */
+/*   W_k = 1/2 I_k(a_k, min(b_k, t_sat)),  P(escape) = 1 - sum W = T(t1).     */
+/* One uniform u picks an outcome by walking a fixed ordering of H and        */
+/* returning the first k whose running sum of W exceeds u.  The ordering is   */
+/* canonical (independent of any tree): exit order, key (min(b_k, t_sat), k), */
+/* so primitives that straddle t_sat come last, by index.  The disambiguation */
+/* step of Sec. 5.2 is subsumed: straddlers get their exact clipped weights.  */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    double key;
+    int64_t k;
+    double W, a, b;
+} wentry;
+
+static int cmp_wentry(const void *x, const void *y) {
+    const wentry *a = (const wentry *)x, *b = (const wentry *)y;
+    if (a->key < b->key) return -1;
+    if (a->key > b->key) return 1;
+    return (a->k > b->k) - (a->k < b->k);
+}
+
+typedef struct {
+    int64_t prim;
+    double t_hit, F_end, t_sat, margin, W_total;
+} ocoll;
+
+static void collide(const orc_scene *S, const hitvec *H, double t0, double t1, double u, ocoll *c) {
+    double Fend = accumulated_F(S, H);
+    double tsat = (Fend < 1.0) ? t1 : solve_tsat(S, H, t0);
+    wentry *E = (wentry *)malloc(sizeof(wentry) * (size_t)(H->n > 0 ? H->n : 1));
+    int64_t m = 0;
+    for (int64_t i = 0; i < H->n; ++i) {
+        const ohit *h = &H->v[i];
+        if (!(h->a < tsat)) continue;
+        double e = fmin(h->b, tsat);
+        E[m].key = e;
+        E[m].k = h->k;
+        E[m].W = 0.5 * seg_integral(S, h, h->a, e);
+        E[m].a = h->a;
+        E[m].b = h->b;
+        ++m;
+    }
+    qsort(E, (size_t)m, sizeof(wentry), cmp_wentry);
+    c->prim = -1;
+    c->t_hit = NAN;
+    c->F_end = Fend;
+    c->t_sat = tsat;
+    double run = 0.0, margin = fabs(u);
+    for (int64_t i = 0; i < m; ++i) {
+        run += E[i].W;
+        margin = fmin(margin, fabs(u - run));
+        if (c->prim < 0 && run > u) {
+            c->prim = E[i].k;
+            c->t_hit = 0.5 * (E[i].a + E[i].b);
+        }
+    }
+    c->margin = margin;
+    c->W_total = run;
+    free(E);
+}
+
+void orc_sample_collision(const orc_scene *S, int64_t n, const float *rays, const int32_t *exclude,
+                          const double *u, int use_bvh, int32_t *prim_out, double *t_out,
+                          double *F_out, double *tsat_out, double *margin_out) {
+    hitvec H = {0};
+    for (int64_t i = 0; i < n; ++i) {
+        const float *r = rays + 8 * i;
+        double o[3] = {r[0], r[1], r[2]}, w[3] = {r[3], r[4], r[5]};
+        gather(S, o, w, r[6], r[7], exclude ? exclude[i] : -1, use_bvh, &H);
+        ocoll c;
+        collide(S, &H, r[6], r[7], u[i], &c);
+        if (prim_out) prim_out[i] = (int32_t)c.prim;
+        if (t_out) t_out[i] = c.t_hit;
+        if (F_out) F_out[i] = c.F_end;
+        if (tsat_out) tsat_out[i] = c.t_sat;
+        if (margin_out) margin_out[i] = c.margin;
+    }
+    free(H.v);
+}
+
+/* Emission carried by primitive k along a ray (eq. rte: emission rides on the
+ * free-flight pdf, so k contributes 1/2 L_e int_0^{t_sat} G_k dt).  The ray is
+ * (x, w, 0, b_k) with b_k the exit of k's chord; t_sat is taken over every
+ * primitive except `exclude`, k included.  Returns the factor multiplying
+ * L_e: 1/2 I_k(a_k, min(b_k, t_sat)), 0 when the ray misses k. */
+static double emitter_factor(const orc_scene *S, const double x[3], const double w[3],
+                             int64_t exclude, int64_t k, int use_bvh, hitvec *H) {
+    ohit hk;
+    if (k == exclude || !ray_prim(S, k, x, w, 0.0, INFINITY, &hk)) return 0.0;
+    double tend = hk.b;
+    gather(S, x, w, 0.0, tend, exclude, use_bvh, H);
+    double F = accumulated_F(S, H);
+    double tsat = (F < 1.0) ? tend : solve_tsat(S, H, 0.0);
+    if (!(hk.a < tsat)) return 0.0;
+    return 0.5 * seg_integral(S, &hk, hk.a, fmin(hk.b, tsat));
+}
+
+void orc_emitter_query(const orc_scene *S, int64_t n, const float *rays, const int32_t *exclude,
+                       const int32_t *target, int use_bvh, double *L_out) {
+    hitvec H = {0};
+    for (int64_t i = 0; i < n; ++i) {
+        const float *r = rays + 8 * i;
+        double o[3] = {r[0], r[1], r[2]}, w[3] = {r[3], r[4], r[5]};
+        L_out[i] = emitter_factor(S, o, w, exclude ? exclude[i] : -1, target[i], use_bvh, &H);
+    }
+    free(H.v);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Phase function in the delta-NDF limit (Sec. 6: with a single facet normal  */
+/* eq. phase_function reduces to the surface BSDF times the foreshortening    */
+/* cosine).  Normal n = R e_argmin(s), flipped toward w_o; reflection only.   */
+/*   Lambert:  f = albedo/pi cos_i,             pdf = cos_i/pi                */
+/*   GGX:      f = F D G2 / (4 cos_o),          pdf = G1(w_o) D(h) / (4 cos_o) */
+/* with alpha = roughness^2 (floored at 1e-4), height-correlated Smith G2,    */
+/* Schlick Fresnel with F0 = albedo, sampling by visible normals (Heitz,      */
+/* "Sampling the GGX Distribution of Visible Normals", JCGT 2018).            */
+/* All vectors are in the local frame (z = n).                                */
+/* ------------------------------------------------------------------------- */
+static double ggx_alpha(double rough) { return fmax(rough * rough, 1e-4); }
+
+static double ggx_D(double a, double cos_h) {
+    double a2 = a * a;
+    double t = cos_h * cos_h * (a2 - 1.0) + 1.0;
+    return a2 / (M_PI * t * t);
+}
+
+static double ggx_lambda(double a, double c) {
+    double c2 = c * c;
+    double tan2 = fmax(0.0, 1.0 - c2) / c2;
+    return 0.5 * (-1.0 + sqrt(1.0 + a * a * tan2));
+}
+
+/* local-frame eval; returns f (rgb) and the sampling pdf */
+static void phase_eval_local(int mat, const double alb[3], double rough, const double wo[3],
+                             const double wi[3], double f[3], double *pdf) {
+    f[0] = f[1] = f[2] = 0.0;
+    *pdf = 0.0;
+    if (wo[2] <= 0.0 || wi[2] <= 0.0) return;
+    if (mat == 0) {
+        for (int c = 0; c < 3; ++c) f[c] = alb[c] / M_PI * wi[2];
+        *pdf = wi[2] / M_PI;
+        return;
+    }
+    double a = ggx_alpha(rough);
+    double h[3] = {wo[0] + wi[0], wo[1] + wi[1], wo[2] + wi[2]};
+    normalize3(h);
+    double D = ggx_D(a, h[2]);
+    double lo = ggx_lambda(a, wo[2]), li = ggx_lambda(a, wi[2]);
+    double G2 = 1.0 / (1.0 + lo + li), G1 = 1.0 / (1.0 + lo);
+    double c = dot3(wi, h);
+    double sch = pow(1.0 - fmax(0.0, c), 5.0);
+    for (int k = 0; k < 3; ++k) {
+        double F = alb[k] + (1.0 - alb[k]) * sch;
+        f[k] = F * D * G2 / (4.0 * wo[2]);
+    }
+    *pdf = G1 * D / (4.0 * wo[2]);
+}
+
+/* local-frame sample; returns wi, weight f/pdf and pdf (pdf 0 = no sample) */
+static void phase_sample_local(int mat, const double alb[3], double rough, const double wo[3],
+                               double u1, double u2, double wi[3], double wgt[3], double *pdf) {
+    wgt[0] = wgt[1] = wgt[2] = 0.0;
+    *pdf = 0.0;
+    if (wo[2] <= 0.0) return;
+    if (mat == 0) {
+        double rr = sqrt(u1), ph = 2.0 * M_PI * u2;
+        wi[0] = rr * cos(ph);
+        wi[1] = rr * sin(ph);
+        wi[2] = sqrt(fmax(0.0, 1.0 - u1));
+        if (wi[2] <= 0.0) return;
+        *pdf = wi[2] / M_PI;
+        for (int c = 0; c < 3; ++c) wgt[c] = alb[c];
+        return;
+    }
+    double a = ggx_alpha(rough);
+    /* visible-normal sampling: stretch, sample the projected hemisphere, unstretch */
+    double Vh[3] = {a * wo[0], a * wo[1], wo[2]};
+    normalize3(Vh);
+    double lensq = Vh[0] * Vh[0] + Vh[1] * Vh[1];
+    double T1[3];
+    if (lensq > 0.0) {
+        double il = 1.0 / sqrt(lensq);
+        T1[0] = -Vh[1] * il; T1[1] = Vh[0] * il; T1[2] = 0.0;
+    } else {
+        T1[0] = 1.0; T1[1] = 0.0; T1[2] = 0.0;
+    }
+    double T2[3];
+    cross3(Vh, T1, T2);
+    double rr = sqrt(u1), ph = 2.0 * M_PI * u2;
+    double p1 = rr * cos(ph), p2 = rr * sin(ph);
+    double sv = 0.5 * (1.0 + Vh[2]);
+    p2 = (1.0 - sv) * sqrt(fmax(0.0, 1.0 - p1 * p1)) + sv * p2;
+    double p3 = sqrt(fmax(0.0, 1.0 - p1 * p1 - p2 * p2));
+    double Nh[3];
+    for (int i = 0; i < 3; ++i) Nh[i] = p1 * T1[i] + p2 * T2[i] + p3 * Vh[i];
+    double h[3] = {a * Nh[0], a * Nh[1], fmax(0.0, Nh[2])};
+    normalize3(h);
+    double c = dot3(wo, h);
+    for (int i = 0; i < 3; ++i) wi[i] = 2.0 * c * h[i] - wo[i];
+    if (wi[2] <= 0.0) return;
+    double D = ggx_D(a, h[2]);
+    double lo = ggx_lambda(a, wo[2]), li = ggx_lambda(a, wi[2]);
+    double G2 = 1.0 / (1.0 + lo + li), G1 = 1.0 / (1.0 + lo);
+    *pdf = G1 * D / (4.0 * wo[2]);
+    double sch = pow(1.0 - fmax(0.0, c), 5.0);
+    for (int k = 0; k < 3; ++k) {
+        double F = alb[k] + (1.0 - alb[k]) * sch;
+        wgt[k] = F * G2 / G1;
+    }
+}
+
+static void to_local(const double b1[3], const double b2[3], const double n[3], const double v[3],
+                     double l[3]) {
+    l[0] = dot3(v, b1); l[1] = dot3(v, b2); l[2] = dot3(v, n);
+}
+
+/* world-frame wrappers: n is the stored facet normal, flipped toward wo */
+static void facet_frame(const double nrm[3], const double wo[3], double n[3], double b1[3],
+                        double b2[3]) {
+    double s = dot3(nrm, wo) >= 0.0 ? 1.0 : -1.0;
+    n[0] = s * nrm[0]; n[1] = s * nrm[1]; n[2] = s * nrm[2];
+    onb(n, b1, b2);
+}
+
+void orc_phase_eval(int mat, const double alb[3], double rough, const double nrm[3],
+                    const double wo[3], const double wi[3], double f[3], double *pdf) {
+    double n[3], b1[3], b2[3], lo[3], li[3];
+    facet_frame(nrm, wo, n, b1, b2);
+    to_local(b1, b2, n, wo, lo);
+    to_local(b1, b2, n, wi, li);
+    phase_eval_local(mat, alb, rough, lo, li, f, pdf);
+}
+
+void orc_phase_sample(int mat, const double alb[3], double rough, const double nrm[3],
+                      const double wo[3], double u1, double u2, double wi[3], double wgt[3],
+                      double *pdf) {
+    double n[3], b1[3], b2[3], lo[3], li[3] = {0.0, 0.0, 0.0};
+    facet_frame(nrm, wo, n, b1, b2);
+    to_local(b1, b2, n, wo, lo);
+    phase_sample_local(mat, alb, rough, lo, u1, u2, li, wgt, pdf);
+    for (int i = 0; i < 3; ++i) wi[i] = li[0] * b1[i] + li[1] * b2[i] + li[2] * n[i];
+}
+
+/* ------------------------------------------------------------------------- */
+/* Path tracer (Sec. 5, Table tab:highlevel, right column; eq. rte), with     */
+/* next-event estimation to emissive primitives and to a constant environment */
+/* and the balance heuristic between light and phase sampling.                */
+/* ------------------------------------------------------------------------- */
+
+/* NEE cone pdf of emitter k seen from x: uniform over the cone subtending k's
+ * bounding sphere, times the uniform emitter-choice probability; 0 when x is
+ * inside the sphere. */
+static double nee_pdf(const orc_scene *S, int64_t k, const double x[3]) {
+    double c[3] = {S->mu[3 * k] - x[0], S->mu[3 * k + 1] - x[1], S->mu[3 * k + 2] - x[2]};
+    double d2 = dot3(c, c), rs = S->rsph[k];
+    if (d2 <= rs * rs) return 0.0;
+    double sin2 = rs * rs / d2;
+    double cosm = sqrt(fmax(0.0, 1.0 - sin2));
+    double omc = sin2 / (1.0 + cosm);
+    return 1.0 / ((double)S->n_emit * 2.0 * M_PI * omc);
+}
+
+typedef struct {
+    const orc_scene *S;
+    orc_camera cam;
+    orc_render_params p;
+    const int64_t *pixels; /* NULL = all */
+    int64_t n_pix;
+    double *sum, *sumsq;
+    int nthreads, tid;
+    int64_t rays;
+} rjob;
+
+static void camera_ray(const orc_camera *cam, int64_t px, int64_t py, double jx, double jy,
+                       double o[3], double w[3]) {
+    double f[3] = {cam->target[0] - cam->origin[0], cam->target[1] - cam->origin[1],
+                   cam->target[2] - cam->origin[2]};
+    normalize3(f);
+    double up[3] = {cam->up[0], cam->up[1], cam->up[2]};
+    double rgt[3];
+    cross3(f, up, rgt);
+    normalize3(rgt);
+    double u[3];
+    cross3(rgt, f, u);
+    double th = tan(0.5 * cam->vfov_deg * M_PI / 180.0);
+    double asp = (double)cam->width / (double)cam->height;
+    double sx = (2.0 * ((double)px + jx) / (double)cam->width - 1.0) * th * asp;
+    double sy = (1.0 - 2.0 * ((double)py + jy) / (double)cam->height) * th;
+    for (int i = 0; i < 3; ++i) {
+        o[i] = cam->origin[i];
+        w[i] = f[i] + sx * rgt[i] + sy * u[i];
+    }
+    normalize3(w);
+}
+
+/* Radiance of one camera path (vertex v = 1, 2, ...: collide, pick up
+ * emission, stop after max_depth scattering events, else NEE and phase
+ * sampling). */
+static void trace_path(const orc_scene *S, const orc_render_params *P, const orc_camera *cam,
+                       uint32_t pix, uint32_t sample, hitvec *H, hitvec *H2, double L[3],
+                       int64_t *rays) {
+    const uint64_t seed = P->seed;
+    double u[4], g[4];
+    rng4(seed, pix, sample, 0, 0, u);
+    double o[3], w[3];
+    camera_ray(cam, pix % (uint32_t)cam->width, pix / (uint32_t)cam->width, u[0], u[1], o, w);
+    double beta[3] = {1.0, 1.0, 1.0};
+    L[0] = L[1] = L[2] = 0.0;
+    int64_t self = -1;
+    double p_prev = 0.0, x_prev[3] = {0, 0, 0};
+    const int env = (P->env_radiance[0] > 0.0 || P->env_radiance[1] > 0.0 || P->env_radiance[2] > 0.0);
+    const double p_env = 1.0 / (4.0 * M_PI);
+    for (uint32_t v = 1;; ++v) {
+        rng4(seed, pix, sample, v, 0, u);
+        rng4(seed, pix, sample, v, 1, g);
+        gather(S, o, w, 0.0, INFINITY, self, 1, H);
+        ocoll c;
+        collide(S, H, 0.0, INFINITY, u[0], &c);
+        ++*rays;
+        if (c.prim < 0) {
+            if (env) {
+                double wt;
+                if (v == 1) wt = 1.0;
+                else if (P->mis_mode == 1) wt = 1.0;
+                else if (P->mis_mode == 2) wt = 0.0;
+                else wt = p_prev / (p_prev + p_env);
+                for (int i = 0; i < 3; ++i) L[i] += beta[i] * P->env_radiance[i] * wt;
+            }
+            break;
+        }
+        int64_t k = c.prim;
+        double x[3] = {o[0] + c.t_hit * w[0], o[1] + c.t_hit * w[1], o[2] + c.t_hit * w[2]};
+        const double *Le = S->emis + 3 * k;
+        if (Le[0] > 0.0 || Le[1] > 0.0 || Le[2] > 0.0) {
+            double wt;
+            if (v == 1) wt = 1.0;
+            else {
+                double pn = nee_pdf(S, k, x_prev);
+                if (P->mis_mode == 1) wt = 1.0;
+                else if (P->mis_mode == 2) wt = (pn > 0.0) ? 0.0 : 1.0;
+                else wt = p_prev / (p_prev + pn);
+            }
+            for (int i = 0; i < 3; ++i) L[i] += beta[i] * Le[i] * wt;
+        }
+        if ((int)v == P->max_depth + 1) break;
+        double wo[3] = {-w[0], -w[1], -w[2]};
+        const double *nrm = S->nrm + 3 * k, *alb = S->alb + 3 * k;
+        int mat = S->mat[k];
+        double rough = S->rough[k];
+        /* NEE to one emissive primitive */
+        if (S->n_emit > 0 && P->mis_mode != 1) {
+            int64_t j = (int64_t)(u[1] * (double)S->n_emit);
+            if (j >= S->n_emit) j = S->n_emit - 1;
+            int64_t e = S->emitters[j];
+            double pn = nee_pdf(S, e, x);
+            if (pn > 0.0) {
+                double cdir[3] = {S->mu[3 * e] - x[0], S->mu[3 * e + 1] - x[1], S->mu[3 * e + 2] - x[2]};
+                double d2 = dot3(cdir, cdir), rs = S->rsph[e];
+                double dist = sqrt(d2);
+                for (int i = 0; i < 3; ++i) cdir[i] /= dist;
+                double sin2m = rs * rs / d2;
+                double cosm = sqrt(fmax(0.0, 1.0 - sin2m));
+                double omc = sin2m / (1.0 + cosm);
+                double one_m_cos = u[2] * omc;
+                double cost = 1.0 - one_m_cos;
+                double sint = sqrt(fmax(0.0, one_m_cos * (2.0 - one_m_cos)));
+                double ph = 2.0 * M_PI * u[3];
+                double b1[3], b2[3], wl[3];
+                onb(cdir, b1, b2);
+                for (int i = 0; i < 3; ++i)
+                    wl[i] = sint * cos(ph) * b1[i] + sint * sin(ph) * b2[i] + cost * cdir[i];
+                double f[3], pph;
+                orc_phase_eval(mat, alb, rough, nrm, wo, wl, f, &pph);
+                if (f[0] > 0.0 || f[1] > 0.0 || f[2] > 0.0) {
+                    double fac = emitter_factor(S, x, wl, k, e, 1, H2);
+                    ++*rays;
+                    double wt = (P->mis_mode == 2) ? 1.0 : pn / (pn + pph);
+                    for (int i = 0; i < 3; ++i)
+                        L[i] += beta[i] * f[i] * S->emis[3 * e + i] * fac * wt / pn;
+                }
+            }
+        }
+        /* NEE to the constant environment */
+        if (env && P->mis_mode != 1) {
+            double z = 1.0 - 2.0 * g[2];
+            double rr = sqrt(fmax(0.0, 1.0 - z * z));
+            double ph = 2.0 * M_PI * g[3];
+            double wl[3] = {rr * cos(ph), rr * sin(ph), z};
+            double f[3], pph;
+            orc_phase_eval(mat, alb, rough, nrm, wo, wl, f, &pph);
+            if (f[0] > 0.0 || f[1] > 0.0 || f[2] > 0.0) {
+                gather(S, x, wl, 0.0, INFINITY, k, 1, H2);
+                double T = fmax(0.0, 1.0 - accumulated_F(S, H2));
+                ++*rays;
+                double wt = (P->mis_mode == 2) ? 1.0 : p_env / (p_env + pph);
+                for (int i = 0; i < 3; ++i) L[i] += beta[i] * f[i] * T * P->env_radiance[i] * wt / p_env;
+            }
+        }
+        /* continue by phase sampling; spawn at the chord centre, skip self */
+        double wi[3], wgt[3], pdf;
+        orc_phase_sample(mat, alb, rough, nrm, wo, g[0], g[1], wi, wgt, &pdf);
+        if (!(pdf > 0.0)) break;
+        for (int i = 0; i < 3; ++i) beta[i] *= wgt[i];
+        if (beta[0] == 0.0 && beta[1] == 0.0 && beta[2] == 0.0) break;
+        for (int i = 0; i < 3; ++i) { o[i] = x[i]; w[i] = wi[i]; x_prev[i] = x[i]; }
+        self = k;
+        p_prev = pdf;
+    }
+}
+
+static void *render_worker(void *arg) {
+    rjob *J = (rjob *)arg;
+    hitvec H = {0}, H2 = {0};
+    int64_t npix = J->pixels ? J->n_pix : (int64_t)J->cam.width * J->cam.height;
+    for (int64_t i = J->tid; i < npix; i += J->nthreads) {
+        int64_t pix = J->pixels ? J->pixels[i] : i;
+        double s[3] = {0, 0, 0}, s2[3] = {0, 0, 0};
+        for (int32_t sp = 0; sp < J->p.spp; ++sp) {
+            double L[3];
+            uint32_t sample = (uint32_t)(J->p.sample_offset + sp);
+            trace_path(J->S, &J->p, &J->cam, (uint32_t)pix, sample, &H, &H2, L, &J->rays);
+            for (int c = 0; c < 3; ++c) { s[c] += L[c]; s2[c] += L[c] * L[c]; }
+        }
+        for (int c = 0; c < 3; ++c) {
+            J->sum[3 * i + c] += s[c];
+            if (J->sumsq) J->sumsq[3 * i + c] += s2[c];
+        }
+    }
+    free(H.v);
+    free(H2.v);
+    return NULL;
+}
+
+int64_t orc_render(const orc_scene *S, const orc_camera *cam, const orc_render_params *p,
+                   int64_t n_pix, const int64_t *pixels, int nthreads, double *sum, double *sumsq) {
+    if (nthreads < 1) nthreads = 1;
+    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);
+    rjob *jobs = (rjob *)malloc(sizeof(rjob) * (size_t)nthreads);
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t] = (rjob){S, *cam, *p, pixels, n_pix, sum, sumsq, nthreads, t, 0};
+        pthread_create(&th[t], NULL, render_worker, &jobs[t]);
+    }
+    int64_t rays = 0;
+    for (int t = 0; t < nthreads; ++t) {
+        pthread_join(th[t], NULL);
+        rays += jobs[t].rays;
+    }
+    free(th);
+    free(jobs);
+    return rays;
+}
+
+/* single path, for expected-value tests: radiance of (pixel, sample) */
+void orc_path_radiance(const orc_scene *S, const orc_camera *cam, const orc_render_params *p,
+                       uint32_t pix, uint32_t sample, double L[3]) {
+    hitvec H = {0}, H2 = {0};
+    int64_t rays = 0;
+    trace_path(S, p, cam, pix, sample, &H, &H2, L, &rays);
+    free(H.v);
+    free(H2.v);
+}

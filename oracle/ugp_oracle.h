@@ -1,0 +1,72 @@
+/*
+ * ugp_oracle.h -- interface of the FP64 CPU oracle (test infrastructure only).
+ *
+ * Used by the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark.  Not part of the product; shares nothing with the GPU library.
+ * Arrays are host memory.  Rays are float32 [o.xyz, w.xyz, t0, t1] exactly as
+ * the GPU receives them; all arithmetic is double precision.
+ */
+#ifndef UGP_ORACLE_H
+#define UGP_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct orc_scene orc_scene;
+
+typedef struct {
+    double origin[3], target[3], up[3];
+    double vfov_deg;
+    int32_t width, height;
+} orc_camera;
+
+typedef struct {
+    int32_t spp, max_depth;
+    uint64_t seed;
+    int64_t sample_offset;
+    double env_radiance[3];
+    int32_t mis_mode; /* 0 balance heuristic, 1 phase sampling only, 2 light sampling only */
+} orc_render_params;
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+
+int orc_scene_create(int64_t n, const float *mean, const float *scale, const float *rotation,
+                     const float *density, const float *albedo, const float *roughness,
+                     const float *emission, const int32_t *material, double eps, orc_scene **out);
+void orc_scene_destroy(orc_scene *S);
+int orc_scene_build_bvh(orc_scene *S);
+double orc_cutoff_radius(const orc_scene *S);
+void orc_prim_frame(const orc_scene *S, int64_t k, double M[9], double normal[3], double lo[3],
+                    double hi[3]);
+
+int orc_chord(const orc_scene *S, int64_t k, const float ray[8], double out[2]);
+double orc_ray_integral(const orc_scene *S, int64_t k, const double ray[8], double x, double y);
+
+void orc_transmittance(const orc_scene *S, int64_t n, const float *rays, const int32_t *exclude,
+                       int use_bvh, double *F_out, double *T_out);
+void orc_saturation(const orc_scene *S, int64_t n, const float *rays, const int32_t *exclude,
+                    int use_bvh, double *tsat_out);
+void orc_sample_collision(const orc_scene *S, int64_t n, const float *rays, const int32_t *exclude,
+                          const double *u, int use_bvh, int32_t *prim_out, double *t_out,
+                          double *F_out, double *tsat_out, double *margin_out);
+void orc_emitter_query(const orc_scene *S, int64_t n, const float *rays, const int32_t *exclude,
+                       const int32_t *target, int use_bvh, double *L_out);
+
+void orc_phase_eval(int mat, const double alb[3], double rough, const double nrm[3],
+                    const double wo[3], const double wi[3], double f[3], double *pdf);
+void orc_phase_sample(int mat, const double alb[3], double rough, const double nrm[3],
+                      const double wo[3], double u1, double u2, double wi[3], double wgt[3],
+                      double *pdf);
+
+int64_t orc_render(const orc_scene *S, const orc_camera *cam, const orc_render_params *p,
+                   int64_t n_pix, const int64_t *pixels, int nthreads, double *sum, double *sumsq);
+void orc_path_radiance(const orc_scene *S, const orc_camera *cam, const orc_render_params *p,
+                       uint32_t pix, uint32_t sample, double L[3]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,341 @@
+"""Seeded synthetic inputs: scenes of Gaussian primitives, cameras and rays.
+
+This module only builds inputs.  It holds none of the rendering method's
+arithmetic (no ray integral, transmittance, sampling or shading); both the GPU
+library and the CPU oracle consume what it returns.  Every generator takes a
+seed and uses numpy's PCG64, so a workload is reproduced exactly from its name.
+
+Scene dictionaries hold float32 / int32 numpy arrays:
+  mean [n,3], scale [n,3] (>0), rotation [n,4] (w,x,y,z quaternion, any norm),
+  density [n] (peak value of the Gaussian), albedo [n,3], roughness [n],
+  emission [n,3] (radiance, 0 = not emissive), material [n] (0 diffuse, 1 glossy)
+and a "bounds" entry (lo, hi) used by camera set-up and the cache's position
+normalisation.
+
+The workloads stand in for the paper's scenes, whose assets are not available:
+  tiny_random  -- 1,000 random Gaussians in the unit cube (the shape of the
+                  paper's random-scene convergence experiment, Sec. 5.2),
+  mixed_100k   -- 70% flat surface Gaussians on spheres and planes, 30% a
+                  volumetric cloud,
+  room_5p5m    -- a room of boxes and planes tiled with flat Gaussians plus 40
+                  clusters of elongated Gaussians and two emissive panels, at
+                  the primitive count of the paper's largest scene (~5.5M).
+Flat primitives follow the paper's mesh-conversion rule (Sec. 7.1): tangent
+scale sqrt(eps*k*A/N) with eps = 0.01, k = 16, thin axis along the surface
+normal; each one is opaque on its own (normal-incidence opacity alpha >= 1.5)
+and centres are placed on a jittered grid so the tiled surface has no holes.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+EPS = 0.01
+K_COVER = 16.0
+# ray integral through the centre of an untruncated-at-r normal-incidence flat
+# Gaussian is d * sqrt(2 pi) * s_n * erf(r / sqrt 2); this constant turns a
+# chosen normal-incidence opacity alpha (= half that integral) into a density.
+_R_CUT = math.sqrt(-2.0 * math.log(EPS))
+_CENTRE_INTEGRAL = math.sqrt(2.0 * math.pi) * math.erf(_R_CUT / math.sqrt(2.0))
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def _loguniform(rng, lo, hi, size):
+    return np.exp(rng.uniform(np.log(lo), np.log(hi), size))
+
+
+def _random_quat(rng, n):
+    q = rng.normal(size=(n, 4))
+    return q / np.linalg.norm(q, axis=1, keepdims=True)
+
+
+def _quat_from_frames(t1, t2, nrm):
+    """Unit quaternions (w,x,y,z) of rotations whose columns are (t1, t2, nrm)."""
+    R = np.stack([t1, t2, nrm], axis=2)  # [n,3,3], columns
+    m00, m11, m22 = R[:, 0, 0], R[:, 1, 1], R[:, 2, 2]
+    tr = m00 + m11 + m22
+    q = np.zeros((R.shape[0], 4))
+    # Shepperd's method, choosing the largest diagonal term for stability
+    c0 = tr > 0
+    s = np.sqrt(np.maximum(tr + 1.0, 1e-30)) * 2
+    q[c0, 0] = 0.25 * s[c0]
+    q[c0, 1] = (R[c0, 2, 1] - R[c0, 1, 2]) / s[c0]
+    q[c0, 2] = (R[c0, 0, 2] - R[c0, 2, 0]) / s[c0]
+    q[c0, 3] = (R[c0, 1, 0] - R[c0, 0, 1]) / s[c0]
+    c1 = (~c0) & (m00 > m11) & (m00 > m22)
+    s = np.sqrt(np.maximum(1.0 + m00 - m11 - m22, 1e-30)) * 2
+    q[c1, 0] = (R[c1, 2, 1] - R[c1, 1, 2]) / s[c1]
+    q[c1, 1] = 0.25 * s[c1]
+    q[c1, 2] = (R[c1, 0, 1] + R[c1, 1, 0]) / s[c1]
+    q[c1, 3] = (R[c1, 0, 2] + R[c1, 2, 0]) / s[c1]
+    c2 = (~c0) & (~c1) & (m11 > m22)
+    s = np.sqrt(np.maximum(1.0 + m11 - m00 - m22, 1e-30)) * 2
+    q[c2, 0] = (R[c2, 0, 2] - R[c2, 2, 0]) / s[c2]
+    q[c2, 1] = (R[c2, 0, 1] + R[c2, 1, 0]) / s[c2]
+    q[c2, 2] = 0.25 * s[c2]
+    q[c2, 3] = (R[c2, 1, 2] + R[c2, 2, 1]) / s[c2]
+    c3 = (~c0) & (~c1) & (~c2)
+    s = np.sqrt(np.maximum(1.0 + m22 - m00 - m11, 1e-30)) * 2
+    q[c3, 0] = (R[c3, 1, 0] - R[c3, 0, 1]) / s[c3]
+    q[c3, 1] = (R[c3, 0, 2] + R[c3, 2, 0]) / s[c3]
+    q[c3, 2] = (R[c3, 1, 2] + R[c3, 2, 1]) / s[c3]
+    q[c3, 3] = 0.25 * s[c3]
+    return q / np.linalg.norm(q, axis=1, keepdims=True)
+
+
+def _tangent_frame(nrm, angle):
+    """Two unit tangents orthogonal to unit normals, rotated in-plane by angle."""
+    helper = np.where(np.abs(nrm[:, :1]) < 0.9, np.array([[1.0, 0, 0]]), np.array([[0, 1.0, 0]]))
+    a = np.cross(nrm, helper)
+    a /= np.linalg.norm(a, axis=1, keepdims=True)
+    b = np.cross(nrm, a)
+    c, s = np.cos(angle)[:, None], np.sin(angle)[:, None]
+    return c * a + s * b, -s * a + c * b
+
+
+def _flat(rng, centres, normals, s_t, thin, alpha_lo=1.5, alpha_hi=3.0):
+    """Flat primitives at given centres with normals; returns partial scene."""
+    n = centres.shape[0]
+    t1, t2 = _tangent_frame(normals, rng.uniform(0, 2 * np.pi, n))
+    q = _quat_from_frames(t1, t2, normals)
+    s_t = np.broadcast_to(np.asarray(s_t, dtype=np.float64), (n,))
+    s_n = s_t * thin
+    scale = np.stack([s_t, s_t, s_n], axis=1)
+    alpha = rng.uniform(alpha_lo, alpha_hi, n)
+    dens = 2.0 * alpha / (_CENTRE_INTEGRAL * s_n)
+    return centres, scale, q, dens
+
+
+def _grid_on_rect(rng, origin, eu, ev, w, h, cell, jitter=0.5):
+    """Jittered-grid points on the rectangle origin + [0,w] eu + [0,h] ev."""
+    nu = max(1, int(round(w / cell)))
+    nv = max(1, int(round(h / cell)))
+    iu, iv = np.meshgrid(np.arange(nu), np.arange(nv), indexing="ij")
+    iu = iu.ravel().astype(np.float64)
+    iv = iv.ravel().astype(np.float64)
+    fu = (iu + 0.5 + jitter * rng.uniform(-0.5, 0.5, iu.shape)) / nu * w
+    fv = (iv + 0.5 + jitter * rng.uniform(-0.5, 0.5, iv.shape)) / nv * h
+    return origin[None, :] + fu[:, None] * eu[None, :] + fv[:, None] * ev[None, :]
+
+
+def _sphere_points(rng, centre, radius, n):
+    """Quasi-uniform points on a sphere (golden-angle spiral, jittered)."""
+    i = np.arange(n) + 0.5 + 0.25 * rng.uniform(-1, 1, n)
+    z = 1.0 - 2.0 * i / n
+    phi = np.pi * (3.0 - np.sqrt(5.0)) * np.arange(n) + rng.uniform(0, 2 * np.pi)
+    rr = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    nrm = np.stack([rr * np.cos(phi), rr * np.sin(phi), z], axis=1)
+    return centre[None, :] + radius * nrm, nrm
+
+
+def _finish(parts, rng, *, albedo_lo, albedo_hi, rough_lo, rough_hi, glossy_frac):
+    mean = np.concatenate([p[0] for p in parts])
+    scale = np.concatenate([p[1] for p in parts])
+    rot = np.concatenate([p[2] for p in parts])
+    dens = np.concatenate([p[3] for p in parts])
+    n = mean.shape[0]
+    albedo = rng.uniform(albedo_lo, albedo_hi, (n, 3))
+    rough = rng.uniform(rough_lo, rough_hi, n)
+    material = (rng.uniform(0, 1, n) < glossy_frac).astype(np.int32)
+    return {
+        "mean": mean.astype(np.float32),
+        "scale": scale.astype(np.float32),
+        "rotation": rot.astype(np.float32),
+        "density": dens.astype(np.float32),
+        "albedo": albedo.astype(np.float32),
+        "roughness": rough.astype(np.float32),
+        "emission": np.zeros((n, 3), np.float32),
+        "material": material,
+    }
+
+
+def tiny_random(seed: int = 0, n: int = 1000, n_emit: int = 10, emit: float = 5.0) -> dict:
+    """1,000 random Gaussians in the unit cube: means U[0,1]^3, per-axis scales
+    log-uniform in [0.005, 0.05], random rotations, peak density U[0.5, 5],
+    diffuse albedo U[0.2, 0.8]^3, n_emit of them emissive with radiance emit."""
+    rng = _rng(seed)
+    mean = rng.uniform(0, 1, (n, 3))
+    scale = _loguniform(rng, 0.005, 0.05, (n, 3))
+    q = _random_quat(rng, n)
+    dens = rng.uniform(0.5, 5.0, n)
+    sc = _finish([(mean, scale, q, dens)], rng, albedo_lo=0.2, albedo_hi=0.8, rough_lo=0.5,
+                 rough_hi=0.5, glossy_frac=0.0)
+    idx = rng.choice(n, size=min(n_emit, n), replace=False)
+    sc["emission"][idx] = emit
+    sc["bounds"] = (np.zeros(3, np.float32), np.ones(3, np.float32))
+    return sc
+
+
+def mixed_100k(seed: int = 1, n_flat: int = 70_000, n_cloud: int = 30_000,
+               n_emit: int = 1_000, emit: float = 5.0) -> dict:
+    """70% flat Gaussians (one axis 100x thinner) on 10 spheres and 10 square
+    planes, 30% a volumetric cloud; half diffuse, half glossy (roughness
+    U[0.05, 1]); 1% emissive."""
+    rng = _rng(seed)
+    shapes = []
+    for _ in range(10):
+        shapes.append(("sphere", rng.uniform(0.2, 0.8, 3), rng.uniform(0.05, 0.2)))
+    for _ in range(10):
+        nrm = rng.normal(size=3)
+        nrm /= np.linalg.norm(nrm)
+        shapes.append(("plane", rng.uniform(0.2, 0.8, 3), nrm, rng.uniform(0.2, 0.6)))
+    areas = np.array([4 * np.pi * s[2] ** 2 if s[0] == "sphere" else s[3] ** 2 for s in shapes])
+    cell = math.sqrt(areas.sum() / n_flat)
+    s_t = math.sqrt(EPS * K_COVER) * cell
+    parts = []
+    for s in shapes:
+        if s[0] == "sphere":
+            m = int(round(4 * np.pi * s[2] ** 2 / cell ** 2))
+            pts, nrm = _sphere_points(rng, s[1], s[2], m)
+        else:
+            c, nrm1, side = s[1], s[2], s[3]
+            t1, t2 = _tangent_frame(nrm1[None, :], rng.uniform(0, 2 * np.pi, 1))
+            o = c - 0.5 * side * (t1[0] + t2[0])
+            pts = _grid_on_rect(rng, o, t1[0], t2[0], side, side, cell)
+            nrm = np.broadcast_to(nrm1, pts.shape).copy()
+        parts.append(_flat(rng, pts, nrm, s_t, 0.01))
+    # volumetric cloud: a ball of small random Gaussians
+    centre = rng.uniform(0.3, 0.7, 3)
+    d = rng.normal(size=(n_cloud, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    rad = 0.2 * rng.uniform(0, 1, n_cloud) ** (1.0 / 3.0)
+    cmean = centre[None, :] + rad[:, None] * d
+    cscale = _loguniform(rng, 0.002, 0.006, (n_cloud, 3))
+    parts.append((cmean, cscale, _random_quat(rng, n_cloud), rng.uniform(1.0, 10.0, n_cloud)))
+    sc = _finish(parts, rng, albedo_lo=0.2, albedo_hi=0.8, rough_lo=0.05, rough_hi=1.0,
+                 glossy_frac=0.5)
+    n = sc["mean"].shape[0]
+    idx = rng.choice(n, size=min(n_emit, n), replace=False)
+    sc["emission"][idx] = emit
+    sc["bounds"] = (np.zeros(3, np.float32), np.ones(3, np.float32))
+    return sc
+
+
+ROOM = np.array([8.0, 3.0, 8.0])
+
+
+def room_5p5m(seed: int = 2, n_surface: int = 4_300_000, n_clusters: int = 40,
+              per_cluster: int = 30_000, panel_radiance: float = 12.0) -> dict:
+    """An 8 x 3 x 8 m room (6 walls), 60 boxes on the floor, 12 free planes and
+    two 1 x 1 m emissive ceiling panels, all tiled with flat Gaussians
+    (n_surface in total, thin axis 0.1 x the tangent scale as in the paper's
+    mesh conversion), plus n_clusters clusters of elongated Gaussians
+    (20:1:1, short scale log-uniform [0.5, 2] mm, spread 0.15 m, peak density
+    U[8, 80] /m).  Albedo U[0.1, 0.9]^3, roughness U[0.02, 1], 50/50 diffuse /
+    glossy."""
+    rng = _rng(seed)
+    X, Y, Z = ROOM
+    rects = []  # (origin, eu, ev, w, h, normal, emissive)
+
+    def add(o, eu, ev, w, h, emissive=False):
+        o, eu, ev = np.asarray(o, float), np.asarray(eu, float), np.asarray(ev, float)
+        nrm = np.cross(eu, ev)
+        nrm /= np.linalg.norm(nrm)
+        rects.append((o, eu, ev, w, h, nrm, emissive))
+
+    ex, ey, ez = np.eye(3)
+    add([0, 0, 0], ex, ez, X, Z)            # floor
+    add([0, Y, 0], ex, ez, X, Z)            # ceiling
+    add([0, 0, 0], ex, ey, X, Y)            # wall z = 0
+    add([0, 0, Z], ex, ey, X, Y)            # wall z = Z
+    add([0, 0, 0], ez, ey, Z, Y)            # wall x = 0
+    add([X, 0, 0], ez, ey, Z, Y)            # wall x = X
+    for _ in range(60):
+        w, h, d = rng.uniform(0.3, 1.5, 3)
+        cx, cz = rng.uniform(0.8, X - 0.8), rng.uniform(0.8, Z - 0.8)
+        yaw = rng.uniform(0, 2 * np.pi)
+        u = np.array([np.cos(yaw), 0.0, np.sin(yaw)])
+        v = np.array([-np.sin(yaw), 0.0, np.cos(yaw)])
+        base = np.array([cx, 0.0, cz]) - 0.5 * w * u - 0.5 * d * v
+        add(base, u, ey, w, h)
+        add(base + d * v, u, ey, w, h)
+        add(base, v, ey, d, h)
+        add(base + w * u, v, ey, d, h)
+        add(base + h * ey, u, v, w, d)       # top
+    for _ in range(12):
+        side = rng.uniform(0.5, 1.5)
+        nrm = rng.normal(size=3)
+        nrm /= np.linalg.norm(nrm)
+        t1, t2 = _tangent_frame(nrm[None, :], rng.uniform(0, 2 * np.pi, 1))
+        c = np.array([rng.uniform(1, X - 1), rng.uniform(0.6, Y - 0.6), rng.uniform(1, Z - 1)])
+        add(c - 0.5 * side * (t1[0] + t2[0]), t1[0], t2[0], side, side)
+    for px in (2.5, 5.5):  # emissive panels hang 1 cm under the ceiling
+        add([px - 0.5, Y - 0.01, 3.5], ex, ez, 1.0, 1.0, emissive=True)
+    area = sum(r[3] * r[4] for r in rects)
+    cell = math.sqrt(area / n_surface)
+    s_t = math.sqrt(EPS * K_COVER) * cell
+    parts, emissive_mask = [], []
+    for (o, eu, ev, w, h, nrm, em) in rects:
+        pts = _grid_on_rect(rng, o, eu, ev, w, h, cell)
+        nn = np.broadcast_to(nrm, pts.shape).copy()
+        parts.append(_flat(rng, pts, nn, s_t, 0.1))
+        emissive_mask.append(np.full(pts.shape[0], em))
+    centres = np.stack([rng.uniform(0.5, X - 0.5, n_clusters), rng.uniform(0.5, Y - 0.5, n_clusters),
+                        rng.uniform(0.5, Z - 0.5, n_clusters)], axis=1)
+    for c in centres:
+        m = c[None, :] + rng.normal(0, 0.15, (per_cluster, 3))
+        short = _loguniform(rng, 0.0005, 0.002, per_cluster)
+        sc = np.stack([20 * short, short, short], axis=1)
+        parts.append((m, sc, _random_quat(rng, per_cluster), rng.uniform(8.0, 80.0, per_cluster)))
+        emissive_mask.append(np.zeros(per_cluster, bool))
+    sc = _finish(parts, rng, albedo_lo=0.1, albedo_hi=0.9, rough_lo=0.02, rough_hi=1.0,
+                 glossy_frac=0.5)
+    em = np.concatenate(emissive_mask)
+    sc["emission"][em] = panel_radiance
+    sc["bounds"] = (np.zeros(3, np.float32), ROOM.astype(np.float32))
+    return sc
+
+
+# ---------------------------------------------------------------------------
+# cameras and render settings of the workloads
+# ---------------------------------------------------------------------------
+def camera(name: str) -> dict:
+    if name in ("tiny_random", "mixed_100k"):
+        w = 128 if name == "tiny_random" else 512
+        return {"origin": (0.5, 0.5, -1.0), "target": (0.5, 0.5, 0.5), "up": (0.0, 1.0, 0.0),
+                "vfov_deg": 45.0, "width": w, "height": w}
+    if name == "room_5p5m":
+        return {"origin": (1.0, 1.6, 1.0), "target": (7.0, 1.0, 7.0), "up": (0.0, 1.0, 0.0),
+                "vfov_deg": 60.0, "width": 1920, "height": 1080}
+    raise KeyError(name)
+
+
+def render_settings(name: str) -> dict:
+    return {"tiny_random": {"spp": 4, "max_depth": 4, "seed": 0},
+            "mixed_100k": {"spp": 16, "max_depth": 8, "seed": 1},
+            "room_5p5m": {"spp": 64, "max_depth": 12, "seed": 2}}[name]
+
+
+def scene(name: str, **kw) -> dict:
+    return {"tiny_random": tiny_random, "mixed_100k": mixed_100k, "room_5p5m": room_5p5m}[name](**kw)
+
+
+# ---------------------------------------------------------------------------
+# rays for per-ray parity tests
+# ---------------------------------------------------------------------------
+def probe_rays(sc: dict, n: int, seed: int = 0, aimed_frac: float = 0.7,
+               finite_frac: float = 0.3) -> np.ndarray:
+    """Rays [n, 8] = (o, w, t0, t1): origins uniform in the scene bounds
+    (slightly enlarged), aimed_frac of them pointed at a random primitive's
+    mean, the rest in uniform random directions; t0 = 0 and t1 = +inf except
+    finite_frac of them ending at a random distance (some inside primitives)."""
+    rng = _rng(seed)
+    lo, hi = (np.asarray(b, np.float64) for b in sc["bounds"])
+    ext = hi - lo
+    o = rng.uniform(lo - 0.1 * ext, hi + 0.1 * ext, (n, 3))
+    w = rng.normal(size=(n, 3))
+    m = rng.uniform(0, 1, n) < aimed_frac
+    tgt = sc["mean"][rng.integers(0, sc["mean"].shape[0], n)].astype(np.float64)
+    w[m] = tgt[m] - o[m]
+    w /= np.linalg.norm(w, axis=1, keepdims=True)
+    t0 = np.zeros(n)
+    t1 = np.full(n, np.inf)
+    f = rng.uniform(0, 1, n) < finite_frac
+    dist = np.linalg.norm(tgt - o, axis=1)
+    t1[f] = dist[f] * rng.uniform(0.2, 1.5, f.sum())
+    rays = np.concatenate([o, w, t0[:, None], t1[:, None]], axis=1).astype(np.float32)
+    return rays

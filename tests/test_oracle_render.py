@@ -1,0 +1,89 @@
+"""Pins of the oracle's path tracer (Sec. 5 table tab:highlevel, eq. rte):
+white furnace, direct view of an emitter, and agreement of the light-sampling,
+phase-sampling and MIS estimators."""
+import math
+
+import numpy as np
+import pytest
+
+import indep
+from paper_2406_09733_amd import scenes
+
+
+def _furnace_scene():
+    sc = scenes.tiny_random(seed=21, n_emit=0)
+    sc["albedo"][:] = 1.0
+    sc["material"][:] = 0
+    return sc
+
+
+def test_white_furnace_phase_sampling_is_exact(orc):
+    # Absorption lives in the phase function (Sec. 3.2); with albedo 1, a
+    # Lambert phase function, unit environment and no emitters every path that
+    # escapes carries exactly 1 (P + T = 1 at every vertex).
+    sc = _furnace_scene()
+    S = orc.Scene(sc)
+    cam = dict(scenes.camera("tiny_random"), width=16, height=16)
+    s, s2, _ = S.render(cam, {"spp": 8, "max_depth": 1000, "seed": 3, "env_radiance": (1, 1, 1),
+                              "mis_mode": 1})
+    assert np.allclose(s / 8, 1.0, rtol=0, atol=1e-12)
+
+
+def test_white_furnace_with_mis(orc):
+    sc = _furnace_scene()
+    S = orc.Scene(sc)
+    cam = dict(scenes.camera("tiny_random"), width=16, height=16)
+    spp = 16
+    s, s2, _ = S.render(cam, {"spp": spp, "max_depth": 1000, "seed": 4, "env_radiance": (1, 1, 1)})
+    n = s.size * spp / 3
+    mean = s.sum(0) / (s.shape[0] * spp)
+    var = s2.sum(0) / (s.shape[0] * spp) - mean ** 2
+    err = np.sqrt(var / (s.shape[0] * spp))
+    assert np.all(np.abs(mean - 1.0) <= 3 * err + 1e-12), (mean, err)
+
+
+def test_direct_view_expected_value(orc):
+    # With max_depth 0 a camera path only picks up emission of the selected
+    # primitive: E[L] = sum_k W_k L_e,k (eq. rte, emission riding on the
+    # free-flight pdf).  One emissive Gaussian seen by a near-pinpoint camera.
+    sc = {"mean": np.array([[0.5, 0.5, 0.5]], np.float32), "scale": np.array([[0.1, 0.2, 0.15]], np.float32),
+          "rotation": np.array([[0.9, 0.2, 0.1, 0.3]], np.float32), "density": np.array([3.0], np.float32),
+          "albedo": np.full((1, 3), 0.5, np.float32), "roughness": np.full(1, 0.5, np.float32),
+          "emission": np.array([[2.0, 3.0, 4.0]], np.float32), "material": np.zeros(1, np.int32)}
+    S = orc.Scene(sc)
+    cam = {"origin": (0.5, 0.52, -1.0), "target": (0.5, 0.52, 0.5), "up": (0, 1, 0), "vfov_deg": 1e-6,
+           "width": 1, "height": 1}
+    p = {"spp": 1, "max_depth": 0, "seed": 5}
+    n = 4000
+    Ls = np.array([S.path_radiance(cam, p, 0, i) for i in range(n)])
+    o = np.float32([0.5, 0.52, -1.0]).astype(np.float64)
+    w = np.array([0.0, 0.0, 1.0])
+    W = 0.5 * indep.integral(sc, 0, o, w, 0.0, np.inf)
+    assert W < 1.0
+    ref = W * np.array([2.0, 3.0, 4.0])
+    m = Ls.mean(0)
+    se = Ls.std(0) / np.sqrt(n)
+    assert np.all(np.abs(m - ref) <= 3 * se + 1e-4), (m, ref, se)
+
+
+@pytest.mark.slow
+def test_mis_estimators_agree(orc):
+    # Light sampling only, phase sampling only and the balance heuristic
+    # estimate the same image (a wrong MIS weight or pdf shows up as a bias).
+    sc = scenes.tiny_random(seed=0, n_emit=200)
+    sc["material"][::2] = 1
+    sc["roughness"][:] = np.linspace(0.1, 1.0, sc["roughness"].size, dtype=np.float32)
+    S = orc.Scene(sc)
+    cam = dict(scenes.camera("tiny_random"), width=32, height=32)
+    spp = 512
+    res = {}
+    for mode in (0, 1, 2):
+        s, s2, _ = S.render(cam, {"spp": spp, "max_depth": 3, "seed": 7 + mode, "mis_mode": mode})
+        npx = s.shape[0]
+        mean = s.sum() / (npx * spp * 3)
+        per = s.sum(1) / 3 / spp
+        var = (s2.sum(1) / 3 / spp - per ** 2).mean()
+        res[mode] = (mean, math.sqrt(max(var, 0) / (npx * spp)))
+    for a in (1, 2):
+        d = abs(res[a][0] - res[0][0])
+        assert d <= 3 * math.hypot(res[a][1], res[0][1]), res
