@@ -1,0 +1,215 @@
+/*
+ * ugp.h -- C ABI of libugp: Monte Carlo path tracing of scenes made entirely of
+ * linear-transmittance Gaussian primitives on AMD Instinct MI355X (gfx950).
+ *
+ * Method: "Unified Gaussian Primitives for Scene Representation and Rendering"
+ * (arXiv 2406.09733).  The entry points are the scene operations a path tracer
+ * needs (Sec. 5, table tab:highlevel, right column): free-flight (primitive)
+ * sampling, transmittance evaluation, and a full path tracer with next-event
+ * estimation built on them.
+ *
+ * Conventions for every entry point:
+ *  - Array arguments are DEVICE pointers (e.g. torch tensor storage on the
+ *    context's device) unless marked [host].  The caller owns them.
+ *  - Work is enqueued on the context's stream and the call returns without
+ *    waiting, except where stated.  Inputs must stay alive until the stream
+ *    has consumed them (torch's caching allocator on the same stream does this).
+ *  - Rays are float32 [n][8] = (origin.xyz, direction.xyz, t0, t1), direction of
+ *    unit length, t1 may be +inf.  The ray is x(t) = origin + t * direction,
+ *    t in [t0, t1] (Sec. 4.1 "Ray Integral").
+ *  - Primitive indices in and out are the caller's original indices
+ *    (0 .. n-1 in the order the scene was given); -1 means "none".
+ *  - Problems a host check can see (NULL required pointer, bad sizes, eps
+ *    outside (0,1), no scene) return UGP_ERR_INVALID_ARGUMENT / UGP_ERR_NO_SCENE
+ *    and enqueue nothing.  Device failures return UGP_ERR_DEVICE.  No C++
+ *    exception crosses this boundary and nothing aborts.
+ *  - One host thread uses a context at a time.
+ */
+#ifndef UGP_H
+#define UGP_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ugp_ctx_s *ugp_ctx;
+
+typedef enum {
+    UGP_OK = 0,
+    UGP_ERR_INVALID_ARGUMENT = 1,
+    UGP_ERR_OUT_OF_MEMORY = 2,
+    UGP_ERR_DEVICE = 3,
+    UGP_ERR_NO_SCENE = 4,
+    UGP_ERR_UNSUPPORTED = 5,
+    UGP_ERR_OVERFLOW = 6
+} ugp_status;
+
+/* [host] struct of DEVICE pointers describing n primitives (Sec. 3.1, Sec. 4,
+ * Sec. 6).  All float32 unless noted.
+ *   mean[n][3]      mean mu
+ *   scale[n][3]     per-axis scale s (> 0); Sigma = (R S)(R S)^T (eq. covariance_decomposition)
+ *   rotation[n][4]  quaternion (w, x, y, z) of R, any non-zero norm (normalised here)
+ *   density[n]      peak value d = G(mu) >= 0 (the paper's magnitude c equals
+ *                   d (2 pi)^(3/2) s_x s_y s_z)
+ *   albedo[n][3]    base colour: Lambert albedo, or GGX F0
+ *   roughness[n]    GGX roughness in (0, 1]; alpha = roughness^2
+ *   emission[n][3]  emitted radiance (0 = not an emitter)
+ *   material[n]     int32: 0 = diffuse (Lambert), 1 = glossy (GGX); the phase
+ *                   function is the delta-NDF limit of eq. phase_function with the
+ *                   facet normal along the axis of the smallest scale            */
+typedef struct {
+    int64_t n;
+    const float *mean, *scale, *rotation, *density, *albedo, *roughness, *emission;
+    const int32_t *material;
+} ugp_scene;
+
+/* [host] pinhole camera: pixel (i, j), j = 0 at the top, jitter (jx, jy) in
+ * [0,1)^2 maps to direction normalize(f + sx*right + sy*up) with
+ * sx = (2 (i + jx) / width - 1) tan(vfov/2) width/height,
+ * sy = (1 - 2 (j + jy) / height) tan(vfov/2),
+ * f = normalize(target - origin), right = normalize(f x up_hint), up = right x f. */
+typedef struct {
+    float origin[3], target[3], up[3];
+    float vfov_deg;
+    int32_t width, height;
+} ugp_camera;
+
+/* [host] render settings.
+ *   spp            samples per pixel of this call (>= 1)
+ *   max_depth      number of scattering events per path (>= 0); emission is
+ *                  still picked up at collision max_depth + 1
+ *   seed           key of the Philox4x32-10 generator; counters are
+ *                  (pixel, sample_offset + s, vertex, group)
+ *   sample_offset  first sample index, so progressive calls resume exactly
+ *   env_radiance   constant environment radiance (0 = black background)
+ *   mis_mode       0 balance heuristic, 1 phase sampling only, 2 light sampling only
+ *   nrc_mode       0 plain tracer; 1 radiance cache: infer at the termination
+ *                  vertex and train on this call's paths; 2 infer only
+ *   nrc_terminate_after  scattering events before a cached path ends (>= 1)
+ *   nrc_train_records    training records collected per call (<= 1 << 20)      */
+typedef struct {
+    int32_t spp, max_depth;
+    uint64_t seed;
+    int64_t sample_offset;
+    float env_radiance[3];
+    int32_t mis_mode;
+    int32_t nrc_mode, nrc_terminate_after, nrc_train_records;
+} ugp_render_params;
+
+/* Create a context on `device` that enqueues on `hip_stream` (a hipStream_t;
+ * NULL = the null stream).  Allocates nothing on the device until a scene is
+ * built.  Returns UGP_ERR_DEVICE if the device is not a usable gfx950. */
+ugp_status ugp_create(int device, void *hip_stream, ugp_ctx *out);
+ugp_status ugp_destroy(ugp_ctx ctx);
+ugp_status ugp_set_stream(ugp_ctx ctx, void *hip_stream);
+
+/* Build the scene: pack the primitives (normalise rotations, form the
+ * world-to-unit-Gaussian map M = S^-1 R^T, the facet normal and the box of the
+ * cut-off ellipsoid |M (x - mu)| = sqrt(-2 ln eps), eq. cutoff_threshold) and
+ * build a bounding volume hierarchy over those boxes on the GPU.  The scene is
+ * copied into library-owned memory (leaf order), so the input arrays may be
+ * freed once the stream passes this call.  eps in (0, 1); the paper uses 0.01.
+ * Synchronises the stream once (to size the tree).  n >= 1. */
+ugp_status ugp_build_bvh(ugp_ctx ctx, const ugp_scene *scene, float cutoff_eps);
+
+/* Transmittance along each ray (Sec. 4 eq. transmittance, Sec. 5.3):
+ * F = 1/2 sum_k I_k(a_k, b_k) over every primitive k != exclude[i] whose
+ * cut-off ellipsoid meets [t0, t1] in the chord [a_k, b_k], with I_k the
+ * closed-form ray integral (App. A); T = max(0, 1 - F).
+ *   exclude  int32 [n] original indices, or NULL (none)
+ *   T_out    float [n]
+ *   F_out    float [n] or NULL.  If given, F is the full sum (no early exit at
+ *            F >= 1); if NULL the traversal stops once F reaches 1 (T = 0). */
+ugp_status ugp_transmittance(ugp_ctx ctx, int64_t n_rays, const float *rays,
+                             const int32_t *exclude, float *T_out, float *F_out);
+
+/* Primitive-level free-flight sampling (Sec. 5.2, Sec. 4.1 eq.
+ * sampling_overlaps): with the saturating distance t_sat (smallest t with
+ * F(t) = 1, or t1 if F never reaches 1) each primitive k is selected with
+ * probability W_k = 1/2 I_k(a_k, min(b_k, t_sat)) and the ray escapes with
+ * probability max(0, 1 - F(t1)).  One uniform u[i] in [0,1) picks the outcome
+ * deterministically: primitives are ordered by exit key (min(b_k, t_sat), k)
+ * and the first k whose running sum of W exceeds u is returned.
+ *   u         float [n]
+ *   prim_out  int32 [n] selected original index, -1 = escape
+ *   t_out     float [n] scatter distance 1/2 (a_k + b_k), the centre of the
+ *             clipped chord (Sec. 6 "Importance Sampling"); NaN on escape.
+ * Returns UGP_ERR_OVERFLOW (and leaves those outputs at -1 / NaN) if more than
+ * 64 primitives overlap a single point of a ray. */
+ugp_status ugp_sample_collision(ugp_ctx ctx, int64_t n_rays, const float *rays,
+                                const int32_t *exclude, const float *u, int32_t *prim_out,
+                                float *t_out);
+
+/* Saturating distance per ray: smallest t in [t0, t1] with F(t) = 1 (Sec. 4,
+ * below eq. free_flight_pdf), or t1 when F(t1) < 1.  tsat_out float [n]. */
+ugp_status ugp_saturation(ugp_ctx ctx, int64_t n_rays, const float *rays,
+                          const int32_t *exclude, float *tsat_out);
+
+/* Emission factor of primitive target[i] along each ray: emission rides on the
+ * free-flight pdf (eq. rte), so target k contributes L_e,k times
+ *   out = 1/2 I_k(a_k, min(b_k, t_sat))
+ * where the ray is clipped to [t0, b_k] and t_sat is taken over every primitive
+ * except exclude[i] (k included); 0 if the ray misses k or k == exclude[i].
+ * This is the light-sampling query of next-event estimation. */
+ugp_status ugp_emitter_query(ugp_ctx ctx, int64_t n_rays, const float *rays,
+                             const int32_t *exclude, const int32_t *target, float *out);
+
+/* Instrumentation: runs the ordered sweep of ugp_sample_collision (mode 0),
+ * ugp_saturation (mode 1) or ugp_emitter_query (mode 2) and writes, per ray,
+ * counts int32 [n][4] = (BVH nodes fetched, primitive records chord-tested,
+ * primitive records re-read for partial integrals, traversal rounds).  Other
+ * arguments as in those calls; results are discarded. */
+ugp_status ugp_trace_counts(ugp_ctx ctx, int mode, int64_t n_rays, const float *rays,
+                            const int32_t *exclude, const float *u, const int32_t *target,
+                            int32_t *counts);
+
+/* Path tracing (Sec. 5 table tab:highlevel, eq. rte) with next-event
+ * estimation to emissive primitives and to the environment and the balance
+ * heuristic against phase sampling.  Adds, per pixel, the sum over this call's
+ * samples of the path radiance to sum_rgb [height][width][3] and of its square
+ * to sumsq_rgb (or NULL).  Enqueued; may synchronise internally between
+ * bounces only through device-side queue counters (no host round trip). */
+ugp_status ugp_render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p,
+                      float *sum_rgb, float *sumsq_rgb);
+
+/* Waits for the context's stream and reports deferred device-side errors
+ * (queue or stack overflow) as UGP_ERR_OVERFLOW, clearing them. */
+ugp_status ugp_sync(ugp_ctx ctx);
+
+/* [host] statistics of the last ugp_render call.  A "ray" is one traversal
+ * query: a free-flight (collision) query, a light-sample emitter query or an
+ * environment transmittance query. */
+typedef struct {
+    int64_t paths;           /* camera paths (pixels x samples) */
+    int64_t collision_rays;  /* free-flight sampling queries */
+    int64_t light_rays;      /* emitter queries of next-event estimation */
+    int64_t env_rays;        /* environment transmittance queries */
+    int64_t node_visits;     /* BVH nodes fetched by all queries (profiling level 2, else -1) */
+    int64_t prim_tests;      /* primitive records fetched and chord-tested (level 2, else -1) */
+    int64_t prim_reloads;    /* primitive records re-read for partial integrals (level 2, else -1) */
+    double ms_collide;       /* summed duration of the main collision kernel launches (level >= 1, else -1) */
+    double ms_collide_wide;  /* ... of the overflow collision launches */
+    double ms_light;         /* ... of the light-sample kernels (main + overflow) */
+    double ms_env;           /* ... of the environment kernels */
+    int32_t launches_collide, launches_light, launches_env;
+    /* the three traversal counters split by kernel: [0] collision, [1] collision
+       overflow pass, [2] light samples, [3] environment samples (level 2, else -1) */
+    int64_t cat_nodes[4], cat_prims[4], cat_reloads[4];
+} ugp_render_stats;
+
+/* Profiling level of later ugp_render calls: 0 off; 1 every kernel launch is
+ * bracketed by HIP events on the context's stream and the durations summed;
+ * 2 additionally counts BVH node visits and primitive tests (algorithmic
+ * traffic).  [host] call, no device work. */
+ugp_status ugp_set_profiling(ugp_ctx ctx, int level);
+
+/* Statistics of the last ugp_render call (synchronises the stream). */
+ugp_status ugp_get_render_stats(ugp_ctx ctx, ugp_render_stats *out);
+
+const char *ugp_status_string(ugp_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -66,6 +66,7 @@ def lib():
         L.orc_ray_integral.restype = C.c_double
         L.orc_transmittance.argtypes = [vp, C.c_int64, vp, vp, C.c_int, vp, vp]
         L.orc_saturation.argtypes = [vp, C.c_int64, vp, vp, C.c_int, vp]
+        L.orc_F_at.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_int, vp]
         L.orc_sample_collision.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_int, vp, vp, vp, vp, vp]
         L.orc_emitter_query.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_int, vp]
         L.orc_phase_eval.argtypes = [C.c_int, vp, C.c_double, vp, vp, vp, vp, vp]
@@ -184,6 +185,17 @@ class Scene:
         ub = self.use_bvh if use_bvh is None else int(use_bvh)
         lib().orc_saturation(self.h, n, _addr(r), _addr(e), ub, _addr(t))
         return t
+
+    def F_at(self, rays, t, exclude=None, use_bvh=None):
+        """F(t) = 1/2 sum_k I_k(a_k, min(b_k, t)) per ray."""
+        r = _rays(rays)
+        n = r.shape[0]
+        e = _excl(exclude, n)
+        tt = np.ascontiguousarray(t, dtype=np.float64)
+        F = np.zeros(n)
+        ub = self.use_bvh if use_bvh is None else int(use_bvh)
+        lib().orc_F_at(self.h, n, _addr(r), _addr(e), _addr(tt), ub, _addr(F))
+        return F
 
     def sample_collision(self, rays, u, exclude=None, use_bvh=None):
         r = _rays(rays)

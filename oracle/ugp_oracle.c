@@ -523,6 +523,19 @@ void orc_transmittance(const orc_scene *S, int64_t n, const float *rays, const i
     free(H.v);
 }
 
+/* F(t) = 1/2 sum_k I_k(a_k, min(b_k, t)) along each ray (t inside [t0, t1]) */
+void orc_F_at(const orc_scene *S, int64_t n, const float *rays, const int32_t *exclude,
+              const double *t, int use_bvh, double *F_out) {
+    hitvec H = {0};
+    for (int64_t i = 0; i < n; ++i) {
+        const float *r = rays + 8 * i;
+        double o[3] = {r[0], r[1], r[2]}, w[3] = {r[3], r[4], r[5]};
+        gather(S, o, w, r[6], r[7], exclude ? exclude[i] : -1, use_bvh, &H);
+        F_out[i] = F_at(S, &H, t[i]);
+    }
+    free(H.v);
+}
+
 void orc_saturation(const orc_scene *S, int64_t n, const float *rays, const int32_t *exclude,
                     int use_bvh, double *tsat_out) {
     hitvec H = {0};
@@ -623,15 +636,16 @@ void orc_sample_collision(const orc_scene *S, int64_t n, const float *rays, cons
  * free-flight pdf, so k contributes 1/2 L_e int_0^{t_sat} G_k dt).  The ray is
  * (x, w, 0, b_k) with b_k the exit of k's chord; t_sat is taken over every
  * primitive except `exclude`, k included.  Returns the factor multiplying
- * L_e: 1/2 I_k(a_k, min(b_k, t_sat)), 0 when the ray misses k. */
-static double emitter_factor(const orc_scene *S, const double x[3], const double w[3],
-                             int64_t exclude, int64_t k, int use_bvh, hitvec *H) {
+ * L_e: 1/2 I_k(a_k, min(b_k, t_sat)), 0 when the ray misses k.  The ray is
+ * clipped to [t0, min(t1, b_k)]. */
+static double emitter_factor(const orc_scene *S, const double x[3], const double w[3], double t0,
+                             double t1, int64_t exclude, int64_t k, int use_bvh, hitvec *H) {
     ohit hk;
-    if (k == exclude || !ray_prim(S, k, x, w, 0.0, INFINITY, &hk)) return 0.0;
+    if (k < 0 || k >= S->n || k == exclude || !ray_prim(S, k, x, w, t0, t1, &hk)) return 0.0;
     double tend = hk.b;
-    gather(S, x, w, 0.0, tend, exclude, use_bvh, H);
+    gather(S, x, w, t0, tend, exclude, use_bvh, H);
     double F = accumulated_F(S, H);
-    double tsat = (F < 1.0) ? tend : solve_tsat(S, H, 0.0);
+    double tsat = (F < 1.0) ? tend : solve_tsat(S, H, t0);
     if (!(hk.a < tsat)) return 0.0;
     return 0.5 * seg_integral(S, &hk, hk.a, fmin(hk.b, tsat));
 }
@@ -642,7 +656,7 @@ void orc_emitter_query(const orc_scene *S, int64_t n, const float *rays, const i
     for (int64_t i = 0; i < n; ++i) {
         const float *r = rays + 8 * i;
         double o[3] = {r[0], r[1], r[2]}, w[3] = {r[3], r[4], r[5]};
-        L_out[i] = emitter_factor(S, o, w, exclude ? exclude[i] : -1, target[i], use_bvh, &H);
+        L_out[i] = emitter_factor(S, o, w, r[6], r[7], exclude ? exclude[i] : -1, target[i], use_bvh, &H);
     }
     free(H.v);
 }
@@ -913,8 +927,9 @@ static void trace_path(const orc_scene *S, const orc_render_params *P, const orc
                     wl[i] = sint * cos(ph) * b1[i] + sint * sin(ph) * b2[i] + cost * cdir[i];
                 double f[3], pph;
                 orc_phase_eval(mat, alb, rough, nrm, wo, wl, f, &pph);
-                if (f[0] > 0.0 || f[1] > 0.0 || f[2] > 0.0) {
-                    double fac = emitter_factor(S, x, wl, k, e, 1, H2);
+                ohit he;
+                if ((f[0] > 0.0 || f[1] > 0.0 || f[2] > 0.0) && ray_prim(S, e, x, wl, 0.0, INFINITY, &he)) {
+                    double fac = emitter_factor(S, x, wl, 0.0, INFINITY, k, e, 1, H2);
                     ++*rays;
                     double wt = (P->mis_mode == 2) ? 1.0 : pn / (pn + pph);
                     for (int i = 0; i < 3; ++i)

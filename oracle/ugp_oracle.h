@@ -47,6 +47,8 @@ double orc_ray_integral(const orc_scene *S, int64_t k, const double ray[8], doub
 
 void orc_transmittance(const orc_scene *S, int64_t n, const float *rays, const int32_t *exclude,
                        int use_bvh, double *F_out, double *T_out);
+void orc_F_at(const orc_scene *S, int64_t n, const float *rays, const int32_t *exclude,
+              const double *t, int use_bvh, double *F_out);
 void orc_saturation(const orc_scene *S, int64_t n, const float *rays, const int32_t *exclude,
                     int use_bvh, double *tsat_out);
 void orc_sample_collision(const orc_scene *S, int64_t n, const float *rays, const int32_t *exclude,

@@ -1,0 +1,267 @@
+"""paper_2406_09733_amd -- MI355X-native path tracing of scenes made of
+linear-transmittance Gaussian primitives ("Unified Gaussian Primitives for
+Scene Representation and Rendering", arXiv 2406.09733).
+
+The compute lives in ``libugp.so`` (hand-written HIP for gfx950, C ABI in
+``include/ugp.h``).  This module is a thin ctypes binding with the same names:
+it checks shapes and dtypes, takes device pointers from torch tensors and the
+current HIP stream, and raises on any non-OK status.  There is no CPU path: if
+the library is missing the import of ``Context`` fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libugp.so")
+_lib = None
+
+STATUS = {0: "ok", 1: "invalid argument", 2: "out of device memory", 3: "device error",
+          4: "no scene has been built", 5: "unsupported", 6: "a per-ray buffer overflowed"}
+
+
+class UGPError(RuntimeError):
+    def __init__(self, call: str, code: int):
+        super().__init__(f"{call}: {STATUS.get(code, code)} (status {code})")
+        self.code = code
+
+
+class _Scene(C.Structure):
+    _fields_ = [("n", C.c_int64), ("mean", C.c_void_p), ("scale", C.c_void_p), ("rotation", C.c_void_p),
+                ("density", C.c_void_p), ("albedo", C.c_void_p), ("roughness", C.c_void_p),
+                ("emission", C.c_void_p), ("material", C.c_void_p)]
+
+
+class _Camera(C.Structure):
+    _fields_ = [("origin", C.c_float * 3), ("target", C.c_float * 3), ("up", C.c_float * 3),
+                ("vfov_deg", C.c_float), ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("spp", C.c_int32), ("max_depth", C.c_int32), ("seed", C.c_uint64),
+                ("sample_offset", C.c_int64), ("env_radiance", C.c_float * 3), ("mis_mode", C.c_int32),
+                ("nrc_mode", C.c_int32), ("nrc_terminate_after", C.c_int32),
+                ("nrc_train_records", C.c_int32)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("paths", C.c_int64), ("collision_rays", C.c_int64), ("light_rays", C.c_int64),
+                ("env_rays", C.c_int64), ("node_visits", C.c_int64), ("prim_tests", C.c_int64),
+                ("prim_reloads", C.c_int64), ("ms_collide", C.c_double), ("ms_collide_wide", C.c_double),
+                ("ms_light", C.c_double), ("ms_env", C.c_double), ("launches_collide", C.c_int32),
+                ("launches_light", C.c_int32), ("launches_env", C.c_int32),
+                ("cat_nodes", C.c_int64 * 4), ("cat_prims", C.c_int64 * 4), ("cat_reloads", C.c_int64 * 4)]
+
+
+EXPORTS = ["ugp_create", "ugp_destroy", "ugp_set_stream", "ugp_build_bvh", "ugp_transmittance",
+           "ugp_sample_collision", "ugp_saturation", "ugp_emitter_query", "ugp_render", "ugp_sync",
+           "ugp_set_profiling", "ugp_get_render_stats", "ugp_trace_counts", "ugp_status_string"]
+
+
+def lib():
+    """Load libugp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_2406_09733_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i64 = C.c_void_p, C.c_int64
+        L.ugp_create.argtypes = [C.c_int, vp, C.POINTER(vp)]
+        L.ugp_destroy.argtypes = [vp]
+        L.ugp_set_stream.argtypes = [vp, vp]
+        L.ugp_build_bvh.argtypes = [vp, C.POINTER(_Scene), C.c_float]
+        L.ugp_transmittance.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.ugp_sample_collision.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+        L.ugp_saturation.argtypes = [vp, i64, vp, vp, vp]
+        L.ugp_emitter_query.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.ugp_render.argtypes = [vp, C.POINTER(_Camera), C.POINTER(_Params), vp, vp]
+        L.ugp_sync.argtypes = [vp]
+        L.ugp_set_profiling.argtypes = [vp, C.c_int]
+        L.ugp_trace_counts.argtypes = [vp, C.c_int, i64, vp, vp, vp, vp, vp]
+        L.ugp_get_render_stats.argtypes = [vp, C.POINTER(_Stats)]
+        L.ugp_status_string.argtypes = [C.c_int]
+        L.ugp_status_string.restype = C.c_char_p
+        for name in EXPORTS:
+            if name != "ugp_status_string":
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(call: str, code: int):
+    if code != 0:
+        raise UGPError(call, code)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A libugp context bound to one GPU and a HIP stream (torch's current
+    stream by default).  Owns the packed scene and the BVH."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _check("ugp_create", lib().ugp_create(device, C.c_void_p(self._stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self.n = 0
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().ugp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self, a, dtype, shape=None):
+        t = self.torch.as_tensor(a)
+        t = t.to(device=self.device, dtype=dtype).contiguous()
+        if shape is not None:
+            assert tuple(t.shape) == tuple(shape), (t.shape, shape)
+        return t
+
+    # ---- scene -----------------------------------------------------------
+    def build_bvh(self, scene: dict, cutoff_eps: float = 0.01):
+        """ugp_build_bvh: pack the primitives and build the hierarchy."""
+        torch = self.torch
+        n = int(np.asarray(scene["mean"]).shape[0]) if not torch.is_tensor(scene["mean"]) else scene["mean"].shape[0]
+        t = {
+            "mean": self._dev(scene["mean"], torch.float32, (n, 3)),
+            "scale": self._dev(scene["scale"], torch.float32, (n, 3)),
+            "rotation": self._dev(scene["rotation"], torch.float32, (n, 4)),
+            "density": self._dev(scene["density"], torch.float32, (n,)),
+            "albedo": self._dev(scene["albedo"], torch.float32, (n, 3)),
+            "roughness": self._dev(scene["roughness"], torch.float32, (n,)),
+            "emission": self._dev(scene["emission"], torch.float32, (n, 3)),
+            "material": self._dev(scene["material"], torch.int32, (n,)),
+        }
+        s = _Scene(n, *[t[k].data_ptr() for k in ("mean", "scale", "rotation", "density", "albedo",
+                                                  "roughness", "emission", "material")])
+        _check("ugp_build_bvh", lib().ugp_build_bvh(self.h, C.byref(s), float(cutoff_eps)))
+        self.n = n
+        return self
+
+    # ---- per-ray queries --------------------------------------------------
+    def _rays(self, rays):
+        r = self._dev(rays, self.torch.float32)
+        assert r.ndim == 2 and r.shape[1] == 8
+        return r
+
+    def _excl(self, exclude, n):
+        return None if exclude is None else self._dev(exclude, self.torch.int32, (n,))
+
+    def transmittance(self, rays, exclude=None, want_F: bool = False):
+        """ugp_transmittance -> (T, F or None)"""
+        r = self._rays(rays)
+        n = r.shape[0]
+        e = self._excl(exclude, n)
+        T = self.torch.empty(n, device=self.device, dtype=self.torch.float32)
+        F = self.torch.empty_like(T) if want_F else None
+        _check("ugp_transmittance", lib().ugp_transmittance(self.h, n, _ptr(r), _ptr(e), _ptr(T), _ptr(F)))
+        return T, F
+
+    def sample_collision(self, rays, u, exclude=None):
+        """ugp_sample_collision -> (prim int32, t float32)"""
+        r = self._rays(rays)
+        n = r.shape[0]
+        e = self._excl(exclude, n)
+        uu = self._dev(u, self.torch.float32, (n,))
+        prim = self.torch.empty(n, device=self.device, dtype=self.torch.int32)
+        t = self.torch.empty(n, device=self.device, dtype=self.torch.float32)
+        _check("ugp_sample_collision",
+               lib().ugp_sample_collision(self.h, n, _ptr(r), _ptr(e), _ptr(uu), _ptr(prim), _ptr(t)))
+        return prim, t
+
+    def saturation(self, rays, exclude=None):
+        """ugp_saturation -> t_sat float32"""
+        r = self._rays(rays)
+        n = r.shape[0]
+        e = self._excl(exclude, n)
+        t = self.torch.empty(n, device=self.device, dtype=self.torch.float32)
+        _check("ugp_saturation", lib().ugp_saturation(self.h, n, _ptr(r), _ptr(e), _ptr(t)))
+        return t
+
+    def emitter_query(self, rays, target, exclude=None):
+        """ugp_emitter_query -> 1/2 I_target(a, min(b, t_sat)) float32"""
+        r = self._rays(rays)
+        n = r.shape[0]
+        e = self._excl(exclude, n)
+        tg = self._dev(target, self.torch.int32, (n,))
+        out = self.torch.empty(n, device=self.device, dtype=self.torch.float32)
+        _check("ugp_emitter_query", lib().ugp_emitter_query(self.h, n, _ptr(r), _ptr(e), _ptr(tg), _ptr(out)))
+        return out
+
+    def trace_counts(self, mode: int, rays, u=None, target=None, exclude=None):
+        """ugp_trace_counts -> int32 [n, 4] (nodes, prims, reloads, rounds) per ray"""
+        r = self._rays(rays)
+        n = r.shape[0]
+        e = self._excl(exclude, n)
+        uu = None if u is None else self._dev(u, self.torch.float32, (n,))
+        tg = None if target is None else self._dev(target, self.torch.int32, (n,))
+        out = self.torch.zeros((n, 4), device=self.device, dtype=self.torch.int32)
+        _check("ugp_trace_counts", lib().ugp_trace_counts(self.h, int(mode), n, _ptr(r), _ptr(e), _ptr(uu),
+                                                          _ptr(tg), _ptr(out)))
+        return out
+
+    # ---- path tracing -----------------------------------------------------
+    def render(self, cam: dict, params: dict, sum_rgb=None, sumsq_rgb=None):
+        """ugp_render: adds this call's per-pixel sums of path radiance (and of
+        its square) into sum_rgb / sumsq_rgb [H, W, 3] float32 (allocated if
+        None) and returns them."""
+        torch = self.torch
+        W, H = int(cam["width"]), int(cam["height"])
+        if sum_rgb is None:
+            sum_rgb = torch.zeros((H, W, 3), device=self.device, dtype=torch.float32)
+        if sumsq_rgb is None and params.get("want_sumsq", True):
+            sumsq_rgb = torch.zeros((H, W, 3), device=self.device, dtype=torch.float32)
+        c = _Camera()
+        for i in range(3):
+            c.origin[i] = cam["origin"][i]
+            c.target[i] = cam["target"][i]
+            c.up[i] = cam["up"][i]
+        c.vfov_deg = cam["vfov_deg"]
+        c.width, c.height = W, H
+        p = _Params()
+        p.spp = int(params.get("spp", 1))
+        p.max_depth = int(params.get("max_depth", 4))
+        p.seed = int(params.get("seed", 0))
+        p.sample_offset = int(params.get("sample_offset", 0))
+        env = params.get("env_radiance", (0.0, 0.0, 0.0))
+        for i in range(3):
+            p.env_radiance[i] = float(env[i])
+        p.mis_mode = int(params.get("mis_mode", 0))
+        p.nrc_mode = int(params.get("nrc_mode", 0))
+        p.nrc_terminate_after = int(params.get("nrc_terminate_after", 2))
+        p.nrc_train_records = int(params.get("nrc_train_records", 65536))
+        _check("ugp_render", lib().ugp_render(self.h, C.byref(c), C.byref(p), _ptr(sum_rgb), _ptr(sumsq_rgb)))
+        return sum_rgb, sumsq_rgb
+
+    def sync(self):
+        _check("ugp_sync", lib().ugp_sync(self.h))
+
+    def set_profiling(self, level: int):
+        """ugp_set_profiling: 0 off, 1 time kernels with HIP events, 2 also count traversal work."""
+        _check("ugp_set_profiling", lib().ugp_set_profiling(self.h, int(level)))
+
+    def render_stats(self) -> dict:
+        """ugp_get_render_stats of the last render (synchronises)."""
+        st = _Stats()
+        _check("ugp_get_render_stats", lib().ugp_get_render_stats(self.h, C.byref(st)))
+        d = {}
+        for name, _ in _Stats._fields_:
+            v = getattr(st, name)
+            d[name] = list(v) if name.startswith("cat_") else v
+        d["rays"] = d["collision_rays"] + d["light_rays"] + d["env_rays"]
+        return d

@@ -1,0 +1,277 @@
+// api.hip -- the C ABI of libugp (declared in include/ugp.h): host-side
+// argument checks, the context, and dispatch to the kernels.  No C++ exception
+// crosses this boundary; every failure is a ugp_status.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "ugp_internal.hpp"
+
+namespace ugp {
+
+void *ctx_scratch(ugp_ctx ctx, size_t bytes) {
+    if (ctx->scratch_bytes >= bytes) return ctx->scratch;
+    hipStreamSynchronize(ctx->stream);
+    hipFree(ctx->scratch);
+    ctx->scratch = nullptr;
+    ctx->scratch_bytes = 0;
+    const size_t want = bytes < (1u << 20) ? (1u << 20) : bytes;
+    if (hipMalloc(&ctx->scratch, want) != hipSuccess) return nullptr;
+    ctx->scratch_bytes = want;
+    return ctx->scratch;
+}
+
+}  // namespace ugp
+
+namespace {
+
+ugp_status from_hip(hipError_t e) {
+    if (e == hipSuccess) return UGP_OK;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return UGP_ERR_OUT_OF_MEMORY;
+    if (e == hipErrorInvalidValue) return UGP_ERR_INVALID_ARGUMENT;
+    if (e == hipErrorNotSupported) return UGP_ERR_UNSUPPORTED;
+    return UGP_ERR_DEVICE;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int d) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != d) hipSetDevice(d);
+    }
+    ~DeviceGuard() {
+        int cur;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) hipSetDevice(prev);
+    }
+};
+
+bool query_args_ok(ugp_ctx ctx, int64_t n, const float *rays) {
+    return ctx && n >= 0 && n < (int64_t(1) << 31) && (n == 0 || rays);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ugp_status_string(ugp_status s) {
+    switch (s) {
+        case UGP_OK: return "ok";
+        case UGP_ERR_INVALID_ARGUMENT: return "invalid argument";
+        case UGP_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case UGP_ERR_DEVICE: return "device error";
+        case UGP_ERR_NO_SCENE: return "no scene has been built";
+        case UGP_ERR_UNSUPPORTED: return "unsupported (device or scene)";
+        case UGP_ERR_OVERFLOW: return "a per-ray buffer overflowed";
+    }
+    return "unknown status";
+}
+
+ugp_status ugp_create(int device, void *hip_stream, ugp_ctx *out) {
+    if (!out) return UGP_ERR_INVALID_ARGUMENT;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return UGP_ERR_DEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return UGP_ERR_DEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return UGP_ERR_UNSUPPORTED;
+    DeviceGuard g(device);
+    ugp_ctx c = new (std::nothrow) ugp_ctx_s();
+    if (!c) return UGP_ERR_OUT_OF_MEMORY;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipMalloc((void **)&c->err, sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc((void **)&c->stats, sizeof(int64_t) * 4) != hipSuccess) {
+        hipFree(c->err);
+        delete c;
+        return UGP_ERR_OUT_OF_MEMORY;
+    }
+    hipMemset(c->err, 0, sizeof(uint32_t));
+    hipMemset(c->stats, 0, sizeof(int64_t) * 4);
+    *out = c;
+    return UGP_OK;
+}
+
+ugp_status ugp_destroy(ugp_ctx ctx) {
+    if (!ctx) return UGP_ERR_INVALID_ARGUMENT;
+    DeviceGuard g(ctx->device);
+    hipStreamSynchronize(ctx->stream);
+    ugp::free_scene(ctx->scene);
+    ugp::free_render(ctx);
+    hipFree(ctx->scratch);
+    hipFree(ctx->err);
+    hipFree(ctx->stats);
+    hipFree(ctx->counters);
+    for (hipEvent_t ev : ctx->ev_pool) hipEventDestroy(ev);
+    delete ctx;
+    return UGP_OK;
+}
+
+ugp_status ugp_set_stream(ugp_ctx ctx, void *hip_stream) {
+    if (!ctx) return UGP_ERR_INVALID_ARGUMENT;
+    ctx->stream = (hipStream_t)hip_stream;
+    return UGP_OK;
+}
+
+ugp_status ugp_build_bvh(ugp_ctx ctx, const ugp_scene *s, float eps) {
+    if (!ctx || !s || s->n < 1 || s->n >= (int64_t(1) << 31) || !(eps > 0.f && eps < 1.f)) return UGP_ERR_INVALID_ARGUMENT;
+    if (!s->mean || !s->scale || !s->rotation || !s->density || !s->albedo || !s->roughness ||
+        !s->emission || !s->material)
+        return UGP_ERR_INVALID_ARGUMENT;
+    DeviceGuard g(ctx->device);
+    return from_hip(ugp::build_scene(ctx, s, eps));
+}
+
+ugp_status ugp_transmittance(ugp_ctx ctx, int64_t n, const float *rays, const int32_t *exclude, float *T,
+                             float *F) {
+    if (!query_args_ok(ctx, n, rays) || (n > 0 && !T)) return UGP_ERR_INVALID_ARGUMENT;
+    if (ctx->scene.n == 0) return UGP_ERR_NO_SCENE;
+    if (n == 0) return UGP_OK;
+    DeviceGuard g(ctx->device);
+    return from_hip(ugp::launch_transmittance(ctx, n, rays, exclude, T, F));
+}
+
+ugp_status ugp_sample_collision(ugp_ctx ctx, int64_t n, const float *rays, const int32_t *exclude,
+                                const float *u, int32_t *prim, float *t) {
+    if (!query_args_ok(ctx, n, rays) || (n > 0 && (!u || !prim || !t))) return UGP_ERR_INVALID_ARGUMENT;
+    if (ctx->scene.n == 0) return UGP_ERR_NO_SCENE;
+    if (n == 0) return UGP_OK;
+    DeviceGuard g(ctx->device);
+    return from_hip(ugp::launch_sweep(ctx, ugp::kModeCollide, n, rays, exclude, u, nullptr, prim, t));
+}
+
+ugp_status ugp_saturation(ugp_ctx ctx, int64_t n, const float *rays, const int32_t *exclude, float *tsat) {
+    if (!query_args_ok(ctx, n, rays) || (n > 0 && !tsat)) return UGP_ERR_INVALID_ARGUMENT;
+    if (ctx->scene.n == 0) return UGP_ERR_NO_SCENE;
+    if (n == 0) return UGP_OK;
+    DeviceGuard g(ctx->device);
+    return from_hip(ugp::launch_sweep(ctx, ugp::kModeSaturate, n, rays, exclude, nullptr, nullptr, nullptr, tsat));
+}
+
+ugp_status ugp_emitter_query(ugp_ctx ctx, int64_t n, const float *rays, const int32_t *exclude,
+                             const int32_t *target, float *out) {
+    if (!query_args_ok(ctx, n, rays) || (n > 0 && (!target || !out))) return UGP_ERR_INVALID_ARGUMENT;
+    if (ctx->scene.n == 0) return UGP_ERR_NO_SCENE;
+    if (n == 0) return UGP_OK;
+    DeviceGuard g(ctx->device);
+    return from_hip(ugp::launch_sweep(ctx, ugp::kModeEmitter, n, rays, exclude, nullptr, target, nullptr, out));
+}
+
+ugp_status ugp_trace_counts(ugp_ctx ctx, int mode, int64_t n, const float *rays, const int32_t *exclude,
+                            const float *u, const int32_t *target, int32_t *counts) {
+    if (!query_args_ok(ctx, n, rays) || (n > 0 && !counts) || mode < 0 || mode > 2) return UGP_ERR_INVALID_ARGUMENT;
+    if (mode == ugp::kModeCollide && n > 0 && !u) return UGP_ERR_INVALID_ARGUMENT;
+    if (mode == ugp::kModeEmitter && n > 0 && !target) return UGP_ERR_INVALID_ARGUMENT;
+    if (ctx->scene.n == 0) return UGP_ERR_NO_SCENE;
+    if (n == 0) return UGP_OK;
+    DeviceGuard g(ctx->device);
+    float *scratch = (float *)ugp::ctx_scratch(ctx, 0);
+    (void)scratch;
+    float *fo = nullptr;
+    int32_t *po = nullptr;
+    if (hipMallocAsync((void **)&fo, sizeof(float) * n, ctx->stream) != hipSuccess) return UGP_ERR_OUT_OF_MEMORY;
+    if (hipMallocAsync((void **)&po, sizeof(int32_t) * n, ctx->stream) != hipSuccess) {
+        hipFreeAsync(fo, ctx->stream);
+        return UGP_ERR_OUT_OF_MEMORY;
+    }
+    hipError_t e = ugp::launch_sweep(ctx, mode, n, rays, exclude, u, target, po, fo, counts);
+    hipFreeAsync(fo, ctx->stream);
+    hipFreeAsync(po, ctx->stream);
+    return from_hip(e);
+}
+
+ugp_status ugp_render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p, float *sum,
+                      float *sumsq) {
+    if (!ctx || !cam || !p || !sum) return UGP_ERR_INVALID_ARGUMENT;
+    if (cam->width < 1 || cam->height < 1 || (int64_t)cam->width * cam->height >= (int64_t(1) << 31) ||
+        !(cam->vfov_deg > 0.f && cam->vfov_deg < 180.f))
+        return UGP_ERR_INVALID_ARGUMENT;
+    if (p->spp < 1 || p->max_depth < 0 || p->max_depth > 1000 || p->mis_mode < 0 || p->mis_mode > 2 ||
+        p->sample_offset < 0 || p->sample_offset + p->spp > (int64_t(1) << 32))
+        return UGP_ERR_INVALID_ARGUMENT;
+    for (int c = 0; c < 3; ++c)
+        if (!(p->env_radiance[c] >= 0.f) || !std::isfinite(p->env_radiance[c])) return UGP_ERR_INVALID_ARGUMENT;
+    if (p->nrc_mode != 0) return UGP_ERR_UNSUPPORTED;
+    if (ctx->scene.n == 0) return UGP_ERR_NO_SCENE;
+    DeviceGuard g(ctx->device);
+    return from_hip(ugp::render(ctx, cam, p, sum, sumsq));
+}
+
+ugp_status ugp_sync(ugp_ctx ctx) {
+    if (!ctx) return UGP_ERR_INVALID_ARGUMENT;
+    DeviceGuard g(ctx->device);
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return from_hip(e);
+    uint32_t h = 0;
+    e = hipMemcpy(&h, ctx->err, sizeof(uint32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return from_hip(e);
+    if (h) {
+        hipMemset(ctx->err, 0, sizeof(uint32_t));
+        return UGP_ERR_OVERFLOW;
+    }
+    return UGP_OK;
+}
+
+ugp_status ugp_set_profiling(ugp_ctx ctx, int level) {
+    if (!ctx || level < 0 || level > 2) return UGP_ERR_INVALID_ARGUMENT;
+    if (level >= 2 && !ctx->counters) {
+        DeviceGuard g(ctx->device);
+        if (hipMalloc((void **)&ctx->counters, sizeof(unsigned long long) * 12) != hipSuccess)
+            return UGP_ERR_OUT_OF_MEMORY;
+    }
+    ctx->profiling = level;
+    return UGP_OK;
+}
+
+ugp_status ugp_get_render_stats(ugp_ctx ctx, ugp_render_stats *out) {
+    if (!ctx || !out) return UGP_ERR_INVALID_ARGUMENT;
+    DeviceGuard g(ctx->device);
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    int64_t h[4] = {0, 0, 0, 0};
+    if (e == hipSuccess) e = hipMemcpy(h, ctx->stats, sizeof(h), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return from_hip(e);
+    std::memset(out, 0, sizeof(*out));
+    out->paths = ctx->last_paths;
+    out->collision_rays = h[0];
+    out->light_rays = h[1];
+    out->env_rays = h[2];
+    out->node_visits = out->prim_tests = out->prim_reloads = -1;
+    for (int c = 0; c < 4; ++c) out->cat_nodes[c] = out->cat_prims[c] = out->cat_reloads[c] = -1;
+    if (ctx->profiling >= 2 && ctx->counters) {
+        unsigned long long c[12];
+        e = hipMemcpy(c, ctx->counters, sizeof(c), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return from_hip(e);
+        out->node_visits = out->prim_tests = out->prim_reloads = 0;
+        for (int k = 0; k < 4; ++k) {
+            out->cat_nodes[k] = (int64_t)c[3 * k];
+            out->cat_prims[k] = (int64_t)c[3 * k + 1];
+            out->cat_reloads[k] = (int64_t)c[3 * k + 2];
+            out->node_visits += out->cat_nodes[k];
+            out->prim_tests += out->cat_prims[k];
+            out->prim_reloads += out->cat_reloads[k];
+        }
+    }
+    out->ms_collide = out->ms_collide_wide = out->ms_light = out->ms_env = -1.0;
+    if (ctx->ev_cat_valid) {
+        double ms[4] = {0, 0, 0, 0};
+        int cnt[4] = {0, 0, 0, 0};
+        for (const auto &u : ctx->ev_used) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, ctx->ev_pool[u.second], ctx->ev_pool[u.second + 1]) == hipSuccess) {
+                ms[u.first] += t;
+                cnt[u.first] += 1;
+            }
+        }
+        out->ms_collide = ms[0];
+        out->ms_collide_wide = ms[1];
+        out->ms_light = ms[2];
+        out->ms_env = ms[3];
+        out->launches_collide = cnt[0];
+        out->launches_light = cnt[2];
+        out->launches_env = cnt[3];
+    }
+    return UGP_OK;
+}
+
+}  // extern "C"

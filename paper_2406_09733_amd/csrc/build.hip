@@ -1,0 +1,578 @@
+// build.hip -- scene packing and linear BVH construction on the GPU.
+//
+// 1. pack: per primitive (FP64 from the FP32 inputs) the rotation R from the
+//    quaternion, the facet normal R e_argmin(s), the bounding-sphere radius
+//    r max(s) and the box of the cut-off ellipsoid |S^-1 R^T (x - mu)| = r
+//    (eq. cutoff_threshold), half-extent r sqrt(sum_i (R_ji s_i)^2), rounded
+//    outward to float.  Inputs are validated here.
+// 2. 30-bit Morton codes of the box centres in the scene bounds.
+// 3. Stable LSD radix sort of (code, original index), 4 passes of 8 bits.
+// 4. Binary radix tree over the sorted codes (Karras, "Maximizing Parallelism
+//    in the Construction of BVHs, Octrees, and k-d Trees", HPG 2012); equal
+//    codes are split by position.
+// 5. Bottom-up refit: every leaf climbs, the second child to arrive at a node
+//    forms its box (agent-scope atomics and fences, so it is safe across XCDs).
+// 6. Scatter the hot / cold records into leaf order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "ugp_internal.hpp"
+
+namespace ugp {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ float round_down(double x) {
+    float f = (float)x;
+    return ((double)f > x) ? nextafterf(f, -__builtin_huge_valf()) : f;
+}
+__device__ __forceinline__ float round_up(double x) {
+    float f = (float)x;
+    return ((double)f < x) ? nextafterf(f, __builtin_huge_valf()) : f;
+}
+
+// order-preserving float <-> uint for atomic min / max
+__device__ __forceinline__ uint32_t f2o(float f) {
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__host__ __device__ __forceinline__ float o2f(uint32_t u) {
+    uint32_t v = (u & 0x80000000u) ? (u & 0x7fffffffu) : ~u;
+    float f;
+    __builtin_memcpy(&f, &v, 4);
+    return f;
+}
+
+struct PackIn {
+    int64_t n;
+    const float *mean, *scale, *rot, *dens, *alb, *rough, *emis;
+    const int32_t *mat;
+    double r;
+};
+
+// boxes [n][6] (lo.xyz, hi.xyz) in original order; cold written in original
+// order into a temporary; bounds[6] ordered-uint min/max of box centres
+__global__ void k_pack(PackIn in, float *boxes, float4 *cold_tmp, uint32_t *bounds, uint32_t *err) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= in.n) return;
+    const double qw = in.rot[4 * k], qx = in.rot[4 * k + 1], qy = in.rot[4 * k + 2], qz = in.rot[4 * k + 3];
+    const double s[3] = {in.scale[3 * k], in.scale[3 * k + 1], in.scale[3 * k + 2]};
+    const double mu[3] = {in.mean[3 * k], in.mean[3 * k + 1], in.mean[3 * k + 2]};
+    const double qn = qw * qw + qx * qx + qy * qy + qz * qz;
+    const float d = in.dens[k];
+    const int m = in.mat[k];
+    bool bad = !(qn > 0.0) || !isfinite(qn) || !(d >= 0.f) || !isfinite(d) || (m != 0 && m != 1);
+    for (int i = 0; i < 3; ++i) bad = bad || !(s[i] > 0.0) || !isfinite(s[i]) || !isfinite(mu[i]);
+    if (bad) {
+        atomicOr(err, 8u);
+        for (int i = 0; i < 6; ++i) boxes[6 * k + i] = 0.f;
+        return;
+    }
+    const double t = 2.0 / qn;
+    const double xx = qx * qx * t, yy = qy * qy * t, zz = qz * qz * t;
+    const double xy = qx * qy * t, xz = qx * qz * t, yz = qy * qz * t;
+    const double wx = qw * qx * t, wy = qw * qy * t, wz = qw * qz * t;
+    const double R[3][3] = {{1.0 - yy - zz, xy - wz, xz + wy},
+                            {xy + wz, 1.0 - xx - zz, yz - wx},
+                            {xz - wy, yz + wx, 1.0 - xx - yy}};
+    int am = 0;
+    if (s[1] < s[am]) am = 1;
+    if (s[2] < s[am]) am = 2;
+    const double smax = fmax(s[0], fmax(s[1], s[2]));
+    float lo[3], hi[3];
+    for (int j = 0; j < 3; ++j) {
+        double h2 = 0.0;
+        for (int i = 0; i < 3; ++i) h2 += (R[j][i] * s[i]) * (R[j][i] * s[i]);
+        const double h = in.r * sqrt(h2) * (1.0 + 1e-6);
+        lo[j] = round_down(mu[j] - h);
+        hi[j] = round_up(mu[j] + h);
+        boxes[6 * k + j] = lo[j];
+        boxes[6 * k + 3 + j] = hi[j];
+    }
+    cold_tmp[3 * k] = make_float4((float)R[0][am], (float)R[1][am], (float)R[2][am], __int_as_float(m));
+    cold_tmp[3 * k + 1] = make_float4(in.alb[3 * k], in.alb[3 * k + 1], in.alb[3 * k + 2], in.rough[k]);
+    cold_tmp[3 * k + 2] = make_float4(in.emis[3 * k], in.emis[3 * k + 1], in.emis[3 * k + 2],
+                                      (float)(in.r * smax));
+    for (int j = 0; j < 3; ++j) {
+        const float c = 0.5f * (lo[j] + hi[j]);
+        atomicMin(&bounds[j], f2o(c));
+        atomicMax(&bounds[3 + j], f2o(c));
+    }
+}
+
+__global__ void k_init_bounds(uint32_t *b) {
+    if (threadIdx.x < 3) b[threadIdx.x] = 0xffffffffu;
+    else if (threadIdx.x < 6) b[threadIdx.x] = 0u;
+}
+
+__device__ __forceinline__ uint32_t expand10(uint32_t v) {
+    v = (v * 0x00010001u) & 0xFF0000FFu;
+    v = (v * 0x00000101u) & 0x0F00F00Fu;
+    v = (v * 0x00000011u) & 0xC30C30C3u;
+    v = (v * 0x00000005u) & 0x49249249u;
+    return v;
+}
+
+__global__ void k_morton(int64_t n, const float *boxes, const uint32_t *bounds, uint32_t *keys,
+                         int32_t *vals) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    uint32_t code = 0;
+    uint32_t q[3];
+    for (int j = 0; j < 3; ++j) {
+        const float lo = o2f(bounds[j]), hi = o2f(bounds[3 + j]);
+        const float c = 0.5f * (boxes[6 * k + j] + boxes[6 * k + 3 + j]);
+        const float ext = hi - lo;
+        float f = ext > 0.f ? (c - lo) / ext : 0.5f;
+        f = fminf(fmaxf(f, 0.f), 1.f);
+        q[j] = min((uint32_t)(f * 1024.f), 1023u);
+    }
+    code = (expand10(q[0]) << 2) | (expand10(q[1]) << 1) | expand10(q[2]);
+    keys[k] = code;
+    vals[k] = (int32_t)k;
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of int32 (device-wide, recursive over block sums)
+// ---------------------------------------------------------------------------
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kThreads * kScanItems;
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int *sh, int &total) {
+    // Hillis-Steele over kThreads values in LDS
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kThreads; off <<= 1) {
+        const int x = t >= off ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += x;
+        __syncthreads();
+    }
+    total = sh[kThreads - 1];
+    const int incl = sh[t];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ void k_scan_tiles(const int *in, int *out, int64_t n, int *tile_sums) {
+    __shared__ int sh[kThreads];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int sum = 0;
+    for (int i = 0; i < kScanItems; ++i) {
+        v[i] = (base + i < n) ? in[base + i] : 0;
+        sum += v[i];
+    }
+    int total;
+    int run = block_exclusive_scan(sum, sh, total);
+    for (int i = 0; i < kScanItems; ++i) {
+        if (base + i < n) out[base + i] = run;
+        run += v[i];
+    }
+    if (threadIdx.x == 0 && tile_sums) tile_sums[blockIdx.x] = total;
+}
+
+__global__ void k_scan_add(int *out, int64_t n, const int *tile_off) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    const int add = tile_off[blockIdx.x];
+    for (int i = 0; i < kScanItems; ++i)
+        if (base + i < n) out[base + i] += add;
+}
+
+hipError_t exclusive_scan(const int *in, int *out, int64_t n, hipStream_t st) {
+    const int64_t tiles = (n + kScanTile - 1) / kScanTile;
+    if (tiles <= 1) {
+        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kThreads), 0, st, in, out, n, (int *)nullptr);
+        return hipGetLastError();
+    }
+    int *sums = nullptr;
+    hipError_t e = hipMallocAsync((void **)&sums, sizeof(int) * 2 * tiles, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(kThreads), 0, st, in, out, n, sums);
+    e = exclusive_scan(sums, sums + tiles, tiles, st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)tiles), dim3(kThreads), 0, st, out, n,
+                           (const int *)(sums + tiles));
+        e = hipGetLastError();
+    }
+    hipFreeAsync(sums, st);
+    return e;
+}
+
+// ---------------------------------------------------------------------------
+// stable LSD radix sort, 8-bit digits
+// ---------------------------------------------------------------------------
+constexpr int kSortChunks = 16;
+constexpr int kSortTile = kThreads * kSortChunks;
+
+__global__ void k_sort_hist(const uint32_t *keys, int64_t n, int shift, int *hist, int nblocks) {
+    __shared__ int h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int c = 0; c < kSortChunks; ++c) {
+        const int64_t i = base + (int64_t)c * kThreads + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void k_sort_scatter(const uint32_t *keys, const int32_t *vals, uint32_t *okeys,
+                               int32_t *ovals, int64_t n, int shift, const int *offs, int nblocks) {
+    __shared__ int base[256];
+    __shared__ int cnt[kThreads / 64][256];
+    const int t = threadIdx.x;
+    const int wave = t >> 6, lane = t & 63;
+    base[t] = offs[(int64_t)t * nblocks + blockIdx.x];
+    const int64_t tile = (int64_t)blockIdx.x * kSortTile;
+    for (int c = 0; c < kSortChunks; ++c) {
+        for (int w = 0; w < kThreads / 64; ++w) cnt[w][t] = 0;
+        __syncthreads();
+        const int64_t i = tile + (int64_t)c * kThreads + t;
+        const bool valid = i < n;
+        const uint32_t key = valid ? keys[i] : 0u;
+        const int32_t val = valid ? vals[i] : 0;
+        const uint32_t dig = (key >> shift) & 255u;
+        // lanes of this wave holding the same digit
+        uint64_t same = __ballot(valid);
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t bal = __ballot((dig >> b) & 1u);
+            same &= ((dig >> b) & 1u) ? bal : ~bal;
+        }
+        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        const int rank = __popcll(same & below);
+        if (valid && rank == 0) cnt[wave][dig] = __popcll(same);
+        __syncthreads();
+        if (valid) {
+            int pos = base[dig] + rank;
+            for (int w = 0; w < wave; ++w) pos += cnt[w][dig];
+            okeys[pos] = key;
+            ovals[pos] = val;
+        }
+        __syncthreads();
+        int tot = 0;
+        for (int w = 0; w < kThreads / 64; ++w) tot += cnt[w][t];
+        base[t] += tot;
+        __syncthreads();
+    }
+}
+
+hipError_t radix_sort(uint32_t *keys, int32_t *vals, uint32_t *tk, int32_t *tv, int64_t n,
+                      hipStream_t st) {
+    const int nblocks = (int)((n + kSortTile - 1) / kSortTile);
+    int *hist = nullptr;
+    hipError_t e = hipMallocAsync((void **)&hist, sizeof(int) * 2 * 256 * (size_t)nblocks, st);
+    if (e != hipSuccess) return e;
+    int *offs = hist + 256 * (size_t)nblocks;
+    uint32_t *ka = keys, *kb = tk;
+    int32_t *va = vals, *vb = tv;
+    for (int shift = 0; shift < 32 && e == hipSuccess; shift += 8) {
+        hipLaunchKernelGGL(k_sort_hist, dim3(nblocks), dim3(kThreads), 0, st, ka, n, shift, hist, nblocks);
+        e = exclusive_scan(hist, offs, 256 * (int64_t)nblocks, st);
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(k_sort_scatter, dim3(nblocks), dim3(kThreads), 0, st, ka, va, kb, vb, n, shift,
+                           offs, nblocks);
+        e = hipGetLastError();
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    hipFreeAsync(hist, st);
+    return e;  // 4 passes: result back in keys / vals
+}
+
+// ---------------------------------------------------------------------------
+// Karras radix tree
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int delta(const uint32_t *keys, int64_t n, int64_t i, int64_t j) {
+    if (j < 0 || j >= n) return -1;
+    const uint32_t a = keys[i], b = keys[j];
+    if (a == b) return 32 + __clz((uint32_t)(i ^ j));
+    return __clz(a ^ b);
+}
+
+__global__ void k_karras(const uint32_t *keys, int64_t n, float4 *nodes, int32_t *parent_node,
+                         int32_t *parent_leaf) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    const int d = (delta(keys, n, i, i + 1) - delta(keys, n, i, i - 1)) >= 0 ? 1 : -1;
+    const int dmin = delta(keys, n, i, i - d);
+    int64_t lmax = 2;
+    while (delta(keys, n, i, i + lmax * d) > dmin) lmax *= 2;
+    int64_t l = 0;
+    for (int64_t t = lmax / 2; t >= 1; t /= 2)
+        if (delta(keys, n, i, i + (l + t) * d) > dmin) l += t;
+    const int64_t j = i + l * d;
+    const int dnode = delta(keys, n, i, j);
+    int64_t s = 0, t = l;
+    do {
+        t = (t + 1) >> 1;
+        if (delta(keys, n, i, i + (s + t) * d) > dnode) s += t;
+    } while (t > 1);
+    const int64_t gamma = i + s * d + (d < 0 ? -1 : 0);
+    const int64_t lo = i < j ? i : j, hi = i < j ? j : i;
+    int32_t left, right;
+    if (lo == gamma) {
+        left = ~(int32_t)gamma;
+        parent_leaf[gamma] = (int32_t)i;
+    } else {
+        left = (int32_t)gamma;
+        parent_node[gamma] = (int32_t)i;
+    }
+    if (hi == gamma + 1) {
+        right = ~(int32_t)(gamma + 1);
+        parent_leaf[gamma + 1] = (int32_t)i;
+    } else {
+        right = (int32_t)(gamma + 1);
+        parent_node[gamma + 1] = (int32_t)i;
+    }
+    nodes[4 * i + 3] = make_float4(__int_as_float(left), __int_as_float(right), 0.f, 0.f);
+}
+
+// Structural check of the radix tree before anything climbs it: every child
+// ref is in range, the root is nobody's child, and every other node and every
+// leaf has exactly one parent.  Failures set bit 16 of the error word and the
+// kernels that follow return at once.
+__global__ void k_validate_refs(int64_t n, const float4 *nodes, int32_t *pc_node, int32_t *pc_leaf,
+                                uint32_t *err) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    const float4 n3 = nodes[4 * i + 3];
+    const int32_t c[2] = {__float_as_int(n3.x), __float_as_int(n3.y)};
+    for (int k = 0; k < 2; ++k) {
+        if (c[k] >= 0) {
+            if (c[k] == 0 || c[k] >= n - 1) atomicOr(err, 16u);
+            else atomicAdd(&pc_node[c[k]], 1);
+        } else {
+            const int64_t leaf = ~c[k];
+            if (leaf >= n) atomicOr(err, 16u);
+            else atomicAdd(&pc_leaf[leaf], 1);
+        }
+    }
+}
+
+__global__ void k_validate_counts(int64_t n, const int32_t *pc_node, const int32_t *pc_leaf, uint32_t *err) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && pc_leaf[i] != 1) atomicOr(err, 16u);
+    if (i < n - 1 && pc_node[i] != (i == 0 ? 0 : 1)) atomicOr(err, 16u);
+}
+
+__device__ __forceinline__ void write_child_box(float4 *nodes, int32_t p, bool left, const float b[6]) {
+    float *nd = reinterpret_cast<float *>(nodes + 4 * (int64_t)p);
+    const int o = left ? 0 : 6;
+    for (int i = 0; i < 6; ++i)
+        __hip_atomic_store(&nd[o + i], b[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void k_refit(int64_t n, const int32_t *sorted_orig, const float *boxes, float4 *nodes,
+                        const int32_t *parent_node, const int32_t *parent_leaf, int32_t *flags,
+                        const uint32_t *err) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || (*err & 16u)) return;
+    float b[6];
+    const int32_t o = sorted_orig[i];
+    for (int c = 0; c < 6; ++c) b[c] = boxes[6 * (int64_t)o + c];
+    int32_t child = ~(int32_t)i;
+    int32_t p = parent_leaf[i];
+    while (true) {
+        const float4 n3 = nodes[4 * (int64_t)p + 3];
+        const bool left = __float_as_int(n3.x) == child;
+        write_child_box(nodes, p, left, b);
+        __threadfence();
+        const int old = __hip_atomic_fetch_add(&flags[p], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == 0) return;  // the sibling will finish this node
+        __threadfence();
+        const float *nd = reinterpret_cast<const float *>(nodes + 4 * (int64_t)p);
+        float v[12];
+        for (int c = 0; c < 12; ++c)
+            v[c] = __hip_atomic_load(&nd[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int c = 0; c < 3; ++c) {
+            b[c] = fminf(v[c], v[6 + c]);
+            b[3 + c] = fmaxf(v[3 + c], v[9 + c]);
+        }
+        if (p == 0) return;
+        child = p;
+        p = parent_node[p];
+    }
+}
+
+__global__ void k_depth(int64_t n, const int32_t *parent_node, const int32_t *parent_leaf, int32_t *depth,
+                        uint32_t *err) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || (*err & 16u)) return;
+    int d = 1;
+    int32_t p = parent_leaf[i];
+    while (true) {
+        ++d;
+        if (p == 0) break;
+        if (d > 4096) {  // a cycle: not a tree
+            atomicOr(err, 16u);
+            break;
+        }
+        p = parent_node[p];
+    }
+    atomicMax(depth, d);
+}
+
+__global__ void k_scatter(int64_t n, const int32_t *sorted_orig, PackIn in, const float4 *cold_tmp,
+                          float4 *hot, float4 *cold, int32_t *inv, int32_t *emit_flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t o = sorted_orig[i];
+    hot[3 * i] = make_float4(in.mean[3 * (int64_t)o], in.mean[3 * (int64_t)o + 1], in.mean[3 * (int64_t)o + 2],
+                             in.dens[o]);
+    hot[3 * i + 1] = make_float4(in.rot[4 * (int64_t)o], in.rot[4 * (int64_t)o + 1], in.rot[4 * (int64_t)o + 2],
+                                 in.rot[4 * (int64_t)o + 3]);
+    hot[3 * i + 2] = make_float4(in.scale[3 * (int64_t)o], in.scale[3 * (int64_t)o + 1],
+                                 in.scale[3 * (int64_t)o + 2], __int_as_float(o));
+    for (int c = 0; c < 3; ++c) cold[3 * i + c] = cold_tmp[3 * (int64_t)o + c];
+    inv[o] = (int32_t)i;
+    const float4 e = cold_tmp[3 * (int64_t)o + 2];
+    emit_flag[o] = (e.x > 0.f || e.y > 0.f || e.z > 0.f) ? 1 : 0;
+}
+
+__global__ void k_compact(int64_t n, const int32_t *flag, const int32_t *pos, int32_t *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && flag[i]) out[pos[i]] = (int32_t)i;
+}
+
+inline unsigned blocks(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+}  // namespace
+
+void free_scene(SceneDev &sc) {
+    hipFree(sc.hot);
+    hipFree(sc.cold);
+    hipFree(sc.nodes);
+    hipFree(sc.inv);
+    hipFree(sc.emit);
+    sc = SceneDev{};
+}
+
+#define UGP_CHECK(x)                      \
+    do {                                  \
+        hipError_t e_ = (x);              \
+        if (e_ != hipSuccess) goto fail;  \
+    } while (0)
+
+hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
+    hipStream_t st = ctx->stream;
+    const int64_t n = s->n;
+    SceneDev sc;
+    sc.n = n;
+    const double r = sqrt(-2.0 * log((double)eps));
+    sc.r2 = (float)(r * r);
+    PackIn in{n, s->mean, s->scale, s->rotation, s->density, s->albedo, s->roughness, s->emission,
+              s->material, r};
+    float *boxes = nullptr;
+    float4 *cold_tmp = nullptr;
+    uint32_t *bounds = nullptr, *keys = nullptr, *tk = nullptr;
+    int32_t *vals = nullptr, *tv = nullptr, *pnode = nullptr, *pleaf = nullptr, *flags = nullptr;
+    int32_t *emit_flag = nullptr, *emit_pos = nullptr, *depth = nullptr;
+    hipError_t e = hipSuccess;
+    uint32_t h_err = 0;
+    int32_t h_depth = 0, h_nemit = 0, h_last_flag = 0;
+    const int64_t ni = n > 1 ? n - 1 : 1;
+
+    UGP_CHECK(hipMalloc((void **)&sc.hot, sizeof(float4) * 3 * n));
+    UGP_CHECK(hipMalloc((void **)&sc.cold, sizeof(float4) * 3 * n));
+    UGP_CHECK(hipMalloc((void **)&sc.nodes, sizeof(float4) * 4 * ni));
+    UGP_CHECK(hipMalloc((void **)&sc.inv, sizeof(int32_t) * n));
+    UGP_CHECK(hipMallocAsync((void **)&boxes, sizeof(float) * 6 * n, st));
+    UGP_CHECK(hipMallocAsync((void **)&cold_tmp, sizeof(float4) * 3 * n, st));
+    UGP_CHECK(hipMallocAsync((void **)&bounds, sizeof(uint32_t) * 8, st));
+    UGP_CHECK(hipMallocAsync((void **)&keys, sizeof(uint32_t) * n, st));
+    UGP_CHECK(hipMallocAsync((void **)&tk, sizeof(uint32_t) * n, st));
+    UGP_CHECK(hipMallocAsync((void **)&vals, sizeof(int32_t) * n, st));
+    UGP_CHECK(hipMallocAsync((void **)&tv, sizeof(int32_t) * n, st));
+    UGP_CHECK(hipMallocAsync((void **)&pnode, sizeof(int32_t) * ni, st));
+    UGP_CHECK(hipMallocAsync((void **)&pleaf, sizeof(int32_t) * n, st));
+    UGP_CHECK(hipMallocAsync((void **)&flags, sizeof(int32_t) * ni, st));
+    UGP_CHECK(hipMallocAsync((void **)&emit_flag, sizeof(int32_t) * n, st));
+    UGP_CHECK(hipMallocAsync((void **)&emit_pos, sizeof(int32_t) * n, st));
+    UGP_CHECK(hipMallocAsync((void **)&depth, sizeof(int32_t), st));
+    UGP_CHECK(hipMemsetAsync(ctx->err, 0, sizeof(uint32_t), st));
+    UGP_CHECK(hipMemsetAsync(flags, 0, sizeof(int32_t) * ni, st));
+    UGP_CHECK(hipMemsetAsync(depth, 0, sizeof(int32_t), st));
+    hipLaunchKernelGGL(k_init_bounds, dim3(1), dim3(64), 0, st, bounds);
+    hipLaunchKernelGGL(k_pack, dim3(blocks(n)), dim3(kThreads), 0, st, in, boxes, cold_tmp, bounds, ctx->err);
+    hipLaunchKernelGGL(k_morton, dim3(blocks(n)), dim3(kThreads), 0, st, n, boxes, bounds, keys, vals);
+    UGP_CHECK(hipGetLastError());
+    UGP_CHECK(radix_sort(keys, vals, tk, tv, n, st));
+    if (n > 1) {
+        hipLaunchKernelGGL(k_karras, dim3(blocks(n - 1)), dim3(kThreads), 0, st, keys, n, sc.nodes, pnode, pleaf);
+        UGP_CHECK(hipMemsetAsync(emit_flag, 0, sizeof(int32_t) * n, st));
+        UGP_CHECK(hipMemsetAsync(emit_pos, 0, sizeof(int32_t) * n, st));
+        hipLaunchKernelGGL(k_validate_refs, dim3(blocks(n - 1)), dim3(kThreads), 0, st, n, sc.nodes, emit_pos,
+                           emit_flag, ctx->err);
+        hipLaunchKernelGGL(k_validate_counts, dim3(blocks(n)), dim3(kThreads), 0, st, n, emit_pos, emit_flag,
+                           ctx->err);
+        hipLaunchKernelGGL(k_refit, dim3(blocks(n)), dim3(kThreads), 0, st, n, vals, boxes, sc.nodes, pnode,
+                           pleaf, flags, (const uint32_t *)ctx->err);
+        hipLaunchKernelGGL(k_depth, dim3(blocks(n)), dim3(kThreads), 0, st, n, pnode, pleaf, depth, ctx->err);
+    }
+    hipLaunchKernelGGL(k_scatter, dim3(blocks(n)), dim3(kThreads), 0, st, n, vals, in, cold_tmp, sc.hot,
+                       sc.cold, sc.inv, emit_flag);
+    UGP_CHECK(hipGetLastError());
+    UGP_CHECK(exclusive_scan(emit_flag, emit_pos, n, st));
+    UGP_CHECK(hipMemcpyAsync(&h_nemit, emit_pos + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    UGP_CHECK(hipMemcpyAsync(&h_last_flag, emit_flag + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    UGP_CHECK(hipMemcpyAsync(&h_depth, depth, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    UGP_CHECK(hipMemcpyAsync(&h_err, ctx->err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    {
+        float rootb[12];
+        if (n > 1) UGP_CHECK(hipMemcpyAsync(rootb, sc.nodes, sizeof(float) * 12, hipMemcpyDeviceToHost, st));
+        else UGP_CHECK(hipMemcpyAsync(rootb, boxes, sizeof(float) * 6, hipMemcpyDeviceToHost, st));
+        UGP_CHECK(hipStreamSynchronize(st));
+        if (n > 1) {
+            for (int c = 0; c < 3; ++c) {
+                sc.lo[c] = std::min(rootb[c], rootb[6 + c]);
+                sc.hi[c] = std::max(rootb[3 + c], rootb[9 + c]);
+            }
+        } else {
+            for (int c = 0; c < 3; ++c) { sc.lo[c] = rootb[c]; sc.hi[c] = rootb[3 + c]; }
+        }
+    }
+    if (h_err & 8u) {
+        e = hipErrorInvalidValue;
+        goto fail;
+    }
+    if (h_err & 16u) {
+        e = hipErrorUnknown;
+        goto fail;
+    }
+    h_nemit += h_last_flag;
+    sc.n_emit = h_nemit;
+    sc.depth = n > 1 ? h_depth : 1;
+    sc.root = n > 1 ? 0 : ~0;
+    if (sc.depth > kStackSize) {
+        e = hipErrorNotSupported;
+        goto fail;
+    }
+    if (h_nemit > 0) {
+        UGP_CHECK(hipMalloc((void **)&sc.emit, sizeof(int32_t) * h_nemit));
+        hipLaunchKernelGGL(k_compact, dim3(blocks(n)), dim3(kThreads), 0, st, n, emit_flag, emit_pos, sc.emit);
+        UGP_CHECK(hipGetLastError());
+    }
+    hipFreeAsync(boxes, st); hipFreeAsync(cold_tmp, st); hipFreeAsync(bounds, st);
+    hipFreeAsync(keys, st); hipFreeAsync(tk, st); hipFreeAsync(vals, st); hipFreeAsync(tv, st);
+    hipFreeAsync(pnode, st); hipFreeAsync(pleaf, st); hipFreeAsync(flags, st);
+    hipFreeAsync(emit_flag, st); hipFreeAsync(emit_pos, st); hipFreeAsync(depth, st);
+    UGP_CHECK(hipStreamSynchronize(st));
+    free_scene(ctx->scene);
+    ctx->scene = sc;
+    return hipSuccess;
+fail:
+    hipStreamSynchronize(st);
+    hipFree(boxes); hipFree(cold_tmp); hipFree(bounds); hipFree(keys); hipFree(tk);
+    hipFree(vals); hipFree(tv); hipFree(pnode); hipFree(pleaf); hipFree(flags);
+    hipFree(emit_flag); hipFree(emit_pos); hipFree(depth);
+    free_scene(sc);
+    return e == hipSuccess ? hipErrorUnknown : e;
+}
+
+}  // namespace ugp

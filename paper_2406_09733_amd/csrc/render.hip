@@ -1,0 +1,500 @@
+// render.hip -- wavefront path tracer over Gaussian primitives (Sec. 5, table
+// tab:highlevel right column, eq. rte) with next-event estimation to emissive
+// primitives and to a constant environment, balance-heuristic MIS.
+//
+// One sample pass = raygen, then per vertex v = 1 .. max_depth+1:
+//   collide : primitive-level free-flight sampling of every live path; emission
+//             pick-up (MIS-weighted against the light pdf of the previous
+//             vertex); light / environment samples appended to their queues;
+//             phase sampling; surviving paths compacted into the next queue
+//             (wave ballot + one atomic per wave)
+//   light   : emitter query per light sample (emission rides on the
+//             free-flight pdf, so emitter k contributes L_e,k I_k(a, min(b,
+//             t_sat))/2 along the sampled direction)
+//   env     : transmittance per environment sample
+// and a final accumulation of each path's radiance into sum / sum of squares.
+// Random numbers: Philox4x32-10 keyed by the seed, counter (pixel, sample,
+// vertex, group): group 0 = (collision, emitter pick, cone u, cone v), group 1 =
+// (phase u, phase v, environment u, environment v); the camera jitter uses
+// vertex 0, group 0.
+#include <algorithm>
+
+#include "trace_device.hpp"
+
+namespace ugp {
+
+struct Queue {        // path (ray) queue, structure of arrays
+    float4 *a;        // origin.xyz, pdf of the previous phase sample (0 = camera ray)
+    float4 *b;        // direction.xyz, excluded primitive (original index bits)
+    float4 *c;        // throughput.rgb, pixel bits
+};
+struct LightQueue {   // light-sample queue
+    float4 *a;        // origin.xyz, target primitive bits
+    float4 *b;        // direction.xyz, excluded primitive bits
+    float4 *c;        // weight.rgb, pixel bits
+};
+
+struct RenderBuffers {
+    int64_t cap = 0;
+    int max_vertices = 0;
+    Queue q[2];
+    LightQueue nee, env;
+    float4 *L = nullptr;     // path radiance per pixel
+    int32_t *ovf = nullptr;  // overflow index list (cap entries)
+    int32_t *counts = nullptr;  // per vertex: [queue in, nee, env] ...
+    void *block = nullptr;
+};
+
+namespace {
+
+constexpr int kPersistBlocks = 4096;
+
+struct PassArgs {
+    CamDev cam;
+    uint64_t seed;
+    uint32_t sample;
+    int max_depth;
+    int mis_mode;
+    float env[3];
+    int has_env;
+};
+
+__device__ __forceinline__ V3 f3(float4 v) { return v3(v.x, v.y, v.z); }
+
+// light pdf of emitter (leaf position ke) seen from x: uniform cone over its
+// bounding sphere, times the uniform emitter choice; 0 inside the sphere
+__device__ __forceinline__ float nee_pdf(const SceneDev &S, int ke, V3 x) {
+    const float4 h0 = S.hot[3 * ke];
+    const float rs = S.cold[3 * ke + 2].w;
+    const V3 c = v3(h0.x - x.x, h0.y - x.y, h0.z - x.z);
+    const float d2 = dot(c, c);
+    if (d2 <= rs * rs) return 0.f;
+    const float sin2 = rs * rs / d2;
+    const float omc = sin2 / (1.f + sqrtf(fmaxf(0.f, 1.f - sin2)));
+    return 1.f / ((float)S.n_emit * 2.f * kPi * omc);
+}
+
+__global__ void k_raygen(PassArgs P, int64_t npix, Queue q, float4 *L) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    const Rng4 g = rng4(P.seed, (uint32_t)p, P.sample, 0, 0);
+    const int px = (int)(p % P.cam.width), py = (int)(p / P.cam.width);
+    const V3 d = camera_dir(P.cam, px, py, g.u[0], g.u[1]);
+    q.a[p] = make_float4(P.cam.ox, P.cam.oy, P.cam.oz, 0.f);
+    q.b[p] = make_float4(d.x, d.y, d.z, __int_as_float(-1));
+    q.c[p] = make_float4(1.f, 1.f, 1.f, __int_as_float((int)p));
+    L[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+__device__ __forceinline__ int wave_append(bool want, int32_t *counter) {
+    const uint64_t m = __ballot(want);
+    if (m == 0ull) return 0;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, __popcll(m));
+    base = __shfl(base, leader);
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    return base + __popcll(m & below);
+}
+
+// Paths whose collision overflows the register event buffer are listed in
+// `ovf` and redone by the wide instantiation (WIDE = true), which walks that
+// list instead of the queue.
+struct Overflow {
+    int32_t *idx;
+    int32_t *count;
+};
+
+template <int K, bool WIDE>
+__global__ __launch_bounds__(kBlock) void k_collide(SceneDev S, PassArgs P, int v, Queue qin,
+                                                    const int32_t *n_in, Queue qout, int32_t *n_out,
+                                                    LightQueue nee, int32_t *n_nee, LightQueue env,
+                                                    int32_t *n_env, float4 *L, int64_t *stats,
+                                                    Overflow ovf, uint32_t *err) {
+    __shared__ int stack[kStackSize * kBlock];
+    const int n = WIDE ? *ovf.count : *n_in;
+    if (!WIDE && blockIdx.x == 0 && threadIdx.x == 0)
+        atomicAdd((unsigned long long *)&stats[0], (unsigned long long)n);
+    TraceCount tc;
+    for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += (int64_t)gridDim.x * kBlock) {
+        const int64_t j = base + threadIdx.x;
+        const bool active = j < n;
+        bool cont = false, do_nee = false, do_env = false, spill = false;
+        float4 ca{}, cb{}, cc{}, na{}, nb{}, nc{}, ea{}, eb{}, ec{};
+        if (active) {
+            const int64_t i = WIDE ? (int64_t)ovf.idx[j] : j;
+            const float4 A = qin.a[i], B = qin.b[i], C = qin.c[i];
+            const int pix = __float_as_int(C.w);
+            const int excl = __float_as_int(B.w);
+            const float p_prev = A.w;
+            const V3 o = f3(A), d = f3(B);
+            V3 beta = f3(C);
+            const Rng4 g0 = rng4(P.seed, (uint32_t)pix, P.sample, (uint32_t)v, 0);
+            const Rng4 g1 = rng4(P.seed, (uint32_t)pix, P.sample, (uint32_t)v, 1);
+            const RayD r = make_ray(o.x, o.y, o.z, d.x, d.y, d.z, 0.0, __builtin_huge_val());
+            const SweepOut so = sweep<K>(S, r, excl, kModeCollide, g0.u[0], -1, stack, err, tc);
+            if (so.status != 0) {
+                if (WIDE) atomicOr(err, kErrEvents);
+                else spill = true;
+            }
+            V3 Ladd = v3(0.f, 0.f, 0.f);
+            if (spill) {
+                // redone by the wide pass
+            } else if (so.prim < 0 || so.status != 0) {
+                if (P.has_env) {
+                    float w = 1.f;
+                    if (v > 1) {
+                        if (P.mis_mode == 2) w = 0.f;
+                        else if (P.mis_mode == 0) w = p_prev / (p_prev + 0.25f * kInvPi);
+                    }
+                    Ladd = w * mul(beta, v3(P.env[0], P.env[1], P.env[2]));
+                }
+            } else {
+                const int k = so.prim;
+                const int ks = S.inv[k];
+                const float4 c0 = S.cold[3 * ks], c1 = S.cold[3 * ks + 1], c2 = S.cold[3 * ks + 2];
+                const V3 x = o + so.t * d;
+                const V3 Le = f3(c2);
+                if (nonzero(Le)) {
+                    float w = 1.f;
+                    if (v > 1) {
+                        const float pn = nee_pdf(S, ks, o);
+                        if (P.mis_mode == 2) w = pn > 0.f ? 0.f : 1.f;
+                        else if (P.mis_mode == 0) w = p_prev / (p_prev + pn);
+                    }
+                    Ladd = w * mul(beta, Le);
+                }
+                if (v <= P.max_depth) {
+                    const V3 wo = -d;
+                    const Facet F = facet(f3(c0), wo);
+                    const V3 wol = to_local(F, wo);
+                    const int mat = __float_as_int(c0.w);
+                    const V3 alb = f3(c1);
+                    const float rough = c1.w;
+                    // light sample: one emitter, uniform in the cone of its bounding sphere
+                    if (S.n_emit > 0 && P.mis_mode != 1) {
+                        // floor(u * n_emit) in exact integer arithmetic (u has 24 bits)
+                        int j = (int)(((uint64_t)(g0.u[1] * 16777216.f) * (uint64_t)S.n_emit) >> 24);
+                        j = min(j, S.n_emit - 1);
+                        const int e = S.emit[j];
+                        const int es = S.inv[e];
+                        const float4 eh = S.hot[3 * es];
+                        const float rs = S.cold[3 * es + 2].w;
+                        V3 cd = v3(eh.x - x.x, eh.y - x.y, eh.z - x.z);
+                        const float d2 = dot(cd, cd);
+                        if (d2 > rs * rs) {
+                            cd = rsqrtf(d2) * cd;
+                            const float sin2 = rs * rs / d2;
+                            const float cosm = sqrtf(fmaxf(0.f, 1.f - sin2));
+                            const float omc = sin2 / (1.f + cosm);
+                            const float pn = 1.f / ((float)S.n_emit * 2.f * kPi * omc);
+                            const float omcos = g0.u[2] * omc;
+                            const float cost = 1.f - omcos;
+                            const float sint = sqrtf(fmaxf(0.f, omcos * (2.f - omcos)));
+                            float sp, cp;
+                            sincosf(2.f * kPi * g0.u[3], &sp, &cp);
+                            V3 b1, b2;
+                            onb(cd, b1, b2);
+                            const V3 wl = (sint * cp) * b1 + (sint * sp) * b2 + cost * cd;
+                            float pph;
+                            const V3 f = phase_eval_local(mat, alb, rough, wol, to_local(F, wl), pph);
+                            Chord tc;
+                            const RayD lr = make_ray(x.x, x.y, x.z, wl.x, wl.y, wl.z, 0.0, __builtin_huge_val());
+                            if (nonzero(f) && chord(load_hot(S.hot, es), lr, S.r2, tc)) {
+                                const float w = P.mis_mode == 2 ? 1.f : pn / (pn + pph);
+                                const float4 eL = S.cold[3 * es + 2];
+                                const V3 wt = (w / pn) * mul(mul(beta, f), f3(eL));
+                                do_nee = true;
+                                na = make_float4(x.x, x.y, x.z, __int_as_float(e));
+                                nb = make_float4(wl.x, wl.y, wl.z, __int_as_float(k));
+                                nc = make_float4(wt.x, wt.y, wt.z, __int_as_float(pix));
+                            }
+                        }
+                    }
+                    // environment sample: uniform direction
+                    if (P.has_env && P.mis_mode != 1) {
+                        const float z = 1.f - 2.f * g1.u[2];
+                        const float rr = sqrtf(fmaxf(0.f, 1.f - z * z));
+                        float sp, cp;
+                        sincosf(2.f * kPi * g1.u[3], &sp, &cp);
+                        const V3 wl = v3(rr * cp, rr * sp, z);
+                        float pph;
+                        const V3 f = phase_eval_local(mat, alb, rough, wol, to_local(F, wl), pph);
+                        if (nonzero(f)) {
+                            const float pe = 0.25f * kInvPi;
+                            const float w = P.mis_mode == 2 ? 1.f : pe / (pe + pph);
+                            const V3 wt = (w / pe) * mul(mul(beta, f), v3(P.env[0], P.env[1], P.env[2]));
+                            do_env = true;
+                            ea = make_float4(x.x, x.y, x.z, 0.f);
+                            eb = make_float4(wl.x, wl.y, wl.z, __int_as_float(k));
+                            ec = make_float4(wt.x, wt.y, wt.z, __int_as_float(pix));
+                        }
+                    }
+                    // continue by phase sampling from the chord centre, skipping k
+                    V3 wgt;
+                    float pdf;
+                    const V3 wil = phase_sample_local(mat, alb, rough, wol, g1.u[0], g1.u[1], wgt, pdf);
+                    if (pdf > 0.f) {
+                        beta = mul(beta, wgt);
+                        if (nonzero(beta)) {
+                            const V3 wi = to_world(F, wil);
+                            cont = true;
+                            ca = make_float4(x.x, x.y, x.z, pdf);
+                            cb = make_float4(wi.x, wi.y, wi.z, __int_as_float(k));
+                            cc = make_float4(beta.x, beta.y, beta.z, __int_as_float(pix));
+                        }
+                    }
+                }
+            }
+            if (Ladd.x != 0.f || Ladd.y != 0.f || Ladd.z != 0.f) {
+                float4 l = L[pix];
+                l.x += Ladd.x; l.y += Ladd.y; l.z += Ladd.z;
+                L[pix] = l;
+            }
+        }
+        if (!WIDE) {
+            const int ps = wave_append(spill, ovf.count);
+            if (spill) ovf.idx[ps] = (int32_t)j;
+        }
+        const int pc = wave_append(cont, n_out);
+        if (cont) { qout.a[pc] = ca; qout.b[pc] = cb; qout.c[pc] = cc; }
+        const int pn = wave_append(do_nee, n_nee);
+        if (do_nee) { nee.a[pn] = na; nee.b[pn] = nb; nee.c[pn] = nc; }
+        const int pe = wave_append(do_env, n_env);
+        if (do_env) { env.a[pe] = ea; env.b[pe] = eb; env.c[pe] = ec; }
+    }
+    flush_counts(S, tc);
+}
+
+template <int K, bool WIDE>
+__global__ __launch_bounds__(kBlock) void k_light(SceneDev S, LightQueue q, const int32_t *n_in, float4 *L,
+                                                  int64_t *stats, Overflow ovf, uint32_t *err) {
+    __shared__ int stack[kStackSize * kBlock];
+    const int n = WIDE ? *ovf.count : *n_in;
+    if (!WIDE && blockIdx.x == 0 && threadIdx.x == 0)
+        atomicAdd((unsigned long long *)&stats[1], (unsigned long long)n);
+    TraceCount tc;
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = WIDE ? (int64_t)ovf.idx[j] : j;
+        const float4 A = q.a[i], B = q.b[i], C = q.c[i];
+        const int target = __float_as_int(A.w), excl = __float_as_int(B.w), pix = __float_as_int(C.w);
+        RayD r = make_ray(A.x, A.y, A.z, B.x, B.y, B.z, 0.0, __builtin_huge_val());
+        const HotRec h = load_hot(S.hot, S.inv[target]);
+        Chord c;
+        if (!chord(h, r, S.r2, c)) continue;
+        r.t1 = c.bd;
+        const SweepOut so = sweep<K>(S, r, excl, kModeEmitter, 0.f, target, stack, err, tc);
+        if (so.status != 0) {
+            if (WIDE) {
+                atomicOr(err, kErrEvents);
+            } else {
+                const int slot = atomicAdd(ovf.count, 1);
+                ovf.idx[slot] = (int32_t)i;
+            }
+            continue;
+        }
+        if (so.t > 0.f) {
+            float4 l = L[pix];
+            l.x += C.x * so.t; l.y += C.y * so.t; l.z += C.z * so.t;
+            L[pix] = l;
+        }
+    }
+    flush_counts(S, tc);
+}
+
+__global__ __launch_bounds__(kBlock) void k_env(SceneDev S, LightQueue q, const int32_t *n_in, float4 *L,
+                                                int64_t *stats, uint32_t *err) {
+    __shared__ int stack[kStackSize * kBlock];
+    const int n = *n_in;
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd((unsigned long long *)&stats[2], (unsigned long long)n);
+    TraceCount tc;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const float4 A = q.a[i], B = q.b[i], C = q.c[i];
+        const int excl = __float_as_int(B.w), pix = __float_as_int(C.w);
+        const RayD r = make_ray(A.x, A.y, A.z, B.x, B.y, B.z, 0.0, __builtin_huge_val());
+        const float F = transmittance_F(S, r, excl, true, stack, err, tc);
+        const float T = fmaxf(0.f, 1.f - F);
+        if (T > 0.f) {
+            float4 l = L[pix];
+            l.x += C.x * T; l.y += C.y * T; l.z += C.z * T;
+            L[pix] = l;
+        }
+    }
+    flush_counts(S, tc);
+}
+
+__global__ void k_accum(int64_t npix, const float4 *L, float *sum, float *sumsq) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    const float4 l = L[p];
+    sum[3 * p] += l.x;
+    sum[3 * p + 1] += l.y;
+    sum[3 * p + 2] += l.z;
+    if (sumsq) {
+        sumsq[3 * p] += l.x * l.x;
+        sumsq[3 * p + 1] += l.y * l.y;
+        sumsq[3 * p + 2] += l.z * l.z;
+    }
+}
+
+__global__ void k_set_count(int32_t *c, int32_t v) { *c = v; }
+
+hipError_t ensure_buffers(ugp_ctx ctx, int64_t cap, int max_vertices) {
+    RenderBuffers *rb = ctx->rb;
+    if (rb && rb->cap >= cap && rb->max_vertices >= max_vertices) return hipSuccess;
+    free_render(ctx);
+    rb = new RenderBuffers();
+    const size_t q = sizeof(float4) * (size_t)cap;
+    const size_t counts = sizeof(int32_t) * 4 * (size_t)(max_vertices + 2);
+    const size_t total = 12 * q + q + sizeof(int32_t) * (size_t)cap + counts + 16 * 256;
+    hipError_t e = hipMalloc(&rb->block, total);
+    if (e != hipSuccess) {
+        delete rb;
+        return e;
+    }
+    char *p = (char *)rb->block;
+    auto take = [&](size_t bytes) {
+        void *r = p;
+        p += (bytes + 255) & ~(size_t)255;
+        return r;
+    };
+    for (int k = 0; k < 2; ++k) {
+        rb->q[k].a = (float4 *)take(q);
+        rb->q[k].b = (float4 *)take(q);
+        rb->q[k].c = (float4 *)take(q);
+    }
+    rb->nee.a = (float4 *)take(q); rb->nee.b = (float4 *)take(q); rb->nee.c = (float4 *)take(q);
+    rb->env.a = (float4 *)take(q); rb->env.b = (float4 *)take(q); rb->env.c = (float4 *)take(q);
+    rb->L = (float4 *)take(q);
+    rb->ovf = (int32_t *)take(sizeof(int32_t) * (size_t)cap);
+    rb->counts = (int32_t *)take(counts);
+    rb->cap = cap;
+    rb->max_vertices = max_vertices;
+    ctx->rb = rb;
+    return hipSuccess;
+}
+
+}  // namespace
+
+void free_render(ugp_ctx ctx) {
+    if (ctx->rb) {
+        hipFree(ctx->rb->block);
+        delete ctx->rb;
+        ctx->rb = nullptr;
+    }
+}
+
+hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p, float *sum, float *sumsq) {
+    const SceneDev &S0 = ctx->scene;
+    const int64_t npix = (int64_t)cam->width * cam->height;
+    const int nv = p->max_depth + 1;
+    hipError_t e = ensure_buffers(ctx, npix, nv);
+    if (e != hipSuccess) return e;
+    RenderBuffers *rb = ctx->rb;
+    hipStream_t st = ctx->stream;
+    // camera basis (double on the host, float on the device)
+    double f[3] = {(double)cam->target[0] - cam->origin[0], (double)cam->target[1] - cam->origin[1],
+                   (double)cam->target[2] - cam->origin[2]};
+    double fl = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    for (double &x : f) x /= fl;
+    const double up[3] = {cam->up[0], cam->up[1], cam->up[2]};
+    double rt[3] = {f[1] * up[2] - f[2] * up[1], f[2] * up[0] - f[0] * up[2], f[0] * up[1] - f[1] * up[0]};
+    const double rl = sqrt(rt[0] * rt[0] + rt[1] * rt[1] + rt[2] * rt[2]);
+    for (double &x : rt) x /= rl;
+    const double u[3] = {rt[1] * f[2] - rt[2] * f[1], rt[2] * f[0] - rt[0] * f[2], rt[0] * f[1] - rt[1] * f[0]};
+    const double th = tan(0.5 * (double)cam->vfov_deg * 3.14159265358979323846 / 180.0);
+    const double asp = (double)cam->width / (double)cam->height;
+    PassArgs P;
+    P.cam = CamDev{cam->origin[0], cam->origin[1], cam->origin[2], (float)f[0], (float)f[1], (float)f[2],
+                   (float)(rt[0] * th * asp), (float)(rt[1] * th * asp), (float)(rt[2] * th * asp),
+                   (float)(u[0] * th), (float)(u[1] * th), (float)(u[2] * th), cam->width, cam->height};
+    P.seed = p->seed;
+    P.max_depth = p->max_depth;
+    P.mis_mode = p->mis_mode;
+    P.env[0] = p->env_radiance[0]; P.env[1] = p->env_radiance[1]; P.env[2] = p->env_radiance[2];
+    P.has_env = (P.env[0] > 0.f || P.env[1] > 0.f || P.env[2] > 0.f) ? 1 : 0;
+    e = hipMemsetAsync(ctx->stats, 0, sizeof(int64_t) * 4, st);
+    if (e != hipSuccess) return e;
+    // profiling: level 2 counts traversal work, level >= 1 brackets launches with events
+    // per kernel category c (0 collide, 1 collide overflow, 2 light, 3 env) the
+    // counters live at ctx->counters + 3 c
+    SceneDev S = S0, Sc[4] = {S0, S0, S0, S0};
+    if (ctx->profiling >= 2) {
+        e = hipMemsetAsync(ctx->counters, 0, sizeof(unsigned long long) * 12, st);
+        if (e != hipSuccess) return e;
+        for (int c = 0; c < 4; ++c) Sc[c].count = ctx->counters + 3 * c;
+    }
+    ctx->ev_used.clear();
+    ctx->ev_cat_valid = ctx->profiling >= 1;
+    size_t ev_next = 0;
+    auto timed = [&](int cat, auto &&launch) {
+        if (ctx->profiling < 1) {
+            launch();
+            return;
+        }
+        while (ctx->ev_pool.size() < ev_next + 2) {
+            hipEvent_t ev;
+            if (hipEventCreate(&ev) != hipSuccess) {
+                launch();
+                return;
+            }
+            ctx->ev_pool.push_back(ev);
+        }
+        hipEventRecord(ctx->ev_pool[ev_next], st);
+        launch();
+        hipEventRecord(ctx->ev_pool[ev_next + 1], st);
+        ctx->ev_used.push_back({cat, (int)ev_next});
+        ev_next += 2;
+    };
+    const unsigned gpix = (unsigned)((npix + 255) / 256);
+    const unsigned gq = (unsigned)std::min<int64_t>((npix + kBlock - 1) / kBlock, kPersistBlocks);
+    const unsigned gw = 256;  // the overflow pass: few paths
+    for (int s = 0; s < p->spp; ++s) {
+        P.sample = (uint32_t)(p->sample_offset + s);
+        e = hipMemsetAsync(rb->counts, 0, sizeof(int32_t) * 4 * (size_t)(nv + 2), st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, st, rb->counts, (int32_t)npix);
+        hipLaunchKernelGGL(k_raygen, dim3(gpix), dim3(256), 0, st, P, npix, rb->q[0], rb->L);
+        for (int v = 1; v <= nv; ++v) {
+            // counts of vertex v: [paths in, light samples, environment samples,
+            // overflow]; the next vertex's paths-in is c + 4
+            int32_t *c = rb->counts + 4 * (v - 1);
+            Queue qin = rb->q[(v - 1) & 1], qout = rb->q[v & 1];
+            Overflow ov{rb->ovf, c + 3};
+            timed(0, [&] {
+                hipLaunchKernelGGL((k_collide<kEventsMain, false>), dim3(gq), dim3(kBlock), 0, st, Sc[0], P, v, qin,
+                                   (const int32_t *)c, qout, c + 4, rb->nee, c + 1, rb->env, c + 2, rb->L,
+                                   ctx->stats, ov, ctx->err);
+            });
+            timed(1, [&] {
+                hipLaunchKernelGGL((k_collide<kEventsWide, true>), dim3(gw), dim3(kBlock), 0, st, Sc[1], P, v, qin,
+                                   (const int32_t *)c, qout, c + 4, rb->nee, c + 1, rb->env, c + 2, rb->L,
+                                   ctx->stats, ov, ctx->err);
+            });
+            if (v <= p->max_depth) {
+                if (S.n_emit > 0 && p->mis_mode != 1) {
+                    timed(2, [&] {
+                        hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, st, c + 3, 0);
+                        hipLaunchKernelGGL((k_light<kEventsMain, false>), dim3(gq), dim3(kBlock), 0, st, Sc[2], rb->nee,
+                                           (const int32_t *)(c + 1), rb->L, ctx->stats, ov, ctx->err);
+                        hipLaunchKernelGGL((k_light<kEventsWide, true>), dim3(gw), dim3(kBlock), 0, st, Sc[2], rb->nee,
+                                           (const int32_t *)(c + 1), rb->L, ctx->stats, ov, ctx->err);
+                    });
+                }
+                if (P.has_env && p->mis_mode != 1)
+                    timed(3, [&] {
+                        hipLaunchKernelGGL(k_env, dim3(gq), dim3(kBlock), 0, st, Sc[3], rb->env,
+                                           (const int32_t *)(c + 2), rb->L, ctx->stats, ctx->err);
+                    });
+            }
+        }
+        hipLaunchKernelGGL(k_accum, dim3(gpix), dim3(256), 0, st, npix, rb->L, sum, sumsq);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    ctx->last_paths = npix * p->spp;
+    return hipSuccess;
+}
+
+}  // namespace ugp

@@ -1,0 +1,93 @@
+// ugp_internal.hpp -- library-private declarations shared by the HIP sources of
+// libugp: the context, the device-side scene layout and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ugp.h"
+
+namespace ugp {
+
+// Device-side scene, all arrays in leaf (Morton) order of the hierarchy.
+//   hot   [n][3] float4: (mu.xyz, density), (q.wxyz as given), (scale.xyz, orig id bits)
+//   cold  [n][3] float4: (facet normal.xyz, material), (albedo.rgb, roughness),
+//                        (emission.rgb, bounding-sphere radius)
+//   nodes [n-1][4] float4: internal nodes holding the boxes of both children:
+//         (L.lo.xyz, L.hi.x), (L.hi.yz, R.lo.xy), (R.lo.z, R.hi.xyz), (refL, refR, -, -)
+//         a child ref >= 0 is an internal node, < 0 is the leaf primitive ~ref
+//   inv   [n] original index -> leaf position
+//   emit  [n_emit] original indices of emissive primitives, ascending
+struct SceneDev {
+    int64_t n = 0;
+    int32_t root = 0;      // ref of the root (a leaf ref when n == 1)
+    float r2 = 0.f;        // squared Mahalanobis radius of the cut-off ellipsoid
+    float4 *hot = nullptr;
+    float4 *cold = nullptr;
+    float4 *nodes = nullptr;
+    int32_t *inv = nullptr;
+    int32_t *emit = nullptr;
+    int32_t n_emit = 0;
+    int32_t depth = 0;     // depth of the hierarchy (root = 1)
+    unsigned long long *count = nullptr;  // [3] node visits, primitive tests, reloads (profiling)
+    float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};  // bounds of the primitive boxes
+};
+
+// Device error word bits (deferred errors reported by ugp_sync)
+enum : uint32_t { kErrStack = 1u, kErrEvents = 2u, kErrQueue = 4u };
+
+// Sweep modes of the ordered traversal
+enum SweepMode : int { kModeCollide = 0, kModeSaturate = 1, kModeEmitter = 2 };
+
+constexpr int kStackSize = 64;   // traversal stack entries per lane (LDS)
+constexpr int kEventsMain = 16;  // event buffer of the main sweep (registers)
+constexpr int kEventsWide = 64;  // event buffer of the overflow sweep
+
+struct RenderBuffers;
+struct NrcState;
+
+}  // namespace ugp
+
+#include <vector>
+
+struct ugp_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    ugp::SceneDev scene;
+    uint32_t *err = nullptr;        // device error word
+    // scratch for queries (grown on demand)
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    ugp::RenderBuffers *rb = nullptr;
+    ugp::NrcState *nrc = nullptr;
+    int64_t last_paths = 0;
+    int64_t *stats = nullptr;       // device counters of the last render: [collision, light, env]
+    unsigned long long *counters = nullptr;  // [3] traversal counters (profiling level 2)
+    int profiling = 0;
+    // event pairs of the last render, by category: 0 collide main, 1 collide wide, 2 light, 3 env
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, int>> ev_used;  // (category, index of the start event)
+    bool ev_cat_valid = false;
+};
+
+namespace ugp {
+
+// build.hip
+hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps);
+void free_scene(SceneDev &sc);
+
+// trace.hip
+hipError_t launch_transmittance(ugp_ctx ctx, int64_t n, const float *rays, const int32_t *excl,
+                                float *T, float *F);
+hipError_t launch_sweep(ugp_ctx ctx, int mode, int64_t n, const float *rays, const int32_t *excl,
+                        const float *u, const int32_t *target, int32_t *prim_out, float *f_out,
+                        int32_t *counts = nullptr);
+
+// render.hip
+hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p, float *sum,
+                  float *sumsq);
+void free_render(ugp_ctx ctx);
+
+// device scratch of the context: returns a buffer of at least `bytes`
+void *ctx_scratch(ugp_ctx ctx, size_t bytes);
+
+}  // namespace ugp

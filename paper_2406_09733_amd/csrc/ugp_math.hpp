@@ -1,0 +1,189 @@
+// ugp_math.hpp -- device math for libugp: small vectors, the Philox4x32-10
+// counter-based generator, orthonormal frames, the delta-NDF phase functions
+// and the pinhole camera.  FP32 unless a name says otherwise.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ugp {
+
+constexpr float kPi = 3.14159265358979323846f;
+constexpr float kInvPi = 0.318309886183790671538f;
+constexpr float kInf = __builtin_huge_valf();
+
+struct V3 {
+    float x, y, z;
+};
+__device__ __forceinline__ V3 v3(float x, float y, float z) { return V3{x, y, z}; }
+__device__ __forceinline__ V3 operator+(V3 a, V3 b) { return v3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ V3 operator-(V3 a, V3 b) { return v3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ V3 operator-(V3 a) { return v3(-a.x, -a.y, -a.z); }
+__device__ __forceinline__ V3 operator*(float s, V3 a) { return v3(s * a.x, s * a.y, s * a.z); }
+__device__ __forceinline__ V3 mul(V3 a, V3 b) { return v3(a.x * b.x, a.y * b.y, a.z * b.z); }
+__device__ __forceinline__ float dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ V3 cross(V3 a, V3 b) {
+    return v3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ V3 normalize(V3 a) { return rsqrtf(dot(a, a)) * a; }
+__device__ __forceinline__ bool nonzero(V3 a) { return a.x > 0.f || a.y > 0.f || a.z > 0.f; }
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
+// multiplies (hi/lo halves), a word permutation and an xor with the round key;
+// the key advances by the Weyl constants between rounds.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// top 24 bits -> [0,1), exact in float
+__device__ __forceinline__ float u01(uint32_t x) { return (float)(x >> 8) * (1.0f / 16777216.0f); }
+
+struct Rng4 {
+    float u[4];
+};
+__device__ __forceinline__ Rng4 rng4(uint64_t seed, uint32_t pixel, uint32_t sample, uint32_t vertex,
+                                     uint32_t group) {
+    uint4 x = philox4x32_10(make_uint4(pixel, sample, vertex, group), (uint32_t)seed,
+                            (uint32_t)(seed >> 32));
+    return Rng4{{u01(x.x), u01(x.y), u01(x.z), u01(x.w)}};
+}
+
+// Orthonormal basis around unit n (Duff et al., "Building an Orthonormal Basis,
+// Revisited", JCGT 2017).
+__device__ __forceinline__ void onb(V3 n, V3 &b1, V3 &b2) {
+    const float sign = n.z >= 0.f ? 1.f : -1.f;
+    const float a = -1.f / (sign + n.z);
+    const float b = n.x * n.y * a;
+    b1 = v3(1.f + sign * n.x * n.x * a, sign * b, -sign * n.x);
+    b2 = v3(b, sign + n.y * n.y * a, -n.y);
+}
+
+// ---------------------------------------------------------------------------
+// Delta-NDF phase function (Sec. 6): with a single facet normal the phase
+// function of eq. phase_function is the surface BSDF times the cosine.  The
+// facet normal is flipped toward w_o; only reflection scatters.
+//   diffuse: f = albedo/pi cos_i, pdf = cos_i/pi (cosine sampling)
+//   glossy : GGX with alpha = roughness^2 (>= 1e-4), height-correlated Smith
+//            G2, Schlick Fresnel with F0 = albedo; sampled by visible normals
+//            (Heitz, "Sampling the GGX Distribution of Visible Normals",
+//            JCGT 2018): f = F D G2/(4 cos_o), pdf = G1(w_o) D / (4 cos_o).
+// ---------------------------------------------------------------------------
+struct Facet {
+    V3 n, b1, b2;
+};
+__device__ __forceinline__ Facet facet(V3 nrm, V3 wo) {
+    Facet f;
+    f.n = dot(nrm, wo) >= 0.f ? nrm : -nrm;
+    onb(f.n, f.b1, f.b2);
+    return f;
+}
+__device__ __forceinline__ V3 to_local(const Facet &f, V3 v) { return v3(dot(v, f.b1), dot(v, f.b2), dot(v, f.n)); }
+__device__ __forceinline__ V3 to_world(const Facet &f, V3 l) {
+    return l.x * f.b1 + l.y * f.b2 + l.z * f.n;
+}
+
+__device__ __forceinline__ float ggx_alpha(float rough) { return fmaxf(rough * rough, 1e-4f); }
+__device__ __forceinline__ float ggx_D(float a, float ch) {
+    const float a2 = a * a;
+    const float t = ch * ch * (a2 - 1.f) + 1.f;
+    return a2 / (kPi * t * t);
+}
+__device__ __forceinline__ float ggx_lambda(float a, float c) {
+    const float c2 = c * c;
+    const float tan2 = fmaxf(0.f, 1.f - c2) / c2;
+    return 0.5f * (-1.f + sqrtf(1.f + a * a * tan2));
+}
+__device__ __forceinline__ float pow5(float x) {
+    const float x2 = x * x;
+    return x2 * x2 * x;
+}
+
+// local frame: returns f (rgb) and pdf
+__device__ inline V3 phase_eval_local(int mat, V3 alb, float rough, V3 wo, V3 wi, float &pdf) {
+    pdf = 0.f;
+    if (wo.z <= 0.f || wi.z <= 0.f) return v3(0.f, 0.f, 0.f);
+    if (mat == 0) {
+        pdf = wi.z * kInvPi;
+        return (wi.z * kInvPi) * alb;
+    }
+    const float a = ggx_alpha(rough);
+    const V3 h = normalize(wo + wi);
+    const float D = ggx_D(a, h.z);
+    const float lo = ggx_lambda(a, wo.z), li = ggx_lambda(a, wi.z);
+    const float G2 = 1.f / (1.f + lo + li), G1 = 1.f / (1.f + lo);
+    const float sch = pow5(1.f - fmaxf(0.f, dot(wi, h)));
+    const float k = D * G2 / (4.f * wo.z);
+    pdf = G1 * D / (4.f * wo.z);
+    return v3((alb.x + (1.f - alb.x) * sch) * k, (alb.y + (1.f - alb.y) * sch) * k,
+              (alb.z + (1.f - alb.z) * sch) * k);
+}
+
+// local frame sample: returns wi, weight f/pdf; pdf 0 = no sample
+__device__ inline V3 phase_sample_local(int mat, V3 alb, float rough, V3 wo, float u1, float u2,
+                                        V3 &wgt, float &pdf) {
+    pdf = 0.f;
+    wgt = v3(0.f, 0.f, 0.f);
+    if (wo.z <= 0.f) return v3(0.f, 0.f, 1.f);
+    float sp, cp;
+    sincosf(2.f * kPi * u2, &sp, &cp);
+    if (mat == 0) {
+        const float r = sqrtf(u1);
+        const V3 wi = v3(r * cp, r * sp, sqrtf(fmaxf(0.f, 1.f - u1)));
+        if (wi.z <= 0.f) return wi;
+        pdf = wi.z * kInvPi;
+        wgt = alb;
+        return wi;
+    }
+    const float a = ggx_alpha(rough);
+    const V3 Vh = normalize(v3(a * wo.x, a * wo.y, wo.z));
+    const float lensq = Vh.x * Vh.x + Vh.y * Vh.y;
+    V3 T1 = lensq > 0.f ? rsqrtf(lensq) * v3(-Vh.y, Vh.x, 0.f) : v3(1.f, 0.f, 0.f);
+    const V3 T2 = cross(Vh, T1);
+    const float r = sqrtf(u1);
+    const float p1 = r * cp;
+    float p2 = r * sp;
+    const float s = 0.5f * (1.f + Vh.z);
+    p2 = (1.f - s) * sqrtf(fmaxf(0.f, 1.f - p1 * p1)) + s * p2;
+    const float p3 = sqrtf(fmaxf(0.f, 1.f - p1 * p1 - p2 * p2));
+    const V3 Nh = p1 * T1 + p2 * T2 + p3 * Vh;
+    const V3 h = normalize(v3(a * Nh.x, a * Nh.y, fmaxf(0.f, Nh.z)));
+    const float c = dot(wo, h);
+    const V3 wi = (2.f * c) * h - wo;
+    if (wi.z <= 0.f) return wi;
+    const float D = ggx_D(a, h.z);
+    const float lo = ggx_lambda(a, wo.z), li = ggx_lambda(a, wi.z);
+    const float G2 = 1.f / (1.f + lo + li), G1 = 1.f / (1.f + lo);
+    pdf = G1 * D / (4.f * wo.z);
+    const float sch = pow5(1.f - fmaxf(0.f, c));
+    const float k = G2 / G1;
+    wgt = v3((alb.x + (1.f - alb.x) * sch) * k, (alb.y + (1.f - alb.y) * sch) * k,
+             (alb.z + (1.f - alb.z) * sch) * k);
+    return wi;
+}
+
+// Camera set up on the host: origin, forward f, right r' = tan(vfov/2) aspect r,
+// up u' = tan(vfov/2) u.
+struct CamDev {
+    float ox, oy, oz;
+    float fx, fy, fz;
+    float rx, ry, rz;
+    float ux, uy, uz;
+    int32_t width, height;
+};
+__device__ __forceinline__ V3 camera_dir(const CamDev &c, int px, int py, float jx, float jy) {
+    const float sx = 2.f * ((float)px + jx) / (float)c.width - 1.f;
+    const float sy = 1.f - 2.f * ((float)py + jy) / (float)c.height;
+    return normalize(v3(c.fx + sx * c.rx + sy * c.ux, c.fy + sx * c.ry + sy * c.uy,
+                        c.fz + sx * c.rz + sy * c.uz));
+}
+
+}  // namespace ugp

@@ -1,0 +1,67 @@
+"""The C-ABI library loads and exports every entry point its header declares;
+host-side argument checks return status codes without touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ugp.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ugp_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_2406_09733_amd as P
+    if not os.path.exists(P.LIB_PATH):
+        from paper_2406_09733_amd import build
+        build.build()
+    return P.lib()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ["ugp_create", "ugp_destroy", "ugp_build_bvh", "ugp_transmittance", "ugp_sample_collision",
+              "ugp_saturation", "ugp_emitter_query", "ugp_render", "ugp_sync", "ugp_status_string"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    for n in _declared():
+        assert hasattr(L, n), n
+
+
+def test_binding_names_match_header():
+    import paper_2406_09733_amd as P
+    assert sorted(P.EXPORTS) == _declared()
+
+
+def test_status_strings(L):
+    for code in range(7):
+        s = L.ugp_status_string(code)
+        assert isinstance(s, bytes) and len(s) > 0
+
+
+def test_host_side_argument_checks(L):
+    # none of these reach the device
+    assert L.ugp_create(0, None, None) == 1
+    assert L.ugp_build_bvh(None, None, C.c_float(0.01)) == 1
+    assert L.ugp_transmittance(None, 1, None, None, None, None) == 1
+    assert L.ugp_sample_collision(None, 1, None, None, None, None, None) == 1
+    assert L.ugp_render(None, None, None, None, None) == 1
+    assert L.ugp_sync(None) == 1
+    assert L.ugp_destroy(None) == 1
+
+
+def test_create_without_gpu_reports_device_error(L):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = C.c_void_p()
+    assert L.ugp_create(0, None, C.byref(h)) == 3

@@ -1,0 +1,272 @@
+"""GPU parity: libugp (FP32 kernels, FP64 ray-frame transform) against the FP64
+CPU oracle on identical seeded inputs, through the C ABI.
+
+Tolerances ("Parity bar"):
+  T                    |dT| <= 1e-5
+  F, I, emitter factor |dx| <= 1e-5 max(|x|, 1e-3)
+  t_sat, scatter t     |dt| <= 1e-5 max(|t|, 1e-3), or F_oracle(t_gpu) within 2e-5 of 1
+  selected primitive   identical wherever the oracle's margin |u - boundary| > 1e-5
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2406_09733_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    import paper_2406_09733_amd as P
+    return P.Context(0)
+
+
+def _build(ctx, sc):
+    ctx.build_bvh(sc)
+    ctx.sync()
+    return ctx
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _rel_ok(got, ref, rtol=1e-5, floor=1e-3):
+    return np.abs(got - ref) <= rtol * np.maximum(np.abs(ref), floor)
+
+
+def _cases():
+    return {"tiny_random": (scenes.tiny_random(), 4096), "mixed_100k": (scenes.mixed_100k(), 2048)}
+
+
+@pytest.fixture(scope="module")
+def built(ctx, orc):
+    out = {}
+    for name, (sc, nr) in _cases().items():
+        out[name] = (sc, orc.Scene(sc), nr)
+    return out
+
+
+def _with_exclude(sc, rays, seed):
+    rng = np.random.default_rng(seed)
+    ex = rng.integers(-1, sc["mean"].shape[0], rays.shape[0]).astype(np.int32)
+    ex[::2] = -1
+    return ex
+
+
+@pytest.mark.parametrize("name", ["tiny_random", "mixed_100k"])
+def test_transmittance_parity(ctx, built, name):
+    sc, S, nr = built[name]
+    _say("transmittance parity", name, nr)
+    _build(ctx, sc)
+    rays = scenes.probe_rays(sc, nr, seed=101)
+    ex = _with_exclude(sc, rays, 5)
+    F_ref, T_ref = S.transmittance(rays, ex)
+    T, F = ctx.transmittance(rays, ex, want_F=True)
+    ctx.sync()
+    T, F = _np(T), _np(F)
+    assert np.all(np.abs(T - T_ref) <= 1e-5), np.abs(T - T_ref).max()
+    ok = _rel_ok(F, F_ref)
+    assert ok.all(), (np.where(~ok)[0][:10], F[~ok][:5], F_ref[~ok][:5])
+    # early-exit variant: same T
+    T2, _ = ctx.transmittance(rays, ex)
+    assert np.all(np.abs(_np(T2) - T_ref) <= 1e-5)
+
+
+@pytest.mark.parametrize("name", ["tiny_random", "mixed_100k"])
+def test_saturation_parity(ctx, built, name):
+    sc, S, nr = built[name]
+    _say("saturation parity", name, nr)
+    _build(ctx, sc)
+    rays = scenes.probe_rays(sc, nr, seed=102)
+    ex = _with_exclude(sc, rays, 6)
+    ts_ref = S.saturation(rays, ex)
+    ts = _np(ctx.saturation(rays, ex)).astype(np.float64)
+    ctx.sync()
+    t1 = rays[:, 7].astype(np.float64)
+    same = (ts == t1) == (ts_ref == t1)
+    if same.mean() <= 0.999:
+        F_end, _ = S.transmittance(rays, ex)
+        bad = np.where(~same)[0][:8]
+        _say("  disagreeing rays:", [(int(i), float(ts[i]), float(ts_ref[i]), float(t1[i]), float(F_end[i]))
+                                     for i in bad])
+    assert same.mean() > 0.999
+    sat = (ts_ref < t1) & (ts < t1)
+    close = _rel_ok(ts, ts_ref)
+    resid = np.abs(S.F_at(rays[sat], ts[sat], ex[sat]) - 1.0) <= 2e-5
+    ok = close.copy()
+    ok[np.where(sat)[0]] |= resid
+    ok |= ~sat
+    assert ok.all(), (np.where(~ok)[0][:10], ts[~ok][:5], ts_ref[~ok][:5])
+
+
+@pytest.mark.parametrize("name", ["tiny_random", "mixed_100k"])
+def test_collision_parity(ctx, built, name):
+    sc, S, nr = built[name]
+    _say("collision parity", name, nr)
+    _build(ctx, sc)
+    rays = scenes.probe_rays(sc, nr, seed=103)
+    ex = _with_exclude(sc, rays, 7)
+    u = np.random.default_rng(8).uniform(0, 1, nr).astype(np.float32)
+    ref = S.sample_collision(rays, u.astype(np.float64), ex)
+    prim, t = ctx.sample_collision(rays, u, ex)
+    ctx.sync()
+    prim, t = _np(prim), _np(t).astype(np.float64)
+    clear = ref["margin"] > 1e-5
+    mism = (prim != ref["prim"]) & clear
+    assert mism.sum() == 0, (np.where(mism)[0][:10], prim[mism][:5], ref["prim"][mism][:5])
+    both = (prim == ref["prim"]) & (prim >= 0)
+    assert _rel_ok(t[both], ref["t"][both]).all()
+    assert np.all(np.isnan(t[prim < 0]))
+    _say("  ambiguous picks (margin <= 1e-5):", int((~clear).sum()), "of", nr,
+         "escape fraction", float((prim < 0).mean()))
+
+
+@pytest.mark.parametrize("name", ["tiny_random", "mixed_100k"])
+def test_emitter_query_parity(ctx, built, name):
+    sc, S, nr = built[name]
+    _say("emitter query parity", name, nr)
+    _build(ctx, sc)
+    rng = np.random.default_rng(104)
+    rays = scenes.probe_rays(sc, nr, seed=104, aimed_frac=0.0)
+    tgt = rng.integers(0, sc["mean"].shape[0], nr).astype(np.int32)
+    d = sc["mean"][tgt].astype(np.float64) - rays[:, :3].astype(np.float64)
+    d += rng.normal(size=d.shape) * sc["scale"][tgt].max(1, keepdims=True)
+    rays[:, 3:6] = d / np.linalg.norm(d, axis=1, keepdims=True)
+    ex = _with_exclude(sc, rays, 9)
+    ref = S.emitter_query(rays, tgt, ex)
+    got = _np(ctx.emitter_query(rays, tgt, ex)).astype(np.float64)
+    ctx.sync()
+    ok = _rel_ok(got, ref)
+    if not ok.all():
+        for i in np.where(~ok)[0][:6]:
+            ch = S.chord(int(tgt[i]), rays[i])
+            r2 = rays[i:i + 1].copy()
+            r2[0, 7] = np.float32(ch[1])
+            ts = S.saturation(r2, ex[i:i + 1])[0]
+            Fe = S.transmittance(r2, ex[i:i + 1])[0][0]
+            W = S.emitter_query(rays[i:i + 1], tgt[i:i + 1], np.array([-2], np.int32))[0]
+            _say(f"  ray {i}: gpu {got[i]:.7g} oracle {ref[i]:.7g} chord {ch} tsat {ts:.9g} F(b) {Fe:.6g}"
+                 f" t1 {rays[i, 7]} excl {ex[i]} tgt {tgt[i]}")
+    assert ok.all(), (np.where(~ok)[0][:10], got[~ok][:5], ref[~ok][:5])
+    assert (ref > 0).mean() > 0.03
+
+
+def test_edge_cases(ctx, orc, torch):
+    _say("edge cases")
+    # a single primitive: the hierarchy degenerates to one leaf
+    one = {k: (v[:1] if isinstance(v, np.ndarray) else v) for k, v in scenes.tiny_random().items()}
+    one["density"][:] = 60.0
+    S = orc.Scene(one)
+    _build(ctx, one)
+    mu = one["mean"][0].astype(np.float64)
+    rng = np.random.default_rng(3)
+    o = mu + rng.normal(size=(256, 3)) * 0.2
+    w = mu + rng.normal(size=(256, 3)) * 0.01 - o
+    w /= np.linalg.norm(w, axis=1, keepdims=True)
+    rays = np.concatenate([o, w, np.zeros((256, 1)), np.full((256, 1), np.inf)], 1).astype(np.float32)
+    rays[:8, 7] = rays[:8, 6]           # empty interval
+    rays[8:16, :3] = mu                 # origin inside the primitive
+    F_ref, T_ref = S.transmittance(rays)
+    T, F = ctx.transmittance(rays, want_F=True)
+    assert np.all(np.abs(_np(T) - T_ref) <= 1e-5)
+    assert np.all(_np(T)[:8] == 1.0)
+    u = rng.uniform(0, 1, 256).astype(np.float32)
+    ref = S.sample_collision(rays, u.astype(np.float64))
+    prim, t = ctx.sample_collision(rays, u)
+    clear = ref["margin"] > 1e-5
+    assert np.all((_np(prim) == ref["prim"]) | ~clear)
+    ts_ref = S.saturation(rays)
+    ts = _np(ctx.saturation(rays)).astype(np.float64)
+    sat = ts_ref < rays[:, 7]
+    assert np.all(_rel_ok(ts[sat], ts_ref[sat]) | (np.abs(S.F_at(rays[sat], ts[sat]) - 1) <= 2e-5))
+    # excluding the only primitive empties the ray
+    ex = np.zeros(256, np.int32)
+    T, _ = ctx.transmittance(rays, ex)
+    assert np.all(_np(T) == 1.0)
+    prim, _ = ctx.sample_collision(rays, u, ex)
+    assert np.all(_np(prim) == -1)
+    # zero rays is a no-op
+    e = np.zeros((0, 8), np.float32)
+    T, _ = ctx.transmittance(e)
+    assert T.numel() == 0
+    ctx.sync()
+
+
+def test_render_furnace_gpu(ctx, torch):
+    # albedo-1 Lambert primitives under a unit environment: phase sampling
+    # returns exactly 1 per path; the MIS estimator has mean 1
+    _say("furnace")
+    sc = scenes.tiny_random(seed=21, n_emit=0)
+    sc["albedo"][:] = 1.0
+    _build(ctx, sc)
+    cam = dict(scenes.camera("tiny_random"), width=64, height=64)
+    s, s2 = ctx.render(cam, {"spp": 8, "max_depth": 1000, "seed": 3, "env_radiance": (1, 1, 1), "mis_mode": 1})
+    ctx.sync()
+    m = _np(s) / 8
+    assert np.allclose(m, 1.0, atol=2e-5), np.abs(m - 1).max()
+    s, s2 = ctx.render(cam, {"spp": 16, "max_depth": 1000, "seed": 4, "env_radiance": (1, 1, 1)})
+    ctx.sync()
+    s, s2 = _np(s), _np(s2)
+    n = 16 * s.shape[0] * s.shape[1]
+    mean = s.sum((0, 1)) / n
+    var = s2.sum((0, 1)) / n - mean ** 2
+    assert np.all(np.abs(mean - 1) <= 3 * np.sqrt(var / n) + 1e-6), (mean, np.sqrt(var / n))
+
+
+def _image_parity(ctx, orc, sc, name, spp, depth, seed, res=None, extra=None):
+    cam = scenes.camera(name)
+    if res:
+        cam = dict(cam, width=res[0], height=res[1])
+    p = {"spp": spp, "max_depth": depth, "seed": seed}
+    if extra:
+        p.update(extra)
+    S = orc.Scene(sc)
+    s_ref, s2_ref, _ = S.render(cam, p)
+    _build(ctx, sc)
+    s, s2 = ctx.render(cam, p)
+    ctx.sync()
+    H, W = cam["height"], cam["width"]
+    s = _np(s).reshape(-1, 3).astype(np.float64)
+    s2 = _np(s2).reshape(-1, 3).astype(np.float64)
+    m, m_ref = s / spp, s_ref / spp
+    v = np.maximum(s2 / spp - m ** 2, 0) / spp
+    v_ref = np.maximum(s2_ref / spp - m_ref ** 2, 0) / spp
+    z = np.abs(m - m_ref) / np.sqrt(v + v_ref + 1e-12)
+    frac = float((z > 3).mean())
+    gm, gr = m.mean(), m_ref.mean()
+    gse = np.sqrt((v + v_ref).sum()) / m.size
+    _say(f"  {name}: mean gpu {gm:.6f} oracle {gr:.6f} se {gse:.2e}; pixels beyond 3 sigma {frac:.4f};"
+         f" identical pixels {(np.abs(m - m_ref) < 1e-4).mean():.3f}")
+    return frac, abs(gm - gr), gse
+
+
+def test_render_parity_tiny(ctx, orc, torch):
+    _say("render parity tiny_random 128x128 4 spp depth 4")
+    sc = scenes.tiny_random()
+    frac, d, se = _image_parity(ctx, orc, sc, "tiny_random", 4, 4, 0)
+    assert frac < 0.01
+    assert d <= 3 * se + 1e-6
+
+
+def test_render_parity_mixed(ctx, orc, torch):
+    _say("render parity mixed_100k 128x128 4 spp depth 8")
+    sc = scenes.mixed_100k()
+    frac, d, se = _image_parity(ctx, orc, sc, "mixed_100k", 4, 8, 1, res=(128, 128))
+    assert frac < 0.01
+    assert d <= 3 * se + 1e-6
