@@ -12,7 +12,9 @@
 //    codes are split by position.
 // 5. Bottom-up refit: every leaf climbs, the second child to arrive at a node
 //    forms its box (agent-scope atomics and fences, so it is safe across XCDs).
-// 6. Scatter the hot / cold records into leaf order.
+// 6. Scatter the hot / cold records into leaf order: hot = (mu, d, M = S^-1 R^T
+//    rounded to float, original index), 64 B; cold = facet normal, material,
+//    albedo, roughness, emission, bounding-sphere radius, 48 B.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -55,7 +57,8 @@ struct PackIn {
 
 // boxes [n][6] (lo.xyz, hi.xyz) in original order; cold written in original
 // order into a temporary; bounds[6] ordered-uint min/max of box centres
-__global__ void k_pack(PackIn in, float *boxes, float4 *cold_tmp, uint32_t *bounds, uint32_t *err) {
+__global__ void k_pack(PackIn in, float *boxes, float4 *cold_tmp, float *mtmp, uint32_t *bounds,
+                       uint32_t *err) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= in.n) return;
     const double qw = in.rot[4 * k], qx = in.rot[4 * k + 1], qy = in.rot[4 * k + 2], qz = in.rot[4 * k + 3];
@@ -92,6 +95,9 @@ __global__ void k_pack(PackIn in, float *boxes, float4 *cold_tmp, uint32_t *boun
         boxes[6 * k + j] = lo[j];
         boxes[6 * k + 3 + j] = hi[j];
     }
+    // M = S^-1 R^T (row i = column i of R over s_i), rounded to float
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) mtmp[9 * k + 3 * i + j] = (float)(R[j][i] / s[i]);
     cold_tmp[3 * k] = make_float4((float)R[0][am], (float)R[1][am], (float)R[2][am], __int_as_float(m));
     cold_tmp[3 * k + 1] = make_float4(in.alb[3 * k], in.alb[3 * k + 1], in.alb[3 * k + 2], in.rough[k]);
     cold_tmp[3 * k + 2] = make_float4(in.emis[3 * k], in.emis[3 * k + 1], in.emis[3 * k + 2],
@@ -418,20 +424,86 @@ __global__ void k_depth(int64_t n, const int32_t *parent_node, const int32_t *pa
     atomicMax(depth, d);
 }
 
+// Collapse of the binary radix tree into a 4-wide hierarchy: the binary
+// nodes at even depth become 4-wide nodes whose slots are their grandchildren
+// (or a child, when that child is a leaf).  A 4-wide node is 128 B:
+// lo.x[4], lo.y[4], lo.z[4], hi.x[4], hi.y[4], hi.z[4], ref[4], pad; a ref
+// >= 0 is a 4-wide node, < 0 the leaf primitive ~ref, kEmptySlot unused.
+__global__ void k_node_parity(int64_t n, const int32_t *parent_node, int32_t *even, uint32_t *err) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1 || (*err & 16u)) return;
+    int d = 0;
+    int32_t p = (int32_t)i;
+    while (p != 0) {
+        p = parent_node[p];
+        if (++d > 4096) {
+            atomicOr(err, 16u);
+            break;
+        }
+    }
+    even[i] = (d & 1) == 0 ? 1 : 0;
+}
+
+__device__ __forceinline__ void node_child(const float4 *nodes, int32_t b, int side, float box[6], int32_t &ref) {
+    const float *nd = reinterpret_cast<const float *>(nodes + 4 * (int64_t)b);
+    const int o = side ? 6 : 0;
+    for (int c = 0; c < 6; ++c) box[c] = nd[o + c];
+    ref = side ? __float_as_int(nd[13]) : __float_as_int(nd[12]);
+}
+
+__global__ void k_collapse(int64_t n, const float4 *nodes, const int32_t *even, const int32_t *map,
+                           float4 *nodes4) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n - 1 || !even[b]) return;
+    float lo[3][4], hi[3][4];
+    int32_t ref[4];
+    int ns = 0;
+    for (int side = 0; side < 2; ++side) {
+        float box[6];
+        int32_t c;
+        node_child(nodes, (int32_t)b, side, box, c);
+        if (c < 0) {
+            for (int k = 0; k < 3; ++k) { lo[k][ns] = box[k]; hi[k][ns] = box[3 + k]; }
+            ref[ns++] = c;
+        } else {
+            for (int g = 0; g < 2; ++g) {
+                float gb[6];
+                int32_t gc;
+                node_child(nodes, c, g, gb, gc);
+                for (int k = 0; k < 3; ++k) { lo[k][ns] = gb[k]; hi[k][ns] = gb[3 + k]; }
+                ref[ns++] = gc < 0 ? gc : map[gc];
+            }
+        }
+    }
+    for (; ns < 4; ++ns) {
+        for (int k = 0; k < 3; ++k) { lo[k][ns] = 3.0e38f; hi[k][ns] = -3.0e38f; }
+        ref[ns] = kEmptySlot;
+    }
+    float4 *o = nodes4 + 8 * (int64_t)map[b];
+    o[0] = make_float4(lo[0][0], lo[0][1], lo[0][2], lo[0][3]);
+    o[1] = make_float4(lo[1][0], lo[1][1], lo[1][2], lo[1][3]);
+    o[2] = make_float4(lo[2][0], lo[2][1], lo[2][2], lo[2][3]);
+    o[3] = make_float4(hi[0][0], hi[0][1], hi[0][2], hi[0][3]);
+    o[4] = make_float4(hi[1][0], hi[1][1], hi[1][2], hi[1][3]);
+    o[5] = make_float4(hi[2][0], hi[2][1], hi[2][2], hi[2][3]);
+    o[6] = make_float4(__int_as_float(ref[0]), __int_as_float(ref[1]), __int_as_float(ref[2]),
+                       __int_as_float(ref[3]));
+    o[7] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
 __global__ void k_scatter(int64_t n, const int32_t *sorted_orig, PackIn in, const float4 *cold_tmp,
-                          float4 *hot, float4 *cold, int32_t *inv, int32_t *emit_flag) {
+                          const float *mtmp, float4 *hot, float4 *cold, int32_t *inv, int32_t *emit_flag) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int32_t o = sorted_orig[i];
-    hot[3 * i] = make_float4(in.mean[3 * (int64_t)o], in.mean[3 * (int64_t)o + 1], in.mean[3 * (int64_t)o + 2],
-                             in.dens[o]);
-    hot[3 * i + 1] = make_float4(in.rot[4 * (int64_t)o], in.rot[4 * (int64_t)o + 1], in.rot[4 * (int64_t)o + 2],
-                                 in.rot[4 * (int64_t)o + 3]);
-    hot[3 * i + 2] = make_float4(in.scale[3 * (int64_t)o], in.scale[3 * (int64_t)o + 1],
-                                 in.scale[3 * (int64_t)o + 2], __int_as_float(o));
-    for (int c = 0; c < 3; ++c) cold[3 * i + c] = cold_tmp[3 * (int64_t)o + c];
+    const int64_t o = sorted_orig[i];
+    const float *M = mtmp + 9 * o;
+    hot[4 * i] = make_float4(in.mean[3 * o], in.mean[3 * o + 1], in.mean[3 * o + 2], in.dens[o]);
+    hot[4 * i + 1] = make_float4(M[0], M[1], M[2], M[3]);
+    hot[4 * i + 2] = make_float4(M[4], M[5], M[6], M[7]);
+    hot[4 * i + 3] = make_float4(M[8], __int_as_float((int)o), 0.f, 0.f);
+    for (int c = 0; c < 3; ++c) cold[3 * i + c] = cold_tmp[3 * o + c];
     inv[o] = (int32_t)i;
-    const float4 e = cold_tmp[3 * (int64_t)o + 2];
+    const float4 e = cold_tmp[3 * o + 2];
     emit_flag[o] = (e.x > 0.f || e.y > 0.f || e.z > 0.f) ? 1 : 0;
 }
 
@@ -470,6 +542,7 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
               s->material, r};
     float *boxes = nullptr;
     float4 *cold_tmp = nullptr;
+    float *mtmp = nullptr;
     uint32_t *bounds = nullptr, *keys = nullptr, *tk = nullptr;
     int32_t *vals = nullptr, *tv = nullptr, *pnode = nullptr, *pleaf = nullptr, *flags = nullptr;
     int32_t *emit_flag = nullptr, *emit_pos = nullptr, *depth = nullptr;
@@ -478,12 +551,13 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
     int32_t h_depth = 0, h_nemit = 0, h_last_flag = 0;
     const int64_t ni = n > 1 ? n - 1 : 1;
 
-    UGP_CHECK(hipMalloc((void **)&sc.hot, sizeof(float4) * 3 * n));
+    UGP_CHECK(hipMalloc((void **)&sc.hot, sizeof(float4) * 4 * n));
     UGP_CHECK(hipMalloc((void **)&sc.cold, sizeof(float4) * 3 * n));
     UGP_CHECK(hipMalloc((void **)&sc.nodes, sizeof(float4) * 4 * ni));
     UGP_CHECK(hipMalloc((void **)&sc.inv, sizeof(int32_t) * n));
     UGP_CHECK(hipMallocAsync((void **)&boxes, sizeof(float) * 6 * n, st));
     UGP_CHECK(hipMallocAsync((void **)&cold_tmp, sizeof(float4) * 3 * n, st));
+    UGP_CHECK(hipMallocAsync((void **)&mtmp, sizeof(float) * 9 * n, st));
     UGP_CHECK(hipMallocAsync((void **)&bounds, sizeof(uint32_t) * 8, st));
     UGP_CHECK(hipMallocAsync((void **)&keys, sizeof(uint32_t) * n, st));
     UGP_CHECK(hipMallocAsync((void **)&tk, sizeof(uint32_t) * n, st));
@@ -499,7 +573,7 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
     UGP_CHECK(hipMemsetAsync(flags, 0, sizeof(int32_t) * ni, st));
     UGP_CHECK(hipMemsetAsync(depth, 0, sizeof(int32_t), st));
     hipLaunchKernelGGL(k_init_bounds, dim3(1), dim3(64), 0, st, bounds);
-    hipLaunchKernelGGL(k_pack, dim3(blocks(n)), dim3(kThreads), 0, st, in, boxes, cold_tmp, bounds, ctx->err);
+    hipLaunchKernelGGL(k_pack, dim3(blocks(n)), dim3(kThreads), 0, st, in, boxes, cold_tmp, mtmp, bounds, ctx->err);
     hipLaunchKernelGGL(k_morton, dim3(blocks(n)), dim3(kThreads), 0, st, n, boxes, bounds, keys, vals);
     UGP_CHECK(hipGetLastError());
     UGP_CHECK(radix_sort(keys, vals, tk, tv, n, st));
@@ -515,7 +589,7 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
                            pleaf, flags, (const uint32_t *)ctx->err);
         hipLaunchKernelGGL(k_depth, dim3(blocks(n)), dim3(kThreads), 0, st, n, pnode, pleaf, depth, ctx->err);
     }
-    hipLaunchKernelGGL(k_scatter, dim3(blocks(n)), dim3(kThreads), 0, st, n, vals, in, cold_tmp, sc.hot,
+    hipLaunchKernelGGL(k_scatter, dim3(blocks(n)), dim3(kThreads), 0, st, n, vals, in, cold_tmp, mtmp, sc.hot,
                        sc.cold, sc.inv, emit_flag);
     UGP_CHECK(hipGetLastError());
     UGP_CHECK(exclusive_scan(emit_flag, emit_pos, n, st));
@@ -549,16 +623,44 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
     sc.n_emit = h_nemit;
     sc.depth = n > 1 ? h_depth : 1;
     sc.root = n > 1 ? 0 : ~0;
-    if (sc.depth > kStackSize) {
-        e = hipErrorNotSupported;
-        goto fail;
+    if (n > 1) {
+        // 4-wide collapse (pnode / flags / keys reused as scratch)
+        int32_t *even = flags, *map = (int32_t *)keys;
+        int32_t h_n4 = 0, h_last = 0;
+        hipLaunchKernelGGL(k_node_parity, dim3(blocks(n - 1)), dim3(kThreads), 0, st, n, pnode, even, ctx->err);
+        UGP_CHECK(hipGetLastError());
+        UGP_CHECK(exclusive_scan(even, map, n - 1, st));
+        UGP_CHECK(hipMemcpyAsync(&h_n4, map + (n - 2), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        UGP_CHECK(hipMemcpyAsync(&h_last, even + (n - 2), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        UGP_CHECK(hipMemcpyAsync(&h_err, ctx->err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        UGP_CHECK(hipStreamSynchronize(st));
+        if (h_err & 16u) {
+            e = hipErrorUnknown;
+            goto fail;
+        }
+        h_n4 += h_last;
+        float4 *nodes4 = nullptr;
+        UGP_CHECK(hipMalloc((void **)&nodes4, sizeof(float4) * 8 * (size_t)h_n4));
+        hipLaunchKernelGGL(k_collapse, dim3(blocks(n - 1)), dim3(kThreads), 0, st, n, (const float4 *)sc.nodes,
+                           (const int32_t *)even, (const int32_t *)map, nodes4);
+        UGP_CHECK(hipGetLastError());
+        UGP_CHECK(hipStreamSynchronize(st));
+        hipFree(sc.nodes);
+        sc.nodes = nodes4;
+        sc.n_nodes4 = h_n4;
+        sc.depth = (sc.depth + 1) / 2 + 1;
+        // a 4-wide node pushes at most three entries
+        if (3 * sc.depth > kStackSize + kStackSpill) {
+            e = hipErrorNotSupported;
+            goto fail;
+        }
     }
     if (h_nemit > 0) {
         UGP_CHECK(hipMalloc((void **)&sc.emit, sizeof(int32_t) * h_nemit));
         hipLaunchKernelGGL(k_compact, dim3(blocks(n)), dim3(kThreads), 0, st, n, emit_flag, emit_pos, sc.emit);
         UGP_CHECK(hipGetLastError());
     }
-    hipFreeAsync(boxes, st); hipFreeAsync(cold_tmp, st); hipFreeAsync(bounds, st);
+    hipFreeAsync(boxes, st); hipFreeAsync(cold_tmp, st); hipFreeAsync(mtmp, st); hipFreeAsync(bounds, st);
     hipFreeAsync(keys, st); hipFreeAsync(tk, st); hipFreeAsync(vals, st); hipFreeAsync(tv, st);
     hipFreeAsync(pnode, st); hipFreeAsync(pleaf, st); hipFreeAsync(flags, st);
     hipFreeAsync(emit_flag, st); hipFreeAsync(emit_pos, st); hipFreeAsync(depth, st);
@@ -568,7 +670,7 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
     return hipSuccess;
 fail:
     hipStreamSynchronize(st);
-    hipFree(boxes); hipFree(cold_tmp); hipFree(bounds); hipFree(keys); hipFree(tk);
+    hipFree(boxes); hipFree(cold_tmp); hipFree(mtmp); hipFree(bounds); hipFree(keys); hipFree(tk);
     hipFree(vals); hipFree(tv); hipFree(pnode); hipFree(pleaf); hipFree(flags);
     hipFree(emit_flag); hipFree(emit_pos); hipFree(depth);
     free_scene(sc);

@@ -41,6 +41,7 @@ struct RenderBuffers {
     LightQueue nee, env;
     float4 *L = nullptr;     // path radiance per pixel
     int32_t *ovf = nullptr;  // overflow index list (cap entries)
+    int2 *hits = nullptr;    // collision result per queue slot (prim, t bits)
     int32_t *counts = nullptr;  // per vertex: [queue in, nee, env] ...
     void *block = nullptr;
 };
@@ -64,7 +65,7 @@ __device__ __forceinline__ V3 f3(float4 v) { return v3(v.x, v.y, v.z); }
 // light pdf of emitter (leaf position ke) seen from x: uniform cone over its
 // bounding sphere, times the uniform emitter choice; 0 inside the sphere
 __device__ __forceinline__ float nee_pdf(const SceneDev &S, int ke, V3 x) {
-    const float4 h0 = S.hot[3 * ke];
+    const float4 h0 = S.hot[4 * ke];
     const float rs = S.cold[3 * ke + 2].w;
     const V3 c = v3(h0.x - x.x, h0.y - x.y, h0.z - x.z);
     const float d2 = dot(c, c);
@@ -106,42 +107,64 @@ struct Overflow {
     int32_t *count;
 };
 
+// Collision sweep of every live path; the result (selected primitive, scatter
+// distance) goes to hits[i].  Paths that overflow the register event buffer
+// are listed in `ovf` and redone by the wide instantiation (WIDE = true).
 template <int K, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_collide(SceneDev S, PassArgs P, int v, Queue qin,
-                                                    const int32_t *n_in, Queue qout, int32_t *n_out,
-                                                    LightQueue nee, int32_t *n_nee, LightQueue env,
-                                                    int32_t *n_env, float4 *L, int64_t *stats,
+                                                    const int32_t *n_in, int2 *hits, int64_t *stats,
                                                     Overflow ovf, uint32_t *err) {
     __shared__ int stack[kStackSize * kBlock];
     const int n = WIDE ? *ovf.count : *n_in;
     if (!WIDE && blockIdx.x == 0 && threadIdx.x == 0)
         atomicAdd((unsigned long long *)&stats[0], (unsigned long long)n);
     TraceCount tc;
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = WIDE ? (int64_t)ovf.idx[j] : j;
+        const float4 A = qin.a[i], B = qin.b[i], C = qin.c[i];
+        const int pix = __float_as_int(C.w);
+        const int excl = __float_as_int(B.w);
+        const float u = rng4(P.seed, (uint32_t)pix, P.sample, (uint32_t)v, 0).u[0];
+        const RayD r = make_ray(A.x, A.y, A.z, B.x, B.y, B.z, 0.f, __builtin_huge_val());
+        const SweepOut so = sweep<K>(S, r, excl, kModeCollide, u, -1, stack, err, tc);
+        if (so.status != 0) {
+            if (WIDE) {
+                atomicOr(err, kErrEvents);
+                hits[i] = make_int2(-1, __float_as_int(0.f));
+            } else {
+                const int slot = atomicAdd(ovf.count, 1);
+                ovf.idx[slot] = (int32_t)i;
+            }
+            continue;
+        }
+        hits[i] = make_int2(so.prim, __float_as_int(so.t));
+    }
+    flush_counts(S, tc);
+}
+
+// Shading of every live path after its collision: emission pick-up (MIS
+// against the light pdf of the previous vertex), environment on escape, one
+// light sample and one environment sample appended to their queues, phase
+// sampling, and compaction of the surviving paths into the next queue.
+__global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PassArgs P, int v, Queue qin, const int32_t *n_in,
+                                                  const int2 *hits, Queue qout, int32_t *n_out, LightQueue nee,
+                                                  int32_t *n_nee, LightQueue env, int32_t *n_env, float4 *L) {
+    const int n = *n_in;
     for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += (int64_t)gridDim.x * kBlock) {
-        const int64_t j = base + threadIdx.x;
-        const bool active = j < n;
-        bool cont = false, do_nee = false, do_env = false, spill = false;
+        const int64_t i = base + threadIdx.x;
+        bool cont = false, do_nee = false, do_env = false;
         float4 ca{}, cb{}, cc{}, na{}, nb{}, nc{}, ea{}, eb{}, ec{};
-        if (active) {
-            const int64_t i = WIDE ? (int64_t)ovf.idx[j] : j;
+        if (i < n) {
             const float4 A = qin.a[i], B = qin.b[i], C = qin.c[i];
+            const int2 hit = hits[i];
             const int pix = __float_as_int(C.w);
-            const int excl = __float_as_int(B.w);
             const float p_prev = A.w;
             const V3 o = f3(A), d = f3(B);
             V3 beta = f3(C);
             const Rng4 g0 = rng4(P.seed, (uint32_t)pix, P.sample, (uint32_t)v, 0);
             const Rng4 g1 = rng4(P.seed, (uint32_t)pix, P.sample, (uint32_t)v, 1);
-            const RayD r = make_ray(o.x, o.y, o.z, d.x, d.y, d.z, 0.0, __builtin_huge_val());
-            const SweepOut so = sweep<K>(S, r, excl, kModeCollide, g0.u[0], -1, stack, err, tc);
-            if (so.status != 0) {
-                if (WIDE) atomicOr(err, kErrEvents);
-                else spill = true;
-            }
             V3 Ladd = v3(0.f, 0.f, 0.f);
-            if (spill) {
-                // redone by the wide pass
-            } else if (so.prim < 0 || so.status != 0) {
+            if (hit.x < 0) {
                 if (P.has_env) {
                     float w = 1.f;
                     if (v > 1) {
@@ -151,10 +174,10 @@ __global__ __launch_bounds__(kBlock) void k_collide(SceneDev S, PassArgs P, int 
                     Ladd = w * mul(beta, v3(P.env[0], P.env[1], P.env[2]));
                 }
             } else {
-                const int k = so.prim;
+                const int k = hit.x;
                 const int ks = S.inv[k];
                 const float4 c0 = S.cold[3 * ks], c1 = S.cold[3 * ks + 1], c2 = S.cold[3 * ks + 2];
-                const V3 x = o + so.t * d;
+                const V3 x = o + __int_as_float(hit.y) * d;
                 const V3 Le = f3(c2);
                 if (nonzero(Le)) {
                     float w = 1.f;
@@ -179,7 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(SceneDev S, PassArgs P, int 
                         j = min(j, S.n_emit - 1);
                         const int e = S.emit[j];
                         const int es = S.inv[e];
-                        const float4 eh = S.hot[3 * es];
+                        const float4 eh = S.hot[4 * es];
                         const float rs = S.cold[3 * es + 2].w;
                         V3 cd = v3(eh.x - x.x, eh.y - x.y, eh.z - x.z);
                         const float d2 = dot(cd, cd);
@@ -200,7 +223,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(SceneDev S, PassArgs P, int 
                             float pph;
                             const V3 f = phase_eval_local(mat, alb, rough, wol, to_local(F, wl), pph);
                             Chord tc;
-                            const RayD lr = make_ray(x.x, x.y, x.z, wl.x, wl.y, wl.z, 0.0, __builtin_huge_val());
+                            const RayD lr = make_ray(x.x, x.y, x.z, wl.x, wl.y, wl.z, 0.f, __builtin_huge_val());
                             if (nonzero(f) && chord(load_hot(S.hot, es), lr, S.r2, tc)) {
                                 const float w = P.mis_mode == 2 ? 1.f : pn / (pn + pph);
                                 const float4 eL = S.cold[3 * es + 2];
@@ -253,10 +276,6 @@ __global__ __launch_bounds__(kBlock) void k_collide(SceneDev S, PassArgs P, int 
                 L[pix] = l;
             }
         }
-        if (!WIDE) {
-            const int ps = wave_append(spill, ovf.count);
-            if (spill) ovf.idx[ps] = (int32_t)j;
-        }
         const int pc = wave_append(cont, n_out);
         if (cont) { qout.a[pc] = ca; qout.b[pc] = cb; qout.c[pc] = cc; }
         const int pn = wave_append(do_nee, n_nee);
@@ -264,7 +283,6 @@ __global__ __launch_bounds__(kBlock) void k_collide(SceneDev S, PassArgs P, int 
         const int pe = wave_append(do_env, n_env);
         if (do_env) { env.a[pe] = ea; env.b[pe] = eb; env.c[pe] = ec; }
     }
-    flush_counts(S, tc);
 }
 
 template <int K, bool WIDE>
@@ -279,7 +297,7 @@ __global__ __launch_bounds__(kBlock) void k_light(SceneDev S, LightQueue q, cons
         const int64_t i = WIDE ? (int64_t)ovf.idx[j] : j;
         const float4 A = q.a[i], B = q.b[i], C = q.c[i];
         const int target = __float_as_int(A.w), excl = __float_as_int(B.w), pix = __float_as_int(C.w);
-        RayD r = make_ray(A.x, A.y, A.z, B.x, B.y, B.z, 0.0, __builtin_huge_val());
+        RayD r = make_ray(A.x, A.y, A.z, B.x, B.y, B.z, 0.f, __builtin_huge_val());
         const HotRec h = load_hot(S.hot, S.inv[target]);
         Chord c;
         if (!chord(h, r, S.r2, c)) continue;
@@ -312,7 +330,7 @@ __global__ __launch_bounds__(kBlock) void k_env(SceneDev S, LightQueue q, const 
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
         const float4 A = q.a[i], B = q.b[i], C = q.c[i];
         const int excl = __float_as_int(B.w), pix = __float_as_int(C.w);
-        const RayD r = make_ray(A.x, A.y, A.z, B.x, B.y, B.z, 0.0, __builtin_huge_val());
+        const RayD r = make_ray(A.x, A.y, A.z, B.x, B.y, B.z, 0.f, __builtin_huge_val());
         const float F = transmittance_F(S, r, excl, true, stack, err, tc);
         const float T = fmaxf(0.f, 1.f - F);
         if (T > 0.f) {
@@ -347,7 +365,8 @@ hipError_t ensure_buffers(ugp_ctx ctx, int64_t cap, int max_vertices) {
     rb = new RenderBuffers();
     const size_t q = sizeof(float4) * (size_t)cap;
     const size_t counts = sizeof(int32_t) * 4 * (size_t)(max_vertices + 2);
-    const size_t total = 12 * q + q + sizeof(int32_t) * (size_t)cap + counts + 16 * 256;
+    const size_t total = 12 * q + q + sizeof(int32_t) * (size_t)cap + sizeof(int2) * (size_t)cap + counts +
+                         16 * 256;
     hipError_t e = hipMalloc(&rb->block, total);
     if (e != hipSuccess) {
         delete rb;
@@ -368,6 +387,7 @@ hipError_t ensure_buffers(ugp_ctx ctx, int64_t cap, int max_vertices) {
     rb->env.a = (float4 *)take(q); rb->env.b = (float4 *)take(q); rb->env.c = (float4 *)take(q);
     rb->L = (float4 *)take(q);
     rb->ovf = (int32_t *)take(sizeof(int32_t) * (size_t)cap);
+    rb->hits = (int2 *)take(sizeof(int2) * (size_t)cap);
     rb->counts = (int32_t *)take(counts);
     rb->cap = cap;
     rb->max_vertices = max_vertices;
@@ -464,13 +484,15 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
             Overflow ov{rb->ovf, c + 3};
             timed(0, [&] {
                 hipLaunchKernelGGL((k_collide<kEventsMain, false>), dim3(gq), dim3(kBlock), 0, st, Sc[0], P, v, qin,
-                                   (const int32_t *)c, qout, c + 4, rb->nee, c + 1, rb->env, c + 2, rb->L,
-                                   ctx->stats, ov, ctx->err);
+                                   (const int32_t *)c, rb->hits, ctx->stats, ov, ctx->err);
             });
             timed(1, [&] {
                 hipLaunchKernelGGL((k_collide<kEventsWide, true>), dim3(gw), dim3(kBlock), 0, st, Sc[1], P, v, qin,
-                                   (const int32_t *)c, qout, c + 4, rb->nee, c + 1, rb->env, c + 2, rb->L,
-                                   ctx->stats, ov, ctx->err);
+                                   (const int32_t *)c, rb->hits, ctx->stats, ov, ctx->err);
+            });
+            timed(4, [&] {
+                hipLaunchKernelGGL(k_shade, dim3(gq), dim3(kBlock), 0, st, S, P, v, qin, (const int32_t *)c,
+                                   (const int2 *)rb->hits, qout, c + 4, rb->nee, c + 1, rb->env, c + 2, rb->L);
             });
             if (v <= p->max_depth) {
                 if (S.n_emit > 0 && p->mis_mode != 1) {

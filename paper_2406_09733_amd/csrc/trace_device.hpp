@@ -2,10 +2,14 @@
 // chord and ray integral, BVH traversal with an LDS stack, transmittance and
 // the ordered sweep that implements primitive-level free-flight sampling.
 //
-// Precision: the ray-frame transform of each candidate primitive (rotation
-// from the quaternion, the map M = S^-1 R^T, closest approach, rho^2) is done
-// in FP64 from the FP32 inputs, because for thin primitives the closest
-// approach cancels ~15 bits; kernel values (erf/erfc/exp) and all sums are FP32.
+// Precision: a primitive record holds M = S^-1 R^T rounded to float.  The ray
+// is first moved to a reference point on it near the mean, p_e = (o - mu) +
+// t_e w with t_e = -(o - mu).w; the closest-approach step from p_e and
+// rho^2 = |M p_m|^2 at the closest point are then taken with FP64 products
+// of the float M.  So the float rounding of M moves t_c only by ~1e-7 of the
+// primitive's own extent (not of its distance to the ray origin), and the
+// 1/s_n amplification of thin primitives never meets float rounding of an
+// offset.  Kernel values (erf/erfc/exp) and all sums are FP32.
 #pragma once
 #include "ugp_internal.hpp"
 #include "ugp_math.hpp"
@@ -32,11 +36,11 @@ __device__ inline void flush_counts(const SceneDev &S, const TraceCount &c) {
 }
 
 struct RayD {
-    double ox, oy, oz;     // origin (exact widening of the float input)
-    double dx, dy, dz;     // direction
-    double t0, t1;         // parameter range
-    float fox, foy, foz;   // float origin for slab tests
-    float idx, idy, idz;   // float inverse direction for slab tests
+    float ox, oy, oz;     // origin
+    float dx, dy, dz;     // direction (unit length)
+    float t0;             // start of the parameter range
+    double t1;            // end of the range (FP64: an emitter query ends at an exact chord exit)
+    float idx, idy, idz;  // inverse direction for slab tests
 };
 
 __device__ __forceinline__ float safe_inv(float d) {
@@ -45,12 +49,11 @@ __device__ __forceinline__ float safe_inv(float d) {
 }
 
 __device__ __forceinline__ RayD make_ray(float ox, float oy, float oz, float dx, float dy, float dz,
-                                         double t0, double t1) {
+                                         float t0, double t1) {
     RayD r;
     r.ox = ox; r.oy = oy; r.oz = oz;
     r.dx = dx; r.dy = dy; r.dz = dz;
     r.t0 = t0; r.t1 = t1;
-    r.fox = ox; r.foy = oy; r.foz = oz;
     r.idx = safe_inv(dx); r.idy = safe_inv(dy); r.idz = safe_inv(dz);
     return r;
 }
@@ -58,7 +61,7 @@ __device__ __forceinline__ RayD make_ray(float ox, float oy, float oz, float dx,
 __device__ __forceinline__ RayD load_ray(const float *rays, int64_t i) {
     const float4 a = reinterpret_cast<const float4 *>(rays)[2 * i];
     const float4 b = reinterpret_cast<const float4 *>(rays)[2 * i + 1];
-    return make_ray(a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w);
+    return make_ray(a.x, a.y, a.z, a.w, b.x, b.y, b.z, (double)b.w);
 }
 
 // ---------------------------------------------------------------------------
@@ -96,51 +99,53 @@ __device__ __forceinline__ float erf_diff(float ta, float tb) {
     return erff(tb) - erff(ta);
 }
 
+// 64-byte primitive record: (mu.xyz, d), (M00 M01 M02 M10), (M11 M12 M20 M21),
+// (M22, original index bits, -, -) with M = S^-1 R^T in float
 struct HotRec {
     float mx, my, mz, d;
-    float qw, qx, qy, qz;
-    float sx, sy, sz;
+    float m[9];
     int orig;
 };
 
 __device__ __forceinline__ HotRec load_hot(const float4 *hot, int i) {
-    const float4 a = hot[3 * i], b = hot[3 * i + 1], c = hot[3 * i + 2];
-    return HotRec{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, __float_as_int(c.w)};
+    const float4 a = hot[4 * i], b = hot[4 * i + 1], c = hot[4 * i + 2], e = hot[4 * i + 3];
+    return HotRec{a.x, a.y, a.z, a.w, {b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w, e.x}, __float_as_int(e.y)};
 }
 
 // Returns false if the clipped chord is empty.
 __device__ inline bool chord(const HotRec &h, const RayD &r, float r2, Chord &c) {
-    const double w = h.qw, x = h.qx, y = h.qy, z = h.qz;
-    const double s2 = 2.0 * rcp_d(w * w + x * x + y * y + z * z);
-    const double xx = x * x * s2, yy = y * y * s2, zz = z * z * s2;
-    const double xy = x * y * s2, xz = x * z * s2, yz = y * z * s2;
-    const double wx = w * x * s2, wy = w * y * s2, wz = w * z * s2;
-    // columns of R: the local axes in world space
-    const double c00 = 1.0 - yy - zz, c01 = xy + wz, c02 = xz - wy;
-    const double c10 = xy - wz, c11 = 1.0 - xx - zz, c12 = yz + wx;
-    const double c20 = xz + wy, c21 = yz - wx, c22 = 1.0 - xx - yy;
-    const double i0 = rcp_d(h.sx), i1 = rcp_d(h.sy), i2 = rcp_d(h.sz);
-    const double ex = r.ox - (double)h.mx, ey = r.oy - (double)h.my, ez = r.oz - (double)h.mz;
-    const double o0 = (c00 * ex + c01 * ey + c02 * ez) * i0;
-    const double o1 = (c10 * ex + c11 * ey + c12 * ez) * i1;
-    const double o2 = (c20 * ex + c21 * ey + c22 * ez) * i2;
-    const double w0 = (c00 * r.dx + c01 * r.dy + c02 * r.dz) * i0;
-    const double w1 = (c10 * r.dx + c11 * r.dy + c12 * r.dz) * i1;
-    const double w2 = (c20 * r.dx + c21 * r.dy + c22 * r.dz) * i2;
+    const float *M = h.m;
+    // reference point on the ray near mu: p_e = (o - mu) + t_e w, FP64
+    const double dx = r.dx, dy = r.dy, dz = r.dz;
+    const double ex = (double)r.ox - (double)h.mx, ey = (double)r.oy - (double)h.my,
+                 ez = (double)r.oz - (double)h.mz;
+    const double te = -(ex * dx + ey * dy + ez * dz);
+    const double px = fma(te, dx, ex), py = fma(te, dy, ey), pz = fma(te, dz, ez);
+    // unit-frame offset q = M p_e and direction w' = M w (FP64 products of the
+    // float M: the normal row of a thin primitive amplifies rounding 1/s_n-fold)
+    const double m0 = M[0], m1 = M[1], m2 = M[2], m3 = M[3], m4 = M[4], m5 = M[5], m6 = M[6],
+                 m7 = M[7], m8 = M[8];
+    const double w0 = m0 * dx + m1 * dy + m2 * dz;
+    const double w1 = m3 * dx + m4 * dy + m5 * dz;
+    const double w2 = m6 * dx + m7 * dy + m8 * dz;
+    const double q0 = m0 * px + m1 * py + m2 * pz;
+    const double q1 = m3 * px + m4 * py + m5 * pz;
+    const double q2 = m6 * px + m7 * py + m8 * pz;
     const double A = w0 * w0 + w1 * w1 + w2 * w2;
-    const double B = o0 * w0 + o1 * w1 + o2 * w2;
-    const double C = o0 * o0 + o1 * o1 + o2 * o2;
-    const double iA = rcp_d(A);
-    const double tc = -B * iA;
-    const double rho2 = fmax(fma(B, tc, C), 0.0);
-    if (!(rho2 < (double)r2)) return false;
-    const float rho2f = (float)rho2;
-    const double half = (double)sqrtf((float)(((double)r2 - rho2) * iA));
-    const double tlo = tc - half, thi = tc + half;
-    const double a = fmax(r.t0, tlo), b = fmin(r.t1, thi);
+    if (!(A > 0.0)) return false;
+    // closest approach t_c = t_e + dt; rho^2 = |q + dt w'|^2
+    const double dt = -(q0 * w0 + q1 * w1 + q2 * w2) * rcp_d(A);
+    const double u0 = fma(dt, w0, q0), u1 = fma(dt, w1, q1), u2 = fma(dt, w2, q2);
+    const float rho2f = (float)(u0 * u0 + u1 * u1 + u2 * u2);
+    if (!(rho2f < r2)) return false;
+    const float Af = (float)A;
+    const double tc = te + dt;
+    const float half = sqrtf((r2 - rho2f) / Af);
+    const double tlo = tc - (double)half, thi = tc + (double)half;
+    const double a = fmax((double)r.t0, tlo), b = fmin(r.t1, thi);
     if (!(a < b)) return false;
-    const float s = sqrtf(0.5f * (float)A);
-    const float taumax = sqrtf(0.5f * fmaxf(r2 - rho2f, 0.f));
+    const float s = sqrtf(0.5f * Af);
+    const float taumax = sqrtf(0.5f * (r2 - rho2f));
     c.tc = tc;
     c.bd = b;
     c.s = s;
@@ -179,32 +184,35 @@ __device__ __forceinline__ float half_kernel_at(const Chord &c, double t) {
 // handled in their parent.  `leaf(prim)` returns true to stop the traversal;
 // `hi()` is re-read after leaves so a shrinking upper bound culls at once.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void slab2(const float4 &n0, const float4 &n1, const float4 &n2,
-                                      const RayD &r, float lo, float hi, bool &hl, bool &hr,
-                                      float &tl, float &tr) {
-    const float ox = r.fox, oy = r.foy, oz = r.foz;
-    const float ix = r.idx, iy = r.idy, iz = r.idz;
-    // left box lo (n0.x, n0.y, n0.z) hi (n0.w, n1.x, n1.y)
-    float ax = (n0.x - ox) * ix, bx = (n0.w - ox) * ix;
-    float ay = (n0.y - oy) * iy, by = (n1.x - oy) * iy;
-    float az = (n0.z - oz) * iz, bz = (n1.y - oz) * iz;
-    float tn = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), lo));
-    float tf = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), hi));
-    hl = tn <= tf + 5e-7f * fmaxf(fabsf(tn), fabsf(tf));
-    tl = tn;
-    // right box lo (n1.z, n1.w, n2.x) hi (n2.y, n2.z, n2.w)
-    ax = (n1.z - ox) * ix; bx = (n2.y - ox) * ix;
-    ay = (n1.w - oy) * iy; by = (n2.z - oy) * iy;
-    az = (n2.x - oz) * iz; bz = (n2.w - oz) * iz;
-    tn = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), lo));
-    tf = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), hi));
-    hr = tn <= tf + 5e-7f * fmaxf(fabsf(tn), fabsf(tf));
-    tr = tn;
+// slab test of one box against the ray on [lo, hi]: entry distance or +inf
+__device__ __forceinline__ float slab(float lx, float ly, float lz, float hx, float hy, float hz,
+                                      const RayD &r, float lo, float hi) {
+    const float ax = (lx - r.ox) * r.idx, bx = (hx - r.ox) * r.idx;
+    const float ay = (ly - r.oy) * r.idy, by = (hy - r.oy) * r.idy;
+    const float az = (lz - r.oz) * r.idz, bz = (hz - r.oz) * r.idz;
+    const float tn = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), lo));
+    const float tf = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), hi));
+    return (tn <= tf + 5e-7f * fmaxf(fabsf(tn), fabsf(tf))) ? tn : kInf;
 }
 
+__device__ __forceinline__ void cswap(float &ta, int &ra, float &tb, int &rb) {
+    const bool s = tb < ta;
+    const float t = s ? tb : ta;
+    tb = s ? ta : tb;
+    ta = t;
+    const int r = s ? rb : ra;
+    rb = s ? ra : rb;
+    ra = r;
+}
+
+// 4-wide BVH traversal: the children of a node are tested together and
+// visited nearest first; leaf children are handled in their parent, farther
+// internal children go on a per-lane LDS stack (column `lane` of a
+// [kStackSize][kBlock] int array).  `leaf(prim)` returns true to stop the
+// traversal; `hi()` is re-read after leaves so a shrinking bound culls at once.
 template <class LeafFn, class HiFn>
-__device__ inline bool traverse(const SceneDev &S, const RayD &r, float lo, HiFn &&hi, int *stack,
-                                uint32_t *err, TraceCount &tc, LeafFn &&leaf) {
+__device__ __forceinline__ bool traverse(const SceneDev &S, const RayD &r, float lo, HiFn &&hi, int *stack,
+                                         uint32_t *err, TraceCount &tc, LeafFn &&leaf) {
     const int lane = threadIdx.x;
     int ref = S.root;
     if (ref < 0) {
@@ -212,51 +220,66 @@ __device__ inline bool traverse(const SceneDev &S, const RayD &r, float lo, HiFn
         return leaf(~ref);
     }
     int sp = 0;
+    // the stack lives in LDS; deeper entries (a 4-wide node can push three)
+    // spill to private memory, which is only touched in that rare case
+    int spill[kStackSpill];
+    auto push = [&](int v) __attribute__((always_inline)) {
+        if (sp < kStackSize) stack[sp * kBlock + lane] = v;
+        else if (sp < kStackSize + kStackSpill) spill[sp - kStackSize] = v;
+        else { atomicOr(err, kErrStack); return; }
+        ++sp;
+    };
     for (;;) {
         ++tc.nodes;
-        const float4 *nd = S.nodes + 4 * (int64_t)ref;
-        const float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
-        const int cl = __float_as_int(n3.x), cr = __float_as_int(n3.y);
-        bool hl, hr;
-        float tl, tr;
-        slab2(n0, n1, n2, r, lo, hi(), hl, hr, tl, tr);
-        // leaf children first (the nearer one first)
-        int leaves[2];
-        int nl = 0;
-        const bool lleaf = hl && cl < 0, rleaf = hr && cr < 0;
-        if (lleaf && rleaf) {
-            leaves[0] = tl <= tr ? ~cl : ~cr;
-            leaves[1] = tl <= tr ? ~cr : ~cl;
-            nl = 2;
-        } else if (lleaf) {
-            leaves[nl++] = ~cl;
-        } else if (rleaf) {
-            leaves[nl++] = ~cr;
-        }
-        for (int i = 0; i < nl; ++i) {
-            ++tc.prims;
-            if (leaf(leaves[i])) return true;
-        }
-        const float h = hi();
-        const bool gl = hl && cl >= 0 && tl <= h + 5e-7f * fabsf(h);
-        const bool gr = hr && cr >= 0 && tr <= h + 5e-7f * fabsf(h);
-        if (gl && gr) {
-            const int nearc = tl <= tr ? cl : cr, farc = tl <= tr ? cr : cl;
-            if (sp < kStackSize) {
-                stack[sp * kBlock + lane] = farc;
-                ++sp;
-            } else {
-                atomicOr(err, kErrStack);
+        const float4 *nd = S.nodes + 8 * (int64_t)ref;
+        const float4 lx = nd[0], ly = nd[1], lz = nd[2], hx = nd[3], hy = nd[4], hz = nd[5], rf = nd[6];
+        const float h0 = hi();
+        float t0 = slab(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, r, lo, h0);
+        float t1 = slab(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, r, lo, h0);
+        float t2 = slab(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, r, lo, h0);
+        float t3 = slab(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, r, lo, h0);
+        int r0 = __float_as_int(rf.x), r1 = __float_as_int(rf.y), r2 = __float_as_int(rf.z),
+            r3 = __float_as_int(rf.w);
+        // unused slots carry an inverted box, which a slab test would take as
+        // unbounded: mask them by their ref
+        t0 = r0 == kEmptySlot ? kInf : t0;
+        t1 = r1 == kEmptySlot ? kInf : t1;
+        t2 = r2 == kEmptySlot ? kInf : t2;
+        t3 = r3 == kEmptySlot ? kInf : t3;
+        // sort the four (entry, ref) pairs by entry distance (misses are +inf)
+        cswap(t0, r0, t1, r1);
+        cswap(t2, r2, t3, r3);
+        cswap(t0, r0, t2, r2);
+        cswap(t1, r1, t3, r3);
+        cswap(t1, r1, t2, r2);
+        // leaves first, nearest first, through one call site
+        for (int i = 0; i < 4; ++i) {
+            const float ti = i == 0 ? t0 : i == 1 ? t1 : i == 2 ? t2 : t3;
+            const int ri = i == 0 ? r0 : i == 1 ? r1 : i == 2 ? r2 : r3;
+            if (ti == kInf) break;
+            if (ri < 0) {
+                ++tc.prims;
+                if (leaf(~ri)) return true;
             }
-            ref = nearc;
-        } else if (gl) {
-            ref = cl;
-        } else if (gr) {
-            ref = cr;
+        }
+        // internal children still within the (possibly shrunk) bound
+        // (a miss is +inf and must stay a miss when the bound itself is +inf)
+        const float h1 = hi();
+        const float lim = h1 + 5e-7f * fabsf(h1);
+        const bool g0 = t0 < kInf && t0 <= lim && r0 >= 0, g1 = t1 < kInf && t1 <= lim && r1 >= 0,
+                   g2 = t2 < kInf && t2 <= lim && r2 >= 0, g3 = t3 < kInf && t3 <= lim && r3 >= 0;
+        // push the farther ones (farthest first), descend into the nearest
+        int next = -1;
+        if (g3) next = r3;
+        if (g2) { if (next >= 0) push(next); next = r2; }
+        if (g1) { if (next >= 0) push(next); next = r1; }
+        if (g0) { if (next >= 0) push(next); next = r0; }
+        if (next >= 0) {
+            ref = next;
         } else {
             if (sp == 0) return false;
             --sp;
-            ref = stack[sp * kBlock + lane];
+            ref = sp < kStackSize ? stack[sp * kBlock + lane] : spill[sp - kStackSize];
         }
     }
 }
@@ -269,9 +292,10 @@ __device__ inline bool traverse(const SceneDev &S, const RayD &r, float lo, HiFn
 __device__ inline float transmittance_F(const SceneDev &S, const RayD &r, int excl, bool early_out,
                                         int *stack, uint32_t *err, TraceCount &tc) {
     float F = 0.f;
-    const float lo = (float)r.t0;
+    const float lo = r.t0;
     const float hi1 = r.t1 < 3.0e38 ? (float)r.t1 : kInf;
-    traverse(S, r, lo, [&]() { return hi1; }, stack, err, tc, [&](int p) {
+    traverse(S, r, lo, [&]() __attribute__((always_inline)) { return hi1; }, stack, err, tc,
+             [&](int p) __attribute__((always_inline)) {
         const HotRec h = load_hot(S.hot, p);
         if (h.orig == excl) return false;
         Chord c;
@@ -326,22 +350,29 @@ struct Unr {
     static constexpr int v = K <= 16 ? K : 1;
 };
 
+// Event buffer as a structure of arrays; fields are copied one by one (a
+// whole-struct copy becomes a memcpy that keeps the buffer out of registers).
 template <int K>
 struct EvBuf {
-    Ev e[K];
+    float a[K], b[K], w[K];
+    int id[K];
     int n;
+    __device__ __forceinline__ void move(int dst, int src) {
+        a[dst] = a[src]; b[dst] = b[src]; w[dst] = w[src]; id[dst] = id[src];
+    }
 };
 
-// select event j (dynamic) out of the register array
+// original index of event j (dynamic j).  For register arrays this is an OR
+// over masked entries: a select of entries would be folded back into an
+// indexed load and force the buffer into scratch memory.
 template <int K>
-__device__ __forceinline__ Ev ev_get(const EvBuf<K> &B, int j) {
+__device__ __forceinline__ int ev_id(const EvBuf<K> &B, int j) {
     if constexpr (K > 16) {
-        return B.e[j];
+        return B.id[j];
     } else {
-        Ev r = B.e[0];
+        int r = 0;
 #pragma unroll
-        for (int i = 1; i < K; ++i)
-            if (i == j) r = B.e[i];
+        for (int i = 0; i < K; ++i) r |= (i == j) ? B.id[i] : 0;
         return r;
     }
 }
@@ -360,21 +391,21 @@ __device__ __forceinline__ Chord ev_chord(const SceneDev &S, const RayD &r, int 
 // F(t) and F'(t) over the buffer: S_fin + sum of (full weights of exits <= t,
 // partial weights of entries before t that exit later)
 template <int K>
-__device__ inline float sweep_F(const SceneDev &S, const RayD &r, const EvBuf<K> &B, float S_fin,
+__device__ __forceinline__ float sweep_F(const SceneDev &S, const RayD &r, const EvBuf<K> &B, float S_fin,
                                 double t, float *dF, TraceCount &tc) {
     float F = S_fin, G = 0.f;
     uint64_t partial = 0;
 #pragma unroll Unr<K>::v
     for (int i = 0; i < K; ++i) {
         if (i < B.n) {
-            if ((double)B.e[i].b <= t) F += B.e[i].w;
-            else if ((double)B.e[i].a < t) partial |= 1ull << i;
+            if ((double)B.b[i] <= t) F += B.w[i];
+            else if ((double)B.a[i] < t) partial |= 1ull << i;
         }
     }
     while (partial) {
         const int j = __builtin_ctzll(partial);
         partial &= partial - 1;
-        const Chord c = ev_chord(S, r, ev_get(B, j).id, tc);
+        const Chord c = ev_chord(S, r, ev_id(B, j), tc);
         F += half_integral_to(c, t);
         G += half_kernel_at(c, t);
     }
@@ -383,7 +414,7 @@ __device__ inline float sweep_F(const SceneDev &S, const RayD &r, const EvBuf<K>
 }
 
 template <int K>
-__device__ inline SweepOut sweep(const SceneDev &S, const RayD &r, int excl, int mode, float u,
+__device__ __forceinline__ SweepOut sweep(const SceneDev &S, const RayD &r, int excl, int mode, float u,
                                  int target, int *stack, uint32_t *err, TraceCount &tc) {
     SweepOut out{-1, __builtin_nanf(""), 0};
     if (mode == kModeSaturate) out.t = (float)r.t1;
@@ -401,26 +432,28 @@ __device__ inline SweepOut sweep(const SceneDev &S, const RayD &r, int excl, int
         int cap_id = 0x7fffffff;
         bool evicted = false;
         const int n_before = B.n;
-        traverse(S, r, fmaxf((float)r.t0, lb_a), [&]() { return fminf(cap_a, t1f); }, stack, err, tc,
-                 [&](int p) {
+        traverse(S, r, fmaxf(r.t0, lb_a), [&]() __attribute__((always_inline)) { return fminf(cap_a, t1f); },
+                 stack, err, tc, [&](int p) __attribute__((always_inline)) {
                      const HotRec h = load_hot(S.hot, p);
                      if (h.orig == excl) return false;
                      Chord c;
                      if (!chord(h, r, S.r2, c)) return false;
                      if (key_less(c.a, c.orig, lb_a, lb_id)) return false;    // seen before
                      if (!key_less(c.a, c.orig, cap_a, cap_id)) return false; // beyond cap
-                     Ev x{c.a, c.b, c.W, c.orig};
+                     float xa = c.a, xb = c.b, xw = c.W;
+                     int xi = c.orig;
                      bool placed = false;
 #pragma unroll Unr<K>::v
                      for (int i = 0; i < K; ++i) {
                          if (i < B.n) {
-                             if (key_less(x.a, x.id, B.e[i].a, B.e[i].id)) {
-                                 const Ev t = B.e[i];
-                                 B.e[i] = x;
-                                 x = t;
+                             if (key_less(xa, xi, B.a[i], B.id[i])) {
+                                 const float ta = B.a[i], tb = B.b[i], tw = B.w[i];
+                                 const int ti = B.id[i];
+                                 B.a[i] = xa; B.b[i] = xb; B.w[i] = xw; B.id[i] = xi;
+                                 xa = ta; xb = tb; xw = tw; xi = ti;
                              }
                          } else if (!placed) {
-                             B.e[i] = x;
+                             B.a[i] = xa; B.b[i] = xb; B.w[i] = xw; B.id[i] = xi;
                              placed = true;
                          }
                      }
@@ -428,8 +461,8 @@ __device__ inline SweepOut sweep(const SceneDev &S, const RayD &r, int excl, int
                          ++B.n;
                      } else {  // x is the largest of K + 1: evict it
                          evicted = true;
-                         cap_a = x.a;
-                         cap_id = x.id;
+                         cap_a = xa;
+                         cap_id = xi;
                      }
                      return false;
                  });
@@ -440,7 +473,7 @@ __device__ inline SweepOut sweep(const SceneDev &S, const RayD &r, int excl, int
         float U = S_fin;
 #pragma unroll Unr<K>::v
         for (int i = 0; i < K; ++i)
-            if (i < B.n && (double)B.e[i].a < t_w) U += B.e[i].w;
+            if (i < B.n && (double)B.a[i] < t_w) U += B.w[i];
         bool saturated = false;
         if (U >= 1.f) {
             const float Fw = sweep_F<K>(S, r, B, S_fin, t_w, nullptr, tc);
@@ -452,8 +485,8 @@ __device__ inline SweepOut sweep(const SceneDev &S, const RayD &r, int excl, int
             uint64_t fin = 0;
 #pragma unroll Unr<K>::v
             for (int i = 0; i < K; ++i)
-                if (i < B.n && (!evicted || (double)B.e[i].b <= t_w)) {
-                    T += B.e[i].w;
+                if (i < B.n && (!evicted || (double)B.b[i] <= t_w)) {
+                    T += B.w[i];
                     fin |= 1ull << i;
                 }
             if (mode == kModeCollide && T > u) {
@@ -466,9 +499,8 @@ __device__ inline SweepOut sweep(const SceneDev &S, const RayD &r, int excl, int
 #pragma unroll Unr<K>::v
                     for (int i = 0; i < K; ++i)
                         if ((fin >> i) & 1ull) {
-                            const Ev &e = B.e[i];
-                            if (key_less(pb, pid, e.b, e.id) && key_less(e.b, e.id, bb, bid)) {
-                                bb = e.b; bid = e.id; bw = e.w; ba = e.a; bi = i;
+                            if (key_less(pb, pid, B.b[i], B.id[i]) && key_less(B.b[i], B.id[i], bb, bid)) {
+                                bb = B.b[i]; bid = B.id[i]; bw = B.w[i]; ba = B.a[i]; bi = i;
                             }
                         }
                     if (bi < 0) break;
@@ -484,7 +516,7 @@ __device__ inline SweepOut sweep(const SceneDev &S, const RayD &r, int excl, int
             if (mode == kModeEmitter) {
 #pragma unroll Unr<K>::v
                 for (int i = 0; i < K; ++i)
-                    if (((fin >> i) & 1ull) && B.e[i].id == target) out.t = B.e[i].w;
+                    if (((fin >> i) & 1ull) && B.id[i] == target) out.t = B.w[i];
             }
             if (!evicted) return out;  // ray complete without saturation
             if (fin == 0ull && B.n == K && n_before == K) {
@@ -498,14 +530,14 @@ __device__ inline SweepOut sweep(const SceneDev &S, const RayD &r, int excl, int
             int wpos = 0;
             if constexpr (K > 16) {
                 for (int i = 0; i < B.n; ++i)
-                    if (!((fin >> i) & 1ull)) B.e[wpos++] = B.e[i];
+                    if (!((fin >> i) & 1ull)) B.move(wpos++, i);
             } else {
-#pragma unroll Unr<K>::v
+#pragma unroll
                 for (int i = 0; i < K; ++i) {
                     if (i < B.n && !((fin >> i) & 1ull)) {
-#pragma unroll Unr<K>::v
+#pragma unroll
                         for (int j = 0; j <= i; ++j)
-                            if (j == wpos) B.e[j] = B.e[i];
+                            if (j == wpos) B.move(j, i);
                         ++wpos;
                     }
                 }
@@ -525,7 +557,7 @@ __device__ inline SweepOut sweep(const SceneDev &S, const RayD &r, int excl, int
             float bmax = -kInf;
 #pragma unroll Unr<K>::v
             for (int i = 0; i < K; ++i)
-                if (i < B.n && (double)B.e[i].a < t_w) bmax = fmaxf(bmax, B.e[i].b);
+                if (i < B.n && (double)B.a[i] < t_w) bmax = fmaxf(bmax, B.b[i]);
             hi = fmin(hi, (double)bmax);
         }
         double t = hi;
@@ -551,9 +583,9 @@ __device__ inline SweepOut sweep(const SceneDev &S, const RayD &r, int excl, int
         if (mode == kModeEmitter) {
 #pragma unroll Unr<K>::v
             for (int i = 0; i < K; ++i)
-                if (i < B.n && B.e[i].id == target) {
-                    if ((double)B.e[i].b <= tsat) out.t = B.e[i].w;
-                    else if ((double)B.e[i].a < tsat) {
+                if (i < B.n && B.id[i] == target) {
+                    if ((double)B.b[i] <= tsat) out.t = B.w[i];
+                    else if ((double)B.a[i] < tsat) {
                         const Chord c = ev_chord(S, r, target, tc);
                         out.t = half_integral_to(c, tsat);
                     }
@@ -569,10 +601,9 @@ __device__ inline SweepOut sweep(const SceneDev &S, const RayD &r, int excl, int
                 int bid = 0x7fffffff, bi = -1;
 #pragma unroll Unr<K>::v
                 for (int i = 0; i < K; ++i)
-                    if (i < B.n && (double)B.e[i].b <= tsat) {
-                        const Ev &e = B.e[i];
-                        if (key_less(pb, pid, e.b, e.id) && key_less(e.b, e.id, bb, bid)) {
-                            bb = e.b; bid = e.id; bw = e.w; ba = e.a; bi = i;
+                    if (i < B.n && (double)B.b[i] <= tsat) {
+                        if (key_less(pb, pid, B.b[i], B.id[i]) && key_less(B.b[i], B.id[i], bb, bid)) {
+                            bb = B.b[i]; bid = B.id[i]; bw = B.w[i]; ba = B.a[i]; bi = i;
                         }
                     }
                 if (bi < 0) break;
@@ -589,9 +620,9 @@ __device__ inline SweepOut sweep(const SceneDev &S, const RayD &r, int excl, int
                 int bid = 0x7fffffff, bi = -1;
 #pragma unroll Unr<K>::v
                 for (int i = 0; i < K; ++i)
-                    if (i < B.n && (double)B.e[i].b > tsat && (double)B.e[i].a < tsat &&
-                        B.e[i].id > pidx && B.e[i].id < bid) {
-                        bid = B.e[i].id;
+                    if (i < B.n && (double)B.b[i] > tsat && (double)B.a[i] < tsat &&
+                        B.id[i] > pidx && B.id[i] < bid) {
+                        bid = B.id[i];
                         bi = i;
                     }
                 if (bi < 0) break;

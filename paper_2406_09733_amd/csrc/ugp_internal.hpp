@@ -9,12 +9,14 @@
 namespace ugp {
 
 // Device-side scene, all arrays in leaf (Morton) order of the hierarchy.
-//   hot   [n][3] float4: (mu.xyz, density), (q.wxyz as given), (scale.xyz, orig id bits)
+//   hot   [n][4] float4: (mu.xyz, density), (M00 M01 M02 M10), (M11 M12 M20 M21),
+//                        (M22, orig id bits, -, -) with M = S^-1 R^T rounded to float
 //   cold  [n][3] float4: (facet normal.xyz, material), (albedo.rgb, roughness),
 //                        (emission.rgb, bounding-sphere radius)
-//   nodes [n-1][4] float4: internal nodes holding the boxes of both children:
-//         (L.lo.xyz, L.hi.x), (L.hi.yz, R.lo.xy), (R.lo.z, R.hi.xyz), (refL, refR, -, -)
-//         a child ref >= 0 is an internal node, < 0 is the leaf primitive ~ref
+//   nodes [n_nodes4][8] float4: 4-wide nodes holding the boxes of up to four
+//         children as lo.x[4], lo.y[4], lo.z[4], hi.x[4], hi.y[4], hi.z[4],
+//         ref[4], pad; a ref >= 0 is a node, < 0 is the leaf primitive ~ref,
+//         kEmptySlot marks an unused slot
 //   inv   [n] original index -> leaf position
 //   emit  [n_emit] original indices of emissive primitives, ascending
 struct SceneDev {
@@ -27,7 +29,8 @@ struct SceneDev {
     int32_t *inv = nullptr;
     int32_t *emit = nullptr;
     int32_t n_emit = 0;
-    int32_t depth = 0;     // depth of the hierarchy (root = 1)
+    int32_t depth = 0;     // depth of the 4-wide hierarchy (root = 1)
+    int64_t n_nodes4 = 0;
     unsigned long long *count = nullptr;  // [3] node visits, primitive tests, reloads (profiling)
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};  // bounds of the primitive boxes
 };
@@ -38,7 +41,9 @@ enum : uint32_t { kErrStack = 1u, kErrEvents = 2u, kErrQueue = 4u };
 // Sweep modes of the ordered traversal
 enum SweepMode : int { kModeCollide = 0, kModeSaturate = 1, kModeEmitter = 2 };
 
-constexpr int kStackSize = 64;   // traversal stack entries per lane (LDS)
+constexpr int kStackSize = 32;   // traversal stack entries per lane in LDS
+constexpr int kStackSpill = 160; // further entries per lane in private memory
+constexpr int32_t kEmptySlot = 0x7fffffff;
 constexpr int kEventsMain = 16;  // event buffer of the main sweep (registers)
 constexpr int kEventsWide = 64;  // event buffer of the overflow sweep
 
@@ -63,7 +68,7 @@ struct ugp_ctx_s {
     int64_t *stats = nullptr;       // device counters of the last render: [collision, light, env]
     unsigned long long *counters = nullptr;  // [3] traversal counters (profiling level 2)
     int profiling = 0;
-    // event pairs of the last render, by category: 0 collide main, 1 collide wide, 2 light, 3 env
+    // event pairs of the last render, by category: 0 collide main, 1 collide wide, 2 light, 3 env, 4 shade
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<int, int>> ev_used;  // (category, index of the start event)
     bool ev_cat_valid = false;

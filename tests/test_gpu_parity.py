@@ -3,7 +3,9 @@ CPU oracle on identical seeded inputs, through the C ABI.
 
 Tolerances ("Parity bar"):
   T                    |dT| <= 1e-5
-  F, I, emitter factor |dx| <= 1e-5 max(|x|, 1e-3)
+  F, I, emitter factor |dx| <= 1e-5 max(|x|, 1e-3) + 5e-7   (5e-7 = 4 ulp of 1.0 in
+                       float32: these are float sums / differences of erf values of
+                       order one, so their absolute error does not shrink with x)
   t_sat, scatter t     |dt| <= 1e-5 max(|t|, 1e-3), or F_oracle(t_gpu) within 2e-5 of 1
   selected primitive   identical wherever the oracle's margin |u - boundary| > 1e-5
 """
@@ -46,8 +48,11 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-def _rel_ok(got, ref, rtol=1e-5, floor=1e-3):
-    return np.abs(got - ref) <= rtol * np.maximum(np.abs(ref), floor)
+def _rel_ok(got, ref, rtol=1e-5, floor=1e-3, atol=0.0):
+    return np.abs(got - ref) <= rtol * np.maximum(np.abs(ref), floor) + atol
+
+
+ATOL_SUM = 5e-7  # 4 ulp of 1.0 in float32
 
 
 def _cases():
@@ -81,7 +86,7 @@ def test_transmittance_parity(ctx, built, name):
     ctx.sync()
     T, F = _np(T), _np(F)
     assert np.all(np.abs(T - T_ref) <= 1e-5), np.abs(T - T_ref).max()
-    ok = _rel_ok(F, F_ref)
+    ok = _rel_ok(F, F_ref, atol=ATOL_SUM)
     assert ok.all(), (np.where(~ok)[0][:10], F[~ok][:5], F_ref[~ok][:5])
     # early-exit variant: same T
     T2, _ = ctx.transmittance(rays, ex)
@@ -152,7 +157,7 @@ def test_emitter_query_parity(ctx, built, name):
     ref = S.emitter_query(rays, tgt, ex)
     got = _np(ctx.emitter_query(rays, tgt, ex)).astype(np.float64)
     ctx.sync()
-    ok = _rel_ok(got, ref)
+    ok = _rel_ok(got, ref, atol=ATOL_SUM)
     if not ok.all():
         for i in np.where(~ok)[0][:6]:
             ch = S.chord(int(tgt[i]), rays[i])
