@@ -13,8 +13,8 @@ paper_2406_09733_amd/scenes.py); inputs are resident in HBM before timing.
 
 Besides the JSON line's throughput it reports:
   roofline     the dominant kernel (the collision kernel): algorithmic bytes
-               per launch (BVH node records 64 B, primitive records 48 B,
-               re-read records 48 B, path-queue records 96 B per ray) divided
+               per launch (4-wide BVH node records 128 B, primitive records 64 B,
+               re-read records 64 B, path-queue records 96 B per ray) divided
                by its mean launch duration from HIP events recorded around
                every launch during the timed run, against 8 TB/s HBM;
   cpu_baseline the FP64 CPU oracle on a bounded pixel subset of the same
@@ -34,7 +34,7 @@ if ROOT not in sys.path:
 
 METRIC = "Mrays/s at 5.5M prims; time-to-RMSE 0.01, plain vs neural-cache tracer"
 HBM_PEAK_GBS = 8000.0
-NODE_B, PRIM_B, PATH_B = 64, 48, 96
+NODE_B, PRIM_B, PATH_B = 128, 64, 96
 
 
 def log(*a):
@@ -139,7 +139,8 @@ def main():
         f"{st['light_rays']} light, {st['env_rays']} env), {mrays:.1f} Mrays/s, "
         f"{st['paths'] / dt / 1e6:.2f} M paths/s; mean clamped pixel {mean_pix:.4f}")
     log(f"[bench] kernel ms: collide {st['ms_collide']:.1f} ({st['launches_collide']} launches), "
-        f"overflow {st['ms_collide_wide']:.2f}, light {st['ms_light']:.1f}, env {st['ms_env']:.1f}")
+        f"overflow {st['ms_collide_wide']:.2f}, light {st['ms_light']:.1f}, env {st['ms_env']:.1f}, "
+        f"shade {st['ms_shade']:.1f}, sort {st['ms_sort']:.1f}")
 
     launches = max(st["launches_collide"], 1)
     achieved = (bytes_per_coll_ray * st["collision_rays"] / launches) / (st["ms_collide"] / launches * 1e-3) / 1e9

@@ -193,6 +193,7 @@ typedef struct {
     double ms_light;         /* ... of the light-sample kernels (main + overflow) */
     double ms_env;           /* ... of the environment kernels */
     double ms_shade;         /* ... of the shading / path-compaction kernels */
+    double ms_sort;          /* ... of the ray-sorting kernels */
     int32_t launches_collide, launches_light, launches_env;
     /* the three traversal counters split by kernel: [0] collision, [1] collision
        overflow pass, [2] light samples, [3] environment samples (level 2, else -1) */

@@ -52,6 +52,7 @@ class _Stats(C.Structure):
                 ("env_rays", C.c_int64), ("node_visits", C.c_int64), ("prim_tests", C.c_int64),
                 ("prim_reloads", C.c_int64), ("ms_collide", C.c_double), ("ms_collide_wide", C.c_double),
                 ("ms_light", C.c_double), ("ms_env", C.c_double), ("ms_shade", C.c_double),
+                ("ms_sort", C.c_double),
                 ("launches_collide", C.c_int32),
                 ("launches_light", C.c_int32), ("launches_env", C.c_int32),
                 ("cat_nodes", C.c_int64 * 4), ("cat_prims", C.c_int64 * 4), ("cat_reloads", C.c_int64 * 4)]

@@ -252,13 +252,14 @@ ugp_status ugp_get_render_stats(ugp_ctx ctx, ugp_render_stats *out) {
             out->prim_reloads += out->cat_reloads[k];
         }
     }
-    out->ms_collide = out->ms_collide_wide = out->ms_light = out->ms_env = out->ms_shade = -1.0;
+    out->ms_collide = out->ms_collide_wide = out->ms_light = out->ms_env = out->ms_shade = out->ms_sort = -1.0;
     if (ctx->ev_cat_valid) {
-        double ms[5] = {0, 0, 0, 0, 0};
-        int cnt[5] = {0, 0, 0, 0, 0};
+        double ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         for (const auto &u : ctx->ev_used) {
             float t = 0.f;
-            if (hipEventElapsedTime(&t, ctx->ev_pool[u.second], ctx->ev_pool[u.second + 1]) == hipSuccess) {
+            if (u.first >= 0 && u.first < 8 &&
+                hipEventElapsedTime(&t, ctx->ev_pool[u.second], ctx->ev_pool[u.second + 1]) == hipSuccess) {
                 ms[u.first] += t;
                 cnt[u.first] += 1;
             }
@@ -268,6 +269,7 @@ ugp_status ugp_get_render_stats(ugp_ctx ctx, ugp_render_stats *out) {
         out->ms_light = ms[2];
         out->ms_env = ms[3];
         out->ms_shade = ms[4];
+        out->ms_sort = ms[5];
         out->launches_collide = cnt[0];
         out->launches_light = cnt[2];
         out->launches_env = cnt[3];

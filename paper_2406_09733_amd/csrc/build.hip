@@ -24,8 +24,166 @@
 
 namespace ugp {
 namespace {
-
 constexpr int kThreads = 256;
+}  // namespace
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// exclusive scan of int32 (device-wide, recursive over block sums)
+// ---------------------------------------------------------------------------
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kThreads * kScanItems;
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int *sh, int &total) {
+    // Hillis-Steele over kThreads values in LDS
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kThreads; off <<= 1) {
+        const int x = t >= off ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += x;
+        __syncthreads();
+    }
+    total = sh[kThreads - 1];
+    const int incl = sh[t];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ void k_scan_tiles(const int *in, int *out, int64_t n, int *tile_sums) {
+    __shared__ int sh[kThreads];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int sum = 0;
+    for (int i = 0; i < kScanItems; ++i) {
+        v[i] = (base + i < n) ? in[base + i] : 0;
+        sum += v[i];
+    }
+    int total;
+    int run = block_exclusive_scan(sum, sh, total);
+    for (int i = 0; i < kScanItems; ++i) {
+        if (base + i < n) out[base + i] = run;
+        run += v[i];
+    }
+    if (threadIdx.x == 0 && tile_sums) tile_sums[blockIdx.x] = total;
+}
+
+__global__ void k_scan_add(int *out, int64_t n, const int *tile_off) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    const int add = tile_off[blockIdx.x];
+    for (int i = 0; i < kScanItems; ++i)
+        if (base + i < n) out[base + i] += add;
+}
+
+// ---------------------------------------------------------------------------
+// stable LSD radix sort, 8-bit digits
+// ---------------------------------------------------------------------------
+constexpr int kSortChunks = 16;
+constexpr int kSortTile = kThreads * kSortChunks;
+
+__global__ void k_sort_hist(const uint32_t *keys, int64_t n, int shift, int *hist, int nblocks) {
+    __shared__ int h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int c = 0; c < kSortChunks; ++c) {
+        const int64_t i = base + (int64_t)c * kThreads + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void k_sort_scatter(const uint32_t *keys, const int32_t *vals, uint32_t *okeys,
+                               int32_t *ovals, int64_t n, int shift, const int *offs, int nblocks) {
+    __shared__ int base[256];
+    __shared__ int cnt[kThreads / 64][256];
+    const int t = threadIdx.x;
+    const int wave = t >> 6, lane = t & 63;
+    base[t] = offs[(int64_t)t * nblocks + blockIdx.x];
+    const int64_t tile = (int64_t)blockIdx.x * kSortTile;
+    for (int c = 0; c < kSortChunks; ++c) {
+        for (int w = 0; w < kThreads / 64; ++w) cnt[w][t] = 0;
+        __syncthreads();
+        const int64_t i = tile + (int64_t)c * kThreads + t;
+        const bool valid = i < n;
+        const uint32_t key = valid ? keys[i] : 0u;
+        const int32_t val = valid ? vals[i] : 0;
+        const uint32_t dig = (key >> shift) & 255u;
+        // lanes of this wave holding the same digit
+        uint64_t same = __ballot(valid);
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t bal = __ballot((dig >> b) & 1u);
+            same &= ((dig >> b) & 1u) ? bal : ~bal;
+        }
+        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        const int rank = __popcll(same & below);
+        if (valid && rank == 0) cnt[wave][dig] = __popcll(same);
+        __syncthreads();
+        if (valid) {
+            int pos = base[dig] + rank;
+            for (int w = 0; w < wave; ++w) pos += cnt[w][dig];
+            okeys[pos] = key;
+            ovals[pos] = val;
+        }
+        __syncthreads();
+        int tot = 0;
+        for (int w = 0; w < kThreads / 64; ++w) tot += cnt[w][t];
+        base[t] += tot;
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+hipError_t exclusive_scan(const int *in, int *out, int64_t n, hipStream_t st) {
+    const int64_t tiles = (n + kScanTile - 1) / kScanTile;
+    if (tiles <= 1) {
+        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kThreads), 0, st, in, out, n, (int *)nullptr);
+        return hipGetLastError();
+    }
+    int *sums = nullptr;
+    hipError_t e = hipMallocAsync((void **)&sums, sizeof(int) * 2 * tiles, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(kThreads), 0, st, in, out, n, sums);
+    e = exclusive_scan(sums, sums + tiles, tiles, st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)tiles), dim3(kThreads), 0, st, out, n,
+                           (const int *)(sums + tiles));
+        e = hipGetLastError();
+    }
+    hipFreeAsync(sums, st);
+    return e;
+}
+
+hipError_t radix_sort(uint32_t *keys, int32_t *vals, uint32_t *tk, int32_t *tv, int64_t n,
+                      hipStream_t st) {
+    const int nblocks = (int)((n + kSortTile - 1) / kSortTile);
+    int *hist = nullptr;
+    hipError_t e = hipMallocAsync((void **)&hist, sizeof(int) * 2 * 256 * (size_t)nblocks, st);
+    if (e != hipSuccess) return e;
+    int *offs = hist + 256 * (size_t)nblocks;
+    uint32_t *ka = keys, *kb = tk;
+    int32_t *va = vals, *vb = tv;
+    for (int shift = 0; shift < 32 && e == hipSuccess; shift += 8) {
+        hipLaunchKernelGGL(k_sort_hist, dim3(nblocks), dim3(kThreads), 0, st, ka, n, shift, hist, nblocks);
+        e = exclusive_scan(hist, offs, 256 * (int64_t)nblocks, st);
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(k_sort_scatter, dim3(nblocks), dim3(kThreads), 0, st, ka, va, kb, vb, n, shift,
+                           offs, nblocks);
+        e = hipGetLastError();
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    hipFreeAsync(hist, st);
+    return e;  // 4 passes: result back in keys / vals
+}
+
+
+namespace {
+
 
 __device__ __forceinline__ float round_down(double x) {
     float f = (float)x;
@@ -139,156 +297,6 @@ __global__ void k_morton(int64_t n, const float *boxes, const uint32_t *bounds, 
     code = (expand10(q[0]) << 2) | (expand10(q[1]) << 1) | expand10(q[2]);
     keys[k] = code;
     vals[k] = (int32_t)k;
-}
-
-// ---------------------------------------------------------------------------
-// exclusive scan of int32 (device-wide, recursive over block sums)
-// ---------------------------------------------------------------------------
-constexpr int kScanItems = 4;
-constexpr int kScanTile = kThreads * kScanItems;
-
-__device__ __forceinline__ int block_exclusive_scan(int v, int *sh, int &total) {
-    // Hillis-Steele over kThreads values in LDS
-    const int t = threadIdx.x;
-    sh[t] = v;
-    __syncthreads();
-    for (int off = 1; off < kThreads; off <<= 1) {
-        const int x = t >= off ? sh[t - off] : 0;
-        __syncthreads();
-        sh[t] += x;
-        __syncthreads();
-    }
-    total = sh[kThreads - 1];
-    const int incl = sh[t];
-    __syncthreads();
-    return incl - v;
-}
-
-__global__ void k_scan_tiles(const int *in, int *out, int64_t n, int *tile_sums) {
-    __shared__ int sh[kThreads];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    int v[kScanItems];
-    int sum = 0;
-    for (int i = 0; i < kScanItems; ++i) {
-        v[i] = (base + i < n) ? in[base + i] : 0;
-        sum += v[i];
-    }
-    int total;
-    int run = block_exclusive_scan(sum, sh, total);
-    for (int i = 0; i < kScanItems; ++i) {
-        if (base + i < n) out[base + i] = run;
-        run += v[i];
-    }
-    if (threadIdx.x == 0 && tile_sums) tile_sums[blockIdx.x] = total;
-}
-
-__global__ void k_scan_add(int *out, int64_t n, const int *tile_off) {
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    const int add = tile_off[blockIdx.x];
-    for (int i = 0; i < kScanItems; ++i)
-        if (base + i < n) out[base + i] += add;
-}
-
-hipError_t exclusive_scan(const int *in, int *out, int64_t n, hipStream_t st) {
-    const int64_t tiles = (n + kScanTile - 1) / kScanTile;
-    if (tiles <= 1) {
-        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kThreads), 0, st, in, out, n, (int *)nullptr);
-        return hipGetLastError();
-    }
-    int *sums = nullptr;
-    hipError_t e = hipMallocAsync((void **)&sums, sizeof(int) * 2 * tiles, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(kThreads), 0, st, in, out, n, sums);
-    e = exclusive_scan(sums, sums + tiles, tiles, st);
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)tiles), dim3(kThreads), 0, st, out, n,
-                           (const int *)(sums + tiles));
-        e = hipGetLastError();
-    }
-    hipFreeAsync(sums, st);
-    return e;
-}
-
-// ---------------------------------------------------------------------------
-// stable LSD radix sort, 8-bit digits
-// ---------------------------------------------------------------------------
-constexpr int kSortChunks = 16;
-constexpr int kSortTile = kThreads * kSortChunks;
-
-__global__ void k_sort_hist(const uint32_t *keys, int64_t n, int shift, int *hist, int nblocks) {
-    __shared__ int h[256];
-    h[threadIdx.x] = 0;
-    __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
-    for (int c = 0; c < kSortChunks; ++c) {
-        const int64_t i = base + (int64_t)c * kThreads + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1);
-    }
-    __syncthreads();
-    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
-}
-
-__global__ void k_sort_scatter(const uint32_t *keys, const int32_t *vals, uint32_t *okeys,
-                               int32_t *ovals, int64_t n, int shift, const int *offs, int nblocks) {
-    __shared__ int base[256];
-    __shared__ int cnt[kThreads / 64][256];
-    const int t = threadIdx.x;
-    const int wave = t >> 6, lane = t & 63;
-    base[t] = offs[(int64_t)t * nblocks + blockIdx.x];
-    const int64_t tile = (int64_t)blockIdx.x * kSortTile;
-    for (int c = 0; c < kSortChunks; ++c) {
-        for (int w = 0; w < kThreads / 64; ++w) cnt[w][t] = 0;
-        __syncthreads();
-        const int64_t i = tile + (int64_t)c * kThreads + t;
-        const bool valid = i < n;
-        const uint32_t key = valid ? keys[i] : 0u;
-        const int32_t val = valid ? vals[i] : 0;
-        const uint32_t dig = (key >> shift) & 255u;
-        // lanes of this wave holding the same digit
-        uint64_t same = __ballot(valid);
-        for (int b = 0; b < 8; ++b) {
-            const uint64_t bal = __ballot((dig >> b) & 1u);
-            same &= ((dig >> b) & 1u) ? bal : ~bal;
-        }
-        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-        const int rank = __popcll(same & below);
-        if (valid && rank == 0) cnt[wave][dig] = __popcll(same);
-        __syncthreads();
-        if (valid) {
-            int pos = base[dig] + rank;
-            for (int w = 0; w < wave; ++w) pos += cnt[w][dig];
-            okeys[pos] = key;
-            ovals[pos] = val;
-        }
-        __syncthreads();
-        int tot = 0;
-        for (int w = 0; w < kThreads / 64; ++w) tot += cnt[w][t];
-        base[t] += tot;
-        __syncthreads();
-    }
-}
-
-hipError_t radix_sort(uint32_t *keys, int32_t *vals, uint32_t *tk, int32_t *tv, int64_t n,
-                      hipStream_t st) {
-    const int nblocks = (int)((n + kSortTile - 1) / kSortTile);
-    int *hist = nullptr;
-    hipError_t e = hipMallocAsync((void **)&hist, sizeof(int) * 2 * 256 * (size_t)nblocks, st);
-    if (e != hipSuccess) return e;
-    int *offs = hist + 256 * (size_t)nblocks;
-    uint32_t *ka = keys, *kb = tk;
-    int32_t *va = vals, *vb = tv;
-    for (int shift = 0; shift < 32 && e == hipSuccess; shift += 8) {
-        hipLaunchKernelGGL(k_sort_hist, dim3(nblocks), dim3(kThreads), 0, st, ka, n, shift, hist, nblocks);
-        e = exclusive_scan(hist, offs, 256 * (int64_t)nblocks, st);
-        if (e != hipSuccess) break;
-        hipLaunchKernelGGL(k_sort_scatter, dim3(nblocks), dim3(kThreads), 0, st, ka, va, kb, vb, n, shift,
-                           offs, nblocks);
-        e = hipGetLastError();
-        std::swap(ka, kb);
-        std::swap(va, vb);
-    }
-    hipFreeAsync(hist, st);
-    return e;  // 4 passes: result back in keys / vals
 }
 
 // ---------------------------------------------------------------------------
@@ -500,7 +508,9 @@ __global__ void k_scatter(int64_t n, const int32_t *sorted_orig, PackIn in, cons
     hot[4 * i] = make_float4(in.mean[3 * o], in.mean[3 * o + 1], in.mean[3 * o + 2], in.dens[o]);
     hot[4 * i + 1] = make_float4(M[0], M[1], M[2], M[3]);
     hot[4 * i + 2] = make_float4(M[4], M[5], M[6], M[7]);
-    hot[4 * i + 3] = make_float4(M[8], __int_as_float((int)o), 0.f, 0.f);
+    // largest row norm of M, 1 / min(s): bounds how M magnifies an offset
+    const float smin = fminf(in.scale[3 * o], fminf(in.scale[3 * o + 1], in.scale[3 * o + 2]));
+    hot[4 * i + 3] = make_float4(M[8], __int_as_float((int)o), 1.0f / smin, 0.f);
     for (int c = 0; c < 3; ++c) cold[3 * i + c] = cold_tmp[3 * o + c];
     inv[o] = (int32_t)i;
     const float4 e = cold_tmp[3 * o + 2];

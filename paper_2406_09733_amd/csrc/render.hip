@@ -42,6 +42,8 @@ struct RenderBuffers {
     float4 *L = nullptr;     // path radiance per pixel
     int32_t *ovf = nullptr;  // overflow index list (cap entries)
     int2 *hits = nullptr;    // collision result per queue slot (prim, t bits)
+    uint32_t *skey = nullptr, *skey2 = nullptr;  // ray-sort keys (and scratch)
+    int32_t *sval = nullptr, *sval2 = nullptr;   // ray-sort permutation (and scratch)
     int32_t *counts = nullptr;  // per vertex: [queue in, nee, env] ...
     void *block = nullptr;
 };
@@ -49,9 +51,13 @@ struct RenderBuffers {
 namespace {
 
 constexpr int kPersistBlocks = 4096;
+// per-vertex counters: [0] paths in, [1] light samples, [2] environment
+// samples, [3] overflow, [4] collision work, [5] light work
+constexpr int kCountStride = 8;
 
 struct PassArgs {
     CamDev cam;
+    float blo[3], binv[3];   // scene bounds (origin quantisation for ray sorting)
     uint64_t seed;
     uint32_t sample;
     int max_depth;
@@ -107,20 +113,67 @@ struct Overflow {
     int32_t *count;
 };
 
+// Sort key of a queued ray: 6 bits each of its origin (in the scene bounds)
+// and of its direction (octahedral map) interleaved into 30 bits, so that a
+// wave's rays start near each other and point the same way.  Slots past the
+// queue length get the largest key.
+__device__ __forceinline__ uint32_t spread5(uint32_t v, int k) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) r |= ((v >> b) & 1u) << (5 * b + k);
+    return r;
+}
+
+__global__ void k_sort_keys(PassArgs P, Queue q, const int32_t *n_in, int64_t cap, uint32_t *keys,
+                            int32_t *vals) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= cap) return;
+    vals[j] = (int32_t)j;
+    if (j >= *n_in) {
+        keys[j] = 0xffffffffu;
+        return;
+    }
+    const float4 A = q.a[j], B = q.b[j];
+    uint32_t c[5];
+    const float o[3] = {A.x, A.y, A.z};
+    for (int k = 0; k < 3; ++k)
+        c[k] = (uint32_t)fminf(fmaxf((o[k] - P.blo[k]) * P.binv[k] * 64.f, 0.f), 63.f);
+    // octahedral map of the direction to [0,1]^2
+    const float l1 = fabsf(B.x) + fabsf(B.y) + fabsf(B.z);
+    float u = B.x / l1, v = B.y / l1;
+    if (B.z < 0.f) {
+        const float uu = (1.f - fabsf(v)) * (u >= 0.f ? 1.f : -1.f);
+        const float vv = (1.f - fabsf(u)) * (v >= 0.f ? 1.f : -1.f);
+        u = uu;
+        v = vv;
+    }
+    c[3] = (uint32_t)fminf(fmaxf((u * 0.5f + 0.5f) * 64.f, 0.f), 63.f);
+    c[4] = (uint32_t)fminf(fmaxf((v * 0.5f + 0.5f) * 64.f, 0.f), 63.f);
+    uint32_t key = 0;
+    for (int k = 0; k < 5; ++k) key |= spread5(c[k], 4 - k);
+    keys[j] = key;
+}
+
+// next chunk of 64 queue entries for this wave (dynamic load balance)
+__device__ __forceinline__ int64_t wave_grab(int32_t *work) {
+    int base = 0;
+    if ((threadIdx.x & 63) == 0) base = atomicAdd(work, 64);
+    return (int64_t)__shfl(base, 0);
+}
+
 // Collision sweep of every live path; the result (selected primitive, scatter
 // distance) goes to hits[i].  Paths that overflow the register event buffer
 // are listed in `ovf` and redone by the wide instantiation (WIDE = true).
 template <int K, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_collide(SceneDev S, PassArgs P, int v, Queue qin,
-                                                    const int32_t *n_in, int2 *hits, int64_t *stats,
-                                                    Overflow ovf, uint32_t *err) {
+                                                    const int32_t *n_in, const int32_t *order, int32_t *work,
+                                                    int2 *hits, int64_t *stats, Overflow ovf, uint32_t *err) {
     __shared__ int stack[kStackSize * kBlock];
     const int n = WIDE ? *ovf.count : *n_in;
     if (!WIDE && blockIdx.x == 0 && threadIdx.x == 0)
         atomicAdd((unsigned long long *)&stats[0], (unsigned long long)n);
     TraceCount tc;
-    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
-        const int64_t i = WIDE ? (int64_t)ovf.idx[j] : j;
+    auto process = [&](int64_t i) __attribute__((always_inline)) {
         const float4 A = qin.a[i], B = qin.b[i], C = qin.c[i];
         const int pix = __float_as_int(C.w);
         const int excl = __float_as_int(B.w);
@@ -135,9 +188,21 @@ __global__ __launch_bounds__(kBlock) void k_collide(SceneDev S, PassArgs P, int 
                 const int slot = atomicAdd(ovf.count, 1);
                 ovf.idx[slot] = (int32_t)i;
             }
-            continue;
+            return;
         }
         hits[i] = make_int2(so.prim, __float_as_int(so.t));
+    };
+    if (WIDE) {
+        for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock)
+            process((int64_t)ovf.idx[j]);
+    } else {
+        // waves take chunks of 64 sorted queue entries until the queue is done
+        for (;;) {
+            const int64_t base = wave_grab(work);
+            if (base >= n) break;
+            const int64_t j = base + threadIdx.x;
+            if (j < n) process((int64_t)order[j]);
+        }
     }
     flush_counts(S, tc);
 }
@@ -286,21 +351,21 @@ __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PassArgs P, int v,
 }
 
 template <int K, bool WIDE>
-__global__ __launch_bounds__(kBlock) void k_light(SceneDev S, LightQueue q, const int32_t *n_in, float4 *L,
-                                                  int64_t *stats, Overflow ovf, uint32_t *err) {
+__global__ __launch_bounds__(kBlock) void k_light(SceneDev S, LightQueue q, const int32_t *n_in,
+                                                  const int32_t *order, int32_t *work, float4 *L, int64_t *stats,
+                                                  Overflow ovf, uint32_t *err) {
     __shared__ int stack[kStackSize * kBlock];
     const int n = WIDE ? *ovf.count : *n_in;
     if (!WIDE && blockIdx.x == 0 && threadIdx.x == 0)
         atomicAdd((unsigned long long *)&stats[1], (unsigned long long)n);
     TraceCount tc;
-    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
-        const int64_t i = WIDE ? (int64_t)ovf.idx[j] : j;
+    auto process = [&](int64_t i) __attribute__((always_inline)) {
         const float4 A = q.a[i], B = q.b[i], C = q.c[i];
         const int target = __float_as_int(A.w), excl = __float_as_int(B.w), pix = __float_as_int(C.w);
         RayD r = make_ray(A.x, A.y, A.z, B.x, B.y, B.z, 0.f, __builtin_huge_val());
         const HotRec h = load_hot(S.hot, S.inv[target]);
         Chord c;
-        if (!chord(h, r, S.r2, c)) continue;
+        if (!chord(h, r, S.r2, c)) return;
         r.t1 = c.bd;
         const SweepOut so = sweep<K>(S, r, excl, kModeEmitter, 0.f, target, stack, err, tc);
         if (so.status != 0) {
@@ -310,12 +375,23 @@ __global__ __launch_bounds__(kBlock) void k_light(SceneDev S, LightQueue q, cons
                 const int slot = atomicAdd(ovf.count, 1);
                 ovf.idx[slot] = (int32_t)i;
             }
-            continue;
+            return;
         }
         if (so.t > 0.f) {
             float4 l = L[pix];
             l.x += C.x * so.t; l.y += C.y * so.t; l.z += C.z * so.t;
             L[pix] = l;
+        }
+    };
+    if (WIDE) {
+        for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock)
+            process((int64_t)ovf.idx[j]);
+    } else {
+        for (;;) {
+            const int64_t base = wave_grab(work);
+            if (base >= n) break;
+            const int64_t j = base + threadIdx.x;
+            if (j < n) process((int64_t)order[j]);
         }
     }
     flush_counts(S, tc);
@@ -364,9 +440,9 @@ hipError_t ensure_buffers(ugp_ctx ctx, int64_t cap, int max_vertices) {
     free_render(ctx);
     rb = new RenderBuffers();
     const size_t q = sizeof(float4) * (size_t)cap;
-    const size_t counts = sizeof(int32_t) * 4 * (size_t)(max_vertices + 2);
+    const size_t counts = sizeof(int32_t) * kCountStride * (size_t)(max_vertices + 2);
     const size_t total = 12 * q + q + sizeof(int32_t) * (size_t)cap + sizeof(int2) * (size_t)cap + counts +
-                         16 * 256;
+                         4 * sizeof(int32_t) * (size_t)cap + 32 * 256;
     hipError_t e = hipMalloc(&rb->block, total);
     if (e != hipSuccess) {
         delete rb;
@@ -388,6 +464,10 @@ hipError_t ensure_buffers(ugp_ctx ctx, int64_t cap, int max_vertices) {
     rb->L = (float4 *)take(q);
     rb->ovf = (int32_t *)take(sizeof(int32_t) * (size_t)cap);
     rb->hits = (int2 *)take(sizeof(int2) * (size_t)cap);
+    rb->skey = (uint32_t *)take(sizeof(uint32_t) * (size_t)cap);
+    rb->skey2 = (uint32_t *)take(sizeof(uint32_t) * (size_t)cap);
+    rb->sval = (int32_t *)take(sizeof(int32_t) * (size_t)cap);
+    rb->sval2 = (int32_t *)take(sizeof(int32_t) * (size_t)cap);
     rb->counts = (int32_t *)take(counts);
     rb->cap = cap;
     rb->max_vertices = max_vertices;
@@ -429,6 +509,11 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
     P.cam = CamDev{cam->origin[0], cam->origin[1], cam->origin[2], (float)f[0], (float)f[1], (float)f[2],
                    (float)(rt[0] * th * asp), (float)(rt[1] * th * asp), (float)(rt[2] * th * asp),
                    (float)(u[0] * th), (float)(u[1] * th), (float)(u[2] * th), cam->width, cam->height};
+    for (int k = 0; k < 3; ++k) {
+        P.blo[k] = S0.lo[k];
+        const float ext = S0.hi[k] - S0.lo[k];
+        P.binv[k] = ext > 0.f ? 1.f / ext : 0.f;
+    }
     P.seed = p->seed;
     P.max_depth = p->max_depth;
     P.mis_mode = p->mis_mode;
@@ -472,36 +557,53 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
     const unsigned gw = 256;  // the overflow pass: few paths
     for (int s = 0; s < p->spp; ++s) {
         P.sample = (uint32_t)(p->sample_offset + s);
-        e = hipMemsetAsync(rb->counts, 0, sizeof(int32_t) * 4 * (size_t)(nv + 2), st);
+        e = hipMemsetAsync(rb->counts, 0, sizeof(int32_t) * kCountStride * (size_t)(nv + 2), st);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, st, rb->counts, (int32_t)npix);
         hipLaunchKernelGGL(k_raygen, dim3(gpix), dim3(256), 0, st, P, npix, rb->q[0], rb->L);
         for (int v = 1; v <= nv; ++v) {
-            // counts of vertex v: [paths in, light samples, environment samples,
-            // overflow]; the next vertex's paths-in is c + 4
-            int32_t *c = rb->counts + 4 * (v - 1);
+            // counters of vertex v (see kCountStride); the next vertex's paths-in is c + kCountStride
+            int32_t *c = rb->counts + kCountStride * (v - 1);
             Queue qin = rb->q[(v - 1) & 1], qout = rb->q[v & 1];
             Overflow ov{rb->ovf, c + 3};
+            // order the queue so each wave's rays are coherent
+            timed(5, [&] {
+                hipLaunchKernelGGL(k_sort_keys, dim3(gpix), dim3(256), 0, st, P, qin, (const int32_t *)c, npix,
+                                   rb->skey, rb->sval);
+                radix_sort(rb->skey, rb->sval, rb->skey2, rb->sval2, npix, st);
+            });
             timed(0, [&] {
                 hipLaunchKernelGGL((k_collide<kEventsMain, false>), dim3(gq), dim3(kBlock), 0, st, Sc[0], P, v, qin,
-                                   (const int32_t *)c, rb->hits, ctx->stats, ov, ctx->err);
+                                   (const int32_t *)c, (const int32_t *)rb->sval, c + 4, rb->hits, ctx->stats, ov,
+                                   ctx->err);
             });
             timed(1, [&] {
                 hipLaunchKernelGGL((k_collide<kEventsWide, true>), dim3(gw), dim3(kBlock), 0, st, Sc[1], P, v, qin,
-                                   (const int32_t *)c, rb->hits, ctx->stats, ov, ctx->err);
+                                   (const int32_t *)c, (const int32_t *)rb->sval, c + 4, rb->hits, ctx->stats, ov,
+                                   ctx->err);
             });
             timed(4, [&] {
                 hipLaunchKernelGGL(k_shade, dim3(gq), dim3(kBlock), 0, st, S, P, v, qin, (const int32_t *)c,
-                                   (const int2 *)rb->hits, qout, c + 4, rb->nee, c + 1, rb->env, c + 2, rb->L);
+                                   (const int2 *)rb->hits, qout, c + kCountStride, rb->nee, c + 1, rb->env, c + 2,
+                                   rb->L);
             });
             if (v <= p->max_depth) {
                 if (S.n_emit > 0 && p->mis_mode != 1) {
+                    // light queue sorted like the path queue (its records share the layout)
+                    timed(5, [&] {
+                        const Queue lq{rb->nee.a, rb->nee.b, rb->nee.c};
+                        hipLaunchKernelGGL(k_sort_keys, dim3(gpix), dim3(256), 0, st, P, lq, (const int32_t *)(c + 1),
+                                           npix, rb->skey, rb->sval);
+                        radix_sort(rb->skey, rb->sval, rb->skey2, rb->sval2, npix, st);
+                    });
                     timed(2, [&] {
                         hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, st, c + 3, 0);
                         hipLaunchKernelGGL((k_light<kEventsMain, false>), dim3(gq), dim3(kBlock), 0, st, Sc[2], rb->nee,
-                                           (const int32_t *)(c + 1), rb->L, ctx->stats, ov, ctx->err);
+                                           (const int32_t *)(c + 1), (const int32_t *)rb->sval, c + 5, rb->L,
+                                           ctx->stats, ov, ctx->err);
                         hipLaunchKernelGGL((k_light<kEventsWide, true>), dim3(gw), dim3(kBlock), 0, st, Sc[2], rb->nee,
-                                           (const int32_t *)(c + 1), rb->L, ctx->stats, ov, ctx->err);
+                                           (const int32_t *)(c + 1), (const int32_t *)rb->sval, c + 5, rb->L,
+                                           ctx->stats, ov, ctx->err);
                     });
                 }
                 if (P.has_env && p->mis_mode != 1)

@@ -100,20 +100,47 @@ __device__ __forceinline__ float erf_diff(float ta, float tb) {
 }
 
 // 64-byte primitive record: (mu.xyz, d), (M00 M01 M02 M10), (M11 M12 M20 M21),
-// (M22, original index bits, -, -) with M = S^-1 R^T in float
+// (M22, original index bits, 1/min(s), -) with M = S^-1 R^T in float
 struct HotRec {
     float mx, my, mz, d;
     float m[9];
     int orig;
+    float mnorm;  // largest row norm of M
 };
 
 __device__ __forceinline__ HotRec load_hot(const float4 *hot, int i) {
     const float4 a = hot[4 * i], b = hot[4 * i + 1], c = hot[4 * i + 2], e = hot[4 * i + 3];
-    return HotRec{a.x, a.y, a.z, a.w, {b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w, e.x}, __float_as_int(e.y)};
+    return HotRec{a.x, a.y, a.z, a.w, {b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w, e.x}, __float_as_int(e.y), e.z};
+}
+
+// Cheap float test that the ray surely misses the cut-off ellipsoid: the
+// distance of closest approach in the unit frame is computed in float and
+// compared with r plus a bound on its rounding error (offsets in float carry
+// ~1e-6 of |o - mu|, magnified at most mnorm-fold by M).  Only candidates
+// that survive take the FP64 path of chord().
+__device__ __forceinline__ bool surely_missed(const HotRec &h, const RayD &r, float r2) {
+    const float *M = h.m;
+    const float ex = r.ox - h.mx, ey = r.oy - h.my, ez = r.oz - h.mz;
+    const float te = -(ex * r.dx + ey * r.dy + ez * r.dz);
+    const float px = fmaf(te, r.dx, ex), py = fmaf(te, r.dy, ey), pz = fmaf(te, r.dz, ez);
+    const float w0 = M[0] * r.dx + M[1] * r.dy + M[2] * r.dz;
+    const float w1 = M[3] * r.dx + M[4] * r.dy + M[5] * r.dz;
+    const float w2 = M[6] * r.dx + M[7] * r.dy + M[8] * r.dz;
+    const float q0 = M[0] * px + M[1] * py + M[2] * pz;
+    const float q1 = M[3] * px + M[4] * py + M[5] * pz;
+    const float q2 = M[6] * px + M[7] * py + M[8] * pz;
+    const float A = w0 * w0 + w1 * w1 + w2 * w2;
+    const float dt = -(q0 * w0 + q1 * w1 + q2 * w2) / A;
+    const float u0 = fmaf(dt, w0, q0), u1 = fmaf(dt, w1, q1), u2 = fmaf(dt, w2, q2);
+    const float rho = sqrtf(u0 * u0 + u1 * u1 + u2 * u2);
+    const float err = 2e-6f * h.mnorm * (fabsf(ex) + fabsf(ey) + fabsf(ez)) +
+                      2e-5f * (1.f + fabsf(q0) + fabsf(q1) + fabsf(q2));
+    return rho > sqrtf(r2) + err;
 }
 
 // Returns false if the clipped chord is empty.
 __device__ inline bool chord(const HotRec &h, const RayD &r, float r2, Chord &c) {
+    if (surely_missed(h, r, r2)) return false;
     const float *M = h.m;
     // reference point on the ray near mu: p_e = (o - mu) + t_e w, FP64
     const double dx = r.dx, dy = r.dy, dz = r.dz;

@@ -10,7 +10,7 @@ namespace ugp {
 
 // Device-side scene, all arrays in leaf (Morton) order of the hierarchy.
 //   hot   [n][4] float4: (mu.xyz, density), (M00 M01 M02 M10), (M11 M12 M20 M21),
-//                        (M22, orig id bits, -, -) with M = S^-1 R^T rounded to float
+//                        (M22, orig id bits, 1/min(s), -) with M = S^-1 R^T rounded to float
 //   cold  [n][3] float4: (facet normal.xyz, material), (albedo.rgb, roughness),
 //                        (emission.rgb, bounding-sphere radius)
 //   nodes [n_nodes4][8] float4: 4-wide nodes holding the boxes of up to four
@@ -68,7 +68,8 @@ struct ugp_ctx_s {
     int64_t *stats = nullptr;       // device counters of the last render: [collision, light, env]
     unsigned long long *counters = nullptr;  // [3] traversal counters (profiling level 2)
     int profiling = 0;
-    // event pairs of the last render, by category: 0 collide main, 1 collide wide, 2 light, 3 env, 4 shade
+    // event pairs of the last render, by category: 0 collide main, 1 collide wide, 2 light, 3 env,
+    // 4 shade, 5 ray sort
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<int, int>> ev_used;  // (category, index of the start event)
     bool ev_cat_valid = false;
@@ -78,6 +79,11 @@ namespace ugp {
 
 // build.hip
 hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps);
+// device-wide exclusive scan of int32, and a stable LSD radix sort of
+// (uint32 key, int32 value) pairs (4 passes of 8 bits; result in keys / vals,
+// tk / tv are scratch of the same size)
+hipError_t exclusive_scan(const int *in, int *out, int64_t n, hipStream_t st);
+hipError_t radix_sort(uint32_t *keys, int32_t *vals, uint32_t *tk, int32_t *tv, int64_t n, hipStream_t st);
 void free_scene(SceneDev &sc);
 
 // trace.hip
