@@ -78,6 +78,13 @@ def lib():
         L.orc_path_radiance.argtypes = [vp, C.POINTER(_Camera), C.POINTER(_Params), C.c_uint32,
                                         C.c_uint32, vp]
         L.orc_philox4x32_10.argtypes = [vp, vp, vp]
+        L.orc_nrc_num_params.restype = C.c_int
+        L.orc_nrc_encode.argtypes = [C.c_int64, vp, vp, vp, vp]
+        L.orc_nrc_forward.argtypes = [C.c_int64, vp, vp, vp]
+        L.orc_nrc_loss_grad.argtypes = [C.c_int64, vp, vp, vp, vp]
+        L.orc_nrc_loss_grad.restype = C.c_double
+        L.orc_nrc_adam.argtypes = [C.c_int64, vp, vp, vp, vp, C.c_int, C.c_double, C.c_double, C.c_double,
+                                   C.c_double]
         L.orc_philox4x64_10.argtypes = [vp, vp, vp]
         _lib = L
     return _lib
@@ -288,3 +295,48 @@ def phase_sample(mat, albedo, rough, normal, wo, u1, u2):
     lib().orc_phase_sample(int(mat), _addr(a), float(rough), _addr(n), _addr(o), float(u1),
                            float(u2), _addr(wi), _addr(w), _addr(pdf))
     return wi, w, float(pdf[0])
+
+
+# ---------------------------------------------------------------------------
+# neural radiance cache reference (double precision)
+# ---------------------------------------------------------------------------
+NRC_LAYERS = [(64, 96), (64, 64), (64, 64), (64, 64), (3, 64)]  # (n_out, n_in)
+
+
+def nrc_num_params() -> int:
+    return lib().orc_nrc_num_params()
+
+
+def nrc_encode(inputs, lo, hi) -> np.ndarray:
+    """inputs float32 [n,16] = pos, wo, normal, roughness, albedo, pad -> [n,96]"""
+    x = np.ascontiguousarray(inputs, dtype=np.float32)
+    n = x.shape[0]
+    f = np.zeros((n, 96))
+    lo_ = np.ascontiguousarray(lo, dtype=np.float64)
+    hi_ = np.ascontiguousarray(hi, dtype=np.float64)
+    lib().orc_nrc_encode(n, _addr(x), _addr(lo_), _addr(hi_), _addr(f))
+    return f
+
+
+def nrc_forward(W, feat) -> np.ndarray:
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    f = np.ascontiguousarray(feat, dtype=np.float64)
+    y = np.zeros((f.shape[0], 3))
+    lib().orc_nrc_forward(f.shape[0], _addr(W), _addr(f), _addr(y))
+    return y
+
+
+def nrc_loss_grad(W, feat, target):
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    f = np.ascontiguousarray(feat, dtype=np.float64)
+    t = np.ascontiguousarray(target, dtype=np.float64)
+    g = np.zeros(W.shape[0])
+    loss = lib().orc_nrc_loss_grad(f.shape[0], _addr(W), _addr(f), _addr(t), _addr(g))
+    return loss, g
+
+
+def nrc_adam(W, m, v, g, t, lr=1e-3, b1=0.9, b2=0.99, eps=1e-8):
+    W = np.array(W, dtype=np.float64); m = np.array(m, dtype=np.float64); v = np.array(v, dtype=np.float64)
+    gg = np.ascontiguousarray(g, dtype=np.float64)
+    lib().orc_nrc_adam(W.shape[0], _addr(W), _addr(m), _addr(v), _addr(gg), int(t), lr, b1, b2, eps)
+    return W, m, v

@@ -1016,3 +1016,133 @@ void orc_path_radiance(const orc_scene *S, const orc_camera *cam, const orc_rend
     free(H.v);
     free(H2.v);
 }
+
+/* ------------------------------------------------------------------------- */
+/* Neural radiance cache (the learned radiance cache that terminates paths):  */
+/* input encoding, MLP 96 -> 64 -> 64 -> 64 -> 64 -> 3 with ReLU and no       */
+/* biases, relative-L2 loss and Adam, all in double precision.  Weights are   */
+/* stored per layer as [n_out][n_in], layers back to back.                    */
+/* ------------------------------------------------------------------------- */
+#define NRC_IN 96
+#define NRC_H 64
+#define NRC_OUT 3
+#define NRC_NPARAM (NRC_H * NRC_IN + 3 * NRC_H * NRC_H + NRC_OUT * NRC_H)
+
+int orc_nrc_num_params(void) { return NRC_NPARAM; }
+
+/* Encoding: position normalised to the scene box, x_hat in [0,1]^3, as
+ * sin / cos(2^j pi x_hat) for j = 0..11 per axis (72); the outgoing direction
+ * as real spherical harmonics of bands 0..3 (16); the facet normal (3),
+ * roughness (1) and albedo (3); one zero pad.  in[16] = pos, wo, normal,
+ * roughness, albedo, unused. */
+void orc_nrc_encode(int64_t n, const float *in, const double lo[3], const double hi[3], double *feat) {
+    for (int64_t r = 0; r < n; ++r) {
+        const float *p = in + 16 * r;
+        double *f = feat + NRC_IN * r;
+        int o = 0;
+        for (int a = 0; a < 3; ++a) {
+            double xh = ((double)p[a] - lo[a]) / (hi[a] - lo[a]);
+            for (int j = 0; j < 12; ++j) {
+                double arg = ldexp(M_PI * xh, j);
+                f[o++] = sin(arg);
+                f[o++] = cos(arg);
+            }
+        }
+        double x = p[3], y = p[4], z = p[5];
+        double x2 = x * x, y2 = y * y, z2 = z * z;
+        f[o++] = 0.28209479177387814;
+        f[o++] = -0.48860251190291987 * y;
+        f[o++] = 0.48860251190291987 * z;
+        f[o++] = -0.48860251190291987 * x;
+        f[o++] = 1.0925484305920792 * x * y;
+        f[o++] = -1.0925484305920792 * y * z;
+        f[o++] = 0.31539156525252005 * (3.0 * z2 - 1.0);
+        f[o++] = -1.0925484305920792 * x * z;
+        f[o++] = 0.5462742152960396 * (x2 - y2);
+        f[o++] = -0.5900435899266435 * y * (3.0 * x2 - y2);
+        f[o++] = 2.890611442640554 * x * y * z;
+        f[o++] = -0.4570457994644658 * y * (5.0 * z2 - 1.0);
+        f[o++] = 0.3731763325901154 * z * (5.0 * z2 - 3.0);
+        f[o++] = -0.4570457994644658 * x * (5.0 * z2 - 1.0);
+        f[o++] = 1.445305721320277 * z * (x2 - y2);
+        f[o++] = -0.5900435899266435 * x * (x2 - 3.0 * y2);
+        for (int k = 6; k < 13; ++k) f[o++] = p[k];
+        f[o++] = 0.0;
+    }
+}
+
+static const int nrc_nin[5] = {NRC_IN, NRC_H, NRC_H, NRC_H, NRC_H};
+static const int nrc_nout[5] = {NRC_H, NRC_H, NRC_H, NRC_H, NRC_OUT};
+
+static int nrc_offset(int l) {
+    int o = 0;
+    for (int k = 0; k < l; ++k) o += nrc_nin[k] * nrc_nout[k];
+    return o;
+}
+
+/* forward: act[l] holds the input of layer l (act[0] = features); out = y */
+static void nrc_forward_one(const double *W, const double *x, double act[5][NRC_IN], double y[3]) {
+    for (int i = 0; i < NRC_IN; ++i) act[0][i] = x[i];
+    for (int l = 0; l < 5; ++l) {
+        const double *w = W + nrc_offset(l);
+        for (int o = 0; o < nrc_nout[l]; ++o) {
+            double s = 0.0;
+            for (int i = 0; i < nrc_nin[l]; ++i) s += w[o * nrc_nin[l] + i] * act[l][i];
+            if (l < 4) act[l + 1][o] = s > 0.0 ? s : 0.0;
+            else y[o] = s;
+        }
+    }
+}
+
+void orc_nrc_forward(int64_t n, const double *W, const double *feat, double *y) {
+    double act[5][NRC_IN];
+    for (int64_t r = 0; r < n; ++r) nrc_forward_one(W, feat + NRC_IN * r, act, y + 3 * r);
+}
+
+/* Relative L2 loss mean over records and channels of (y - t)^2 / (sg(y)^2 +
+ * 0.01), its gradient with respect to W (back-propagation through the ReLU
+ * network, y in the denominator held constant). */
+double orc_nrc_loss_grad(int64_t n, const double *W, const double *feat, const double *target,
+                         double *grad) {
+    double act[5][NRC_IN], y[3], d[5][NRC_IN];
+    memset(grad, 0, sizeof(double) * NRC_NPARAM);
+    double loss = 0.0;
+    const double scale = 1.0 / (3.0 * (double)n);
+    for (int64_t r = 0; r < n; ++r) {
+        nrc_forward_one(W, feat + NRC_IN * r, act, y);
+        double dy[3];
+        for (int c = 0; c < 3; ++c) {
+            double den = y[c] * y[c] + 0.01;
+            double e = y[c] - target[3 * r + c];
+            loss += e * e / den * scale;
+            dy[c] = 2.0 * e / den * scale;
+        }
+        /* output layer */
+        for (int c = 0; c < 3; ++c) d[4][c] = dy[c];
+        for (int l = 4; l >= 0; --l) {
+            const double *w = W + nrc_offset(l);
+            double *g = grad + nrc_offset(l);
+            for (int o = 0; o < nrc_nout[l]; ++o)
+                for (int i = 0; i < nrc_nin[l]; ++i) g[o * nrc_nin[l] + i] += d[l][o] * act[l][i];
+            if (l == 0) break;
+            /* delta of the layer input, through the ReLU that produced it */
+            for (int i = 0; i < nrc_nin[l]; ++i) {
+                double s = 0.0;
+                for (int o = 0; o < nrc_nout[l]; ++o) s += w[o * nrc_nin[l] + i] * d[l][o];
+                d[l - 1][i] = act[l][i] > 0.0 ? s : 0.0;
+            }
+        }
+    }
+    return loss;
+}
+
+/* one Adam step (Kingma and Ba, 2015) with bias correction, step t >= 1 */
+void orc_nrc_adam(int64_t np, double *W, double *m, double *v, const double *g, int t, double lr, double b1,
+                  double b2, double eps) {
+    double c1 = 1.0 - pow(b1, t), c2 = 1.0 - pow(b2, t);
+    for (int64_t i = 0; i < np; ++i) {
+        m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+        v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+        W[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+    }
+}

@@ -68,6 +68,14 @@ int64_t orc_render(const orc_scene *S, const orc_camera *cam, const orc_render_p
 void orc_path_radiance(const orc_scene *S, const orc_camera *cam, const orc_render_params *p,
                        uint32_t pix, uint32_t sample, double L[3]);
 
+/* neural radiance cache (double precision reference) */
+int orc_nrc_num_params(void);
+void orc_nrc_encode(int64_t n, const float *in, const double lo[3], const double hi[3], double *feat);
+void orc_nrc_forward(int64_t n, const double *W, const double *feat, double *y);
+double orc_nrc_loss_grad(int64_t n, const double *W, const double *feat, const double *target, double *grad);
+void orc_nrc_adam(int64_t np, double *W, double *m, double *v, const double *g, int t, double lr, double b1,
+                  double b2, double eps);
+
 #ifdef __cplusplus
 }
 #endif
