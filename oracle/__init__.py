@@ -41,7 +41,8 @@ class _Camera(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("spp", C.c_int32), ("max_depth", C.c_int32), ("seed", C.c_uint64),
                 ("sample_offset", C.c_int64), ("env_radiance", C.c_double * 3),
-                ("mis_mode", C.c_int32)]
+                ("mis_mode", C.c_int32), ("nrc_mode", C.c_int32), ("nrc_terminate_after", C.c_int32),
+                ("nrc_train_frac", C.c_double), ("nrc_weights", C.c_void_p), ("nrc_box", C.c_double * 6)]
 
 
 def _p(a, ct):
@@ -77,6 +78,9 @@ def lib():
         L.orc_render.restype = C.c_int64
         L.orc_path_radiance.argtypes = [vp, C.POINTER(_Camera), C.POINTER(_Params), C.c_uint32,
                                         C.c_uint32, vp]
+        L.orc_path_records.argtypes = [vp, C.POINTER(_Camera), C.POINTER(_Params), C.c_uint32, C.c_uint32,
+                                       vp, C.c_int, vp]
+        L.orc_path_records.restype = C.c_int
         L.orc_philox4x32_10.argtypes = [vp, vp, vp]
         L.orc_nrc_num_params.restype = C.c_int
         L.orc_nrc_encode.argtypes = [C.c_int64, vp, vp, vp, vp]
@@ -249,6 +253,16 @@ class Scene:
         lib().orc_path_radiance(self.h, C.byref(c), C.byref(p), int(pixel), int(sample), _addr(L))
         return L
 
+    def path_records(self, cam: dict, params: dict, pixel: int, sample: int, max_rec: int = 64):
+        """(radiance [3], records [n, 24]) of one path; records as in orc_path_records"""
+        c = make_camera(cam)
+        p = make_params(params)
+        L = np.zeros(3)
+        rec = np.zeros((max_rec, 24))
+        n = lib().orc_path_records(self.h, C.byref(c), C.byref(p), int(pixel), int(sample), _addr(rec),
+                                   int(max_rec), _addr(L))
+        return L, rec[:min(n, max_rec)]
+
 
 def make_camera(cam: dict) -> _Camera:
     c = _Camera()
@@ -272,6 +286,19 @@ def make_params(p: dict) -> _Params:
     for i in range(3):
         q.env_radiance[i] = float(env[i])
     q.mis_mode = int(p.get("mis_mode", 0))
+    q.nrc_mode = int(p.get("nrc_mode", 0))
+    q.nrc_terminate_after = int(p.get("nrc_terminate_after", 2))
+    q.nrc_train_frac = float(p.get("nrc_train_frac", 0.0))
+    if q.nrc_mode in (1, 2):
+        W = np.ascontiguousarray(p["nrc_weights"], dtype=np.float64)
+        assert W.shape == (nrc_num_params(),)
+        q._keep = W  # the array must outlive the call
+        q.nrc_weights = W.ctypes.data
+    box = p.get("nrc_box", None)
+    if q.nrc_mode != 0:
+        assert box is not None, "nrc_box (lo[3], hi[3]) is required with a cache mode"
+        for i in range(6):
+            q.nrc_box[i] = float(box[i])
     return q
 
 

@@ -803,6 +803,10 @@ void orc_phase_sample(int mat, const double alb[3], double rough, const double n
 /* and the balance heuristic between light and phase sampling.                */
 /* ------------------------------------------------------------------------- */
 
+/* the radiance cache's network (defined with the cache below) */
+void orc_nrc_encode(int64_t n, const float *in, const double lo[3], const double hi[3], double *feat);
+static void nrc_predict(const double *W, const float in[16], const double box[6], double y[3]);
+
 /* NEE cone pdf of emitter k seen from x: uniform over the cone subtending k's
  * bounding sphere, times the uniform emitter-choice probability; 0 when x is
  * inside the sphere. */
@@ -854,7 +858,7 @@ static void camera_ray(const orc_camera *cam, int64_t px, int64_t py, double jx,
  * sampling). */
 static void trace_path(const orc_scene *S, const orc_render_params *P, const orc_camera *cam,
                        uint32_t pix, uint32_t sample, hitvec *H, hitvec *H2, double L[3],
-                       int64_t *rays) {
+                       int64_t *rays, double *rec, int max_rec, int *n_rec) {
     const uint64_t seed = P->seed;
     double u[4], g[4];
     rng4(seed, pix, sample, 0, 0, u);
@@ -866,6 +870,15 @@ static void trace_path(const orc_scene *S, const orc_render_params *P, const orc
     double p_prev = 0.0, x_prev[3] = {0, 0, 0};
     const int env = (P->env_radiance[0] > 0.0 || P->env_radiance[1] > 0.0 || P->env_radiance[2] > 0.0);
     const double p_env = 1.0 / (4.0 * M_PI);
+    /* radiance cache: a training path runs to max_depth and records its
+     * vertices; any other path ends at collision nrc_terminate_after + 1 */
+    int train = 0;
+    if (P->nrc_mode == 1) {
+        double t4[4];
+        rng4(seed, pix, sample, 0, 2, t4);
+        train = t4[0] < P->nrc_train_frac;
+    }
+    if (n_rec) *n_rec = 0;
     for (uint32_t v = 1;; ++v) {
         rng4(seed, pix, sample, v, 0, u);
         rng4(seed, pix, sample, v, 1, g);
@@ -903,6 +916,33 @@ static void trace_path(const orc_scene *S, const orc_render_params *P, const orc
         const double *nrm = S->nrm + 3 * k, *alb = S->alb + 3 * k;
         int mat = S->mat[k];
         double rough = S->rough[k];
+        if (P->nrc_mode != 0) {
+            /* cache inputs at this vertex: position, outgoing direction, facet
+             * normal turned toward it, roughness, albedo */
+            double nf[3] = {nrm[0], nrm[1], nrm[2]};
+            if (dot3(nf, wo) < 0.0) for (int i = 0; i < 3; ++i) nf[i] = -nf[i];
+            float in[16] = {(float)x[0], (float)x[1], (float)x[2], (float)wo[0], (float)wo[1], (float)wo[2],
+                            (float)nf[0], (float)nf[1], (float)nf[2], (float)rough, (float)alb[0],
+                            (float)alb[1], (float)alb[2], 0.f, 0.f, 0.f};
+            if (!train && (int)v == P->nrc_terminate_after + 1) {
+                if (P->nrc_mode == 1 || P->nrc_mode == 2) {
+                    double y[3];
+                    nrc_predict(P->nrc_weights, in, P->nrc_box, y);
+                    for (int i = 0; i < 3; ++i) L[i] += beta[i] * fmax(0.0, y[i]);
+                }
+                break;
+            }
+            if (train && n_rec) {
+                if (*n_rec < max_rec) {
+                    double *r = rec + 24 * (*n_rec);
+                    for (int i = 0; i < 16; ++i) r[i] = in[i];
+                    for (int i = 0; i < 3; ++i) { r[16 + i] = beta[i]; r[20 + i] = L[i]; }
+                    r[19] = (double)pix;
+                    r[23] = (double)v;
+                }
+                ++*n_rec;
+            }
+        }
         /* NEE to one emissive primitive */
         if (S->n_emit > 0 && P->mis_mode != 1) {
             int64_t j = (int64_t)(u[1] * (double)S->n_emit);
@@ -975,7 +1015,7 @@ static void *render_worker(void *arg) {
         for (int32_t sp = 0; sp < J->p.spp; ++sp) {
             double L[3];
             uint32_t sample = (uint32_t)(J->p.sample_offset + sp);
-            trace_path(J->S, &J->p, &J->cam, (uint32_t)pix, sample, &H, &H2, L, &J->rays);
+            trace_path(J->S, &J->p, &J->cam, (uint32_t)pix, sample, &H, &H2, L, &J->rays, NULL, 0, NULL);
             for (int c = 0; c < 3; ++c) { s[c] += L[c]; s2[c] += L[c] * L[c]; }
         }
         for (int c = 0; c < 3; ++c) {
@@ -1012,9 +1052,20 @@ void orc_path_radiance(const orc_scene *S, const orc_camera *cam, const orc_rend
                        uint32_t pix, uint32_t sample, double L[3]) {
     hitvec H = {0}, H2 = {0};
     int64_t rays = 0;
-    trace_path(S, p, cam, pix, sample, &H, &H2, L, &rays);
+    trace_path(S, p, cam, pix, sample, &H, &H2, L, &rays, NULL, 0, NULL);
     free(H.v);
     free(H2.v);
+}
+
+int orc_path_records(const orc_scene *S, const orc_camera *cam, const orc_render_params *p, uint32_t pix,
+                     uint32_t sample, double *rec, int max_rec, double L[3]) {
+    hitvec H = {0}, H2 = {0};
+    int64_t rays = 0;
+    int n = 0;
+    trace_path(S, p, cam, pix, sample, &H, &H2, L, &rays, rec, max_rec, &n);
+    free(H.v);
+    free(H2.v);
+    return n;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -1102,6 +1153,13 @@ void orc_nrc_forward(int64_t n, const double *W, const double *feat, double *y) 
 /* Relative L2 loss mean over records and channels of (y - t)^2 / (sg(y)^2 +
  * 0.01), its gradient with respect to W (back-propagation through the ReLU
  * network, y in the denominator held constant). */
+/* cache prediction for one vertex: encode, then the network */
+static void nrc_predict(const double *W, const float in[16], const double box[6], double y[3]) {
+    double feat[NRC_IN], act[5][NRC_IN];
+    orc_nrc_encode(1, in, box, box + 3, feat);
+    nrc_forward_one(W, feat, act, y);
+}
+
 double orc_nrc_loss_grad(int64_t n, const double *W, const double *feat, const double *target,
                          double *grad) {
     double act[5][NRC_IN], y[3], d[5][NRC_IN];

@@ -28,6 +28,15 @@ typedef struct {
     int64_t sample_offset;
     double env_radiance[3];
     int32_t mis_mode; /* 0 balance heuristic, 1 phase sampling only, 2 light sampling only */
+    /* radiance cache: mode 0 off; 1 training paths (chosen with probability
+     * nrc_train_frac) run to max_depth, the others end in the cache; 2 every
+     * path ends in the cache; 3 paths end after nrc_terminate_after scattering
+     * events with nothing added.  nrc_weights: double [orc_nrc_num_params()];
+     * nrc_box: lo[3], hi[3] of the position encoding. */
+    int32_t nrc_mode, nrc_terminate_after;
+    double nrc_train_frac;
+    const double *nrc_weights;
+    double nrc_box[6];
 } orc_render_params;
 
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -67,6 +76,13 @@ int64_t orc_render(const orc_scene *S, const orc_camera *cam, const orc_render_p
                    int64_t n_pix, const int64_t *pixels, int nthreads, double *sum, double *sumsq);
 void orc_path_radiance(const orc_scene *S, const orc_camera *cam, const orc_render_params *p,
                        uint32_t pix, uint32_t sample, double L[3]);
+/* radiance of one path and its cache-training records: per scattering vertex
+ * of a training path, 24 doubles = network inputs (position, outgoing
+ * direction, facet normal, roughness, albedo, 3 zeros), throughput, pixel,
+ * path radiance before the vertex's scattered light, vertex index.  Returns
+ * the number of records (at most max_rec are written). */
+int orc_path_records(const orc_scene *S, const orc_camera *cam, const orc_render_params *p, uint32_t pix,
+                     uint32_t sample, double *rec, int max_rec, double L[3]);
 
 /* neural radiance cache (double precision reference) */
 int orc_nrc_num_params(void);
