@@ -84,10 +84,25 @@ typedef struct {
  *   sample_offset  first sample index, so progressive calls resume exactly
  *   env_radiance   constant environment radiance (0 = black background)
  *   mis_mode       0 balance heuristic, 1 phase sampling only, 2 light sampling only
- *   nrc_mode       0 plain tracer; 1 radiance cache: infer at the termination
- *                  vertex and train on this call's paths; 2 infer only
+ *   nrc_mode       neural radiance cache (the learned cache that ends paths early):
+ *                  0 off (plain tracer);
+ *                  1 infer and train: a path is a training path with probability
+ *                    f (Philox vertex 0, group 2); other paths end at collision
+ *                    nrc_terminate_after + 1 (if <= max_depth) where, after
+ *                    the emission pick-up, throughput x max(0, cache) is
+ *                    added; training paths run to max_depth and record every
+ *                    scattering vertex; after each sample pass the records'
+ *                    targets (path radiance - radiance so far) / throughput
+ *                    drive one Adam step (ugp_nrc_train_step) and f is
+ *                    rescaled toward nrc_train_records records per pass;
+ *                  2 infer only (every path ends in the cache);
+ *                  3 end paths at nrc_terminate_after + 1 and add nothing
  *   nrc_terminate_after  scattering events before a cached path ends (>= 1)
- *   nrc_train_records    training records collected per call (<= 1 << 20)      */
+ *   nrc_train_records    records used per training step, 1 .. 1 << 20 (mode 1);
+ *                  f starts at min(1, nrc_train_records / (2 pixels))
+ *   nrc_lr         Adam learning rate of the cache (0 = 1e-3)
+ *   nrc_box        lo[3], hi[3] of the cache's position encoding; hi <= lo on
+ *                  any axis = the scene bounds                                  */
 typedef struct {
     int32_t spp, max_depth;
     uint64_t seed;
@@ -95,6 +110,8 @@ typedef struct {
     float env_radiance[3];
     int32_t mis_mode;
     int32_t nrc_mode, nrc_terminate_after, nrc_train_records;
+    float nrc_lr;
+    float nrc_box[6];
 } ugp_render_params;
 
 /* Create a context on `device` that enqueues on `hip_stream` (a hipStream_t;
@@ -198,6 +215,11 @@ typedef struct {
     /* the three traversal counters split by kernel: [0] collision, [1] collision
        overflow pass, [2] light samples, [3] environment samples (level 2, else -1) */
     int64_t cat_nodes[4], cat_prims[4], cat_reloads[4];
+    int64_t nrc_queries;     /* paths that ended in the radiance cache */
+    int64_t nrc_records;     /* training records appended (before the per-pass cap) */
+    double ms_nrc_infer;     /* duration of the cache inference launches (level >= 1, else -1) */
+    double ms_nrc_train;     /* ... of the cache training steps */
+    float nrc_loss;          /* loss of the last training step (NaN if none) */
 } ugp_render_stats;
 
 /* Profiling level of later ugp_render calls: 0 off; 1 every kernel launch is
@@ -210,6 +232,56 @@ ugp_status ugp_set_profiling(ugp_ctx ctx, int level);
 ugp_status ugp_get_render_stats(ugp_ctx ctx, ugp_render_stats *out);
 
 const char *ugp_status_string(ugp_status s);
+
+/* ------------------------------------------------------------------------
+ * Neural radiance cache: a network that predicts the radiance scattered from a
+ * path vertex toward the previous vertex, so that paths can end early
+ * (ugp_render_params.nrc_mode).  Not part of the paper's method: it follows
+ * the rendering workload of the cache configuration (a fully fused MLP
+ * 96 -> 64 -> 64 -> 64 -> 64 -> 3, ReLU, no biases).
+ *
+ * Inputs per query: float32 [16] = position[3], outgoing direction[3] (unit),
+ * facet normal[3], roughness, albedo[3], 3 unused.  Encoding (96 features):
+ * for each axis the position normalised to the box, x_hat = (x - lo) / (hi -
+ * lo), as sin(2^j pi x_hat), cos(2^j pi x_hat) for j = 0..11 (72); the real
+ * spherical harmonics of the direction, bands 0..3 (16); normal, roughness,
+ * albedo (7); one zero.  Weights: float32 [ugp_nrc_num_params()] = 18624,
+ * per layer [n_out][n_in], layers in order.  Arithmetic: bf16 weights and
+ * activations on the matrix cores, float32 accumulation, float32 master
+ * weights for Adam.  Loss: mean over records and channels of
+ * (y - t)^2 / (y^2 + 0.01), the denominator held constant.
+ * `box` is [host] lo[3], hi[3], or NULL for the scene bounds (then a scene
+ * must have been built: UGP_ERR_NO_SCENE otherwise).
+ * ------------------------------------------------------------------------ */
+int32_t ugp_nrc_num_params(void);
+/* Set the float32 master weights (device [P]) and reset the Adam moments and
+ * step count.  The first call allocates the cache state. */
+ugp_status ugp_nrc_set_weights(ugp_ctx ctx, const float *weights);
+/* Copy the float32 master weights to weights_out (device [P]).
+ * UGP_ERR_INVALID_ARGUMENT if the cache has no state yet. */
+ugp_status ugp_nrc_get_weights(ugp_ctx ctx, float *weights_out);
+/* Encoded features: inputs float [n][16] -> feat_out float [n][96]. */
+ugp_status ugp_nrc_encode(ugp_ctx ctx, int64_t n, const float *inputs, const float *box,
+                          float *feat_out);
+/* Network prediction y_out float [n][3].  x_kind 0: x = inputs [n][16]
+ * (encoded inside the kernel); 1: x = features [n][96].  Uses the bf16 copy
+ * of the current weights. */
+ugp_status ugp_nrc_forward(ugp_ctx ctx, int64_t n, const float *x, int32_t x_kind, const float *box,
+                           float *y_out);
+/* One optimisation step on n records: forward, loss, back-propagation,
+ * weight gradient (per-slice partials summed in a fixed order), Adam (lr,
+ * beta1 0.9, beta2 0.99, eps 1e-8, bias-corrected) on the master weights, new
+ * bf16 copies.  targets float [n][3]; loss_out float [1] and grad_out float
+ * [P] (device, or NULL) receive this step's loss and gradient.  1 <= n <= 1 << 22. */
+ugp_status ugp_nrc_train_step(ugp_ctx ctx, int64_t n, const float *x, int32_t x_kind, const float *box,
+                              const float *targets, float lr, float *loss_out, float *grad_out);
+/* The training records of the last sample pass of the last ugp_render call
+ * with nrc_mode 1: records_out float [cap][24] (inputs[16], throughput[3],
+ * pixel index as int32 bits, radiance before the vertex's scattered light[3],
+ * vertex index) and targets_out float [cap][3] (or NULL), in no particular
+ * order; *count_out [host] = records written (<= cap).  Synchronises. */
+ugp_status ugp_nrc_records(ugp_ctx ctx, int64_t cap, float *records_out, float *targets_out,
+                           int64_t *count_out);
 
 #ifdef __cplusplus
 }

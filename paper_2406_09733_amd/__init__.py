@@ -44,7 +44,7 @@ class _Params(C.Structure):
     _fields_ = [("spp", C.c_int32), ("max_depth", C.c_int32), ("seed", C.c_uint64),
                 ("sample_offset", C.c_int64), ("env_radiance", C.c_float * 3), ("mis_mode", C.c_int32),
                 ("nrc_mode", C.c_int32), ("nrc_terminate_after", C.c_int32),
-                ("nrc_train_records", C.c_int32)]
+                ("nrc_train_records", C.c_int32), ("nrc_lr", C.c_float), ("nrc_box", C.c_float * 6)]
 
 
 class _Stats(C.Structure):
@@ -55,12 +55,16 @@ class _Stats(C.Structure):
                 ("ms_sort", C.c_double),
                 ("launches_collide", C.c_int32),
                 ("launches_light", C.c_int32), ("launches_env", C.c_int32),
-                ("cat_nodes", C.c_int64 * 4), ("cat_prims", C.c_int64 * 4), ("cat_reloads", C.c_int64 * 4)]
+                ("cat_nodes", C.c_int64 * 4), ("cat_prims", C.c_int64 * 4), ("cat_reloads", C.c_int64 * 4),
+                ("nrc_queries", C.c_int64), ("nrc_records", C.c_int64), ("ms_nrc_infer", C.c_double),
+                ("ms_nrc_train", C.c_double), ("nrc_loss", C.c_float)]
 
 
 EXPORTS = ["ugp_create", "ugp_destroy", "ugp_set_stream", "ugp_build_bvh", "ugp_transmittance",
            "ugp_sample_collision", "ugp_saturation", "ugp_emitter_query", "ugp_render", "ugp_sync",
-           "ugp_set_profiling", "ugp_get_render_stats", "ugp_trace_counts", "ugp_status_string"]
+           "ugp_set_profiling", "ugp_get_render_stats", "ugp_trace_counts", "ugp_status_string",
+           "ugp_nrc_num_params", "ugp_nrc_set_weights", "ugp_nrc_get_weights", "ugp_nrc_encode",
+           "ugp_nrc_forward", "ugp_nrc_train_step", "ugp_nrc_records"]
 
 
 def lib():
@@ -84,6 +88,13 @@ def lib():
         L.ugp_set_profiling.argtypes = [vp, C.c_int]
         L.ugp_trace_counts.argtypes = [vp, C.c_int, i64, vp, vp, vp, vp, vp]
         L.ugp_get_render_stats.argtypes = [vp, C.POINTER(_Stats)]
+        L.ugp_nrc_num_params.argtypes = []
+        L.ugp_nrc_set_weights.argtypes = [vp, vp]
+        L.ugp_nrc_get_weights.argtypes = [vp, vp]
+        L.ugp_nrc_encode.argtypes = [vp, i64, vp, vp, vp]
+        L.ugp_nrc_forward.argtypes = [vp, i64, vp, C.c_int32, vp, vp]
+        L.ugp_nrc_train_step.argtypes = [vp, i64, vp, C.c_int32, vp, vp, C.c_float, vp, vp]
+        L.ugp_nrc_records.argtypes = [vp, i64, vp, vp, C.POINTER(C.c_int64)]
         L.ugp_status_string.argtypes = [C.c_int]
         L.ugp_status_string.restype = C.c_char_p
         for name in EXPORTS:
@@ -247,6 +258,10 @@ class Context:
         p.nrc_mode = int(params.get("nrc_mode", 0))
         p.nrc_terminate_after = int(params.get("nrc_terminate_after", 2))
         p.nrc_train_records = int(params.get("nrc_train_records", 65536))
+        p.nrc_lr = float(params.get("nrc_lr", 0.0))
+        box = params.get("nrc_box", None)
+        for i in range(6):
+            p.nrc_box[i] = 0.0 if box is None else float(box[i])
         _check("ugp_render", lib().ugp_render(self.h, C.byref(c), C.byref(p), _ptr(sum_rgb), _ptr(sumsq_rgb)))
         return sum_rgb, sumsq_rgb
 
@@ -267,3 +282,62 @@ class Context:
             d[name] = list(v) if name.startswith("cat_") else v
         d["rays"] = d["collision_rays"] + d["light_rays"] + d["env_rays"]
         return d
+
+    # ---- neural radiance cache -------------------------------------------
+    def _box(self, box):
+        if box is None:
+            return None
+        b = (C.c_float * 6)(*[float(v) for v in box])
+        return b
+
+    def nrc_set_weights(self, w):
+        """ugp_nrc_set_weights: float32 [P] master weights (resets Adam)."""
+        t = self._dev(w, self.torch.float32, (nrc_num_params(),))
+        _check("ugp_nrc_set_weights", lib().ugp_nrc_set_weights(self.h, _ptr(t)))
+
+    def nrc_get_weights(self):
+        out = self.torch.empty(nrc_num_params(), device=self.device, dtype=self.torch.float32)
+        _check("ugp_nrc_get_weights", lib().ugp_nrc_get_weights(self.h, _ptr(out)))
+        return out
+
+    def nrc_encode(self, inputs, box=None):
+        """ugp_nrc_encode: float32 [n,16] -> [n,96]"""
+        x = self._dev(inputs, self.torch.float32)
+        assert x.ndim == 2 and x.shape[1] == 16
+        out = self.torch.empty((x.shape[0], 96), device=self.device, dtype=self.torch.float32)
+        _check("ugp_nrc_encode", lib().ugp_nrc_encode(self.h, x.shape[0], _ptr(x), self._box(box), _ptr(out)))
+        return out
+
+    def nrc_forward(self, x, box=None):
+        """ugp_nrc_forward: x float32 [n,16] (inputs) or [n,96] (features) -> [n,3]"""
+        t = self._dev(x, self.torch.float32)
+        assert t.ndim == 2 and t.shape[1] in (16, 96)
+        kind = 0 if t.shape[1] == 16 else 1
+        y = self.torch.empty((t.shape[0], 3), device=self.device, dtype=self.torch.float32)
+        _check("ugp_nrc_forward", lib().ugp_nrc_forward(self.h, t.shape[0], _ptr(t), kind, self._box(box), _ptr(y)))
+        return y
+
+    def nrc_train_step(self, x, targets, lr: float = 1e-3, box=None, want_grad: bool = False):
+        """ugp_nrc_train_step -> (loss tensor [1], gradient [P] or None)"""
+        t = self._dev(x, self.torch.float32)
+        assert t.ndim == 2 and t.shape[1] in (16, 96)
+        kind = 0 if t.shape[1] == 16 else 1
+        tg = self._dev(targets, self.torch.float32, (t.shape[0], 3))
+        loss = self.torch.empty(1, device=self.device, dtype=self.torch.float32)
+        g = self.torch.empty(nrc_num_params(), device=self.device, dtype=self.torch.float32) if want_grad else None
+        _check("ugp_nrc_train_step", lib().ugp_nrc_train_step(self.h, t.shape[0], _ptr(t), kind, self._box(box),
+                                                              _ptr(tg), float(lr), _ptr(loss), _ptr(g)))
+        return loss, g
+
+    def nrc_records(self, cap: int):
+        """ugp_nrc_records -> (records [n,24], targets [n,3]) of the last training pass"""
+        rec = self.torch.empty((cap, 24), device=self.device, dtype=self.torch.float32)
+        tgt = self.torch.empty((cap, 3), device=self.device, dtype=self.torch.float32)
+        n = C.c_int64(0)
+        _check("ugp_nrc_records", lib().ugp_nrc_records(self.h, int(cap), _ptr(rec), _ptr(tgt), C.byref(n)))
+        return rec[:n.value], tgt[:n.value]
+
+
+def nrc_num_params() -> int:
+    """ugp_nrc_num_params"""
+    return int(lib().ugp_nrc_num_params())

@@ -82,13 +82,13 @@ ugp_status ugp_create(int device, void *hip_stream, ugp_ctx *out) {
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
     if (hipMalloc((void **)&c->err, sizeof(uint32_t)) != hipSuccess ||
-        hipMalloc((void **)&c->stats, sizeof(int64_t) * 4) != hipSuccess) {
+        hipMalloc((void **)&c->stats, sizeof(int64_t) * 8) != hipSuccess) {
         hipFree(c->err);
         delete c;
         return UGP_ERR_OUT_OF_MEMORY;
     }
     hipMemset(c->err, 0, sizeof(uint32_t));
-    hipMemset(c->stats, 0, sizeof(int64_t) * 4);
+    hipMemset(c->stats, 0, sizeof(int64_t) * 8);
     *out = c;
     return UGP_OK;
 }
@@ -99,6 +99,7 @@ ugp_status ugp_destroy(ugp_ctx ctx) {
     hipStreamSynchronize(ctx->stream);
     ugp::free_scene(ctx->scene);
     ugp::free_render(ctx);
+    ugp::nrc_free(ctx);
     hipFree(ctx->scratch);
     hipFree(ctx->err);
     hipFree(ctx->stats);
@@ -192,7 +193,13 @@ ugp_status ugp_render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_param
         return UGP_ERR_INVALID_ARGUMENT;
     for (int c = 0; c < 3; ++c)
         if (!(p->env_radiance[c] >= 0.f) || !std::isfinite(p->env_radiance[c])) return UGP_ERR_INVALID_ARGUMENT;
-    if (p->nrc_mode != 0) return UGP_ERR_UNSUPPORTED;
+    if (p->nrc_mode < 0 || p->nrc_mode > 3) return UGP_ERR_INVALID_ARGUMENT;
+    if (p->nrc_mode != 0 && p->nrc_terminate_after < 1) return UGP_ERR_INVALID_ARGUMENT;
+    if (p->nrc_mode == 1 && (p->nrc_train_records < 1 || p->nrc_train_records > (1 << 20)))
+        return UGP_ERR_INVALID_ARGUMENT;
+    if (!(p->nrc_lr >= 0.f) || !std::isfinite(p->nrc_lr)) return UGP_ERR_INVALID_ARGUMENT;
+    for (int k = 0; k < 6; ++k)
+        if (!std::isfinite(p->nrc_box[k])) return UGP_ERR_INVALID_ARGUMENT;
     if (ctx->scene.n == 0) return UGP_ERR_NO_SCENE;
     DeviceGuard g(ctx->device);
     return from_hip(ugp::render(ctx, cam, p, sum, sumsq));
@@ -228,7 +235,7 @@ ugp_status ugp_get_render_stats(ugp_ctx ctx, ugp_render_stats *out) {
     if (!ctx || !out) return UGP_ERR_INVALID_ARGUMENT;
     DeviceGuard g(ctx->device);
     hipError_t e = hipStreamSynchronize(ctx->stream);
-    int64_t h[4] = {0, 0, 0, 0};
+    int64_t h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (e == hipSuccess) e = hipMemcpy(h, ctx->stats, sizeof(h), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return from_hip(e);
     std::memset(out, 0, sizeof(*out));
@@ -236,6 +243,13 @@ ugp_status ugp_get_render_stats(ugp_ctx ctx, ugp_render_stats *out) {
     out->collision_rays = h[0];
     out->light_rays = h[1];
     out->env_rays = h[2];
+    out->nrc_queries = h[3];
+    out->nrc_records = h[4];
+    out->nrc_loss = NAN;
+    if (const float *lp = ugp::render_nrc_loss(ctx)) {
+        float l = NAN;
+        if (hipMemcpy(&l, lp, sizeof(float), hipMemcpyDeviceToHost) == hipSuccess) out->nrc_loss = l;
+    }
     out->node_visits = out->prim_tests = out->prim_reloads = -1;
     for (int c = 0; c < 4; ++c) out->cat_nodes[c] = out->cat_prims[c] = out->cat_reloads[c] = -1;
     if (ctx->profiling >= 2 && ctx->counters) {
@@ -253,6 +267,7 @@ ugp_status ugp_get_render_stats(ugp_ctx ctx, ugp_render_stats *out) {
         }
     }
     out->ms_collide = out->ms_collide_wide = out->ms_light = out->ms_env = out->ms_shade = out->ms_sort = -1.0;
+    out->ms_nrc_infer = out->ms_nrc_train = -1.0;
     if (ctx->ev_cat_valid) {
         double ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         int cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -270,11 +285,67 @@ ugp_status ugp_get_render_stats(ugp_ctx ctx, ugp_render_stats *out) {
         out->ms_env = ms[3];
         out->ms_shade = ms[4];
         out->ms_sort = ms[5];
+        out->ms_nrc_infer = ms[6];
+        out->ms_nrc_train = ms[7];
         out->launches_collide = cnt[0];
         out->launches_light = cnt[2];
         out->launches_env = cnt[3];
     }
     return UGP_OK;
+}
+
+int32_t ugp_nrc_num_params(void) { return ugp::nrc_num_params(); }
+
+ugp_status ugp_nrc_set_weights(ugp_ctx ctx, const float *weights) {
+    if (!ctx || !weights) return UGP_ERR_INVALID_ARGUMENT;
+    DeviceGuard g(ctx->device);
+    return from_hip(ugp::nrc_set_weights(ctx, weights));
+}
+
+ugp_status ugp_nrc_get_weights(ugp_ctx ctx, float *weights_out) {
+    if (!ctx || !weights_out || !ugp::nrc_ready(ctx)) return UGP_ERR_INVALID_ARGUMENT;
+    DeviceGuard g(ctx->device);
+    return from_hip(ugp::nrc_get_weights(ctx, weights_out));
+}
+
+ugp_status ugp_nrc_encode(ugp_ctx ctx, int64_t n, const float *inputs, const float *box, float *feat_out) {
+    if (!ctx || n < 0 || n > (int64_t(1) << 28) || (n > 0 && (!inputs || !feat_out))) return UGP_ERR_INVALID_ARGUMENT;
+    if (!box && ctx->scene.n == 0) return UGP_ERR_NO_SCENE;
+    if (n == 0) return UGP_OK;
+    DeviceGuard g(ctx->device);
+    return from_hip(ugp::nrc_encode(ctx, n, inputs, 16, box, feat_out));
+}
+
+ugp_status ugp_nrc_forward(ugp_ctx ctx, int64_t n, const float *x, int32_t x_kind, const float *box,
+                           float *y_out) {
+    if (!ctx || n < 0 || n > (int64_t(1) << 28) || x_kind < 0 || x_kind > 1 || (n > 0 && (!x || !y_out)))
+        return UGP_ERR_INVALID_ARGUMENT;
+    if (x_kind == 0 && !box && ctx->scene.n == 0) return UGP_ERR_NO_SCENE;
+    if (n == 0) return UGP_OK;
+    DeviceGuard g(ctx->device);
+    hipError_t e = ugp::nrc_ensure(ctx);
+    if (e == hipSuccess) e = ugp::nrc_forward(ctx, n, nullptr, x, x_kind == 0 ? 16 : 96, x_kind, box, y_out, nullptr);
+    return from_hip(e);
+}
+
+ugp_status ugp_nrc_train_step(ugp_ctx ctx, int64_t n, const float *x, int32_t x_kind, const float *box,
+                              const float *targets, float lr, float *loss_out, float *grad_out) {
+    if (!ctx || n < 1 || n > (int64_t(1) << 22) || x_kind < 0 || x_kind > 1 || !x || !targets ||
+        !(lr >= 0.f) || !std::isfinite(lr))
+        return UGP_ERR_INVALID_ARGUMENT;
+    if (x_kind == 0 && !box && ctx->scene.n == 0) return UGP_ERR_NO_SCENE;
+    DeviceGuard g(ctx->device);
+    hipError_t e = ugp::nrc_ensure(ctx);
+    if (e == hipSuccess)
+        e = ugp::nrc_train_step(ctx, n, nullptr, x, x_kind == 0 ? 16 : 96, x_kind, box, targets, lr, loss_out,
+                                grad_out);
+    return from_hip(e);
+}
+
+ugp_status ugp_nrc_records(ugp_ctx ctx, int64_t cap, float *records_out, float *targets_out, int64_t *count_out) {
+    if (!ctx || cap < 0 || !count_out || (cap > 0 && !records_out)) return UGP_ERR_INVALID_ARGUMENT;
+    DeviceGuard g(ctx->device);
+    return from_hip(ugp::render_nrc_records(ctx, cap, records_out, targets_out, count_out));
 }
 
 }  // extern "C"

@@ -16,7 +16,16 @@
 // Random numbers: Philox4x32-10 keyed by the seed, counter (pixel, sample,
 // vertex, group): group 0 = (collision, emitter pick, cone u, cone v), group 1 =
 // (phase u, phase v, environment u, environment v); the camera jitter uses
-// vertex 0, group 0.
+// vertex 0, group 0, the choice of radiance-cache training paths vertex 0,
+// group 2.
+//
+// With the radiance cache, a path that is not a training path ends at
+// collision nrc_terminate_after + 1: after its emission pick-up, its
+// throughput times the cache's prediction at that vertex is added.  Training
+// paths run to max_depth and record, at every scattering vertex, the cache
+// inputs, the throughput and the radiance gathered so far; after the pass the
+// record's target is (path radiance - radiance so far) / throughput, and one
+// optimisation step is taken on the pass's records.
 #include <algorithm>
 
 #include "trace_device.hpp"
@@ -26,7 +35,7 @@ namespace ugp {
 struct Queue {        // path (ray) queue, structure of arrays
     float4 *a;        // origin.xyz, pdf of the previous phase sample (0 = camera ray)
     float4 *b;        // direction.xyz, excluded primitive (original index bits)
-    float4 *c;        // throughput.rgb, pixel bits
+    float4 *c;        // throughput.rgb, pixel bits (bit 30: radiance-cache training path)
 };
 struct LightQueue {   // light-sample queue
     float4 *a;        // origin.xyz, target primitive bits
@@ -45,7 +54,12 @@ struct RenderBuffers {
     uint32_t *skey = nullptr, *skey2 = nullptr;  // ray-sort keys (and scratch)
     int32_t *sval = nullptr, *sval2 = nullptr;   // ray-sort permutation (and scratch)
     int32_t *counts = nullptr;  // per vertex: [queue in, nee, env] ...
+    float *qry = nullptr;       // radiance-cache queries (kNrcRecordFloats per path)
     void *block = nullptr;
+    // radiance-cache training state (grown on demand)
+    int64_t rec_cap = 0;
+    float *rec = nullptr, *targets = nullptr, *frac = nullptr, *loss = nullptr;
+    void *nrc_block = nullptr;
 };
 
 namespace {
@@ -54,6 +68,17 @@ constexpr int kPersistBlocks = 4096;
 // per-vertex counters: [0] paths in, [1] light samples, [2] environment
 // samples, [3] overflow, [4] collision work, [5] light work
 constexpr int kCountStride = 8;
+
+struct NrcArgs {
+    int mode;              // 0 off, 1 infer + train, 2 infer, 3 terminate only
+    int term;              // scattering events before a cached path ends
+    float *rec;            // training records [rec_cap][kNrcRecordFloats]
+    int32_t *n_rec;        // records appended (may exceed rec_cap: the excess is dropped)
+    int32_t rec_cap;
+    float *qry;            // cache queries [npix][kNrcRecordFloats]
+    int32_t *n_qry;
+    const float *frac;     // probability of a training path
+};
 
 struct PassArgs {
     CamDev cam;
@@ -64,7 +89,11 @@ struct PassArgs {
     int mis_mode;
     float env[3];
     int has_env;
+    NrcArgs nrc;
 };
+
+constexpr int kPixMask = 0x3fffffff;
+constexpr int kTrainBit = 0x40000000;
 
 __device__ __forceinline__ V3 f3(float4 v) { return v3(v.x, v.y, v.z); }
 
@@ -87,9 +116,11 @@ __global__ void k_raygen(PassArgs P, int64_t npix, Queue q, float4 *L) {
     const Rng4 g = rng4(P.seed, (uint32_t)p, P.sample, 0, 0);
     const int px = (int)(p % P.cam.width), py = (int)(p / P.cam.width);
     const V3 d = camera_dir(P.cam, px, py, g.u[0], g.u[1]);
+    int bits = (int)p;
+    if (P.nrc.mode == 1 && rng4(P.seed, (uint32_t)p, P.sample, 0, 2).u[0] < *P.nrc.frac) bits |= kTrainBit;
     q.a[p] = make_float4(P.cam.ox, P.cam.oy, P.cam.oz, 0.f);
     q.b[p] = make_float4(d.x, d.y, d.z, __int_as_float(-1));
-    q.c[p] = make_float4(1.f, 1.f, 1.f, __int_as_float((int)p));
+    q.c[p] = make_float4(1.f, 1.f, 1.f, __int_as_float(bits));
     L[p] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
@@ -175,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(SceneDev S, PassArgs P, int 
     TraceCount tc;
     auto process = [&](int64_t i) __attribute__((always_inline)) {
         const float4 A = qin.a[i], B = qin.b[i], C = qin.c[i];
-        const int pix = __float_as_int(C.w);
+        const int pix = __float_as_int(C.w) & kPixMask;
         const int excl = __float_as_int(B.w);
         const float u = rng4(P.seed, (uint32_t)pix, P.sample, (uint32_t)v, 0).u[0];
         const RayD r = make_ray(A.x, A.y, A.z, B.x, B.y, B.z, 0.f, __builtin_huge_val());
@@ -217,12 +248,15 @@ __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PassArgs P, int v,
     const int n = *n_in;
     for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += (int64_t)gridDim.x * kBlock) {
         const int64_t i = base + threadIdx.x;
-        bool cont = false, do_nee = false, do_env = false;
+        bool cont = false, do_nee = false, do_env = false, do_qry = false, do_rec = false;
         float4 ca{}, cb{}, cc{}, na{}, nb{}, nc{}, ea{}, eb{}, ec{};
+        float4 r0{}, r1{}, r2{}, r3{}, r4{}, r5{};  // cache query / training record
         if (i < n) {
             const float4 A = qin.a[i], B = qin.b[i], C = qin.c[i];
             const int2 hit = hits[i];
-            const int pix = __float_as_int(C.w);
+            const int pbits = __float_as_int(C.w);
+            const int pix = pbits & kPixMask;
+            const bool train = (pbits & kTrainBit) != 0;
             const float p_prev = A.w;
             const V3 o = f3(A), d = f3(B);
             V3 beta = f3(C);
@@ -253,7 +287,27 @@ __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PassArgs P, int v,
                     }
                     Ladd = w * mul(beta, Le);
                 }
-                if (v <= P.max_depth) {
+                bool stop = false;
+                if (v <= P.max_depth && P.nrc.mode != 0) {
+                    // radiance cache: inputs of this vertex (position, outgoing
+                    // direction, facet normal turned toward it, roughness, albedo)
+                    const V3 wo = -d;
+                    const V3 nf = dot(f3(c0), wo) >= 0.f ? f3(c0) : -f3(c0);
+                    r0 = make_float4(x.x, x.y, x.z, wo.x);
+                    r1 = make_float4(wo.y, wo.z, nf.x, nf.y);
+                    r2 = make_float4(nf.z, c1.w, c1.x, c1.y);
+                    r3 = make_float4(c1.z, 0.f, 0.f, 0.f);
+                    r4 = make_float4(beta.x, beta.y, beta.z, __int_as_float(pix));
+                    if (!train && v == P.nrc.term + 1) {
+                        stop = true;
+                        do_qry = P.nrc.mode != 3;
+                    } else if (train) {
+                        const float4 l = L[pix];
+                        r5 = make_float4(l.x + Ladd.x, l.y + Ladd.y, l.z + Ladd.z, (float)v);
+                        do_rec = true;
+                    }
+                }
+                if (v <= P.max_depth && !stop) {
                     const V3 wo = -d;
                     const Facet F = facet(f3(c0), wo);
                     const V3 wol = to_local(F, wo);
@@ -330,7 +384,7 @@ __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PassArgs P, int v,
                             cont = true;
                             ca = make_float4(x.x, x.y, x.z, pdf);
                             cb = make_float4(wi.x, wi.y, wi.z, __int_as_float(k));
-                            cc = make_float4(beta.x, beta.y, beta.z, __int_as_float(pix));
+                            cc = make_float4(beta.x, beta.y, beta.z, __int_as_float(pbits));
                         }
                     }
                 }
@@ -347,6 +401,18 @@ __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PassArgs P, int v,
         if (do_nee) { nee.a[pn] = na; nee.b[pn] = nb; nee.c[pn] = nc; }
         const int pe = wave_append(do_env, n_env);
         if (do_env) { env.a[pe] = ea; env.b[pe] = eb; env.c[pe] = ec; }
+        if (P.nrc.mode != 0) {
+            const int pq = wave_append(do_qry, P.nrc.n_qry);
+            if (do_qry) {
+                float4 *q = reinterpret_cast<float4 *>(P.nrc.qry + (int64_t)kNrcRecordFloats * pq);
+                q[0] = r0; q[1] = r1; q[2] = r2; q[3] = r3; q[4] = r4;
+            }
+            const int pr = wave_append(do_rec, P.nrc.n_rec);
+            if (do_rec && pr < P.nrc.rec_cap) {
+                float4 *q = reinterpret_cast<float4 *>(P.nrc.rec + (int64_t)kNrcRecordFloats * pr);
+                q[0] = r0; q[1] = r1; q[2] = r2; q[3] = r3; q[4] = r4; q[5] = r5;
+            }
+        }
     }
 }
 
@@ -434,6 +500,12 @@ __global__ void k_accum(int64_t npix, const float4 *L, float *sum, float *sumsq)
 
 __global__ void k_set_count(int32_t *c, int32_t v) { *c = v; }
 
+// running totals of radiance-cache queries ([3]) and training records kept ([4])
+__global__ void k_nrc_stats(const int32_t *cnt, int64_t *stats) {
+    stats[3] += cnt[0];
+    stats[4] += cnt[1];
+}
+
 hipError_t ensure_buffers(ugp_ctx ctx, int64_t cap, int max_vertices) {
     RenderBuffers *rb = ctx->rb;
     if (rb && rb->cap >= cap && rb->max_vertices >= max_vertices) return hipSuccess;
@@ -480,10 +552,48 @@ hipError_t ensure_buffers(ugp_ctx ctx, int64_t cap, int max_vertices) {
 void free_render(ugp_ctx ctx) {
     if (ctx->rb) {
         hipFree(ctx->rb->block);
+        hipFree(ctx->rb->qry);
+        hipFree(ctx->rb->nrc_block);
         delete ctx->rb;
         ctx->rb = nullptr;
     }
 }
+
+namespace {
+
+__global__ void k_set_float(float *p, float v) { *p = v; }
+
+// radiance-cache buffers of a render: queries for every pixel, training
+// records and targets for rec_cap records, the training-path probability
+hipError_t ensure_nrc_buffers(ugp_ctx ctx, int64_t npix, int64_t rec_cap, bool *fresh) {
+    RenderBuffers *rb = ctx->rb;
+    *fresh = false;
+    if (!rb->qry) {
+        hipError_t e = hipMalloc((void **)&rb->qry, sizeof(float) * kNrcRecordFloats * (size_t)rb->cap);
+        if (e != hipSuccess) return e;
+    }
+    if (rb->rec_cap < rec_cap || !rb->nrc_block) {
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) return e;
+        hipFree(rb->nrc_block);
+        rb->nrc_block = nullptr;
+        rb->rec_cap = 0;
+        const int64_t cap = rec_cap < 1024 ? 1024 : rec_cap;
+        const size_t bytes = sizeof(float) * (size_t)cap * (kNrcRecordFloats + 3) + 2 * 256;
+        e = hipMalloc(&rb->nrc_block, bytes);
+        if (e != hipSuccess) return e;
+        rb->rec = (float *)rb->nrc_block;
+        rb->targets = rb->rec + (size_t)cap * kNrcRecordFloats;
+        rb->frac = (float *)((char *)rb->nrc_block + bytes - 2 * 256);
+        rb->loss = rb->frac + 64;
+        rb->rec_cap = cap;
+        *fresh = true;
+    }
+    (void)npix;
+    return hipSuccess;
+}
+
+}  // namespace
 
 hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p, float *sum, float *sumsq) {
     const SceneDev &S0 = ctx->scene;
@@ -519,7 +629,42 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
     P.mis_mode = p->mis_mode;
     P.env[0] = p->env_radiance[0]; P.env[1] = p->env_radiance[1]; P.env[2] = p->env_radiance[2];
     P.has_env = (P.env[0] > 0.f || P.env[1] > 0.f || P.env[2] > 0.f) ? 1 : 0;
-    e = hipMemsetAsync(ctx->stats, 0, sizeof(int64_t) * 4, st);
+    // radiance cache: modes 1 and 2 need the network; records only in mode 1
+    P.nrc = NrcArgs{p->nrc_mode, p->nrc_terminate_after, nullptr, nullptr, 0, nullptr, nullptr, nullptr};
+    int32_t *nrc_cnt = rb->counts + kCountStride * (nv + 1);  // [0] queries, [1] records appended
+    float nrc_box[6];
+    const float *box = nullptr;
+    if (p->nrc_mode != 0) {
+        bool valid = true;
+        for (int k = 0; k < 3; ++k) valid = valid && p->nrc_box[3 + k] > p->nrc_box[k];
+        if (valid) {
+            for (int k = 0; k < 6; ++k) nrc_box[k] = p->nrc_box[k];
+            box = nrc_box;
+        }
+        if (p->nrc_mode != 3) {
+            e = nrc_ensure(ctx);
+            if (e != hipSuccess) return e;
+        }
+        bool fresh = false;
+        e = ensure_nrc_buffers(ctx, npix, p->nrc_mode == 1 ? p->nrc_train_records : 0, &fresh);
+        if (e != hipSuccess) return e;
+        if (p->nrc_mode == 1 && (fresh || ctx->nrc_frac_pixels != npix)) {
+            // a training path is chosen with probability frac; frac starts at
+            // records / (2 pixels) and is adapted after every pass
+            const float f0 = std::min(1.0f, (float)p->nrc_train_records / (2.0f * (float)npix));
+            hipLaunchKernelGGL(k_set_float, dim3(1), dim3(1), 0, st, rb->frac, f0);
+            ctx->nrc_frac_pixels = npix;
+        }
+        P.nrc.qry = rb->qry;
+        P.nrc.n_qry = nrc_cnt;
+        P.nrc.frac = rb->frac;
+        if (p->nrc_mode == 1) {
+            P.nrc.rec = rb->rec;
+            P.nrc.n_rec = nrc_cnt + 1;
+            P.nrc.rec_cap = p->nrc_train_records;
+        }
+    }
+    e = hipMemsetAsync(ctx->stats, 0, sizeof(int64_t) * 8, st);
     if (e != hipSuccess) return e;
     // profiling: level 2 counts traversal work, level >= 1 brackets launches with events
     // per kernel category c (0 collide, 1 collide overflow, 2 light, 3 env) the
@@ -613,11 +758,56 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
                     });
             }
         }
+        if (p->nrc_mode == 1 || p->nrc_mode == 2) {
+            // cached radiance of the paths that ended in the cache
+            timed(6, [&] {
+                e = nrc_forward(ctx, npix, nrc_cnt, rb->qry, kNrcRecordFloats, 2, box, nullptr, rb->L);
+            });
+            if (e != hipSuccess) return e;
+        }
         hipLaunchKernelGGL(k_accum, dim3(gpix), dim3(256), 0, st, npix, rb->L, sum, sumsq);
+        if (p->nrc_mode == 1) {
+            // targets of this pass's records, one optimisation step, new training-path probability
+            timed(7, [&] {
+                e = nrc_targets(ctx, p->nrc_train_records, nrc_cnt + 1, rb->rec, rb->L, rb->targets);
+                if (e == hipSuccess)
+                    e = nrc_train_step(ctx, p->nrc_train_records, nrc_cnt + 1, rb->rec, kNrcRecordFloats, 0, box,
+                                       rb->targets, p->nrc_lr > 0.f ? p->nrc_lr : 1e-3f, rb->loss, nullptr);
+                if (e == hipSuccess) e = nrc_adapt(ctx, nrc_cnt + 1, p->nrc_train_records, rb->frac);
+            });
+            if (e != hipSuccess) return e;
+        }
+        if (p->nrc_mode != 0)
+            hipLaunchKernelGGL(k_nrc_stats, dim3(1), dim3(1), 0, st, (const int32_t *)nrc_cnt, ctx->stats);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     ctx->last_paths = npix * p->spp;
+    ctx->last_nrc_counts = p->nrc_mode == 1 ? (int64_t)(nrc_cnt - rb->counts) : -1;
+    ctx->last_nrc_cap = p->nrc_mode == 1 ? p->nrc_train_records : 0;
+    return hipSuccess;
+}
+
+const float *render_nrc_loss(ugp_ctx ctx) { return ctx->rb ? ctx->rb->loss : nullptr; }
+
+hipError_t render_nrc_records(ugp_ctx ctx, int64_t cap, float *rec_out, float *tgt_out, int64_t *count) {
+    *count = 0;
+    RenderBuffers *rb = ctx->rb;
+    if (!rb || !rb->nrc_block || ctx->last_nrc_counts < 0) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return e;
+    int32_t appended = 0;
+    e = hipMemcpy(&appended, rb->counts + ctx->last_nrc_counts + 1, sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return e;
+    int64_t n = std::min<int64_t>((int64_t)appended, ctx->last_nrc_cap);
+    n = std::min<int64_t>(n, cap);
+    if (n > 0) {
+        e = hipMemcpy(rec_out, rb->rec, sizeof(float) * kNrcRecordFloats * (size_t)n, hipMemcpyDeviceToDevice);
+        if (e == hipSuccess && tgt_out)
+            e = hipMemcpy(tgt_out, rb->targets, sizeof(float) * 3 * (size_t)n, hipMemcpyDeviceToDevice);
+        if (e != hipSuccess) return e;
+    }
+    *count = n;
     return hipSuccess;
 }
 

@@ -65,7 +65,11 @@ struct ugp_ctx_s {
     ugp::RenderBuffers *rb = nullptr;
     ugp::NrcState *nrc = nullptr;
     int64_t last_paths = 0;
-    int64_t *stats = nullptr;       // device counters of the last render: [collision, light, env]
+    int64_t nrc_frac_pixels = 0;    // image size the training-path probability was set for
+    int64_t last_nrc_counts = -1;   // offset of the cache counters of the last mode-1 render in the count buffer
+    int64_t last_nrc_cap = 0;       // records cap of that render
+    int64_t *stats = nullptr;       // device counters of the last render: [collision, light, env,
+                                    //  cache queries, cache training records, -, -, -]
     unsigned long long *counters = nullptr;  // [3] traversal counters (profiling level 2)
     int profiling = 0;
     // event pairs of the last render, by category: 0 collide main, 1 collide wide, 2 light, 3 env,
@@ -97,6 +101,35 @@ hipError_t launch_sweep(ugp_ctx ctx, int mode, int64_t n, const float *rays, con
 hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p, float *sum,
                   float *sumsq);
 void free_render(ugp_ctx ctx);
+// device float: loss of the last radiance-cache training step of a render (or NULL)
+const float *render_nrc_loss(ugp_ctx ctx);
+// copy the training records (and targets) of the last pass; synchronises
+hipError_t render_nrc_records(ugp_ctx ctx, int64_t cap, float *rec_out, float *tgt_out, int64_t *count);
+
+// nrc.hip -- the neural radiance cache.  Record layout shared with the
+// renderer (kNrcRecordFloats floats per record): [0..15] network inputs
+// (position, outgoing direction, normal, roughness, albedo, 3 unused),
+// [16..18] throughput at the vertex, [19] pixel index bits (bit 30 free for
+// the renderer's flags), [20..22] path radiance before the vertex's
+// scattered light, [23] vertex index.
+constexpr int kNrcRecordFloats = 24;
+int nrc_num_params();
+hipError_t nrc_ensure(ugp_ctx ctx);
+void nrc_free(ugp_ctx ctx);
+bool nrc_ready(ugp_ctx ctx);
+hipError_t nrc_set_weights(ugp_ctx ctx, const float *w);
+hipError_t nrc_get_weights(ugp_ctx ctx, float *w);
+// box: [host] lo[3], hi[3] of the position normalisation, or NULL for the scene bounds
+hipError_t nrc_encode(ugp_ctx ctx, int64_t n, const float *inputs, int stride, const float *box, float *feat);
+// src_kind 0: raw inputs (stride floats per record) -> y; 1: features [n][96]
+// -> y; 2: records (kNrcRecordFloats) -> L[pixel] += throughput * max(0, y)
+hipError_t nrc_forward(ugp_ctx ctx, int64_t n, const int32_t *n_dev, const float *src, int stride, int src_kind,
+                       const float *box, float *y, float4 *L);
+hipError_t nrc_train_step(ugp_ctx ctx, int64_t n, const int32_t *n_dev, const float *src, int stride, int src_kind,
+                          const float *box, const float *targets, float lr, float *loss_out, float *grad_out);
+hipError_t nrc_targets(ugp_ctx ctx, int64_t cap, const int32_t *n_dev, const float *rec, const float4 *L,
+                       float *targets);
+hipError_t nrc_adapt(ugp_ctx ctx, const int32_t *attempted, int32_t cap, float *frac);
 
 // device scratch of the context: returns a buffer of at least `bytes`
 void *ctx_scratch(ugp_ctx ctx, size_t bytes);
