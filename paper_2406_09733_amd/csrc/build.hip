@@ -5,16 +5,23 @@
 //    r max(s) and the box of the cut-off ellipsoid |S^-1 R^T (x - mu)| = r
 //    (eq. cutoff_threshold), half-extent r sqrt(sum_i (R_ji s_i)^2), rounded
 //    outward to float.  Inputs are validated here.
-// 2. 30-bit Morton codes of the box centres in the scene bounds.
-// 3. Stable LSD radix sort of (code, original index), 4 passes of 8 bits.
+// 2. References: a primitive whose largest scale exceeds 4x its middle one is
+//    cut along its long axis into m <= 8 slabs of equal thickness in its unit
+//    frame, each referenced by its own (much tighter) box; the others have one
+//    reference with the whole box.  A ray reports such a primitive only
+//    through the slab that holds its chord entry point, so every primitive is
+//    seen once.
+// 3. 30-bit Morton codes of the reference box centres in the scene bounds,
+//    stable LSD radix sort of (code, reference), 4 passes of 8 bits.
 // 4. Binary radix tree over the sorted codes (Karras, "Maximizing Parallelism
 //    in the Construction of BVHs, Octrees, and k-d Trees", HPG 2012); equal
 //    codes are split by position.
 // 5. Bottom-up refit: every leaf climbs, the second child to arrive at a node
 //    forms its box (agent-scope atomics and fences, so it is safe across XCDs).
-// 6. Scatter the hot / cold records into leaf order: hot = (mu, d, M = S^-1 R^T
-//    rounded to float, original index), 64 B; cold = facet normal, material,
-//    albedo, roughness, emission, bounding-sphere radius, 48 B.
+// 6. Scatter the hot records into leaf order, one per reference: hot = (mu,
+//    d, M = S^-1 R^T rounded to float, original index, slab), 64 B; the cold
+//    records (facet normal, material, albedo, roughness, emission,
+//    bounding-sphere radius, 48 B) stay in original order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -215,8 +222,29 @@ struct PackIn {
 
 // boxes [n][6] (lo.xyz, hi.xyz) in original order; cold written in original
 // order into a temporary; bounds[6] ordered-uint min/max of box centres
+// slabs of a primitive: 1, or up to 8 along the long axis when it is more
+// than 4x longer than its middle scale
+__device__ __forceinline__ int slab_count(const double s[3]) {
+    const double smax = fmax(s[0], fmax(s[1], s[2])), smin = fmin(s[0], fmin(s[1], s[2]));
+    const double smid = s[0] + s[1] + s[2] - smax - smin;
+    const double ratio = smax / smid;
+    return ratio > 4.0 ? (int)fmin(8.0, ceil(ratio / 2.5)) : 1;
+}
+
+__device__ __forceinline__ void quat_to_R(const PackIn &in, int64_t k, double R[3][3]) {
+    const double qw = in.rot[4 * k], qx = in.rot[4 * k + 1], qy = in.rot[4 * k + 2], qz = in.rot[4 * k + 3];
+    const double qn = qw * qw + qx * qx + qy * qy + qz * qz;
+    const double t = 2.0 / qn;
+    const double xx = qx * qx * t, yy = qy * qy * t, zz = qz * qz * t;
+    const double xy = qx * qy * t, xz = qx * qz * t, yz = qy * qz * t;
+    const double wx = qw * qx * t, wy = qw * qy * t, wz = qw * qz * t;
+    R[0][0] = 1.0 - yy - zz; R[0][1] = xy - wz; R[0][2] = xz + wy;
+    R[1][0] = xy + wz; R[1][1] = 1.0 - xx - zz; R[1][2] = yz - wx;
+    R[2][0] = xz - wy; R[2][1] = yz + wx; R[2][2] = 1.0 - xx - yy;
+}
+
 __global__ void k_pack(PackIn in, float *boxes, float4 *cold_tmp, float *mtmp, uint32_t *bounds,
-                       uint32_t *err) {
+                       int32_t *pieces, uint32_t *err) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= in.n) return;
     const double qw = in.rot[4 * k], qx = in.rot[4 * k + 1], qy = in.rot[4 * k + 2], qz = in.rot[4 * k + 3];
@@ -230,15 +258,12 @@ __global__ void k_pack(PackIn in, float *boxes, float4 *cold_tmp, float *mtmp, u
     if (bad) {
         atomicOr(err, 8u);
         for (int i = 0; i < 6; ++i) boxes[6 * k + i] = 0.f;
+        pieces[k] = 1;
         return;
     }
-    const double t = 2.0 / qn;
-    const double xx = qx * qx * t, yy = qy * qy * t, zz = qz * qz * t;
-    const double xy = qx * qy * t, xz = qx * qz * t, yz = qy * qz * t;
-    const double wx = qw * qx * t, wy = qw * qy * t, wz = qw * qz * t;
-    const double R[3][3] = {{1.0 - yy - zz, xy - wz, xz + wy},
-                            {xy + wz, 1.0 - xx - zz, yz - wx},
-                            {xz - wy, yz + wx, 1.0 - xx - yy}};
+    double R[3][3];
+    quat_to_R(in, k, R);
+    pieces[k] = slab_count(s);
     int am = 0;
     if (s[1] < s[am]) am = 1;
     if (s[2] < s[am]) am = 2;
@@ -265,6 +290,60 @@ __global__ void k_pack(PackIn in, float *boxes, float4 *cold_tmp, float *mtmp, u
         atomicMin(&bounds[j], f2o(c));
         atomicMax(&bounds[3 + j], f2o(c));
     }
+}
+
+// References of primitive k at roff[k] ..: the whole box, or the boxes of its
+// slabs.  Slab i of m holds the unit-frame points y with |y| <= r and y_L in
+// [-r + 2 r i / m, -r + 2 r (i + 1) / m] (L = the long axis).  Its box bounds
+// mu + A_L y_L (the axis segment) plus the cross-section disc of radius
+// sqrt(r^2 - min y_L^2) spanned by A_a, A_b (A = R S), widened by a small
+// margin so that a chord entry computed with the float M falls inside the
+// box of the slab that owns it; it is clipped to the whole box.
+__global__ void k_refs(PackIn in, const int32_t *pieces, const int32_t *roff, const float *boxes, float *rbox,
+                       int32_t *rprim, int32_t *rinfo) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= in.n) return;
+    const int m = pieces[k];
+    const int64_t j0 = roff[k];
+    if (m == 1) {
+        for (int c = 0; c < 6; ++c) rbox[6 * j0 + c] = boxes[6 * k + c];
+        rprim[j0] = (int32_t)k;
+        rinfo[j0] = 1 << 8;
+        return;
+    }
+    double R[3][3];
+    quat_to_R(in, k, R);
+    const double s[3] = {in.scale[3 * k], in.scale[3 * k + 1], in.scale[3 * k + 2]};
+    int L = 0;
+    if (s[1] > s[L]) L = 1;
+    if (s[2] > s[L]) L = 2;
+    const int a = (L + 1) % 3, b = (L + 2) % 3;
+    const double r = in.r * (1.0 + 1e-5), dl = 1e-4 * in.r;
+    for (int i = 0; i < m; ++i) {
+        const double v0 = fmax(-r, -in.r + 2.0 * in.r * i / m - dl);
+        const double v1 = fmin(r, -in.r + 2.0 * in.r * (i + 1) / m + dl);
+        const double rho = (v0 <= 0.0 && v1 >= 0.0) ? r : sqrt(fmax(0.0, r * r - fmin(v0 * v0, v1 * v1)));
+        const int64_t j = j0 + i;
+        for (int d = 0; d < 3; ++d) {
+            const double mu = in.mean[3 * k + d];
+            const double AL = R[d][L] * s[L], Aa = R[d][a] * s[a], Ab = R[d][b] * s[b];
+            const double c0 = AL * v0, c1 = AL * v1;
+            const double cs = rho * sqrt(Aa * Aa + Ab * Ab);
+            const double lo = fmax(mu + fmin(c0, c1) - cs, (double)boxes[6 * k + d]);
+            const double hi = fmin(mu + fmax(c0, c1) + cs, (double)boxes[6 * k + 3 + d]);
+            rbox[6 * j + d] = round_down(lo);
+            rbox[6 * j + 3 + d] = round_up(hi);
+        }
+        rprim[j] = (int32_t)k;
+        rinfo[j] = i | (m << 8) | (L << 16);
+    }
+}
+
+__global__ void k_emit_flags(int64_t n, const float4 *cold, int32_t *flag) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const float4 e = cold[3 * k + 2];
+    flag[k] = (e.x > 0.f || e.y > 0.f || e.z > 0.f) ? 1 : 0;
 }
 
 __global__ void k_init_bounds(uint32_t *b) {
@@ -499,22 +578,23 @@ __global__ void k_collapse(int64_t n, const float4 *nodes, const int32_t *even, 
     o[7] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
-__global__ void k_scatter(int64_t n, const int32_t *sorted_orig, PackIn in, const float4 *cold_tmp,
-                          const float *mtmp, float4 *hot, float4 *cold, int32_t *inv, int32_t *emit_flag) {
+// hot record of leaf i (reference sorted_ref[i]); inv[o] = the leaf of the
+// first slab of primitive o
+__global__ void k_scatter(int64_t nr, const int32_t *sorted_ref, const int32_t *rprim, const int32_t *rinfo,
+                          PackIn in, const float *mtmp, float4 *hot, int32_t *inv) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t o = sorted_orig[i];
+    if (i >= nr) return;
+    const int32_t j = sorted_ref[i];
+    const int64_t o = rprim[j];
+    const int info = rinfo[j];
     const float *M = mtmp + 9 * o;
     hot[4 * i] = make_float4(in.mean[3 * o], in.mean[3 * o + 1], in.mean[3 * o + 2], in.dens[o]);
     hot[4 * i + 1] = make_float4(M[0], M[1], M[2], M[3]);
     hot[4 * i + 2] = make_float4(M[4], M[5], M[6], M[7]);
     // largest row norm of M, 1 / min(s): bounds how M magnifies an offset
     const float smin = fminf(in.scale[3 * o], fminf(in.scale[3 * o + 1], in.scale[3 * o + 2]));
-    hot[4 * i + 3] = make_float4(M[8], __int_as_float((int)o), 1.0f / smin, 0.f);
-    for (int c = 0; c < 3; ++c) cold[3 * i + c] = cold_tmp[3 * o + c];
-    inv[o] = (int32_t)i;
-    const float4 e = cold_tmp[3 * o + 2];
-    emit_flag[o] = (e.x > 0.f || e.y > 0.f || e.z > 0.f) ? 1 : 0;
+    hot[4 * i + 3] = make_float4(M[8], __int_as_float((int)o), 1.0f / smin, __int_as_float(info));
+    if ((info & 255) == 0) inv[o] = (int32_t)i;
 }
 
 __global__ void k_compact(int64_t n, const int32_t *flag, const int32_t *pos, int32_t *out) {
@@ -550,57 +630,86 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
     sc.r2 = (float)(r * r);
     PackIn in{n, s->mean, s->scale, s->rotation, s->density, s->albedo, s->roughness, s->emission,
               s->material, r};
-    float *boxes = nullptr;
-    float4 *cold_tmp = nullptr;
+    float *boxes = nullptr, *rbox = nullptr;
     float *mtmp = nullptr;
     uint32_t *bounds = nullptr, *keys = nullptr, *tk = nullptr;
     int32_t *vals = nullptr, *tv = nullptr, *pnode = nullptr, *pleaf = nullptr, *flags = nullptr;
+    int32_t *pc_node = nullptr, *pc_leaf = nullptr, *pieces = nullptr, *roff = nullptr, *rprim = nullptr,
+            *rinfo = nullptr;
     int32_t *emit_flag = nullptr, *emit_pos = nullptr, *depth = nullptr;
     hipError_t e = hipSuccess;
     uint32_t h_err = 0;
-    int32_t h_depth = 0, h_nemit = 0, h_last_flag = 0;
-    const int64_t ni = n > 1 ? n - 1 : 1;
+    int32_t h_depth = 0, h_nemit = 0, h_last_flag = 0, h_roff_last = 0, h_pieces_last = 0;
+    int64_t nr = 0, ni = 1;
 
-    UGP_CHECK(hipMalloc((void **)&sc.hot, sizeof(float4) * 4 * n));
+    // pack, slab counts, reference offsets
     UGP_CHECK(hipMalloc((void **)&sc.cold, sizeof(float4) * 3 * n));
-    UGP_CHECK(hipMalloc((void **)&sc.nodes, sizeof(float4) * 4 * ni));
     UGP_CHECK(hipMalloc((void **)&sc.inv, sizeof(int32_t) * n));
     UGP_CHECK(hipMallocAsync((void **)&boxes, sizeof(float) * 6 * n, st));
-    UGP_CHECK(hipMallocAsync((void **)&cold_tmp, sizeof(float4) * 3 * n, st));
     UGP_CHECK(hipMallocAsync((void **)&mtmp, sizeof(float) * 9 * n, st));
     UGP_CHECK(hipMallocAsync((void **)&bounds, sizeof(uint32_t) * 8, st));
-    UGP_CHECK(hipMallocAsync((void **)&keys, sizeof(uint32_t) * n, st));
-    UGP_CHECK(hipMallocAsync((void **)&tk, sizeof(uint32_t) * n, st));
-    UGP_CHECK(hipMallocAsync((void **)&vals, sizeof(int32_t) * n, st));
-    UGP_CHECK(hipMallocAsync((void **)&tv, sizeof(int32_t) * n, st));
-    UGP_CHECK(hipMallocAsync((void **)&pnode, sizeof(int32_t) * ni, st));
-    UGP_CHECK(hipMallocAsync((void **)&pleaf, sizeof(int32_t) * n, st));
-    UGP_CHECK(hipMallocAsync((void **)&flags, sizeof(int32_t) * ni, st));
+    UGP_CHECK(hipMallocAsync((void **)&pieces, sizeof(int32_t) * n, st));
+    UGP_CHECK(hipMallocAsync((void **)&roff, sizeof(int32_t) * n, st));
     UGP_CHECK(hipMallocAsync((void **)&emit_flag, sizeof(int32_t) * n, st));
     UGP_CHECK(hipMallocAsync((void **)&emit_pos, sizeof(int32_t) * n, st));
     UGP_CHECK(hipMallocAsync((void **)&depth, sizeof(int32_t), st));
     UGP_CHECK(hipMemsetAsync(ctx->err, 0, sizeof(uint32_t), st));
-    UGP_CHECK(hipMemsetAsync(flags, 0, sizeof(int32_t) * ni, st));
     UGP_CHECK(hipMemsetAsync(depth, 0, sizeof(int32_t), st));
     hipLaunchKernelGGL(k_init_bounds, dim3(1), dim3(64), 0, st, bounds);
-    hipLaunchKernelGGL(k_pack, dim3(blocks(n)), dim3(kThreads), 0, st, in, boxes, cold_tmp, mtmp, bounds, ctx->err);
-    hipLaunchKernelGGL(k_morton, dim3(blocks(n)), dim3(kThreads), 0, st, n, boxes, bounds, keys, vals);
+    hipLaunchKernelGGL(k_pack, dim3(blocks(n)), dim3(kThreads), 0, st, in, boxes, sc.cold, mtmp, bounds, pieces,
+                       ctx->err);
     UGP_CHECK(hipGetLastError());
-    UGP_CHECK(radix_sort(keys, vals, tk, tv, n, st));
-    if (n > 1) {
-        hipLaunchKernelGGL(k_karras, dim3(blocks(n - 1)), dim3(kThreads), 0, st, keys, n, sc.nodes, pnode, pleaf);
-        UGP_CHECK(hipMemsetAsync(emit_flag, 0, sizeof(int32_t) * n, st));
-        UGP_CHECK(hipMemsetAsync(emit_pos, 0, sizeof(int32_t) * n, st));
-        hipLaunchKernelGGL(k_validate_refs, dim3(blocks(n - 1)), dim3(kThreads), 0, st, n, sc.nodes, emit_pos,
-                           emit_flag, ctx->err);
-        hipLaunchKernelGGL(k_validate_counts, dim3(blocks(n)), dim3(kThreads), 0, st, n, emit_pos, emit_flag,
-                           ctx->err);
-        hipLaunchKernelGGL(k_refit, dim3(blocks(n)), dim3(kThreads), 0, st, n, vals, boxes, sc.nodes, pnode,
-                           pleaf, flags, (const uint32_t *)ctx->err);
-        hipLaunchKernelGGL(k_depth, dim3(blocks(n)), dim3(kThreads), 0, st, n, pnode, pleaf, depth, ctx->err);
+    UGP_CHECK(exclusive_scan(pieces, roff, n, st));
+    UGP_CHECK(hipMemcpyAsync(&h_roff_last, roff + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    UGP_CHECK(hipMemcpyAsync(&h_pieces_last, pieces + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    UGP_CHECK(hipMemcpyAsync(&h_err, ctx->err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    UGP_CHECK(hipStreamSynchronize(st));
+    if (h_err & 8u) {
+        e = hipErrorInvalidValue;
+        goto fail;
     }
-    hipLaunchKernelGGL(k_scatter, dim3(blocks(n)), dim3(kThreads), 0, st, n, vals, in, cold_tmp, mtmp, sc.hot,
-                       sc.cold, sc.inv, emit_flag);
+    nr = (int64_t)h_roff_last + h_pieces_last;
+    if (nr >= (int64_t(1) << 31) - 1) {
+        e = hipErrorNotSupported;
+        goto fail;
+    }
+    ni = nr > 1 ? nr - 1 : 1;
+    sc.n_refs = nr;
+    UGP_CHECK(hipMalloc((void **)&sc.hot, sizeof(float4) * 4 * nr));
+    UGP_CHECK(hipMalloc((void **)&sc.nodes, sizeof(float4) * 4 * ni));
+    UGP_CHECK(hipMallocAsync((void **)&rbox, sizeof(float) * 6 * nr, st));
+    UGP_CHECK(hipMallocAsync((void **)&rprim, sizeof(int32_t) * nr, st));
+    UGP_CHECK(hipMallocAsync((void **)&rinfo, sizeof(int32_t) * nr, st));
+    UGP_CHECK(hipMallocAsync((void **)&keys, sizeof(uint32_t) * nr, st));
+    UGP_CHECK(hipMallocAsync((void **)&tk, sizeof(uint32_t) * nr, st));
+    UGP_CHECK(hipMallocAsync((void **)&vals, sizeof(int32_t) * nr, st));
+    UGP_CHECK(hipMallocAsync((void **)&tv, sizeof(int32_t) * nr, st));
+    UGP_CHECK(hipMallocAsync((void **)&pnode, sizeof(int32_t) * ni, st));
+    UGP_CHECK(hipMallocAsync((void **)&pleaf, sizeof(int32_t) * nr, st));
+    UGP_CHECK(hipMallocAsync((void **)&flags, sizeof(int32_t) * ni, st));
+    UGP_CHECK(hipMallocAsync((void **)&pc_node, sizeof(int32_t) * ni, st));
+    UGP_CHECK(hipMallocAsync((void **)&pc_leaf, sizeof(int32_t) * nr, st));
+    UGP_CHECK(hipMemsetAsync(flags, 0, sizeof(int32_t) * ni, st));
+    hipLaunchKernelGGL(k_refs, dim3(blocks(n)), dim3(kThreads), 0, st, in, (const int32_t *)pieces,
+                       (const int32_t *)roff, (const float *)boxes, rbox, rprim, rinfo);
+    hipLaunchKernelGGL(k_morton, dim3(blocks(nr)), dim3(kThreads), 0, st, nr, rbox, bounds, keys, vals);
+    UGP_CHECK(hipGetLastError());
+    UGP_CHECK(radix_sort(keys, vals, tk, tv, nr, st));
+    if (nr > 1) {
+        hipLaunchKernelGGL(k_karras, dim3(blocks(nr - 1)), dim3(kThreads), 0, st, keys, nr, sc.nodes, pnode, pleaf);
+        UGP_CHECK(hipMemsetAsync(pc_leaf, 0, sizeof(int32_t) * nr, st));
+        UGP_CHECK(hipMemsetAsync(pc_node, 0, sizeof(int32_t) * ni, st));
+        hipLaunchKernelGGL(k_validate_refs, dim3(blocks(nr - 1)), dim3(kThreads), 0, st, nr, sc.nodes, pc_node,
+                           pc_leaf, ctx->err);
+        hipLaunchKernelGGL(k_validate_counts, dim3(blocks(nr)), dim3(kThreads), 0, st, nr, pc_node, pc_leaf,
+                           ctx->err);
+        hipLaunchKernelGGL(k_refit, dim3(blocks(nr)), dim3(kThreads), 0, st, nr, vals, rbox, sc.nodes, pnode,
+                           pleaf, flags, (const uint32_t *)ctx->err);
+        hipLaunchKernelGGL(k_depth, dim3(blocks(nr)), dim3(kThreads), 0, st, nr, pnode, pleaf, depth, ctx->err);
+    }
+    hipLaunchKernelGGL(k_scatter, dim3(blocks(nr)), dim3(kThreads), 0, st, nr, vals, (const int32_t *)rprim,
+                       (const int32_t *)rinfo, in, mtmp, sc.hot, sc.inv);
+    hipLaunchKernelGGL(k_emit_flags, dim3(blocks(n)), dim3(kThreads), 0, st, n, (const float4 *)sc.cold, emit_flag);
     UGP_CHECK(hipGetLastError());
     UGP_CHECK(exclusive_scan(emit_flag, emit_pos, n, st));
     UGP_CHECK(hipMemcpyAsync(&h_nemit, emit_pos + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -609,10 +718,10 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
     UGP_CHECK(hipMemcpyAsync(&h_err, ctx->err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     {
         float rootb[12];
-        if (n > 1) UGP_CHECK(hipMemcpyAsync(rootb, sc.nodes, sizeof(float) * 12, hipMemcpyDeviceToHost, st));
-        else UGP_CHECK(hipMemcpyAsync(rootb, boxes, sizeof(float) * 6, hipMemcpyDeviceToHost, st));
+        if (nr > 1) UGP_CHECK(hipMemcpyAsync(rootb, sc.nodes, sizeof(float) * 12, hipMemcpyDeviceToHost, st));
+        else UGP_CHECK(hipMemcpyAsync(rootb, rbox, sizeof(float) * 6, hipMemcpyDeviceToHost, st));
         UGP_CHECK(hipStreamSynchronize(st));
-        if (n > 1) {
+        if (nr > 1) {
             for (int c = 0; c < 3; ++c) {
                 sc.lo[c] = std::min(rootb[c], rootb[6 + c]);
                 sc.hi[c] = std::max(rootb[3 + c], rootb[9 + c]);
@@ -631,17 +740,17 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
     }
     h_nemit += h_last_flag;
     sc.n_emit = h_nemit;
-    sc.depth = n > 1 ? h_depth : 1;
-    sc.root = n > 1 ? 0 : ~0;
-    if (n > 1) {
-        // 4-wide collapse (pnode / flags / keys reused as scratch)
+    sc.depth = nr > 1 ? h_depth : 1;
+    sc.root = nr > 1 ? 0 : ~0;
+    if (nr > 1) {
+        // 4-wide collapse (flags / keys reused as scratch)
         int32_t *even = flags, *map = (int32_t *)keys;
         int32_t h_n4 = 0, h_last = 0;
-        hipLaunchKernelGGL(k_node_parity, dim3(blocks(n - 1)), dim3(kThreads), 0, st, n, pnode, even, ctx->err);
+        hipLaunchKernelGGL(k_node_parity, dim3(blocks(nr - 1)), dim3(kThreads), 0, st, nr, pnode, even, ctx->err);
         UGP_CHECK(hipGetLastError());
-        UGP_CHECK(exclusive_scan(even, map, n - 1, st));
-        UGP_CHECK(hipMemcpyAsync(&h_n4, map + (n - 2), sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        UGP_CHECK(hipMemcpyAsync(&h_last, even + (n - 2), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        UGP_CHECK(exclusive_scan(even, map, nr - 1, st));
+        UGP_CHECK(hipMemcpyAsync(&h_n4, map + (nr - 2), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        UGP_CHECK(hipMemcpyAsync(&h_last, even + (nr - 2), sizeof(int32_t), hipMemcpyDeviceToHost, st));
         UGP_CHECK(hipMemcpyAsync(&h_err, ctx->err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
         UGP_CHECK(hipStreamSynchronize(st));
         if (h_err & 16u) {
@@ -651,7 +760,7 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
         h_n4 += h_last;
         float4 *nodes4 = nullptr;
         UGP_CHECK(hipMalloc((void **)&nodes4, sizeof(float4) * 8 * (size_t)h_n4));
-        hipLaunchKernelGGL(k_collapse, dim3(blocks(n - 1)), dim3(kThreads), 0, st, n, (const float4 *)sc.nodes,
+        hipLaunchKernelGGL(k_collapse, dim3(blocks(nr - 1)), dim3(kThreads), 0, st, nr, (const float4 *)sc.nodes,
                            (const int32_t *)even, (const int32_t *)map, nodes4);
         UGP_CHECK(hipGetLastError());
         UGP_CHECK(hipStreamSynchronize(st));
@@ -670,9 +779,11 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
         hipLaunchKernelGGL(k_compact, dim3(blocks(n)), dim3(kThreads), 0, st, n, emit_flag, emit_pos, sc.emit);
         UGP_CHECK(hipGetLastError());
     }
-    hipFreeAsync(boxes, st); hipFreeAsync(cold_tmp, st); hipFreeAsync(mtmp, st); hipFreeAsync(bounds, st);
+    hipFreeAsync(boxes, st); hipFreeAsync(rbox, st); hipFreeAsync(mtmp, st); hipFreeAsync(bounds, st);
     hipFreeAsync(keys, st); hipFreeAsync(tk, st); hipFreeAsync(vals, st); hipFreeAsync(tv, st);
     hipFreeAsync(pnode, st); hipFreeAsync(pleaf, st); hipFreeAsync(flags, st);
+    hipFreeAsync(pc_node, st); hipFreeAsync(pc_leaf, st); hipFreeAsync(pieces, st); hipFreeAsync(roff, st);
+    hipFreeAsync(rprim, st); hipFreeAsync(rinfo, st);
     hipFreeAsync(emit_flag, st); hipFreeAsync(emit_pos, st); hipFreeAsync(depth, st);
     UGP_CHECK(hipStreamSynchronize(st));
     free_scene(ctx->scene);
@@ -680,8 +791,9 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
     return hipSuccess;
 fail:
     hipStreamSynchronize(st);
-    hipFree(boxes); hipFree(cold_tmp); hipFree(mtmp); hipFree(bounds); hipFree(keys); hipFree(tk);
+    hipFree(boxes); hipFree(rbox); hipFree(mtmp); hipFree(bounds); hipFree(keys); hipFree(tk);
     hipFree(vals); hipFree(tv); hipFree(pnode); hipFree(pleaf); hipFree(flags);
+    hipFree(pc_node); hipFree(pc_leaf); hipFree(pieces); hipFree(roff); hipFree(rprim); hipFree(rinfo);
     hipFree(emit_flag); hipFree(emit_pos); hipFree(depth);
     free_scene(sc);
     return e == hipSuccess ? hipErrorUnknown : e;

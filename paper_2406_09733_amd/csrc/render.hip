@@ -97,11 +97,11 @@ constexpr int kTrainBit = 0x40000000;
 
 __device__ __forceinline__ V3 f3(float4 v) { return v3(v.x, v.y, v.z); }
 
-// light pdf of emitter (leaf position ke) seen from x: uniform cone over its
+// light pdf of emitter k (original index) seen from x: uniform cone over its
 // bounding sphere, times the uniform emitter choice; 0 inside the sphere
-__device__ __forceinline__ float nee_pdf(const SceneDev &S, int ke, V3 x) {
-    const float4 h0 = S.hot[4 * ke];
-    const float rs = S.cold[3 * ke + 2].w;
+__device__ __forceinline__ float nee_pdf(const SceneDev &S, int k, V3 x) {
+    const float4 h0 = S.hot[4 * S.inv[k]];
+    const float rs = S.cold[3 * k + 2].w;
     const V3 c = v3(h0.x - x.x, h0.y - x.y, h0.z - x.z);
     const float d2 = dot(c, c);
     if (d2 <= rs * rs) return 0.f;
@@ -274,14 +274,13 @@ __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PassArgs P, int v,
                 }
             } else {
                 const int k = hit.x;
-                const int ks = S.inv[k];
-                const float4 c0 = S.cold[3 * ks], c1 = S.cold[3 * ks + 1], c2 = S.cold[3 * ks + 2];
+                const float4 c0 = S.cold[3 * k], c1 = S.cold[3 * k + 1], c2 = S.cold[3 * k + 2];
                 const V3 x = o + __int_as_float(hit.y) * d;
                 const V3 Le = f3(c2);
                 if (nonzero(Le)) {
                     float w = 1.f;
                     if (v > 1) {
-                        const float pn = nee_pdf(S, ks, o);
+                        const float pn = nee_pdf(S, k, o);
                         if (P.mis_mode == 2) w = pn > 0.f ? 0.f : 1.f;
                         else if (P.mis_mode == 0) w = p_prev / (p_prev + pn);
                     }
@@ -322,7 +321,7 @@ __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PassArgs P, int v,
                         const int e = S.emit[j];
                         const int es = S.inv[e];
                         const float4 eh = S.hot[4 * es];
-                        const float rs = S.cold[3 * es + 2].w;
+                        const float rs = S.cold[3 * e + 2].w;
                         V3 cd = v3(eh.x - x.x, eh.y - x.y, eh.z - x.z);
                         const float d2 = dot(cd, cd);
                         if (d2 > rs * rs) {
@@ -345,7 +344,7 @@ __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PassArgs P, int v,
                             const RayD lr = make_ray(x.x, x.y, x.z, wl.x, wl.y, wl.z, 0.f, __builtin_huge_val());
                             if (nonzero(f) && chord(load_hot(S.hot, es), lr, S.r2, tc)) {
                                 const float w = P.mis_mode == 2 ? 1.f : pn / (pn + pph);
-                                const float4 eL = S.cold[3 * es + 2];
+                                const float4 eL = S.cold[3 * e + 2];
                                 const V3 wt = (w / pn) * mul(mul(beta, f), f3(eL));
                                 do_nee = true;
                                 na = make_float4(x.x, x.y, x.z, __int_as_float(e));

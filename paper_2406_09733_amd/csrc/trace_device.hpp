@@ -82,6 +82,7 @@ struct Chord {
     float ta, tb;  // tau at the clipped ends
     float W;       // 1/2 I(a, b)
     int orig;      // original index
+    bool own;      // this reference holds the chord entry (always, for an uncut primitive)
 };
 
 __device__ __forceinline__ double rcp_d(double x) {
@@ -100,17 +101,19 @@ __device__ __forceinline__ float erf_diff(float ta, float tb) {
 }
 
 // 64-byte primitive record: (mu.xyz, d), (M00 M01 M02 M10), (M11 M12 M20 M21),
-// (M22, original index bits, 1/min(s), -) with M = S^-1 R^T in float
+// (M22, original index bits, 1/min(s), slab bits) with M = S^-1 R^T in float
 struct HotRec {
     float mx, my, mz, d;
     float m[9];
     int orig;
     float mnorm;  // largest row norm of M
+    int slab;     // slab index | count << 8 | long axis << 16
 };
 
 __device__ __forceinline__ HotRec load_hot(const float4 *hot, int i) {
     const float4 a = hot[4 * i], b = hot[4 * i + 1], c = hot[4 * i + 2], e = hot[4 * i + 3];
-    return HotRec{a.x, a.y, a.z, a.w, {b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w, e.x}, __float_as_int(e.y), e.z};
+    return HotRec{a.x, a.y, a.z, a.w, {b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w, e.x}, __float_as_int(e.y), e.z,
+                  __float_as_int(e.w)};
 }
 
 // Cheap float test that the ray surely misses the cut-off ellipsoid: the
@@ -183,6 +186,21 @@ __device__ inline bool chord(const HotRec &h, const RayD &r, float r2, Chord &c)
     c.b = (float)b;
     c.W = 0.5f * c.pref * erf_diff(c.ta, c.tb);
     c.orig = h.orig;
+    // a cut primitive is reported by the slab holding the chord entry: the
+    // long-axis coordinate of x(a) in the unit frame, q + (a - t_e) w', in
+    // m equal slabs of [-r, r]
+    const int m = (h.slab >> 8) & 255;
+    c.own = true;
+    if (m > 1) {
+        const int L = h.slab >> 16;
+        const double qL = L == 0 ? q0 : (L == 1 ? q1 : q2);
+        const double wL = L == 0 ? w0 : (L == 1 ? w1 : w2);
+        const double rr = (double)sqrtf(r2);
+        const double v = fma(a - te, wL, qL);
+        int own = (int)floor((v + rr) * (double)m / (2.0 * rr));
+        own = own < 0 ? 0 : (own >= m ? m - 1 : own);
+        c.own = own == (h.slab & 255);
+    }
     return true;
 }
 
@@ -326,7 +344,7 @@ __device__ inline float transmittance_F(const SceneDev &S, const RayD &r, int ex
         const HotRec h = load_hot(S.hot, p);
         if (h.orig == excl) return false;
         Chord c;
-        if (!chord(h, r, S.r2, c)) return false;
+        if (!chord(h, r, S.r2, c) || !c.own) return false;
         F += c.W;
         return early_out && F >= 1.f;
     });
@@ -355,6 +373,12 @@ __device__ inline float transmittance_F(const SceneDev &S, const RayD &r, int ex
 //     eq. sampling_overlaps), the exits before t_sat are finalised in exit
 //     order and the straddlers follow by index with clipped weights.
 // Primitives still active at the cap stay in the buffer for the next round.
+// During a round the traversal is also cut at a saturation bound: F(t) is at
+// least the finalised weight plus the full weights of buffered primitives
+// that exit by t, so once that sum passes 1 at the exit b of a newly buffered
+// primitive, t_sat <= b and nothing entering after b can carry weight (all
+// primitives entering before b are still gathered, so the round then
+// saturates with F exact on [t_cur, b]).
 // ---------------------------------------------------------------------------
 struct Ev {
     float a, b, w;
@@ -457,16 +481,19 @@ __device__ __forceinline__ SweepOut sweep(const SceneDev &S, const RayD &r, int 
         ++tc.rounds;
         float cap_a = kInf;
         int cap_id = 0x7fffffff;
+        float cap_sat = kInf;  // saturation bound: t_sat <= cap_sat
         bool evicted = false;
         const int n_before = B.n;
-        traverse(S, r, fmaxf(r.t0, lb_a), [&]() __attribute__((always_inline)) { return fminf(cap_a, t1f); },
+        traverse(S, r, fmaxf(r.t0, lb_a),
+                 [&]() __attribute__((always_inline)) { return fminf(fminf(cap_a, cap_sat), t1f); },
                  stack, err, tc, [&](int p) __attribute__((always_inline)) {
                      const HotRec h = load_hot(S.hot, p);
                      if (h.orig == excl) return false;
                      Chord c;
-                     if (!chord(h, r, S.r2, c)) return false;
+                     if (!chord(h, r, S.r2, c) || !c.own) return false;
                      if (key_less(c.a, c.orig, lb_a, lb_id)) return false;    // seen before
                      if (!key_less(c.a, c.orig, cap_a, cap_id)) return false; // beyond cap
+                     if (c.a > cap_sat) return false;                          // past saturation
                      float xa = c.a, xb = c.b, xw = c.W;
                      int xi = c.orig;
                      bool placed = false;
@@ -490,6 +517,15 @@ __device__ __forceinline__ SweepOut sweep(const SceneDev &S, const RayD &r, int 
                          evicted = true;
                          cap_a = xa;
                          cap_id = xi;
+                     }
+                     if (c.b < cap_sat && key_less(c.a, c.orig, cap_a, cap_id)) {
+                         // the new primitive is buffered: lower bound of F(c.b)
+                         float lo_F = S_fin;
+#pragma unroll Unr<K>::v
+                         for (int i = 0; i < K; ++i)
+                             if (i < B.n && B.b[i] <= c.b) lo_F += B.w[i];
+                         // margin: the exact F(b) sums the same terms in another order
+                         if (lo_F >= 1.0001f) cap_sat = c.b;
                      }
                      return false;
                  });

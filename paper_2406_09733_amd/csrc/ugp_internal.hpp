@@ -8,19 +8,24 @@
 
 namespace ugp {
 
-// Device-side scene, all arrays in leaf (Morton) order of the hierarchy.
-//   hot   [n][4] float4: (mu.xyz, density), (M00 M01 M02 M10), (M11 M12 M20 M21),
-//                        (M22, orig id bits, 1/min(s), -) with M = S^-1 R^T rounded to float
-//   cold  [n][3] float4: (facet normal.xyz, material), (albedo.rgb, roughness),
-//                        (emission.rgb, bounding-sphere radius)
+// Device-side scene.  A primitive has one or more references (leaves of the
+// hierarchy): long primitives are cut into slabs along their long axis, each
+// slab a reference with its own box.
+//   hot   [n_refs][4] float4, leaf (Morton) order: (mu.xyz, density),
+//         (M00 M01 M02 M10), (M11 M12 M20 M21), (M22, orig id bits, 1/min(s),
+//         slab bits) with M = S^-1 R^T rounded to float; slab bits = slab index
+//         | slab count << 8 | long axis << 16
+//   cold  [n][3] float4, original order: (facet normal.xyz, material),
+//         (albedo.rgb, roughness), (emission.rgb, bounding-sphere radius)
 //   nodes [n_nodes4][8] float4: 4-wide nodes holding the boxes of up to four
 //         children as lo.x[4], lo.y[4], lo.z[4], hi.x[4], hi.y[4], hi.z[4],
-//         ref[4], pad; a ref >= 0 is a node, < 0 is the leaf primitive ~ref,
+//         ref[4], pad; a ref >= 0 is a node, < 0 is the leaf ~ref,
 //         kEmptySlot marks an unused slot
-//   inv   [n] original index -> leaf position
+//   inv   [n] original index -> leaf of its first slab
 //   emit  [n_emit] original indices of emissive primitives, ascending
 struct SceneDev {
     int64_t n = 0;
+    int64_t n_refs = 0;    // leaves (references) of the hierarchy
     int32_t root = 0;      // ref of the root (a leaf ref when n == 1)
     float r2 = 0.f;        // squared Mahalanobis radius of the cut-off ellipsoid
     float4 *hot = nullptr;

@@ -170,6 +170,27 @@ def tiny_random(seed: int = 0, n: int = 1000, n_emit: int = 10, emit: float = 5.
     return sc
 
 
+def needles(seed: int = 4, n: int = 3000, n_emit: int = 30, emit: float = 5.0) -> dict:
+    """A ball of long thin Gaussians (long scale 5-20x the two equal short
+    ones, short scale log-uniform in [0.003, 0.01]), means N(0.5, 0.12^2) per
+    axis, random rotations, peak density U[5, 50]: the shape of the elongated
+    clusters of the room workload, small enough for the oracle.  The BVH cuts
+    these primitives into slabs along their long axis."""
+    rng = _rng(seed)
+    mean = rng.normal(0.5, 0.12, (n, 3))
+    short = _loguniform(rng, 0.003, 0.01, n)
+    ratio = rng.uniform(5.0, 20.0, n)
+    scale = np.stack([short * ratio, short, short], 1)
+    q = _random_quat(rng, n)
+    dens = rng.uniform(5.0, 50.0, n)
+    sc = _finish([(mean, scale, q, dens)], rng, albedo_lo=0.2, albedo_hi=0.8, rough_lo=0.1,
+                 rough_hi=1.0, glossy_frac=0.5)
+    idx = rng.choice(n, size=min(n_emit, n), replace=False)
+    sc["emission"][idx] = emit
+    sc["bounds"] = (np.zeros(3, np.float32), np.ones(3, np.float32))
+    return sc
+
+
 def mixed_100k(seed: int = 1, n_flat: int = 70_000, n_cloud: int = 30_000,
                n_emit: int = 1_000, emit: float = 5.0) -> dict:
     """70% flat Gaussians (one axis 100x thinner) on 10 spheres and 10 square
@@ -294,8 +315,8 @@ def room_5p5m(seed: int = 2, n_surface: int = 4_300_000, n_clusters: int = 40,
 # cameras and render settings of the workloads
 # ---------------------------------------------------------------------------
 def camera(name: str) -> dict:
-    if name in ("tiny_random", "mixed_100k"):
-        w = 128 if name == "tiny_random" else 512
+    if name in ("tiny_random", "mixed_100k", "needles"):
+        w = 512 if name == "mixed_100k" else 128
         return {"origin": (0.5, 0.5, -1.0), "target": (0.5, 0.5, 0.5), "up": (0.0, 1.0, 0.0),
                 "vfov_deg": 45.0, "width": w, "height": w}
     if name == "room_5p5m":
@@ -306,6 +327,7 @@ def camera(name: str) -> dict:
 
 def render_settings(name: str) -> dict:
     return {"tiny_random": {"spp": 4, "max_depth": 4, "seed": 0},
+            "needles": {"spp": 4, "max_depth": 6, "seed": 4},
             "mixed_100k": {"spp": 16, "max_depth": 8, "seed": 1},
             "room_5p5m": {"spp": 64, "max_depth": 12, "seed": 2}}[name]
 

@@ -56,7 +56,8 @@ ATOL_SUM = 5e-7  # 4 ulp of 1.0 in float32
 
 
 def _cases():
-    return {"tiny_random": (scenes.tiny_random(), 4096), "mixed_100k": (scenes.mixed_100k(), 2048)}
+    return {"tiny_random": (scenes.tiny_random(), 4096), "mixed_100k": (scenes.mixed_100k(), 2048),
+            "needles": (scenes.needles(), 4096)}
 
 
 @pytest.fixture(scope="module")
@@ -74,7 +75,7 @@ def _with_exclude(sc, rays, seed):
     return ex
 
 
-@pytest.mark.parametrize("name", ["tiny_random", "mixed_100k"])
+@pytest.mark.parametrize("name", ["tiny_random", "mixed_100k", "needles"])
 def test_transmittance_parity(ctx, built, name):
     sc, S, nr = built[name]
     _say("transmittance parity", name, nr)
@@ -93,7 +94,7 @@ def test_transmittance_parity(ctx, built, name):
     assert np.all(np.abs(_np(T2) - T_ref) <= 1e-5)
 
 
-@pytest.mark.parametrize("name", ["tiny_random", "mixed_100k"])
+@pytest.mark.parametrize("name", ["tiny_random", "mixed_100k", "needles"])
 def test_saturation_parity(ctx, built, name):
     sc, S, nr = built[name]
     _say("saturation parity", name, nr)
@@ -120,7 +121,7 @@ def test_saturation_parity(ctx, built, name):
     assert ok.all(), (np.where(~ok)[0][:10], ts[~ok][:5], ts_ref[~ok][:5])
 
 
-@pytest.mark.parametrize("name", ["tiny_random", "mixed_100k"])
+@pytest.mark.parametrize("name", ["tiny_random", "mixed_100k", "needles"])
 def test_collision_parity(ctx, built, name):
     sc, S, nr = built[name]
     _say("collision parity", name, nr)
@@ -142,7 +143,7 @@ def test_collision_parity(ctx, built, name):
          "escape fraction", float((prim < 0).mean()))
 
 
-@pytest.mark.parametrize("name", ["tiny_random", "mixed_100k"])
+@pytest.mark.parametrize("name", ["tiny_random", "mixed_100k", "needles"])
 def test_emitter_query_parity(ctx, built, name):
     sc, S, nr = built[name]
     _say("emitter query parity", name, nr)
@@ -169,7 +170,7 @@ def test_emitter_query_parity(ctx, built, name):
             _say(f"  ray {i}: gpu {got[i]:.7g} oracle {ref[i]:.7g} chord {ch} tsat {ts:.9g} F(b) {Fe:.6g}"
                  f" t1 {rays[i, 7]} excl {ex[i]} tgt {tgt[i]}")
     assert ok.all(), (np.where(~ok)[0][:10], got[~ok][:5], ref[~ok][:5])
-    assert (ref > 0).mean() > 0.03
+    assert (ref > 0).mean() > 0.02  # targets deep in the needle ball are mostly hidden
 
 
 def test_edge_cases(ctx, orc, torch):
@@ -273,5 +274,14 @@ def test_render_parity_mixed(ctx, orc, torch):
     _say("render parity mixed_100k 128x128 4 spp depth 8")
     sc = scenes.mixed_100k()
     frac, d, se = _image_parity(ctx, orc, sc, "mixed_100k", 4, 8, 1, res=(128, 128))
+    assert frac < 0.01
+    assert d <= 3 * se + 1e-6
+
+
+def test_render_parity_needles(ctx, orc, torch):
+    # long primitives cut into slabs by the hierarchy, many overlapping
+    _say("render parity needles 96x96 4 spp depth 6")
+    sc = scenes.needles()
+    frac, d, se = _image_parity(ctx, orc, sc, "needles", 4, 6, 4, res=(96, 96))
     assert frac < 0.01
     assert d <= 3 * se + 1e-6
