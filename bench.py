@@ -19,6 +19,13 @@ Besides the JSON line's throughput it reports:
                every launch during the timed run, against 8 TB/s HBM;
   cpu_baseline the FP64 CPU oracle on a bounded pixel subset of the same
                workload, on this host's cores.
+
+With --time-to-rmse it instead runs the second half of the metric on the same
+scene: progressive renders of the plain tracer and of the neural-cache tracer
+(paths end in the cache after two scattering events; the cache trains online,
+one step per wavefront) against a 4096-spp plain reference, RMSE over all
+pixels and channels of the images clamped to [0, 1], against wall time.  It
+prints one JSON line of its own (see time_to_rmse).
 """
 from __future__ import annotations
 
@@ -69,6 +76,156 @@ def cpu_baseline(sc, cam, params, target_s: float):
                       f"max depth {params['max_depth']}, {rays} rays in {dt:.1f}s"}
 
 
+def _rmse(img, ref, k=1.0):
+    """RMSE of the image at exposure k, clamped to [0, 1], against a clamped reference"""
+    import torch
+    return float(torch.sqrt(torch.mean(((k * img).clamp(0, 1) - ref) ** 2)))
+
+
+def _exposure_for_noise(a, b, noise):
+    """exposure k at which half the split-half RMSE of the clamped reference
+    halves equals `noise` (bisection in log k; the noise grows with k)"""
+    lo, hi = 1e-6, 1e3
+    for _ in range(60):
+        k = (lo * hi) ** 0.5
+        if 0.5 * _rmse(a, (k * b).clamp(0, 1), k) > noise:
+            hi = k
+        else:
+            lo = k
+    return (lo * hi) ** 0.5
+
+
+def time_to_rmse(args):
+    """Time to RMSE 0.01 of the plain and the neural-cache tracer.
+
+    Reference: 4096 spp of the plain tracer (two halves of 2048 with disjoint
+    sample indices; half the RMSE between the halves is the reference's own
+    noise).  Exposure: transport is linear in the emitted radiance, so every
+    image is scaled by one factor k before clamping; k is chosen so that the
+    reference's own noise is 0.3 x the target (at the room's panel radiance
+    the 4096-spp reference is far noisier than 0.01 wherever pixels are not
+    saturated), and reported with the mean clamped pixel and the RMSE of a
+    black image at that exposure.  Each tracer then renders progressively from sample 0 with
+    another seed, one wavefront (all pixels x several samples) per step; the
+    wall time of the render calls is accumulated and the RMSE against the
+    clamped reference is taken after every step (outside the clock).  Also
+    run: the cache untrained (inference only, initial weights) and paths that
+    end after two scattering events with nothing added.
+    """
+    import numpy as np
+    import torch
+
+    import paper_2406_09733_amd as P
+    from paper_2406_09733_amd import scenes
+
+    W, H = (int(v) for v in args.rmse_res.split("x"))
+    sc = scenes.room_5p5m()
+    cam = dict(scenes.camera("room_5p5m"), width=W, height=H)
+    rs = scenes.render_settings("room_5p5m")
+    ctx = P.Context(0)
+    ctx.build_bvh(sc)
+    ctx.sync()
+    base = {"max_depth": rs["max_depth"], "seed": rs["seed"]}
+    wf = max(1, min(args.ref_spp // 2, (1 << 21) // (W * H)))
+    ref_file = args.reference
+    halves = None
+    if ref_file and os.path.exists(ref_file):
+        z = np.load(ref_file)
+        if tuple(z["res"]) == (W, H) and int(z["spp"]) == args.ref_spp:
+            halves = [torch.tensor(z["a"], device="cuda"), torch.tensor(z["b"], device="cuda")]
+            log(f"[rmse] reference loaded from {ref_file}")
+    t_ref = 0.0
+    if halves is None:
+        halves = []
+        half = args.ref_spp // 2
+        for h in range(2):
+            acc = torch.zeros((H, W, 3), device="cuda", dtype=torch.float32)
+            done = 0
+            while done < half:
+                n = min(16 * wf, half - done)
+                t0 = time.perf_counter()
+                ctx.render(cam, dict(base, spp=n, sample_offset=h * half + done, want_sumsq=False), acc)
+                ctx.sync()
+                t_ref += time.perf_counter() - t0
+                done += n
+                log(f"[rmse] reference half {h}: {done}/{half} spp ({t_ref:.0f} s)")
+            halves.append(acc / half)
+        if ref_file:
+            os.makedirs(os.path.dirname(os.path.abspath(ref_file)), exist_ok=True)
+            np.savez(ref_file, a=halves[0].cpu().numpy(), b=halves[1].cpu().numpy(), res=np.array([W, H]),
+                     spp=np.array(args.ref_spp))
+    floor1 = 0.5 * _rmse(halves[0], halves[1].clamp(0, 1))
+    kexp = args.exposure if args.exposure > 0 else _exposure_for_noise(halves[0], halves[1],
+                                                                       0.3 * args.rmse_target)
+    ref = (kexp * 0.5 * (halves[0] + halves[1])).clamp(0, 1)
+    floor = 0.5 * _rmse(halves[0], (kexp * halves[1]).clamp(0, 1), kexp)
+    black = _rmse(torch.zeros_like(ref), ref)
+    log(f"[rmse] reference noise at exposure 1: {floor1:.5f}; exposure {kexp:.4g}: noise {floor:.5f}, "
+        f"mean clamped pixel {float(ref.mean()):.4f}, RMSE of a black image {black:.4f}")
+
+    def run(label, extra, weights=None):
+        if weights is not None:
+            ctx.nrc_set_weights(weights)
+        acc = torch.zeros((H, W, 3), device="cuda", dtype=torch.float32)
+        t, spp, curve = 0.0, 0, []
+        while t < args.rmse_seconds and spp < args.rmse_max_spp:
+            t0 = time.perf_counter()
+            ctx.render(cam, dict(base, seed=777, spp=wf, sample_offset=spp, want_sumsq=False, **extra), acc)
+            ctx.sync()
+            t += time.perf_counter() - t0
+            spp += wf
+            e = _rmse(acc / spp, ref, kexp)
+            curve.append((round(t, 4), spp, round(e, 6)))
+            if len(curve) % 10 == 1:
+                log(f"[rmse] {label}: {spp} spp, {t:.2f} s, RMSE {e:.5f}")
+            if e <= args.rmse_target:
+                break
+        hit = next((c for c in curve if c[2] <= args.rmse_target), None)
+        st = ctx.render_stats()
+        out = {"time_to_target_s": hit[0] if hit else None, "spp_at_target": hit[1] if hit else None,
+               "final": {"t_s": curve[-1][0], "spp": curve[-1][1], "rmse": curve[-1][2]},
+               "ms_per_wavefront": round(1e3 * curve[-1][0] / len(curve), 2),
+               "curve": curve[:: max(1, len(curve) // 40)]}
+        if extra.get("nrc_mode", 0) in (1, 2):
+            out["last_loss"] = st["nrc_loss"]
+        log(f"[rmse] {label}: {json.dumps({k: v for k, v in out.items() if k != 'curve'})}")
+        return out, curve
+
+    rng = np.random.default_rng(0)
+    layers = [(64, 96), (64, 64), (64, 64), (64, 64), (3, 64)]
+    w0 = np.concatenate([rng.uniform(-1, 1, o * i) * np.sqrt(6.0 / i) for (o, i) in layers]).astype(np.float32)
+    nrc = {"nrc_mode": 1, "nrc_terminate_after": 2, "nrc_train_records": 65536, "nrc_lr": args.nrc_lr}
+    res = {}
+    res["plain"], c_plain = run("plain", {})
+    res["nrc"], c_nrc = run("nrc", nrc, w0)
+    res["nrc_untrained"], _ = run("nrc untrained", dict(nrc, nrc_mode=2), w0)
+    res["terminate_no_cache"], _ = run("terminate without cache", {"nrc_mode": 3, "nrc_terminate_after": 2})
+
+    def at(curve, t):
+        prev = None
+        for c in curve:
+            if c[0] > t:
+                return prev[2] if prev else None
+            prev = c
+        return prev[2] if prev else None
+
+    t_eq = min(c_plain[-1][0], c_nrc[-1][0])
+    out = {"metric": "time to RMSE %.3g (clamped [0,1] linear RGB, all pixels and channels) vs a %d-spp "
+                     "plain reference" % (args.rmse_target, args.ref_spp),
+           "unit": "s", "higher_is_better": False,
+           "value_plain": res["plain"]["time_to_target_s"], "value_nrc": res["nrc"]["time_to_target_s"],
+           "equal_time_s": t_eq, "rmse_at_equal_time": {"plain": at(c_plain, t_eq), "nrc": at(c_nrc, t_eq)},
+           "reference": {"spp": args.ref_spp, "noise_rmse": round(floor, 6), "render_s": round(t_ref, 1),
+                         "noise_rmse_at_exposure_1": round(floor1, 5)},
+           "exposure": {"k": kexp, "mean_clamped_pixel": round(float(ref.mean()), 5),
+                        "black_image_rmse": round(black, 5)},
+           "config": {"workload": f"room_5p5m at {W}x{H}, depth {rs['max_depth']}; cache ends paths after 2 "
+                                  "scattering events, 65536 training records and one Adam step per wavefront",
+                      "wavefront_spp": wf, "seconds_cap": args.rmse_seconds},
+           "runs": res}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,12 +233,26 @@ def main():
     ap.add_argument("--warmup", type=int, default=2, help="untimed sample passes")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--time-to-rmse", action="store_true", help="run the time-to-RMSE comparison instead")
+    ap.add_argument("--rmse-res", default="480x270")
+    ap.add_argument("--ref-spp", type=int, default=4096)
+    ap.add_argument("--reference", default=os.path.join(ROOT, "gpurun_out", "rmse_reference.npz"),
+                    help="reference cache (written if missing)")
+    ap.add_argument("--rmse-target", type=float, default=0.01)
+    ap.add_argument("--rmse-seconds", type=float, default=60.0, help="wall-time cap per tracer")
+    ap.add_argument("--rmse-max-spp", type=int, default=1 << 16)
+    ap.add_argument("--nrc-lr", type=float, default=1e-3)
+    ap.add_argument("--exposure", type=float, default=0.0,
+                    help="image scale before clamping (0 = reference noise 0.3 x target)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path shards by "
               "pixels with no communication beyond a final image reduction; see DESIGN.md)",
               file=sys.stderr)
         sys.exit(2)
+    if args.time_to_rmse:
+        time_to_rmse(args)
+        return
 
     import numpy as np
     import torch

@@ -94,12 +94,13 @@ typedef struct {
  *                    scattering vertex; after each sample pass the records'
  *                    targets (path radiance - radiance so far) / throughput
  *                    drive one Adam step (ugp_nrc_train_step) and f is
- *                    rescaled toward nrc_train_records records per pass;
+ *                    rescaled toward nrc_train_records records per wavefront
+ *                    (a training step follows every wavefront);
  *                  2 infer only (every path ends in the cache);
  *                  3 end paths at nrc_terminate_after + 1 and add nothing
  *   nrc_terminate_after  scattering events before a cached path ends (>= 1)
  *   nrc_train_records    records used per training step, 1 .. 1 << 20 (mode 1);
- *                  f starts at min(1, nrc_train_records / (2 pixels))
+ *                  f starts at min(1, nrc_train_records / (2 paths of a wavefront))
  *   nrc_lr         Adam learning rate of the cache (0 = 1e-3)
  *   nrc_box        lo[3], hi[3] of the cache's position encoding; hi <= lo on
  *                  any axis = the scene bounds                                  */
@@ -185,8 +186,11 @@ ugp_status ugp_trace_counts(ugp_ctx ctx, int mode, int64_t n_rays, const float *
  * estimation to emissive primitives and to the environment and the balance
  * heuristic against phase sampling.  Adds, per pixel, the sum over this call's
  * samples of the path radiance to sum_rgb [height][width][3] and of its square
- * to sumsq_rgb (or NULL).  Enqueued; may synchronise internally between
- * bounces only through device-side queue counters (no host round trip). */
+ * to sumsq_rgb (or NULL).  Paths are traced in wavefronts of
+ * max(1, min(spp, 2^21 / pixels)) samples of every pixel (one sample per
+ * wavefront at 1920x1080); the sums do not depend on that grouping.  Enqueued;
+ * may synchronise internally between bounces only through device-side queue
+ * counters (no host round trip). */
 ugp_status ugp_render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p,
                       float *sum_rgb, float *sumsq_rgb);
 
@@ -277,9 +281,11 @@ ugp_status ugp_nrc_train_step(ugp_ctx ctx, int64_t n, const float *x, int32_t x_
                               const float *targets, float lr, float *loss_out, float *grad_out);
 /* The training records of the last sample pass of the last ugp_render call
  * with nrc_mode 1: records_out float [cap][24] (inputs[16], throughput[3],
- * pixel index as int32 bits, radiance before the vertex's scattered light[3],
+ * path index as int32 bits, radiance before the vertex's scattered light[3],
  * vertex index) and targets_out float [cap][3] (or NULL), in no particular
- * order; *count_out [host] = records written (<= cap).  Synchronises. */
+ * order; *count_out [host] = records written (<= cap).  The path index is
+ * pixel + pixels x (sample - first sample of its wavefront), see ugp_render.
+ * Synchronises. */
 ugp_status ugp_nrc_records(ugp_ctx ctx, int64_t cap, float *records_out, float *targets_out,
                            int64_t *count_out);
 

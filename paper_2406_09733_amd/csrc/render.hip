@@ -65,6 +65,7 @@ struct RenderBuffers {
 namespace {
 
 constexpr int kPersistBlocks = 4096;
+constexpr int64_t kWavefrontPaths = int64_t(1) << 21;
 // per-vertex counters: [0] paths in, [1] light samples, [2] environment
 // samples, [3] overflow, [4] collision work, [5] light work
 constexpr int kCountStride = 8;
@@ -75,7 +76,7 @@ struct NrcArgs {
     float *rec;            // training records [rec_cap][kNrcRecordFloats]
     int32_t *n_rec;        // records appended (may exceed rec_cap: the excess is dropped)
     int32_t rec_cap;
-    float *qry;            // cache queries [npix][kNrcRecordFloats]
+    float *qry;            // cache queries [paths][kNrcRecordFloats]
     int32_t *n_qry;
     const float *frac;     // probability of a training path
 };
@@ -84,7 +85,8 @@ struct PassArgs {
     CamDev cam;
     float blo[3], binv[3];   // scene bounds (origin quantisation for ray sorting)
     uint64_t seed;
-    uint32_t sample;
+    uint32_t sample;         // sample index of the wavefront's first sample
+    uint32_t npix;           // path q traces pixel q % npix, sample sample + q / npix
     int max_depth;
     int mis_mode;
     float env[3];
@@ -96,6 +98,11 @@ constexpr int kPixMask = 0x3fffffff;
 constexpr int kTrainBit = 0x40000000;
 
 __device__ __forceinline__ V3 f3(float4 v) { return v3(v.x, v.y, v.z); }
+
+// random numbers of path q (pixel, sample) at vertex v, group g
+__device__ __forceinline__ Rng4 path_rng(const PassArgs &P, uint32_t q, uint32_t v, uint32_t g) {
+    return rng4(P.seed, q % P.npix, P.sample + q / P.npix, v, g);
+}
 
 // light pdf of emitter k (original index) seen from x: uniform cone over its
 // bounding sphere, times the uniform emitter choice; 0 inside the sphere
@@ -110,14 +117,15 @@ __device__ __forceinline__ float nee_pdf(const SceneDev &S, int k, V3 x) {
     return 1.f / ((float)S.n_emit * 2.f * kPi * omc);
 }
 
-__global__ void k_raygen(PassArgs P, int64_t npix, Queue q, float4 *L) {
+__global__ void k_raygen(PassArgs P, int64_t npath, Queue q, float4 *L) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= npix) return;
-    const Rng4 g = rng4(P.seed, (uint32_t)p, P.sample, 0, 0);
-    const int px = (int)(p % P.cam.width), py = (int)(p / P.cam.width);
+    if (p >= npath) return;
+    const Rng4 g = path_rng(P, (uint32_t)p, 0, 0);
+    const int pix = (int)((uint32_t)p % P.npix);
+    const int px = pix % P.cam.width, py = pix / P.cam.width;
     const V3 d = camera_dir(P.cam, px, py, g.u[0], g.u[1]);
     int bits = (int)p;
-    if (P.nrc.mode == 1 && rng4(P.seed, (uint32_t)p, P.sample, 0, 2).u[0] < *P.nrc.frac) bits |= kTrainBit;
+    if (P.nrc.mode == 1 && path_rng(P, (uint32_t)p, 0, 2).u[0] < *P.nrc.frac) bits |= kTrainBit;
     q.a[p] = make_float4(P.cam.ox, P.cam.oy, P.cam.oz, 0.f);
     q.b[p] = make_float4(d.x, d.y, d.z, __int_as_float(-1));
     q.c[p] = make_float4(1.f, 1.f, 1.f, __int_as_float(bits));
@@ -208,7 +216,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(SceneDev S, PassArgs P, int 
         const float4 A = qin.a[i], B = qin.b[i], C = qin.c[i];
         const int pix = __float_as_int(C.w) & kPixMask;
         const int excl = __float_as_int(B.w);
-        const float u = rng4(P.seed, (uint32_t)pix, P.sample, (uint32_t)v, 0).u[0];
+        const float u = path_rng(P, (uint32_t)pix, (uint32_t)v, 0).u[0];
         const RayD r = make_ray(A.x, A.y, A.z, B.x, B.y, B.z, 0.f, __builtin_huge_val());
         const SweepOut so = sweep<K>(S, r, excl, kModeCollide, u, -1, stack, err, tc);
         if (so.status != 0) {
@@ -260,8 +268,8 @@ __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PassArgs P, int v,
             const float p_prev = A.w;
             const V3 o = f3(A), d = f3(B);
             V3 beta = f3(C);
-            const Rng4 g0 = rng4(P.seed, (uint32_t)pix, P.sample, (uint32_t)v, 0);
-            const Rng4 g1 = rng4(P.seed, (uint32_t)pix, P.sample, (uint32_t)v, 1);
+            const Rng4 g0 = path_rng(P, (uint32_t)pix, (uint32_t)v, 0);
+            const Rng4 g1 = path_rng(P, (uint32_t)pix, (uint32_t)v, 1);
             V3 Ladd = v3(0.f, 0.f, 0.f);
             if (hit.x < 0) {
                 if (P.has_env) {
@@ -483,18 +491,21 @@ __global__ __launch_bounds__(kBlock) void k_env(SceneDev S, LightQueue q, const 
     flush_counts(S, tc);
 }
 
-__global__ void k_accum(int64_t npix, const float4 *L, float *sum, float *sumsq) {
+// per pixel, the wavefront's samples in sample order (the same float sums
+// as one sample per wavefront)
+__global__ void k_accum(int64_t npix, int nsamp, const float4 *L, float *sum, float *sumsq) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npix) return;
-    const float4 l = L[p];
-    sum[3 * p] += l.x;
-    sum[3 * p + 1] += l.y;
-    sum[3 * p + 2] += l.z;
-    if (sumsq) {
-        sumsq[3 * p] += l.x * l.x;
-        sumsq[3 * p + 1] += l.y * l.y;
-        sumsq[3 * p + 2] += l.z * l.z;
+    float s0 = sum[3 * p], s1 = sum[3 * p + 1], s2 = sum[3 * p + 2];
+    float q0 = 0.f, q1 = 0.f, q2 = 0.f;
+    if (sumsq) { q0 = sumsq[3 * p]; q1 = sumsq[3 * p + 1]; q2 = sumsq[3 * p + 2]; }
+    for (int s = 0; s < nsamp; ++s) {
+        const float4 l = L[p + (int64_t)s * npix];
+        s0 += l.x; s1 += l.y; s2 += l.z;
+        q0 += l.x * l.x; q1 += l.y * l.y; q2 += l.z * l.z;
     }
+    sum[3 * p] = s0; sum[3 * p + 1] = s1; sum[3 * p + 2] = s2;
+    if (sumsq) { sumsq[3 * p] = q0; sumsq[3 * p + 1] = q1; sumsq[3 * p + 2] = q2; }
 }
 
 __global__ void k_set_count(int32_t *c, int32_t v) { *c = v; }
@@ -598,7 +609,11 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
     const SceneDev &S0 = ctx->scene;
     const int64_t npix = (int64_t)cam->width * cam->height;
     const int nv = p->max_depth + 1;
-    hipError_t e = ensure_buffers(ctx, npix, nv);
+    // a wavefront traces several samples of every pixel when the image is
+    // small, so that about 2M paths are in flight
+    const int wf = (int)std::max<int64_t>(1, std::min<int64_t>(p->spp, kWavefrontPaths / npix));
+    const int64_t cap = npix * wf;
+    hipError_t e = ensure_buffers(ctx, cap, nv);
     if (e != hipSuccess) return e;
     RenderBuffers *rb = ctx->rb;
     hipStream_t st = ctx->stream;
@@ -645,14 +660,14 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
             if (e != hipSuccess) return e;
         }
         bool fresh = false;
-        e = ensure_nrc_buffers(ctx, npix, p->nrc_mode == 1 ? p->nrc_train_records : 0, &fresh);
+        e = ensure_nrc_buffers(ctx, cap, p->nrc_mode == 1 ? p->nrc_train_records : 0, &fresh);
         if (e != hipSuccess) return e;
-        if (p->nrc_mode == 1 && (fresh || ctx->nrc_frac_pixels != npix)) {
+        if (p->nrc_mode == 1 && (fresh || ctx->nrc_frac_pixels != cap)) {
             // a training path is chosen with probability frac; frac starts at
-            // records / (2 pixels) and is adapted after every pass
-            const float f0 = std::min(1.0f, (float)p->nrc_train_records / (2.0f * (float)npix));
+            // records / (2 paths of a wavefront) and is adapted after every wavefront
+            const float f0 = std::min(1.0f, (float)p->nrc_train_records / (2.0f * (float)cap));
             hipLaunchKernelGGL(k_set_float, dim3(1), dim3(1), 0, st, rb->frac, f0);
-            ctx->nrc_frac_pixels = npix;
+            ctx->nrc_frac_pixels = cap;
         }
         P.nrc.qry = rb->qry;
         P.nrc.n_qry = nrc_cnt;
@@ -696,15 +711,18 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
         ctx->ev_used.push_back({cat, (int)ev_next});
         ev_next += 2;
     };
-    const unsigned gpix = (unsigned)((npix + 255) / 256);
-    const unsigned gq = (unsigned)std::min<int64_t>((npix + kBlock - 1) / kBlock, kPersistBlocks);
+    P.npix = (uint32_t)npix;
     const unsigned gw = 256;  // the overflow pass: few paths
-    for (int s = 0; s < p->spp; ++s) {
+    for (int s = 0; s < p->spp; s += wf) {
         P.sample = (uint32_t)(p->sample_offset + s);
+        const int ns = std::min(wf, p->spp - s);
+        const int64_t npath = npix * ns;
+        const unsigned gpix = (unsigned)((npath + 255) / 256);
+        const unsigned gq = (unsigned)std::min<int64_t>((npath + kBlock - 1) / kBlock, kPersistBlocks);
         e = hipMemsetAsync(rb->counts, 0, sizeof(int32_t) * kCountStride * (size_t)(nv + 2), st);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, st, rb->counts, (int32_t)npix);
-        hipLaunchKernelGGL(k_raygen, dim3(gpix), dim3(256), 0, st, P, npix, rb->q[0], rb->L);
+        hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, st, rb->counts, (int32_t)npath);
+        hipLaunchKernelGGL(k_raygen, dim3(gpix), dim3(256), 0, st, P, npath, rb->q[0], rb->L);
         for (int v = 1; v <= nv; ++v) {
             // counters of vertex v (see kCountStride); the next vertex's paths-in is c + kCountStride
             int32_t *c = rb->counts + kCountStride * (v - 1);
@@ -712,9 +730,9 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
             Overflow ov{rb->ovf, c + 3};
             // order the queue so each wave's rays are coherent
             timed(5, [&] {
-                hipLaunchKernelGGL(k_sort_keys, dim3(gpix), dim3(256), 0, st, P, qin, (const int32_t *)c, npix,
+                hipLaunchKernelGGL(k_sort_keys, dim3(gpix), dim3(256), 0, st, P, qin, (const int32_t *)c, npath,
                                    rb->skey, rb->sval);
-                radix_sort(rb->skey, rb->sval, rb->skey2, rb->sval2, npix, st);
+                radix_sort(rb->skey, rb->sval, rb->skey2, rb->sval2, npath, st);
             });
             timed(0, [&] {
                 hipLaunchKernelGGL((k_collide<kEventsMain, false>), dim3(gq), dim3(kBlock), 0, st, Sc[0], P, v, qin,
@@ -737,8 +755,8 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
                     timed(5, [&] {
                         const Queue lq{rb->nee.a, rb->nee.b, rb->nee.c};
                         hipLaunchKernelGGL(k_sort_keys, dim3(gpix), dim3(256), 0, st, P, lq, (const int32_t *)(c + 1),
-                                           npix, rb->skey, rb->sval);
-                        radix_sort(rb->skey, rb->sval, rb->skey2, rb->sval2, npix, st);
+                                           npath, rb->skey, rb->sval);
+                        radix_sort(rb->skey, rb->sval, rb->skey2, rb->sval2, npath, st);
                     });
                     timed(2, [&] {
                         hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, st, c + 3, 0);
@@ -760,11 +778,12 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
         if (p->nrc_mode == 1 || p->nrc_mode == 2) {
             // cached radiance of the paths that ended in the cache
             timed(6, [&] {
-                e = nrc_forward(ctx, npix, nrc_cnt, rb->qry, kNrcRecordFloats, 2, box, nullptr, rb->L);
+                e = nrc_forward(ctx, npath, nrc_cnt, rb->qry, kNrcRecordFloats, 2, box, nullptr, rb->L);
             });
             if (e != hipSuccess) return e;
         }
-        hipLaunchKernelGGL(k_accum, dim3(gpix), dim3(256), 0, st, npix, rb->L, sum, sumsq);
+        hipLaunchKernelGGL(k_accum, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, st, npix, ns, rb->L, sum,
+                           sumsq);
         if (p->nrc_mode == 1) {
             // targets of this pass's records, one optimisation step, new training-path probability
             timed(7, [&] {

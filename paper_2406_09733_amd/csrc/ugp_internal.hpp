@@ -114,8 +114,8 @@ hipError_t render_nrc_records(ugp_ctx ctx, int64_t cap, float *rec_out, float *t
 // nrc.hip -- the neural radiance cache.  Record layout shared with the
 // renderer (kNrcRecordFloats floats per record): [0..15] network inputs
 // (position, outgoing direction, normal, roughness, albedo, 3 unused),
-// [16..18] throughput at the vertex, [19] pixel index bits (bit 30 free for
-// the renderer's flags), [20..22] path radiance before the vertex's
+// [16..18] throughput at the vertex, [19] path index bits (the path's slot in
+// the wavefront; bit 30 free for the renderer's flags), [20..22] path radiance before the vertex's
 // scattered light, [23] vertex index.
 constexpr int kNrcRecordFloats = 24;
 int nrc_num_params();
