@@ -14,9 +14,13 @@ paper_2406_09733_amd/scenes.py); inputs are resident in HBM before timing.
 Besides the JSON line's throughput it reports:
   roofline     the dominant kernel (the collision kernel): algorithmic bytes
                per launch (4-wide BVH node records 128 B, primitive records 64 B,
-               re-read records 64 B, path-queue records 96 B per ray) divided
-               by its mean launch duration from HIP events recorded around
-               every launch during the timed run, against 8 TB/s HBM;
+               re-read records 64 B; per ray the 48-B path record, its 4-B sort
+               index and the 8-B hit record) divided by its mean launch
+               duration from HIP events recorded around every launch during
+               the timed run, against 8 TB/s HBM; `traffic` is the HBM bytes
+               per launch measured with rocprofv3 counters (the summary under
+               profiles/), reported only while the kernel sources still hash
+               to the value recorded there;
   cpu_baseline the FP64 CPU oracle on a bounded pixel subset of the same
                workload, on this host's cores.
 
@@ -41,11 +45,33 @@ if ROOT not in sys.path:
 
 METRIC = "Mrays/s at 5.5M prims; time-to-RMSE 0.01, plain vs neural-cache tracer"
 HBM_PEAK_GBS = 8000.0
-NODE_B, PRIM_B, PATH_B = 128, 64, 96
+NODE_B, PRIM_B, PATH_B = 128, 64, 60
+COUNTERS = os.path.join(ROOT, "profiles", "k_collide_room_5p5m_hbm_counters.md")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def measured_traffic():
+    """HBM bytes per k_collide launch from the committed counter summary, or
+    None when the kernel sources changed since the counters were taken."""
+    import glob
+    import hashlib
+    import re
+    if not os.path.exists(COUNTERS):
+        return None
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2406_09733_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    text = open(COUNTERS).read()
+    m1 = re.search(r"kernel_sources_sha256: ([0-9a-f]+)", text)
+    m2 = re.search(r"traffic_bytes_per_launch: ([0-9.e+]+)", text)
+    if not (m1 and m2) or m1.group(1) != h.hexdigest():
+        return None
+    return float(m2.group(1))
 
 
 def cpu_baseline(sc, cam, params, target_s: float):
@@ -226,6 +252,19 @@ def time_to_rmse(args):
     print(json.dumps(out), flush=True)
 
 
+def copy_probe(nbytes: int):
+    """A plain device copy of nbytes (three launches), the known-size kernel
+    against which HBM byte counters are scaled."""
+    import torch
+    n = nbytes // 4
+    a = torch.ones(n, device="cuda", dtype=torch.float32)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": 3}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -242,6 +281,8 @@ def main():
     ap.add_argument("--rmse-seconds", type=float, default=60.0, help="wall-time cap per tracer")
     ap.add_argument("--rmse-max-spp", type=int, default=1 << 16)
     ap.add_argument("--nrc-lr", type=float, default=1e-3)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a device copy of BYTES (counter calibration) and exit")
     ap.add_argument("--exposure", type=float, default=0.0,
                     help="image scale before clamping (0 = reference noise 0.3 x target)")
     args = ap.parse_args()
@@ -250,6 +291,9 @@ def main():
               "pixels with no communication beyond a final image reduction; see DESIGN.md)",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.time_to_rmse:
         time_to_rmse(args)
         return
@@ -315,8 +359,11 @@ def main():
 
     launches = max(st["launches_collide"], 1)
     achieved = (bytes_per_coll_ray * st["collision_rays"] / launches) / (st["ms_collide"] / launches * 1e-3) / 1e9
+    traffic = measured_traffic()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else round(traffic / 1e9, 3),
+                "traffic_unit": "GB per launch",
                 "kernel": "k_collide (main)", "bytes_per_ray": round(bytes_per_coll_ray, 1),
                 "nodes_per_ray": round(cnt["cat_nodes"][0] / coll_rays_c, 2),
                 "prims_per_ray": round(cnt["cat_prims"][0] / coll_rays_c, 2),
