@@ -220,12 +220,41 @@ def time_to_rmse(args):
     rng = np.random.default_rng(0)
     layers = [(64, 96), (64, 64), (64, 64), (64, 64), (3, 64)]
     w0 = np.concatenate([rng.uniform(-1, 1, o * i) * np.sqrt(6.0 / i) for (o, i) in layers]).astype(np.float32)
-    nrc = {"nrc_mode": 1, "nrc_terminate_after": 2, "nrc_train_records": 65536, "nrc_lr": args.nrc_lr}
+    nrc = {"nrc_mode": 1, "nrc_terminate_after": 2, "nrc_train_records": 65536, "nrc_lr": args.nrc_lr,
+           "nrc_train_steps": args.nrc_steps, "nrc_target_clamp": args.nrc_clamp}
+    runs = args.runs.split(",")
     res = {}
-    res["plain"], c_plain = run("plain", {})
-    res["nrc"], c_nrc = run("nrc", nrc, w0)
-    res["nrc_untrained"], _ = run("nrc untrained", dict(nrc, nrc_mode=2), w0)
-    res["terminate_no_cache"], _ = run("terminate without cache", {"nrc_mode": 3, "nrc_terminate_after": 2})
+    c_plain = c_nrc = None
+    if "plain" in runs:
+        res["plain"], c_plain = run("plain", {})
+    if "nrc" in runs:
+        res["nrc"], c_nrc = run("nrc", nrc, w0)
+        # the trained cache alone: inference only, weights frozen after training
+        if args.frozen_spp > 0:
+            acc = torch.zeros((H, W, 3), device="cuda", dtype=torch.float32)
+            ctx.render(cam, dict(base, seed=991, spp=args.frozen_spp, want_sumsq=False, **dict(nrc, nrc_mode=2)),
+                       acc)
+            ctx.sync()
+            res["nrc"]["frozen_rmse"] = {"spp": args.frozen_spp, "rmse": round(_rmse(acc / args.frozen_spp, ref,
+                                                                                    kexp), 6)}
+            log(f"[rmse] trained cache, inference only, {args.frozen_spp} spp: {res['nrc']['frozen_rmse']}")
+    for extra in args.nrc_variants.split(";") if args.nrc_variants else []:
+        kv = dict(x.split("=") for x in extra.split(","))
+        cfg = dict(nrc, nrc_lr=float(kv.get("lr", args.nrc_lr)), nrc_train_steps=int(kv.get("steps", 1)),
+                   nrc_target_clamp=float(kv.get("clamp", 0.0)))
+        res["nrc " + extra], _ = run("nrc " + extra, cfg, w0)
+    if "nrc_untrained" in runs:
+        res["nrc_untrained"], _ = run("nrc untrained", dict(nrc, nrc_mode=2), w0)
+    if "terminate" in runs:
+        res["terminate_no_cache"], c_term = run("terminate without cache", {"nrc_mode": 3, "nrc_terminate_after": 2})
+        if args.frozen_spp > 0:
+            acc = torch.zeros((H, W, 3), device="cuda", dtype=torch.float32)
+            ctx.render(cam, dict(base, seed=991, spp=args.frozen_spp, want_sumsq=False, nrc_mode=3,
+                                 nrc_terminate_after=2), acc)
+            ctx.sync()
+            res["terminate_no_cache"]["frozen_rmse"] = {"spp": args.frozen_spp,
+                                                        "rmse": round(_rmse(acc / args.frozen_spp, ref, kexp), 6)}
+            log(f"[rmse] termination without cache, {args.frozen_spp} spp: {res['terminate_no_cache']['frozen_rmse']}")
 
     def at(curve, t):
         prev = None
@@ -235,19 +264,22 @@ def time_to_rmse(args):
             prev = c
         return prev[2] if prev else None
 
-    t_eq = min(c_plain[-1][0], c_nrc[-1][0])
+    t_eq = min(c_plain[-1][0], c_nrc[-1][0]) if c_plain and c_nrc else None
     out = {"metric": "time to RMSE %.3g (clamped [0,1] linear RGB, all pixels and channels) vs a %d-spp "
                      "plain reference" % (args.rmse_target, args.ref_spp),
            "unit": "s", "higher_is_better": False,
-           "value_plain": res["plain"]["time_to_target_s"], "value_nrc": res["nrc"]["time_to_target_s"],
-           "equal_time_s": t_eq, "rmse_at_equal_time": {"plain": at(c_plain, t_eq), "nrc": at(c_nrc, t_eq)},
+           "value_plain": res.get("plain", {}).get("time_to_target_s"),
+           "value_nrc": res.get("nrc", {}).get("time_to_target_s"),
+           "equal_time_s": t_eq,
+           "rmse_at_equal_time": {"plain": at(c_plain, t_eq), "nrc": at(c_nrc, t_eq)} if t_eq else None,
            "reference": {"spp": args.ref_spp, "noise_rmse": round(floor, 6), "render_s": round(t_ref, 1),
                          "noise_rmse_at_exposure_1": round(floor1, 5)},
            "exposure": {"k": kexp, "mean_clamped_pixel": round(float(ref.mean()), 5),
                         "black_image_rmse": round(black, 5)},
            "config": {"workload": f"room_5p5m at {W}x{H}, depth {rs['max_depth']}; cache ends paths after 2 "
-                                  "scattering events, 65536 training records and one Adam step per wavefront",
-                      "wavefront_spp": wf, "seconds_cap": args.rmse_seconds},
+                                  "scattering events, 65536 training records per chunk of samples",
+                      "spp_per_call": wf, "seconds_cap": args.rmse_seconds,
+                      "nrc": {k: v for k, v in nrc.items()}},
            "runs": res}
     print(json.dumps(out), flush=True)
 
@@ -280,7 +312,13 @@ def main():
     ap.add_argument("--rmse-target", type=float, default=0.01)
     ap.add_argument("--rmse-seconds", type=float, default=60.0, help="wall-time cap per tracer")
     ap.add_argument("--rmse-max-spp", type=int, default=1 << 16)
-    ap.add_argument("--nrc-lr", type=float, default=1e-3)
+    ap.add_argument("--nrc-lr", type=float, default=1e-2)
+    ap.add_argument("--nrc-steps", type=int, default=4, help="Adam steps per chunk")
+    ap.add_argument("--nrc-clamp", type=float, default=20.0, help="training target clamp (radiance units)")
+    ap.add_argument("--nrc-variants", default="", help="extra cache runs: 'lr=..,steps=..,clamp=..;...'")
+    ap.add_argument("--runs", default="plain,nrc,nrc_untrained,terminate")
+    ap.add_argument("--frozen-spp", type=int, default=512,
+                    help="spp of the inference-only renders that measure each cache's bias")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device copy of BYTES (counter calibration) and exit")
     ap.add_argument("--exposure", type=float, default=0.0,

@@ -93,17 +93,25 @@ typedef struct {
  *                    added; training paths run to max_depth and record every
  *                    scattering vertex; after each sample pass the records'
  *                    targets (path radiance - radiance so far) / throughput
- *                    drive one Adam step (ugp_nrc_train_step) and f is
- *                    rescaled toward nrc_train_records records per wavefront
- *                    (a training step follows every wavefront);
+ *                    drive nrc_train_steps Adam steps (as ugp_nrc_train_step)
+ *                    after every chunk of samples (see ugp_render) and f is
+ *                    rescaled toward nrc_train_records records per chunk;
  *                  2 infer only (every path ends in the cache);
  *                  3 end paths at nrc_terminate_after + 1 and add nothing
  *   nrc_terminate_after  scattering events before a cached path ends (>= 1)
  *   nrc_train_records    records used per training step, 1 .. 1 << 20 (mode 1);
- *                  f starts at min(1, nrc_train_records / (2 paths of a wavefront))
- *   nrc_lr         Adam learning rate of the cache (0 = 1e-3)
+ *                  f starts at min(1, nrc_train_records / (2 paths of a chunk))
+ *   nrc_lr         Adam learning rate of the cache (0 = 1e-2)
  *   nrc_box        lo[3], hi[3] of the cache's position encoding; hi <= lo on
- *                  any axis = the scene bounds                                  */
+ *                  any axis = the scene bounds
+ *   nrc_train_steps  Adam steps per chunk, on consecutive batches of the
+ *                  chunk's records (0 = 1)
+ *   nrc_radiance_scale  radiance unit of the network's output (targets are
+ *                  divided by it, predictions multiplied); 0 = keep the
+ *                  current unit, which the first training after
+ *                  ugp_nrc_set_weights sets to the mean of its targets
+ *   nrc_target_clamp  training targets (in that unit) are clamped at this
+ *                  value in the loss (0 = no clamp)                           */
 typedef struct {
     int32_t spp, max_depth;
     uint64_t seed;
@@ -113,6 +121,9 @@ typedef struct {
     int32_t nrc_mode, nrc_terminate_after, nrc_train_records;
     float nrc_lr;
     float nrc_box[6];
+    int32_t nrc_train_steps;
+    float nrc_radiance_scale;
+    float nrc_target_clamp;
 } ugp_render_params;
 
 /* Create a context on `device` that enqueues on `hip_stream` (a hipStream_t;
@@ -186,11 +197,11 @@ ugp_status ugp_trace_counts(ugp_ctx ctx, int mode, int64_t n_rays, const float *
  * estimation to emissive primitives and to the environment and the balance
  * heuristic against phase sampling.  Adds, per pixel, the sum over this call's
  * samples of the path radiance to sum_rgb [height][width][3] and of its square
- * to sumsq_rgb (or NULL).  Paths are traced in wavefronts of
- * max(1, min(spp, 2^21 / pixels)) samples of every pixel (one sample per
- * wavefront at 1920x1080); the sums do not depend on that grouping.  Enqueued;
- * may synchronise internally between bounces only through device-side queue
- * counters (no host round trip). */
+ * to sumsq_rgb (or NULL).  The samples are traced in chunks of
+ * max(1, min(spp, 2^24 / pixels)) samples of every pixel; within a chunk a
+ * pool of about 2M path slots is refilled with new camera paths as paths end.
+ * The sums do not depend on that scheduling.  Synchronises the stream once
+ * per bounce iteration (to read two queue counters). */
 ugp_status ugp_render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p,
                       float *sum_rgb, float *sumsq_rgb);
 
@@ -284,7 +295,7 @@ ugp_status ugp_nrc_train_step(ugp_ctx ctx, int64_t n, const float *x, int32_t x_
  * path index as int32 bits, radiance before the vertex's scattered light[3],
  * vertex index) and targets_out float [cap][3] (or NULL), in no particular
  * order; *count_out [host] = records written (<= cap).  The path index is
- * pixel + pixels x (sample - first sample of its wavefront), see ugp_render.
+ * pixel + pixels x (sample - first sample of its chunk), see ugp_render.
  * Synchronises. */
 ugp_status ugp_nrc_records(ugp_ctx ctx, int64_t cap, float *records_out, float *targets_out,
                            int64_t *count_out);

@@ -44,7 +44,9 @@ class _Params(C.Structure):
     _fields_ = [("spp", C.c_int32), ("max_depth", C.c_int32), ("seed", C.c_uint64),
                 ("sample_offset", C.c_int64), ("env_radiance", C.c_float * 3), ("mis_mode", C.c_int32),
                 ("nrc_mode", C.c_int32), ("nrc_terminate_after", C.c_int32),
-                ("nrc_train_records", C.c_int32), ("nrc_lr", C.c_float), ("nrc_box", C.c_float * 6)]
+                ("nrc_train_records", C.c_int32), ("nrc_lr", C.c_float), ("nrc_box", C.c_float * 6),
+                ("nrc_train_steps", C.c_int32), ("nrc_radiance_scale", C.c_float),
+                ("nrc_target_clamp", C.c_float)]
 
 
 class _Stats(C.Structure):
@@ -262,6 +264,9 @@ class Context:
         box = params.get("nrc_box", None)
         for i in range(6):
             p.nrc_box[i] = 0.0 if box is None else float(box[i])
+        p.nrc_train_steps = int(params.get("nrc_train_steps", 1))
+        p.nrc_radiance_scale = float(params.get("nrc_radiance_scale", 0.0))
+        p.nrc_target_clamp = float(params.get("nrc_target_clamp", 0.0))
         _check("ugp_render", lib().ugp_render(self.h, C.byref(c), C.byref(p), _ptr(sum_rgb), _ptr(sumsq_rgb)))
         return sum_rgb, sumsq_rgb
 

@@ -198,6 +198,9 @@ ugp_status ugp_render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_param
     if (p->nrc_mode == 1 && (p->nrc_train_records < 1 || p->nrc_train_records > (1 << 20)))
         return UGP_ERR_INVALID_ARGUMENT;
     if (!(p->nrc_lr >= 0.f) || !std::isfinite(p->nrc_lr)) return UGP_ERR_INVALID_ARGUMENT;
+    if (p->nrc_train_steps < 0 || p->nrc_train_steps > 64) return UGP_ERR_INVALID_ARGUMENT;
+    if (!(p->nrc_radiance_scale >= 0.f) || !std::isfinite(p->nrc_radiance_scale)) return UGP_ERR_INVALID_ARGUMENT;
+    if (!(p->nrc_target_clamp >= 0.f) || !std::isfinite(p->nrc_target_clamp)) return UGP_ERR_INVALID_ARGUMENT;
     for (int k = 0; k < 6; ++k)
         if (!std::isfinite(p->nrc_box[k])) return UGP_ERR_INVALID_ARGUMENT;
     if (ctx->scene.n == 0) return UGP_ERR_NO_SCENE;

@@ -38,6 +38,8 @@ constexpr int kMOff[5] = {0, 6144, 10240, 14336, 18432};  // master weight offse
 
 struct NrcState {
     float *master = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
+    float *scale = nullptr;    // radiance unit of the network's output (device; <= 0: not set yet)
+    int32_t *bcnt = nullptr;   // per-batch record counts of a render's training steps
     __bf16 *wf = nullptr, *wb = nullptr;
     int step = 0;
     // training buffers for up to cap records
@@ -156,13 +158,14 @@ struct SavePtrs {
 
 // Forward pass over n records.  MODE 0: raw inputs (16 floats at src + stride
 // * r) encoded here, y[n][3] written; MODE 1: features [n][96] given, y
-// written; MODE 2: raw inputs as MODE 0 followed by a weight (rgb) and pixel
-// (int bits) at floats 16..19 of the record -- the prediction, clamped at 0
-// and times the weight, is added to L[pixel] (one record per pixel).
+// written; MODE 2: raw inputs as MODE 0 followed by a weight (rgb) and path
+// index (int bits) at floats 16..19 of the record -- the prediction, clamped
+// at 0, times the radiance unit *scale (1 if unset) and the weight, is added
+// to L[path] (one record per path).
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_nrc_forward(int64_t n_host, const int32_t *n_dev, const float *src,
                                                           int stride, EncodeBox box, const __bf16 *wf, float *y,
-                                                          float4 *L, SavePtrs save) {
+                                                          float4 *L, SavePtrs save, const float *scale) {
     __shared__ __attribute__((aligned(16))) __bf16 sw[kWfSize];
     __shared__ __attribute__((aligned(16))) __bf16 sact[kWaves][2][16 * kActStride];
     const int64_t n = rec_count(n_host, n_dev);
@@ -240,8 +243,9 @@ __global__ __launch_bounds__(kThreads) void k_nrc_forward(int64_t n_host, const 
                         if (MODE == 2) {
                             const float *rec = src + (int64_t)stride * r;
                             const int pix = __float_as_int(rec[19]) & 0x3fffffff;
+                            const float unit = (scale && *scale > 0.f) ? *scale : 1.f;
                             float *lp = reinterpret_cast<float *>(L + pix) + col;
-                            *lp += rec[16 + col] * fmaxf(acc[i], 0.f);
+                            *lp += rec[16 + col] * unit * fmaxf(acc[i], 0.f);
                         } else {
                             y[3 * r + col] = acc[i];
                         }
@@ -254,20 +258,24 @@ __global__ __launch_bounds__(kThreads) void k_nrc_forward(int64_t n_host, const 
 }
 
 // Relative L2 loss, mean over records and channels of (y - t)^2 / (y^2 +
-// 0.01) with the denominator held constant; writes dL/dy as bf16 [n][32]
+// 0.01) with the denominator held constant, targets in units of *tscale (if
+// given and set) and clamped at tclamp (if > 0); writes dL/dy as bf16 [n][32]
 // (columns >= 3 zero) and per-block loss partial sums.
-__global__ void k_nrc_loss(int64_t n_host, const int32_t *n_dev, const float *y, const float *t, __bf16 *d4,
-                           float *loss_part) {
+__global__ void k_nrc_loss(int64_t n_host, const int32_t *n_dev, const float *y, const float *t, const float *tscale,
+                           float tclamp, __bf16 *d4, float *loss_part) {
     __shared__ float red[256];
     const int64_t n = rec_count(n_host, n_dev);
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     float l = 0.f;
     if (r < n) {
         const float scale = 1.f / (3.f * (float)n);
+        const float tinv = (tscale && *tscale > 0.f) ? 1.f / *tscale : 1.f;
         for (int c = 0; c < 32; ++c) {
             float g = 0.f;
             if (c < 3) {
-                const float yy = y[3 * r + c], e = yy - t[3 * r + c];
+                float tt = t[3 * r + c] * tinv;
+                if (tclamp > 0.f) tt = fminf(tt, tclamp);
+                const float yy = y[3 * r + c], e = yy - tt;
                 const float den = yy * yy + 0.01f;
                 l += e * e / den * scale;
                 g = 2.f * e / den * scale;
@@ -453,6 +461,33 @@ __global__ void k_nrc_adapt(const int32_t *attempted, int32_t cap, float *frac) 
     *frac = fminf(1.f, fmaxf(1e-5f, f));
 }
 
+// radiance unit from the first training batch: the mean target (once)
+__global__ void k_nrc_scale_init(int64_t n_host, const int32_t *n_dev, const float *targets, float *scale) {
+    __shared__ float red[256];
+    if (*scale > 0.f) return;
+    const int64_t n = rec_count(n_host, n_dev);
+    float s = 0.f;
+    for (int64_t i = threadIdx.x; i < 3 * n; i += blockDim.x) s += targets[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && n > 0 && red[0] > 0.f) *scale = red[0] / (3.f * (float)n);
+}
+
+// record count of each of `steps` batches of `per` records
+__global__ void k_nrc_batches(const int32_t *n_dev, int64_t cap, int steps, int64_t per, int32_t *bcnt) {
+    const int b = threadIdx.x;
+    if (b >= steps) return;
+    const int64_t n = (int64_t)*n_dev < cap ? (int64_t)*n_dev : cap;
+    const int64_t left = n - (int64_t)b * per;
+    bcnt[b] = (int32_t)(left < 0 ? 0 : (left > per ? per : left));
+}
+
+__global__ void k_nrc_set(float *p, float v) { *p = v; }
+
 EncodeBox make_box(ugp_ctx ctx, const float *box) {
     EncodeBox b;
     for (int k = 0; k < 3; ++k) {
@@ -479,7 +514,7 @@ int nrc_num_params() { return kNParam; }
 hipError_t nrc_ensure(ugp_ctx ctx) {
     if (ctx->nrc) return hipSuccess;
     NrcState *s = new NrcState();
-    hipError_t e = hipMalloc((void **)&s->master, sizeof(float) * kNParam * 4);
+    hipError_t e = hipMalloc((void **)&s->master, sizeof(float) * kNParam * 4 + 1024);
     if (e != hipSuccess) {
         delete s;
         return e;
@@ -487,6 +522,8 @@ hipError_t nrc_ensure(ugp_ctx ctx) {
     s->m = s->master + kNParam;
     s->v = s->m + kNParam;
     s->grad = s->v + kNParam;
+    s->scale = s->grad + kNParam;
+    s->bcnt = reinterpret_cast<int32_t *>(s->scale + 64);
     e = hipMalloc((void **)&s->wf, sizeof(__bf16) * (kWfSize + kWbSize));
     if (e != hipSuccess) {
         hipFree(s->master);
@@ -494,7 +531,7 @@ hipError_t nrc_ensure(ugp_ctx ctx) {
         return e;
     }
     s->wb = s->wf + kWfSize;
-    hipMemsetAsync(s->master, 0, sizeof(float) * kNParam * 4, ctx->stream);
+    hipMemsetAsync(s->master, 0, sizeof(float) * kNParam * 4 + 1024, ctx->stream);
     hipMemsetAsync(s->wf, 0, sizeof(__bf16) * (kWfSize + kWbSize), ctx->stream);
     ctx->nrc = s;
     return hipSuccess;
@@ -519,6 +556,8 @@ hipError_t nrc_set_weights(ugp_ctx ctx, const float *w) {
     if (e != hipSuccess) return e;
     e = hipMemsetAsync(s->m, 0, sizeof(float) * kNParam * 2, ctx->stream);
     if (e != hipSuccess) return e;
+    e = hipMemsetAsync(s->scale, 0, sizeof(float), ctx->stream);  // radiance unit: set by the next training
+    if (e != hipSuccess) return e;
     s->step = 0;
     hipLaunchKernelGGL(k_nrc_publish, dim3((kWfSize + 255) / 256), dim3(256), 0, ctx->stream, (const float *)s->master,
                        s->wf, s->wb);
@@ -538,18 +577,18 @@ hipError_t nrc_encode(ugp_ctx ctx, int64_t n, const float *inputs, int stride, c
 }
 
 hipError_t nrc_forward(ugp_ctx ctx, int64_t n, const int32_t *n_dev, const float *src, int stride, int src_kind,
-                       const float *box, float *y, float4 *L) {
+                       const float *box, float *y, float4 *L, const float *scale) {
     if (!ctx->nrc) return hipErrorNotReady;
     const EncodeBox b = make_box(ctx, box);
     const SavePtrs none{{nullptr, nullptr, nullptr, nullptr, nullptr}};
     const __bf16 *wf = ctx->nrc->wf;
     const dim3 g(fwd_grid(n)), t(kThreads);
     if (src_kind == 0)
-        hipLaunchKernelGGL((k_nrc_forward<0>), g, t, 0, ctx->stream, n, n_dev, src, stride, b, wf, y, L, none);
+        hipLaunchKernelGGL((k_nrc_forward<0>), g, t, 0, ctx->stream, n, n_dev, src, stride, b, wf, y, L, none, scale);
     else if (src_kind == 1)
-        hipLaunchKernelGGL((k_nrc_forward<1>), g, t, 0, ctx->stream, n, n_dev, src, stride, b, wf, y, L, none);
+        hipLaunchKernelGGL((k_nrc_forward<1>), g, t, 0, ctx->stream, n, n_dev, src, stride, b, wf, y, L, none, scale);
     else
-        hipLaunchKernelGGL((k_nrc_forward<2>), g, t, 0, ctx->stream, n, n_dev, src, stride, b, wf, y, L, none);
+        hipLaunchKernelGGL((k_nrc_forward<2>), g, t, 0, ctx->stream, n, n_dev, src, stride, b, wf, y, L, none, scale);
     return hipGetLastError();
 }
 
@@ -592,8 +631,9 @@ static hipError_t nrc_train_buffers(ugp_ctx ctx, int64_t n) {
 // gradients (per-slice partials reduced in a fixed order), Adam, new bf16
 // copies.  grad_out / loss_out (device, optional) receive the gradient and
 // the loss of this step.
-hipError_t nrc_train_step(ugp_ctx ctx, int64_t n, const int32_t *n_dev, const float *src, int stride, int src_kind,
-                          const float *box, const float *targets, float lr, float *loss_out, float *grad_out) {
+static hipError_t train_step_impl(ugp_ctx ctx, int64_t n, const int32_t *n_dev, const float *src, int stride,
+                                  int src_kind, const float *box, const float *targets, const float *tscale,
+                                  float tclamp, float lr, float *loss_out, float *grad_out) {
     if (!ctx->nrc) return hipErrorNotReady;
     NrcState *s = ctx->nrc;
     hipError_t e = nrc_train_buffers(ctx, n);
@@ -605,13 +645,13 @@ hipError_t nrc_train_step(ugp_ctx ctx, int64_t n, const int32_t *n_dev, const fl
     const dim3 g(fwd_grid(n)), t(kThreads);
     if (src_kind == 1)
         hipLaunchKernelGGL((k_nrc_forward<1>), g, t, 0, st, n, n_dev, src, stride, b, (const __bf16 *)s->wf, s->y,
-                           (float4 *)nullptr, save);
+                           (float4 *)nullptr, save, (const float *)nullptr);
     else
         hipLaunchKernelGGL((k_nrc_forward<0>), g, t, 0, st, n, n_dev, src, stride, b, (const __bf16 *)s->wf, s->y,
-                           (float4 *)nullptr, save);
+                           (float4 *)nullptr, save, (const float *)nullptr);
     const unsigned lb = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_nrc_loss, dim3(lb), dim3(256), 0, st, n, n_dev, (const float *)s->y, targets, s->delta[4],
-                       s->loss);
+    hipLaunchKernelGGL(k_nrc_loss, dim3(lb), dim3(256), 0, st, n, n_dev, (const float *)s->y, targets, tscale,
+                       tclamp, s->delta[4], s->loss);
     hipLaunchKernelGGL((k_nrc_backprop<32>), g, t, 0, st, n, n_dev, (const __bf16 *)s->delta[4],
                        (const __bf16 *)(s->wb + kWbOff[4]), (const __bf16 *)s->act[4], s->delta[3]);
     for (int l = 3; l >= 1; --l)
@@ -649,6 +689,37 @@ hipError_t nrc_train_step(ugp_ctx ctx, int64_t n, const int32_t *n_dev, const fl
                        s->wb);
     return hipGetLastError();
 }
+
+hipError_t nrc_train_step(ugp_ctx ctx, int64_t n, const int32_t *n_dev, const float *src, int stride, int src_kind,
+                          const float *box, const float *targets, float lr, float *loss_out, float *grad_out) {
+    return train_step_impl(ctx, n, n_dev, src, stride, src_kind, box, targets, nullptr, 0.f, lr, loss_out, grad_out);
+}
+
+// Training of a render: the radiance unit is set from the first batch's
+// targets (unless given), then `steps` Adam steps on consecutive batches of
+// the records (targets in that unit).
+hipError_t nrc_train_render(ugp_ctx ctx, int64_t cap, const int32_t *n_dev, const float *rec, const float *box,
+                            const float *targets, float lr, int steps, float tclamp, float *loss_out) {
+    NrcState *s = ctx->nrc;
+    if (!s) return hipErrorNotReady;
+    if (steps > 64) steps = 64;
+    hipLaunchKernelGGL(k_nrc_scale_init, dim3(1), dim3(256), 0, ctx->stream, cap, n_dev, targets, s->scale);
+    const int64_t per = (cap + steps - 1) / steps;
+    hipLaunchKernelGGL(k_nrc_batches, dim3(1), dim3(64), 0, ctx->stream, n_dev, cap, steps, per, s->bcnt);
+    hipError_t e = hipGetLastError();
+    for (int b = 0; b < steps && e == hipSuccess; ++b)
+        e = train_step_impl(ctx, per, s->bcnt + b, rec + (int64_t)kNrcRecordFloats * per * b, kNrcRecordFloats, 0,
+                            box, targets + 3 * per * b, s->scale, tclamp, lr, loss_out, nullptr);
+    return e;
+}
+
+hipError_t nrc_set_scale(ugp_ctx ctx, float value) {
+    if (!ctx->nrc) return hipErrorNotReady;
+    if (value > 0.f) hipLaunchKernelGGL(k_nrc_set, dim3(1), dim3(1), 0, ctx->stream, ctx->nrc->scale, value);
+    return hipGetLastError();
+}
+
+const float *nrc_scale_ptr(ugp_ctx ctx) { return ctx->nrc ? ctx->nrc->scale : nullptr; }
 
 hipError_t nrc_targets(ugp_ctx ctx, int64_t cap, const int32_t *n_dev, const float *rec, const float4 *L,
                        float *targets) {

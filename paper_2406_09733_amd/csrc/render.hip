@@ -2,17 +2,23 @@
 // tab:highlevel right column, eq. rte) with next-event estimation to emissive
 // primitives and to a constant environment, balance-heuristic MIS.
 //
-// One sample pass = raygen, then per vertex v = 1 .. max_depth+1:
-//   collide : primitive-level free-flight sampling of every live path; emission
-//             pick-up (MIS-weighted against the light pdf of the previous
-//             vertex); light / environment samples appended to their queues;
-//             phase sampling; surviving paths compacted into the next queue
-//             (wave ballot + one atomic per wave)
+// Paths live in a pool of queue slots (about 2M).  The samples of a call are
+// traced in chunks of several samples of every pixel; within a chunk each
+// iteration first refills the free slots with new camera paths of the chunk
+// (path g traces pixel g % pixels, sample chunk start + g / pixels), then:
+//   collide : primitive-level free-flight sampling of every live path, each
+//             at its own vertex; emission pick-up (MIS-weighted against the
+//             light pdf of the previous vertex); light / environment samples
+//             appended to their queues; phase sampling; surviving paths
+//             compacted into the next queue (wave ballot + one atomic per wave)
 //   light   : emitter query per light sample (emission rides on the
 //             free-flight pdf, so emitter k contributes L_e,k I_k(a, min(b,
 //             t_sat))/2 along the sampled direction)
 //   env     : transmittance per environment sample
-// and a final accumulation of each path's radiance into sum / sum of squares.
+// until the chunk's paths are all done; the host reads two counters per
+// iteration.  Each path's radiance has its own slot, so the final
+// accumulation into sum / sum of squares runs pixel by pixel in sample order
+// and the image does not depend on how paths were scheduled.
 // Random numbers: Philox4x32-10 keyed by the seed, counter (pixel, sample,
 // vertex, group): group 0 = (collision, emitter pick, cone u, cone v), group 1 =
 // (phase u, phase v, environment u, environment v); the camera jitter uses
@@ -23,9 +29,9 @@
 // collision nrc_terminate_after + 1: after its emission pick-up, its
 // throughput times the cache's prediction at that vertex is added.  Training
 // paths run to max_depth and record, at every scattering vertex, the cache
-// inputs, the throughput and the radiance gathered so far; after the pass the
-// record's target is (path radiance - radiance so far) / throughput, and one
-// optimisation step is taken on the pass's records.
+// inputs, the throughput and the radiance gathered so far; after the chunk the
+// record's target is (path radiance - radiance so far) / throughput, and the
+// optimisation steps are taken on the chunk's records.
 #include <algorithm>
 
 #include "trace_device.hpp"
@@ -35,25 +41,27 @@ namespace ugp {
 struct Queue {        // path (ray) queue, structure of arrays
     float4 *a;        // origin.xyz, pdf of the previous phase sample (0 = camera ray)
     float4 *b;        // direction.xyz, excluded primitive (original index bits)
-    float4 *c;        // throughput.rgb, pixel bits (bit 30: radiance-cache training path)
+    float4 *c;        // throughput.rgb, path index bits (bit 30: radiance-cache training path)
+    int32_t *v;       // vertex index of the path's next collision (1 = camera ray)
 };
 struct LightQueue {   // light-sample queue
     float4 *a;        // origin.xyz, target primitive bits
     float4 *b;        // direction.xyz, excluded primitive bits
-    float4 *c;        // weight.rgb, pixel bits
+    float4 *c;        // weight.rgb, path index bits
 };
 
 struct RenderBuffers {
-    int64_t cap = 0;
-    int max_vertices = 0;
+    int64_t cap = 0;         // path slots of the pool
+    int64_t lcap = 0;        // paths of a chunk (radiance slots)
     Queue q[2];
     LightQueue nee, env;
-    float4 *L = nullptr;     // path radiance per pixel
+    float4 *L = nullptr;     // radiance per path of the chunk
     int32_t *ovf = nullptr;  // overflow index list (cap entries)
     int2 *hits = nullptr;    // collision result per queue slot (prim, t bits)
     uint32_t *skey = nullptr, *skey2 = nullptr;  // ray-sort keys (and scratch)
     int32_t *sval = nullptr, *sval2 = nullptr;   // ray-sort permutation (and scratch)
-    int32_t *counts = nullptr;  // per vertex: [queue in, nee, env] ...
+    int32_t *counts = nullptr;  // iteration counters (two blocks) and chunk counters
+    int32_t *host = nullptr;    // pinned: [paths left in the next queue, paths generated]
     float *qry = nullptr;       // radiance-cache queries (kNrcRecordFloats per path)
     void *block = nullptr;
     // radiance-cache training state (grown on demand)
@@ -65,10 +73,15 @@ struct RenderBuffers {
 namespace {
 
 constexpr int kPersistBlocks = 4096;
-constexpr int64_t kWavefrontPaths = int64_t(1) << 21;
-// per-vertex counters: [0] paths in, [1] light samples, [2] environment
-// samples, [3] overflow, [4] collision work, [5] light work
+constexpr int64_t kPoolPaths = int64_t(1) << 21;   // path slots of the pool
+constexpr int64_t kChunkPaths = int64_t(1) << 24;  // paths of a chunk (radiance slots)
+// iteration counters, two blocks used alternately (input / output queue):
+// [0] paths in the queue, [1] light samples, [2] environment samples,
+// [3] overflow, [4] collision work, [5] light work, [6] cache queries;
+// then the chunk block: [0] paths generated, [1] training records appended
 constexpr int kCountStride = 8;
+constexpr int kChunkBlock = 2 * kCountStride;
+constexpr int64_t kSortMin = 16384;  // queues shorter than this are traced unsorted
 
 struct NrcArgs {
     int mode;              // 0 off, 1 infer + train, 2 infer, 3 terminate only
@@ -117,19 +130,37 @@ __device__ __forceinline__ float nee_pdf(const SceneDev &S, int k, V3 x) {
     return 1.f / ((float)S.n_emit * 2.f * kPi * omc);
 }
 
-__global__ void k_raygen(PassArgs P, int64_t npath, Queue q, float4 *L) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= npath) return;
-    const Rng4 g = path_rng(P, (uint32_t)p, 0, 0);
-    const int pix = (int)((uint32_t)p % P.npix);
+// Refill the free slots of the input queue with new camera paths of the
+// chunk: n_new = min(free slots, paths not yet generated); path g = generated
+// + j goes to slot n_in + j, its radiance slot is cleared.  k_regen_commit
+// then advances both counters and clears this iteration's other counters.
+__global__ void k_regen(PassArgs P, int64_t pool, int64_t total, const int32_t *cnt_in, const int32_t *chunk,
+                        Queue q, float4 *L) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n_in = cnt_in[0], gen = chunk[0];
+    const int64_t n_new = pool - n_in < total - gen ? pool - n_in : total - gen;
+    if (j >= n_new) return;
+    const int64_t g = gen + j, slot = n_in + j;
+    const Rng4 r = path_rng(P, (uint32_t)g, 0, 0);
+    const int pix = (int)((uint32_t)g % P.npix);
     const int px = pix % P.cam.width, py = pix / P.cam.width;
-    const V3 d = camera_dir(P.cam, px, py, g.u[0], g.u[1]);
-    int bits = (int)p;
-    if (P.nrc.mode == 1 && path_rng(P, (uint32_t)p, 0, 2).u[0] < *P.nrc.frac) bits |= kTrainBit;
-    q.a[p] = make_float4(P.cam.ox, P.cam.oy, P.cam.oz, 0.f);
-    q.b[p] = make_float4(d.x, d.y, d.z, __int_as_float(-1));
-    q.c[p] = make_float4(1.f, 1.f, 1.f, __int_as_float(bits));
-    L[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+    const V3 d = camera_dir(P.cam, px, py, r.u[0], r.u[1]);
+    int bits = (int)g;
+    if (P.nrc.mode == 1 && path_rng(P, (uint32_t)g, 0, 2).u[0] < *P.nrc.frac) bits |= kTrainBit;
+    q.a[slot] = make_float4(P.cam.ox, P.cam.oy, P.cam.oz, 0.f);
+    q.b[slot] = make_float4(d.x, d.y, d.z, __int_as_float(-1));
+    q.c[slot] = make_float4(1.f, 1.f, 1.f, __int_as_float(bits));
+    q.v[slot] = 1;
+    L[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+__global__ void k_regen_commit(int64_t pool, int64_t total, int32_t *cnt_in, int32_t *cnt_out, int32_t *chunk) {
+    const int64_t n_in = cnt_in[0], gen = chunk[0];
+    const int64_t n_new = pool - n_in < total - gen ? pool - n_in : total - gen;
+    cnt_in[0] = (int32_t)(n_in + n_new);
+    chunk[0] = (int32_t)(gen + n_new);
+    for (int k = 1; k < kCountStride; ++k) cnt_in[k] = 0;
+    for (int k = 0; k < kCountStride; ++k) cnt_out[k] = 0;
 }
 
 __device__ __forceinline__ int wave_append(bool want, int32_t *counter) {
@@ -204,7 +235,7 @@ __device__ __forceinline__ int64_t wave_grab(int32_t *work) {
 // distance) goes to hits[i].  Paths that overflow the register event buffer
 // are listed in `ovf` and redone by the wide instantiation (WIDE = true).
 template <int K, bool WIDE>
-__global__ __launch_bounds__(kBlock) void k_collide(SceneDev S, PassArgs P, int v, Queue qin,
+__global__ __launch_bounds__(kBlock) void k_collide(SceneDev S, PassArgs P, Queue qin,
                                                     const int32_t *n_in, const int32_t *order, int32_t *work,
                                                     int2 *hits, int64_t *stats, Overflow ovf, uint32_t *err) {
     __shared__ int stack[kStackSize * kBlock];
@@ -216,6 +247,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(SceneDev S, PassArgs P, int 
         const float4 A = qin.a[i], B = qin.b[i], C = qin.c[i];
         const int pix = __float_as_int(C.w) & kPixMask;
         const int excl = __float_as_int(B.w);
+        const int v = qin.v[i];
         const float u = path_rng(P, (uint32_t)pix, (uint32_t)v, 0).u[0];
         const RayD r = make_ray(A.x, A.y, A.z, B.x, B.y, B.z, 0.f, __builtin_huge_val());
         const SweepOut so = sweep<K>(S, r, excl, kModeCollide, u, -1, stack, err, tc);
@@ -240,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(SceneDev S, PassArgs P, int 
             const int64_t base = wave_grab(work);
             if (base >= n) break;
             const int64_t j = base + threadIdx.x;
-            if (j < n) process((int64_t)order[j]);
+            if (j < n) process(order ? (int64_t)order[j] : j);
         }
     }
     flush_counts(S, tc);
@@ -250,18 +282,20 @@ __global__ __launch_bounds__(kBlock) void k_collide(SceneDev S, PassArgs P, int 
 // against the light pdf of the previous vertex), environment on escape, one
 // light sample and one environment sample appended to their queues, phase
 // sampling, and compaction of the surviving paths into the next queue.
-__global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PassArgs P, int v, Queue qin, const int32_t *n_in,
+__global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PassArgs P, Queue qin, const int32_t *n_in,
                                                   const int2 *hits, Queue qout, int32_t *n_out, LightQueue nee,
                                                   int32_t *n_nee, LightQueue env, int32_t *n_env, float4 *L) {
     const int n = *n_in;
     for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += (int64_t)gridDim.x * kBlock) {
         const int64_t i = base + threadIdx.x;
         bool cont = false, do_nee = false, do_env = false, do_qry = false, do_rec = false;
+        int v = 0;
         float4 ca{}, cb{}, cc{}, na{}, nb{}, nc{}, ea{}, eb{}, ec{};
         float4 r0{}, r1{}, r2{}, r3{}, r4{}, r5{};  // cache query / training record
         if (i < n) {
             const float4 A = qin.a[i], B = qin.b[i], C = qin.c[i];
             const int2 hit = hits[i];
+            v = qin.v[i];
             const int pbits = __float_as_int(C.w);
             const int pix = pbits & kPixMask;
             const bool train = (pbits & kTrainBit) != 0;
@@ -403,7 +437,7 @@ __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PassArgs P, int v,
             }
         }
         const int pc = wave_append(cont, n_out);
-        if (cont) { qout.a[pc] = ca; qout.b[pc] = cb; qout.c[pc] = cc; }
+        if (cont) { qout.a[pc] = ca; qout.b[pc] = cb; qout.c[pc] = cc; qout.v[pc] = v + 1; }
         const int pn = wave_append(do_nee, n_nee);
         if (do_nee) { nee.a[pn] = na; nee.b[pn] = nb; nee.c[pn] = nc; }
         const int pe = wave_append(do_env, n_env);
@@ -464,7 +498,7 @@ __global__ __launch_bounds__(kBlock) void k_light(SceneDev S, LightQueue q, cons
             const int64_t base = wave_grab(work);
             if (base >= n) break;
             const int64_t j = base + threadIdx.x;
-            if (j < n) process((int64_t)order[j]);
+            if (j < n) process(order ? (int64_t)order[j] : j);
         }
     }
     flush_counts(S, tc);
@@ -510,23 +544,32 @@ __global__ void k_accum(int64_t npix, int nsamp, const float4 *L, float *sum, fl
 
 __global__ void k_set_count(int32_t *c, int32_t v) { *c = v; }
 
-// running totals of radiance-cache queries ([3]) and training records kept ([4])
-__global__ void k_nrc_stats(const int32_t *cnt, int64_t *stats) {
-    stats[3] += cnt[0];
-    stats[4] += cnt[1];
-}
+// running total of a count (radiance-cache queries, training records)
+__global__ void k_nrc_count(const int32_t *cnt, int64_t *total) { *total += *cnt; }
 
-hipError_t ensure_buffers(ugp_ctx ctx, int64_t cap, int max_vertices) {
+// pool buffers for `cap` path slots and radiance slots for `lcap` paths
+hipError_t ensure_buffers(ugp_ctx ctx, int64_t cap, int64_t lcap) {
     RenderBuffers *rb = ctx->rb;
-    if (rb && rb->cap >= cap && rb->max_vertices >= max_vertices) return hipSuccess;
+    if (rb && rb->cap >= cap && rb->lcap >= lcap) return hipSuccess;
+    if (rb) {
+        cap = std::max(cap, rb->cap);
+        lcap = std::max(lcap, rb->lcap);
+    }
     free_render(ctx);
     rb = new RenderBuffers();
     const size_t q = sizeof(float4) * (size_t)cap;
-    const size_t counts = sizeof(int32_t) * kCountStride * (size_t)(max_vertices + 2);
-    const size_t total = 12 * q + q + sizeof(int32_t) * (size_t)cap + sizeof(int2) * (size_t)cap + counts +
+    const size_t counts = sizeof(int32_t) * (kChunkBlock + kCountStride);
+    const size_t total = 12 * q + sizeof(float4) * (size_t)lcap + 2 * sizeof(int32_t) * (size_t)cap +
+                         sizeof(int32_t) * (size_t)cap + sizeof(int2) * (size_t)cap + counts +
                          4 * sizeof(int32_t) * (size_t)cap + 32 * 256;
     hipError_t e = hipMalloc(&rb->block, total);
     if (e != hipSuccess) {
+        delete rb;
+        return e;
+    }
+    e = hipHostMalloc((void **)&rb->host, sizeof(int32_t) * 4, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        hipFree(rb->block);
         delete rb;
         return e;
     }
@@ -540,10 +583,11 @@ hipError_t ensure_buffers(ugp_ctx ctx, int64_t cap, int max_vertices) {
         rb->q[k].a = (float4 *)take(q);
         rb->q[k].b = (float4 *)take(q);
         rb->q[k].c = (float4 *)take(q);
+        rb->q[k].v = (int32_t *)take(sizeof(int32_t) * (size_t)cap);
     }
     rb->nee.a = (float4 *)take(q); rb->nee.b = (float4 *)take(q); rb->nee.c = (float4 *)take(q);
     rb->env.a = (float4 *)take(q); rb->env.b = (float4 *)take(q); rb->env.c = (float4 *)take(q);
-    rb->L = (float4 *)take(q);
+    rb->L = (float4 *)take(sizeof(float4) * (size_t)lcap);
     rb->ovf = (int32_t *)take(sizeof(int32_t) * (size_t)cap);
     rb->hits = (int2 *)take(sizeof(int2) * (size_t)cap);
     rb->skey = (uint32_t *)take(sizeof(uint32_t) * (size_t)cap);
@@ -552,7 +596,7 @@ hipError_t ensure_buffers(ugp_ctx ctx, int64_t cap, int max_vertices) {
     rb->sval2 = (int32_t *)take(sizeof(int32_t) * (size_t)cap);
     rb->counts = (int32_t *)take(counts);
     rb->cap = cap;
-    rb->max_vertices = max_vertices;
+    rb->lcap = lcap;
     ctx->rb = rb;
     return hipSuccess;
 }
@@ -562,6 +606,7 @@ hipError_t ensure_buffers(ugp_ctx ctx, int64_t cap, int max_vertices) {
 void free_render(ugp_ctx ctx) {
     if (ctx->rb) {
         hipFree(ctx->rb->block);
+        hipHostFree(ctx->rb->host);
         hipFree(ctx->rb->qry);
         hipFree(ctx->rb->nrc_block);
         delete ctx->rb;
@@ -608,12 +653,11 @@ hipError_t ensure_nrc_buffers(ugp_ctx ctx, int64_t npix, int64_t rec_cap, bool *
 hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p, float *sum, float *sumsq) {
     const SceneDev &S0 = ctx->scene;
     const int64_t npix = (int64_t)cam->width * cam->height;
-    const int nv = p->max_depth + 1;
-    // a wavefront traces several samples of every pixel when the image is
-    // small, so that about 2M paths are in flight
-    const int wf = (int)std::max<int64_t>(1, std::min<int64_t>(p->spp, kWavefrontPaths / npix));
-    const int64_t cap = npix * wf;
-    hipError_t e = ensure_buffers(ctx, cap, nv);
+    // chunks of `cs` samples of every pixel share the pool of path slots
+    const int cs = (int)std::max<int64_t>(1, std::min<int64_t>(p->spp, kChunkPaths / npix));
+    const int64_t lcap = npix * cs;
+    const int64_t pool = std::min<int64_t>(kPoolPaths, lcap);
+    hipError_t e = ensure_buffers(ctx, pool, lcap);
     if (e != hipSuccess) return e;
     RenderBuffers *rb = ctx->rb;
     hipStream_t st = ctx->stream;
@@ -639,15 +683,17 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
         P.binv[k] = ext > 0.f ? 1.f / ext : 0.f;
     }
     P.seed = p->seed;
+    P.npix = (uint32_t)npix;
     P.max_depth = p->max_depth;
     P.mis_mode = p->mis_mode;
     P.env[0] = p->env_radiance[0]; P.env[1] = p->env_radiance[1]; P.env[2] = p->env_radiance[2];
     P.has_env = (P.env[0] > 0.f || P.env[1] > 0.f || P.env[2] > 0.f) ? 1 : 0;
+    int32_t *chunk_cnt = rb->counts + kChunkBlock;  // [0] paths generated, [1] records appended
     // radiance cache: modes 1 and 2 need the network; records only in mode 1
     P.nrc = NrcArgs{p->nrc_mode, p->nrc_terminate_after, nullptr, nullptr, 0, nullptr, nullptr, nullptr};
-    int32_t *nrc_cnt = rb->counts + kCountStride * (nv + 1);  // [0] queries, [1] records appended
     float nrc_box[6];
     const float *box = nullptr;
+    const float *nrc_scale = nullptr;
     if (p->nrc_mode != 0) {
         bool valid = true;
         for (int k = 0; k < 3; ++k) valid = valid && p->nrc_box[3 + k] > p->nrc_box[k];
@@ -658,23 +704,25 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
         if (p->nrc_mode != 3) {
             e = nrc_ensure(ctx);
             if (e != hipSuccess) return e;
+            e = nrc_set_scale(ctx, p->nrc_radiance_scale);
+            if (e != hipSuccess) return e;
+            nrc_scale = nrc_scale_ptr(ctx);
         }
         bool fresh = false;
-        e = ensure_nrc_buffers(ctx, cap, p->nrc_mode == 1 ? p->nrc_train_records : 0, &fresh);
+        e = ensure_nrc_buffers(ctx, pool, p->nrc_mode == 1 ? p->nrc_train_records : 0, &fresh);
         if (e != hipSuccess) return e;
-        if (p->nrc_mode == 1 && (fresh || ctx->nrc_frac_pixels != cap)) {
+        if (p->nrc_mode == 1 && (fresh || ctx->nrc_frac_pixels != lcap)) {
             // a training path is chosen with probability frac; frac starts at
-            // records / (2 paths of a wavefront) and is adapted after every wavefront
-            const float f0 = std::min(1.0f, (float)p->nrc_train_records / (2.0f * (float)cap));
+            // records / (2 paths of a chunk) and is adapted after every chunk
+            const float f0 = std::min(1.0f, (float)p->nrc_train_records / (2.0f * (float)lcap));
             hipLaunchKernelGGL(k_set_float, dim3(1), dim3(1), 0, st, rb->frac, f0);
-            ctx->nrc_frac_pixels = cap;
+            ctx->nrc_frac_pixels = lcap;
         }
         P.nrc.qry = rb->qry;
-        P.nrc.n_qry = nrc_cnt;
         P.nrc.frac = rb->frac;
         if (p->nrc_mode == 1) {
             P.nrc.rec = rb->rec;
-            P.nrc.n_rec = nrc_cnt + 1;
+            P.nrc.n_rec = chunk_cnt + 1;
             P.nrc.rec_cap = p->nrc_train_records;
         }
     }
@@ -711,97 +759,116 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
         ctx->ev_used.push_back({cat, (int)ev_next});
         ev_next += 2;
     };
-    P.npix = (uint32_t)npix;
     const unsigned gw = 256;  // the overflow pass: few paths
-    for (int s = 0; s < p->spp; s += wf) {
-        P.sample = (uint32_t)(p->sample_offset + s);
-        const int ns = std::min(wf, p->spp - s);
-        const int64_t npath = npix * ns;
-        const unsigned gpix = (unsigned)((npath + 255) / 256);
-        const unsigned gq = (unsigned)std::min<int64_t>((npath + kBlock - 1) / kBlock, kPersistBlocks);
-        e = hipMemsetAsync(rb->counts, 0, sizeof(int32_t) * kCountStride * (size_t)(nv + 2), st);
+    for (int s0 = 0; s0 < p->spp; s0 += cs) {
+        P.sample = (uint32_t)(p->sample_offset + s0);
+        const int ns = std::min(cs, p->spp - s0);
+        const int64_t total = npix * ns;
+        e = hipMemsetAsync(rb->counts, 0, sizeof(int32_t) * (kChunkBlock + kCountStride), st);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, st, rb->counts, (int32_t)npath);
-        hipLaunchKernelGGL(k_raygen, dim3(gpix), dim3(256), 0, st, P, npath, rb->q[0], rb->L);
-        for (int v = 1; v <= nv; ++v) {
-            // counters of vertex v (see kCountStride); the next vertex's paths-in is c + kCountStride
-            int32_t *c = rb->counts + kCountStride * (v - 1);
-            Queue qin = rb->q[(v - 1) & 1], qout = rb->q[v & 1];
+        // iterations until every path of the chunk has ended; each path takes
+        // at most max_depth + 1 iterations once generated
+        const int64_t max_iter = (int64_t)(p->max_depth + 2) * (total / pool + 2);
+        int64_t it = 0;
+        int64_t left = 0, gen = 0;  // paths carried into this iteration, paths generated (host copies)
+        for (;; ++it) {
+            if (it > max_iter) return hipErrorUnknown;  // a path outlived its depth: internal error
+            int32_t *c = rb->counts + kCountStride * (it & 1);        // input queue's counters
+            int32_t *cn = rb->counts + kCountStride * ((it + 1) & 1); // output queue's counters
+            Queue qin = rb->q[it & 1], qout = rb->q[(it + 1) & 1];
             Overflow ov{rb->ovf, c + 3};
+            // queue length of this iteration, known on the host: launches are sized to it
+            const int64_t n_new = std::min(pool - left, total - gen);
+            const int64_t n_it = left + n_new;
+            const unsigned gn = (unsigned)std::max<int64_t>(1, (n_it + 255) / 256);
+            const unsigned gq = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n_it + kBlock - 1) / kBlock,
+                                                                                  kPersistBlocks));
+            const bool sorted = n_it >= kSortMin;
+            const int32_t *order = sorted ? (const int32_t *)rb->sval : nullptr;
+            hipLaunchKernelGGL(k_regen, dim3((unsigned)std::max<int64_t>(1, (n_new + 255) / 256)), dim3(256), 0, st,
+                               P, pool, total, (const int32_t *)c, (const int32_t *)chunk_cnt, qin, rb->L);
+            hipLaunchKernelGGL(k_regen_commit, dim3(1), dim3(1), 0, st, pool, total, c, cn, chunk_cnt);
+            P.nrc.n_qry = c + 6;
             // order the queue so each wave's rays are coherent
-            timed(5, [&] {
-                hipLaunchKernelGGL(k_sort_keys, dim3(gpix), dim3(256), 0, st, P, qin, (const int32_t *)c, npath,
-                                   rb->skey, rb->sval);
-                radix_sort(rb->skey, rb->sval, rb->skey2, rb->sval2, npath, st);
-            });
+            if (sorted)
+                timed(5, [&] {
+                    hipLaunchKernelGGL(k_sort_keys, dim3(gn), dim3(256), 0, st, P, qin, (const int32_t *)c, n_it,
+                                       rb->skey, rb->sval);
+                    radix_sort(rb->skey, rb->sval, rb->skey2, rb->sval2, n_it, st);
+                });
             timed(0, [&] {
-                hipLaunchKernelGGL((k_collide<kEventsMain, false>), dim3(gq), dim3(kBlock), 0, st, Sc[0], P, v, qin,
-                                   (const int32_t *)c, (const int32_t *)rb->sval, c + 4, rb->hits, ctx->stats, ov,
-                                   ctx->err);
+                hipLaunchKernelGGL((k_collide<kEventsMain, false>), dim3(gq), dim3(kBlock), 0, st, Sc[0], P, qin,
+                                   (const int32_t *)c, order, c + 4, rb->hits, ctx->stats, ov, ctx->err);
             });
             timed(1, [&] {
-                hipLaunchKernelGGL((k_collide<kEventsWide, true>), dim3(gw), dim3(kBlock), 0, st, Sc[1], P, v, qin,
-                                   (const int32_t *)c, (const int32_t *)rb->sval, c + 4, rb->hits, ctx->stats, ov,
-                                   ctx->err);
+                hipLaunchKernelGGL((k_collide<kEventsWide, true>), dim3(gw), dim3(kBlock), 0, st, Sc[1], P, qin,
+                                   (const int32_t *)c, order, c + 4, rb->hits, ctx->stats, ov, ctx->err);
             });
             timed(4, [&] {
-                hipLaunchKernelGGL(k_shade, dim3(gq), dim3(kBlock), 0, st, S, P, v, qin, (const int32_t *)c,
-                                   (const int2 *)rb->hits, qout, c + kCountStride, rb->nee, c + 1, rb->env, c + 2,
-                                   rb->L);
+                hipLaunchKernelGGL(k_shade, dim3(gq), dim3(kBlock), 0, st, S, P, qin, (const int32_t *)c,
+                                   (const int2 *)rb->hits, qout, cn, rb->nee, c + 1, rb->env, c + 2, rb->L);
             });
-            if (v <= p->max_depth) {
-                if (S.n_emit > 0 && p->mis_mode != 1) {
-                    // light queue sorted like the path queue (its records share the layout)
+            if (S.n_emit > 0 && p->mis_mode != 1) {
+                // light queue (at most n_it records) sorted like the path queue
+                if (sorted)
                     timed(5, [&] {
-                        const Queue lq{rb->nee.a, rb->nee.b, rb->nee.c};
-                        hipLaunchKernelGGL(k_sort_keys, dim3(gpix), dim3(256), 0, st, P, lq, (const int32_t *)(c + 1),
-                                           npath, rb->skey, rb->sval);
-                        radix_sort(rb->skey, rb->sval, rb->skey2, rb->sval2, npath, st);
+                        const Queue lq{rb->nee.a, rb->nee.b, rb->nee.c, nullptr};
+                        hipLaunchKernelGGL(k_sort_keys, dim3(gn), dim3(256), 0, st, P, lq, (const int32_t *)(c + 1),
+                                           n_it, rb->skey, rb->sval);
+                        radix_sort(rb->skey, rb->sval, rb->skey2, rb->sval2, n_it, st);
                     });
-                    timed(2, [&] {
-                        hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, st, c + 3, 0);
-                        hipLaunchKernelGGL((k_light<kEventsMain, false>), dim3(gq), dim3(kBlock), 0, st, Sc[2], rb->nee,
-                                           (const int32_t *)(c + 1), (const int32_t *)rb->sval, c + 5, rb->L,
-                                           ctx->stats, ov, ctx->err);
-                        hipLaunchKernelGGL((k_light<kEventsWide, true>), dim3(gw), dim3(kBlock), 0, st, Sc[2], rb->nee,
-                                           (const int32_t *)(c + 1), (const int32_t *)rb->sval, c + 5, rb->L,
-                                           ctx->stats, ov, ctx->err);
-                    });
-                }
-                if (P.has_env && p->mis_mode != 1)
-                    timed(3, [&] {
-                        hipLaunchKernelGGL(k_env, dim3(gq), dim3(kBlock), 0, st, Sc[3], rb->env,
-                                           (const int32_t *)(c + 2), rb->L, ctx->stats, ctx->err);
-                    });
+                timed(2, [&] {
+                    hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, st, c + 3, 0);
+                    hipLaunchKernelGGL((k_light<kEventsMain, false>), dim3(gq), dim3(kBlock), 0, st, Sc[2], rb->nee,
+                                       (const int32_t *)(c + 1), order, c + 5, rb->L, ctx->stats, ov, ctx->err);
+                    hipLaunchKernelGGL((k_light<kEventsWide, true>), dim3(gw), dim3(kBlock), 0, st, Sc[2], rb->nee,
+                                       (const int32_t *)(c + 1), order, c + 5, rb->L, ctx->stats, ov, ctx->err);
+                });
             }
-        }
-        if (p->nrc_mode == 1 || p->nrc_mode == 2) {
-            // cached radiance of the paths that ended in the cache
-            timed(6, [&] {
-                e = nrc_forward(ctx, npath, nrc_cnt, rb->qry, kNrcRecordFloats, 2, box, nullptr, rb->L);
-            });
+            if (P.has_env && p->mis_mode != 1)
+                timed(3, [&] {
+                    hipLaunchKernelGGL(k_env, dim3(gq), dim3(kBlock), 0, st, Sc[3], rb->env,
+                                       (const int32_t *)(c + 2), rb->L, ctx->stats, ctx->err);
+                });
+            if (p->nrc_mode == 1 || p->nrc_mode == 2) {
+                // cached radiance of the paths that ended in the cache this iteration
+                timed(6, [&] {
+                    e = nrc_forward(ctx, n_it, c + 6, rb->qry, kNrcRecordFloats, 2, box, nullptr, rb->L, nrc_scale);
+                });
+                if (e != hipSuccess) return e;
+                hipLaunchKernelGGL(k_nrc_count, dim3(1), dim3(1), 0, st, (const int32_t *)(c + 6), ctx->stats + 3);
+            }
+            // continue while paths remain in the next queue or wait to be generated
+            e = hipMemcpyAsync(rb->host, cn, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(rb->host + 1, chunk_cnt, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
             if (e != hipSuccess) return e;
+            left = rb->host[0];
+            gen = rb->host[1];
+            if (left == 0 && gen >= total) break;
         }
         hipLaunchKernelGGL(k_accum, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, st, npix, ns, rb->L, sum,
                            sumsq);
         if (p->nrc_mode == 1) {
-            // targets of this pass's records, one optimisation step, new training-path probability
+            // targets of this chunk's records, the optimisation steps, new training-path probability
             timed(7, [&] {
-                e = nrc_targets(ctx, p->nrc_train_records, nrc_cnt + 1, rb->rec, rb->L, rb->targets);
+                e = nrc_targets(ctx, p->nrc_train_records, chunk_cnt + 1, rb->rec, rb->L, rb->targets);
                 if (e == hipSuccess)
-                    e = nrc_train_step(ctx, p->nrc_train_records, nrc_cnt + 1, rb->rec, kNrcRecordFloats, 0, box,
-                                       rb->targets, p->nrc_lr > 0.f ? p->nrc_lr : 1e-3f, rb->loss, nullptr);
-                if (e == hipSuccess) e = nrc_adapt(ctx, nrc_cnt + 1, p->nrc_train_records, rb->frac);
+                    e = nrc_train_render(ctx, p->nrc_train_records, chunk_cnt + 1, rb->rec, box, rb->targets,
+                                         p->nrc_lr > 0.f ? p->nrc_lr : 1e-2f, std::max(1, p->nrc_train_steps),
+                                         p->nrc_target_clamp, rb->loss);
+                if (e == hipSuccess) e = nrc_adapt(ctx, chunk_cnt + 1, p->nrc_train_records, rb->frac);
             });
             if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_nrc_count, dim3(1), dim3(1), 0, st, (const int32_t *)(chunk_cnt + 1),
+                               ctx->stats + 4);
         }
-        if (p->nrc_mode != 0)
-            hipLaunchKernelGGL(k_nrc_stats, dim3(1), dim3(1), 0, st, (const int32_t *)nrc_cnt, ctx->stats);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     ctx->last_paths = npix * p->spp;
-    ctx->last_nrc_counts = p->nrc_mode == 1 ? (int64_t)(nrc_cnt - rb->counts) : -1;
+    ctx->last_nrc_counts = p->nrc_mode == 1 ? (int64_t)kChunkBlock : -1;
     ctx->last_nrc_cap = p->nrc_mode == 1 ? p->nrc_train_records : 0;
     return hipSuccess;
 }

@@ -129,11 +129,18 @@ hipError_t nrc_encode(ugp_ctx ctx, int64_t n, const float *inputs, int stride, c
 // src_kind 0: raw inputs (stride floats per record) -> y; 1: features [n][96]
 // -> y; 2: records (kNrcRecordFloats) -> L[pixel] += throughput * max(0, y)
 hipError_t nrc_forward(ugp_ctx ctx, int64_t n, const int32_t *n_dev, const float *src, int stride, int src_kind,
-                       const float *box, float *y, float4 *L);
+                       const float *box, float *y, float4 *L, const float *scale = nullptr);
 hipError_t nrc_train_step(ugp_ctx ctx, int64_t n, const int32_t *n_dev, const float *src, int stride, int src_kind,
                           const float *box, const float *targets, float lr, float *loss_out, float *grad_out);
 hipError_t nrc_targets(ugp_ctx ctx, int64_t cap, const int32_t *n_dev, const float *rec, const float4 *L,
                        float *targets);
+// the training of a render: radiance unit from the first batch (unless set),
+// then `steps` Adam steps on consecutive batches of the records
+hipError_t nrc_train_render(ugp_ctx ctx, int64_t cap, const int32_t *n_dev, const float *rec, const float *box,
+                            const float *targets, float lr, int steps, float tclamp, float *loss_out);
+// radiance unit of the network's output: value > 0 sets it, 0 keeps the current one
+hipError_t nrc_set_scale(ugp_ctx ctx, float value);
+const float *nrc_scale_ptr(ugp_ctx ctx);
 hipError_t nrc_adapt(ugp_ctx ctx, const int32_t *attempted, int32_t cap, float *frac);
 
 // device scratch of the context: returns a buffer of at least `bytes`
