@@ -235,7 +235,7 @@ __device__ __forceinline__ int64_t wave_grab(int32_t *work) {
 // distance) goes to hits[i].  Paths that overflow the register event buffer
 // are listed in `ovf` and redone by the wide instantiation (WIDE = true).
 template <int K, bool WIDE>
-__global__ __launch_bounds__(kBlock) void k_collide(SceneDev S, PassArgs P, Queue qin,
+__global__ __launch_bounds__(kBlock, 2) void k_collide(SceneDev S, PassArgs P, Queue qin,
                                                     const int32_t *n_in, const int32_t *order, int32_t *work,
                                                     int2 *hits, int64_t *stats, Overflow ovf, uint32_t *err) {
     __shared__ int stack[kStackSize * kBlock];
@@ -458,7 +458,7 @@ __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PassArgs P, Queue 
 }
 
 template <int K, bool WIDE>
-__global__ __launch_bounds__(kBlock) void k_light(SceneDev S, LightQueue q, const int32_t *n_in,
+__global__ __launch_bounds__(kBlock, 2) void k_light(SceneDev S, LightQueue q, const int32_t *n_in,
                                                   const int32_t *order, int32_t *work, float4 *L, int64_t *stats,
                                                   Overflow ovf, uint32_t *err) {
     __shared__ int stack[kStackSize * kBlock];

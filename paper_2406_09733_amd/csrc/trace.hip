@@ -86,7 +86,7 @@ __device__ __forceinline__ void run_sweep(const SceneDev &S, const SweepArgs &A,
     if (A.f_out) A.f_out[i] = o.t;
 }
 
-__global__ __launch_bounds__(kBlock) void k_sweep_main(SceneDev S, SweepArgs A, uint32_t *err) {
+__global__ __launch_bounds__(kBlock, 2) void k_sweep_main(SceneDev S, SweepArgs A, uint32_t *err) {
     __shared__ int stack[kStackSize * kBlock];
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= A.n) return;

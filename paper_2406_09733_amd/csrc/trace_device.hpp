@@ -439,11 +439,55 @@ __device__ __forceinline__ Chord ev_chord(const SceneDev &S, const RayD &r, int 
     return c;
 }
 
+// Chords of up to kChordCache buffered primitives that may straddle the
+// saturation point are kept in LDS (two float4 per chord, column = lane)
+// while t_sat is solved, so the Newton steps do not re-read their records.
+constexpr int kChordCache = 4;
+
+struct ChordCache {
+    float4 *base;    // [kChordCache * 2][kBlock]
+    uint64_t mask;   // buffer entries held (slot = rank among the set bits)
+};
+
+__device__ __forceinline__ void cache_put(ChordCache &cc, int slot, const Chord &c) {
+    const int lane = threadIdx.x & (kBlock - 1);
+    cc.base[(2 * slot) * kBlock + lane] =
+        make_float4(__int_as_float(__double2loint(c.tc)), __int_as_float(__double2hiint(c.tc)), c.s, c.pref);
+    cc.base[(2 * slot + 1) * kBlock + lane] = make_float4(c.ta, c.tb, c.a, c.b);
+}
+
+__device__ __forceinline__ Chord cache_get(const ChordCache &cc, int j) {
+    const int lane = threadIdx.x & (kBlock - 1);
+    const int slot = __popcll(cc.mask & ((1ull << j) - 1ull));
+    const float4 x = cc.base[(2 * slot) * kBlock + lane], y = cc.base[(2 * slot + 1) * kBlock + lane];
+    Chord c;
+    c.tc = __hiloint2double(__float_as_int(x.y), __float_as_int(x.x));
+    c.s = x.z;
+    c.pref = x.w;
+    c.ta = y.x;
+    c.tb = y.y;
+    c.a = y.z;
+    c.b = y.w;
+    c.bd = (double)y.w;
+    c.W = 0.f;  // not kept: cached chords are only evaluated strictly inside (a, b)
+    c.orig = -1;
+    c.own = true;
+    return c;
+}
+
+// chord of buffer entry j: from the cache when held, else re-derived
+template <int K>
+__device__ __forceinline__ Chord ev_chord_c(const SceneDev &S, const RayD &r, const EvBuf<K> &B, int j,
+                                           const ChordCache *cc, TraceCount &tc) {
+    if (cc && ((cc->mask >> j) & 1ull)) return cache_get(*cc, j);
+    return ev_chord(S, r, ev_id(B, j), tc);
+}
+
 // F(t) and F'(t) over the buffer: S_fin + sum of (full weights of exits <= t,
 // partial weights of entries before t that exit later)
 template <int K>
 __device__ __forceinline__ float sweep_F(const SceneDev &S, const RayD &r, const EvBuf<K> &B, float S_fin,
-                                double t, float *dF, TraceCount &tc) {
+                                double t, float *dF, TraceCount &tc, const ChordCache *cc = nullptr) {
     float F = S_fin, G = 0.f;
     uint64_t partial = 0;
 #pragma unroll Unr<K>::v
@@ -456,7 +500,7 @@ __device__ __forceinline__ float sweep_F(const SceneDev &S, const RayD &r, const
     while (partial) {
         const int j = __builtin_ctzll(partial);
         partial &= partial - 1;
-        const Chord c = ev_chord(S, r, ev_id(B, j), tc);
+        const Chord c = ev_chord_c(S, r, B, j, cc, tc);
         F += half_integral_to(c, t);
         G += half_kernel_at(c, t);
     }
@@ -623,13 +667,25 @@ __device__ __forceinline__ SweepOut sweep(const SceneDev &S, const RayD &r, int 
                 if (i < B.n && (double)B.a[i] < t_w) bmax = fmaxf(bmax, B.b[i]);
             hi = fmin(hi, (double)bmax);
         }
+        // keep the chords of the entries that can straddle a point of [lo, hi]
+        __shared__ float4 cc_lds[kChordCache * 2 * kBlock];
+        ChordCache cc{cc_lds, 0ull};
+        {
+            int ns = 0;
+#pragma unroll Unr<K>::v
+            for (int i = 0; i < K; ++i)
+                if (i < B.n && ns < kChordCache && (double)B.a[i] < hi && (double)B.b[i] > lo) {
+                    cache_put(cc, ns++, ev_chord(S, r, B.id[i], tc));
+                    cc.mask |= 1ull << i;
+                }
+        }
         double t = hi;
         // Iterate in t to well below float resolution: near a thin primitive
         // dF/dt is ~1e4, so t_sat must be resolved far finer than t's ulp for
         // the clipped weights to be accurate; F itself is float.
         for (int it = 0; it < 60; ++it) {
             float g;
-            const float f = sweep_F<K>(S, r, B, S_fin, t, &g, tc) - 1.f;
+            const float f = sweep_F<K>(S, r, B, S_fin, t, &g, tc, &cc) - 1.f;
             if (f == 0.f) break;
             if (f > 0.f) hi = t; else lo = t;
             if (hi - lo <= 1e-13 * fmax(fabs(hi), 1e-30)) break;
@@ -644,15 +700,18 @@ __device__ __forceinline__ SweepOut sweep(const SceneDev &S, const RayD &r, int 
             return out;
         }
         if (mode == kModeEmitter) {
+            int ti = -1;
 #pragma unroll Unr<K>::v
             for (int i = 0; i < K; ++i)
-                if (i < B.n && B.id[i] == target) {
-                    if ((double)B.b[i] <= tsat) out.t = B.w[i];
-                    else if ((double)B.a[i] < tsat) {
-                        const Chord c = ev_chord(S, r, target, tc);
-                        out.t = half_integral_to(c, tsat);
-                    }
-                }
+                if (i < B.n && B.id[i] == target) ti = i;
+            if (ti >= 0) {
+                float tb = 0.f, ta = 0.f, tw = 0.f;
+#pragma unroll Unr<K>::v
+                for (int i = 0; i < K; ++i)
+                    if (i == ti) { tb = B.b[i]; ta = B.a[i]; tw = B.w[i]; }
+                if ((double)tb <= tsat) out.t = tw;
+                else if ((double)ta < tsat) out.t = half_integral_to(ev_chord_c(S, r, B, ti, &cc, tc), tsat);
+            }
             return out;
         }
         // collide: exits before t_sat in (b, id) order, then straddlers by id
@@ -689,7 +748,7 @@ __device__ __forceinline__ SweepOut sweep(const SceneDev &S, const RayD &r, int 
                         bi = i;
                     }
                 if (bi < 0) break;
-                const Chord c = ev_chord(S, r, bid, tc);
+                const Chord c = ev_chord_c(S, r, B, bi, &cc, tc);
                 run += half_integral_to(c, tsat);
                 out.prim = bid;
                 out.t = 0.5f * (c.a + c.b);
