@@ -474,7 +474,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_light(SceneDev S, LightQueue q, c
         Chord c;
         if (!chord(h, r, S.r2, c)) return;
         r.t1 = c.bd;
-        const SweepOut so = sweep<K>(S, r, excl, kModeEmitter, 0.f, target, stack, err, tc);
+        const SweepOut so = sweep<K>(S, r, excl, kModeEmitter, 0.f, target, stack, err, tc, c.a);
         if (so.status != 0) {
             if (WIDE) {
                 atomicOr(err, kErrEvents);

@@ -36,12 +36,13 @@ struct SweepArgs {
 };
 
 // emitter mode: clip the ray at the exit of the target's chord
-__device__ __forceinline__ bool emitter_ray(const SceneDev &S, RayD &r, int target, int excl) {
+__device__ __forceinline__ bool emitter_ray(const SceneDev &S, RayD &r, int target, int excl, float &entry) {
     if (target < 0 || target >= S.n || target == excl) return false;
     const HotRec h = load_hot(S.hot, S.inv[target]);
     Chord c;
     if (!chord(h, r, S.r2, c)) return false;
     r.t1 = c.bd;  // the exit in full precision (the float b is rounded)
+    entry = c.a;
     return true;
 }
 
@@ -51,16 +52,17 @@ __device__ __forceinline__ void run_sweep(const SceneDev &S, const SweepArgs &A,
     RayD r = load_ray(A.rays, i);
     const int ex = A.excl ? A.excl[i] : -1;
     int target = -1;
+    float entry = -__builtin_huge_valf();
     if (A.mode == kModeEmitter) {
         target = A.target[i];
-        if (!emitter_ray(S, r, target, ex)) {
+        if (!emitter_ray(S, r, target, ex, entry)) {
             A.f_out[i] = 0.f;
             return;
         }
     }
     const float u = A.u ? A.u[i] : 0.f;
     TraceCount tc;
-    const SweepOut o = sweep<K>(S, r, ex, A.mode, u, target, stack, err, tc);
+    const SweepOut o = sweep<K>(S, r, ex, A.mode, u, target, stack, err, tc, entry);
     if (A.counts) {
         int32_t *c = A.counts + 4 * i;
         if (wide) {  // add to the main pass's counts

@@ -508,9 +508,12 @@ __device__ __forceinline__ float sweep_F(const SceneDev &S, const RayD &r, const
     return F;
 }
 
+// stop_a (emitter mode): the target's chord entry; once a saturation bound
+// falls at or before it the target is hidden (weight 0) and the sweep ends.
 template <int K>
 __device__ __forceinline__ SweepOut sweep(const SceneDev &S, const RayD &r, int excl, int mode, float u,
-                                 int target, int *stack, uint32_t *err, TraceCount &tc) {
+                                 int target, int *stack, uint32_t *err, TraceCount &tc,
+                                 float stop_a = -__builtin_huge_valf()) {
     SweepOut out{-1, __builtin_nanf(""), 0};
     if (mode == kModeSaturate) out.t = (float)r.t1;
     if (mode == kModeEmitter) out.t = 0.f;
@@ -526,7 +529,7 @@ __device__ __forceinline__ SweepOut sweep(const SceneDev &S, const RayD &r, int 
         float cap_a = kInf;
         int cap_id = 0x7fffffff;
         float cap_sat = kInf;  // saturation bound: t_sat <= cap_sat
-        bool evicted = false;
+        bool evicted = false, hidden = false;
         const int n_before = B.n;
         traverse(S, r, fmaxf(r.t0, lb_a),
                  [&]() __attribute__((always_inline)) { return fminf(fminf(cap_a, cap_sat), t1f); },
@@ -569,10 +572,17 @@ __device__ __forceinline__ SweepOut sweep(const SceneDev &S, const RayD &r, int 
                          for (int i = 0; i < K; ++i)
                              if (i < B.n && B.b[i] <= c.b) lo_F += B.w[i];
                          // margin: the exact F(b) sums the same terms in another order
-                         if (lo_F >= 1.0001f) cap_sat = c.b;
+                         if (lo_F >= 1.0001f) {
+                             cap_sat = c.b;
+                             if (cap_sat <= stop_a) {
+                                 hidden = true;  // t_sat < entry of the target
+                                 return true;
+                             }
+                         }
                      }
                      return false;
                  });
+        if (hidden) return out;
         // window end: every primitive entering before t_w is in the buffer
         const double t_w = evicted ? (double)cap_a : r.t1;
         // progress check: nothing new and nothing can exit -> overflow
