@@ -251,10 +251,16 @@ __device__ __forceinline__ void cswap(float &ta, int &ra, float &tb, int &rb) {
 }
 
 // 4-wide BVH traversal: the children of a node are tested together and
-// visited nearest first; leaf children are handled in their parent, farther
-// internal children go on a per-lane LDS stack (column `lane` of a
-// [kStackSize][kBlock] int array).  `leaf(prim)` returns true to stop the
-// traversal; `hi()` is re-read after leaves so a shrinking bound culls at once.
+// visited nearest first; farther internal children go on a per-lane LDS stack
+// (column `lane` of a [kStackSize][kBlock] int array).  Leaf children are not
+// tested where they are found: they are queued per lane (LDS, up to kPend)
+// and the lanes test their queued leaves together, after every lane of the
+// wave has found leaves or run out of nodes (a lane with leaves queued keeps
+// descending meanwhile) -- so the long leaf code runs with most lanes active.
+// `leaf(prim)` returns true to stop the traversal; `hi()` is re-read before
+// every node test so a shrinking bound culls as soon as leaves were tested.
+constexpr int kPend = 8;
+
 template <class LeafFn, class HiFn>
 __device__ __forceinline__ bool traverse(const SceneDev &S, const RayD &r, float lo, HiFn &&hi, int *stack,
                                          uint32_t *err, TraceCount &tc, LeafFn &&leaf) {
@@ -264,6 +270,9 @@ __device__ __forceinline__ bool traverse(const SceneDev &S, const RayD &r, float
         ++tc.prims;
         return leaf(~ref);
     }
+    __shared__ int pend[kPend * kBlock];
+    int np = 0;          // queued leaves of this lane
+    bool nodes = true;   // this lane still has a node to visit (ref)
     int sp = 0;
     // the stack lives in LDS; deeper entries (a 4-wide node can push three)
     // spill to private memory, which is only touched in that rare case
@@ -275,57 +284,64 @@ __device__ __forceinline__ bool traverse(const SceneDev &S, const RayD &r, float
         ++sp;
     };
     for (;;) {
-        ++tc.nodes;
-        const float4 *nd = S.nodes + 8 * (int64_t)ref;
-        const float4 lx = nd[0], ly = nd[1], lz = nd[2], hx = nd[3], hy = nd[4], hz = nd[5], rf = nd[6];
-        const float h0 = hi();
-        float t0 = slab(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, r, lo, h0);
-        float t1 = slab(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, r, lo, h0);
-        float t2 = slab(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, r, lo, h0);
-        float t3 = slab(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, r, lo, h0);
-        int r0 = __float_as_int(rf.x), r1 = __float_as_int(rf.y), r2 = __float_as_int(rf.z),
-            r3 = __float_as_int(rf.w);
-        // unused slots carry an inverted box, which a slab test would take as
-        // unbounded: mask them by their ref
-        t0 = r0 == kEmptySlot ? kInf : t0;
-        t1 = r1 == kEmptySlot ? kInf : t1;
-        t2 = r2 == kEmptySlot ? kInf : t2;
-        t3 = r3 == kEmptySlot ? kInf : t3;
-        // sort the four (entry, ref) pairs by entry distance (misses are +inf)
-        cswap(t0, r0, t1, r1);
-        cswap(t2, r2, t3, r3);
-        cswap(t0, r0, t2, r2);
-        cswap(t1, r1, t3, r3);
-        cswap(t1, r1, t2, r2);
-        // leaves first, nearest first, through one call site
-        for (int i = 0; i < 4; ++i) {
-            const float ti = i == 0 ? t0 : i == 1 ? t1 : i == 2 ? t2 : t3;
-            const int ri = i == 0 ? r0 : i == 1 ? r1 : i == 2 ? r2 : r3;
-            if (ti == kInf) break;
-            if (ri < 0) {
-                ++tc.prims;
-                if (leaf(~ri)) return true;
+        // descend while there is room for one more node's leaves
+        while (nodes && np <= kPend - 4) {
+            ++tc.nodes;
+            const float4 *nd = S.nodes + 8 * (int64_t)ref;
+            const float4 lx = nd[0], ly = nd[1], lz = nd[2], hx = nd[3], hy = nd[4], hz = nd[5], rf = nd[6];
+            const float h0 = hi();
+            float t0 = slab(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, r, lo, h0);
+            float t1 = slab(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, r, lo, h0);
+            float t2 = slab(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, r, lo, h0);
+            float t3 = slab(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, r, lo, h0);
+            int r0 = __float_as_int(rf.x), r1 = __float_as_int(rf.y), r2 = __float_as_int(rf.z),
+                r3 = __float_as_int(rf.w);
+            // unused slots carry an inverted box, which a slab test would take as
+            // unbounded: mask them by their ref
+            t0 = r0 == kEmptySlot ? kInf : t0;
+            t1 = r1 == kEmptySlot ? kInf : t1;
+            t2 = r2 == kEmptySlot ? kInf : t2;
+            t3 = r3 == kEmptySlot ? kInf : t3;
+            // sort the four (entry, ref) pairs by entry distance (misses are +inf)
+            cswap(t0, r0, t1, r1);
+            cswap(t2, r2, t3, r3);
+            cswap(t0, r0, t2, r2);
+            cswap(t1, r1, t3, r3);
+            cswap(t1, r1, t2, r2);
+            // queue the leaf children, nearest first
+            if (t0 < kInf && r0 < 0) pend[(np++) * kBlock + lane] = ~r0;
+            if (t1 < kInf && r1 < 0) pend[(np++) * kBlock + lane] = ~r1;
+            if (t2 < kInf && r2 < 0) pend[(np++) * kBlock + lane] = ~r2;
+            if (t3 < kInf && r3 < 0) pend[(np++) * kBlock + lane] = ~r3;
+            // internal children within the bound (a miss is +inf and must
+            // stay a miss when the bound itself is +inf)
+            const float lim = h0 + 5e-7f * fabsf(h0);
+            const bool g0 = t0 < kInf && t0 <= lim && r0 >= 0, g1 = t1 < kInf && t1 <= lim && r1 >= 0,
+                       g2 = t2 < kInf && t2 <= lim && r2 >= 0, g3 = t3 < kInf && t3 <= lim && r3 >= 0;
+            // push the farther ones (farthest first), descend into the nearest
+            int next = -1;
+            if (g3) next = r3;
+            if (g2) { if (next >= 0) push(next); next = r2; }
+            if (g1) { if (next >= 0) push(next); next = r1; }
+            if (g0) { if (next >= 0) push(next); next = r0; }
+            if (next >= 0) {
+                ref = next;
+            } else if (sp == 0) {
+                nodes = false;
+            } else {
+                --sp;
+                ref = sp < kStackSize ? stack[sp * kBlock + lane] : spill[sp - kStackSize];
             }
+            // leaves are tested once every lane has some queued (or no nodes left)
+            if (__all(np > 0 || !nodes)) break;
         }
-        // internal children still within the (possibly shrunk) bound
-        // (a miss is +inf and must stay a miss when the bound itself is +inf)
-        const float h1 = hi();
-        const float lim = h1 + 5e-7f * fabsf(h1);
-        const bool g0 = t0 < kInf && t0 <= lim && r0 >= 0, g1 = t1 < kInf && t1 <= lim && r1 >= 0,
-                   g2 = t2 < kInf && t2 <= lim && r2 >= 0, g3 = t3 < kInf && t3 <= lim && r3 >= 0;
-        // push the farther ones (farthest first), descend into the nearest
-        int next = -1;
-        if (g3) next = r3;
-        if (g2) { if (next >= 0) push(next); next = r2; }
-        if (g1) { if (next >= 0) push(next); next = r1; }
-        if (g0) { if (next >= 0) push(next); next = r0; }
-        if (next >= 0) {
-            ref = next;
-        } else {
-            if (sp == 0) return false;
-            --sp;
-            ref = sp < kStackSize ? stack[sp * kBlock + lane] : spill[sp - kStackSize];
+        // test the queued leaves, nearest first
+        for (int q = 0; q < np; ++q) {
+            ++tc.prims;
+            if (leaf(pend[q * kBlock + lane])) return true;
         }
+        np = 0;
+        if (!nodes) return false;
     }
 }
 
