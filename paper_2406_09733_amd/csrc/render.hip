@@ -231,6 +231,21 @@ __device__ __forceinline__ int64_t wave_grab(int32_t *work) {
     return (int64_t)__shfl(base, 0);
 }
 
+// Lanes whose ray is done (want) take the next entries of the queue: one
+// atomic per wave, entries handed out in lane order.  Returns the queue
+// position for wanting lanes (>= n when the queue is exhausted), -1 otherwise.
+__device__ __forceinline__ int64_t lane_refill(bool want, int32_t *work) {
+    const uint64_t m = __ballot(want);
+    if (m == 0ull) return -1;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(work, __popcll(m));
+    base = __shfl(base, leader);
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    return want ? (int64_t)base + __popcll(m & below) : -1;
+}
+
 // Collision sweep of every live path; the result (selected primitive, scatter
 // distance) goes to hits[i].  Paths that overflow the register event buffer
 // are listed in `ovf` and redone by the wide instantiation (WIDE = true).
@@ -267,12 +282,41 @@ __global__ __launch_bounds__(kBlock, 2) void k_collide(SceneDev S, PassArgs P, Q
         for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock)
             process((int64_t)ovf.idx[j]);
     } else {
-        // waves take chunks of 64 sorted queue entries until the queue is done
+        // one sweep round per iteration; a lane whose ray is done takes the
+        // next ray of the sorted queue at once, so lanes do not wait for the
+        // slowest ray of their wave
+        int64_t i = -1;
+        bool exhausted = false;
+        RayD r = make_ray(0.f, 0.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.0);
+        float u = 0.f;
+        int excl = -1;
+        SweepState<K> st;
+        SweepOut so;
         for (;;) {
-            const int64_t base = wave_grab(work);
-            if (base >= n) break;
-            const int64_t j = base + threadIdx.x;
-            if (j < n) process(order ? (int64_t)order[j] : j);
+            const int64_t j = lane_refill(i < 0 && !exhausted, work);
+            if (j >= 0) {
+                if (j < n) {
+                    i = order ? (int64_t)order[j] : j;
+                    const float4 A = qin.a[i], B = qin.b[i], C = qin.c[i];
+                    const int pix = __float_as_int(C.w) & kPixMask;
+                    excl = __float_as_int(B.w);
+                    u = path_rng(P, (uint32_t)pix, (uint32_t)qin.v[i], 0).u[0];
+                    r = make_ray(A.x, A.y, A.z, B.x, B.y, B.z, 0.f, __builtin_huge_val());
+                    sweep_start(st, so, r, kModeCollide);
+                } else {
+                    exhausted = true;
+                }
+            }
+            if (!__any(i >= 0)) break;
+            if (i >= 0 && sweep_round<K>(S, r, excl, kModeCollide, u, -1, -kInf, st, so, stack, err, tc)) {
+                if (so.status != 0) {
+                    const int slot = atomicAdd(ovf.count, 1);
+                    ovf.idx[slot] = (int32_t)i;
+                } else {
+                    hits[i] = make_int2(so.prim, __float_as_int(so.t));
+                }
+                i = -1;
+            }
         }
     }
     flush_counts(S, tc);
@@ -494,11 +538,48 @@ __global__ __launch_bounds__(kBlock, 2) void k_light(SceneDev S, LightQueue q, c
         for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock)
             process((int64_t)ovf.idx[j]);
     } else {
+        // one sweep round per iteration, lanes refilled as their rays finish
+        int64_t i = -1;
+        bool exhausted = false;
+        RayD r = make_ray(0.f, 0.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.0);
+        int excl = -1, target = -1;
+        float entry = 0.f;
+        SweepState<K> st;
+        SweepOut so;
         for (;;) {
-            const int64_t base = wave_grab(work);
-            if (base >= n) break;
-            const int64_t j = base + threadIdx.x;
-            if (j < n) process(order ? (int64_t)order[j] : j);
+            const int64_t j = lane_refill(i < 0 && !exhausted, work);
+            if (j >= 0) {
+                if (j < n) {
+                    const int64_t k = order ? (int64_t)order[j] : j;
+                    const float4 A = q.a[k], B = q.b[k];
+                    target = __float_as_int(A.w);
+                    excl = __float_as_int(B.w);
+                    r = make_ray(A.x, A.y, A.z, B.x, B.y, B.z, 0.f, __builtin_huge_val());
+                    Chord c;
+                    if (chord(load_hot(S.hot, S.inv[target]), r, S.r2, c)) {
+                        r.t1 = c.bd;
+                        entry = c.a;
+                        i = k;
+                        sweep_start(st, so, r, kModeEmitter);
+                    }
+                } else {
+                    exhausted = true;
+                }
+            }
+            if (!__any(i >= 0 || (j >= 0 && j < n))) break;
+            if (i >= 0 && sweep_round<K>(S, r, excl, kModeEmitter, 0.f, target, entry, st, so, stack, err, tc)) {
+                if (so.status != 0) {
+                    const int slot = atomicAdd(ovf.count, 1);
+                    ovf.idx[slot] = (int32_t)i;
+                } else if (so.t > 0.f) {
+                    const float4 C = q.c[i];
+                    const int pix = __float_as_int(C.w);
+                    float4 l = L[pix];
+                    l.x += C.x * so.t; l.y += C.y * so.t; l.z += C.z * so.t;
+                    L[pix] = l;
+                }
+                i = -1;
+            }
         }
     }
     flush_counts(S, tc);

@@ -259,7 +259,7 @@ __device__ __forceinline__ void cswap(float &ta, int &ra, float &tb, int &rb) {
 // descending meanwhile) -- so the long leaf code runs with most lanes active.
 // `leaf(prim)` returns true to stop the traversal; `hi()` is re-read before
 // every node test so a shrinking bound culls as soon as leaves were tested.
-constexpr int kPend = 8;
+constexpr int kPend = 12;
 
 template <class LeafFn, class HiFn>
 __device__ __forceinline__ bool traverse(const SceneDev &S, const RayD &r, float lo, HiFn &&hi, int *stack,
@@ -524,23 +524,50 @@ __device__ __forceinline__ float sweep_F(const SceneDev &S, const RayD &r, const
     return F;
 }
 
+// State of one ray's sweep between rounds.
+template <int K>
+struct SweepState {
+    EvBuf<K> B;
+    float S_fin;     // finalised weight (exits before t_cur)
+    double t_cur;
+    float lb_a;      // entries with key <= (lb_a, lb_id) were seen
+    int lb_id;
+    int round;
+};
+
+template <int K>
+__device__ __forceinline__ void sweep_start(SweepState<K> &st, SweepOut &out, const RayD &r, int mode) {
+    out = SweepOut{-1, __builtin_nanf(""), 0};
+    if (mode == kModeSaturate) out.t = (float)r.t1;
+    if (mode == kModeEmitter) out.t = 0.f;
+    st.B.n = 0;
+    st.S_fin = 0.f;
+    st.t_cur = r.t0;
+    st.lb_a = -kInf;
+    st.lb_id = -1;
+    st.round = 0;
+}
+
+// One round of the sweep: gather, then finalise the window (or solve the
+// saturation inside it).  Returns true when the ray is done and `out` holds
+// its result, false when another round is needed.
 // stop_a (emitter mode): the target's chord entry; once a saturation bound
 // falls at or before it the target is hidden (weight 0) and the sweep ends.
 template <int K>
-__device__ __forceinline__ SweepOut sweep(const SceneDev &S, const RayD &r, int excl, int mode, float u,
-                                 int target, int *stack, uint32_t *err, TraceCount &tc,
-                                 float stop_a = -__builtin_huge_valf()) {
-    SweepOut out{-1, __builtin_nanf(""), 0};
-    if (mode == kModeSaturate) out.t = (float)r.t1;
-    if (mode == kModeEmitter) out.t = 0.f;
-    EvBuf<K> B;
-    B.n = 0;
-    float S_fin = 0.f;          // finalised weight (exits before t_cur)
-    double t_cur = r.t0;
-    float lb_a = -kInf;         // entries with key <= (lb_a, lb_id) were seen
-    int lb_id = -1;
+__device__ __forceinline__ bool sweep_round(const SceneDev &S, const RayD &r, int excl, int mode, float u,
+                                            int target, float stop_a, SweepState<K> &st, SweepOut &out,
+                                            int *stack, uint32_t *err, TraceCount &tc) {
+    EvBuf<K> &B = st.B;
+    float &S_fin = st.S_fin;
+    double &t_cur = st.t_cur;
+    float &lb_a = st.lb_a;
+    int &lb_id = st.lb_id;
     const float t1f = r.t1 < 3.0e38 ? (float)r.t1 : kInf;
-    for (int round = 0; round < 4096; ++round) {
+    if (st.round++ >= 4096) {
+        out.status = 1;
+        return true;
+    }
+    {
         ++tc.rounds;
         float cap_a = kInf;
         int cap_id = 0x7fffffff;
@@ -598,7 +625,7 @@ __device__ __forceinline__ SweepOut sweep(const SceneDev &S, const RayD &r, int 
                      }
                      return false;
                  });
-        if (hidden) return out;
+        if (hidden) return true;
         // window end: every primitive entering before t_w is in the buffer
         const double t_w = evicted ? (double)cap_a : r.t1;
         // progress check: nothing new and nothing can exit -> overflow
@@ -644,19 +671,19 @@ __device__ __forceinline__ SweepOut sweep(const SceneDev &S, const RayD &r, int 
                     pb = bb;
                     pid = bid;
                 }
-                return out;
+                return true;
             }
             if (mode == kModeEmitter) {
 #pragma unroll Unr<K>::v
                 for (int i = 0; i < K; ++i)
                     if (((fin >> i) & 1ull) && B.id[i] == target) out.t = B.w[i];
             }
-            if (!evicted) return out;  // ray complete without saturation
+            if (!evicted) return true;  // ray complete without saturation
             if (fin == 0ull && B.n == K && n_before == K) {
                 // a full buffer of primitives that all outlive the window:
                 // more than K primitives overlap one point of the ray
                 out.status = 1;
-                return out;
+                return true;
             }
             // drop finalised events (stable, in place: the write index never
             // passes the read index)
@@ -680,7 +707,7 @@ __device__ __forceinline__ SweepOut sweep(const SceneDev &S, const RayD &r, int 
             t_cur = t_w;
             lb_a = cap_a;   // the next round gathers keys >= the first rejected one
             lb_id = cap_id;
-            continue;
+            return false;
         }
         // saturation inside (t_cur, t_w]: bracketed Newton on F(t) = 1.  F is
         // constant after the last exit in the buffer, so that bounds the bracket
@@ -723,7 +750,7 @@ __device__ __forceinline__ SweepOut sweep(const SceneDev &S, const RayD &r, int 
         const double tsat = t;
         if (mode == kModeSaturate) {
             out.t = (float)tsat;
-            return out;
+            return true;
         }
         if (mode == kModeEmitter) {
             int ti = -1;
@@ -738,7 +765,7 @@ __device__ __forceinline__ SweepOut sweep(const SceneDev &S, const RayD &r, int 
                 if ((double)tb <= tsat) out.t = tw;
                 else if ((double)ta < tsat) out.t = half_integral_to(ev_chord_c(S, r, B, ti, &cc, tc), tsat);
             }
-            return out;
+            return true;
         }
         // collide: exits before t_sat in (b, id) order, then straddlers by id
         {
@@ -758,7 +785,7 @@ __device__ __forceinline__ SweepOut sweep(const SceneDev &S, const RayD &r, int 
                 run += bw;
                 out.prim = bid;
                 out.t = 0.5f * (ba + bb);
-                if (run > u) return out;
+                if (run > u) return true;
                 pb = bb;
                 pid = bid;
             }
@@ -778,14 +805,26 @@ __device__ __forceinline__ SweepOut sweep(const SceneDev &S, const RayD &r, int 
                 run += half_integral_to(c, tsat);
                 out.prim = bid;
                 out.t = 0.5f * (c.a + c.b);
-                if (run > u) return out;
+                if (run > u) return true;
                 pidx = bid;
             }
             // rounding left u above the total of 1: keep the last candidate
-            return out;
+            return true;
         }
     }
-    out.status = 1;
+    return false;  // not reached: every path above returns
+}
+
+// The whole sweep of one ray.
+template <int K>
+__device__ __forceinline__ SweepOut sweep(const SceneDev &S, const RayD &r, int excl, int mode, float u,
+                                          int target, int *stack, uint32_t *err, TraceCount &tc,
+                                          float stop_a = -__builtin_huge_valf()) {
+    SweepState<K> st;
+    SweepOut out;
+    sweep_start(st, out, r, mode);
+    while (!sweep_round<K>(S, r, excl, mode, u, target, stop_a, st, out, stack, err, tc)) {
+    }
     return out;
 }
 
