@@ -142,8 +142,8 @@ __device__ __forceinline__ bool surely_missed(const HotRec &h, const RayD &r, fl
 }
 
 // Returns false if the clipped chord is empty.
-__device__ inline bool chord(const HotRec &h, const RayD &r, float r2, Chord &c) {
-    if (surely_missed(h, r, r2)) return false;
+__device__ inline bool chord(const HotRec &h, const RayD &r, float r2, Chord &c, bool screened = false) {
+    if (!screened && surely_missed(h, r, r2)) return false;
     const float *M = h.m;
     // reference point on the ray near mu: p_e = (o - mu) + t_e w, FP64
     const double dx = r.dx, dy = r.dy, dz = r.dz;
@@ -257,18 +257,21 @@ __device__ __forceinline__ void cswap(float &ta, int &ra, float &tb, int &rb) {
 // and the lanes test their queued leaves together, after every lane of the
 // wave has found leaves or run out of nodes (a lane with leaves queued keeps
 // descending meanwhile) -- so the long leaf code runs with most lanes active.
-// `leaf(prim)` returns true to stop the traversal; `hi()` is re-read before
-// every node test so a shrinking bound culls as soon as leaves were tested.
+// The queued leaves first go through the cheap screen `pre(prim)` (record
+// fetch and float reject test); only the survivors, compacted in the queue,
+// reach `leaf(prim)` (the exact chord and the caller's bookkeeping), which
+// returns true to stop the traversal.  `hi()` is re-read before every node
+// test so a shrinking bound culls as soon as leaves were tested.
 constexpr int kPend = 12;
 
-template <class LeafFn, class HiFn>
+template <class PreFn, class LeafFn, class HiFn>
 __device__ __forceinline__ bool traverse(const SceneDev &S, const RayD &r, float lo, HiFn &&hi, int *stack,
-                                         uint32_t *err, TraceCount &tc, LeafFn &&leaf) {
+                                         uint32_t *err, TraceCount &tc, PreFn &&pre, LeafFn &&leaf) {
     const int lane = threadIdx.x;
     int ref = S.root;
     if (ref < 0) {
         ++tc.prims;
-        return leaf(~ref);
+        return pre(~ref) && leaf(~ref);
     }
     __shared__ int pend[kPend * kBlock];
     int np = 0;          // queued leaves of this lane
@@ -335,9 +338,15 @@ __device__ __forceinline__ bool traverse(const SceneDev &S, const RayD &r, float
             // leaves are tested once every lane has some queued (or no nodes left)
             if (__all(np > 0 || !nodes)) break;
         }
-        // test the queued leaves, nearest first
+        // screen the queued leaves, keep the survivors in order, then test them
+        int ns = 0;
         for (int q = 0; q < np; ++q) {
             ++tc.prims;
+            const int p = pend[q * kBlock + lane];
+            if (pre(p)) pend[(ns++) * kBlock + lane] = p;
+        }
+        for (int q = 0; q < ns; ++q) {
+            ++tc.reloads;  // the survivor's record is read again (from cache, normally)
             if (leaf(pend[q * kBlock + lane])) return true;
         }
         np = 0;
@@ -358,9 +367,12 @@ __device__ inline float transmittance_F(const SceneDev &S, const RayD &r, int ex
     traverse(S, r, lo, [&]() __attribute__((always_inline)) { return hi1; }, stack, err, tc,
              [&](int p) __attribute__((always_inline)) {
         const HotRec h = load_hot(S.hot, p);
-        if (h.orig == excl) return false;
+        return h.orig != excl && !surely_missed(h, r, S.r2);
+    },
+             [&](int p) __attribute__((always_inline)) {
+        const HotRec h = load_hot(S.hot, p);
         Chord c;
-        if (!chord(h, r, S.r2, c) || !c.own) return false;
+        if (!chord(h, r, S.r2, c, true) || !c.own) return false;
         F += c.W;
         return early_out && F >= 1.f;
     });
@@ -576,11 +588,15 @@ __device__ __forceinline__ bool sweep_round(const SceneDev &S, const RayD &r, in
         const int n_before = B.n;
         traverse(S, r, fmaxf(r.t0, lb_a),
                  [&]() __attribute__((always_inline)) { return fminf(fminf(cap_a, cap_sat), t1f); },
-                 stack, err, tc, [&](int p) __attribute__((always_inline)) {
+                 stack, err, tc,
+                 [&](int p) __attribute__((always_inline)) {
                      const HotRec h = load_hot(S.hot, p);
-                     if (h.orig == excl) return false;
+                     return h.orig != excl && !surely_missed(h, r, S.r2);
+                 },
+                 [&](int p) __attribute__((always_inline)) {
+                     const HotRec h = load_hot(S.hot, p);
                      Chord c;
-                     if (!chord(h, r, S.r2, c) || !c.own) return false;
+                     if (!chord(h, r, S.r2, c, true) || !c.own) return false;
                      if (key_less(c.a, c.orig, lb_a, lb_id)) return false;    // seen before
                      if (!key_less(c.a, c.orig, cap_a, cap_id)) return false; // beyond cap
                      if (c.a > cap_sat) return false;                          // past saturation
