@@ -484,9 +484,8 @@ __device__ __forceinline__ void cache_put(ChordCache &cc, int slot, const Chord 
     cc.base[(2 * slot + 1) * kBlock + lane] = make_float4(c.ta, c.tb, c.a, c.b);
 }
 
-__device__ __forceinline__ Chord cache_get(const ChordCache &cc, int j) {
+__device__ __forceinline__ Chord cache_get_slot(const ChordCache &cc, int slot) {
     const int lane = threadIdx.x & (kBlock - 1);
-    const int slot = __popcll(cc.mask & ((1ull << j) - 1ull));
     const float4 x = cc.base[(2 * slot) * kBlock + lane], y = cc.base[(2 * slot + 1) * kBlock + lane];
     Chord c;
     c.tc = __hiloint2double(__float_as_int(x.y), __float_as_int(x.x));
@@ -501,6 +500,10 @@ __device__ __forceinline__ Chord cache_get(const ChordCache &cc, int j) {
     c.orig = -1;
     c.own = true;
     return c;
+}
+
+__device__ __forceinline__ Chord cache_get(const ChordCache &cc, int j) {
+    return cache_get_slot(cc, __popcll(cc.mask & ((1ull << j) - 1ull)));
 }
 
 // chord of buffer entry j: from the cache when held, else re-derived
@@ -725,37 +728,80 @@ __device__ __forceinline__ bool sweep_round(const SceneDev &S, const RayD &r, in
             lb_id = cap_id;
             return false;
         }
-        // saturation inside (t_cur, t_w]: bracketed Newton on F(t) = 1.  F is
-        // constant after the last exit in the buffer, so that bounds the bracket
+        // saturation inside (t_cur, t_w]: bracketed Newton on F(t) = 1.
+        // Bracket: F is constant after the last exit in the buffer; F(t) is at
+        // most S_fin plus the full weights of the entries before t, so F < 1 at
+        // every entry reached before that sum comes near 1; and t_sat <= cap_sat
         // (t_w itself may be +inf).
         double lo = t_cur, hi = t_w;
         {
-            float bmax = -kInf;
+            float bmax = -kInf, cum = S_fin, lo_a = -kInf;
 #pragma unroll Unr<K>::v
             for (int i = 0; i < K; ++i)
-                if (i < B.n && (double)B.a[i] < t_w) bmax = fmaxf(bmax, B.b[i]);
-            hi = fmin(hi, (double)bmax);
+                if (i < B.n && (double)B.a[i] < t_w) {
+                    bmax = fmaxf(bmax, B.b[i]);
+                    if (cum < 1.f - 1e-4f) lo_a = B.a[i];  // F(a_i) <= cum < 1
+                    cum += B.w[i];
+                }
+            hi = fmin(fmin(hi, (double)bmax), (double)cap_sat);
+            lo = fmax(lo, (double)lo_a);
         }
-        // keep the chords of the entries that can straddle a point of [lo, hi]
+        // Entries exiting by lo count in full at every t of the bracket and
+        // entries starting at or after hi not at all; the chords of the others
+        // (the only ones that can straddle t) are kept in LDS while t_sat is
+        // solved, with their full weights in registers.
         __shared__ float4 cc_lds[kChordCache * 2 * kBlock];
         ChordCache cc{cc_lds, 0ull};
-        {
-            int ns = 0;
+        float F_base = S_fin;
+        float wc[kChordCache];
+        int ns = 0, n_act = 0;
 #pragma unroll Unr<K>::v
-            for (int i = 0; i < K; ++i)
-                if (i < B.n && ns < kChordCache && (double)B.a[i] < hi && (double)B.b[i] > lo) {
-                    cache_put(cc, ns++, ev_chord(S, r, B.id[i], tc));
-                    cc.mask |= 1ull << i;
+        for (int i = 0; i < K; ++i) {
+            if (i < B.n) {
+                if ((double)B.b[i] <= lo) {
+                    F_base += B.w[i];
+                } else if ((double)B.a[i] < hi) {
+                    ++n_act;
+                    if (ns < kChordCache) {
+#pragma unroll
+                        for (int k = 0; k < kChordCache; ++k)
+                            if (k == ns) wc[k] = B.w[i];
+                        cache_put(cc, ns++, ev_chord(S, r, B.id[i], tc));
+                        cc.mask |= 1ull << i;
+                    }
                 }
+            }
         }
-        double t = hi;
-        // Iterate in t to well below float resolution: near a thin primitive
-        // dF/dt is ~1e4, so t_sat must be resolved far finer than t's ulp for
-        // the clipped weights to be accurate; F itself is float.
+        const bool cached = n_act <= kChordCache;
+        // F(t) - 1 and F'(t) on the bracket
+        auto eval = [&](double t, float &g) __attribute__((always_inline)) {
+            if (!cached) return sweep_F<K>(S, r, B, S_fin, t, &g, tc, &cc) - 1.f;
+            float F = F_base, G = 0.f;
+#pragma unroll
+            for (int k = 0; k < kChordCache; ++k) {
+                if (k < ns) {
+                    const Chord c = cache_get_slot(cc, k);
+                    if (t >= c.bd) {
+                        F += wc[k];
+                    } else if (t > (double)c.a) {
+                        F += 0.5f * c.pref * erf_diff(c.ta, tau_at(c, t));
+                        G += half_kernel_at(c, t);
+                    }
+                }
+            }
+            g = G;
+            return F - 1.f;
+        };
+        // Start at the middle of the bracket (for a lone saturating primitive
+        // the middle of its chord, where its kernel peaks).  t_sat is resolved
+        // far below float resolution in t (near a thin primitive dF/dt is ~1e4),
+        // until F itself is within a few float ulps of 1, where the float sum
+        // cannot tell the sides apart.
+        double t = 0.5 * (lo + hi);
         for (int it = 0; it < 60; ++it) {
             float g;
-            const float f = sweep_F<K>(S, r, B, S_fin, t, &g, tc, &cc) - 1.f;
-            if (f == 0.f) break;
+            const float f = eval(t, g);
+            if (fabsf(f) <= 3e-7f) break;
             if (f > 0.f) hi = t; else lo = t;
             if (hi - lo <= 1e-13 * fmax(fabs(hi), 1e-30)) break;
             double tn = (g > 0.f) ? t - (double)f / (double)g : 0.5 * (lo + hi);
