@@ -224,6 +224,10 @@ __global__ void k_sort_keys(PassArgs P, Queue q, const int32_t *n_in, int64_t ca
     keys[j] = key;
 }
 
+// a traversal is suspended when at most this many lanes of the wave are still
+// walking the tree (the others then take new rays)
+constexpr int kSuspendAt = 32;
+
 // next chunk of 64 queue entries for this wave (dynamic load balance)
 __device__ __forceinline__ int64_t wave_grab(int32_t *work) {
     int base = 0;
@@ -282,8 +286,9 @@ __global__ __launch_bounds__(kBlock, 2) void k_collide(SceneDev S, PassArgs P, Q
         for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock)
             process((int64_t)ovf.idx[j]);
     } else {
-        // one sweep round per iteration; a lane whose ray is done takes the
-        // next ray of the sorted queue at once, so lanes do not wait for the
+        // one sweep round (or part of one) per iteration; a lane whose ray is
+        // done takes the next ray of the sorted queue at once, and traversals
+        // are suspended while many lanes wait, so lanes do not wait for the
         // slowest ray of their wave
         int64_t i = -1;
         bool exhausted = false;
@@ -292,6 +297,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_collide(SceneDev S, PassArgs P, Q
         int excl = -1;
         SweepState<K> st;
         SweepOut so;
+        int spill[kStackSpill];
         for (;;) {
             const int64_t j = lane_refill(i < 0 && !exhausted, work);
             if (j >= 0) {
@@ -308,7 +314,9 @@ __global__ __launch_bounds__(kBlock, 2) void k_collide(SceneDev S, PassArgs P, Q
                 }
             }
             if (!__any(i >= 0)) break;
-            if (i >= 0 && sweep_round<K>(S, r, excl, kModeCollide, u, -1, -kInf, st, so, stack, err, tc)) {
+            const int susp = __any(exhausted) ? 0 : kSuspendAt;
+            if (i >= 0 &&
+                sweep_round<K>(S, r, excl, kModeCollide, u, -1, -kInf, st, so, stack, spill, susp, err, tc)) {
                 if (so.status != 0) {
                     const int slot = atomicAdd(ovf.count, 1);
                     ovf.idx[slot] = (int32_t)i;
@@ -546,6 +554,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_light(SceneDev S, LightQueue q, c
         float entry = 0.f;
         SweepState<K> st;
         SweepOut so;
+        int spill[kStackSpill];
         for (;;) {
             const int64_t j = lane_refill(i < 0 && !exhausted, work);
             if (j >= 0) {
@@ -567,7 +576,9 @@ __global__ __launch_bounds__(kBlock, 2) void k_light(SceneDev S, LightQueue q, c
                 }
             }
             if (!__any(i >= 0 || (j >= 0 && j < n))) break;
-            if (i >= 0 && sweep_round<K>(S, r, excl, kModeEmitter, 0.f, target, entry, st, so, stack, err, tc)) {
+            const int susp = __any(exhausted) ? 0 : kSuspendAt;
+            if (i >= 0 && sweep_round<K>(S, r, excl, kModeEmitter, 0.f, target, entry, st, so, stack, spill, susp,
+                                         err, tc)) {
                 if (so.status != 0) {
                     const int slot = atomicAdd(ovf.count, 1);
                     ovf.idx[slot] = (int32_t)i;

@@ -262,24 +262,46 @@ __device__ __forceinline__ void cswap(float &ta, int &ra, float &tb, int &rb) {
 // reach `leaf(prim)` (the exact chord and the caller's bookkeeping), which
 // returns true to stop the traversal.  `hi()` is re-read before every node
 // test so a shrinking bound culls as soon as leaves were tested.
+//
+// A traversal can be suspended: after a leaf phase, when at most
+// `suspend_at` lanes of the wave still have nodes to visit, those lanes save
+// their position (TravState; the stack stays in the lane's LDS column and
+// `spill`) and return kTravSuspended, so the caller can give the idle lanes
+// new rays; the next call with the same state resumes the walk.  The set of
+// leaves a traversal reaches does not depend on where it was suspended.
 constexpr int kPend = 12;
 
+struct TravState {
+    int ref;     // next node to visit
+    int sp;      // stack depth
+    bool nodes;  // `ref` is still to be visited
+};
+
+__device__ __forceinline__ void trav_begin(TravState &ts, const SceneDev &S) {
+    ts.ref = S.root;
+    ts.sp = 0;
+    ts.nodes = true;
+}
+
+enum : int { kTravDone = 0, kTravStopped = 1, kTravSuspended = 2 };
+
 template <class PreFn, class LeafFn, class HiFn>
-__device__ __forceinline__ bool traverse(const SceneDev &S, const RayD &r, float lo, HiFn &&hi, int *stack,
-                                         uint32_t *err, TraceCount &tc, PreFn &&pre, LeafFn &&leaf) {
+__device__ __forceinline__ int traverse(const SceneDev &S, const RayD &r, float lo, HiFn &&hi, int *stack,
+                                        int *spill, TravState &ts, int suspend_at, uint32_t *err,
+                                        TraceCount &tc, PreFn &&pre, LeafFn &&leaf) {
     const int lane = threadIdx.x;
-    int ref = S.root;
-    if (ref < 0) {
+    int ref = ts.ref;
+    if (ref < 0) {  // a tree of one primitive
+        ts.nodes = false;
         ++tc.prims;
-        return pre(~ref) && leaf(~ref);
+        return pre(~ref) && leaf(~ref) ? kTravStopped : kTravDone;
     }
     __shared__ int pend[kPend * kBlock];
-    int np = 0;          // queued leaves of this lane
-    bool nodes = true;   // this lane still has a node to visit (ref)
-    int sp = 0;
+    int np = 0;             // queued leaves of this lane
+    bool nodes = ts.nodes;  // this lane still has a node to visit (ref)
+    int sp = ts.sp;
     // the stack lives in LDS; deeper entries (a 4-wide node can push three)
     // spill to private memory, which is only touched in that rare case
-    int spill[kStackSpill];
     auto push = [&](int v) __attribute__((always_inline)) {
         if (sp < kStackSize) stack[sp * kBlock + lane] = v;
         else if (sp < kStackSize + kStackSpill) spill[sp - kStackSize] = v;
@@ -347,10 +369,18 @@ __device__ __forceinline__ bool traverse(const SceneDev &S, const RayD &r, float
         }
         for (int q = 0; q < ns; ++q) {
             ++tc.reloads;  // the survivor's record is read again (from cache, normally)
-            if (leaf(pend[q * kBlock + lane])) return true;
+            if (leaf(pend[q * kBlock + lane])) return kTravStopped;
         }
         np = 0;
-        if (!nodes) return false;
+        if (!nodes) {
+            ts.nodes = false;
+            return kTravDone;
+        }
+        if (__popcll(__ballot(1)) <= suspend_at) {
+            ts.ref = ref;
+            ts.sp = sp;
+            return kTravSuspended;
+        }
     }
 }
 
@@ -364,7 +394,10 @@ __device__ inline float transmittance_F(const SceneDev &S, const RayD &r, int ex
     float F = 0.f;
     const float lo = r.t0;
     const float hi1 = r.t1 < 3.0e38 ? (float)r.t1 : kInf;
-    traverse(S, r, lo, [&]() __attribute__((always_inline)) { return hi1; }, stack, err, tc,
+    int spill[kStackSpill];
+    TravState ts;
+    trav_begin(ts, S);
+    traverse(S, r, lo, [&]() __attribute__((always_inline)) { return hi1; }, stack, spill, ts, 0, err, tc,
              [&](int p) __attribute__((always_inline)) {
         const HotRec h = load_hot(S.hot, p);
         return h.orig != excl && !surely_missed(h, r, S.r2);
@@ -548,6 +581,14 @@ struct SweepState {
     float lb_a;      // entries with key <= (lb_a, lb_id) were seen
     int lb_id;
     int round;
+    // the round in progress (its traversal may be suspended)
+    bool in_round;
+    float cap_a;     // key of the first evicted entry: the window ends there
+    int cap_id;
+    float cap_sat;   // saturation bound: t_sat <= cap_sat
+    bool evicted, hidden;
+    int n_before;    // buffered entries when the round began
+    TravState ts;
 };
 
 template <int K>
@@ -561,37 +602,49 @@ __device__ __forceinline__ void sweep_start(SweepState<K> &st, SweepOut &out, co
     st.lb_a = -kInf;
     st.lb_id = -1;
     st.round = 0;
+    st.in_round = false;
 }
 
 // One round of the sweep: gather, then finalise the window (or solve the
 // saturation inside it).  Returns true when the ray is done and `out` holds
-// its result, false when another round is needed.
+// its result, false when another round is needed or the round's traversal
+// was suspended (suspend_at > 0; the next call resumes it).
 // stop_a (emitter mode): the target's chord entry; once a saturation bound
 // falls at or before it the target is hidden (weight 0) and the sweep ends.
 template <int K>
 __device__ __forceinline__ bool sweep_round(const SceneDev &S, const RayD &r, int excl, int mode, float u,
                                             int target, float stop_a, SweepState<K> &st, SweepOut &out,
-                                            int *stack, uint32_t *err, TraceCount &tc) {
+                                            int *stack, int *spill, int suspend_at, uint32_t *err,
+                                            TraceCount &tc) {
     EvBuf<K> &B = st.B;
     float &S_fin = st.S_fin;
     double &t_cur = st.t_cur;
     float &lb_a = st.lb_a;
     int &lb_id = st.lb_id;
     const float t1f = r.t1 < 3.0e38 ? (float)r.t1 : kInf;
-    if (st.round++ >= 4096) {
-        out.status = 1;
-        return true;
+    float &cap_a = st.cap_a;
+    int &cap_id = st.cap_id;
+    float &cap_sat = st.cap_sat;
+    bool &evicted = st.evicted, &hidden = st.hidden;
+    if (!st.in_round) {
+        if (st.round++ >= 4096) {
+            out.status = 1;
+            return true;
+        }
+        ++tc.rounds;
+        cap_a = kInf;
+        cap_id = 0x7fffffff;
+        cap_sat = kInf;
+        evicted = hidden = false;
+        st.n_before = B.n;
+        trav_begin(st.ts, S);
+        st.in_round = true;
     }
     {
-        ++tc.rounds;
-        float cap_a = kInf;
-        int cap_id = 0x7fffffff;
-        float cap_sat = kInf;  // saturation bound: t_sat <= cap_sat
-        bool evicted = false, hidden = false;
-        const int n_before = B.n;
-        traverse(S, r, fmaxf(r.t0, lb_a),
+        const int n_before = st.n_before;
+        const int tr = traverse(S, r, fmaxf(r.t0, lb_a),
                  [&]() __attribute__((always_inline)) { return fminf(fminf(cap_a, cap_sat), t1f); },
-                 stack, err, tc,
+                 stack, spill, st.ts, suspend_at, err, tc,
                  [&](int p) __attribute__((always_inline)) {
                      const HotRec h = load_hot(S.hot, p);
                      return h.orig != excl && !surely_missed(h, r, S.r2);
@@ -644,6 +697,8 @@ __device__ __forceinline__ bool sweep_round(const SceneDev &S, const RayD &r, in
                      }
                      return false;
                  });
+        if (tr == kTravSuspended) return false;
+        st.in_round = false;
         if (hidden) return true;
         // window end: every primitive entering before t_w is in the buffer
         const double t_w = evicted ? (double)cap_a : r.t1;
@@ -884,8 +939,9 @@ __device__ __forceinline__ SweepOut sweep(const SceneDev &S, const RayD &r, int 
                                           float stop_a = -__builtin_huge_valf()) {
     SweepState<K> st;
     SweepOut out;
+    int spill[kStackSpill];
     sweep_start(st, out, r, mode);
-    while (!sweep_round<K>(S, r, excl, mode, u, target, stop_a, st, out, stack, err, tc)) {
+    while (!sweep_round<K>(S, r, excl, mode, u, target, stop_a, st, out, stack, spill, 0, err, tc)) {
     }
     return out;
 }
