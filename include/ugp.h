@@ -198,9 +198,10 @@ ugp_status ugp_trace_counts(ugp_ctx ctx, int mode, int64_t n_rays, const float *
  * heuristic against phase sampling.  Adds, per pixel, the sum over this call's
  * samples of the path radiance to sum_rgb [height][width][3] and of its square
  * to sumsq_rgb (or NULL).  The samples are traced in chunks of
- * max(1, min(spp, 2^24 / pixels)) samples of every pixel; within a chunk a
- * pool of about 2M path slots is refilled with new camera paths as paths end.
- * The sums do not depend on that scheduling.  Synchronises the stream once
+ * max(1, min(spp, 2^25 / pixels)) samples of every pixel, all paths of a
+ * chunk in flight together (about 230 B of device memory per path, 7.6 GB at
+ * 2^25 paths, held by the context until ugp_destroy).  The sums do not depend
+ * on that scheduling.  Synchronises the stream once
  * per bounce iteration (to read two queue counters). */
 ugp_status ugp_render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p,
                       float *sum_rgb, float *sumsq_rgb);

@@ -73,8 +73,8 @@ struct RenderBuffers {
 namespace {
 
 constexpr int kPersistBlocks = 4096;
-constexpr int64_t kPoolPaths = int64_t(1) << 21;   // path slots of the pool
-constexpr int64_t kChunkPaths = int64_t(1) << 24;  // paths of a chunk (radiance slots)
+constexpr int64_t kPoolPaths = int64_t(1) << 25;   // path slots of the pool
+constexpr int64_t kChunkPaths = int64_t(1) << 25;  // paths of a chunk (radiance slots)
 // iteration counters, two blocks used alternately (input / output queue):
 // [0] paths in the queue, [1] light samples, [2] environment samples,
 // [3] overflow, [4] collision work, [5] light work, [6] cache queries;
