@@ -18,9 +18,10 @@ Besides the JSON line's throughput it reports:
                index and the 8-B hit record) divided by its mean launch
                duration from HIP events recorded around every launch during
                the timed run, against 8 TB/s HBM; `traffic` is the HBM bytes
-               per launch measured with rocprofv3 counters (the summary under
-               profiles/), reported only while the kernel sources still hash
-               to the value recorded there;
+               per launch of this run: HBM bytes per collision ray measured
+               with rocprofv3 counters (the summary under profiles/) times the
+               collision rays per launch, reported only while the kernel
+               sources still hash to the value recorded there;
   cpu_baseline the FP64 CPU oracle on a bounded pixel subset of the same
                workload, on this host's cores.
 
@@ -54,8 +55,9 @@ def log(*a):
 
 
 def measured_traffic():
-    """HBM bytes per k_collide launch from the committed counter summary, or
-    None when the kernel sources changed since the counters were taken."""
+    """HBM bytes per collision ray of k_collide from the committed counter
+    summary, or None when the kernel sources changed since the counters were
+    taken."""
     import glob
     import hashlib
     import re
@@ -68,7 +70,7 @@ def measured_traffic():
             h.update(fh.read())
     text = open(COUNTERS).read()
     m1 = re.search(r"kernel_sources_sha256: ([0-9a-f]+)", text)
-    m2 = re.search(r"traffic_bytes_per_launch: ([0-9.e+]+)", text)
+    m2 = re.search(r"traffic_bytes_per_collision_ray: ([0-9.e+]+)", text)
     if not (m1 and m2) or m1.group(1) != h.hexdigest():
         return None
     return float(m2.group(1))
@@ -398,6 +400,8 @@ def main():
     launches = max(st["launches_collide"], 1)
     achieved = (bytes_per_coll_ray * st["collision_rays"] / launches) / (st["ms_collide"] / launches * 1e-3) / 1e9
     traffic = measured_traffic()
+    if traffic is not None:
+        traffic *= st["collision_rays"] / launches  # HBM bytes per launch of this run
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic / 1e9, 3),
@@ -406,7 +410,7 @@ def main():
                 "nodes_per_ray": round(cnt["cat_nodes"][0] / coll_rays_c, 2),
                 "prims_per_ray": round(cnt["cat_prims"][0] / coll_rays_c, 2),
                 "reloads_per_ray": round(cnt["cat_reloads"][0] / coll_rays_c, 2),
-                "mean_launch_ms": round(st["ms_collide"] / launches, 4)}
+                "mean_launch_ms": round(st["ms_collide"] / launches, 4), "launches": launches}
 
     cpu = None
     if not args.no_cpu_baseline:

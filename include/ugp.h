@@ -244,6 +244,14 @@ typedef struct {
  * traffic).  [host] call, no device work. */
 ugp_status ugp_set_profiling(ugp_ctx ctx, int level);
 
+/* Path slots of later ugp_render calls: 0 (the default) keeps every path of
+ * a chunk in flight (up to 2^25); a smaller pool (>= 64) bounds the render
+ * buffers to about 230 B per slot and refills slots with new camera paths as
+ * paths end, at some cost in throughput.  Results do not depend on it
+ * (except the cache training of nrc_mode 1, whose record order does).
+ * Buffers already allocated are kept.  [host] call, no device work. */
+ugp_status ugp_set_path_pool(ugp_ctx ctx, int64_t slots);
+
 /* Statistics of the last ugp_render call (synchronises the stream). */
 ugp_status ugp_get_render_stats(ugp_ctx ctx, ugp_render_stats *out);
 

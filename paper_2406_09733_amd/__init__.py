@@ -64,7 +64,7 @@ class _Stats(C.Structure):
 
 EXPORTS = ["ugp_create", "ugp_destroy", "ugp_set_stream", "ugp_build_bvh", "ugp_transmittance",
            "ugp_sample_collision", "ugp_saturation", "ugp_emitter_query", "ugp_render", "ugp_sync",
-           "ugp_set_profiling", "ugp_get_render_stats", "ugp_trace_counts", "ugp_status_string",
+           "ugp_set_profiling", "ugp_set_path_pool", "ugp_get_render_stats", "ugp_trace_counts", "ugp_status_string",
            "ugp_nrc_num_params", "ugp_nrc_set_weights", "ugp_nrc_get_weights", "ugp_nrc_encode",
            "ugp_nrc_forward", "ugp_nrc_train_step", "ugp_nrc_records"]
 
@@ -88,6 +88,7 @@ def lib():
         L.ugp_render.argtypes = [vp, C.POINTER(_Camera), C.POINTER(_Params), vp, vp]
         L.ugp_sync.argtypes = [vp]
         L.ugp_set_profiling.argtypes = [vp, C.c_int]
+        L.ugp_set_path_pool.argtypes = [vp, C.c_int64]
         L.ugp_trace_counts.argtypes = [vp, C.c_int, i64, vp, vp, vp, vp, vp]
         L.ugp_get_render_stats.argtypes = [vp, C.POINTER(_Stats)]
         L.ugp_nrc_num_params.argtypes = []
@@ -276,6 +277,10 @@ class Context:
     def set_profiling(self, level: int):
         """ugp_set_profiling: 0 off, 1 time kernels with HIP events, 2 also count traversal work."""
         _check("ugp_set_profiling", lib().ugp_set_profiling(self.h, int(level)))
+
+    def set_path_pool(self, slots: int):
+        """ugp_set_path_pool: path slots of later renders (0: every path of a chunk in flight)."""
+        _check("ugp_set_path_pool", lib().ugp_set_path_pool(self.h, int(slots)))
 
     def render_stats(self) -> dict:
         """ugp_get_render_stats of the last render (synchronises)."""

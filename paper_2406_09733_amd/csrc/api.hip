@@ -234,6 +234,12 @@ ugp_status ugp_set_profiling(ugp_ctx ctx, int level) {
     return UGP_OK;
 }
 
+ugp_status ugp_set_path_pool(ugp_ctx ctx, int64_t slots) {
+    if (!ctx || slots < 0 || (slots > 0 && slots < 64)) return UGP_ERR_INVALID_ARGUMENT;
+    ctx->path_pool = slots;
+    return UGP_OK;
+}
+
 ugp_status ugp_get_render_stats(ugp_ctx ctx, ugp_render_stats *out) {
     if (!ctx || !out) return UGP_ERR_INVALID_ARGUMENT;
     DeviceGuard g(ctx->device);

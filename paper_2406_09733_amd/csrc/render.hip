@@ -748,7 +748,7 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
     // chunks of `cs` samples of every pixel share the pool of path slots
     const int cs = (int)std::max<int64_t>(1, std::min<int64_t>(p->spp, kChunkPaths / npix));
     const int64_t lcap = npix * cs;
-    const int64_t pool = std::min<int64_t>(kPoolPaths, lcap);
+    const int64_t pool = std::min<int64_t>(ctx->path_pool > 0 ? ctx->path_pool : kPoolPaths, lcap);
     hipError_t e = ensure_buffers(ctx, pool, lcap);
     if (e != hipSuccess) return e;
     RenderBuffers *rb = ctx->rb;

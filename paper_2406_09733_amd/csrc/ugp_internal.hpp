@@ -77,6 +77,7 @@ struct ugp_ctx_s {
                                     //  cache queries, cache training records, -, -, -]
     unsigned long long *counters = nullptr;  // [3] traversal counters (profiling level 2)
     int profiling = 0;
+    int64_t path_pool = 0;  // path slots of ugp_render (0: every path of a chunk)
     // event pairs of the last render, by category: 0 collide main, 1 collide wide, 2 light, 3 env,
     // 4 shade, 5 ray sort
     std::vector<hipEvent_t> ev_pool;

@@ -285,3 +285,26 @@ def test_render_parity_needles(ctx, orc, torch):
     frac, d, se = _image_parity(ctx, orc, sc, "needles", 4, 6, 4, res=(96, 96))
     assert frac < 0.01
     assert d <= 3 * se + 1e-6
+
+
+@pytest.mark.parametrize("pool", [64, 3000])
+def test_render_independent_of_path_pool(ctx, torch, pool):
+    # a small pool refills its slots with new camera paths as paths end; the
+    # per-path radiance slots and the sample-order accumulation make the image
+    # bit-identical to the one with every path in flight
+    _say(f"render with a pool of {pool} path slots vs all paths in flight")
+    sc = scenes.mixed_100k()
+    _build(ctx, sc)
+    cam = dict(scenes.camera("mixed_100k"), width=96, height=80)
+    p = {"spp": 5, "max_depth": 8, "seed": 7, "env_radiance": (0.2, 0.3, 0.4)}
+    ctx.set_path_pool(0)
+    s0, q0 = ctx.render(cam, p)
+    ctx.sync()
+    try:
+        ctx.set_path_pool(pool)
+        s1, q1 = ctx.render(cam, p)
+        ctx.sync()
+    finally:
+        ctx.set_path_pool(0)
+    assert torch.equal(s0, s1) and torch.equal(q0, q1)
+    assert float(s0.sum()) > 0
