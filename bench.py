@@ -28,7 +28,8 @@ Besides the JSON line's throughput it reports:
 With --time-to-rmse it instead runs the second half of the metric on the same
 scene: progressive renders of the plain tracer and of the neural-cache tracer
 (paths end in the cache after two scattering events; the cache trains online,
-one step per wavefront) against a 4096-spp plain reference, RMSE over all
+a few Adam steps per wavefront of 32 samples per pixel) against a 4096-spp
+plain reference, RMSE over all
 pixels and channels of the images clamped to [0, 1], against wall time.  It
 prints one JSON line of its own (see time_to_rmse).
 """
@@ -154,7 +155,7 @@ def time_to_rmse(args):
     ctx.build_bvh(sc)
     ctx.sync()
     base = {"max_depth": rs["max_depth"], "seed": rs["seed"]}
-    wf = max(1, min(args.ref_spp // 2, (1 << 21) // (W * H)))
+    wf = max(1, min(args.ref_spp // 2, args.rmse_wavefront))
     ref_file = args.reference
     halves = None
     if ref_file and os.path.exists(ref_file):
@@ -214,7 +215,7 @@ def time_to_rmse(args):
                "final": {"t_s": curve[-1][0], "spp": curve[-1][1], "rmse": curve[-1][2]},
                "ms_per_wavefront": round(1e3 * curve[-1][0] / len(curve), 2),
                "curve": curve[:: max(1, len(curve) // 40)]}
-        if extra.get("nrc_mode", 0) in (1, 2):
+        if extra.get("nrc_mode", 0) == 1:
             out["last_loss"] = st["nrc_loss"]
         log(f"[rmse] {label}: {json.dumps({k: v for k, v in out.items() if k != 'curve'})}")
         return out, curve
@@ -314,6 +315,8 @@ def main():
     ap.add_argument("--rmse-target", type=float, default=0.01)
     ap.add_argument("--rmse-seconds", type=float, default=60.0, help="wall-time cap per tracer")
     ap.add_argument("--rmse-max-spp", type=int, default=1 << 16)
+    ap.add_argument("--rmse-wavefront", type=int, default=32,
+                    help="samples per pixel per render call (the RMSE is taken after each call)")
     ap.add_argument("--nrc-lr", type=float, default=1e-2)
     ap.add_argument("--nrc-steps", type=int, default=4, help="Adam steps per chunk")
     ap.add_argument("--nrc-clamp", type=float, default=20.0, help="training target clamp (radiance units)")
