@@ -511,26 +511,10 @@ __global__ void k_depth(int64_t n, const int32_t *parent_node, const int32_t *pa
     atomicMax(depth, d);
 }
 
-// Collapse of the binary radix tree into a 4-wide hierarchy: the binary
-// nodes at even depth become 4-wide nodes whose slots are their grandchildren
-// (or a child, when that child is a leaf).  A 4-wide node is 128 B:
-// lo.x[4], lo.y[4], lo.z[4], hi.x[4], hi.y[4], hi.z[4], ref[4], pad; a ref
-// >= 0 is a 4-wide node, < 0 the leaf primitive ~ref, kEmptySlot unused.
-__global__ void k_node_parity(int64_t n, const int32_t *parent_node, int32_t *even, uint32_t *err) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n - 1 || (*err & 16u)) return;
-    int d = 0;
-    int32_t p = (int32_t)i;
-    while (p != 0) {
-        p = parent_node[p];
-        if (++d > 4096) {
-            atomicOr(err, 16u);
-            break;
-        }
-    }
-    even[i] = (d & 1) == 0 ? 1 : 0;
-}
-
+// The binary radix tree is collapsed into a 4-wide hierarchy (below).  A
+// 4-wide node is 128 B: lo.x[4], lo.y[4], lo.z[4], hi.x[4], hi.y[4], hi.z[4],
+// ref[4], pad; a ref >= 0 is a 4-wide node, < 0 the leaf primitive ~ref,
+// kEmptySlot unused.
 __device__ __forceinline__ void node_child(const float4 *nodes, int32_t b, int side, float box[6], int32_t &ref) {
     const float *nd = reinterpret_cast<const float *>(nodes + 4 * (int64_t)b);
     const int o = side ? 6 : 0;
@@ -538,35 +522,59 @@ __device__ __forceinline__ void node_child(const float4 *nodes, int32_t b, int s
     ref = side ? __float_as_int(nd[13]) : __float_as_int(nd[12]);
 }
 
-__global__ void k_collapse(int64_t n, const float4 *nodes, const int32_t *even, const int32_t *map,
-                           float4 *nodes4) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= n - 1 || !even[b]) return;
+// Greedy collapse, one level of the 4-wide hierarchy per launch: a 4-wide
+// node rooted at binary node b starts with b's two children and repeatedly
+// opens its internal child of largest surface area (the child a ray is most
+// likely to enter) until it holds four children or only leaves.  Its internal
+// children become the roots of the next level's nodes: each gets an output
+// slot (atomic counter) and a place in the next frontier.
+__global__ void k_collapse_greedy(const float4 *nodes, const int32_t *fin, const int32_t *fout, int32_t nf,
+                                  int32_t *gin, int32_t *gout, int32_t *ng, int32_t *n4, float4 *nodes4) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nf) return;
     float lo[3][4], hi[3][4];
     int32_t ref[4];
     int ns = 0;
     for (int side = 0; side < 2; ++side) {
         float box[6];
-        int32_t c;
-        node_child(nodes, (int32_t)b, side, box, c);
-        if (c < 0) {
-            for (int k = 0; k < 3; ++k) { lo[k][ns] = box[k]; hi[k][ns] = box[3 + k]; }
-            ref[ns++] = c;
-        } else {
-            for (int g = 0; g < 2; ++g) {
-                float gb[6];
-                int32_t gc;
-                node_child(nodes, c, g, gb, gc);
-                for (int k = 0; k < 3; ++k) { lo[k][ns] = gb[k]; hi[k][ns] = gb[3 + k]; }
-                ref[ns++] = gc < 0 ? gc : map[gc];
+        node_child(nodes, fin[i], side, box, ref[ns]);
+        for (int k = 0; k < 3; ++k) { lo[k][ns] = box[k]; hi[k][ns] = box[3 + k]; }
+        ++ns;
+    }
+    while (ns < 4) {
+        int best = -1;
+        float best_area = -1.f;
+        for (int k = 0; k < ns; ++k) {
+            if (ref[k] < 0) continue;
+            const float ex = hi[0][k] - lo[0][k], ey = hi[1][k] - lo[1][k], ez = hi[2][k] - lo[2][k];
+            const float area = ex * ey + ey * ez + ez * ex;
+            if (area > best_area) {
+                best_area = area;
+                best = k;
             }
         }
+        if (best < 0) break;
+        const int32_t c = ref[best];
+        float box[6];
+        node_child(nodes, c, 0, box, ref[best]);
+        for (int k = 0; k < 3; ++k) { lo[k][best] = box[k]; hi[k][best] = box[3 + k]; }
+        node_child(nodes, c, 1, box, ref[ns]);
+        for (int k = 0; k < 3; ++k) { lo[k][ns] = box[k]; hi[k][ns] = box[3 + k]; }
+        ++ns;
+    }
+    for (int k = 0; k < ns; ++k) {
+        if (ref[k] < 0) continue;
+        const int32_t slot = atomicAdd(n4, 1);
+        const int32_t q = atomicAdd(ng, 1);
+        gin[q] = ref[k];
+        gout[q] = slot;
+        ref[k] = slot;
     }
     for (; ns < 4; ++ns) {
         for (int k = 0; k < 3; ++k) { lo[k][ns] = 3.0e38f; hi[k][ns] = -3.0e38f; }
         ref[ns] = kEmptySlot;
     }
-    float4 *o = nodes4 + 8 * (int64_t)map[b];
+    float4 *o = nodes4 + 8 * (int64_t)fout[i];
     o[0] = make_float4(lo[0][0], lo[0][1], lo[0][2], lo[0][3]);
     o[1] = make_float4(lo[1][0], lo[1][1], lo[1][2], lo[1][3]);
     o[2] = make_float4(lo[2][0], lo[2][1], lo[2][2], lo[2][3]);
@@ -743,31 +751,54 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
     sc.depth = nr > 1 ? h_depth : 1;
     sc.root = nr > 1 ? 0 : ~0;
     if (nr > 1) {
-        // 4-wide collapse (flags / keys reused as scratch)
-        int32_t *even = flags, *map = (int32_t *)keys;
-        int32_t h_n4 = 0, h_last = 0;
-        hipLaunchKernelGGL(k_node_parity, dim3(blocks(nr - 1)), dim3(kThreads), 0, st, nr, pnode, even, ctx->err);
-        UGP_CHECK(hipGetLastError());
-        UGP_CHECK(exclusive_scan(even, map, nr - 1, st));
-        UGP_CHECK(hipMemcpyAsync(&h_n4, map + (nr - 2), sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        UGP_CHECK(hipMemcpyAsync(&h_last, even + (nr - 2), sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        UGP_CHECK(hipMemcpyAsync(&h_err, ctx->err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-        UGP_CHECK(hipStreamSynchronize(st));
-        if (h_err & 16u) {
-            e = hipErrorUnknown;
+        // greedy 4-wide collapse, level by level (keys / tk / vals / tv reused as frontiers)
+        int32_t *fin = (int32_t *)keys, *fout = (int32_t *)tk, *gin = (int32_t *)vals, *gout = (int32_t *)tv;
+        int32_t *cnt = nullptr;  // [0] next frontier, [1] 4-wide nodes
+        float4 *big = nullptr;
+        UGP_CHECK(hipMalloc((void **)&cnt, sizeof(int32_t) * 2));
+        e = hipMalloc((void **)&big, sizeof(float4) * 8 * (size_t)(nr - 1));
+        if (e != hipSuccess) {
+            hipFree(cnt);
             goto fail;
         }
-        h_n4 += h_last;
+        const int32_t init[2] = {0, 1};
+        UGP_CHECK(hipMemcpyAsync(cnt, init, sizeof(init), hipMemcpyHostToDevice, st));
+        UGP_CHECK(hipMemsetAsync(fin, 0, sizeof(int32_t), st));
+        UGP_CHECK(hipMemsetAsync(fout, 0, sizeof(int32_t), st));
+        int32_t nf = 1, levels = 0;
+        while (nf > 0) {
+            UGP_CHECK(hipMemsetAsync(cnt, 0, sizeof(int32_t), st));
+            hipLaunchKernelGGL(k_collapse_greedy, dim3(blocks(nf)), dim3(kThreads), 0, st,
+                               (const float4 *)sc.nodes, (const int32_t *)fin, (const int32_t *)fout, nf, gin,
+                               gout, cnt, cnt + 1, big);
+            UGP_CHECK(hipGetLastError());
+            UGP_CHECK(hipMemcpyAsync(&nf, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            UGP_CHECK(hipStreamSynchronize(st));
+            std::swap(fin, gin);
+            std::swap(fout, gout);
+            if (++levels > 4096) {
+                hipFree(big);
+                hipFree(cnt);
+                e = hipErrorUnknown;
+                goto fail;
+            }
+        }
+        int32_t h_n4 = 0;
+        e = hipMemcpy(&h_n4, cnt + 1, sizeof(int32_t), hipMemcpyDeviceToHost);
+        hipFree(cnt);
         float4 *nodes4 = nullptr;
-        UGP_CHECK(hipMalloc((void **)&nodes4, sizeof(float4) * 8 * (size_t)h_n4));
-        hipLaunchKernelGGL(k_collapse, dim3(blocks(nr - 1)), dim3(kThreads), 0, st, nr, (const float4 *)sc.nodes,
-                           (const int32_t *)even, (const int32_t *)map, nodes4);
-        UGP_CHECK(hipGetLastError());
+        if (e == hipSuccess) e = hipMalloc((void **)&nodes4, sizeof(float4) * 8 * (size_t)h_n4);
+        if (e != hipSuccess) {
+            hipFree(big);
+            goto fail;
+        }
+        UGP_CHECK(hipMemcpyAsync(nodes4, big, sizeof(float4) * 8 * (size_t)h_n4, hipMemcpyDeviceToDevice, st));
         UGP_CHECK(hipStreamSynchronize(st));
+        hipFree(big);
         hipFree(sc.nodes);
         sc.nodes = nodes4;
         sc.n_nodes4 = h_n4;
-        sc.depth = (sc.depth + 1) / 2 + 1;
+        sc.depth = levels;
         // a 4-wide node pushes at most three entries
         if (3 * sc.depth > kStackSize + kStackSpill) {
             e = hipErrorNotSupported;

@@ -230,11 +230,34 @@ __device__ __forceinline__ float half_kernel_at(const Chord &c, double t) {
 // `hi()` is re-read after leaves so a shrinking upper bound culls at once.
 // ---------------------------------------------------------------------------
 // slab test of one box against the ray on [lo, hi]: entry distance or +inf
+//
+// The plane at coordinate x is crossed at t = (x - o) / d, taken as
+// fma(x, 1/d, c) with c = -o/d.  Rounding c costs at most half an ulp of
+// |o/d|; the per-ray constants move c outwards by 2^-22 |o/d| (the plane of
+// the low corner is the entry when 1/d > 0, the exit otherwise), so a slab
+// interval never shrinks below the exact one.
+struct SlabC {
+    float lx, hx, ly, hy, lz, hz;
+};
+
+__device__ __forceinline__ SlabC slab_consts(const RayD &r) {
+    SlabC k;
+    auto one = [](float o, float inv, float &cl, float &ch) __attribute__((always_inline)) {
+        const float c = -o * inv, m = 2.384185791e-7f * fabsf(c);
+        cl = inv >= 0.f ? c - m : c + m;
+        ch = inv >= 0.f ? c + m : c - m;
+    };
+    one(r.ox, r.idx, k.lx, k.hx);
+    one(r.oy, r.idy, k.ly, k.hy);
+    one(r.oz, r.idz, k.lz, k.hz);
+    return k;
+}
+
 __device__ __forceinline__ float slab(float lx, float ly, float lz, float hx, float hy, float hz,
-                                      const RayD &r, float lo, float hi) {
-    const float ax = (lx - r.ox) * r.idx, bx = (hx - r.ox) * r.idx;
-    const float ay = (ly - r.oy) * r.idy, by = (hy - r.oy) * r.idy;
-    const float az = (lz - r.oz) * r.idz, bz = (hz - r.oz) * r.idz;
+                                      const RayD &r, const SlabC &k, float lo, float hi) {
+    const float ax = fmaf(lx, r.idx, k.lx), bx = fmaf(hx, r.idx, k.hx);
+    const float ay = fmaf(ly, r.idy, k.ly), by = fmaf(hy, r.idy, k.hy);
+    const float az = fmaf(lz, r.idz, k.lz), bz = fmaf(hz, r.idz, k.hz);
     const float tn = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), lo));
     const float tf = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), hi));
     return (tn <= tf + 5e-7f * fmaxf(fabsf(tn), fabsf(tf))) ? tn : kInf;
@@ -297,6 +320,7 @@ __device__ __forceinline__ int traverse(const SceneDev &S, const RayD &r, float 
         return pre(~ref) && leaf(~ref) ? kTravStopped : kTravDone;
     }
     __shared__ int pend[kPend * kBlock];
+    const SlabC kc = slab_consts(r);
     int np = 0;             // queued leaves of this lane
     bool nodes = ts.nodes;  // this lane still has a node to visit (ref)
     int sp = ts.sp;
@@ -315,10 +339,10 @@ __device__ __forceinline__ int traverse(const SceneDev &S, const RayD &r, float 
             const float4 *nd = S.nodes + 8 * (int64_t)ref;
             const float4 lx = nd[0], ly = nd[1], lz = nd[2], hx = nd[3], hy = nd[4], hz = nd[5], rf = nd[6];
             const float h0 = hi();
-            float t0 = slab(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, r, lo, h0);
-            float t1 = slab(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, r, lo, h0);
-            float t2 = slab(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, r, lo, h0);
-            float t3 = slab(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, r, lo, h0);
+            float t0 = slab(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, r, kc, lo, h0);
+            float t1 = slab(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, r, kc, lo, h0);
+            float t2 = slab(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, r, kc, lo, h0);
+            float t3 = slab(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, r, kc, lo, h0);
             int r0 = __float_as_int(rf.x), r1 = __float_as_int(rf.y), r2 = __float_as_int(rf.z),
                 r3 = __float_as_int(rf.w);
             // unused slots carry an inverted box, which a slab test would take as
