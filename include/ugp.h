@@ -229,13 +229,15 @@ typedef struct {
     double ms_sort;          /* ... of the ray-sorting kernels */
     int32_t launches_collide, launches_light, launches_env;
     /* the three traversal counters split by kernel: [0] collision, [1] collision
-       overflow pass, [2] light samples, [3] environment samples (level 2, else -1) */
+       overflow pass and tail kernel, [2] light samples, [3] environment samples
+       (level 2, else -1) */
     int64_t cat_nodes[4], cat_prims[4], cat_reloads[4];
     int64_t nrc_queries;     /* paths that ended in the radiance cache */
     int64_t nrc_records;     /* training records appended (before the per-pass cap) */
     double ms_nrc_infer;     /* duration of the cache inference launches (level >= 1, else -1) */
     double ms_nrc_train;     /* ... of the cache training steps */
     float nrc_loss;          /* loss of the last training step (NaN if none) */
+    double ms_tail;          /* duration of the tail kernel launches (level >= 1, else -1) */
 } ugp_render_stats;
 
 /* Profiling level of later ugp_render calls: 0 off; 1 every kernel launch is
@@ -251,6 +253,14 @@ ugp_status ugp_set_profiling(ugp_ctx ctx, int level);
  * (except the cache training of nrc_mode 1, whose record order does).
  * Buffers already allocated are kept.  [host] call, no device work. */
 ugp_status ugp_set_path_pool(ugp_ctx ctx, int64_t slots);
+
+/* Live paths at or below which ugp_render runs the remaining bounces of a
+ * chunk (once no path is left to generate, from the second bounce on) in one
+ * kernel, one lane following its path to the end, instead of one wavefront
+ * launch per bounce; 0 disables it.  Default 65536.  Results do not depend on
+ * it (except the cache training of nrc_mode 1, whose record order does).
+ * [host] call, no device work. */
+ugp_status ugp_set_tail_paths(ugp_ctx ctx, int64_t paths);
 
 /* Statistics of the last ugp_render call (synchronises the stream). */
 ugp_status ugp_get_render_stats(ugp_ctx ctx, ugp_render_stats *out);

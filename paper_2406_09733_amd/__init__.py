@@ -59,12 +59,12 @@ class _Stats(C.Structure):
                 ("launches_light", C.c_int32), ("launches_env", C.c_int32),
                 ("cat_nodes", C.c_int64 * 4), ("cat_prims", C.c_int64 * 4), ("cat_reloads", C.c_int64 * 4),
                 ("nrc_queries", C.c_int64), ("nrc_records", C.c_int64), ("ms_nrc_infer", C.c_double),
-                ("ms_nrc_train", C.c_double), ("nrc_loss", C.c_float)]
+                ("ms_nrc_train", C.c_double), ("nrc_loss", C.c_float), ("ms_tail", C.c_double)]
 
 
 EXPORTS = ["ugp_create", "ugp_destroy", "ugp_set_stream", "ugp_build_bvh", "ugp_transmittance",
            "ugp_sample_collision", "ugp_saturation", "ugp_emitter_query", "ugp_render", "ugp_sync",
-           "ugp_set_profiling", "ugp_set_path_pool", "ugp_get_render_stats", "ugp_trace_counts", "ugp_status_string",
+           "ugp_set_profiling", "ugp_set_path_pool", "ugp_set_tail_paths", "ugp_get_render_stats", "ugp_trace_counts", "ugp_status_string",
            "ugp_nrc_num_params", "ugp_nrc_set_weights", "ugp_nrc_get_weights", "ugp_nrc_encode",
            "ugp_nrc_forward", "ugp_nrc_train_step", "ugp_nrc_records"]
 
@@ -89,6 +89,7 @@ def lib():
         L.ugp_sync.argtypes = [vp]
         L.ugp_set_profiling.argtypes = [vp, C.c_int]
         L.ugp_set_path_pool.argtypes = [vp, C.c_int64]
+        L.ugp_set_tail_paths.argtypes = [vp, C.c_int64]
         L.ugp_trace_counts.argtypes = [vp, C.c_int, i64, vp, vp, vp, vp, vp]
         L.ugp_get_render_stats.argtypes = [vp, C.POINTER(_Stats)]
         L.ugp_nrc_num_params.argtypes = []
@@ -281,6 +282,10 @@ class Context:
     def set_path_pool(self, slots: int):
         """ugp_set_path_pool: path slots of later renders (0: every path of a chunk in flight)."""
         _check("ugp_set_path_pool", lib().ugp_set_path_pool(self.h, int(slots)))
+
+    def set_tail_paths(self, paths: int):
+        """ugp_set_tail_paths: live paths at or below which a chunk's last bounces run in one kernel (0: never)."""
+        _check("ugp_set_tail_paths", lib().ugp_set_tail_paths(self.h, int(paths)))
 
     def render_stats(self) -> dict:
         """ugp_get_render_stats of the last render (synchronises)."""

@@ -240,6 +240,12 @@ ugp_status ugp_set_path_pool(ugp_ctx ctx, int64_t slots) {
     return UGP_OK;
 }
 
+ugp_status ugp_set_tail_paths(ugp_ctx ctx, int64_t paths) {
+    if (!ctx || paths < 0) return UGP_ERR_INVALID_ARGUMENT;
+    ctx->tail_paths = paths;
+    return UGP_OK;
+}
+
 ugp_status ugp_get_render_stats(ugp_ctx ctx, ugp_render_stats *out) {
     if (!ctx || !out) return UGP_ERR_INVALID_ARGUMENT;
     DeviceGuard g(ctx->device);
@@ -276,13 +282,13 @@ ugp_status ugp_get_render_stats(ugp_ctx ctx, ugp_render_stats *out) {
         }
     }
     out->ms_collide = out->ms_collide_wide = out->ms_light = out->ms_env = out->ms_shade = out->ms_sort = -1.0;
-    out->ms_nrc_infer = out->ms_nrc_train = -1.0;
+    out->ms_nrc_infer = out->ms_nrc_train = out->ms_tail = -1.0;
     if (ctx->ev_cat_valid) {
-        double ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        int cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        double ms[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        int cnt[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         for (const auto &u : ctx->ev_used) {
             float t = 0.f;
-            if (u.first >= 0 && u.first < 8 &&
+            if (u.first >= 0 && u.first < 9 &&
                 hipEventElapsedTime(&t, ctx->ev_pool[u.second], ctx->ev_pool[u.second + 1]) == hipSuccess) {
                 ms[u.first] += t;
                 cnt[u.first] += 1;
@@ -296,6 +302,7 @@ ugp_status ugp_get_render_stats(ugp_ctx ctx, ugp_render_stats *out) {
         out->ms_sort = ms[5];
         out->ms_nrc_infer = ms[6];
         out->ms_nrc_train = ms[7];
+        out->ms_tail = ms[8];
         out->launches_collide = cnt[0];
         out->launches_light = cnt[2];
         out->launches_env = cnt[3];

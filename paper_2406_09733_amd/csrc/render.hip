@@ -330,6 +330,163 @@ __global__ __launch_bounds__(kBlock, 2) void k_collide(SceneDev S, PassArgs P, Q
     flush_counts(S, tc);
 }
 
+// What the shading of one path vertex produces (the wavefront kernel appends
+// it to the queues; the tail kernel consumes it at once).
+struct ShadeOut {
+    bool cont = false, do_nee = false, do_env = false, do_qry = false, do_rec = false;
+    float4 ca{}, cb{}, cc{};                  // next collision ray (origin + pdf, direction + excluded, beta + bits)
+    float4 na{}, nb{}, nc{};                  // light sample (origin + target, direction + excluded, weight + pixel)
+    float4 ea{}, eb{}, ec{};                  // environment sample
+    float4 r0{}, r1{}, r2{}, r3{}, r4{}, r5{};  // cache query / training record
+};
+
+// Shading of one path vertex after its collision `hit` (prim, t bits):
+// emission pick-up (MIS against the light pdf of the previous vertex),
+// environment on escape, one light sample and one environment sample, phase
+// sampling; the picked-up radiance is added to the path's slot L[pixel].
+__device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, const float4 A, const float4 B,
+                                          const float4 C, const int v, const int2 hit, float4 *L, ShadeOut &out) {
+    const int pbits = __float_as_int(C.w);
+    const int pix = pbits & kPixMask;
+    const bool train = (pbits & kTrainBit) != 0;
+    const float p_prev = A.w;
+    const V3 o = f3(A), d = f3(B);
+    V3 beta = f3(C);
+    const Rng4 g0 = path_rng(P, (uint32_t)pix, (uint32_t)v, 0);
+    const Rng4 g1 = path_rng(P, (uint32_t)pix, (uint32_t)v, 1);
+    V3 Ladd = v3(0.f, 0.f, 0.f);
+    if (hit.x < 0) {
+        if (P.has_env) {
+            float w = 1.f;
+            if (v > 1) {
+                if (P.mis_mode == 2) w = 0.f;
+                else if (P.mis_mode == 0) w = p_prev / (p_prev + 0.25f * kInvPi);
+            }
+            Ladd = w * mul(beta, v3(P.env[0], P.env[1], P.env[2]));
+        }
+    } else {
+        const int k = hit.x;
+        const float4 c0 = S.cold[3 * k], c1 = S.cold[3 * k + 1], c2 = S.cold[3 * k + 2];
+        const V3 x = o + __int_as_float(hit.y) * d;
+        const V3 Le = f3(c2);
+        if (nonzero(Le)) {
+            float w = 1.f;
+            if (v > 1) {
+                const float pn = nee_pdf(S, k, o);
+                if (P.mis_mode == 2) w = pn > 0.f ? 0.f : 1.f;
+                else if (P.mis_mode == 0) w = p_prev / (p_prev + pn);
+            }
+            Ladd = w * mul(beta, Le);
+        }
+        bool stop = false;
+        if (v <= P.max_depth && P.nrc.mode != 0) {
+            // radiance cache: inputs of this vertex (position, outgoing
+            // direction, facet normal turned toward it, roughness, albedo)
+            const V3 wo = -d;
+            const V3 nf = dot(f3(c0), wo) >= 0.f ? f3(c0) : -f3(c0);
+            out.r0 = make_float4(x.x, x.y, x.z, wo.x);
+            out.r1 = make_float4(wo.y, wo.z, nf.x, nf.y);
+            out.r2 = make_float4(nf.z, c1.w, c1.x, c1.y);
+            out.r3 = make_float4(c1.z, 0.f, 0.f, 0.f);
+            out.r4 = make_float4(beta.x, beta.y, beta.z, __int_as_float(pix));
+            if (!train && v == P.nrc.term + 1) {
+                stop = true;
+                out.do_qry = P.nrc.mode != 3;
+            } else if (train) {
+                const float4 l = L[pix];
+                out.r5 = make_float4(l.x + Ladd.x, l.y + Ladd.y, l.z + Ladd.z, (float)v);
+                out.do_rec = true;
+            }
+        }
+        if (v <= P.max_depth && !stop) {
+            const V3 wo = -d;
+            const Facet F = facet(f3(c0), wo);
+            const V3 wol = to_local(F, wo);
+            const int mat = __float_as_int(c0.w);
+            const V3 alb = f3(c1);
+            const float rough = c1.w;
+            // light sample: one emitter, uniform in the cone of its bounding sphere
+            if (S.n_emit > 0 && P.mis_mode != 1) {
+                // floor(u * n_emit) in exact integer arithmetic (u has 24 bits)
+                int j = (int)(((uint64_t)(g0.u[1] * 16777216.f) * (uint64_t)S.n_emit) >> 24);
+                j = min(j, S.n_emit - 1);
+                const int e = S.emit[j];
+                const int es = S.inv[e];
+                const float4 eh = S.hot[4 * es];
+                const float rs = S.cold[3 * e + 2].w;
+                V3 cd = v3(eh.x - x.x, eh.y - x.y, eh.z - x.z);
+                const float d2 = dot(cd, cd);
+                if (d2 > rs * rs) {
+                    cd = rsqrtf(d2) * cd;
+                    const float sin2 = rs * rs / d2;
+                    const float cosm = sqrtf(fmaxf(0.f, 1.f - sin2));
+                    const float omc = sin2 / (1.f + cosm);
+                    const float pn = 1.f / ((float)S.n_emit * 2.f * kPi * omc);
+                    const float omcos = g0.u[2] * omc;
+                    const float cost = 1.f - omcos;
+                    const float sint = sqrtf(fmaxf(0.f, omcos * (2.f - omcos)));
+                    float sp, cp;
+                    sincosf(2.f * kPi * g0.u[3], &sp, &cp);
+                    V3 b1, b2;
+                    onb(cd, b1, b2);
+                    const V3 wl = (sint * cp) * b1 + (sint * sp) * b2 + cost * cd;
+                    float pph;
+                    const V3 f = phase_eval_local(mat, alb, rough, wol, to_local(F, wl), pph);
+                    Chord tc;
+                    const RayD lr = make_ray(x.x, x.y, x.z, wl.x, wl.y, wl.z, 0.f, __builtin_huge_val());
+                    if (nonzero(f) && chord(load_hot(S.hot, es), lr, S.r2, tc)) {
+                        const float w = P.mis_mode == 2 ? 1.f : pn / (pn + pph);
+                        const float4 eL = S.cold[3 * e + 2];
+                        const V3 wt = (w / pn) * mul(mul(beta, f), f3(eL));
+                        out.do_nee = true;
+                        out.na = make_float4(x.x, x.y, x.z, __int_as_float(e));
+                        out.nb = make_float4(wl.x, wl.y, wl.z, __int_as_float(k));
+                        out.nc = make_float4(wt.x, wt.y, wt.z, __int_as_float(pix));
+                    }
+                }
+            }
+            // environment sample: uniform direction
+            if (P.has_env && P.mis_mode != 1) {
+                const float z = 1.f - 2.f * g1.u[2];
+                const float rr = sqrtf(fmaxf(0.f, 1.f - z * z));
+                float sp, cp;
+                sincosf(2.f * kPi * g1.u[3], &sp, &cp);
+                const V3 wl = v3(rr * cp, rr * sp, z);
+                float pph;
+                const V3 f = phase_eval_local(mat, alb, rough, wol, to_local(F, wl), pph);
+                if (nonzero(f)) {
+                    const float pe = 0.25f * kInvPi;
+                    const float w = P.mis_mode == 2 ? 1.f : pe / (pe + pph);
+                    const V3 wt = (w / pe) * mul(mul(beta, f), v3(P.env[0], P.env[1], P.env[2]));
+                    out.do_env = true;
+                    out.ea = make_float4(x.x, x.y, x.z, 0.f);
+                    out.eb = make_float4(wl.x, wl.y, wl.z, __int_as_float(k));
+                    out.ec = make_float4(wt.x, wt.y, wt.z, __int_as_float(pix));
+                }
+            }
+            // continue by phase sampling from the chord centre, skipping k
+            V3 wgt;
+            float pdf;
+            const V3 wil = phase_sample_local(mat, alb, rough, wol, g1.u[0], g1.u[1], wgt, pdf);
+            if (pdf > 0.f) {
+                beta = mul(beta, wgt);
+                if (nonzero(beta)) {
+                    const V3 wi = to_world(F, wil);
+                    out.cont = true;
+                    out.ca = make_float4(x.x, x.y, x.z, pdf);
+                    out.cb = make_float4(wi.x, wi.y, wi.z, __int_as_float(k));
+                    out.cc = make_float4(beta.x, beta.y, beta.z, __int_as_float(pbits));
+                }
+            }
+        }
+    }
+    if (Ladd.x != 0.f || Ladd.y != 0.f || Ladd.z != 0.f) {
+        float4 l = L[pix];
+        l.x += Ladd.x; l.y += Ladd.y; l.z += Ladd.z;
+        L[pix] = l;
+    }
+}
+
 // Shading of every live path after its collision: emission pick-up (MIS
 // against the light pdf of the previous vertex), environment on escape, one
 // light sample and one environment sample appended to their queues, phase
@@ -340,170 +497,28 @@ __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PassArgs P, Queue 
     const int n = *n_in;
     for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += (int64_t)gridDim.x * kBlock) {
         const int64_t i = base + threadIdx.x;
-        bool cont = false, do_nee = false, do_env = false, do_qry = false, do_rec = false;
+        ShadeOut o;
         int v = 0;
-        float4 ca{}, cb{}, cc{}, na{}, nb{}, nc{}, ea{}, eb{}, ec{};
-        float4 r0{}, r1{}, r2{}, r3{}, r4{}, r5{};  // cache query / training record
         if (i < n) {
-            const float4 A = qin.a[i], B = qin.b[i], C = qin.c[i];
-            const int2 hit = hits[i];
             v = qin.v[i];
-            const int pbits = __float_as_int(C.w);
-            const int pix = pbits & kPixMask;
-            const bool train = (pbits & kTrainBit) != 0;
-            const float p_prev = A.w;
-            const V3 o = f3(A), d = f3(B);
-            V3 beta = f3(C);
-            const Rng4 g0 = path_rng(P, (uint32_t)pix, (uint32_t)v, 0);
-            const Rng4 g1 = path_rng(P, (uint32_t)pix, (uint32_t)v, 1);
-            V3 Ladd = v3(0.f, 0.f, 0.f);
-            if (hit.x < 0) {
-                if (P.has_env) {
-                    float w = 1.f;
-                    if (v > 1) {
-                        if (P.mis_mode == 2) w = 0.f;
-                        else if (P.mis_mode == 0) w = p_prev / (p_prev + 0.25f * kInvPi);
-                    }
-                    Ladd = w * mul(beta, v3(P.env[0], P.env[1], P.env[2]));
-                }
-            } else {
-                const int k = hit.x;
-                const float4 c0 = S.cold[3 * k], c1 = S.cold[3 * k + 1], c2 = S.cold[3 * k + 2];
-                const V3 x = o + __int_as_float(hit.y) * d;
-                const V3 Le = f3(c2);
-                if (nonzero(Le)) {
-                    float w = 1.f;
-                    if (v > 1) {
-                        const float pn = nee_pdf(S, k, o);
-                        if (P.mis_mode == 2) w = pn > 0.f ? 0.f : 1.f;
-                        else if (P.mis_mode == 0) w = p_prev / (p_prev + pn);
-                    }
-                    Ladd = w * mul(beta, Le);
-                }
-                bool stop = false;
-                if (v <= P.max_depth && P.nrc.mode != 0) {
-                    // radiance cache: inputs of this vertex (position, outgoing
-                    // direction, facet normal turned toward it, roughness, albedo)
-                    const V3 wo = -d;
-                    const V3 nf = dot(f3(c0), wo) >= 0.f ? f3(c0) : -f3(c0);
-                    r0 = make_float4(x.x, x.y, x.z, wo.x);
-                    r1 = make_float4(wo.y, wo.z, nf.x, nf.y);
-                    r2 = make_float4(nf.z, c1.w, c1.x, c1.y);
-                    r3 = make_float4(c1.z, 0.f, 0.f, 0.f);
-                    r4 = make_float4(beta.x, beta.y, beta.z, __int_as_float(pix));
-                    if (!train && v == P.nrc.term + 1) {
-                        stop = true;
-                        do_qry = P.nrc.mode != 3;
-                    } else if (train) {
-                        const float4 l = L[pix];
-                        r5 = make_float4(l.x + Ladd.x, l.y + Ladd.y, l.z + Ladd.z, (float)v);
-                        do_rec = true;
-                    }
-                }
-                if (v <= P.max_depth && !stop) {
-                    const V3 wo = -d;
-                    const Facet F = facet(f3(c0), wo);
-                    const V3 wol = to_local(F, wo);
-                    const int mat = __float_as_int(c0.w);
-                    const V3 alb = f3(c1);
-                    const float rough = c1.w;
-                    // light sample: one emitter, uniform in the cone of its bounding sphere
-                    if (S.n_emit > 0 && P.mis_mode != 1) {
-                        // floor(u * n_emit) in exact integer arithmetic (u has 24 bits)
-                        int j = (int)(((uint64_t)(g0.u[1] * 16777216.f) * (uint64_t)S.n_emit) >> 24);
-                        j = min(j, S.n_emit - 1);
-                        const int e = S.emit[j];
-                        const int es = S.inv[e];
-                        const float4 eh = S.hot[4 * es];
-                        const float rs = S.cold[3 * e + 2].w;
-                        V3 cd = v3(eh.x - x.x, eh.y - x.y, eh.z - x.z);
-                        const float d2 = dot(cd, cd);
-                        if (d2 > rs * rs) {
-                            cd = rsqrtf(d2) * cd;
-                            const float sin2 = rs * rs / d2;
-                            const float cosm = sqrtf(fmaxf(0.f, 1.f - sin2));
-                            const float omc = sin2 / (1.f + cosm);
-                            const float pn = 1.f / ((float)S.n_emit * 2.f * kPi * omc);
-                            const float omcos = g0.u[2] * omc;
-                            const float cost = 1.f - omcos;
-                            const float sint = sqrtf(fmaxf(0.f, omcos * (2.f - omcos)));
-                            float sp, cp;
-                            sincosf(2.f * kPi * g0.u[3], &sp, &cp);
-                            V3 b1, b2;
-                            onb(cd, b1, b2);
-                            const V3 wl = (sint * cp) * b1 + (sint * sp) * b2 + cost * cd;
-                            float pph;
-                            const V3 f = phase_eval_local(mat, alb, rough, wol, to_local(F, wl), pph);
-                            Chord tc;
-                            const RayD lr = make_ray(x.x, x.y, x.z, wl.x, wl.y, wl.z, 0.f, __builtin_huge_val());
-                            if (nonzero(f) && chord(load_hot(S.hot, es), lr, S.r2, tc)) {
-                                const float w = P.mis_mode == 2 ? 1.f : pn / (pn + pph);
-                                const float4 eL = S.cold[3 * e + 2];
-                                const V3 wt = (w / pn) * mul(mul(beta, f), f3(eL));
-                                do_nee = true;
-                                na = make_float4(x.x, x.y, x.z, __int_as_float(e));
-                                nb = make_float4(wl.x, wl.y, wl.z, __int_as_float(k));
-                                nc = make_float4(wt.x, wt.y, wt.z, __int_as_float(pix));
-                            }
-                        }
-                    }
-                    // environment sample: uniform direction
-                    if (P.has_env && P.mis_mode != 1) {
-                        const float z = 1.f - 2.f * g1.u[2];
-                        const float rr = sqrtf(fmaxf(0.f, 1.f - z * z));
-                        float sp, cp;
-                        sincosf(2.f * kPi * g1.u[3], &sp, &cp);
-                        const V3 wl = v3(rr * cp, rr * sp, z);
-                        float pph;
-                        const V3 f = phase_eval_local(mat, alb, rough, wol, to_local(F, wl), pph);
-                        if (nonzero(f)) {
-                            const float pe = 0.25f * kInvPi;
-                            const float w = P.mis_mode == 2 ? 1.f : pe / (pe + pph);
-                            const V3 wt = (w / pe) * mul(mul(beta, f), v3(P.env[0], P.env[1], P.env[2]));
-                            do_env = true;
-                            ea = make_float4(x.x, x.y, x.z, 0.f);
-                            eb = make_float4(wl.x, wl.y, wl.z, __int_as_float(k));
-                            ec = make_float4(wt.x, wt.y, wt.z, __int_as_float(pix));
-                        }
-                    }
-                    // continue by phase sampling from the chord centre, skipping k
-                    V3 wgt;
-                    float pdf;
-                    const V3 wil = phase_sample_local(mat, alb, rough, wol, g1.u[0], g1.u[1], wgt, pdf);
-                    if (pdf > 0.f) {
-                        beta = mul(beta, wgt);
-                        if (nonzero(beta)) {
-                            const V3 wi = to_world(F, wil);
-                            cont = true;
-                            ca = make_float4(x.x, x.y, x.z, pdf);
-                            cb = make_float4(wi.x, wi.y, wi.z, __int_as_float(k));
-                            cc = make_float4(beta.x, beta.y, beta.z, __int_as_float(pbits));
-                        }
-                    }
-                }
-            }
-            if (Ladd.x != 0.f || Ladd.y != 0.f || Ladd.z != 0.f) {
-                float4 l = L[pix];
-                l.x += Ladd.x; l.y += Ladd.y; l.z += Ladd.z;
-                L[pix] = l;
-            }
+            shade_one(S, P, qin.a[i], qin.b[i], qin.c[i], v, hits[i], L, o);
         }
-        const int pc = wave_append(cont, n_out);
-        if (cont) { qout.a[pc] = ca; qout.b[pc] = cb; qout.c[pc] = cc; qout.v[pc] = v + 1; }
-        const int pn = wave_append(do_nee, n_nee);
-        if (do_nee) { nee.a[pn] = na; nee.b[pn] = nb; nee.c[pn] = nc; }
-        const int pe = wave_append(do_env, n_env);
-        if (do_env) { env.a[pe] = ea; env.b[pe] = eb; env.c[pe] = ec; }
+        const int pc = wave_append(o.cont, n_out);
+        if (o.cont) { qout.a[pc] = o.ca; qout.b[pc] = o.cb; qout.c[pc] = o.cc; qout.v[pc] = v + 1; }
+        const int pn = wave_append(o.do_nee, n_nee);
+        if (o.do_nee) { nee.a[pn] = o.na; nee.b[pn] = o.nb; nee.c[pn] = o.nc; }
+        const int pe = wave_append(o.do_env, n_env);
+        if (o.do_env) { env.a[pe] = o.ea; env.b[pe] = o.eb; env.c[pe] = o.ec; }
         if (P.nrc.mode != 0) {
-            const int pq = wave_append(do_qry, P.nrc.n_qry);
-            if (do_qry) {
+            const int pq = wave_append(o.do_qry, P.nrc.n_qry);
+            if (o.do_qry) {
                 float4 *q = reinterpret_cast<float4 *>(P.nrc.qry + (int64_t)kNrcRecordFloats * pq);
-                q[0] = r0; q[1] = r1; q[2] = r2; q[3] = r3; q[4] = r4;
+                q[0] = o.r0; q[1] = o.r1; q[2] = o.r2; q[3] = o.r3; q[4] = o.r4;
             }
-            const int pr = wave_append(do_rec, P.nrc.n_rec);
-            if (do_rec && pr < P.nrc.rec_cap) {
+            const int pr = wave_append(o.do_rec, P.nrc.n_rec);
+            if (o.do_rec && pr < P.nrc.rec_cap) {
                 float4 *q = reinterpret_cast<float4 *>(P.nrc.rec + (int64_t)kNrcRecordFloats * pr);
-                q[0] = r0; q[1] = r1; q[2] = r2; q[3] = r3; q[4] = r4; q[5] = r5;
+                q[0] = o.r0; q[1] = o.r1; q[2] = o.r2; q[3] = o.r3; q[4] = o.r4; q[5] = o.r5;
             }
         }
     }
@@ -632,6 +647,111 @@ __global__ void k_accum(int64_t npix, int nsamp, const float4 *L, float *sum, fl
     }
     sum[3 * p] = s0; sum[3 * p + 1] = s1; sum[3 * p + 2] = s2;
     if (sumsq) { sumsq[3 * p] = q0; sumsq[3 * p + 1] = q1; sumsq[3 * p + 2] = q2; }
+}
+
+// Sweeps of the tail kernel, called rather than inlined (it runs few rays; one
+// copy of each serves every call site).
+__device__ __noinline__ SweepOut tail_sweep_main(const SceneDev &S, const RayD &r, int excl, int mode, float u,
+                                                  int target, float stop_a, int *stack, uint32_t *err,
+                                                  TraceCount &tc) {
+    return sweep<kEventsMain>(S, r, excl, mode, u, target, stack, err, tc, stop_a);
+}
+
+__device__ __noinline__ SweepOut tail_sweep_wide(const SceneDev &S, const RayD &r, int excl, int mode, float u,
+                                                  int target, float stop_a, int *stack, uint32_t *err,
+                                                  TraceCount &tc) {
+    return sweep<kEventsWide>(S, r, excl, mode, u, target, stack, err, tc, stop_a);
+}
+
+__device__ __forceinline__ SweepOut tail_sweep(const SceneDev &S, const RayD &r, int excl, int mode, float u,
+                                               int target, float stop_a, int *stack, uint32_t *err,
+                                               TraceCount &tc) {
+    SweepOut so = tail_sweep_main(S, r, excl, mode, u, target, stop_a, stack, err, tc);
+    if (so.status != 0) so = tail_sweep_wide(S, r, excl, mode, u, target, stop_a, stack, err, tc);
+    if (so.status != 0) atomicOr(err, kErrEvents);
+    return so;
+}
+
+__device__ __forceinline__ void add_radiance(float4 *L, int pix, float x, float y, float z) {
+    float4 l = L[pix];
+    l.x += x; l.y += y; l.z += z;
+    L[pix] = l;
+}
+
+// The last bounces of a chunk, once few paths are left and none is still to
+// be generated: one lane follows its path to the end -- collision, shading,
+// light sample, environment sample, cache query or training record -- with
+// no launch per bounce (each wavefront launch would last as long as the
+// slowest of a few thousand rays).  Every step is the wavefront's, in the same
+// order per path, so the path's radiance is the same float sum.
+__global__ __launch_bounds__(kBlock) void k_tail(SceneDev S, PassArgs P, Queue q, const int32_t *n_in, float4 *L,
+                                                 int64_t *stats, uint32_t *err) {
+    __shared__ int stack[kStackSize * kBlock];
+    const int n = *n_in;
+    TraceCount tc;
+    unsigned long long n_col = 0, n_light = 0, n_env = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        float4 A = q.a[i], B = q.b[i], C = q.c[i];
+        int v = q.v[i];
+        for (;;) {
+            const int pix = __float_as_int(C.w) & kPixMask;
+            const float u = path_rng(P, (uint32_t)pix, (uint32_t)v, 0).u[0];
+            const RayD r = make_ray(A.x, A.y, A.z, B.x, B.y, B.z, 0.f, __builtin_huge_val());
+            ++n_col;
+            const SweepOut so = tail_sweep(S, r, __float_as_int(B.w), kModeCollide, u, -1, -kInf, stack, err, tc);
+            const int2 hit = so.status != 0 ? make_int2(-1, __float_as_int(0.f))
+                                            : make_int2(so.prim, __float_as_int(so.t));
+            ShadeOut o;
+            shade_one(S, P, A, B, C, v, hit, L, o);
+            if (o.do_nee) {
+                ++n_light;
+                const int target = __float_as_int(o.na.w);
+                RayD lr = make_ray(o.na.x, o.na.y, o.na.z, o.nb.x, o.nb.y, o.nb.z, 0.f, __builtin_huge_val());
+                Chord c;
+                if (chord(load_hot(S.hot, S.inv[target]), lr, S.r2, c)) {
+                    lr.t1 = c.bd;
+                    const SweepOut ls =
+                        tail_sweep(S, lr, __float_as_int(o.nb.w), kModeEmitter, 0.f, target, c.a, stack, err, tc);
+                    if (ls.status == 0 && ls.t > 0.f)
+                        add_radiance(L, __float_as_int(o.nc.w), o.nc.x * ls.t, o.nc.y * ls.t, o.nc.z * ls.t);
+                }
+            }
+            if (o.do_env) {
+                ++n_env;
+                const RayD er = make_ray(o.ea.x, o.ea.y, o.ea.z, o.eb.x, o.eb.y, o.eb.z, 0.f, __builtin_huge_val());
+                const float T = fmaxf(0.f, 1.f - transmittance_F(S, er, __float_as_int(o.eb.w), true, stack, err, tc));
+                if (T > 0.f) add_radiance(L, __float_as_int(o.ec.w), o.ec.x * T, o.ec.y * T, o.ec.z * T);
+            }
+            if (P.nrc.mode != 0) {
+                if (o.do_qry) {
+                    const int pq = atomicAdd(P.nrc.n_qry, 1);
+                    float4 *w = reinterpret_cast<float4 *>(P.nrc.qry + (int64_t)kNrcRecordFloats * pq);
+                    w[0] = o.r0; w[1] = o.r1; w[2] = o.r2; w[3] = o.r3; w[4] = o.r4;
+                }
+                if (o.do_rec) {
+                    const int pr = atomicAdd(P.nrc.n_rec, 1);
+                    if (pr < P.nrc.rec_cap) {
+                        float4 *w = reinterpret_cast<float4 *>(P.nrc.rec + (int64_t)kNrcRecordFloats * pr);
+                        w[0] = o.r0; w[1] = o.r1; w[2] = o.r2; w[3] = o.r3; w[4] = o.r4; w[5] = o.r5;
+                    }
+                }
+            }
+            if (!o.cont) break;
+            A = o.ca; B = o.cb; C = o.cc;
+            ++v;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        n_col += __shfl_xor(n_col, off);
+        n_light += __shfl_xor(n_light, off);
+        n_env += __shfl_xor(n_env, off);
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd((unsigned long long *)&stats[0], n_col);
+        atomicAdd((unsigned long long *)&stats[1], n_light);
+        atomicAdd((unsigned long long *)&stats[2], n_env);
+    }
+    flush_counts(S, tc);
 }
 
 __global__ void k_set_count(int32_t *c, int32_t v) { *c = v; }
@@ -881,6 +1001,24 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
                                P, pool, total, (const int32_t *)c, (const int32_t *)chunk_cnt, qin, rb->L);
             hipLaunchKernelGGL(k_regen_commit, dim3(1), dim3(1), 0, st, pool, total, c, cn, chunk_cnt);
             P.nrc.n_qry = c + 6;
+            if (it > 0 && n_new == 0 && n_it <= ctx->tail_paths) {
+                // few paths left and none to generate: they run to the end in one kernel
+                timed(8, [&] {
+                    hipLaunchKernelGGL(k_tail, dim3((unsigned)std::max<int64_t>(1, (n_it + kBlock - 1) / kBlock)),
+                                       dim3(kBlock), 0, st, Sc[1], P, qin, (const int32_t *)c, rb->L, ctx->stats,
+                                       ctx->err);
+                });
+                if (p->nrc_mode == 1 || p->nrc_mode == 2) {
+                    timed(6, [&] {
+                        e = nrc_forward(ctx, n_it, c + 6, rb->qry, kNrcRecordFloats, 2, box, nullptr, rb->L,
+                                        nrc_scale);
+                    });
+                    if (e != hipSuccess) return e;
+                    hipLaunchKernelGGL(k_nrc_count, dim3(1), dim3(1), 0, st, (const int32_t *)(c + 6),
+                                       ctx->stats + 3);
+                }
+                break;
+            }
             // order the queue so each wave's rays are coherent
             if (sorted)
                 timed(5, [&] {

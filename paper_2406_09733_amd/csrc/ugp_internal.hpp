@@ -78,6 +78,7 @@ struct ugp_ctx_s {
     unsigned long long *counters = nullptr;  // [3] traversal counters (profiling level 2)
     int profiling = 0;
     int64_t path_pool = 0;  // path slots of ugp_render (0: every path of a chunk)
+    int64_t tail_paths = 65536;  // live paths at or below which a chunk's last bounces run in one kernel
     // event pairs of the last render, by category: 0 collide main, 1 collide wide, 2 light, 3 env,
     // 4 shade, 5 ray sort
     std::vector<hipEvent_t> ev_pool;

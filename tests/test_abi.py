@@ -58,6 +58,7 @@ def test_host_side_argument_checks(L):
     assert L.ugp_sync(None) == 1
     assert L.ugp_destroy(None) == 1
     assert L.ugp_set_path_pool(None, C.c_int64(0)) == 1
+    assert L.ugp_set_tail_paths(None, C.c_int64(0)) == 1
 
 
 def test_create_without_gpu_reports_device_error(L):

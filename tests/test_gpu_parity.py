@@ -308,3 +308,34 @@ def test_render_independent_of_path_pool(ctx, torch, pool):
         ctx.set_path_pool(0)
     assert torch.equal(s0, s1) and torch.equal(q0, q1)
     assert float(s0.sum()) > 0
+
+
+@pytest.mark.parametrize("mode", ["plain", "env", "cache"])
+def test_render_tail_kernel_matches_wavefront(ctx, torch, mode):
+    # the tail kernel (one lane follows its path to the end) takes the same
+    # steps per path in the same order as the per-bounce launches: the image
+    # is bit-identical whichever runs the last bounces
+    _say(f"tail kernel vs per-bounce launches ({mode})")
+    sc = scenes.mixed_100k()
+    _build(ctx, sc)
+    cam = dict(scenes.camera("mixed_100k"), width=80, height=64)
+    p = {"spp": 4, "max_depth": 9, "seed": 11}
+    if mode == "env":
+        p.update(env_radiance=(0.3, 0.2, 0.1), mis_mode=0)
+    if mode == "cache":
+        from paper_2406_09733_amd import nrc_num_params
+        rng = np.random.default_rng(3)
+        ctx.nrc_set_weights((rng.standard_normal(nrc_num_params()) * 0.1).astype(np.float32))
+        p.update(nrc_mode=2, nrc_terminate_after=2)
+    out = []
+    try:
+        for tail in (0, 1 << 30, 65536):
+            ctx.set_tail_paths(tail)
+            s, q = ctx.render(cam, p)
+            ctx.sync()
+            out.append((s, q))
+    finally:
+        ctx.set_tail_paths(65536)
+    for s, q in out[1:]:
+        assert torch.equal(s, out[0][0]) and torch.equal(q, out[0][1])
+    assert float(out[0][0].sum()) > 0
