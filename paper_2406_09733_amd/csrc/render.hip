@@ -679,66 +679,108 @@ __device__ __forceinline__ void add_radiance(float4 *L, int pix, float x, float 
 }
 
 // The last bounces of a chunk, once few paths are left and none is still to
-// be generated: one lane follows its path to the end -- collision, shading,
-// light sample, environment sample, cache query or training record -- with
-// no launch per bounce (each wavefront launch would last as long as the
-// slowest of a few thousand rays).  Every step is the wavefront's, in the same
-// order per path, so the path's radiance is the same float sum.
+// be generated: the paths run to their end in one launch (each wavefront
+// launch would last as long as the slowest of a few thousand rays).  A path
+// has two lanes of a wave: lane j < 32 traces its collisions and shades, lane
+// j + 32 traces the light sample of the previous vertex meanwhile (the two
+// queries start at the same vertex and are independent).  The radiance is
+// added in the wavefront's order per path -- emission at vertex v, its light
+// sample, its environment sample, then vertex v + 1 -- so it is the same
+// float sum.
 __global__ __launch_bounds__(kBlock) void k_tail(SceneDev S, PassArgs P, Queue q, const int32_t *n_in, float4 *L,
                                                  int64_t *stats, uint32_t *err) {
     __shared__ int stack[kStackSize * kBlock];
     const int n = *n_in;
+    const int lane = threadIdx.x, jl = lane & 31;
+    const bool helper = lane >= 32;
+    const int64_t i = (int64_t)blockIdx.x * 32 + jl;
     TraceCount tc;
     unsigned long long n_col = 0, n_light = 0, n_env = 0;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-        float4 A = q.a[i], B = q.b[i], C = q.c[i];
-        int v = q.v[i];
-        for (;;) {
+    float4 A{}, B{}, C{};
+    int v = 0;
+    bool col = !helper && i < n;  // a collision to trace (path lanes)
+    if (col) {
+        A = q.a[i]; B = q.b[i]; C = q.c[i];
+        v = q.v[i];
+    }
+    bool nee = false, env = false;  // samples of the last shaded vertex still to add (path lanes)
+    float4 na{}, nb{}, nc{}, ea{}, eb{}, ec{};
+    for (;;) {
+        if (!__any(col || nee || env)) break;
+        // the light sample of the path's last vertex goes to its helper lane
+        const bool hq = __shfl(nee ? 1 : 0, jl) != 0;
+        const float4 hna = make_float4(__shfl(na.x, jl), __shfl(na.y, jl), __shfl(na.z, jl), __shfl(na.w, jl));
+        const float4 hnb = make_float4(__shfl(nb.x, jl), __shfl(nb.y, jl), __shfl(nb.z, jl), __shfl(nb.w, jl));
+        bool query = false;
+        RayD r = make_ray(0.f, 0.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.0);
+        int excl = -1, mode = kModeCollide, target = -1;
+        float u = 0.f, stop_a = -kInf;
+        if (!helper && col) {
             const int pix = __float_as_int(C.w) & kPixMask;
-            const float u = path_rng(P, (uint32_t)pix, (uint32_t)v, 0).u[0];
-            const RayD r = make_ray(A.x, A.y, A.z, B.x, B.y, B.z, 0.f, __builtin_huge_val());
+            u = path_rng(P, (uint32_t)pix, (uint32_t)v, 0).u[0];
+            r = make_ray(A.x, A.y, A.z, B.x, B.y, B.z, 0.f, __builtin_huge_val());
+            excl = __float_as_int(B.w);
+            query = true;
             ++n_col;
-            const SweepOut so = tail_sweep(S, r, __float_as_int(B.w), kModeCollide, u, -1, -kInf, stack, err, tc);
-            const int2 hit = so.status != 0 ? make_int2(-1, __float_as_int(0.f))
-                                            : make_int2(so.prim, __float_as_int(so.t));
-            ShadeOut o;
-            shade_one(S, P, A, B, C, v, hit, L, o);
-            if (o.do_nee) {
-                ++n_light;
-                const int target = __float_as_int(o.na.w);
-                RayD lr = make_ray(o.na.x, o.na.y, o.na.z, o.nb.x, o.nb.y, o.nb.z, 0.f, __builtin_huge_val());
-                Chord c;
-                if (chord(load_hot(S.hot, S.inv[target]), lr, S.r2, c)) {
-                    lr.t1 = c.bd;
-                    const SweepOut ls =
-                        tail_sweep(S, lr, __float_as_int(o.nb.w), kModeEmitter, 0.f, target, c.a, stack, err, tc);
-                    if (ls.status == 0 && ls.t > 0.f)
-                        add_radiance(L, __float_as_int(o.nc.w), o.nc.x * ls.t, o.nc.y * ls.t, o.nc.z * ls.t);
-                }
+        }
+        if (helper && hq) {
+            target = __float_as_int(hna.w);
+            r = make_ray(hna.x, hna.y, hna.z, hnb.x, hnb.y, hnb.z, 0.f, __builtin_huge_val());
+            Chord c;
+            if (chord(load_hot(S.hot, S.inv[target]), r, S.r2, c)) {
+                r.t1 = c.bd;
+                stop_a = c.a;
+                excl = __float_as_int(hnb.w);
+                mode = kModeEmitter;
+                query = true;
             }
-            if (o.do_env) {
-                ++n_env;
-                const RayD er = make_ray(o.ea.x, o.ea.y, o.ea.z, o.eb.x, o.eb.y, o.eb.z, 0.f, __builtin_huge_val());
-                const float T = fmaxf(0.f, 1.f - transmittance_F(S, er, __float_as_int(o.eb.w), true, stack, err, tc));
-                if (T > 0.f) add_radiance(L, __float_as_int(o.ec.w), o.ec.x * T, o.ec.y * T, o.ec.z * T);
+        }
+        SweepOut so{-1, 0.f, 1};
+        if (query) so = tail_sweep(S, r, excl, mode, u, target, stop_a, stack, err, tc);
+        const float f = helper && query && so.status == 0 ? so.t : 0.f;
+        const float f_nee = __shfl(f, jl + 32);
+        if (!helper) {
+            if (nee) {
+                if (f_nee > 0.f) add_radiance(L, __float_as_int(nc.w), nc.x * f_nee, nc.y * f_nee, nc.z * f_nee);
+                nee = false;
             }
-            if (P.nrc.mode != 0) {
-                if (o.do_qry) {
-                    const int pq = atomicAdd(P.nrc.n_qry, 1);
-                    float4 *w = reinterpret_cast<float4 *>(P.nrc.qry + (int64_t)kNrcRecordFloats * pq);
-                    w[0] = o.r0; w[1] = o.r1; w[2] = o.r2; w[3] = o.r3; w[4] = o.r4;
-                }
-                if (o.do_rec) {
-                    const int pr = atomicAdd(P.nrc.n_rec, 1);
-                    if (pr < P.nrc.rec_cap) {
-                        float4 *w = reinterpret_cast<float4 *>(P.nrc.rec + (int64_t)kNrcRecordFloats * pr);
-                        w[0] = o.r0; w[1] = o.r1; w[2] = o.r2; w[3] = o.r3; w[4] = o.r4; w[5] = o.r5;
+            if (env) {
+                const RayD er = make_ray(ea.x, ea.y, ea.z, eb.x, eb.y, eb.z, 0.f, __builtin_huge_val());
+                const float T = fmaxf(0.f, 1.f - transmittance_F(S, er, __float_as_int(eb.w), true, stack, err, tc));
+                if (T > 0.f) add_radiance(L, __float_as_int(ec.w), ec.x * T, ec.y * T, ec.z * T);
+                env = false;
+            }
+            if (col) {
+                const int2 hit = so.status != 0 ? make_int2(-1, __float_as_int(0.f))
+                                                : make_int2(so.prim, __float_as_int(so.t));
+                ShadeOut o;
+                shade_one(S, P, A, B, C, v, hit, L, o);
+                nee = o.do_nee;
+                na = o.na; nb = o.nb; nc = o.nc;
+                env = o.do_env;
+                ea = o.ea; eb = o.eb; ec = o.ec;
+                n_light += o.do_nee ? 1 : 0;
+                n_env += o.do_env ? 1 : 0;
+                if (P.nrc.mode != 0) {
+                    if (o.do_qry) {
+                        const int pq = atomicAdd(P.nrc.n_qry, 1);
+                        float4 *w = reinterpret_cast<float4 *>(P.nrc.qry + (int64_t)kNrcRecordFloats * pq);
+                        w[0] = o.r0; w[1] = o.r1; w[2] = o.r2; w[3] = o.r3; w[4] = o.r4;
+                    }
+                    if (o.do_rec) {
+                        const int pr = atomicAdd(P.nrc.n_rec, 1);
+                        if (pr < P.nrc.rec_cap) {
+                            float4 *w = reinterpret_cast<float4 *>(P.nrc.rec + (int64_t)kNrcRecordFloats * pr);
+                            w[0] = o.r0; w[1] = o.r1; w[2] = o.r2; w[3] = o.r3; w[4] = o.r4; w[5] = o.r5;
+                        }
                     }
                 }
+                col = o.cont;
+                if (col) {
+                    A = o.ca; B = o.cb; C = o.cc;
+                    ++v;
+                }
             }
-            if (!o.cont) break;
-            A = o.ca; B = o.cb; C = o.cc;
-            ++v;
         }
     }
     for (int off = 32; off > 0; off >>= 1) {
@@ -1004,7 +1046,7 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
             if (it > 0 && n_new == 0 && n_it <= ctx->tail_paths) {
                 // few paths left and none to generate: they run to the end in one kernel
                 timed(8, [&] {
-                    hipLaunchKernelGGL(k_tail, dim3((unsigned)std::max<int64_t>(1, (n_it + kBlock - 1) / kBlock)),
+                    hipLaunchKernelGGL(k_tail, dim3((unsigned)std::max<int64_t>(1, (n_it + 31) / 32)),
                                        dim3(kBlock), 0, st, Sc[1], P, qin, (const int32_t *)c, rb->L, ctx->stats,
                                        ctx->err);
                 });
