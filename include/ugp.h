@@ -184,6 +184,43 @@ ugp_status ugp_saturation(ugp_ctx ctx, int64_t n_rays, const float *rays,
 ugp_status ugp_emitter_query(ugp_ctx ctx, int64_t n_rays, const float *rays,
                              const int32_t *exclude, const int32_t *target, float *out);
 
+/* ---- Differentiation: the transmittance optimisation of Sec. 7.2 ---------
+ *
+ * Accumulated free-flight CDF of each ray (Sec. 7.2, eq. accum_cdf):
+ *   C = sum_k 1/2 I_k(a_k, min(b_k, t_sat)),
+ * the clipped chords of every primitive except exclude[i], t_sat the ray's
+ * saturating distance (as ugp_saturation; t1 when the ray never saturates).
+ *   C_out     float [n] or NULL
+ * With target (float [n], e.g. one minus a reference transmittance image):
+ *   loss_out  [device] float, += loss_scale * sum_i (C_i - target_i)^2, or NULL
+ *   grad      float [scene->n][11], += the gradient of that loss with respect
+ *             to (mean[3], scale[3], rotation[4] (w,x,y,z, unnormalised as
+ *             given), density) of every primitive, or NULL.  As in Sec. 7.2,
+ *             each primitive's term is differentiated with t_sat held fixed.
+ * scene: the parameters the hierarchy was built from (read for the rotation
+ * and scale chain rule); required with grad.  All arrays are device memory,
+ * owned by the caller; NULL outputs are skipped.  Enqueued on the stream;
+ * temporary buffers are stream-ordered allocations. */
+ugp_status ugp_accum_cdf(ugp_ctx ctx, const ugp_scene *scene, int64_t n_rays, const float *rays,
+                         const int32_t *exclude, const float *target, float loss_scale, float *C_out,
+                         float *loss_out, float *grad);
+
+/* One jittered pinhole ray per pixel of cam (row-major, rays [w*h][8] as the
+ * queries take them, t in [0, inf)); the sub-pixel jitter is the renderer's
+ * camera jitter of sample `sample` (counter-based generator keyed on seed,
+ * pixel, sample).  Sec. 7.2: one jittered ray per pixel per view. */
+ugp_status ugp_camera_rays(ugp_ctx ctx, const ugp_camera *cam, uint64_t seed, int64_t sample, float *rays);
+
+/* One Adam step (Kingma and Ba; beta = (0.9, 0.999), eps = 1e-8) on the
+ * primitive parameters with gradient grad [n][11] (the layout of
+ * ugp_accum_cdf), moments m and v [n][11] (zero before step 1), step >= 1:
+ * learning rate lr_rotation for the rotations and lr for the rest; then, as in
+ * Sec. 7.2, scales clamped to at least min_scale (> 0), densities to at least
+ * 0, rotations renormalised.  Arrays are device memory, updated in place. */
+ugp_status ugp_fit_adam(ugp_ctx ctx, int64_t n, float *mean, float *scale, float *rotation, float *density,
+                        const float *grad, float *m, float *v, int32_t step, float lr, float lr_rotation,
+                        float min_scale);
+
 /* Instrumentation: runs the ordered sweep of ugp_sample_collision (mode 0),
  * ugp_saturation (mode 1) or ugp_emitter_query (mode 2) and writes, per ray,
  * counts int32 [n][4] = (BVH nodes fetched, primitive records chord-tested,

@@ -208,6 +208,16 @@ class Scene:
         lib().orc_F_at(self.h, n, _addr(r), _addr(e), _addr(tt), ub, _addr(F))
         return F
 
+    def accum_cdf(self, rays, exclude=None, tsat=None, use_bvh=None):
+        """Accumulated free-flight CDF (Sec. 7.2, eq. accum_cdf): the sum of the
+        primitives' free-flight probabilities, each chord clipped at the ray's
+        saturating distance -- F at t_sat (at t1 when the ray never saturates).
+        `tsat` may be given (held fixed, as the derivative of Sec. 7.2 takes
+        it).  Returns (C, tsat)."""
+        if tsat is None:
+            tsat = self.saturation(rays, exclude, use_bvh)
+        return self.F_at(rays, tsat, exclude, use_bvh), tsat
+
     def sample_collision(self, rays, u, exclude=None, use_bvh=None):
         r = _rays(rays)
         n = r.shape[0]

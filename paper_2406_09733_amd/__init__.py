@@ -40,6 +40,17 @@ class _Camera(C.Structure):
                 ("vfov_deg", C.c_float), ("width", C.c_int32), ("height", C.c_int32)]
 
 
+def _camera(cam: dict) -> _Camera:
+    c = _Camera()
+    for i in range(3):
+        c.origin[i] = cam["origin"][i]
+        c.target[i] = cam["target"][i]
+        c.up[i] = cam["up"][i]
+    c.vfov_deg = cam["vfov_deg"]
+    c.width, c.height = int(cam["width"]), int(cam["height"])
+    return c
+
+
 class _Params(C.Structure):
     _fields_ = [("spp", C.c_int32), ("max_depth", C.c_int32), ("seed", C.c_uint64),
                 ("sample_offset", C.c_int64), ("env_radiance", C.c_float * 3), ("mis_mode", C.c_int32),
@@ -66,7 +77,8 @@ EXPORTS = ["ugp_create", "ugp_destroy", "ugp_set_stream", "ugp_build_bvh", "ugp_
            "ugp_sample_collision", "ugp_saturation", "ugp_emitter_query", "ugp_render", "ugp_sync",
            "ugp_set_profiling", "ugp_set_path_pool", "ugp_set_tail_paths", "ugp_get_render_stats", "ugp_trace_counts", "ugp_status_string",
            "ugp_nrc_num_params", "ugp_nrc_set_weights", "ugp_nrc_get_weights", "ugp_nrc_encode",
-           "ugp_nrc_forward", "ugp_nrc_train_step", "ugp_nrc_records"]
+           "ugp_nrc_forward", "ugp_nrc_train_step", "ugp_nrc_records", "ugp_accum_cdf", "ugp_camera_rays",
+           "ugp_fit_adam"]
 
 
 def lib():
@@ -99,6 +111,9 @@ def lib():
         L.ugp_nrc_forward.argtypes = [vp, i64, vp, C.c_int32, vp, vp]
         L.ugp_nrc_train_step.argtypes = [vp, i64, vp, C.c_int32, vp, vp, C.c_float, vp, vp]
         L.ugp_nrc_records.argtypes = [vp, i64, vp, vp, C.POINTER(C.c_int64)]
+        L.ugp_accum_cdf.argtypes = [vp, vp, i64, vp, vp, vp, C.c_float, vp, vp, vp]
+        L.ugp_camera_rays.argtypes = [vp, vp, C.c_uint64, i64, vp]
+        L.ugp_fit_adam.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, C.c_int32, C.c_float, C.c_float, C.c_float]
         L.ugp_status_string.argtypes = [C.c_int]
         L.ugp_status_string.restype = C.c_char_p
         for name in EXPORTS:
@@ -168,6 +183,7 @@ class Context:
                                                   "roughness", "emission", "material")])
         _check("ugp_build_bvh", lib().ugp_build_bvh(self.h, C.byref(s), float(cutoff_eps)))
         self.n = n
+        self._scene_t, self._scene_s = t, s  # the parameters the hierarchy was built from
         return self
 
     # ---- per-ray queries --------------------------------------------------
@@ -232,6 +248,48 @@ class Context:
                                                           _ptr(tg), _ptr(out)))
         return out
 
+    # ---- differentiation (transmittance optimisation) ---------------------
+    def accum_cdf(self, rays, target=None, exclude=None, loss_scale: float = 1.0, want_C: bool = True,
+                  loss=None, grad=None):
+        """ugp_accum_cdf -> C (float32 [n]) or None.  With target, adds
+        loss_scale * sum (C - target)^2 into `loss` (device float32 [1]) and its
+        gradient into `grad` (float32 [n_prims, 11]: mean, scale, rotation,
+        density), each when given; the scene is the one of the last build_bvh."""
+        torch = self.torch
+        r = self._rays(rays)
+        n = r.shape[0]
+        e = self._excl(exclude, n)
+        tg = None if target is None else self._dev(target, torch.float32, (n,))
+        C_out = torch.empty(n, device=self.device, dtype=torch.float32) if want_C else None
+        if grad is not None:
+            assert grad.dtype == torch.float32 and tuple(grad.shape) == (self.n, 11) and grad.is_contiguous()
+        if loss is not None:
+            assert loss.dtype == torch.float32 and loss.numel() >= 1
+        sp = C.byref(self._scene_s) if grad is not None else None
+        _check("ugp_accum_cdf", lib().ugp_accum_cdf(self.h, sp, n, _ptr(r), _ptr(e), _ptr(tg), float(loss_scale),
+                                                    _ptr(C_out), _ptr(loss), _ptr(grad)))
+        return C_out
+
+    def camera_rays(self, cam: dict, seed: int = 0, sample: int = 0):
+        """ugp_camera_rays -> float32 [height * width, 8] jittered pinhole rays."""
+        c = _camera(cam)
+        rays = self.torch.empty((cam["width"] * cam["height"], 8), device=self.device, dtype=self.torch.float32)
+        _check("ugp_camera_rays", lib().ugp_camera_rays(self.h, C.byref(c), int(seed), int(sample), _ptr(rays)))
+        return rays
+
+    def fit_adam(self, params: dict, grad, m, v, step: int, lr: float = 1e-4, lr_rotation: float = 2e-5,
+                 min_scale: float = 1e-6):
+        """ugp_fit_adam: one Adam step on params (device float32 tensors mean,
+        scale, rotation, density, updated in place) with clamps and renormalised
+        rotations."""
+        n = params["mean"].shape[0]
+        for k in ("mean", "scale", "rotation", "density"):
+            assert params[k].is_contiguous() and params[k].dtype == self.torch.float32
+        _check("ugp_fit_adam", lib().ugp_fit_adam(self.h, n, _ptr(params["mean"]), _ptr(params["scale"]),
+                                                  _ptr(params["rotation"]), _ptr(params["density"]), _ptr(grad),
+                                                  _ptr(m), _ptr(v), int(step), float(lr), float(lr_rotation),
+                                                  float(min_scale)))
+
     # ---- path tracing -----------------------------------------------------
     def render(self, cam: dict, params: dict, sum_rgb=None, sumsq_rgb=None):
         """ugp_render: adds this call's per-pixel sums of path radiance (and of
@@ -243,13 +301,7 @@ class Context:
             sum_rgb = torch.zeros((H, W, 3), device=self.device, dtype=torch.float32)
         if sumsq_rgb is None and params.get("want_sumsq", True):
             sumsq_rgb = torch.zeros((H, W, 3), device=self.device, dtype=torch.float32)
-        c = _Camera()
-        for i in range(3):
-            c.origin[i] = cam["origin"][i]
-            c.target[i] = cam["target"][i]
-            c.up[i] = cam["up"][i]
-        c.vfov_deg = cam["vfov_deg"]
-        c.width, c.height = W, H
+        c = _camera(cam)
         p = _Params()
         p.spp = int(params.get("spp", 1))
         p.max_depth = int(params.get("max_depth", 4))

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libugp.so")
 OBJ = os.path.join(HERE, "_objs")
-SOURCES = ["api.hip", "build.hip", "trace.hip", "render.hip", "nrc.hip"]
+SOURCES = ["api.hip", "build.hip", "trace.hip", "render.hip", "nrc.hip", "diff.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",

@@ -208,6 +208,41 @@ ugp_status ugp_render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_param
     return from_hip(ugp::render(ctx, cam, p, sum, sumsq));
 }
 
+ugp_status ugp_accum_cdf(ugp_ctx ctx, const ugp_scene *scene, int64_t n, const float *rays,
+                         const int32_t *exclude, const float *target, float loss_scale, float *C_out,
+                         float *loss_out, float *grad) {
+    if (!query_args_ok(ctx, n, rays) || !std::isfinite(loss_scale)) return UGP_ERR_INVALID_ARGUMENT;
+    if ((loss_out || grad) && !target) return UGP_ERR_INVALID_ARGUMENT;
+    if (grad && (!scene || !scene->scale || !scene->rotation || scene->n != ctx->scene.n))
+        return UGP_ERR_INVALID_ARGUMENT;
+    if (ctx->scene.n == 0) return UGP_ERR_NO_SCENE;
+    if (n == 0) return UGP_OK;
+    DeviceGuard g(ctx->device);
+    return from_hip(ugp::accum_cdf(ctx, scene, n, rays, exclude, target, loss_scale, C_out, loss_out, grad));
+}
+
+ugp_status ugp_camera_rays(ugp_ctx ctx, const ugp_camera *cam, uint64_t seed, int64_t sample, float *rays) {
+    if (!ctx || !cam || !rays) return UGP_ERR_INVALID_ARGUMENT;
+    if (cam->width < 1 || cam->height < 1 || (int64_t)cam->width * cam->height >= (int64_t(1) << 31) ||
+        !(cam->vfov_deg > 0.f && cam->vfov_deg < 180.f) || sample < 0 || sample >= (int64_t(1) << 32))
+        return UGP_ERR_INVALID_ARGUMENT;
+    DeviceGuard g(ctx->device);
+    return from_hip(ugp::camera_rays(ctx, cam, seed, (uint32_t)sample, rays));
+}
+
+ugp_status ugp_fit_adam(ugp_ctx ctx, int64_t n, float *mean, float *scale, float *rotation, float *density,
+                        const float *grad, float *m, float *v, int32_t step, float lr, float lr_rotation,
+                        float min_scale) {
+    if (!ctx || n < 0 || step < 1 || !(lr >= 0.f) || !std::isfinite(lr) || !(lr_rotation >= 0.f) ||
+        !std::isfinite(lr_rotation) || !(min_scale > 0.f) || !std::isfinite(min_scale))
+        return UGP_ERR_INVALID_ARGUMENT;
+    if (n > 0 && (!mean || !scale || !rotation || !density || !grad || !m || !v)) return UGP_ERR_INVALID_ARGUMENT;
+    if (n == 0) return UGP_OK;
+    DeviceGuard g(ctx->device);
+    return from_hip(ugp::fit_adam(ctx, n, mean, scale, rotation, density, grad, m, v, step, lr, lr_rotation, 0.9f,
+                                  0.999f, 1e-8f, min_scale));
+}
+
 ugp_status ugp_sync(ugp_ctx ctx) {
     if (!ctx) return UGP_ERR_INVALID_ARGUMENT;
     DeviceGuard g(ctx->device);

@@ -1,0 +1,293 @@
+// diff.hip -- differentiation of the accumulated free-flight CDF of a ray
+// (Sec. 7.2, eq. accum_cdf) with respect to every primitive parameter, the
+// transmittance-image loss built on it, jittered camera rays for such images,
+// and the Adam update with the clamps of the transmittance optimisation.
+//
+// C = sum_k 1/2 I_k(a_k, min(b_k, t_sat)) over the primitives the ray meets,
+// each clipped at the ray's saturating distance (t1 when the ray never
+// saturates).  As in Sec. 7.2 the derivative of C with respect to a parameter
+// of primitive k is the derivative of its own term with t_sat held fixed.
+#include "trace_device.hpp"
+
+namespace ugp {
+namespace {
+
+// 1/2 I(a, min(b, tcl)) of the primitive of record h along ray r, and its
+// gradient with respect to (mu[3], M[3][3] row-major, d) = g[13], for the clip
+// point tcl held fixed.  The closed form of the ray integral (Sec. 4.1, eq.
+// ray_integral), in the unit frame o' = M (o - mu), w' = M w:
+//   A = w'.w', P = o'.w', t_c = -P / A, rho^2 = o'.o' - P^2 / A,
+//   tau(t) = sqrt(A / 2) (t - t_c),
+//   1/2 I = 1/2 d sqrt(pi / (2 A)) exp(-rho^2 / 2) [erf tau_b - erf tau_a].
+// An end on the cut-off ellipsoid has |tau| = sqrt((r^2 - rho^2) / 2) (it moves
+// with the parameters); an end clipped at t0 or at tcl has tau(t) at that t.
+// Plain FP64 throughout (few primitives per ray; the sum C itself comes from
+// the traversal's chord, as in every other query).
+__device__ double w_and_grad(const HotRec &h, const RayD &r, double r2, double tcl, double g[13]) {
+    for (int k = 0; k < 13; ++k) g[k] = 0.0;
+    const double M[9] = {h.m[0], h.m[1], h.m[2], h.m[3], h.m[4], h.m[5], h.m[6], h.m[7], h.m[8]};
+    const double p[3] = {(double)r.ox - (double)h.mx, (double)r.oy - (double)h.my, (double)r.oz - (double)h.mz};
+    const double w[3] = {r.dx, r.dy, r.dz};
+    double op[3], wp[3];
+    for (int i = 0; i < 3; ++i) {
+        op[i] = M[3 * i] * p[0] + M[3 * i + 1] * p[1] + M[3 * i + 2] * p[2];
+        wp[i] = M[3 * i] * w[0] + M[3 * i + 1] * w[1] + M[3 * i + 2] * w[2];
+    }
+    const double A = wp[0] * wp[0] + wp[1] * wp[1] + wp[2] * wp[2];
+    const double P = op[0] * wp[0] + op[1] * wp[1] + op[2] * wp[2];
+    if (!(A > 0.0)) return 0.0;
+    const double tc = -P / A;
+    const double rho2 = op[0] * op[0] + op[1] * op[1] + op[2] * op[2] - P * P / A;
+    if (!(rho2 < r2)) return 0.0;
+    const double half = sqrt((r2 - rho2) / A);
+    const double tlo = tc - half, thi = tc + half;
+    const double a = fmax((double)r.t0, tlo), b = fmin(fmin(r.t1, thi), tcl);
+    if (!(a < b)) return 0.0;
+    const bool clip_a = a > tlo, clip_b = b < thi;
+    const double s = sqrt(0.5 * A), q = sqrt(0.5 * (r2 - rho2));
+    const double ta = clip_a ? s * (a - tc) : -q, tb = clip_b ? s * (b - tc) : q;
+    const double base = sqrt(M_PI / (2.0 * A)) * exp(-0.5 * rho2);
+    const double d = h.d, pref = d * base;
+    const double E = erf(tb) - erf(ta);
+    const double W = 0.5 * pref * E;
+    // gradients of the scalars with respect to o' and w'
+    double tc_o[3], tc_w[3], r_o[3], r_w[3], ta_o[3], ta_w[3], tb_o[3], tb_w[3], W_o[3], W_w[3];
+    const double ka = 2.0 / sqrt(M_PI) * exp(-ta * ta), kb = 2.0 / sqrt(M_PI) * exp(-tb * tb);
+    for (int i = 0; i < 3; ++i) {
+        tc_o[i] = -wp[i] / A;
+        tc_w[i] = -op[i] / A + 2.0 * P * wp[i] / (A * A);
+        r_o[i] = 2.0 * op[i] - 2.0 * P * wp[i] / A;
+        r_w[i] = -2.0 * P * op[i] / A + 2.0 * P * P * wp[i] / (A * A);
+        const double s_w = wp[i] / (2.0 * s);
+        if (clip_a) {
+            ta_o[i] = -s * tc_o[i];
+            ta_w[i] = s_w * (a - tc) - s * tc_w[i];
+        } else {
+            ta_o[i] = -r_o[i] / (4.0 * ta);
+            ta_w[i] = -r_w[i] / (4.0 * ta);
+        }
+        if (clip_b) {
+            tb_o[i] = -s * tc_o[i];
+            tb_w[i] = s_w * (b - tc) - s * tc_w[i];
+        } else {
+            tb_o[i] = -r_o[i] / (4.0 * tb);
+            tb_w[i] = -r_w[i] / (4.0 * tb);
+        }
+        const double lp_o = -0.5 * r_o[i], lp_w = -wp[i] / A - 0.5 * r_w[i];
+        W_o[i] = 0.5 * pref * (E * lp_o + kb * tb_o[i] - ka * ta_o[i]);
+        W_w[i] = 0.5 * pref * (E * lp_w + kb * tb_w[i] - ka * ta_w[i]);
+    }
+    // o' = M (o - mu), w' = M w
+    for (int j = 0; j < 3; ++j) g[j] = -(M[j] * W_o[0] + M[3 + j] * W_o[1] + M[6 + j] * W_o[2]);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) g[3 + 3 * i + j] = W_o[i] * p[j] + W_w[i] * w[j];
+    g[12] = 0.5 * base * E;
+    return W;
+}
+
+// One lane per ray: C (forward), and with a target the loss
+// loss_scale * (C - target)^2 and its gradient with respect to (mu, M, d) of
+// every primitive the ray meets before t_sat, accumulated per original index.
+__global__ __launch_bounds__(kBlock) void k_cdf(SceneDev S, int64_t n, const float *rays, const int32_t *excl,
+                                                const double *tsat, const float *target, float loss_scale,
+                                                float *C_out, float *loss, float *g13, uint32_t *err) {
+    __shared__ int stack[kStackSize * kBlock];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    float l2 = 0.f;
+    if (i < n) {
+        const RayD r = load_ray(rays, i);
+        const int ex = excl ? excl[i] : -1;
+        const double tcl = tsat[i];
+        const float hi = tcl < 3.0e38 ? (float)tcl : kInf;
+        TraceCount tc;
+        int spill[kStackSpill];
+        auto pre = [&](int p) __attribute__((always_inline)) {
+            const HotRec h = load_hot(S.hot, p);
+            return h.orig != ex && !surely_missed(h, r, S.r2);
+        };
+        float C = 0.f;
+        {
+            TravState ts;
+            trav_begin(ts, S);
+            traverse(S, r, r.t0, [&]() __attribute__((always_inline)) { return hi; }, stack, spill, ts, 0, err, tc,
+                     pre, [&](int p) __attribute__((always_inline)) {
+                         const HotRec h = load_hot(S.hot, p);
+                         Chord c;
+                         if (chord(h, r, S.r2, c, true) && c.own) C += half_integral_to(c, tcl);
+                         return false;
+                     });
+        }
+        if (C_out) C_out[i] = C;
+        if (target) {
+            const float diff = C - target[i];
+            l2 = loss_scale * diff * diff;
+            const double dC = 2.0 * (double)loss_scale * (double)diff;
+            if (g13 && dC != 0.0) {
+                TravState ts;
+                trav_begin(ts, S);
+                traverse(S, r, r.t0, [&]() __attribute__((always_inline)) { return hi; }, stack, spill, ts, 0, err,
+                         tc, pre, [&](int p) __attribute__((always_inline)) {
+                             const HotRec h = load_hot(S.hot, p);
+                             Chord c;
+                             if (!chord(h, r, S.r2, c, true) || !c.own) return false;
+                             double gk[13];
+                             w_and_grad(h, r, (double)S.r2, tcl, gk);
+                             float *dst = g13 + 13 * (int64_t)h.orig;
+                             for (int k = 0; k < 13; ++k)
+                                 if (gk[k] != 0.0) atomicAdd(dst + k, (float)(dC * gk[k]));
+                             return false;
+                         });
+            }
+        }
+    }
+    if (loss) {
+        for (int off = 32; off > 0; off >>= 1) l2 += __shfl_xor(l2, off);
+        if ((threadIdx.x & 63) == 0 && l2 != 0.f) atomicAdd(loss, l2);
+    }
+}
+
+// Chain rule from (mu, M, d) to the primitive parameters (mu, s, q, d): with
+// the rotation of the unit quaternion q / |q| (the normalisation included),
+// M = S^-1 R^T, M_ij = R_ji / s_i.  grad [n][11] = (mu, s, q, d) is added to.
+__global__ void k_cdf_chain(int64_t n, const float *scale, const float *rot, const float *g13, float *grad) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const float *g = g13 + 13 * k;
+    const double qw = rot[4 * k], qx = rot[4 * k + 1], qy = rot[4 * k + 2], qz = rot[4 * k + 3];
+    const double nq = qw * qw + qx * qx + qy * qy + qz * qz;
+    const double t = 2.0 / nq;
+    // R = I + t Q(q)
+    const double Q[3][3] = {{-(qy * qy + qz * qz), qx * qy - qw * qz, qx * qz + qw * qy},
+                            {qx * qy + qw * qz, -(qx * qx + qz * qz), qy * qz - qw * qx},
+                            {qx * qz - qw * qy, qy * qz + qw * qx, -(qx * qx + qy * qy)}};
+    // dQ_ij / d(w, x, y, z)
+    const double dQ[4][3][3] = {
+        {{0, -qz, qy}, {qz, 0, -qx}, {-qy, qx, 0}},
+        {{0, qy, qz}, {qy, -2 * qx, -qw}, {qz, qw, -2 * qx}},
+        {{-2 * qy, qx, qw}, {qx, 0, qz}, {-qw, qz, -2 * qy}},
+        {{-2 * qz, -qw, qx}, {qw, -2 * qz, qy}, {qx, qy, 0}}};
+    const double qa[4] = {qw, qx, qy, qz};
+    double R[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) R[i][j] = (i == j ? 1.0 : 0.0) + t * Q[i][j];
+    const double s[3] = {scale[3 * k], scale[3 * k + 1], scale[3 * k + 2]};
+    double gs[3], gR[3][3];
+    for (int i = 0; i < 3; ++i) {
+        gs[i] = 0.0;
+        for (int j = 0; j < 3; ++j) {
+            const double gm = g[3 + 3 * i + j];
+            gs[i] -= gm * R[j][i] / (s[i] * s[i]);
+            gR[j][i] = gm / s[i];
+        }
+    }
+    double gq[4];
+    for (int a = 0; a < 4; ++a) {
+        double acc = 0.0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) acc += gR[i][j] * t * (dQ[a][i][j] - 2.0 * qa[a] * Q[i][j] / nq);
+        gq[a] = acc;
+    }
+    float *o = grad + 11 * k;
+    o[0] += g[0]; o[1] += g[1]; o[2] += g[2];
+    o[3] += (float)gs[0]; o[4] += (float)gs[1]; o[5] += (float)gs[2];
+    o[6] += (float)gq[0]; o[7] += (float)gq[1]; o[8] += (float)gq[2]; o[9] += (float)gq[3];
+    o[10] += g[12];
+}
+
+// Jittered pinhole rays, one per pixel: jitter from the counter-based
+// generator of sample `sample` (the renderer's camera paths use the same
+// stream), origin the camera, t in [0, inf).
+__global__ void k_camera_rays(CamDev cam, uint64_t seed, uint32_t sample, float *rays) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t npix = (int64_t)cam.width * cam.height;
+    if (i >= npix) return;
+    const int px = (int)(i % cam.width), py = (int)(i / cam.width);
+    const Rng4 g = rng4(seed, (uint32_t)i, sample, 0, 0);
+    const V3 d = camera_dir(cam, px, py, g.u[0], g.u[1]);
+    float4 *o = reinterpret_cast<float4 *>(rays) + 2 * i;
+    o[0] = make_float4(cam.ox, cam.oy, cam.oz, d.x);
+    o[1] = make_float4(d.y, d.z, 0.f, __builtin_huge_valf());
+}
+
+// Adam on the primitive parameters (the transmittance optimisation of
+// Sec. 7.2): gradient [n][11] = (mu, s, q, d), moments m, v of the same
+// layout, step `t` (from 1); learning rate lr_rot for q and lr for the rest;
+// then scales at least s_min, densities at least 0, rotations renormalised.
+__global__ void k_fit_adam(int64_t n, float *mean, float *scale, float *rot, float *dens, const float *grad,
+                           float *m, float *v, int t, float lr, float lr_rot, float b1, float b2, float eps,
+                           float s_min) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    float *prm[11] = {mean + 3 * k, mean + 3 * k + 1, mean + 3 * k + 2, scale + 3 * k, scale + 3 * k + 1,
+                      scale + 3 * k + 2, rot + 4 * k, rot + 4 * k + 1, rot + 4 * k + 2, rot + 4 * k + 3, dens + k};
+    const double c1 = 1.0 - pow((double)b1, t), c2 = 1.0 - pow((double)b2, t);
+    for (int j = 0; j < 11; ++j) {
+        const int64_t e = 11 * k + j;
+        const float g = grad[e];
+        const float mj = b1 * m[e] + (1.f - b1) * g;
+        const float vj = b2 * v[e] + (1.f - b2) * g * g;
+        m[e] = mj;
+        v[e] = vj;
+        const double mh = mj / c1, vh = vj / c2;
+        const float rate = (j >= 6 && j < 10) ? lr_rot : lr;
+        *prm[j] -= (float)(rate * mh / (sqrt(vh) + eps));
+    }
+    for (int j = 0; j < 3; ++j) scale[3 * k + j] = fmaxf(scale[3 * k + j], s_min);
+    dens[k] = fmaxf(dens[k], 0.f);
+    const float qn = sqrtf(rot[4 * k] * rot[4 * k] + rot[4 * k + 1] * rot[4 * k + 1] +
+                           rot[4 * k + 2] * rot[4 * k + 2] + rot[4 * k + 3] * rot[4 * k + 3]);
+    if (qn > 0.f)
+        for (int j = 0; j < 4; ++j) rot[4 * k + j] /= qn;
+    else
+        rot[4 * k] = 1.f;
+}
+
+}  // namespace
+
+hipError_t accum_cdf(ugp_ctx ctx, const ugp_scene *scene, int64_t n, const float *rays, const int32_t *excl,
+                     const float *target, float loss_scale, float *C_out, float *loss, float *grad) {
+    hipStream_t st = ctx->stream;
+    const SceneDev &S = ctx->scene;
+    double *tsat = nullptr;
+    float *g13 = nullptr;
+    hipError_t e = hipMallocAsync((void **)&tsat, sizeof(double) * (size_t)n, st);
+    if (e != hipSuccess) return e;
+    if (grad) {
+        e = hipMallocAsync((void **)&g13, sizeof(float) * 13 * (size_t)S.n, st);
+        if (e == hipSuccess) e = hipMemsetAsync(g13, 0, sizeof(float) * 13 * (size_t)S.n, st);
+    }
+    if (e == hipSuccess)
+        e = launch_sweep(ctx, kModeSaturate, n, rays, excl, nullptr, nullptr, nullptr, nullptr, nullptr, tsat);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_cdf, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, S, n, rays,
+                           excl, (const double *)tsat, target, loss_scale, C_out, target ? loss : nullptr,
+                           target ? g13 : nullptr, ctx->err);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && grad && target) {
+        hipLaunchKernelGGL(k_cdf_chain, dim3((unsigned)((S.n + 255) / 256)), dim3(256), 0, st, S.n, scene->scale,
+                           scene->rotation, (const float *)g13, grad);
+        e = hipGetLastError();
+    }
+    hipFreeAsync(tsat, st);
+    if (g13) hipFreeAsync(g13, st);
+    return e;
+}
+
+hipError_t camera_rays(ugp_ctx ctx, const ugp_camera *cam, uint64_t seed, uint32_t sample, float *rays) {
+    CamDev c;
+    make_cam_dev(cam, &c);
+    const int64_t npix = (int64_t)cam->width * cam->height;
+    hipLaunchKernelGGL(k_camera_rays, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, ctx->stream, c, seed,
+                       sample, rays);
+    return hipGetLastError();
+}
+
+hipError_t fit_adam(ugp_ctx ctx, int64_t n, float *mean, float *scale, float *rot, float *dens, const float *grad,
+                    float *m, float *v, int t, float lr, float lr_rot, float b1, float b2, float eps, float s_min) {
+    hipLaunchKernelGGL(k_fit_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, n, mean, scale,
+                       rot, dens, grad, m, v, t, lr, lr_rot, b1, b2, eps, s_min);
+    return hipGetLastError();
+}
+
+}  // namespace ugp

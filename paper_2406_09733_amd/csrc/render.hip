@@ -904,17 +904,7 @@ hipError_t ensure_nrc_buffers(ugp_ctx ctx, int64_t npix, int64_t rec_cap, bool *
 
 }  // namespace
 
-hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p, float *sum, float *sumsq) {
-    const SceneDev &S0 = ctx->scene;
-    const int64_t npix = (int64_t)cam->width * cam->height;
-    // chunks of `cs` samples of every pixel share the pool of path slots
-    const int cs = (int)std::max<int64_t>(1, std::min<int64_t>(p->spp, kChunkPaths / npix));
-    const int64_t lcap = npix * cs;
-    const int64_t pool = std::min<int64_t>(ctx->path_pool > 0 ? ctx->path_pool : kPoolPaths, lcap);
-    hipError_t e = ensure_buffers(ctx, pool, lcap);
-    if (e != hipSuccess) return e;
-    RenderBuffers *rb = ctx->rb;
-    hipStream_t st = ctx->stream;
+void make_cam_dev(const ugp_camera *cam, CamDev *out) {
     // camera basis (double on the host, float on the device)
     double f[3] = {(double)cam->target[0] - cam->origin[0], (double)cam->target[1] - cam->origin[1],
                    (double)cam->target[2] - cam->origin[2]};
@@ -927,10 +917,24 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
     const double u[3] = {rt[1] * f[2] - rt[2] * f[1], rt[2] * f[0] - rt[0] * f[2], rt[0] * f[1] - rt[1] * f[0]};
     const double th = tan(0.5 * (double)cam->vfov_deg * 3.14159265358979323846 / 180.0);
     const double asp = (double)cam->width / (double)cam->height;
+    *out = CamDev{cam->origin[0], cam->origin[1], cam->origin[2], (float)f[0], (float)f[1], (float)f[2],
+                  (float)(rt[0] * th * asp), (float)(rt[1] * th * asp), (float)(rt[2] * th * asp),
+                  (float)(u[0] * th), (float)(u[1] * th), (float)(u[2] * th), cam->width, cam->height};
+}
+
+hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p, float *sum, float *sumsq) {
+    const SceneDev &S0 = ctx->scene;
+    const int64_t npix = (int64_t)cam->width * cam->height;
+    // chunks of `cs` samples of every pixel share the pool of path slots
+    const int cs = (int)std::max<int64_t>(1, std::min<int64_t>(p->spp, kChunkPaths / npix));
+    const int64_t lcap = npix * cs;
+    const int64_t pool = std::min<int64_t>(ctx->path_pool > 0 ? ctx->path_pool : kPoolPaths, lcap);
+    hipError_t e = ensure_buffers(ctx, pool, lcap);
+    if (e != hipSuccess) return e;
+    RenderBuffers *rb = ctx->rb;
+    hipStream_t st = ctx->stream;
     PassArgs P;
-    P.cam = CamDev{cam->origin[0], cam->origin[1], cam->origin[2], (float)f[0], (float)f[1], (float)f[2],
-                   (float)(rt[0] * th * asp), (float)(rt[1] * th * asp), (float)(rt[2] * th * asp),
-                   (float)(u[0] * th), (float)(u[1] * th), (float)(u[2] * th), cam->width, cam->height};
+    make_cam_dev(cam, &P.cam);
     for (int k = 0; k < 3; ++k) {
         P.blo[k] = S0.lo[k];
         const float ext = S0.hi[k] - S0.lo[k];

@@ -33,6 +33,7 @@ struct SweepArgs {
     int32_t *ovf_list;   // rays that overflowed the main buffer
     int32_t *ovf_count;
     int32_t *counts;     // optional [n][4] per-ray traversal counters
+    double *td_out;      // optional: saturate mode, t_sat in full precision
 };
 
 // emitter mode: clip the ray at the exit of the target's chord
@@ -82,10 +83,12 @@ __device__ __forceinline__ void run_sweep(const SceneDev &S, const SweepArgs &A,
         }
         if (A.prim_out) A.prim_out[i] = -1;
         if (A.f_out) A.f_out[i] = __builtin_nanf("");
+        if (A.td_out) A.td_out[i] = __builtin_nan("");
         return;
     }
     if (A.prim_out) A.prim_out[i] = o.prim;
     if (A.f_out) A.f_out[i] = o.t;
+    if (A.td_out) A.td_out[i] = o.td;
 }
 
 __global__ __launch_bounds__(kBlock, 2) void k_sweep_main(SceneDev S, SweepArgs A, uint32_t *err) {
@@ -114,12 +117,12 @@ hipError_t launch_transmittance(ugp_ctx ctx, int64_t n, const float *rays, const
 
 hipError_t launch_sweep(ugp_ctx ctx, int mode, int64_t n, const float *rays, const int32_t *excl,
                         const float *u, const int32_t *target, int32_t *prim_out, float *f_out,
-                        int32_t *counts) {
+                        int32_t *counts, double *td_out) {
     int32_t *buf = (int32_t *)ctx_scratch(ctx, sizeof(int32_t) * (size_t)(n + 1));
     if (!buf) return hipErrorOutOfMemory;
     hipError_t e = hipMemsetAsync(buf, 0, sizeof(int32_t), ctx->stream);
     if (e != hipSuccess) return e;
-    SweepArgs A{mode, n, rays, excl, u, target, prim_out, f_out, buf + 1, buf, counts};
+    SweepArgs A{mode, n, rays, excl, u, target, prim_out, f_out, buf + 1, buf, counts, td_out};
     const unsigned g = (unsigned)((n + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_sweep_main, dim3(g), dim3(kBlock), 0, ctx->stream, ctx->scene, A, ctx->err);
     hipLaunchKernelGGL(k_sweep_wide, dim3(g), dim3(kBlock), 0, ctx->stream, ctx->scene, A, ctx->err);

@@ -478,6 +478,7 @@ struct SweepOut {
     int prim;      // collide: selected original index or -1
     float t;       // collide: scatter distance; saturate: t_sat; emitter: factor
     int status;    // 0 ok, 1 event-buffer overflow
+    double td;     // saturate: t_sat in full precision
 };
 
 // loops over the event buffer are unrolled (register arrays) only for small K
@@ -618,7 +619,10 @@ struct SweepState {
 template <int K>
 __device__ __forceinline__ void sweep_start(SweepState<K> &st, SweepOut &out, const RayD &r, int mode) {
     out = SweepOut{-1, __builtin_nanf(""), 0};
-    if (mode == kModeSaturate) out.t = (float)r.t1;
+    if (mode == kModeSaturate) {
+        out.t = (float)r.t1;
+        out.td = r.t1;
+    }
     if (mode == kModeEmitter) out.t = 0.f;
     st.B.n = 0;
     st.S_fin = 0.f;
@@ -891,6 +895,7 @@ __device__ __forceinline__ bool sweep_round(const SceneDev &S, const RayD &r, in
         const double tsat = t;
         if (mode == kModeSaturate) {
             out.t = (float)tsat;
+            out.td = tsat;
             return true;
         }
         if (mode == kModeEmitter) {

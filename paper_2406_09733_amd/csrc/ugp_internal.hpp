@@ -102,11 +102,14 @@ hipError_t launch_transmittance(ugp_ctx ctx, int64_t n, const float *rays, const
                                 float *T, float *F);
 hipError_t launch_sweep(ugp_ctx ctx, int mode, int64_t n, const float *rays, const int32_t *excl,
                         const float *u, const int32_t *target, int32_t *prim_out, float *f_out,
-                        int32_t *counts = nullptr);
+                        int32_t *counts = nullptr, double *td_out = nullptr);
 
 // render.hip
 hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p, float *sum,
                   float *sumsq);
+struct CamDev;
+// the device camera (origin, forward, right and up scaled to the field of view)
+void make_cam_dev(const ugp_camera *cam, CamDev *out);
 void free_render(ugp_ctx ctx);
 // device float: loss of the last radiance-cache training step of a render (or NULL)
 const float *render_nrc_loss(ugp_ctx ctx);
@@ -144,6 +147,13 @@ hipError_t nrc_train_render(ugp_ctx ctx, int64_t cap, const int32_t *n_dev, cons
 hipError_t nrc_set_scale(ugp_ctx ctx, float value);
 const float *nrc_scale_ptr(ugp_ctx ctx);
 hipError_t nrc_adapt(ugp_ctx ctx, const int32_t *attempted, int32_t cap, float *frac);
+
+// diff.hip -- accumulated free-flight CDF, its loss and gradient; camera rays; Adam with clamps
+hipError_t accum_cdf(ugp_ctx ctx, const ugp_scene *scene, int64_t n, const float *rays, const int32_t *excl,
+                     const float *target, float loss_scale, float *C_out, float *loss, float *grad);
+hipError_t camera_rays(ugp_ctx ctx, const ugp_camera *cam, uint64_t seed, uint32_t sample, float *rays);
+hipError_t fit_adam(ugp_ctx ctx, int64_t n, float *mean, float *scale, float *rot, float *dens, const float *grad,
+                    float *m, float *v, int t, float lr, float lr_rot, float b1, float b2, float eps, float s_min);
 
 // device scratch of the context: returns a buffer of at least `bytes`
 void *ctx_scratch(ugp_ctx ctx, size_t bytes);

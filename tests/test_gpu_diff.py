@@ -1,0 +1,183 @@
+"""GPU tests of the differentiation entry points (transmittance optimisation,
+Sec. 7.2): the accumulated free-flight CDF against the oracle, the gradient
+of the transmittance-image loss against FP64 central finite differences of
+the oracle (t_sat held fixed, as the derivative of Sec. 7.2 takes it), the
+Adam update with its clamps, and the jittered camera rays.
+
+Tolerances:
+  C            |gpu - oracle| <= 2e-5 (float sums of O(1) terms; a saturated
+               ray's C is 1 to the float resolution of the t_sat solve)
+  gradient     per primitive, every component within 2% of that primitive's
+               largest finite-difference component (float accumulation of
+               ~1e2 ray terms; finite-difference truncation ~1e-6)
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2406_09733_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    import paper_2406_09733_amd as P
+    return P.Context(0)
+
+
+def _dense_tiny(factor=8.0):
+    sc = scenes.tiny_random()
+    sc["density"] = (np.asarray(sc["density"], np.float32) * factor).astype(np.float32)
+    return sc
+
+
+@pytest.mark.parametrize("name", ["tiny_random", "mixed_100k"])
+def test_accum_cdf_parity(ctx, orc, torch, name):
+    _say("accum_cdf parity", name)
+    sc = _dense_tiny() if name == "tiny_random" else scenes.mixed_100k()
+    rays = scenes.probe_rays(sc, 2048, seed=201)
+    rng = np.random.default_rng(5)
+    ex = rng.integers(-1, sc["mean"].shape[0], rays.shape[0]).astype(np.int32)
+    ex[::2] = -1
+    S = orc.Scene(sc)
+    C_ref, ts = S.accum_cdf(rays, ex)
+    ctx.build_bvh(sc)
+    C = ctx.accum_cdf(rays, exclude=ex).cpu().numpy().astype(np.float64)
+    ctx.sync()
+    err = np.abs(C - C_ref)
+    _say(f"  max |dC| {err.max():.2e}; saturated rays {(ts < np.inf).sum()} of {len(ts)}")
+    assert np.all(err <= 2e-5)
+
+
+def test_accum_cdf_loss_and_gradient_vs_finite_differences(ctx, orc, torch):
+    _say("accum_cdf loss and gradient vs FP64 central differences")
+    sc = _dense_tiny()
+    n = sc["mean"].shape[0]
+    rays = scenes.probe_rays(sc, 512, seed=202, aimed_frac=1.0, finite_frac=0.2)
+    S = orc.Scene(sc)
+    C0, ts0 = S.accum_cdf(rays)
+    target = (0.5 * C0 + 0.1).astype(np.float32)
+    ctx.build_bvh(sc)
+    loss = torch.zeros(1, device="cuda", dtype=torch.float32)
+    grad = torch.zeros((n, 11), device="cuda", dtype=torch.float32)
+    ctx.accum_cdf(rays, target=target, want_C=False, loss=loss, grad=grad)
+    ctx.sync()
+    L_ref = float(np.sum((C0 - target) ** 2))
+    L_gpu = float(loss.item())
+    _say(f"  loss gpu {L_gpu:.6f} oracle {L_ref:.6f}")
+    assert abs(L_gpu - L_ref) <= 1e-4 * L_ref
+    g = grad.cpu().numpy().astype(np.float64)
+    prims = np.argsort(-np.abs(g).max(axis=1))[:6]
+
+    def loss_of(s2):
+        C, _ = orc.Scene(s2).accum_cdf(rays, tsat=ts0)
+        return float(np.sum((C - target) ** 2))
+
+    fields = [("mean", 0, 3), ("scale", 3, 3), ("rotation", 6, 4), ("density", 10, 1)]
+    worst = 0.0
+    for k in prims:
+        fd = np.zeros(11)
+        smin = float(np.min(sc["scale"][k]))
+        for name, off, w in fields:
+            for j in range(w):
+                base = np.asarray(sc[name], np.float32).reshape(n, -1)
+                v = float(base[k, j])
+                h = {"mean": 1e-3 * smin, "scale": 1e-3 * v, "rotation": 1e-3, "density": 1e-3 * v}[name]
+                vals = []
+                for sgn in (1, -1):
+                    s2 = dict(sc)
+                    arr = base.copy()
+                    arr[k, j] = np.float32(v + sgn * h)
+                    s2[name] = arr.reshape(np.asarray(sc[name]).shape)
+                    vals.append((float(arr[k, j]), loss_of(s2)))
+                fd[off + j] = (vals[0][1] - vals[1][1]) / (vals[0][0] - vals[1][0])
+        scale_k = np.abs(fd).max()
+        rel = np.abs(g[k] - fd).max() / scale_k
+        worst = max(worst, rel)
+        _say(f"  prim {k}: max |g - fd| / max |fd| = {rel:.2e} (max |fd| {scale_k:.3e})")
+        assert rel <= 2e-2, (k, g[k], fd)
+    _say(f"  worst {worst:.2e}")
+
+
+def test_fit_adam_step_and_clamps(ctx, torch):
+    _say("fit_adam vs a numpy Adam with the clamps")
+    rng = np.random.default_rng(9)
+    n = 257
+    P = {"mean": rng.normal(size=(n, 3)), "scale": rng.uniform(0.01, 0.1, (n, 3)),
+         "rotation": rng.normal(size=(n, 4)), "density": rng.uniform(0.1, 2.0, n)}
+    P = {k: v.astype(np.float32) for k, v in P.items()}
+    P["scale"][:5, 0] = 1.5e-6   # pushed below the clamp
+    P["density"][:5] = 1e-6      # pushed below zero
+    G = [rng.normal(size=(n, 11)).astype(np.float32) for _ in range(2)]
+    G[0][:5, 3] = 100.0
+    G[0][:5, 10] = 100.0
+    lr, lr_rot, smin = 1e-3, 2e-4, 1e-6
+    dev = {k: torch.tensor(v, device="cuda").contiguous() for k, v in P.items()}
+    m = torch.zeros((n, 11), device="cuda")
+    v = torch.zeros((n, 11), device="cuda")
+    ref = {k: v_.astype(np.float64).copy() for k, v_ in P.items()}
+    mr = np.zeros((n, 11)); vr = np.zeros((n, 11))
+    for t in (1, 2):
+        ctx.fit_adam(dev, torch.tensor(G[t - 1], device="cuda"), m, v, t, lr=lr, lr_rotation=lr_rot,
+                     min_scale=smin)
+        g = G[t - 1].astype(np.float64)
+        mr = 0.9 * mr + 0.1 * g
+        vr = 0.999 * vr + 0.001 * g * g
+        step = (mr / (1 - 0.9 ** t)) / (np.sqrt(vr / (1 - 0.999 ** t)) + 1e-8)
+        rate = np.full(11, lr); rate[6:10] = lr_rot
+        flat = np.concatenate([ref["mean"], ref["scale"], ref["rotation"], ref["density"][:, None]], axis=1)
+        flat -= rate * step
+        ref["mean"], ref["scale"], ref["rotation"], ref["density"] = (
+            flat[:, 0:3], np.maximum(flat[:, 3:6], smin), flat[:, 6:10], np.maximum(flat[:, 10], 0.0))
+        ref["rotation"] = ref["rotation"] / np.linalg.norm(ref["rotation"], axis=1, keepdims=True)
+    ctx.sync()
+    for k in ref:
+        got = dev[k].cpu().numpy().astype(np.float64)
+        assert np.allclose(got, ref[k], rtol=2e-5, atol=2e-6), (k, np.abs(got - ref[k]).max())
+    got_s = dev["scale"].cpu().numpy()
+    assert np.all(got_s >= smin) and np.all(dev["density"].cpu().numpy() >= 0)
+    assert np.allclose(np.linalg.norm(dev["rotation"].cpu().numpy(), axis=1), 1.0, atol=1e-6)
+
+
+def test_camera_rays(ctx, torch):
+    _say("camera rays: unit directions inside their pixels, deterministic per sample")
+    cam = dict(scenes.camera("tiny_random"), width=48, height=32)
+    r1 = ctx.camera_rays(cam, seed=5, sample=3).cpu().numpy().astype(np.float64)
+    r2 = ctx.camera_rays(cam, seed=5, sample=3).cpu().numpy()
+    r3 = ctx.camera_rays(cam, seed=5, sample=4).cpu().numpy()
+    ctx.sync()
+    assert np.array_equal(r1.astype(np.float32), r2) and not np.array_equal(r2, r3)
+    assert np.allclose(r1[:, 0:3], np.asarray(cam["origin"], np.float64)[None], atol=0)
+    d = r1[:, 3:6]
+    assert np.allclose(np.linalg.norm(d, axis=1), 1.0, atol=1e-6)
+    assert np.all(r1[:, 6] == 0) and np.all(np.isinf(r1[:, 7]))
+    # back to screen coordinates: pixel + jitter in [0, 1)
+    f = np.asarray(cam["target"], np.float64) - np.asarray(cam["origin"], np.float64)
+    f /= np.linalg.norm(f)
+    rt = np.cross(f, np.asarray(cam["up"], np.float64)); rt /= np.linalg.norm(rt)
+    up = np.cross(rt, f)
+    th = np.tan(np.radians(cam["vfov_deg"]) / 2)
+    asp = cam["width"] / cam["height"]
+    sx = (d @ rt) / (d @ f) / (th * asp)
+    sy = (d @ up) / (d @ f) / th
+    px = (sx + 1) / 2 * cam["width"]
+    py = (1 - sy) / 2 * cam["height"]
+    i = np.arange(cam["width"] * cam["height"])
+    jx, jy = px - i % cam["width"], py - i // cam["width"]
+    assert np.all(jx > -1e-3) and np.all(jx < 1 + 1e-3) and np.all(jy > -1e-3) and np.all(jy < 1 + 1e-3)
+    assert 0.3 < jx.mean() < 0.7 and 0.3 < jy.mean() < 0.7

@@ -1,0 +1,39 @@
+"""The oracle's accumulated free-flight CDF (Sec. 7.2, eq. accum_cdf) against
+what its definition fixes: clipped at the saturating distance the primitives'
+free-flight probabilities sum to exactly 1 on a saturated ray, and to the
+ray's opacity 1 - T (eq. transmittance) on any other."""
+import numpy as np
+
+from paper_2406_09733_amd import scenes
+
+
+def _dense(sc):
+    # the tiny scene with 30x the density: rays through it saturate
+    d = dict(sc)
+    d["density"] = np.asarray(sc["density"], np.float32) * 30.0
+    return d
+
+
+def test_accum_cdf_is_one_when_saturated_else_one_minus_T(orc, tiny_scene):
+    S = orc.Scene(_dense(tiny_scene))
+    rays = scenes.probe_rays(tiny_scene, 600, seed=31, aimed_frac=0.9, finite_frac=0.0)
+    C, ts = S.accum_cdf(rays)
+    F, T = S.transmittance(rays)
+    sat = ts < rays[:, 7].astype(np.float64)
+    assert sat.sum() > 50 and (~sat).sum() > 50
+    assert np.all(np.abs(C[sat] - 1.0) <= 1e-9)
+    assert np.allclose(C[~sat], F[~sat], rtol=0, atol=1e-12)
+    assert np.allclose(C[~sat], 1.0 - T[~sat], rtol=0, atol=1e-12)
+
+
+def test_accum_cdf_with_fixed_tsat_is_F_at_that_point(orc, tiny_scene):
+    # holding t_sat fixed (the reading of the derivative in Sec. 7.2) the sum
+    # is F there; moving the clip point inside the saturated region changes it
+    S = orc.Scene(_dense(tiny_scene))
+    rays = scenes.probe_rays(tiny_scene, 200, seed=32, aimed_frac=1.0, finite_frac=0.0)
+    C, ts = S.accum_cdf(rays)
+    sat = ts < np.inf
+    assert sat.sum() > 20
+    C2, _ = S.accum_cdf(rays, tsat=np.where(sat, ts * 0.999, ts))
+    assert np.all(C2[sat] <= C[sat] + 1e-12)
+    assert np.all(C2[sat] < 1.0)
