@@ -300,6 +300,45 @@ def copy_probe(nbytes: int):
     print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": 3}))
 
 
+def transmittance_fit(args):
+    """The transmittance optimisation of Sec. 7.2 on the 100K-primitive mixed
+    scene: reference images of the scene from 8 views of 256x256 (16 jittered
+    rays per pixel), a perturbed copy as the start, then Adam steps with one
+    jittered ray per pixel per view, the hierarchy rebuilt every step.  Prints
+    one JSON line: steps per second, rays per second through the CDF and its
+    gradient, the loss at the start and the end."""
+    import numpy as np
+    import torch
+
+    import paper_2406_09733_amd as P
+    from paper_2406_09733_amd import fit, scenes
+
+    sc = scenes.mixed_100k()
+    n = sc["mean"].shape[0]
+    cams = scenes.ring_cameras((0.5, 0.5, 0.5), 2.2, n=8, size=256)
+    ctx = P.Context(0)
+    target = fit.reference_images(ctx, sc, cams, seed=3, samples=16)
+    start = scenes.perturbed(sc, seed=11)
+    params = {k: torch.tensor(np.asarray(start[k]), device="cuda").contiguous()
+              for k in ("mean", "scale", "rotation", "density", "albedo", "roughness", "emission", "material")}
+    # warm-up step on a copy (kernels loaded, allocations made), then the timed run
+    warm = {k: v.clone() for k, v in params.items()}
+    lr = tuple(float(x) for x in args.fit_lr.split(","))
+    fit.fit_transmittance(ctx, warm, cams, target, iters=1, lr=lr)
+    out = fit.fit_transmittance(ctx, params, cams, target, iters=args.fit_steps, lr=lr,
+                                on_step=lambda it: log(f"[fit] step {it}") if it % 10 == 0 else None)
+    ls = out["loss"]
+    rays = args.fit_steps * sum(c["width"] * c["height"] for c in cams)
+    res = {"metric": "transmittance-fit steps/s (Sec. 7.2) on the 100K mixed scene",
+           "value": round(args.fit_steps / out["seconds"], 3), "unit": "steps/s",
+           "ms_per_step": round(1e3 * out["seconds"] / args.fit_steps, 2),
+           "rays_per_s": round(rays / out["seconds"], 1), "primitives": n, "views": len(cams),
+           "resolution": "256x256", "steps": args.fit_steps, "lr_mean_logscale_rotation_density": lr,
+           "loss_first": ls[0], "loss_last": ls[-1], "loss_ratio": round(ls[-1] / ls[0], 4),
+           "loss_curve": [round(x, 7) for x in ls[:: max(1, len(ls) // 20)]]}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -326,6 +365,10 @@ def main():
                     help="spp of the inference-only renders that measure each cache's bias")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device copy of BYTES (counter calibration) and exit")
+    ap.add_argument("--fit", action="store_true", help="run the transmittance-optimisation benchmark instead")
+    ap.add_argument("--fit-steps", type=int, default=50)
+    ap.add_argument("--fit-lr", default="5e-5,1e-2,2e-3,1e-2",
+                    help="Adam rates of the means, log scales, rotations and densities")
     ap.add_argument("--exposure", type=float, default=0.0,
                     help="image scale before clamping (0 = reference noise 0.3 x target)")
     args = ap.parse_args()
@@ -339,6 +382,9 @@ def main():
         return
     if args.time_to_rmse:
         time_to_rmse(args)
+        return
+    if args.fit:
+        transmittance_fit(args)
         return
 
     import numpy as np

@@ -213,13 +213,15 @@ ugp_status ugp_camera_rays(ugp_ctx ctx, const ugp_camera *cam, uint64_t seed, in
 
 /* One Adam step (Kingma and Ba; beta = (0.9, 0.999), eps = 1e-8) on the
  * primitive parameters with gradient grad [n][11] (the layout of
- * ugp_accum_cdf), moments m and v [n][11] (zero before step 1), step >= 1:
- * learning rate lr_rotation for the rotations and lr for the rest; then, as in
- * Sec. 7.2, scales clamped to at least min_scale (> 0), densities to at least
- * 0, rotations renormalised.  Arrays are device memory, updated in place. */
+ * ugp_accum_cdf), moments m and v [n][11] (zero before step 1), step >= 1.
+ * lr [host] float[4]: the rates of the means, of the scales, of the rotations
+ * and of the densities.  Scales step on log s (moments of s dL/ds; s is
+ * multiplied by exp(-step)), so their rate is relative to each primitive's
+ * extent; the others step linearly.  Then, as in Sec. 7.2, scales are clamped
+ * to at least min_scale (> 0), densities to at least 0, rotations
+ * renormalised.  Arrays are device memory, updated in place. */
 ugp_status ugp_fit_adam(ugp_ctx ctx, int64_t n, float *mean, float *scale, float *rotation, float *density,
-                        const float *grad, float *m, float *v, int32_t step, float lr, float lr_rotation,
-                        float min_scale);
+                        const float *grad, float *m, float *v, int32_t step, const float lr[4], float min_scale);
 
 /* Instrumentation: runs the ordered sweep of ugp_sample_collision (mode 0),
  * ugp_saturation (mode 1) or ugp_emitter_query (mode 2) and writes, per ray,

@@ -113,7 +113,7 @@ def lib():
         L.ugp_nrc_records.argtypes = [vp, i64, vp, vp, C.POINTER(C.c_int64)]
         L.ugp_accum_cdf.argtypes = [vp, vp, i64, vp, vp, vp, C.c_float, vp, vp, vp]
         L.ugp_camera_rays.argtypes = [vp, vp, C.c_uint64, i64, vp]
-        L.ugp_fit_adam.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, C.c_int32, C.c_float, C.c_float, C.c_float]
+        L.ugp_fit_adam.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, C.c_int32, C.POINTER(C.c_float), C.c_float]
         L.ugp_status_string.argtypes = [C.c_int]
         L.ugp_status_string.restype = C.c_char_p
         for name in EXPORTS:
@@ -277,18 +277,18 @@ class Context:
         _check("ugp_camera_rays", lib().ugp_camera_rays(self.h, C.byref(c), int(seed), int(sample), _ptr(rays)))
         return rays
 
-    def fit_adam(self, params: dict, grad, m, v, step: int, lr: float = 1e-4, lr_rotation: float = 2e-5,
-                 min_scale: float = 1e-6):
+    def fit_adam(self, params: dict, grad, m, v, step: int, lr=(1e-4, 1e-2, 2e-5, 1e-4), min_scale: float = 1e-6):
         """ugp_fit_adam: one Adam step on params (device float32 tensors mean,
-        scale, rotation, density, updated in place) with clamps and renormalised
-        rotations."""
+        scale, rotation, density, updated in place); lr = rates of the means,
+        the log scales, the rotations and the densities; clamps and
+        renormalised rotations."""
         n = params["mean"].shape[0]
         for k in ("mean", "scale", "rotation", "density"):
             assert params[k].is_contiguous() and params[k].dtype == self.torch.float32
+        rates = (C.c_float * 4)(*[float(x) for x in lr])
         _check("ugp_fit_adam", lib().ugp_fit_adam(self.h, n, _ptr(params["mean"]), _ptr(params["scale"]),
                                                   _ptr(params["rotation"]), _ptr(params["density"]), _ptr(grad),
-                                                  _ptr(m), _ptr(v), int(step), float(lr), float(lr_rotation),
-                                                  float(min_scale)))
+                                                  _ptr(m), _ptr(v), int(step), rates, float(min_scale)))
 
     # ---- path tracing -----------------------------------------------------
     def render(self, cam: dict, params: dict, sum_rgb=None, sumsq_rgb=None):

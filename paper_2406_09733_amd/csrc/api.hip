@@ -231,16 +231,16 @@ ugp_status ugp_camera_rays(ugp_ctx ctx, const ugp_camera *cam, uint64_t seed, in
 }
 
 ugp_status ugp_fit_adam(ugp_ctx ctx, int64_t n, float *mean, float *scale, float *rotation, float *density,
-                        const float *grad, float *m, float *v, int32_t step, float lr, float lr_rotation,
-                        float min_scale) {
-    if (!ctx || n < 0 || step < 1 || !(lr >= 0.f) || !std::isfinite(lr) || !(lr_rotation >= 0.f) ||
-        !std::isfinite(lr_rotation) || !(min_scale > 0.f) || !std::isfinite(min_scale))
+                        const float *grad, float *m, float *v, int32_t step, const float lr[4], float min_scale) {
+    if (!ctx || n < 0 || step < 1 || !lr || !(min_scale > 0.f) || !std::isfinite(min_scale))
         return UGP_ERR_INVALID_ARGUMENT;
+    for (int k = 0; k < 4; ++k)
+        if (!(lr[k] >= 0.f) || !std::isfinite(lr[k])) return UGP_ERR_INVALID_ARGUMENT;
     if (n > 0 && (!mean || !scale || !rotation || !density || !grad || !m || !v)) return UGP_ERR_INVALID_ARGUMENT;
     if (n == 0) return UGP_OK;
     DeviceGuard g(ctx->device);
-    return from_hip(ugp::fit_adam(ctx, n, mean, scale, rotation, density, grad, m, v, step, lr, lr_rotation, 0.9f,
-                                  0.999f, 1e-8f, min_scale));
+    return from_hip(ugp::fit_adam(ctx, n, mean, scale, rotation, density, grad, m, v, step, lr, 0.9f, 0.999f, 1e-8f,
+                                  min_scale));
 }
 
 ugp_status ugp_sync(ugp_ctx ctx) {

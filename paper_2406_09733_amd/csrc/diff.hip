@@ -211,11 +211,15 @@ __global__ void k_camera_rays(CamDev cam, uint64_t seed, uint32_t sample, float 
 
 // Adam on the primitive parameters (the transmittance optimisation of
 // Sec. 7.2): gradient [n][11] = (mu, s, q, d), moments m, v of the same
-// layout, step `t` (from 1); learning rate lr_rot for q and lr for the rest;
-// then scales at least s_min, densities at least 0, rotations renormalised.
+// layout, step `t` (from 1).  Means, rotations and densities take plain Adam
+// steps (rates lr_mean, lr_rot, lr_dens); scales take them on log s (the
+// moments are of s dL/ds, the update multiplies s by exp(-step)), so a rate
+// is relative to each primitive's own extent -- thin axes are orders of
+// magnitude below the others.  Then, as in Sec. 7.2, scales are clamped to at
+// least s_min, densities to at least 0, rotations renormalised.
 __global__ void k_fit_adam(int64_t n, float *mean, float *scale, float *rot, float *dens, const float *grad,
-                           float *m, float *v, int t, float lr, float lr_rot, float b1, float b2, float eps,
-                           float s_min) {
+                           float *m, float *v, int t, float lr_mean, float lr_log_scale, float lr_rot,
+                           float lr_dens, float b1, float b2, float eps, float s_min) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     float *prm[11] = {mean + 3 * k, mean + 3 * k + 1, mean + 3 * k + 2, scale + 3 * k, scale + 3 * k + 1,
@@ -223,14 +227,19 @@ __global__ void k_fit_adam(int64_t n, float *mean, float *scale, float *rot, flo
     const double c1 = 1.0 - pow((double)b1, t), c2 = 1.0 - pow((double)b2, t);
     for (int j = 0; j < 11; ++j) {
         const int64_t e = 11 * k + j;
-        const float g = grad[e];
+        const bool is_scale = j >= 3 && j < 6;
+        const float g = is_scale ? grad[e] * *prm[j] : grad[e];
         const float mj = b1 * m[e] + (1.f - b1) * g;
         const float vj = b2 * v[e] + (1.f - b2) * g * g;
         m[e] = mj;
         v[e] = vj;
-        const double mh = mj / c1, vh = vj / c2;
-        const float rate = (j >= 6 && j < 10) ? lr_rot : lr;
-        *prm[j] -= (float)(rate * mh / (sqrt(vh) + eps));
+        const double step = (mj / c1) / (sqrt(vj / c2) + eps);
+        if (is_scale) {
+            *prm[j] = (float)((double)*prm[j] * exp(-(double)lr_log_scale * step));
+        } else {
+            const float rate = j < 3 ? lr_mean : (j < 10 ? lr_rot : lr_dens);
+            *prm[j] -= (float)(rate * step);
+        }
     }
     for (int j = 0; j < 3; ++j) scale[3 * k + j] = fmaxf(scale[3 * k + j], s_min);
     dens[k] = fmaxf(dens[k], 0.f);
@@ -284,9 +293,9 @@ hipError_t camera_rays(ugp_ctx ctx, const ugp_camera *cam, uint64_t seed, uint32
 }
 
 hipError_t fit_adam(ugp_ctx ctx, int64_t n, float *mean, float *scale, float *rot, float *dens, const float *grad,
-                    float *m, float *v, int t, float lr, float lr_rot, float b1, float b2, float eps, float s_min) {
+                    float *m, float *v, int t, const float lr[4], float b1, float b2, float eps, float s_min) {
     hipLaunchKernelGGL(k_fit_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, n, mean, scale,
-                       rot, dens, grad, m, v, t, lr, lr_rot, b1, b2, eps, s_min);
+                       rot, dens, grad, m, v, t, lr[0], lr[1], lr[2], lr[3], b1, b2, eps, s_min);
     return hipGetLastError();
 }
 

@@ -338,6 +338,38 @@ def camera(name: str) -> dict:
     raise KeyError(name)
 
 
+def ring_cameras(centre, radius: float, n: int = 8, size: int = 256, height: float = 0.3,
+                 vfov_deg: float = 40.0) -> list:
+    """n pinhole cameras on a ring around `centre` (tilted `height` x radius
+    up), all looking at it: the views of a transmittance fit."""
+    c = np.asarray(centre, np.float64)
+    cams = []
+    for k in range(n):
+        a = 2 * np.pi * k / n
+        o = c + radius * np.array([np.cos(a), height, np.sin(a)])
+        cams.append({"origin": tuple(float(x) for x in o), "target": tuple(float(x) for x in c),
+                     "up": (0.0, 1.0, 0.0), "vfov_deg": vfov_deg, "width": size, "height": size})
+    return cams
+
+
+def perturbed(sc: dict, seed: int = 0, pos: float = 0.5, scale: float = 0.25, dens: float = 0.5,
+              rot: float = 0.2) -> dict:
+    """A start for a transmittance fit: the primitives of `sc` with means moved
+    by N(0, (pos * smallest scale)^2) per axis, scales multiplied by
+    exp(U[-scale, scale]), densities by U[1 - dens, 1 + dens] and rotations
+    turned by a quaternion perturbation of size `rot`."""
+    rng = _rng(seed)
+    n = sc["mean"].shape[0]
+    out = {k: (np.array(v, copy=True) if isinstance(v, np.ndarray) else v) for k, v in sc.items()}
+    smin = np.min(sc["scale"], axis=1, keepdims=True)
+    out["mean"] = (sc["mean"] + rng.normal(size=(n, 3)) * pos * smin).astype(np.float32)
+    out["scale"] = (sc["scale"] * np.exp(rng.uniform(-scale, scale, (n, 3)))).astype(np.float32)
+    out["density"] = (sc["density"] * rng.uniform(1 - dens, 1 + dens, n)).astype(np.float32)
+    q = sc["rotation"] + rot * rng.normal(size=(n, 4))
+    out["rotation"] = (q / np.linalg.norm(q, axis=1, keepdims=True)).astype(np.float32)
+    return out
+
+
 def render_settings(name: str) -> dict:
     return {"tiny_random": {"spp": 4, "max_depth": 4, "seed": 0},
             "needles": {"spp": 4, "max_depth": 6, "seed": 4},
