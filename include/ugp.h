@@ -205,6 +205,20 @@ ugp_status ugp_accum_cdf(ugp_ctx ctx, const ugp_scene *scene, int64_t n_rays, co
                          const int32_t *exclude, const float *target, float loss_scale, float *C_out,
                          float *loss_out, float *grad);
 
+/* Radiance-field mode (Sec. 8, eq. rf): with emission and absorption only,
+ * the radiance along each ray is
+ *   L = sum_k 1/2 I_k(a_k, min(b_k, t_sat)) L_e,k,
+ * the primitives' free-flight probabilities up to the saturating distance
+ * times their emission (the scene's emission, view-independent as in Sec. 8),
+ * with no Monte Carlo.  Arguments as ugp_accum_cdf, but per ray three
+ * channels: L_out float [n][3] or NULL; target float [n][3]; loss_out +=
+ * loss_scale * sum_i |L_i - target_i|^2; grad float [scene->n][14] += its
+ * gradient with respect to (mean[3], scale[3], rotation[4], density,
+ * emission[3]), t_sat held fixed. */
+ugp_status ugp_rf_render(ugp_ctx ctx, const ugp_scene *scene, int64_t n_rays, const float *rays,
+                         const int32_t *exclude, const float *target, float loss_scale, float *L_out,
+                         float *loss_out, float *grad);
+
 /* One jittered pinhole ray per pixel of cam (row-major, rays [w*h][8] as the
  * queries take them, t in [0, inf)); the sub-pixel jitter is the renderer's
  * camera jitter of sample `sample` (counter-based generator keyed on seed,
@@ -212,16 +226,19 @@ ugp_status ugp_accum_cdf(ugp_ctx ctx, const ugp_scene *scene, int64_t n_rays, co
 ugp_status ugp_camera_rays(ugp_ctx ctx, const ugp_camera *cam, uint64_t seed, int64_t sample, float *rays);
 
 /* One Adam step (Kingma and Ba; beta = (0.9, 0.999), eps = 1e-8) on the
- * primitive parameters with gradient grad [n][11] (the layout of
- * ugp_accum_cdf), moments m and v [n][11] (zero before step 1), step >= 1.
- * lr [host] float[4]: the rates of the means, of the scales, of the rotations
- * and of the densities.  Scales step on log s (moments of s dL/ds; s is
- * multiplied by exp(-step)), so their rate is relative to each primitive's
- * extent; the others step linearly.  Then, as in Sec. 7.2, scales are clamped
- * to at least min_scale (> 0), densities to at least 0, rotations
- * renormalised.  Arrays are device memory, updated in place. */
+ * primitive parameters.  emission NULL: gradient grad [n][11] (the layout of
+ * ugp_accum_cdf); emission [n][3]: grad [n][14] (the layout of ugp_rf_render).
+ * Moments m and v have the gradient's layout (zero before step 1); step >= 1.
+ * lr [host] float[5]: the rates of the means, of the scales, of the
+ * rotations, of the densities and of the emissions (ignored without).
+ * Scales step on log s (moments of s dL/ds; s is multiplied by exp(-step)),
+ * so their rate is relative to each primitive's extent; the others step
+ * linearly.  Then, as in Sec. 7.2, scales are clamped to at least min_scale
+ * (> 0), densities and emissions to at least 0, rotations renormalised.
+ * Arrays are device memory, updated in place. */
 ugp_status ugp_fit_adam(ugp_ctx ctx, int64_t n, float *mean, float *scale, float *rotation, float *density,
-                        const float *grad, float *m, float *v, int32_t step, const float lr[4], float min_scale);
+                        float *emission, const float *grad, float *m, float *v, int32_t step, const float lr[5],
+                        float min_scale);
 
 /* Instrumentation: runs the ordered sweep of ugp_sample_collision (mode 0),
  * ugp_saturation (mode 1) or ugp_emitter_query (mode 2) and writes, per ray,

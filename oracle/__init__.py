@@ -68,6 +68,7 @@ def lib():
         L.orc_transmittance.argtypes = [vp, C.c_int64, vp, vp, C.c_int, vp, vp]
         L.orc_saturation.argtypes = [vp, C.c_int64, vp, vp, C.c_int, vp]
         L.orc_F_at.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_int, vp]
+        L.orc_rf_radiance.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_int, vp]
         L.orc_sample_collision.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_int, vp, vp, vp, vp, vp]
         L.orc_emitter_query.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_int, vp]
         L.orc_phase_eval.argtypes = [C.c_int, vp, C.c_double, vp, vp, vp, vp, vp]
@@ -217,6 +218,19 @@ class Scene:
         if tsat is None:
             tsat = self.saturation(rays, exclude, use_bvh)
         return self.F_at(rays, tsat, exclude, use_bvh), tsat
+
+    def rf_radiance(self, rays, exclude=None, tsat=None, use_bvh=None):
+        """Radiance-field mode (Sec. 8, eq. rf): per ray the sum of the
+        primitives' free-flight probabilities up to the saturating distance
+        times their emission.  `tsat` may be given (held fixed).  [n, 3]."""
+        r = _rays(rays)
+        n = r.shape[0]
+        e = _excl(exclude, n)
+        ts = None if tsat is None else np.ascontiguousarray(tsat, dtype=np.float64)
+        L = np.zeros((n, 3))
+        ub = self.use_bvh if use_bvh is None else int(use_bvh)
+        lib().orc_rf_radiance(self.h, n, _addr(r), _addr(e), _addr(ts), ub, _addr(L))
+        return L
 
     def sample_collision(self, rays, u, exclude=None, use_bvh=None):
         r = _rays(rays)

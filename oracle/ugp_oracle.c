@@ -549,6 +549,34 @@ void orc_saturation(const orc_scene *S, int64_t n, const float *rays, const int3
     free(H.v);
 }
 
+/* Radiance-field mode (Sec. 8, eq. rf): with emission and absorption only
+ * the radiance along a ray is the sum over the primitives it meets of their
+ * free-flight probability up to the saturating distance times their emission,
+ *   L = sum_k 1/2 I_k(a_k, min(b_k, t_sat)) L_e,k,
+ * with no Monte Carlo (u = 1 exhausts every contributing primitive).  t_sat
+ * as orc_saturation unless given (tsat may be NULL).  L_out [n][3]. */
+void orc_rf_radiance(const orc_scene *S, int64_t n, const float *rays, const int32_t *exclude,
+                     const double *tsat, int use_bvh, double *L_out) {
+    hitvec H = {0};
+    for (int64_t i = 0; i < n; ++i) {
+        const float *r = rays + 8 * i;
+        double o[3] = {r[0], r[1], r[2]}, w[3] = {r[3], r[4], r[5]};
+        gather(S, o, w, r[6], r[7], exclude ? exclude[i] : -1, use_bvh, &H);
+        double ts;
+        if (tsat) ts = tsat[i];
+        else ts = accumulated_F(S, &H) < 1.0 ? (double)r[7] : solve_tsat(S, &H, r[6]);
+        double L[3] = {0.0, 0.0, 0.0};
+        for (int64_t j = 0; j < H.n; ++j) {
+            const ohit *h = &H.v[j];
+            if (!(h->a < ts)) continue;
+            const double W = 0.5 * seg_integral(S, h, h->a, fmin(h->b, ts));
+            for (int c = 0; c < 3; ++c) L[c] += W * S->emis[3 * h->k + c];
+        }
+        for (int c = 0; c < 3; ++c) L_out[3 * i + c] = L[c];
+    }
+    free(H.v);
+}
+
 /* ------------------------------------------------------------------------- */
 /* Free-flight (primitive) sampling, Sec. 5.2.                                */
 /* The paper samples primitive k with probability equal to its share of the   */

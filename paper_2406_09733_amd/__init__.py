@@ -77,8 +77,8 @@ EXPORTS = ["ugp_create", "ugp_destroy", "ugp_set_stream", "ugp_build_bvh", "ugp_
            "ugp_sample_collision", "ugp_saturation", "ugp_emitter_query", "ugp_render", "ugp_sync",
            "ugp_set_profiling", "ugp_set_path_pool", "ugp_set_tail_paths", "ugp_get_render_stats", "ugp_trace_counts", "ugp_status_string",
            "ugp_nrc_num_params", "ugp_nrc_set_weights", "ugp_nrc_get_weights", "ugp_nrc_encode",
-           "ugp_nrc_forward", "ugp_nrc_train_step", "ugp_nrc_records", "ugp_accum_cdf", "ugp_camera_rays",
-           "ugp_fit_adam"]
+           "ugp_nrc_forward", "ugp_nrc_train_step", "ugp_nrc_records", "ugp_accum_cdf", "ugp_rf_render",
+           "ugp_camera_rays", "ugp_fit_adam"]
 
 
 def lib():
@@ -113,7 +113,9 @@ def lib():
         L.ugp_nrc_records.argtypes = [vp, i64, vp, vp, C.POINTER(C.c_int64)]
         L.ugp_accum_cdf.argtypes = [vp, vp, i64, vp, vp, vp, C.c_float, vp, vp, vp]
         L.ugp_camera_rays.argtypes = [vp, vp, C.c_uint64, i64, vp]
-        L.ugp_fit_adam.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, C.c_int32, C.POINTER(C.c_float), C.c_float]
+        L.ugp_rf_render.argtypes = [vp, vp, i64, vp, vp, vp, C.c_float, vp, vp, vp]
+        L.ugp_fit_adam.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int32, C.POINTER(C.c_float),
+                                   C.c_float]
         L.ugp_status_string.argtypes = [C.c_int]
         L.ugp_status_string.restype = C.c_char_p
         for name in EXPORTS:
@@ -270,6 +272,27 @@ class Context:
                                                     _ptr(C_out), _ptr(loss), _ptr(grad)))
         return C_out
 
+    def rf_render(self, rays, target=None, exclude=None, loss_scale: float = 1.0, want_L: bool = True,
+                  loss=None, grad=None):
+        """ugp_rf_render -> L (float32 [n, 3]) or None.  With target ([n, 3]),
+        adds loss_scale * sum |L - target|^2 into `loss` and its gradient into
+        `grad` (float32 [n_prims, 14]: mean, scale, rotation, density,
+        emission), each when given; the scene is the one of the last build_bvh."""
+        torch = self.torch
+        r = self._rays(rays)
+        n = r.shape[0]
+        e = self._excl(exclude, n)
+        tg = None if target is None else self._dev(target, torch.float32, (n, 3))
+        L_out = torch.empty((n, 3), device=self.device, dtype=torch.float32) if want_L else None
+        if grad is not None:
+            assert grad.dtype == torch.float32 and tuple(grad.shape) == (self.n, 14) and grad.is_contiguous()
+        if loss is not None:
+            assert loss.dtype == torch.float32 and loss.numel() >= 1
+        sp = C.byref(self._scene_s) if grad is not None else None
+        _check("ugp_rf_render", lib().ugp_rf_render(self.h, sp, n, _ptr(r), _ptr(e), _ptr(tg), float(loss_scale),
+                                                    _ptr(L_out), _ptr(loss), _ptr(grad)))
+        return L_out
+
     def camera_rays(self, cam: dict, seed: int = 0, sample: int = 0):
         """ugp_camera_rays -> float32 [height * width, 8] jittered pinhole rays."""
         c = _camera(cam)
@@ -277,17 +300,21 @@ class Context:
         _check("ugp_camera_rays", lib().ugp_camera_rays(self.h, C.byref(c), int(seed), int(sample), _ptr(rays)))
         return rays
 
-    def fit_adam(self, params: dict, grad, m, v, step: int, lr=(1e-4, 1e-2, 2e-5, 1e-4), min_scale: float = 1e-6):
+    def fit_adam(self, params: dict, grad, m, v, step: int, lr=(1e-4, 1e-2, 2e-5, 1e-4, 1e-2),
+                 min_scale: float = 1e-6, emission: bool = False):
         """ugp_fit_adam: one Adam step on params (device float32 tensors mean,
-        scale, rotation, density, updated in place); lr = rates of the means,
-        the log scales, the rotations and the densities; clamps and
-        renormalised rotations."""
+        scale, rotation, density, and with emission=True the emission; updated
+        in place); lr = rates of the means, the log scales, the rotations, the
+        densities (and the emissions); clamps and renormalised rotations."""
         n = params["mean"].shape[0]
-        for k in ("mean", "scale", "rotation", "density"):
+        keys = ("mean", "scale", "rotation", "density") + (("emission",) if emission else ())
+        for k in keys:
             assert params[k].is_contiguous() and params[k].dtype == self.torch.float32
-        rates = (C.c_float * 4)(*[float(x) for x in lr])
+        lr = list(lr) + [0.0] * (5 - len(lr))
+        rates = (C.c_float * 5)(*[float(x) for x in lr[:5]])
         _check("ugp_fit_adam", lib().ugp_fit_adam(self.h, n, _ptr(params["mean"]), _ptr(params["scale"]),
-                                                  _ptr(params["rotation"]), _ptr(params["density"]), _ptr(grad),
+                                                  _ptr(params["rotation"]), _ptr(params["density"]),
+                                                  _ptr(params["emission"]) if emission else None, _ptr(grad),
                                                   _ptr(m), _ptr(v), int(step), rates, float(min_scale)))
 
     # ---- path tracing -----------------------------------------------------

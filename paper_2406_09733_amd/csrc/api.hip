@@ -218,7 +218,19 @@ ugp_status ugp_accum_cdf(ugp_ctx ctx, const ugp_scene *scene, int64_t n, const f
     if (ctx->scene.n == 0) return UGP_ERR_NO_SCENE;
     if (n == 0) return UGP_OK;
     DeviceGuard g(ctx->device);
-    return from_hip(ugp::accum_cdf(ctx, scene, n, rays, exclude, target, loss_scale, C_out, loss_out, grad));
+    return from_hip(ugp::accum_cdf(ctx, scene, n, rays, exclude, target, loss_scale, false, C_out, loss_out, grad));
+}
+
+ugp_status ugp_rf_render(ugp_ctx ctx, const ugp_scene *scene, int64_t n, const float *rays, const int32_t *exclude,
+                         const float *target, float loss_scale, float *L_out, float *loss_out, float *grad) {
+    if (!query_args_ok(ctx, n, rays) || !std::isfinite(loss_scale)) return UGP_ERR_INVALID_ARGUMENT;
+    if ((loss_out || grad) && !target) return UGP_ERR_INVALID_ARGUMENT;
+    if (grad && (!scene || !scene->scale || !scene->rotation || scene->n != ctx->scene.n))
+        return UGP_ERR_INVALID_ARGUMENT;
+    if (ctx->scene.n == 0) return UGP_ERR_NO_SCENE;
+    if (n == 0) return UGP_OK;
+    DeviceGuard g(ctx->device);
+    return from_hip(ugp::accum_cdf(ctx, scene, n, rays, exclude, target, loss_scale, true, L_out, loss_out, grad));
 }
 
 ugp_status ugp_camera_rays(ugp_ctx ctx, const ugp_camera *cam, uint64_t seed, int64_t sample, float *rays) {
@@ -231,16 +243,17 @@ ugp_status ugp_camera_rays(ugp_ctx ctx, const ugp_camera *cam, uint64_t seed, in
 }
 
 ugp_status ugp_fit_adam(ugp_ctx ctx, int64_t n, float *mean, float *scale, float *rotation, float *density,
-                        const float *grad, float *m, float *v, int32_t step, const float lr[4], float min_scale) {
+                        float *emission, const float *grad, float *m, float *v, int32_t step, const float lr[5],
+                        float min_scale) {
     if (!ctx || n < 0 || step < 1 || !lr || !(min_scale > 0.f) || !std::isfinite(min_scale))
         return UGP_ERR_INVALID_ARGUMENT;
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < (emission ? 5 : 4); ++k)
         if (!(lr[k] >= 0.f) || !std::isfinite(lr[k])) return UGP_ERR_INVALID_ARGUMENT;
     if (n > 0 && (!mean || !scale || !rotation || !density || !grad || !m || !v)) return UGP_ERR_INVALID_ARGUMENT;
     if (n == 0) return UGP_OK;
     DeviceGuard g(ctx->device);
-    return from_hip(ugp::fit_adam(ctx, n, mean, scale, rotation, density, grad, m, v, step, lr, 0.9f, 0.999f, 1e-8f,
-                                  min_scale));
+    return from_hip(ugp::fit_adam(ctx, n, mean, scale, rotation, density, emission, grad, m, v, step, lr, 0.9f,
+                                  0.999f, 1e-8f, min_scale));
 }
 
 ugp_status ugp_sync(ugp_ctx ctx) {

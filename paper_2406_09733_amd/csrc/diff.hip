@@ -85,12 +85,19 @@ __device__ double w_and_grad(const HotRec &h, const RayD &r, double r2, double t
     return W;
 }
 
-// One lane per ray: C (forward), and with a target the loss
-// loss_scale * (C - target)^2 and its gradient with respect to (mu, M, d) of
-// every primitive the ray meets before t_sat, accumulated per original index.
+// One lane per ray.  RGB = false: C (eq. accum_cdf), and with a target the
+// loss loss_scale * (C - target)^2 and its gradient with respect to (mu, M, d)
+// of every primitive the ray meets before t_sat, accumulated per original
+// index (13 floats per primitive).  RGB = true, the radiance-field mode
+// (Sec. 8, eq. rf): L = sum_k W_k L_e,k with the emission of the scene, the
+// loss loss_scale * |L - target|^2 and its gradient with respect to
+// (mu, M, d, L_e) (16 floats per primitive): the shape terms are the same
+// derivative of W_k, weighted by dLoss/dL . L_e,k.
+template <bool RGB>
 __global__ __launch_bounds__(kBlock) void k_cdf(SceneDev S, int64_t n, const float *rays, const int32_t *excl,
                                                 const double *tsat, const float *target, float loss_scale,
-                                                float *C_out, float *loss, float *g13, uint32_t *err) {
+                                                float *out, float *loss, float *g, uint32_t *err) {
+    constexpr int kG = RGB ? 16 : 13;
     __shared__ int stack[kStackSize * kBlock];
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     float l2 = 0.f;
@@ -105,7 +112,7 @@ __global__ __launch_bounds__(kBlock) void k_cdf(SceneDev S, int64_t n, const flo
             const HotRec h = load_hot(S.hot, p);
             return h.orig != ex && !surely_missed(h, r, S.r2);
         };
-        float C = 0.f;
+        float acc[3] = {0.f, 0.f, 0.f};
         {
             TravState ts;
             trav_begin(ts, S);
@@ -113,16 +120,30 @@ __global__ __launch_bounds__(kBlock) void k_cdf(SceneDev S, int64_t n, const flo
                      pre, [&](int p) __attribute__((always_inline)) {
                          const HotRec h = load_hot(S.hot, p);
                          Chord c;
-                         if (chord(h, r, S.r2, c, true) && c.own) C += half_integral_to(c, tcl);
+                         if (!chord(h, r, S.r2, c, true) || !c.own) return false;
+                         const float w = half_integral_to(c, tcl);
+                         if (RGB) {
+                             const float4 e = S.cold[3 * (int64_t)h.orig + 2];
+                             acc[0] += w * e.x; acc[1] += w * e.y; acc[2] += w * e.z;
+                         } else {
+                             acc[0] += w;
+                         }
                          return false;
                      });
         }
-        if (C_out) C_out[i] = C;
+        constexpr int nc = RGB ? 3 : 1;
+        if (out)
+            for (int k = 0; k < nc; ++k) out[nc * i + k] = acc[k];
         if (target) {
-            const float diff = C - target[i];
-            l2 = loss_scale * diff * diff;
-            const double dC = 2.0 * (double)loss_scale * (double)diff;
-            if (g13 && dC != 0.0) {
+            double dL[3] = {0.0, 0.0, 0.0};
+            bool any = false;
+            for (int k = 0; k < nc; ++k) {
+                const float diff = acc[k] - target[nc * i + k];
+                l2 += loss_scale * diff * diff;
+                dL[k] = 2.0 * (double)loss_scale * (double)diff;
+                any = any || dL[k] != 0.0;
+            }
+            if (g && any) {
                 TravState ts;
                 trav_begin(ts, S);
                 traverse(S, r, r.t0, [&]() __attribute__((always_inline)) { return hi; }, stack, spill, ts, 0, err,
@@ -131,10 +152,18 @@ __global__ __launch_bounds__(kBlock) void k_cdf(SceneDev S, int64_t n, const flo
                              Chord c;
                              if (!chord(h, r, S.r2, c, true) || !c.own) return false;
                              double gk[13];
-                             w_and_grad(h, r, (double)S.r2, tcl, gk);
-                             float *dst = g13 + 13 * (int64_t)h.orig;
-                             for (int k = 0; k < 13; ++k)
-                                 if (gk[k] != 0.0) atomicAdd(dst + k, (float)(dC * gk[k]));
+                             const double W = w_and_grad(h, r, (double)S.r2, tcl, gk);
+                             float *dst = g + kG * (int64_t)h.orig;
+                             double wt = dL[0];
+                             if (RGB) {
+                                 const float4 e = S.cold[3 * (int64_t)h.orig + 2];
+                                 wt = dL[0] * e.x + dL[1] * e.y + dL[2] * e.z;
+                                 for (int k = 0; k < 3; ++k)
+                                     if (W != 0.0 && dL[k] != 0.0) atomicAdd(dst + 13 + k, (float)(dL[k] * W));
+                             }
+                             if (wt != 0.0)
+                                 for (int k = 0; k < 13; ++k)
+                                     if (gk[k] != 0.0) atomicAdd(dst + k, (float)(wt * gk[k]));
                              return false;
                          });
             }
@@ -148,11 +177,14 @@ __global__ __launch_bounds__(kBlock) void k_cdf(SceneDev S, int64_t n, const flo
 
 // Chain rule from (mu, M, d) to the primitive parameters (mu, s, q, d): with
 // the rotation of the unit quaternion q / |q| (the normalisation included),
-// M = S^-1 R^T, M_ij = R_ji / s_i.  grad [n][11] = (mu, s, q, d) is added to.
-__global__ void k_cdf_chain(int64_t n, const float *scale, const float *rot, const float *g13, float *grad) {
+// M = S^-1 R^T, M_ij = R_ji / s_i.  grad [n][11] = (mu, s, q, d) is added to;
+// with emission gradients (gin rows of 16) grad rows are 14, the last three
+// the emission's.
+__global__ void k_cdf_chain(int64_t n, const float *scale, const float *rot, const float *gin, bool rgb,
+                            float *grad) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    const float *g = g13 + 13 * k;
+    const float *g = gin + (rgb ? 16 : 13) * k;
     const double qw = rot[4 * k], qx = rot[4 * k + 1], qy = rot[4 * k + 2], qz = rot[4 * k + 3];
     const double nq = qw * qw + qx * qx + qy * qy + qz * qz;
     const double t = 2.0 / nq;
@@ -187,11 +219,14 @@ __global__ void k_cdf_chain(int64_t n, const float *scale, const float *rot, con
             for (int j = 0; j < 3; ++j) acc += gR[i][j] * t * (dQ[a][i][j] - 2.0 * qa[a] * Q[i][j] / nq);
         gq[a] = acc;
     }
-    float *o = grad + 11 * k;
+    float *o = grad + (rgb ? 14 : 11) * k;
     o[0] += g[0]; o[1] += g[1]; o[2] += g[2];
     o[3] += (float)gs[0]; o[4] += (float)gs[1]; o[5] += (float)gs[2];
     o[6] += (float)gq[0]; o[7] += (float)gq[1]; o[8] += (float)gq[2]; o[9] += (float)gq[3];
     o[10] += g[12];
+    if (rgb) {
+        o[11] += g[13]; o[12] += g[14]; o[13] += g[15];
+    }
 }
 
 // Jittered pinhole rays, one per pixel: jitter from the counter-based
@@ -215,18 +250,23 @@ __global__ void k_camera_rays(CamDev cam, uint64_t seed, uint32_t sample, float 
 // steps (rates lr_mean, lr_rot, lr_dens); scales take them on log s (the
 // moments are of s dL/ds, the update multiplies s by exp(-step)), so a rate
 // is relative to each primitive's own extent -- thin axes are orders of
-// magnitude below the others.  Then, as in Sec. 7.2, scales are clamped to at
-// least s_min, densities to at least 0, rotations renormalised.
-__global__ void k_fit_adam(int64_t n, float *mean, float *scale, float *rot, float *dens, const float *grad,
-                           float *m, float *v, int t, float lr_mean, float lr_log_scale, float lr_rot,
-                           float lr_dens, float b1, float b2, float eps, float s_min) {
+// magnitude below the others.  With emission (rows of 14: the radiance-field
+// mode) the emissions take plain steps at lr_emis.  Then, as in Sec. 7.2,
+// scales are clamped to at least s_min, densities and emissions to at least
+// 0, rotations renormalised.
+__global__ void k_fit_adam(int64_t n, float *mean, float *scale, float *rot, float *dens, float *emis,
+                           const float *grad, float *m, float *v, int t, float lr_mean, float lr_log_scale,
+                           float lr_rot, float lr_dens, float lr_emis, float b1, float b2, float eps, float s_min) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    float *prm[11] = {mean + 3 * k, mean + 3 * k + 1, mean + 3 * k + 2, scale + 3 * k, scale + 3 * k + 1,
-                      scale + 3 * k + 2, rot + 4 * k, rot + 4 * k + 1, rot + 4 * k + 2, rot + 4 * k + 3, dens + k};
+    const int np = emis ? 14 : 11;
+    float *prm[14] = {mean + 3 * k, mean + 3 * k + 1, mean + 3 * k + 2, scale + 3 * k, scale + 3 * k + 1,
+                      scale + 3 * k + 2, rot + 4 * k, rot + 4 * k + 1, rot + 4 * k + 2, rot + 4 * k + 3, dens + k,
+                      emis ? emis + 3 * k : nullptr, emis ? emis + 3 * k + 1 : nullptr,
+                      emis ? emis + 3 * k + 2 : nullptr};
     const double c1 = 1.0 - pow((double)b1, t), c2 = 1.0 - pow((double)b2, t);
-    for (int j = 0; j < 11; ++j) {
-        const int64_t e = 11 * k + j;
+    for (int j = 0; j < np; ++j) {
+        const int64_t e = np * k + j;
         const bool is_scale = j >= 3 && j < 6;
         const float g = is_scale ? grad[e] * *prm[j] : grad[e];
         const float mj = b1 * m[e] + (1.f - b1) * g;
@@ -237,12 +277,14 @@ __global__ void k_fit_adam(int64_t n, float *mean, float *scale, float *rot, flo
         if (is_scale) {
             *prm[j] = (float)((double)*prm[j] * exp(-(double)lr_log_scale * step));
         } else {
-            const float rate = j < 3 ? lr_mean : (j < 10 ? lr_rot : lr_dens);
+            const float rate = j < 3 ? lr_mean : (j < 10 ? lr_rot : (j == 10 ? lr_dens : lr_emis));
             *prm[j] -= (float)(rate * step);
         }
     }
     for (int j = 0; j < 3; ++j) scale[3 * k + j] = fmaxf(scale[3 * k + j], s_min);
     dens[k] = fmaxf(dens[k], 0.f);
+    if (emis)
+        for (int j = 0; j < 3; ++j) emis[3 * k + j] = fmaxf(emis[3 * k + j], 0.f);
     const float qn = sqrtf(rot[4 * k] * rot[4 * k] + rot[4 * k + 1] * rot[4 * k + 1] +
                            rot[4 * k + 2] * rot[4 * k + 2] + rot[4 * k + 3] * rot[4 * k + 3]);
     if (qn > 0.f)
@@ -254,32 +296,37 @@ __global__ void k_fit_adam(int64_t n, float *mean, float *scale, float *rot, flo
 }  // namespace
 
 hipError_t accum_cdf(ugp_ctx ctx, const ugp_scene *scene, int64_t n, const float *rays, const int32_t *excl,
-                     const float *target, float loss_scale, float *C_out, float *loss, float *grad) {
+                     const float *target, float loss_scale, bool rgb, float *out, float *loss, float *grad) {
     hipStream_t st = ctx->stream;
     const SceneDev &S = ctx->scene;
+    const int kg = rgb ? 16 : 13;
     double *tsat = nullptr;
-    float *g13 = nullptr;
+    float *gtmp = nullptr;
     hipError_t e = hipMallocAsync((void **)&tsat, sizeof(double) * (size_t)n, st);
     if (e != hipSuccess) return e;
     if (grad) {
-        e = hipMallocAsync((void **)&g13, sizeof(float) * 13 * (size_t)S.n, st);
-        if (e == hipSuccess) e = hipMemsetAsync(g13, 0, sizeof(float) * 13 * (size_t)S.n, st);
+        e = hipMallocAsync((void **)&gtmp, sizeof(float) * kg * (size_t)S.n, st);
+        if (e == hipSuccess) e = hipMemsetAsync(gtmp, 0, sizeof(float) * kg * (size_t)S.n, st);
     }
     if (e == hipSuccess)
         e = launch_sweep(ctx, kModeSaturate, n, rays, excl, nullptr, nullptr, nullptr, nullptr, nullptr, tsat);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_cdf, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, S, n, rays,
-                           excl, (const double *)tsat, target, loss_scale, C_out, target ? loss : nullptr,
-                           target ? g13 : nullptr, ctx->err);
+        const dim3 grid((unsigned)((n + kBlock - 1) / kBlock));
+        if (rgb)
+            hipLaunchKernelGGL(k_cdf<true>, grid, dim3(kBlock), 0, st, S, n, rays, excl, (const double *)tsat, target,
+                               loss_scale, out, target ? loss : nullptr, target ? gtmp : nullptr, ctx->err);
+        else
+            hipLaunchKernelGGL(k_cdf<false>, grid, dim3(kBlock), 0, st, S, n, rays, excl, (const double *)tsat,
+                               target, loss_scale, out, target ? loss : nullptr, target ? gtmp : nullptr, ctx->err);
         e = hipGetLastError();
     }
     if (e == hipSuccess && grad && target) {
         hipLaunchKernelGGL(k_cdf_chain, dim3((unsigned)((S.n + 255) / 256)), dim3(256), 0, st, S.n, scene->scale,
-                           scene->rotation, (const float *)g13, grad);
+                           scene->rotation, (const float *)gtmp, rgb, grad);
         e = hipGetLastError();
     }
     hipFreeAsync(tsat, st);
-    if (g13) hipFreeAsync(g13, st);
+    if (gtmp) hipFreeAsync(gtmp, st);
     return e;
 }
 
@@ -292,10 +339,12 @@ hipError_t camera_rays(ugp_ctx ctx, const ugp_camera *cam, uint64_t seed, uint32
     return hipGetLastError();
 }
 
-hipError_t fit_adam(ugp_ctx ctx, int64_t n, float *mean, float *scale, float *rot, float *dens, const float *grad,
-                    float *m, float *v, int t, const float lr[4], float b1, float b2, float eps, float s_min) {
+hipError_t fit_adam(ugp_ctx ctx, int64_t n, float *mean, float *scale, float *rot, float *dens, float *emis,
+                    const float *grad, float *m, float *v, int t, const float lr[5], float b1, float b2, float eps,
+                    float s_min) {
     hipLaunchKernelGGL(k_fit_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, n, mean, scale,
-                       rot, dens, grad, m, v, t, lr[0], lr[1], lr[2], lr[3], b1, b2, eps, s_min);
+                       rot, dens, emis, grad, m, v, t, lr[0], lr[1], lr[2], lr[3], emis ? lr[4] : 0.f, b1, b2, eps,
+                       s_min);
     return hipGetLastError();
 }
 

@@ -62,3 +62,45 @@ def fit_transmittance(ctx, params: dict, cams: list, target, iters: int, lr=(1e-
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return {"loss": [float(x.item()) for x in losses], "seconds": wall}
+
+
+def reference_rf_images(ctx, scene: dict, cams: list, seed: int = 0, samples: int = 16):
+    """Radiance-field images (Sec. 8, eq. rf) of `scene`, per pixel of every
+    view [sum of pixels, 3], averaged over `samples` jittered rays."""
+    ctx.build_bvh(scene)
+    acc = None
+    for s in range(samples):
+        L = ctx.rf_render(view_rays(ctx, cams, seed, s))
+        acc = L if acc is None else acc + L
+    return acc / samples
+
+
+def fit_radiance_field(ctx, params: dict, cams: list, target, iters: int, lr=(1e-4, 1e-2, 2e-5, 1e-4, 1e-2),
+                       min_scale: float = 1e-6, seed: int = 1, on_step=None) -> dict:
+    """Image-based radiance-field reconstruction (Sec. 8): Adam on the mean
+    over the views' pixels of |L - target|^2 with L of eq. rf, one jittered
+    ray per pixel per step, every parameter of every primitive including its
+    emission; lr = rates of the means, log scales, rotations, densities and
+    emissions.  params as fit_transmittance (emission updated too)."""
+    import torch
+    n = params["mean"].shape[0]
+    dev = params["mean"].device
+    m = torch.zeros((n, 14), device=dev, dtype=torch.float32)
+    v = torch.zeros_like(m)
+    grad = torch.zeros_like(m)
+    npix = sum(c["width"] * c["height"] for c in cams)
+    losses = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(1, iters + 1):
+        ctx.build_bvh(params)
+        grad.zero_()
+        loss = torch.zeros(1, device=dev, dtype=torch.float32)
+        ctx.rf_render(view_rays(ctx, cams, seed, it), target=target, want_L=False, loss_scale=1.0 / npix,
+                      loss=loss, grad=grad)
+        ctx.fit_adam(params, grad, m, v, it, lr=lr, min_scale=min_scale, emission=True)
+        losses.append(loss)
+        if on_step is not None:
+            on_step(it)
+    torch.cuda.synchronize()
+    return {"loss": [float(x.item()) for x in losses], "seconds": time.perf_counter() - t0}

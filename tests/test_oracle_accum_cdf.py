@@ -37,3 +37,24 @@ def test_accum_cdf_with_fixed_tsat_is_F_at_that_point(orc, tiny_scene):
     C2, _ = S.accum_cdf(rays, tsat=np.where(sat, ts * 0.999, ts))
     assert np.all(C2[sat] <= C[sat] + 1e-12)
     assert np.all(C2[sat] < 1.0)
+
+
+def test_rf_radiance_reduces_to_the_cdf_and_is_linear_in_emission(orc, tiny_scene):
+    # eq. rf: with one emission e for every primitive L = e C; and L is linear
+    # in the emissions (the clip point t_sat does not depend on them)
+    sc = _dense(tiny_scene)
+    n = sc["mean"].shape[0]
+    rays = scenes.probe_rays(tiny_scene, 300, seed=33)
+    rng = np.random.default_rng(4)
+    e1 = rng.uniform(0, 2, (n, 3)).astype(np.float32)
+    e2 = rng.uniform(0, 2, (n, 3)).astype(np.float32)
+    C, ts = orc.Scene(sc).accum_cdf(rays)
+    L = {}
+    for name, em in (("u", np.full((n, 3), 1.5, np.float32)), ("1", e1), ("2", e2), ("12", e1 + e2)):
+        d = dict(sc)
+        d["emission"] = em
+        L[name] = orc.Scene(d).rf_radiance(rays)
+    assert np.allclose(L["u"], 1.5 * C[:, None], rtol=0, atol=1e-12)
+    # (e1 + e2 is rounded to float32 like every scene input)
+    assert np.allclose(L["12"], L["1"] + L["2"], rtol=1e-6, atol=1e-9)
+    assert (L["1"] > 0).any()
