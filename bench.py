@@ -339,6 +339,39 @@ def transmittance_fit(args):
     print(json.dumps(res), flush=True)
 
 
+def rf_render_bench(args):
+    """Radiance-field rendering (Sec. 8, eq. rf) at the resolution of the
+    paper's timings (800x800, one ray per pixel) on a synthetic scene of
+    300K primitives (the mixed generator at 3x: flat Gaussians on spheres and
+    planes plus a cloud; every primitive emissive).  Prints one JSON line: ms
+    per frame and rays/s (the saturation sweep and the emission-weighted sum)."""
+    import numpy as np
+    import torch
+
+    import paper_2406_09733_amd as P
+    from paper_2406_09733_amd import fit, scenes
+
+    sc = scenes.mixed_100k(n_flat=210_000, n_cloud=90_000, n_emit=0)
+    rng = np.random.default_rng(5)
+    sc["emission"] = rng.uniform(0.0, 1.0, (sc["mean"].shape[0], 3)).astype(np.float32)
+    cams = scenes.ring_cameras((0.5, 0.5, 0.5), 2.2, n=8, size=800)
+    ctx = P.Context(0)
+    ctx.build_bvh(sc)
+    rays = [fit.view_rays(ctx, [c], 1, 0) for c in cams]
+    for r in rays[:2]:
+        ctx.rf_render(r)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.rf_frames):
+        ctx.rf_render(rays[k % len(rays)])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.rf_frames
+    res = {"metric": "radiance-field render ms per 800x800 frame (Sec. 8, eq. rf)", "value": round(1e3 * dt, 3),
+           "unit": "ms", "higher_is_better": False, "primitives": int(sc["mean"].shape[0]),
+           "resolution": "800x800", "frames": args.rf_frames, "rays_per_s": round(800 * 800 / dt, 1)}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -366,6 +399,8 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device copy of BYTES (counter calibration) and exit")
     ap.add_argument("--fit", action="store_true", help="run the transmittance-optimisation benchmark instead")
+    ap.add_argument("--rf", action="store_true", help="run the radiance-field rendering benchmark instead")
+    ap.add_argument("--rf-frames", type=int, default=40)
     ap.add_argument("--fit-steps", type=int, default=50)
     ap.add_argument("--fit-lr", default="5e-5,1e-2,2e-3,1e-2",
                     help="Adam rates of the means, log scales, rotations and densities")
@@ -385,6 +420,9 @@ def main():
         return
     if args.fit:
         transmittance_fit(args)
+        return
+    if args.rf:
+        rf_render_bench(args)
         return
 
     import numpy as np
