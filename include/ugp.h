@@ -184,6 +184,26 @@ ugp_status ugp_saturation(ugp_ctx ctx, int64_t n_rays, const float *rays,
 ugp_status ugp_emitter_query(ugp_ctx ctx, int64_t n_rays, const float *rays,
                              const int32_t *exclude, const int32_t *target, float *out);
 
+/* ---- Exponential variant (App. D; eq. exp_ff) ----------------------------
+ * The same Gaussians read as a heterogeneous exponential medium, sigma_t =
+ * sum_k G_k (the comparison variant of the paper's linear-vs-exponential
+ * study).  Rays and exclude as the queries above.
+ *
+ * Transmittance exp(-sum_k I_k(a_k, b_k)) over the clipped chords (the full
+ * ray integrals).  T_out float [n]. */
+ugp_status ugp_exp_transmittance(ugp_ctx ctx, int64_t n_rays, const float *rays, const int32_t *exclude,
+                                 float *T_out);
+
+/* Free-flight sampling by analog decomposition tracking (App. D): every
+ * Gaussian k the ray meets draws u_k -- Philox4x32-10, counter (ray index
+ * low, ray index high, k, 0), key (seed low, seed high), the top 24 bits of
+ * the first word over 2^24 -- and would collide where its optical depth from
+ * the chord entry reaches -ln(1 - u_k), if that happens before the chord
+ * exit; the ray collides at the nearest such point.  prim_out int32 [n]
+ * (original index, -1 = escape), t_out float [n] (NaN on escape). */
+ugp_status ugp_exp_sample_collision(ugp_ctx ctx, int64_t n_rays, const float *rays, const int32_t *exclude,
+                                    uint64_t seed, int32_t *prim_out, float *t_out);
+
 /* ---- Differentiation: the transmittance optimisation of Sec. 7.2 ---------
  *
  * Accumulated free-flight CDF of each ray (Sec. 7.2, eq. accum_cdf):

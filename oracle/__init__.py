@@ -69,6 +69,8 @@ def lib():
         L.orc_saturation.argtypes = [vp, C.c_int64, vp, vp, C.c_int, vp]
         L.orc_F_at.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_int, vp]
         L.orc_rf_radiance.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_int, vp]
+        L.orc_exp_transmittance.argtypes = [vp, C.c_int64, vp, vp, C.c_int, vp]
+        L.orc_exp_sample.argtypes = [vp, C.c_int64, vp, vp, C.c_uint64, C.c_int, vp, vp, vp]
         L.orc_sample_collision.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_int, vp, vp, vp, vp, vp]
         L.orc_emitter_query.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_int, vp]
         L.orc_phase_eval.argtypes = [C.c_int, vp, C.c_double, vp, vp, vp, vp, vp]
@@ -231,6 +233,29 @@ class Scene:
         ub = self.use_bvh if use_bvh is None else int(use_bvh)
         lib().orc_rf_radiance(self.h, n, _addr(r), _addr(e), _addr(ts), ub, _addr(L))
         return L
+
+    def exp_transmittance(self, rays, exclude=None, use_bvh=None):
+        """Exponential variant (App. D, eq. exp_ff): T = exp(-sum_k I_k)."""
+        r = _rays(rays)
+        n = r.shape[0]
+        e = _excl(exclude, n)
+        T = np.zeros(n)
+        ub = self.use_bvh if use_bvh is None else int(use_bvh)
+        lib().orc_exp_transmittance(self.h, n, _addr(r), _addr(e), ub, _addr(T))
+        return T
+
+    def exp_sample(self, rays, seed: int, exclude=None, use_bvh=None):
+        """Analog decomposition tracking of the exponential variant (App. D):
+        (prim or -1, t or NaN, margin) per ray."""
+        r = _rays(rays)
+        n = r.shape[0]
+        e = _excl(exclude, n)
+        prim = np.zeros(n, np.int32)
+        t = np.zeros(n)
+        margin = np.zeros(n)
+        ub = self.use_bvh if use_bvh is None else int(use_bvh)
+        lib().orc_exp_sample(self.h, n, _addr(r), _addr(e), int(seed), ub, _addr(prim), _addr(t), _addr(margin))
+        return prim, t, margin
 
     def sample_collision(self, rays, u, exclude=None, use_bvh=None):
         r = _rays(rays)

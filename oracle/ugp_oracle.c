@@ -577,6 +577,80 @@ void orc_rf_radiance(const orc_scene *S, int64_t n, const float *rays, const int
     free(H.v);
 }
 
+/* Exponential variant (App. D; eq. exp_ff): the same Gaussians as a
+ * heterogeneous exponential medium, sigma_t = sum_k G_k, so the optical depth
+ * of a ray is sum_k I_k over the clipped chords and T = exp(-depth). */
+void orc_exp_transmittance(const orc_scene *S, int64_t n, const float *rays, const int32_t *exclude,
+                           int use_bvh, double *T_out) {
+    hitvec H = {0};
+    for (int64_t i = 0; i < n; ++i) {
+        const float *r = rays + 8 * i;
+        double o[3] = {r[0], r[1], r[2]}, w[3] = {r[3], r[4], r[5]};
+        gather(S, o, w, r[6], r[7], exclude ? exclude[i] : -1, use_bvh, &H);
+        double depth = 0.0;
+        for (int64_t j = 0; j < H.n; ++j) depth += seg_integral(S, &H.v[j], H.v[j].a, H.v[j].b);
+        T_out[i] = exp(-depth);
+    }
+    free(H.v);
+}
+
+/* The uniform of primitive k on ray i for analog decomposition tracking:
+ * Philox4x32-10 with counter (i low, i high, k, 0) and key (seed low, seed
+ * high); the top 24 bits of the first word. */
+static double exp_uniform(uint64_t seed, int64_t i, int64_t k) {
+    const uint32_t ctr[4] = {(uint32_t)i, (uint32_t)((uint64_t)i >> 32), (uint32_t)k, 0u};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t x[4];
+    orc_philox4x32_10(ctr, key, x);
+    return (double)(x[0] >> 8) * (1.0 / 16777216.0);
+}
+
+/* Free-flight sampling of the exponential variant by analog decomposition
+ * tracking (App. D, after Kutz et al. 2017): every Gaussian the ray meets
+ * draws its own exponential free flight y_k = -ln(1 - u_k); it collides where
+ * its optical depth from the chord entry reaches y_k, t_k = I_k^-1(y_k; a_k),
+ * if y_k is below its whole chord's depth; the ray collides at the nearest
+ * t_k, else escapes (prim -1, t NaN).  The inversion here is a bisection on
+ * the monotone I_k(a_k, t).  margin: the smallest of |y_k - I_k(a_k, b_k)| / y_k
+ * and, when two collide, the relative gap of the two nearest t_k. */
+void orc_exp_sample(const orc_scene *S, int64_t n, const float *rays, const int32_t *exclude, uint64_t seed,
+                    int use_bvh, int32_t *prim_out, double *t_out, double *margin_out) {
+    hitvec H = {0};
+    for (int64_t i = 0; i < n; ++i) {
+        const float *r = rays + 8 * i;
+        double o[3] = {r[0], r[1], r[2]}, w[3] = {r[3], r[4], r[5]};
+        gather(S, o, w, r[6], r[7], exclude ? exclude[i] : -1, use_bvh, &H);
+        double best = INFINITY, second = INFINITY, margin = INFINITY;
+        int64_t bk = -1;
+        for (int64_t j = 0; j < H.n; ++j) {
+            const ohit *h = &H.v[j];
+            const double y = -log1p(-exp_uniform(seed, i, h->k));
+            const double total = seg_integral(S, h, h->a, h->b);
+            margin = fmin(margin, fabs(y - total) / fmax(y, 1e-30));
+            if (!(y < total)) continue;
+            double lo = h->a, hi = h->b;
+            for (int it = 0; it < 200 && hi - lo > 1e-15 * fmax(1.0, fabs(hi)); ++it) {
+                const double mid = 0.5 * (lo + hi);
+                if (seg_integral(S, h, h->a, mid) < y) lo = mid;
+                else hi = mid;
+            }
+            const double t = 0.5 * (lo + hi);
+            if (t < best) {
+                second = best;
+                best = t;
+                bk = h->k;
+            } else if (t < second) {
+                second = t;
+            }
+        }
+        if (second < INFINITY) margin = fmin(margin, (second - best) / fmax(fabs(best), 1e-30));
+        prim_out[i] = (int32_t)bk;
+        t_out[i] = bk >= 0 ? best : NAN;
+        if (margin_out) margin_out[i] = margin;
+    }
+    free(H.v);
+}
+
 /* ------------------------------------------------------------------------- */
 /* Free-flight (primitive) sampling, Sec. 5.2.                                */
 /* The paper samples primitive k with probability equal to its share of the   */

@@ -62,6 +62,10 @@ void orc_saturation(const orc_scene *S, int64_t n, const float *rays, const int3
                     int use_bvh, double *tsat_out);
 void orc_rf_radiance(const orc_scene *S, int64_t n, const float *rays, const int32_t *exclude,
                      const double *tsat, int use_bvh, double *L_out);
+void orc_exp_transmittance(const orc_scene *S, int64_t n, const float *rays, const int32_t *exclude,
+                           int use_bvh, double *T_out);
+void orc_exp_sample(const orc_scene *S, int64_t n, const float *rays, const int32_t *exclude, uint64_t seed,
+                    int use_bvh, int32_t *prim_out, double *t_out, double *margin_out);
 void orc_sample_collision(const orc_scene *S, int64_t n, const float *rays, const int32_t *exclude,
                           const double *u, int use_bvh, int32_t *prim_out, double *t_out,
                           double *F_out, double *tsat_out, double *margin_out);

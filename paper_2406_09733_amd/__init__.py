@@ -77,7 +77,8 @@ EXPORTS = ["ugp_create", "ugp_destroy", "ugp_set_stream", "ugp_build_bvh", "ugp_
            "ugp_sample_collision", "ugp_saturation", "ugp_emitter_query", "ugp_render", "ugp_sync",
            "ugp_set_profiling", "ugp_set_path_pool", "ugp_set_tail_paths", "ugp_get_render_stats", "ugp_trace_counts", "ugp_status_string",
            "ugp_nrc_num_params", "ugp_nrc_set_weights", "ugp_nrc_get_weights", "ugp_nrc_encode",
-           "ugp_nrc_forward", "ugp_nrc_train_step", "ugp_nrc_records", "ugp_accum_cdf", "ugp_rf_render",
+           "ugp_nrc_forward", "ugp_nrc_train_step", "ugp_nrc_records", "ugp_exp_transmittance",
+           "ugp_exp_sample_collision", "ugp_accum_cdf", "ugp_rf_render",
            "ugp_camera_rays", "ugp_fit_adam"]
 
 
@@ -114,6 +115,8 @@ def lib():
         L.ugp_accum_cdf.argtypes = [vp, vp, i64, vp, vp, vp, C.c_float, vp, vp, vp]
         L.ugp_camera_rays.argtypes = [vp, vp, C.c_uint64, i64, vp]
         L.ugp_rf_render.argtypes = [vp, vp, i64, vp, vp, vp, C.c_float, vp, vp, vp]
+        L.ugp_exp_transmittance.argtypes = [vp, i64, vp, vp, vp]
+        L.ugp_exp_sample_collision.argtypes = [vp, i64, vp, vp, C.c_uint64, vp, vp]
         L.ugp_fit_adam.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int32, C.POINTER(C.c_float),
                                    C.c_float]
         L.ugp_status_string.argtypes = [C.c_int]
@@ -249,6 +252,27 @@ class Context:
         _check("ugp_trace_counts", lib().ugp_trace_counts(self.h, int(mode), n, _ptr(r), _ptr(e), _ptr(uu),
                                                           _ptr(tg), _ptr(out)))
         return out
+
+    # ---- exponential variant ----------------------------------------------
+    def exp_transmittance(self, rays, exclude=None):
+        """ugp_exp_transmittance -> T = exp(-sum_k I_k) float32 [n]."""
+        r = self._rays(rays)
+        n = r.shape[0]
+        e = self._excl(exclude, n)
+        T = self.torch.empty(n, device=self.device, dtype=self.torch.float32)
+        _check("ugp_exp_transmittance", lib().ugp_exp_transmittance(self.h, n, _ptr(r), _ptr(e), _ptr(T)))
+        return T
+
+    def exp_sample_collision(self, rays, seed: int, exclude=None):
+        """ugp_exp_sample_collision -> (prim int32, t float32) by analog decomposition tracking."""
+        r = self._rays(rays)
+        n = r.shape[0]
+        e = self._excl(exclude, n)
+        prim = self.torch.empty(n, device=self.device, dtype=self.torch.int32)
+        t = self.torch.empty(n, device=self.device, dtype=self.torch.float32)
+        _check("ugp_exp_sample_collision",
+               lib().ugp_exp_sample_collision(self.h, n, _ptr(r), _ptr(e), int(seed), _ptr(prim), _ptr(t)))
+        return prim, t
 
     # ---- differentiation (transmittance optimisation) ---------------------
     def accum_cdf(self, rays, target=None, exclude=None, loss_scale: float = 1.0, want_C: bool = True,

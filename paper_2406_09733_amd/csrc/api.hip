@@ -208,6 +208,23 @@ ugp_status ugp_render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_param
     return from_hip(ugp::render(ctx, cam, p, sum, sumsq));
 }
 
+ugp_status ugp_exp_transmittance(ugp_ctx ctx, int64_t n, const float *rays, const int32_t *exclude, float *T_out) {
+    if (!query_args_ok(ctx, n, rays) || (n > 0 && !T_out)) return UGP_ERR_INVALID_ARGUMENT;
+    if (ctx->scene.n == 0) return UGP_ERR_NO_SCENE;
+    if (n == 0) return UGP_OK;
+    DeviceGuard g(ctx->device);
+    return from_hip(ugp::launch_exp(ctx, n, rays, exclude, false, 0, T_out, nullptr, nullptr));
+}
+
+ugp_status ugp_exp_sample_collision(ugp_ctx ctx, int64_t n, const float *rays, const int32_t *exclude,
+                                    uint64_t seed, int32_t *prim_out, float *t_out) {
+    if (!query_args_ok(ctx, n, rays) || (n > 0 && (!prim_out || !t_out))) return UGP_ERR_INVALID_ARGUMENT;
+    if (ctx->scene.n == 0) return UGP_ERR_NO_SCENE;
+    if (n == 0) return UGP_OK;
+    DeviceGuard g(ctx->device);
+    return from_hip(ugp::launch_exp(ctx, n, rays, exclude, true, seed, nullptr, prim_out, t_out));
+}
+
 ugp_status ugp_accum_cdf(ugp_ctx ctx, const ugp_scene *scene, int64_t n, const float *rays,
                          const int32_t *exclude, const float *target, float loss_scale, float *C_out,
                          float *loss_out, float *grad) {

@@ -104,6 +104,10 @@ hipError_t launch_sweep(ugp_ctx ctx, int mode, int64_t n, const float *rays, con
                         const float *u, const int32_t *target, int32_t *prim_out, float *f_out,
                         int32_t *counts = nullptr, double *td_out = nullptr);
 
+// exponential variant: T = exp(-sum I_k) (sample = false) or decomposition-tracking samples
+hipError_t launch_exp(ugp_ctx ctx, int64_t n, const float *rays, const int32_t *excl, bool sample, uint64_t seed,
+                      float *T, int32_t *prim_out, float *t_out);
+
 // render.hip
 hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p, float *sum,
                   float *sumsq);
