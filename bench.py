@@ -372,6 +372,47 @@ def rf_render_bench(args):
     print(json.dumps(res), flush=True)
 
 
+def query_bench(args):
+    """Per-ray query rates on the room (5.5M primitives): linear-model
+    transmittance and free-flight sampling (the ordered sweep) against the
+    exponential variant's transmittance and analog decomposition tracking
+    (App. D), on the same 4M rays (origins in the room, directions uniform,
+    t in [0, inf)).  Prints one JSON line of Mrays/s per query."""
+    import numpy as np
+    import torch
+
+    import paper_2406_09733_amd as P
+    from paper_2406_09733_amd import scenes
+
+    sc = scenes.room_5p5m()
+    ctx = P.Context(0)
+    ctx.build_bvh(sc)
+    n = 1 << 22
+    rng = np.random.default_rng(17)
+    o = rng.uniform([0.5, 0.2, 0.5], [7.5, 2.8, 7.5], (n, 3))
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    rays = torch.tensor(np.concatenate([o, d, np.zeros((n, 1)), np.full((n, 1), np.inf)], 1).astype(np.float32),
+                        device="cuda")
+    u = torch.tensor(rng.uniform(0, 1, n).astype(np.float32), device="cuda")
+    runs = {"linear_transmittance": lambda: ctx.transmittance(rays),
+            "linear_sample_collision": lambda: ctx.sample_collision(rays, u),
+            "linear_saturation": lambda: ctx.saturation(rays),
+            "exp_transmittance": lambda: ctx.exp_transmittance(rays),
+            "exp_sample_collision": lambda: ctx.exp_sample_collision(rays, 5)}
+    res = {"metric": "per-ray query Mrays/s on the room, 4M rays", "unit": "Mrays/s", "rays": n}
+    for name, fn in runs.items():
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = round(3 * n / (time.perf_counter() - t0) / 1e6, 2)
+        log(f"[queries] {name}: {res[name]} Mrays/s")
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -400,6 +441,7 @@ def main():
                     help="only run a device copy of BYTES (counter calibration) and exit")
     ap.add_argument("--fit", action="store_true", help="run the transmittance-optimisation benchmark instead")
     ap.add_argument("--rf", action="store_true", help="run the radiance-field rendering benchmark instead")
+    ap.add_argument("--queries", action="store_true", help="run the per-ray query benchmark instead")
     ap.add_argument("--rf-frames", type=int, default=40)
     ap.add_argument("--fit-steps", type=int, default=50)
     ap.add_argument("--fit-lr", default="5e-5,1e-2,2e-3,1e-2",
@@ -423,6 +465,9 @@ def main():
         return
     if args.rf:
         rf_render_bench(args)
+        return
+    if args.queries:
+        query_bench(args)
         return
 
     import numpy as np

@@ -224,32 +224,6 @@ __global__ void k_sort_keys(PassArgs P, Queue q, const int32_t *n_in, int64_t ca
     keys[j] = key;
 }
 
-// a traversal is suspended when at most this many lanes of the wave are still
-// walking the tree (the others then take new rays)
-constexpr int kSuspendAt = 32;
-
-// next chunk of 64 queue entries for this wave (dynamic load balance)
-__device__ __forceinline__ int64_t wave_grab(int32_t *work) {
-    int base = 0;
-    if ((threadIdx.x & 63) == 0) base = atomicAdd(work, 64);
-    return (int64_t)__shfl(base, 0);
-}
-
-// Lanes whose ray is done (want) take the next entries of the queue: one
-// atomic per wave, entries handed out in lane order.  Returns the queue
-// position for wanting lanes (>= n when the queue is exhausted), -1 otherwise.
-__device__ __forceinline__ int64_t lane_refill(bool want, int32_t *work) {
-    const uint64_t m = __ballot(want);
-    if (m == 0ull) return -1;
-    const int lane = threadIdx.x & 63;
-    const int leader = __ffsll((long long)m) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(work, __popcll(m));
-    base = __shfl(base, leader);
-    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    return want ? (int64_t)base + __popcll(m & below) : -1;
-}
-
 // Collision sweep of every live path; the result (selected primitive, scatter
 // distance) goes to hits[i].  Paths that overflow the register event buffer
 // are listed in `ovf` and redone by the wide instantiation (WIDE = true).

@@ -142,6 +142,26 @@ __device__ __forceinline__ bool emitter_ray(const SceneDev &S, RayD &r, int targ
     return true;
 }
 
+// results of ray i; an overflow of the main pass lists the ray for the wide one
+__device__ __forceinline__ void write_out(const SweepArgs &A, int64_t i, const SweepOut &o, uint32_t *err,
+                                          bool wide) {
+    if (o.status != 0) {
+        if (!wide) {
+            const int slot = atomicAdd(A.ovf_count, 1);
+            A.ovf_list[slot] = (int32_t)i;
+        } else {
+            atomicOr(err, kErrEvents);
+        }
+        if (A.prim_out) A.prim_out[i] = -1;
+        if (A.f_out) A.f_out[i] = __builtin_nanf("");
+        if (A.td_out) A.td_out[i] = __builtin_nan("");
+        return;
+    }
+    if (A.prim_out) A.prim_out[i] = o.prim;
+    if (A.f_out) A.f_out[i] = o.t;
+    if (A.td_out) A.td_out[i] = o.td;
+}
+
 template <int K>
 __device__ __forceinline__ void run_sweep(const SceneDev &S, const SweepArgs &A, int64_t i, int *stack,
                                           uint32_t *err, bool wide) {
@@ -169,21 +189,7 @@ __device__ __forceinline__ void run_sweep(const SceneDev &S, const SweepArgs &A,
             c[3] = (int32_t)tc.rounds;
         }
     }
-    if (o.status != 0) {
-        if (!wide) {
-            const int slot = atomicAdd(A.ovf_count, 1);
-            A.ovf_list[slot] = (int32_t)i;
-        } else {
-            atomicOr(err, kErrEvents);
-        }
-        if (A.prim_out) A.prim_out[i] = -1;
-        if (A.f_out) A.f_out[i] = __builtin_nanf("");
-        if (A.td_out) A.td_out[i] = __builtin_nan("");
-        return;
-    }
-    if (A.prim_out) A.prim_out[i] = o.prim;
-    if (A.f_out) A.f_out[i] = o.t;
-    if (A.td_out) A.td_out[i] = o.td;
+    write_out(A, i, o, err, wide);
 }
 
 __global__ __launch_bounds__(kBlock, 2) void k_sweep_main(SceneDev S, SweepArgs A, uint32_t *err) {
@@ -191,6 +197,57 @@ __global__ __launch_bounds__(kBlock, 2) void k_sweep_main(SceneDev S, SweepArgs 
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= A.n) return;
     run_sweep<kEventsMain>(S, A, i, stack, err, false);
+}
+
+// The main pass with persistent waves (lane_refill and suspended traversals):
+// the sweep of each ray in rounds, lanes refilled from the caller's list as
+// their rays finish.  (k_sweep_main, one ray per lane, serves the per-ray
+// traversal counters.)
+__global__ __launch_bounds__(kBlock, 2) void k_sweep_persist(SceneDev S, SweepArgs A, int32_t *work,
+                                                             uint32_t *err) {
+    __shared__ int stack[kStackSize * kBlock];
+    int64_t i = -1;
+    bool exhausted = false;
+    RayD r = make_ray(0.f, 0.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.0);
+    int ex = -1, target = -1;
+    float u = 0.f, entry = -kInf;
+    SweepState<kEventsMain> st;
+    SweepOut so;
+    TraceCount tc;
+    int spill[kStackSpill];
+    for (;;) {
+        const int64_t j = lane_refill(i < 0 && !exhausted, work);
+        bool fresh = false;
+        if (j >= 0) {
+            if (j < A.n) {
+                fresh = true;
+                r = load_ray(A.rays, j);
+                ex = A.excl ? A.excl[j] : -1;
+                target = -1;
+                entry = -kInf;
+                bool ok = true;
+                if (A.mode == kModeEmitter) {
+                    target = A.target[j];
+                    ok = emitter_ray(S, r, target, ex, entry);
+                    if (!ok) A.f_out[j] = 0.f;
+                }
+                if (ok) {
+                    u = A.u ? A.u[j] : 0.f;
+                    i = j;
+                    sweep_start(st, so, r, A.mode);
+                }
+            } else {
+                exhausted = true;
+            }
+        }
+        if (!__any(i >= 0 || fresh)) break;
+        const int susp = __any(exhausted) ? 0 : kSuspendAt;
+        if (i >= 0 &&
+            sweep_round<kEventsMain>(S, r, ex, A.mode, u, target, entry, st, so, stack, spill, susp, err, tc)) {
+            write_out(A, i, so, err, false);
+            i = -1;
+        }
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_sweep_wide(SceneDev S, SweepArgs A, uint32_t *err) {
@@ -225,13 +282,18 @@ hipError_t launch_exp(ugp_ctx ctx, int64_t n, const float *rays, const int32_t *
 hipError_t launch_sweep(ugp_ctx ctx, int mode, int64_t n, const float *rays, const int32_t *excl,
                         const float *u, const int32_t *target, int32_t *prim_out, float *f_out,
                         int32_t *counts, double *td_out) {
-    int32_t *buf = (int32_t *)ctx_scratch(ctx, sizeof(int32_t) * (size_t)(n + 1));
+    // [0] overflow count, [1] work counter, [2..] overflow list
+    int32_t *buf = (int32_t *)ctx_scratch(ctx, sizeof(int32_t) * (size_t)(n + 2));
     if (!buf) return hipErrorOutOfMemory;
-    hipError_t e = hipMemsetAsync(buf, 0, sizeof(int32_t), ctx->stream);
+    hipError_t e = hipMemsetAsync(buf, 0, sizeof(int32_t) * 2, ctx->stream);
     if (e != hipSuccess) return e;
-    SweepArgs A{mode, n, rays, excl, u, target, prim_out, f_out, buf + 1, buf, counts, td_out};
+    SweepArgs A{mode, n, rays, excl, u, target, prim_out, f_out, buf + 2, buf, counts, td_out};
     const unsigned g = (unsigned)((n + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_sweep_main, dim3(g), dim3(kBlock), 0, ctx->stream, ctx->scene, A, ctx->err);
+    if (counts)
+        hipLaunchKernelGGL(k_sweep_main, dim3(g), dim3(kBlock), 0, ctx->stream, ctx->scene, A, ctx->err);
+    else
+        hipLaunchKernelGGL(k_sweep_persist, dim3(std::min<unsigned>(g, 4096u)), dim3(kBlock), 0, ctx->stream,
+                           ctx->scene, A, buf + 1, ctx->err);
     hipLaunchKernelGGL(k_sweep_wide, dim3(g), dim3(kBlock), 0, ctx->stream, ctx->scene, A, ctx->err);
     return hipGetLastError();
 }

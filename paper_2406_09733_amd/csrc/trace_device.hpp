@@ -961,6 +961,29 @@ __device__ __forceinline__ bool sweep_round(const SceneDev &S, const RayD &r, in
     return false;  // not reached: every path above returns
 }
 
+// ---------------------------------------------------------------------------
+// Persistent waves over a list of rays: a lane whose ray is done takes the
+// next entry at once, and a traversal is suspended when at most kSuspendAt
+// lanes of the wave are still walking the tree (the others then take new
+// rays), so lanes do not wait for the slowest ray of their wave.
+// ---------------------------------------------------------------------------
+constexpr int kSuspendAt = 32;
+
+// Lanes whose ray is done (want) take the next entries of the list: one
+// atomic per wave, entries handed out in lane order.  Returns the list
+// position for wanting lanes (>= n when the list is exhausted), -1 otherwise.
+__device__ __forceinline__ int64_t lane_refill(bool want, int32_t *work) {
+    const uint64_t m = __ballot(want);
+    if (m == 0ull) return -1;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(work, __popcll(m));
+    base = __shfl(base, leader);
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    return want ? (int64_t)base + __popcll(m & below) : -1;
+}
+
 // The whole sweep of one ray.
 template <int K>
 __device__ __forceinline__ SweepOut sweep(const SceneDev &S, const RayD &r, int excl, int mode, float u,
