@@ -239,6 +239,24 @@ ugp_status ugp_rf_render(ugp_ctx ctx, const ugp_scene *scene, int64_t n_rays, co
                          const int32_t *exclude, const float *target, float loss_scale, float *L_out,
                          float *loss_out, float *grad);
 
+/* Vector-Jacobian products of the two images above, for a caller's own loss
+ * (e.g. an autograd engine): with dC = dLoss/dC given per ray,
+ *   grad += sum_i dC_i dC_i/d(parameters),
+ * the same derivative as the fused loss gradient (Sec. 7.2: each primitive's
+ * term with t_sat held fixed), in the same layouts.
+ *   dC    float [n] (ugp_accum_cdf_backward) or dL float [n][3]
+ *         (ugp_rf_render_backward)
+ *   grad  float [scene->n][11] (mean, scale, rotation, density) or [n][14]
+ *         (+ emission), added to
+ * scene: the parameters the current hierarchy was built from.  Device memory
+ * owned by the caller; dC and grad are required (UGP_ERR_INVALID_ARGUMENT,
+ * as is a scene whose n differs from the built one); UGP_ERR_NO_SCENE before
+ * a build.  Enqueued on the stream; temporaries are stream-ordered. */
+ugp_status ugp_accum_cdf_backward(ugp_ctx ctx, const ugp_scene *scene, int64_t n_rays, const float *rays,
+                                  const int32_t *exclude, const float *dC, float *grad);
+ugp_status ugp_rf_render_backward(ugp_ctx ctx, const ugp_scene *scene, int64_t n_rays, const float *rays,
+                                  const int32_t *exclude, const float *dL, float *grad);
+
 /* One jittered pinhole ray per pixel of cam (row-major, rays [w*h][8] as the
  * queries take them, t in [0, inf)); the sub-pixel jitter is the renderer's
  * camera jitter of sample `sample` (counter-based generator keyed on seed,

@@ -78,8 +78,8 @@ EXPORTS = ["ugp_create", "ugp_destroy", "ugp_set_stream", "ugp_build_bvh", "ugp_
            "ugp_set_profiling", "ugp_set_path_pool", "ugp_set_tail_paths", "ugp_get_render_stats", "ugp_trace_counts", "ugp_status_string",
            "ugp_nrc_num_params", "ugp_nrc_set_weights", "ugp_nrc_get_weights", "ugp_nrc_encode",
            "ugp_nrc_forward", "ugp_nrc_train_step", "ugp_nrc_records", "ugp_exp_transmittance",
-           "ugp_exp_sample_collision", "ugp_accum_cdf", "ugp_rf_render",
-           "ugp_camera_rays", "ugp_fit_adam"]
+           "ugp_exp_sample_collision", "ugp_accum_cdf", "ugp_rf_render", "ugp_accum_cdf_backward",
+           "ugp_rf_render_backward", "ugp_camera_rays", "ugp_fit_adam"]
 
 
 def lib():
@@ -115,6 +115,8 @@ def lib():
         L.ugp_accum_cdf.argtypes = [vp, vp, i64, vp, vp, vp, C.c_float, vp, vp, vp]
         L.ugp_camera_rays.argtypes = [vp, vp, C.c_uint64, i64, vp]
         L.ugp_rf_render.argtypes = [vp, vp, i64, vp, vp, vp, C.c_float, vp, vp, vp]
+        L.ugp_accum_cdf_backward.argtypes = [vp, vp, i64, vp, vp, vp, vp]
+        L.ugp_rf_render_backward.argtypes = [vp, vp, i64, vp, vp, vp, vp]
         L.ugp_exp_transmittance.argtypes = [vp, i64, vp, vp, vp]
         L.ugp_exp_sample_collision.argtypes = [vp, i64, vp, vp, C.c_uint64, vp, vp]
         L.ugp_fit_adam.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int32, C.POINTER(C.c_float),
@@ -189,6 +191,7 @@ class Context:
         _check("ugp_build_bvh", lib().ugp_build_bvh(self.h, C.byref(s), float(cutoff_eps)))
         self.n = n
         self._scene_t, self._scene_s = t, s  # the parameters the hierarchy was built from
+        self.build_id = getattr(self, "build_id", 0) + 1
         return self
 
     # ---- per-ray queries --------------------------------------------------
@@ -316,6 +319,28 @@ class Context:
         _check("ugp_rf_render", lib().ugp_rf_render(self.h, sp, n, _ptr(r), _ptr(e), _ptr(tg), float(loss_scale),
                                                     _ptr(L_out), _ptr(loss), _ptr(grad)))
         return L_out
+
+    def accum_cdf_backward(self, rays, dC, grad, exclude=None):
+        """ugp_accum_cdf_backward: grad (float32 [n_prims, 11]) += sum_i dC_i
+        dC_i/d(mean, scale, rotation, density), t_sat held fixed; the scene is
+        the one of the last build_bvh."""
+        return self._vjp("ugp_accum_cdf_backward", rays, dC, grad, exclude, 1, 11)
+
+    def rf_render_backward(self, rays, dL, grad, exclude=None):
+        """ugp_rf_render_backward: grad (float32 [n_prims, 14]) += sum_i dL_i .
+        dL_i/d(mean, scale, rotation, density, emission), dL [n, 3]."""
+        return self._vjp("ugp_rf_render_backward", rays, dL, grad, exclude, 3, 14)
+
+    def _vjp(self, name, rays, d, grad, exclude, nc, ng):
+        torch = self.torch
+        r = self._rays(rays)
+        n = r.shape[0]
+        e = self._excl(exclude, n)
+        d = self._dev(d, torch.float32, (n,) if nc == 1 else (n, nc))
+        assert grad.dtype == torch.float32 and tuple(grad.shape) == (self.n, ng) and grad.is_contiguous()
+        _check(name, getattr(lib(), name)(self.h, C.byref(self._scene_s), n, _ptr(r), _ptr(e), _ptr(d),
+                                          _ptr(grad)))
+        return grad
 
     def camera_rays(self, cam: dict, seed: int = 0, sample: int = 0):
         """ugp_camera_rays -> float32 [height * width, 8] jittered pinhole rays."""

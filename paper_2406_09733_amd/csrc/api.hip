@@ -51,6 +51,16 @@ bool query_args_ok(ugp_ctx ctx, int64_t n, const float *rays) {
     return ctx && n >= 0 && n < (int64_t(1) << 31) && (n == 0 || rays);
 }
 
+// Shared argument checks of the two vector-Jacobian products.
+ugp_status vjp_args(ugp_ctx ctx, const ugp_scene *scene, int64_t n, const float *rays, const float *dout,
+                    const float *grad) {
+    if (!query_args_ok(ctx, n, rays) || (n > 0 && !dout) || !grad) return UGP_ERR_INVALID_ARGUMENT;
+    if (!scene || !scene->scale || !scene->rotation) return UGP_ERR_INVALID_ARGUMENT;
+    if (ctx->scene.n == 0) return UGP_ERR_NO_SCENE;
+    if (scene->n != ctx->scene.n) return UGP_ERR_INVALID_ARGUMENT;
+    return UGP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -235,7 +245,8 @@ ugp_status ugp_accum_cdf(ugp_ctx ctx, const ugp_scene *scene, int64_t n, const f
     if (ctx->scene.n == 0) return UGP_ERR_NO_SCENE;
     if (n == 0) return UGP_OK;
     DeviceGuard g(ctx->device);
-    return from_hip(ugp::accum_cdf(ctx, scene, n, rays, exclude, target, loss_scale, false, C_out, loss_out, grad));
+    return from_hip(
+        ugp::accum_cdf(ctx, scene, n, rays, exclude, target, loss_scale, nullptr, false, C_out, loss_out, grad));
 }
 
 ugp_status ugp_rf_render(ugp_ctx ctx, const ugp_scene *scene, int64_t n, const float *rays, const int32_t *exclude,
@@ -247,7 +258,25 @@ ugp_status ugp_rf_render(ugp_ctx ctx, const ugp_scene *scene, int64_t n, const f
     if (ctx->scene.n == 0) return UGP_ERR_NO_SCENE;
     if (n == 0) return UGP_OK;
     DeviceGuard g(ctx->device);
-    return from_hip(ugp::accum_cdf(ctx, scene, n, rays, exclude, target, loss_scale, true, L_out, loss_out, grad));
+    return from_hip(
+        ugp::accum_cdf(ctx, scene, n, rays, exclude, target, loss_scale, nullptr, true, L_out, loss_out, grad));
+}
+
+ugp_status ugp_accum_cdf_backward(ugp_ctx ctx, const ugp_scene *scene, int64_t n, const float *rays,
+                                  const int32_t *exclude, const float *dC, float *grad) {
+    const ugp_status s = vjp_args(ctx, scene, n, rays, dC, grad);
+    if (s != UGP_OK || n == 0) return s;
+    DeviceGuard g(ctx->device);
+    return from_hip(
+        ugp::accum_cdf(ctx, scene, n, rays, exclude, nullptr, 0.f, dC, false, nullptr, nullptr, grad));
+}
+
+ugp_status ugp_rf_render_backward(ugp_ctx ctx, const ugp_scene *scene, int64_t n, const float *rays,
+                                  const int32_t *exclude, const float *dL, float *grad) {
+    const ugp_status s = vjp_args(ctx, scene, n, rays, dL, grad);
+    if (s != UGP_OK || n == 0) return s;
+    DeviceGuard g(ctx->device);
+    return from_hip(ugp::accum_cdf(ctx, scene, n, rays, exclude, nullptr, 0.f, dL, true, nullptr, nullptr, grad));
 }
 
 ugp_status ugp_camera_rays(ugp_ctx ctx, const ugp_camera *cam, uint64_t seed, int64_t sample, float *rays) {

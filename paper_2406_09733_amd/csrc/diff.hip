@@ -92,11 +92,14 @@ __device__ double w_and_grad(const HotRec &h, const RayD &r, double r2, double t
 // (Sec. 8, eq. rf): L = sum_k W_k L_e,k with the emission of the scene, the
 // loss loss_scale * |L - target|^2 and its gradient with respect to
 // (mu, M, d, L_e) (16 floats per primitive): the shape terms are the same
-// derivative of W_k, weighted by dLoss/dL . L_e,k.
+// derivative of W_k, weighted by dLoss/dL . L_e,k.  With dout (a caller's
+// dLoss/dC or dLoss/dL per ray) instead of a target, that is the weight and
+// no loss is formed; the first traversal then runs only for `out`.
 template <bool RGB>
 __global__ __launch_bounds__(kBlock) void k_cdf(SceneDev S, int64_t n, const float *rays, const int32_t *excl,
                                                 const double *tsat, const float *target, float loss_scale,
-                                                float *out, float *loss, float *g, uint32_t *err) {
+                                                const float *dout, float *out, float *loss, float *g,
+                                                uint32_t *err) {
     constexpr int kG = RGB ? 16 : 13;
     __shared__ int stack[kStackSize * kBlock];
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -113,7 +116,7 @@ __global__ __launch_bounds__(kBlock) void k_cdf(SceneDev S, int64_t n, const flo
             return h.orig != ex && !surely_missed(h, r, S.r2);
         };
         float acc[3] = {0.f, 0.f, 0.f};
-        {
+        if (out || target) {
             TravState ts;
             trav_begin(ts, S);
             traverse(S, r, r.t0, [&]() __attribute__((always_inline)) { return hi; }, stack, spill, ts, 0, err, tc,
@@ -134,13 +137,17 @@ __global__ __launch_bounds__(kBlock) void k_cdf(SceneDev S, int64_t n, const flo
         constexpr int nc = RGB ? 3 : 1;
         if (out)
             for (int k = 0; k < nc; ++k) out[nc * i + k] = acc[k];
-        if (target) {
+        if (target || dout) {
             double dL[3] = {0.0, 0.0, 0.0};
             bool any = false;
             for (int k = 0; k < nc; ++k) {
-                const float diff = acc[k] - target[nc * i + k];
-                l2 += loss_scale * diff * diff;
-                dL[k] = 2.0 * (double)loss_scale * (double)diff;
+                if (dout) {
+                    dL[k] = (double)dout[nc * i + k];
+                } else {
+                    const float diff = acc[k] - target[nc * i + k];
+                    l2 += loss_scale * diff * diff;
+                    dL[k] = 2.0 * (double)loss_scale * (double)diff;
+                }
                 any = any || dL[k] != 0.0;
             }
             if (g && any) {
@@ -296,7 +303,9 @@ __global__ void k_fit_adam(int64_t n, float *mean, float *scale, float *rot, flo
 }  // namespace
 
 hipError_t accum_cdf(ugp_ctx ctx, const ugp_scene *scene, int64_t n, const float *rays, const int32_t *excl,
-                     const float *target, float loss_scale, bool rgb, float *out, float *loss, float *grad) {
+                     const float *target, float loss_scale, const float *dout, bool rgb, float *out, float *loss,
+                     float *grad) {
+    const bool backward = target || dout;
     hipStream_t st = ctx->stream;
     const SceneDev &S = ctx->scene;
     const int kg = rgb ? 16 : 13;
@@ -314,13 +323,14 @@ hipError_t accum_cdf(ugp_ctx ctx, const ugp_scene *scene, int64_t n, const float
         const dim3 grid((unsigned)((n + kBlock - 1) / kBlock));
         if (rgb)
             hipLaunchKernelGGL(k_cdf<true>, grid, dim3(kBlock), 0, st, S, n, rays, excl, (const double *)tsat, target,
-                               loss_scale, out, target ? loss : nullptr, target ? gtmp : nullptr, ctx->err);
+                               loss_scale, dout, out, target ? loss : nullptr, backward ? gtmp : nullptr, ctx->err);
         else
             hipLaunchKernelGGL(k_cdf<false>, grid, dim3(kBlock), 0, st, S, n, rays, excl, (const double *)tsat,
-                               target, loss_scale, out, target ? loss : nullptr, target ? gtmp : nullptr, ctx->err);
+                               target, loss_scale, dout, out, target ? loss : nullptr, backward ? gtmp : nullptr,
+                               ctx->err);
         e = hipGetLastError();
     }
-    if (e == hipSuccess && grad && target) {
+    if (e == hipSuccess && grad && backward) {
         hipLaunchKernelGGL(k_cdf_chain, dim3((unsigned)((S.n + 255) / 256)), dim3(256), 0, st, S.n, scene->scale,
                            scene->rotation, (const float *)gtmp, rgb, grad);
         e = hipGetLastError();

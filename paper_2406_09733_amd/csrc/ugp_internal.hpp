@@ -155,7 +155,8 @@ hipError_t nrc_adapt(ugp_ctx ctx, const int32_t *attempted, int32_t cap, float *
 // diff.hip -- accumulated free-flight CDF, its loss and gradient; camera rays; Adam with clamps
 // rgb: the radiance-field mode (outputs, targets [n][3]; gradient rows of 14 with the emission)
 hipError_t accum_cdf(ugp_ctx ctx, const ugp_scene *scene, int64_t n, const float *rays, const int32_t *excl,
-                     const float *target, float loss_scale, bool rgb, float *out, float *loss, float *grad);
+                     const float *target, float loss_scale, const float *dout, bool rgb, float *out, float *loss,
+                     float *grad);
 hipError_t camera_rays(ugp_ctx ctx, const ugp_camera *cam, uint64_t seed, uint32_t sample, float *rays);
 // lr: mean, log scale, rotation, density, emission (emis may be NULL: rows of 11, else 14)
 hipError_t fit_adam(ugp_ctx ctx, int64_t n, float *mean, float *scale, float *rot, float *dens, float *emis,

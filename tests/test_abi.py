@@ -59,6 +59,8 @@ def test_host_side_argument_checks(L):
     assert L.ugp_destroy(None) == 1
     assert L.ugp_set_path_pool(None, C.c_int64(0)) == 1
     assert L.ugp_set_tail_paths(None, C.c_int64(0)) == 1
+    assert L.ugp_accum_cdf_backward(None, None, C.c_int64(1), None, None, None, None) == 1
+    assert L.ugp_rf_render_backward(None, None, C.c_int64(1), None, None, None, None) == 1
 
 
 def test_create_without_gpu_reports_device_error(L):
