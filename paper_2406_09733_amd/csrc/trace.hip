@@ -199,19 +199,22 @@ __global__ __launch_bounds__(kBlock, 2) void k_sweep_main(SceneDev S, SweepArgs 
     run_sweep<kEventsMain>(S, A, i, stack, err, false);
 }
 
-// The main pass with persistent waves (lane_refill and suspended traversals):
-// the sweep of each ray in rounds, lanes refilled from the caller's list as
-// their rays finish.  (k_sweep_main, one ray per lane, serves the per-ray
-// traversal counters.)
+// Persistent waves (lane_refill and suspended traversals): the sweep of each
+// ray in rounds, lanes refilled from the caller's rays (LIST = false, the
+// main pass with the K-entry buffer) or from the main pass's overflow list
+// (LIST = true, the wide pass) as their rays finish.  (k_sweep_main and
+// k_sweep_wide, one ray per lane, serve the per-ray traversal counters.)
+template <int K, bool LIST>
 __global__ __launch_bounds__(kBlock, 2) void k_sweep_persist(SceneDev S, SweepArgs A, int32_t *work,
                                                              uint32_t *err) {
     __shared__ int stack[kStackSize * kBlock];
+    const int64_t n = LIST ? (int64_t)*A.ovf_count : A.n;
     int64_t i = -1;
     bool exhausted = false;
     RayD r = make_ray(0.f, 0.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.0);
     int ex = -1, target = -1;
     float u = 0.f, entry = -kInf;
-    SweepState<kEventsMain> st;
+    SweepState<K> st;
     SweepOut so;
     TraceCount tc;
     int spill[kStackSpill];
@@ -219,21 +222,22 @@ __global__ __launch_bounds__(kBlock, 2) void k_sweep_persist(SceneDev S, SweepAr
         const int64_t j = lane_refill(i < 0 && !exhausted, work);
         bool fresh = false;
         if (j >= 0) {
-            if (j < A.n) {
+            if (j < n) {
+                const int64_t ray = LIST ? (int64_t)A.ovf_list[j] : j;
                 fresh = true;
-                r = load_ray(A.rays, j);
-                ex = A.excl ? A.excl[j] : -1;
+                r = load_ray(A.rays, ray);
+                ex = A.excl ? A.excl[ray] : -1;
                 target = -1;
                 entry = -kInf;
                 bool ok = true;
                 if (A.mode == kModeEmitter) {
-                    target = A.target[j];
+                    target = A.target[ray];
                     ok = emitter_ray(S, r, target, ex, entry);
-                    if (!ok) A.f_out[j] = 0.f;
+                    if (!ok) A.f_out[ray] = 0.f;
                 }
                 if (ok) {
-                    u = A.u ? A.u[j] : 0.f;
-                    i = j;
+                    u = A.u ? A.u[ray] : 0.f;
+                    i = ray;
                     sweep_start(st, so, r, A.mode);
                 }
             } else {
@@ -242,9 +246,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_sweep_persist(SceneDev S, SweepAr
         }
         if (!__any(i >= 0 || fresh)) break;
         const int susp = __any(exhausted) ? 0 : kSuspendAt;
-        if (i >= 0 &&
-            sweep_round<kEventsMain>(S, r, ex, A.mode, u, target, entry, st, so, stack, spill, susp, err, tc)) {
-            write_out(A, i, so, err, false);
+        if (i >= 0 && sweep_round<K>(S, r, ex, A.mode, u, target, entry, st, so, stack, spill, susp, err, tc)) {
+            write_out(A, i, so, err, LIST);
             i = -1;
         }
     }
@@ -282,19 +285,24 @@ hipError_t launch_exp(ugp_ctx ctx, int64_t n, const float *rays, const int32_t *
 hipError_t launch_sweep(ugp_ctx ctx, int mode, int64_t n, const float *rays, const int32_t *excl,
                         const float *u, const int32_t *target, int32_t *prim_out, float *f_out,
                         int32_t *counts, double *td_out) {
-    // [0] overflow count, [1] work counter, [2..] overflow list
-    int32_t *buf = (int32_t *)ctx_scratch(ctx, sizeof(int32_t) * (size_t)(n + 2));
+    // [0] overflow count, [1] main-pass work counter, [2] wide-pass work
+    // counter, [3..] overflow list
+    int32_t *buf = (int32_t *)ctx_scratch(ctx, sizeof(int32_t) * (size_t)(n + 3));
     if (!buf) return hipErrorOutOfMemory;
-    hipError_t e = hipMemsetAsync(buf, 0, sizeof(int32_t) * 2, ctx->stream);
+    hipError_t e = hipMemsetAsync(buf, 0, sizeof(int32_t) * 3, ctx->stream);
     if (e != hipSuccess) return e;
-    SweepArgs A{mode, n, rays, excl, u, target, prim_out, f_out, buf + 2, buf, counts, td_out};
+    SweepArgs A{mode, n, rays, excl, u, target, prim_out, f_out, buf + 3, buf, counts, td_out};
     const unsigned g = (unsigned)((n + kBlock - 1) / kBlock);
-    if (counts)
+    const unsigned gp = std::min<unsigned>(g, 4096u);
+    if (counts) {
         hipLaunchKernelGGL(k_sweep_main, dim3(g), dim3(kBlock), 0, ctx->stream, ctx->scene, A, ctx->err);
-    else
-        hipLaunchKernelGGL(k_sweep_persist, dim3(std::min<unsigned>(g, 4096u)), dim3(kBlock), 0, ctx->stream,
+        hipLaunchKernelGGL(k_sweep_wide, dim3(g), dim3(kBlock), 0, ctx->stream, ctx->scene, A, ctx->err);
+    } else {
+        hipLaunchKernelGGL((k_sweep_persist<kEventsMain, false>), dim3(gp), dim3(kBlock), 0, ctx->stream,
                            ctx->scene, A, buf + 1, ctx->err);
-    hipLaunchKernelGGL(k_sweep_wide, dim3(g), dim3(kBlock), 0, ctx->stream, ctx->scene, A, ctx->err);
+        hipLaunchKernelGGL((k_sweep_persist<kEventsWide, true>), dim3(gp), dim3(kBlock), 0, ctx->stream,
+                           ctx->scene, A, buf + 2, ctx->err);
+    }
     return hipGetLastError();
 }
 

@@ -613,6 +613,7 @@ struct SweepState {
     float cap_sat;   // saturation bound: t_sat <= cap_sat
     bool evicted, hidden;
     int n_before;    // buffered entries when the round began
+    float wbuf;      // K > 16: sum of the buffered full weights (kept up to date)
     TravState ts;
 };
 
@@ -625,6 +626,7 @@ __device__ __forceinline__ void sweep_start(SweepState<K> &st, SweepOut &out, co
     }
     if (mode == kModeEmitter) out.t = 0.f;
     st.B.n = 0;
+    st.wbuf = 0.f;
     st.S_fin = 0.f;
     st.t_cur = r.t0;
     st.lb_a = -kInf;
@@ -687,6 +689,29 @@ __device__ __forceinline__ bool sweep_round(const SceneDev &S, const RayD &r, in
                      float xa = c.a, xb = c.b, xw = c.W;
                      int xi = c.orig;
                      bool placed = false;
+                     if constexpr (K > 16) {
+                         // the buffer is in private memory: binary search for
+                         // the slot, then shift the (usually short) tail up;
+                         // entries arrive near-first, so mostly near the end
+                         int lo = 0, hi = B.n;
+                         while (lo < hi) {
+                             const int mid = (lo + hi) >> 1;
+                             if (key_less(B.a[mid], B.id[mid], xa, xi)) lo = mid + 1;
+                             else hi = mid;
+                         }
+                         if (lo < K) {
+                             const int last = B.n < K ? B.n : K - 1;
+                             if (B.n == K) {  // the largest buffered entry leaves
+                                 xa = B.a[K - 1]; xb = B.b[K - 1]; xw = B.w[K - 1]; xi = B.id[K - 1];
+                                 st.wbuf -= xw;
+                             } else {
+                                 placed = true;
+                             }
+                             for (int i = last; i > lo; --i) B.move(i, i - 1);
+                             B.a[lo] = c.a; B.b[lo] = c.b; B.w[lo] = c.W; B.id[lo] = c.orig;
+                             st.wbuf += c.W;
+                         }
+                     } else {
 #pragma unroll Unr<K>::v
                      for (int i = 0; i < K; ++i) {
                          if (i < B.n) {
@@ -701,6 +726,7 @@ __device__ __forceinline__ bool sweep_round(const SceneDev &S, const RayD &r, in
                              placed = true;
                          }
                      }
+                     }
                      if (placed) {
                          ++B.n;
                      } else {  // x is the largest of K + 1: evict it
@@ -708,7 +734,10 @@ __device__ __forceinline__ bool sweep_round(const SceneDev &S, const RayD &r, in
                          cap_a = xa;
                          cap_id = xi;
                      }
-                     if (c.b < cap_sat && key_less(c.a, c.orig, cap_a, cap_id)) {
+                     // (wide buffer: skip the scan while all buffered weight
+                     // together, an upper bound of the sum below, is short of 1)
+                     if (c.b < cap_sat && key_less(c.a, c.orig, cap_a, cap_id) &&
+                         (K <= 16 || S_fin + st.wbuf >= 1.f)) {
                          // the new primitive is buffered: lower bound of F(c.b)
                          float lo_F = S_fin;
 #pragma unroll Unr<K>::v
@@ -791,8 +820,13 @@ __device__ __forceinline__ bool sweep_round(const SceneDev &S, const RayD &r, in
             // passes the read index)
             int wpos = 0;
             if constexpr (K > 16) {
+                float ws = 0.f;
                 for (int i = 0; i < B.n; ++i)
-                    if (!((fin >> i) & 1ull)) B.move(wpos++, i);
+                    if (!((fin >> i) & 1ull)) {
+                        ws += B.w[i];
+                        B.move(wpos++, i);
+                    }
+                st.wbuf = ws;
             } else {
 #pragma unroll
                 for (int i = 0; i < K; ++i) {

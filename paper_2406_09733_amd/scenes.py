@@ -191,6 +191,24 @@ def needles(seed: int = 4, n: int = 3000, n_emit: int = 30, emit: float = 5.0) -
     return sc
 
 
+def overlap_pile(seed: int = 5, n: int = 40, dens_lo: float = 0.02, dens_hi: float = 0.25) -> dict:
+    """n large, faint Gaussians piled on one point: means N(0.5, 0.02^2) per
+    axis, scales log-uniform in [0.15, 0.3] per axis, random rotations, peak
+    density U[dens_lo, dens_hi].  Every ray through the middle overlaps all
+    of them at once, the case that needs more than the sweep's 16-entry
+    buffer; some rays saturate inside the pile, others cross it."""
+    rng = _rng(seed)
+    mean = rng.normal(0.5, 0.02, (n, 3))
+    scale = _loguniform(rng, 0.15, 0.3, 3 * n).reshape(n, 3)
+    q = _random_quat(rng, n)
+    dens = rng.uniform(dens_lo, dens_hi, n)
+    sc = _finish([(mean, scale, q, dens)], rng, albedo_lo=0.2, albedo_hi=0.8, rough_lo=0.1,
+                 rough_hi=1.0, glossy_frac=0.5)
+    sc["emission"][: max(1, n // 10)] = 5.0
+    sc["bounds"] = (np.zeros(3, np.float32), np.ones(3, np.float32))
+    return sc
+
+
 def mixed_100k(seed: int = 1, n_flat: int = 70_000, n_cloud: int = 30_000,
                n_emit: int = 1_000, emit: float = 5.0) -> dict:
     """70% flat Gaussians (one axis 100x thinner) on 10 spheres and 10 square

@@ -57,7 +57,7 @@ ATOL_SUM = 5e-7  # 4 ulp of 1.0 in float32
 
 def _cases():
     return {"tiny_random": (scenes.tiny_random(), 4096), "mixed_100k": (scenes.mixed_100k(), 2048),
-            "needles": (scenes.needles(), 4096)}
+            "needles": (scenes.needles(), 4096), "overlap_pile": (scenes.overlap_pile(), 2048)}
 
 
 @pytest.fixture(scope="module")
@@ -75,7 +75,7 @@ def _with_exclude(sc, rays, seed):
     return ex
 
 
-@pytest.mark.parametrize("name", ["tiny_random", "mixed_100k", "needles"])
+@pytest.mark.parametrize("name", ["tiny_random", "mixed_100k", "needles", "overlap_pile"])
 def test_transmittance_parity(ctx, built, name):
     sc, S, nr = built[name]
     _say("transmittance parity", name, nr)
@@ -94,7 +94,7 @@ def test_transmittance_parity(ctx, built, name):
     assert np.all(np.abs(_np(T2) - T_ref) <= 1e-5)
 
 
-@pytest.mark.parametrize("name", ["tiny_random", "mixed_100k", "needles"])
+@pytest.mark.parametrize("name", ["tiny_random", "mixed_100k", "needles", "overlap_pile"])
 def test_saturation_parity(ctx, built, name):
     sc, S, nr = built[name]
     _say("saturation parity", name, nr)
@@ -121,7 +121,7 @@ def test_saturation_parity(ctx, built, name):
     assert ok.all(), (np.where(~ok)[0][:10], ts[~ok][:5], ts_ref[~ok][:5])
 
 
-@pytest.mark.parametrize("name", ["tiny_random", "mixed_100k", "needles"])
+@pytest.mark.parametrize("name", ["tiny_random", "mixed_100k", "needles", "overlap_pile"])
 def test_collision_parity(ctx, built, name):
     sc, S, nr = built[name]
     _say("collision parity", name, nr)
@@ -143,7 +143,7 @@ def test_collision_parity(ctx, built, name):
          "escape fraction", float((prim < 0).mean()))
 
 
-@pytest.mark.parametrize("name", ["tiny_random", "mixed_100k", "needles"])
+@pytest.mark.parametrize("name", ["tiny_random", "mixed_100k", "needles", "overlap_pile"])
 def test_emitter_query_parity(ctx, built, name):
     sc, S, nr = built[name]
     _say("emitter query parity", name, nr)
@@ -171,6 +171,27 @@ def test_emitter_query_parity(ctx, built, name):
                  f" t1 {rays[i, 7]} excl {ex[i]} tgt {tgt[i]}")
     assert ok.all(), (np.where(~ok)[0][:10], got[~ok][:5], ref[~ok][:5])
     assert (ref > 0).mean() > 0.02  # targets deep in the needle ball are mostly hidden
+
+
+def test_more_overlaps_than_the_wide_buffer_is_reported(ctx, torch):
+    _say("80 primitives overlapping one point: overflow status")
+    import paper_2406_09733_amd as P
+    sc = scenes.overlap_pile(n=80, dens_lo=0.002, dens_hi=0.004)
+    _build(ctx, sc)
+    rays = np.zeros((64, 8), np.float32)
+    rays[:, 0:3] = (0.5, 0.5, -1.0)
+    rays[:, 5] = 1.0
+    rays[:, 7] = np.inf
+    rays[32:, 0] = 5.0  # these miss the pile
+    u = np.full(64, 0.5, np.float32)
+    prim, t = ctx.sample_collision(rays, u)
+    with pytest.raises(P.UGPError) as e:
+        ctx.sync()
+    assert e.value.code == 6
+    prim = _np(prim)
+    assert np.all(prim[:32] == -1) and np.all(np.isnan(_np(t)[:32]))
+    assert np.all(prim[32:] == -1) and np.all(np.isnan(_np(t)[32:]))
+    ctx.sync()  # the status was reported once and cleared
 
 
 def test_edge_cases(ctx, orc, torch):
