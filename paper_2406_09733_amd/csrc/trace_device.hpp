@@ -487,6 +487,25 @@ struct Unr {
     static constexpr int v = K <= 16 ? K : 1;
 };
 
+// A wide buffer (K > 16, in private memory) also keeps each entry's chord,
+// so the saturation solve and the final walks read it back instead of
+// re-deriving it from the primitive's record; the register buffer does not.
+template <int K, bool kKeep = (K > 16)>
+struct EvChords {
+    __device__ __forceinline__ void move(int, int) {}
+};
+template <int K>
+struct EvChords<K, true> {
+    double tc[K];
+    float s[K], pref[K], ta[K], tb[K];
+    __device__ __forceinline__ void move(int d, int f) {
+        tc[d] = tc[f]; s[d] = s[f]; pref[d] = pref[f]; ta[d] = ta[f]; tb[d] = tb[f];
+    }
+    __device__ __forceinline__ void put(int i, const Chord &c) {
+        tc[i] = c.tc; s[i] = c.s; pref[i] = c.pref; ta[i] = c.ta; tb[i] = c.tb;
+    }
+};
+
 // Event buffer as a structure of arrays; fields are copied one by one (a
 // whole-struct copy becomes a memcpy that keeps the buffer out of registers).
 template <int K>
@@ -494,8 +513,10 @@ struct EvBuf {
     float a[K], b[K], w[K];
     int id[K];
     int n;
+    EvChords<K> ch;
     __device__ __forceinline__ void move(int dst, int src) {
         a[dst] = a[src]; b[dst] = b[src]; w[dst] = w[src]; id[dst] = id[src];
+        ch.move(dst, src);
     }
 };
 
@@ -564,12 +585,29 @@ __device__ __forceinline__ Chord cache_get(const ChordCache &cc, int j) {
     return cache_get_slot(cc, __popcll(cc.mask & ((1ull << j) - 1ull)));
 }
 
-// chord of buffer entry j: from the cache when held, else re-derived
+// chord of buffer entry j: kept in a wide buffer; from the cache when held,
+// else re-derived
 template <int K>
 __device__ __forceinline__ Chord ev_chord_c(const SceneDev &S, const RayD &r, const EvBuf<K> &B, int j,
                                            const ChordCache *cc, TraceCount &tc) {
-    if (cc && ((cc->mask >> j) & 1ull)) return cache_get(*cc, j);
-    return ev_chord(S, r, ev_id(B, j), tc);
+    if constexpr (K > 16) {
+        Chord c;
+        c.tc = B.ch.tc[j];
+        c.s = B.ch.s[j];
+        c.pref = B.ch.pref[j];
+        c.ta = B.ch.ta[j];
+        c.tb = B.ch.tb[j];
+        c.a = B.a[j];
+        c.b = B.b[j];
+        c.bd = (double)B.b[j];
+        c.W = B.w[j];
+        c.orig = B.id[j];
+        c.own = true;
+        return c;
+    } else {
+        if (cc && ((cc->mask >> j) & 1ull)) return cache_get(*cc, j);
+        return ev_chord(S, r, ev_id(B, j), tc);
+    }
 }
 
 // F(t) and F'(t) over the buffer: S_fin + sum of (full weights of exits <= t,
@@ -709,6 +747,7 @@ __device__ __forceinline__ bool sweep_round(const SceneDev &S, const RayD &r, in
                              }
                              for (int i = last; i > lo; --i) B.move(i, i - 1);
                              B.a[lo] = c.a; B.b[lo] = c.b; B.w[lo] = c.W; B.id[lo] = c.orig;
+                             B.ch.put(lo, c);
                              st.wbuf += c.W;
                          }
                      } else {
@@ -866,12 +905,14 @@ __device__ __forceinline__ bool sweep_round(const SceneDev &S, const RayD &r, in
         // Entries exiting by lo count in full at every t of the bracket and
         // entries starting at or after hi not at all; the chords of the others
         // (the only ones that can straddle t) are kept in LDS while t_sat is
-        // solved, with their full weights in registers.
+        // solved, with their full weights in registers (a wide buffer holds
+        // its chords itself: the solve walks the mask of those entries).
         __shared__ float4 cc_lds[kChordCache * 2 * kBlock];
         ChordCache cc{cc_lds, 0ull};
         float F_base = S_fin;
         float wc[kChordCache];
         int ns = 0, n_act = 0;
+        uint64_t act = 0;  // wide buffer: the entries that can straddle t
 #pragma unroll Unr<K>::v
         for (int i = 0; i < K; ++i) {
             if (i < B.n) {
@@ -879,7 +920,9 @@ __device__ __forceinline__ bool sweep_round(const SceneDev &S, const RayD &r, in
                     F_base += B.w[i];
                 } else if ((double)B.a[i] < hi) {
                     ++n_act;
-                    if (ns < kChordCache) {
+                    if constexpr (K > 16) {
+                        act |= 1ull << i;
+                    } else if (ns < kChordCache) {
 #pragma unroll
                         for (int k = 0; k < kChordCache; ++k)
                             if (k == ns) wc[k] = B.w[i];
@@ -892,6 +935,16 @@ __device__ __forceinline__ bool sweep_round(const SceneDev &S, const RayD &r, in
         const bool cached = n_act <= kChordCache;
         // F(t) - 1 and F'(t) on the bracket
         auto eval = [&](double t, float &g) __attribute__((always_inline)) {
+            if constexpr (K > 16) {
+                float F = F_base, G = 0.f;
+                for (uint64_t m = act; m; m &= m - 1) {
+                    const Chord c = ev_chord_c(S, r, B, __builtin_ctzll(m), nullptr, tc);
+                    F += half_integral_to(c, t);
+                    G += half_kernel_at(c, t);
+                }
+                g = G;
+                return F - 1.f;
+            }
             if (!cached) return sweep_F<K>(S, r, B, S_fin, t, &g, tc, &cc) - 1.f;
             float F = F_base, G = 0.f;
 #pragma unroll
