@@ -129,7 +129,50 @@ struct SweepArgs {
     int32_t *ovf_count;
     int32_t *counts;     // optional [n][4] per-ray traversal counters
     double *td_out;      // optional: saturate mode, t_sat in full precision
+    float4 *ovf_state;   // optional [kOvfStateSlots][kOvfStateVecs]: the main pass's
+                         // state of the first overflowed rays, resumed by the wide pass
 };
+
+// An overflow happens at the end of a round that began with a full buffer of
+// carried entries, none of which exits in the window: the round's new entries
+// all have larger keys than the carried ones and were evicted, so the state
+// at the overflow is the state at the start of that round.  The wide pass
+// resumes from it instead of starting the ray again.
+constexpr int64_t kOvfStateSlots = int64_t(1) << 20;
+constexpr int kOvfStateVecs = 2 + kEventsMain;
+
+__device__ __forceinline__ void save_state(float4 *p, const SweepState<kEventsMain> &st) {
+    p[0] = make_float4(st.S_fin, st.lb_a, __int_as_float(st.lb_id), __int_as_float(st.round));
+    p[1] = make_float4(__int_as_float(__double2loint(st.t_cur)), __int_as_float(__double2hiint(st.t_cur)),
+                       __int_as_float(st.B.n), 0.f);
+#pragma unroll
+    for (int i = 0; i < kEventsMain; ++i)
+        if (i < st.B.n) p[2 + i] = make_float4(st.B.a[i], st.B.b[i], st.B.w[i], __int_as_float(st.B.id[i]));
+}
+
+// the wide buffer re-derives the chords of the carried entries
+__device__ __forceinline__ void load_state(const float4 *p, SweepState<kEventsWide> &st, const SceneDev &S,
+                                           const RayD &r, TraceCount &tc) {
+    const float4 h0 = p[0], h1 = p[1];
+    st.S_fin = h0.x;
+    st.lb_a = h0.y;
+    st.lb_id = __float_as_int(h0.z);
+    st.round = __float_as_int(h0.w);
+    st.t_cur = __hiloint2double(__float_as_int(h1.y), __float_as_int(h1.x));
+    const int n = __float_as_int(h1.z);
+    float ws = 0.f;
+    for (int i = 0; i < n; ++i) {
+        const float4 e = p[2 + i];
+        st.B.a[i] = e.x;
+        st.B.b[i] = e.y;
+        st.B.w[i] = e.z;
+        st.B.id[i] = __float_as_int(e.w);
+        st.B.ch.put(i, ev_chord(S, r, st.B.id[i], tc));
+        ws += e.z;
+    }
+    st.B.n = n;
+    st.wbuf = ws;
+}
 
 // emitter mode: clip the ray at the exit of the target's chord
 __device__ __forceinline__ bool emitter_ray(const SceneDev &S, RayD &r, int target, int excl, float &entry) {
@@ -142,12 +185,14 @@ __device__ __forceinline__ bool emitter_ray(const SceneDev &S, RayD &r, int targ
     return true;
 }
 
-// results of ray i; an overflow of the main pass lists the ray for the wide one
-__device__ __forceinline__ void write_out(const SweepArgs &A, int64_t i, const SweepOut &o, uint32_t *err,
-                                          bool wide) {
+// results of ray i; an overflow of the main pass lists the ray for the wide
+// one (returns its slot in the list, else -1)
+__device__ __forceinline__ int write_out(const SweepArgs &A, int64_t i, const SweepOut &o, uint32_t *err,
+                                         bool wide) {
     if (o.status != 0) {
+        int slot = -1;
         if (!wide) {
-            const int slot = atomicAdd(A.ovf_count, 1);
+            slot = atomicAdd(A.ovf_count, 1);
             A.ovf_list[slot] = (int32_t)i;
         } else {
             atomicOr(err, kErrEvents);
@@ -155,11 +200,12 @@ __device__ __forceinline__ void write_out(const SweepArgs &A, int64_t i, const S
         if (A.prim_out) A.prim_out[i] = -1;
         if (A.f_out) A.f_out[i] = __builtin_nanf("");
         if (A.td_out) A.td_out[i] = __builtin_nan("");
-        return;
+        return slot;
     }
     if (A.prim_out) A.prim_out[i] = o.prim;
     if (A.f_out) A.f_out[i] = o.t;
     if (A.td_out) A.td_out[i] = o.td;
+    return -1;
 }
 
 template <int K>
@@ -239,6 +285,9 @@ __global__ __launch_bounds__(kBlock, 2) void k_sweep_persist(SceneDev S, SweepAr
                     u = A.u ? A.u[ray] : 0.f;
                     i = ray;
                     sweep_start(st, so, r, A.mode);
+                    if constexpr (LIST)
+                        if (A.ovf_state && j < kOvfStateSlots)
+                            load_state(A.ovf_state + j * kOvfStateVecs, st, S, r, tc);
                 }
             } else {
                 exhausted = true;
@@ -247,7 +296,10 @@ __global__ __launch_bounds__(kBlock, 2) void k_sweep_persist(SceneDev S, SweepAr
         if (!__any(i >= 0 || fresh)) break;
         const int susp = __any(exhausted) ? 0 : kSuspendAt;
         if (i >= 0 && sweep_round<K>(S, r, ex, A.mode, u, target, entry, st, so, stack, spill, susp, err, tc)) {
-            write_out(A, i, so, err, LIST);
+            const int slot = write_out(A, i, so, err, LIST);
+            if constexpr (!LIST)
+                if (slot >= 0 && slot < kOvfStateSlots && A.ovf_state)
+                    save_state(A.ovf_state + (int64_t)slot * kOvfStateVecs, st);
             i = -1;
         }
     }
@@ -286,12 +338,18 @@ hipError_t launch_sweep(ugp_ctx ctx, int mode, int64_t n, const float *rays, con
                         const float *u, const int32_t *target, int32_t *prim_out, float *f_out,
                         int32_t *counts, double *td_out) {
     // [0] overflow count, [1] main-pass work counter, [2] wide-pass work
-    // counter, [3..] overflow list
-    int32_t *buf = (int32_t *)ctx_scratch(ctx, sizeof(int32_t) * (size_t)(n + 3));
-    if (!buf) return hipErrorOutOfMemory;
+    // counter, [3..] overflow list; then (16-B aligned) the resumable states
+    // of the first kOvfStateSlots overflowed rays (not with counts: the wide
+    // pass then starts each ray again and adds its own counts)
+    const size_t list_bytes = (sizeof(int32_t) * (size_t)(n + 3) + 15) & ~(size_t)15;
+    const size_t state_bytes = counts ? 0 : sizeof(float4) * kOvfStateVecs * (size_t)std::min(n, kOvfStateSlots);
+    char *mem = (char *)ctx_scratch(ctx, list_bytes + state_bytes);
+    if (!mem) return hipErrorOutOfMemory;
+    int32_t *buf = (int32_t *)mem;
     hipError_t e = hipMemsetAsync(buf, 0, sizeof(int32_t) * 3, ctx->stream);
     if (e != hipSuccess) return e;
-    SweepArgs A{mode, n, rays, excl, u, target, prim_out, f_out, buf + 3, buf, counts, td_out};
+    float4 *state = counts ? nullptr : (float4 *)(mem + list_bytes);
+    SweepArgs A{mode, n, rays, excl, u, target, prim_out, f_out, buf + 3, buf, counts, td_out, state};
     const unsigned g = (unsigned)((n + kBlock - 1) / kBlock);
     const unsigned gp = std::min<unsigned>(g, 4096u);
     if (counts) {
