@@ -300,6 +300,27 @@ ugp_status ugp_trace_counts(ugp_ctx ctx, int mode, int64_t n_rays, const float *
 ugp_status ugp_render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p,
                       float *sum_rgb, float *sumsq_rgb);
 
+/* Gradient of a loss of the rendered image with respect to every primitive's
+ * albedo (the shading adjoint of the path tracer of eq. rte), by path
+ * replay: each chunk of paths is traced as ugp_render traces it, then again
+ * with the same random numbers, and at every scattering vertex the radiance
+ * that passes through it is weighted by the derivative of its phase function
+ * (Sec. 4.2; linear in the albedo: albedo/pi cos for the diffuse lobe, the
+ * Schlick term albedo + (1 - albedo) m of the glossy one).  No sampling
+ * decision depends on the albedo, so this is the exact derivative of the
+ * estimate that ugp_render returns for the same arguments.
+ *   d_image      [device] float [height][width][3]: dLoss / d(image), the
+ *                image being the per-pixel mean over the spp samples (sum / spp)
+ *   grad_albedo  [device] float [scene n][3] by original index, added to
+ *   sum_rgb      [device] float [height][width][3] or NULL: the forward pass's
+ *                per-pixel sum is added to it (as ugp_render's)
+ * p->nrc_mode must be 0 (UGP_ERR_UNSUPPORTED otherwise); other arguments and
+ * errors as ugp_render.  A diffuse channel of zero albedo reports a zero
+ * gradient (the replay divides the albedo out).
+ * Temporaries (three float4 per radiance slot) are stream-ordered. */
+ugp_status ugp_render_albedo_grad(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p,
+                                  const float *d_image, float *grad_albedo, float *sum_rgb);
+
 /* Waits for the context's stream and reports deferred device-side errors
  * (queue or stack overflow) as UGP_ERR_OVERFLOW, clearing them. */
 ugp_status ugp_sync(ugp_ctx ctx);

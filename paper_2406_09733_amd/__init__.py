@@ -74,7 +74,7 @@ class _Stats(C.Structure):
 
 
 EXPORTS = ["ugp_create", "ugp_destroy", "ugp_set_stream", "ugp_build_bvh", "ugp_transmittance",
-           "ugp_sample_collision", "ugp_saturation", "ugp_emitter_query", "ugp_render", "ugp_sync",
+           "ugp_sample_collision", "ugp_saturation", "ugp_emitter_query", "ugp_render", "ugp_render_albedo_grad", "ugp_sync",
            "ugp_set_profiling", "ugp_set_path_pool", "ugp_set_tail_paths", "ugp_get_render_stats", "ugp_trace_counts", "ugp_status_string",
            "ugp_nrc_num_params", "ugp_nrc_set_weights", "ugp_nrc_get_weights", "ugp_nrc_encode",
            "ugp_nrc_forward", "ugp_nrc_train_step", "ugp_nrc_records", "ugp_exp_transmittance",
@@ -99,6 +99,7 @@ def lib():
         L.ugp_saturation.argtypes = [vp, i64, vp, vp, vp]
         L.ugp_emitter_query.argtypes = [vp, i64, vp, vp, vp, vp]
         L.ugp_render.argtypes = [vp, C.POINTER(_Camera), C.POINTER(_Params), vp, vp]
+        L.ugp_render_albedo_grad.argtypes = [vp, C.POINTER(_Camera), C.POINTER(_Params), vp, vp, vp]
         L.ugp_sync.argtypes = [vp]
         L.ugp_set_profiling.argtypes = [vp, C.c_int]
         L.ugp_set_path_pool.argtypes = [vp, C.c_int64]
@@ -137,6 +138,30 @@ def _check(call: str, code: int):
 
 def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _render_params(params: dict):
+    """ugp_render_params from a dict (defaults: 1 spp, depth 4, seed 0, no cache)."""
+    p = _Params()
+    p.spp = int(params.get("spp", 1))
+    p.max_depth = int(params.get("max_depth", 4))
+    p.seed = int(params.get("seed", 0))
+    p.sample_offset = int(params.get("sample_offset", 0))
+    env = params.get("env_radiance", (0.0, 0.0, 0.0))
+    for i in range(3):
+        p.env_radiance[i] = float(env[i])
+    p.mis_mode = int(params.get("mis_mode", 0))
+    p.nrc_mode = int(params.get("nrc_mode", 0))
+    p.nrc_terminate_after = int(params.get("nrc_terminate_after", 2))
+    p.nrc_train_records = int(params.get("nrc_train_records", 65536))
+    p.nrc_lr = float(params.get("nrc_lr", 0.0))
+    box = params.get("nrc_box", None)
+    for i in range(6):
+        p.nrc_box[i] = 0.0 if box is None else float(box[i])
+    p.nrc_train_steps = int(params.get("nrc_train_steps", 1))
+    p.nrc_radiance_scale = float(params.get("nrc_radiance_scale", 0.0))
+    p.nrc_target_clamp = float(params.get("nrc_target_clamp", 0.0))
+    return p
 
 
 class Context:
@@ -378,27 +403,26 @@ class Context:
         if sumsq_rgb is None and params.get("want_sumsq", True):
             sumsq_rgb = torch.zeros((H, W, 3), device=self.device, dtype=torch.float32)
         c = _camera(cam)
-        p = _Params()
-        p.spp = int(params.get("spp", 1))
-        p.max_depth = int(params.get("max_depth", 4))
-        p.seed = int(params.get("seed", 0))
-        p.sample_offset = int(params.get("sample_offset", 0))
-        env = params.get("env_radiance", (0.0, 0.0, 0.0))
-        for i in range(3):
-            p.env_radiance[i] = float(env[i])
-        p.mis_mode = int(params.get("mis_mode", 0))
-        p.nrc_mode = int(params.get("nrc_mode", 0))
-        p.nrc_terminate_after = int(params.get("nrc_terminate_after", 2))
-        p.nrc_train_records = int(params.get("nrc_train_records", 65536))
-        p.nrc_lr = float(params.get("nrc_lr", 0.0))
-        box = params.get("nrc_box", None)
-        for i in range(6):
-            p.nrc_box[i] = 0.0 if box is None else float(box[i])
-        p.nrc_train_steps = int(params.get("nrc_train_steps", 1))
-        p.nrc_radiance_scale = float(params.get("nrc_radiance_scale", 0.0))
-        p.nrc_target_clamp = float(params.get("nrc_target_clamp", 0.0))
+        p = _render_params(params)
         _check("ugp_render", lib().ugp_render(self.h, C.byref(c), C.byref(p), _ptr(sum_rgb), _ptr(sumsq_rgb)))
         return sum_rgb, sumsq_rgb
+
+    def render_albedo_grad(self, cam: dict, params: dict, d_image, grad, sum_rgb=None):
+        """ugp_render_albedo_grad: grad (float32 [n_prims, 3]) += dLoss/dalbedo
+        for d_image = dLoss/d(mean image) [H, W, 3]; the forward pass's
+        per-pixel sums are added into sum_rgb when given.  Returns grad."""
+        torch = self.torch
+        W, H = int(cam["width"]), int(cam["height"])
+        d = self._dev(d_image, torch.float32, (H, W, 3))
+        assert grad.dtype == torch.float32 and tuple(grad.shape) == (self.n, 3) and grad.is_contiguous()
+        if sum_rgb is not None:
+            assert sum_rgb.dtype == torch.float32 and tuple(sum_rgb.shape) == (H, W, 3) and sum_rgb.is_contiguous()
+        c = _camera(cam)
+        p = _render_params(params)
+        _check("ugp_render_albedo_grad", lib().ugp_render_albedo_grad(self.h, C.byref(c), C.byref(p), _ptr(d),
+                                                                      _ptr(grad), _ptr(sum_rgb)))
+        return grad
+
 
     def sync(self):
         _check("ugp_sync", lib().ugp_sync(self.h))

@@ -1,6 +1,7 @@
-"""torch.autograd functions over the library's two differentiable images:
-the accumulated free-flight CDF of each ray (Sec. 7.2, eq. accum_cdf) and
-the radiance-field image (Sec. 8, eq. rf).
+"""torch.autograd functions over the library's differentiable images: the
+accumulated free-flight CDF of each ray (Sec. 7.2, eq. accum_cdf), the
+radiance-field image (Sec. 8, eq. rf), and the path-traced image as a
+function of the primitives' albedo (its shading adjoint by path replay).
 
 The forward builds the hierarchy of the given parameters and renders with
 ugp_accum_cdf / ugp_rf_render; the backward is the library's
@@ -66,3 +67,38 @@ def rf_render(ugp, params: dict, rays, exclude=None):
     """Radiance per ray (float32 [n, 3], eq. rf), differentiable with respect
     to mean, scale, rotation, density and emission [P, 3]."""
     return _apply(ugp, params, rays, exclude, True)
+
+
+class _Render(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, ugp, cam, rparams, fixed, albedo):
+        scene = dict(fixed, albedo=albedo.detach())
+        ugp.build_bvh(scene)
+        spp = int(rparams.get("spp", 1))
+        s, _ = ugp.render(cam, dict(rparams, want_sumsq=False))
+        fctx.ugp, fctx.cam, fctx.rparams, fctx.fixed, fctx.build_id = ugp, cam, rparams, fixed, ugp.build_id
+        fctx.save_for_backward(albedo)
+        return s / spp
+
+    @staticmethod
+    def backward(fctx, g):
+        ugp = fctx.ugp
+        (albedo,) = fctx.saved_tensors
+        if ugp.build_id != fctx.build_id:
+            ugp.build_bvh(dict(fctx.fixed, albedo=albedo.detach()))
+            fctx.build_id = ugp.build_id
+        grad = torch.zeros((ugp.n, 3), device=ugp.device, dtype=torch.float32)
+        ugp.render_albedo_grad(fctx.cam, fctx.rparams, g.contiguous(), grad)
+        return None, None, None, None, grad
+
+
+def render(ugp, params: dict, cam: dict, render_params: dict):
+    """Mean path-traced image (float32 [H, W, 3], ugp_render's sum / spp),
+    differentiable with respect to params["albedo"] [P, 3] (the other scene
+    fields are held fixed); the backward is ugp_render_albedo_grad with the
+    same camera and render parameters (same seed: the exact derivative of
+    this estimate).  The radiance cache must be off."""
+    dev = ugp.device
+    albedo = torch.as_tensor(params["albedo"]).to(device=dev, dtype=torch.float32)
+    fixed = {k: params[k] for k in ("mean", "scale", "rotation", "density", "roughness", "emission", "material")}
+    return _Render.apply(ugp, cam, dict(render_params), fixed, albedo)

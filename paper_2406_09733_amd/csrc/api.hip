@@ -61,6 +61,31 @@ ugp_status vjp_args(ugp_ctx ctx, const ugp_scene *scene, int64_t n, const float 
     return UGP_OK;
 }
 
+// Shared argument checks of the render entry points.
+ugp_status render_args(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p) {
+    if (!ctx || !cam || !p) return UGP_ERR_INVALID_ARGUMENT;
+    if (cam->width < 1 || cam->height < 1 || (int64_t)cam->width * cam->height >= (int64_t(1) << 31) ||
+        !(cam->vfov_deg > 0.f && cam->vfov_deg < 180.f))
+        return UGP_ERR_INVALID_ARGUMENT;
+    if (p->spp < 1 || p->max_depth < 0 || p->max_depth > 1000 || p->mis_mode < 0 || p->mis_mode > 2 ||
+        p->sample_offset < 0 || p->sample_offset + p->spp > (int64_t(1) << 32))
+        return UGP_ERR_INVALID_ARGUMENT;
+    for (int c = 0; c < 3; ++c)
+        if (!(p->env_radiance[c] >= 0.f) || !std::isfinite(p->env_radiance[c])) return UGP_ERR_INVALID_ARGUMENT;
+    if (p->nrc_mode < 0 || p->nrc_mode > 3) return UGP_ERR_INVALID_ARGUMENT;
+    if (p->nrc_mode != 0 && p->nrc_terminate_after < 1) return UGP_ERR_INVALID_ARGUMENT;
+    if (p->nrc_mode == 1 && (p->nrc_train_records < 1 || p->nrc_train_records > (1 << 20)))
+        return UGP_ERR_INVALID_ARGUMENT;
+    if (!(p->nrc_lr >= 0.f) || !std::isfinite(p->nrc_lr)) return UGP_ERR_INVALID_ARGUMENT;
+    if (p->nrc_train_steps < 0 || p->nrc_train_steps > 64) return UGP_ERR_INVALID_ARGUMENT;
+    if (!(p->nrc_radiance_scale >= 0.f) || !std::isfinite(p->nrc_radiance_scale)) return UGP_ERR_INVALID_ARGUMENT;
+    if (!(p->nrc_target_clamp >= 0.f) || !std::isfinite(p->nrc_target_clamp)) return UGP_ERR_INVALID_ARGUMENT;
+    for (int k = 0; k < 6; ++k)
+        if (!std::isfinite(p->nrc_box[k])) return UGP_ERR_INVALID_ARGUMENT;
+    if (ctx->scene.n == 0) return UGP_ERR_NO_SCENE;
+    return UGP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -194,29 +219,24 @@ ugp_status ugp_trace_counts(ugp_ctx ctx, int mode, int64_t n, const float *rays,
 
 ugp_status ugp_render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p, float *sum,
                       float *sumsq) {
-    if (!ctx || !cam || !p || !sum) return UGP_ERR_INVALID_ARGUMENT;
-    if (cam->width < 1 || cam->height < 1 || (int64_t)cam->width * cam->height >= (int64_t(1) << 31) ||
-        !(cam->vfov_deg > 0.f && cam->vfov_deg < 180.f))
-        return UGP_ERR_INVALID_ARGUMENT;
-    if (p->spp < 1 || p->max_depth < 0 || p->max_depth > 1000 || p->mis_mode < 0 || p->mis_mode > 2 ||
-        p->sample_offset < 0 || p->sample_offset + p->spp > (int64_t(1) << 32))
-        return UGP_ERR_INVALID_ARGUMENT;
-    for (int c = 0; c < 3; ++c)
-        if (!(p->env_radiance[c] >= 0.f) || !std::isfinite(p->env_radiance[c])) return UGP_ERR_INVALID_ARGUMENT;
-    if (p->nrc_mode < 0 || p->nrc_mode > 3) return UGP_ERR_INVALID_ARGUMENT;
-    if (p->nrc_mode != 0 && p->nrc_terminate_after < 1) return UGP_ERR_INVALID_ARGUMENT;
-    if (p->nrc_mode == 1 && (p->nrc_train_records < 1 || p->nrc_train_records > (1 << 20)))
-        return UGP_ERR_INVALID_ARGUMENT;
-    if (!(p->nrc_lr >= 0.f) || !std::isfinite(p->nrc_lr)) return UGP_ERR_INVALID_ARGUMENT;
-    if (p->nrc_train_steps < 0 || p->nrc_train_steps > 64) return UGP_ERR_INVALID_ARGUMENT;
-    if (!(p->nrc_radiance_scale >= 0.f) || !std::isfinite(p->nrc_radiance_scale)) return UGP_ERR_INVALID_ARGUMENT;
-    if (!(p->nrc_target_clamp >= 0.f) || !std::isfinite(p->nrc_target_clamp)) return UGP_ERR_INVALID_ARGUMENT;
-    for (int k = 0; k < 6; ++k)
-        if (!std::isfinite(p->nrc_box[k])) return UGP_ERR_INVALID_ARGUMENT;
-    if (ctx->scene.n == 0) return UGP_ERR_NO_SCENE;
+    if (!sum) return UGP_ERR_INVALID_ARGUMENT;
+    const ugp_status s = render_args(ctx, cam, p);
+    if (s != UGP_OK) return s;
     DeviceGuard g(ctx->device);
     return from_hip(ugp::render(ctx, cam, p, sum, sumsq));
 }
+
+ugp_status ugp_render_albedo_grad(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p,
+                                  const float *d_image, float *grad_albedo, float *sum) {
+    if (!d_image || !grad_albedo) return UGP_ERR_INVALID_ARGUMENT;
+    const ugp_status s = render_args(ctx, cam, p);
+    if (s != UGP_OK) return s;
+    if (p->nrc_mode != 0) return UGP_ERR_UNSUPPORTED;
+    DeviceGuard g(ctx->device);
+    const ugp::RenderAdjoint adj{d_image, grad_albedo};
+    return from_hip(ugp::render(ctx, cam, p, sum, nullptr, &adj));
+}
+
 
 ugp_status ugp_exp_transmittance(ugp_ctx ctx, int64_t n, const float *rays, const int32_t *exclude, float *T_out) {
     if (!query_args_ok(ctx, n, rays) || (n > 0 && !T_out)) return UGP_ERR_INVALID_ARGUMENT;

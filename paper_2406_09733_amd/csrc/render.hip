@@ -94,6 +94,55 @@ struct NrcArgs {
     const float *frac;     // probability of a training path
 };
 
+// Albedo adjoint by path replay.  A chunk is traced twice with the same
+// random numbers: the forward pass leaves each path's radiance in its slot,
+// the replay subtracts every contribution as it is collected, so the slot
+// holds the radiance still to come.  A path term is linear in the albedo of
+// each vertex it scatters at (f is linear in it and no sampling decision
+// depends on it), so at a vertex the albedo's adjoint is dLoss/dL times the
+// radiance that passes through its scattering times (df/dalbedo)/f: the
+// continuation's remainder is known when the next vertex is shaded, the
+// light and environment samples' terms when they are collected.
+struct AdjArgs {
+    const float *dimg = nullptr;  // dLoss / d(mean image) [npix][3]; null: forward pass
+    float *grad = nullptr;        // [n_prims][3], original index, added to
+    float4 *aux_cont = nullptr;   // per slot: (albedo ratio of the continuation, primitive bits)
+    float4 *aux_nee = nullptr;    // per slot: the same for this vertex's light sample
+    float4 *aux_env = nullptr;    // per slot: the same for its environment sample
+    float inv_spp = 0.f;
+    uint32_t npix = 1;
+};
+
+__device__ __forceinline__ void adj_grad(const AdjArgs &A, int slot, int k, float x, float y, float z) {
+    const float *g = A.dimg + 3 * (int64_t)((uint32_t)slot % A.npix);
+    float *dst = A.grad + 3 * (int64_t)k;
+    const float gx = g[0] * A.inv_spp * x, gy = g[1] * A.inv_spp * y, gz = g[2] * A.inv_spp * z;
+    if (gx != 0.f) atomicAdd(dst, gx);
+    if (gy != 0.f) atomicAdd(dst + 1, gy);
+    if (gz != 0.f) atomicAdd(dst + 2, gz);
+}
+
+// radiance c * f collected by the path of `slot`: added in the forward pass
+// (one explicit fma per channel, the same in every kernel that collects, so
+// that the per-path sums do not depend on which kernel traced the path); in
+// the replay subtracted, and with aux (the collecting vertex's ratio and
+// primitive) its albedo adjoint added
+__device__ __forceinline__ void collect(const AdjArgs &A, float4 *L, int slot, float cx, float cy, float cz,
+                                        float f, const float4 *aux) {
+    float4 l = L[slot];
+    if (!A.dimg) {
+        l.x = fmaf(cx, f, l.x); l.y = fmaf(cy, f, l.y); l.z = fmaf(cz, f, l.z);
+        L[slot] = l;
+        return;
+    }
+    l.x = fmaf(-cx, f, l.x); l.y = fmaf(-cy, f, l.y); l.z = fmaf(-cz, f, l.z);
+    L[slot] = l;
+    if (aux) {
+        const float4 a = aux[slot];
+        adj_grad(A, slot, __float_as_int(a.w), a.x * (cx * f), a.y * (cy * f), a.z * (cz * f));
+    }
+}
+
 struct PassArgs {
     CamDev cam;
     float blo[3], binv[3];   // scene bounds (origin quantisation for ray sorting)
@@ -105,6 +154,7 @@ struct PassArgs {
     float env[3];
     int has_env;
     NrcArgs nrc;
+    AdjArgs adj;
 };
 
 constexpr int kPixMask = 0x3fffffff;
@@ -151,7 +201,7 @@ __global__ void k_regen(PassArgs P, int64_t pool, int64_t total, const int32_t *
     q.b[slot] = make_float4(d.x, d.y, d.z, __int_as_float(-1));
     q.c[slot] = make_float4(1.f, 1.f, 1.f, __int_as_float(bits));
     q.v[slot] = 1;
-    L[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (!P.adj.dimg) L[g] = make_float4(0.f, 0.f, 0.f, 0.f);  // the replay keeps the forward radiance
 }
 
 __global__ void k_regen_commit(int64_t pool, int64_t total, int32_t *cnt_in, int32_t *cnt_out, int32_t *chunk) {
@@ -328,7 +378,13 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
     V3 beta = f3(C);
     const Rng4 g0 = path_rng(P, (uint32_t)pix, (uint32_t)v, 0);
     const Rng4 g1 = path_rng(P, (uint32_t)pix, (uint32_t)v, 1);
-    V3 Ladd = v3(0.f, 0.f, 0.f);
+    if (P.adj.dimg && v >= 2) {
+        // replay: what is left to collect went through the previous vertex's continuation
+        const float4 a = P.adj.aux_cont[pix], R = L[pix];
+        adj_grad(P.adj, pix, __float_as_int(a.w), a.x * R.x, a.y * R.y, a.z * R.z);
+    }
+    V3 Lc = v3(0.f, 0.f, 0.f);  // radiance picked up here: Lw * Lc
+    float Lw = 0.f;
     if (hit.x < 0) {
         if (P.has_env) {
             float w = 1.f;
@@ -336,7 +392,8 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
                 if (P.mis_mode == 2) w = 0.f;
                 else if (P.mis_mode == 0) w = p_prev / (p_prev + 0.25f * kInvPi);
             }
-            Ladd = w * mul(beta, v3(P.env[0], P.env[1], P.env[2]));
+            Lc = mul(beta, v3(P.env[0], P.env[1], P.env[2]));
+            Lw = w;
         }
     } else {
         const int k = hit.x;
@@ -350,7 +407,8 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
                 if (P.mis_mode == 2) w = pn > 0.f ? 0.f : 1.f;
                 else if (P.mis_mode == 0) w = p_prev / (p_prev + pn);
             }
-            Ladd = w * mul(beta, Le);
+            Lc = mul(beta, Le);
+            Lw = w;
         }
         bool stop = false;
         if (v <= P.max_depth && P.nrc.mode != 0) {
@@ -368,7 +426,7 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
                 out.do_qry = P.nrc.mode != 3;
             } else if (train) {
                 const float4 l = L[pix];
-                out.r5 = make_float4(l.x + Ladd.x, l.y + Ladd.y, l.z + Ladd.z, (float)v);
+                out.r5 = make_float4(fmaf(Lc.x, Lw, l.x), fmaf(Lc.y, Lw, l.y), fmaf(Lc.z, Lw, l.z), (float)v);
                 out.do_rec = true;
             }
         }
@@ -413,6 +471,10 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
                         const float4 eL = S.cold[3 * e + 2];
                         const V3 wt = (w / pn) * mul(mul(beta, f), f3(eL));
                         out.do_nee = true;
+                        if (P.adj.dimg) {
+                            const V3 q = phase_albedo_ratio(mat, alb, wol, to_local(F, wl));
+                            P.adj.aux_nee[pix] = make_float4(q.x, q.y, q.z, __int_as_float(k));
+                        }
                         out.na = make_float4(x.x, x.y, x.z, __int_as_float(e));
                         out.nb = make_float4(wl.x, wl.y, wl.z, __int_as_float(k));
                         out.nc = make_float4(wt.x, wt.y, wt.z, __int_as_float(pix));
@@ -433,6 +495,10 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
                     const float w = P.mis_mode == 2 ? 1.f : pe / (pe + pph);
                     const V3 wt = (w / pe) * mul(mul(beta, f), v3(P.env[0], P.env[1], P.env[2]));
                     out.do_env = true;
+                    if (P.adj.dimg) {
+                        const V3 q = phase_albedo_ratio(mat, alb, wol, to_local(F, wl));
+                        P.adj.aux_env[pix] = make_float4(q.x, q.y, q.z, __int_as_float(k));
+                    }
                     out.ea = make_float4(x.x, x.y, x.z, 0.f);
                     out.eb = make_float4(wl.x, wl.y, wl.z, __int_as_float(k));
                     out.ec = make_float4(wt.x, wt.y, wt.z, __int_as_float(pix));
@@ -447,6 +513,10 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
                 if (nonzero(beta)) {
                     const V3 wi = to_world(F, wil);
                     out.cont = true;
+                    if (P.adj.dimg) {
+                        const V3 q = phase_albedo_ratio(mat, alb, wol, wil);
+                        P.adj.aux_cont[pix] = make_float4(q.x, q.y, q.z, __int_as_float(k));
+                    }
                     out.ca = make_float4(x.x, x.y, x.z, pdf);
                     out.cb = make_float4(wi.x, wi.y, wi.z, __int_as_float(k));
                     out.cc = make_float4(beta.x, beta.y, beta.z, __int_as_float(pbits));
@@ -454,11 +524,7 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
             }
         }
     }
-    if (Ladd.x != 0.f || Ladd.y != 0.f || Ladd.z != 0.f) {
-        float4 l = L[pix];
-        l.x += Ladd.x; l.y += Ladd.y; l.z += Ladd.z;
-        L[pix] = l;
-    }
+    if (Lw != 0.f && (Lc.x != 0.f || Lc.y != 0.f || Lc.z != 0.f)) collect(P.adj, L, pix, Lc.x, Lc.y, Lc.z, Lw, nullptr);
 }
 
 // Shading of every live path after its collision: emission pick-up (MIS
@@ -501,7 +567,7 @@ __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PassArgs P, Queue 
 template <int K, bool WIDE>
 __global__ __launch_bounds__(kBlock, 2) void k_light(SceneDev S, LightQueue q, const int32_t *n_in,
                                                   const int32_t *order, int32_t *work, float4 *L, int64_t *stats,
-                                                  Overflow ovf, uint32_t *err) {
+                                                  Overflow ovf, AdjArgs adj, uint32_t *err) {
     __shared__ int stack[kStackSize * kBlock];
     const int n = WIDE ? *ovf.count : *n_in;
     if (!WIDE && blockIdx.x == 0 && threadIdx.x == 0)
@@ -525,11 +591,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_light(SceneDev S, LightQueue q, c
             }
             return;
         }
-        if (so.t > 0.f) {
-            float4 l = L[pix];
-            l.x += C.x * so.t; l.y += C.y * so.t; l.z += C.z * so.t;
-            L[pix] = l;
-        }
+        if (so.t > 0.f) collect(adj, L, pix, C.x, C.y, C.z, so.t, adj.aux_nee);
     };
     if (WIDE) {
         for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock)
@@ -573,10 +635,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_light(SceneDev S, LightQueue q, c
                     ovf.idx[slot] = (int32_t)i;
                 } else if (so.t > 0.f) {
                     const float4 C = q.c[i];
-                    const int pix = __float_as_int(C.w);
-                    float4 l = L[pix];
-                    l.x += C.x * so.t; l.y += C.y * so.t; l.z += C.z * so.t;
-                    L[pix] = l;
+                    collect(adj, L, __float_as_int(C.w), C.x, C.y, C.z, so.t, adj.aux_nee);
                 }
                 i = -1;
             }
@@ -586,7 +645,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_light(SceneDev S, LightQueue q, c
 }
 
 __global__ __launch_bounds__(kBlock) void k_env(SceneDev S, LightQueue q, const int32_t *n_in, float4 *L,
-                                                int64_t *stats, uint32_t *err) {
+                                                int64_t *stats, AdjArgs adj, uint32_t *err) {
     __shared__ int stack[kStackSize * kBlock];
     const int n = *n_in;
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd((unsigned long long *)&stats[2], (unsigned long long)n);
@@ -597,11 +656,7 @@ __global__ __launch_bounds__(kBlock) void k_env(SceneDev S, LightQueue q, const 
         const RayD r = make_ray(A.x, A.y, A.z, B.x, B.y, B.z, 0.f, __builtin_huge_val());
         const float F = transmittance_F(S, r, excl, true, stack, err, tc);
         const float T = fmaxf(0.f, 1.f - F);
-        if (T > 0.f) {
-            float4 l = L[pix];
-            l.x += C.x * T; l.y += C.y * T; l.z += C.z * T;
-            L[pix] = l;
-        }
+        if (T > 0.f) collect(adj, L, pix, C.x, C.y, C.z, T, adj.aux_env);
     }
     flush_counts(S, tc);
 }
@@ -646,9 +701,9 @@ __device__ __forceinline__ SweepOut tail_sweep(const SceneDev &S, const RayD &r,
     return so;
 }
 
-__device__ __forceinline__ void add_radiance(float4 *L, int pix, float x, float y, float z) {
+__device__ __forceinline__ void add_radiance(float4 *L, int pix, float x, float y, float z, float f) {
     float4 l = L[pix];
-    l.x += x; l.y += y; l.z += z;
+    l.x = fmaf(x, f, l.x); l.y = fmaf(y, f, l.y); l.z = fmaf(z, f, l.z);  // as collect()
     L[pix] = l;
 }
 
@@ -715,13 +770,13 @@ __global__ __launch_bounds__(kBlock) void k_tail(SceneDev S, PassArgs P, Queue q
         const float f_nee = __shfl(f, jl + 32);
         if (!helper) {
             if (nee) {
-                if (f_nee > 0.f) add_radiance(L, __float_as_int(nc.w), nc.x * f_nee, nc.y * f_nee, nc.z * f_nee);
+                if (f_nee > 0.f) add_radiance(L, __float_as_int(nc.w), nc.x, nc.y, nc.z, f_nee);
                 nee = false;
             }
             if (env) {
                 const RayD er = make_ray(ea.x, ea.y, ea.z, eb.x, eb.y, eb.z, 0.f, __builtin_huge_val());
                 const float T = fmaxf(0.f, 1.f - transmittance_F(S, er, __float_as_int(eb.w), true, stack, err, tc));
-                if (T > 0.f) add_radiance(L, __float_as_int(ec.w), ec.x * T, ec.y * T, ec.z * T);
+                if (T > 0.f) add_radiance(L, __float_as_int(ec.w), ec.x, ec.y, ec.z, T);
                 env = false;
             }
             if (col) {
@@ -896,7 +951,8 @@ void make_cam_dev(const ugp_camera *cam, CamDev *out) {
                   (float)(u[0] * th), (float)(u[1] * th), (float)(u[2] * th), cam->width, cam->height};
 }
 
-hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p, float *sum, float *sumsq) {
+hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p, float *sum, float *sumsq,
+                  const RenderAdjoint *adj) {
     const SceneDev &S0 = ctx->scene;
     const int64_t npix = (int64_t)cam->width * cam->height;
     // chunks of `cs` samples of every pixel share the pool of path slots
@@ -907,6 +963,27 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
     if (e != hipSuccess) return e;
     RenderBuffers *rb = ctx->rb;
     hipStream_t st = ctx->stream;
+    // albedo adjoint: the replay's per-slot ratios (three float4 per radiance slot)
+    AdjArgs adjA;
+    float4 *aux = nullptr;
+    struct AuxFree {
+        float4 *&p;
+        hipStream_t s;
+        ~AuxFree() {
+            if (p) hipFreeAsync(p, s);
+        }
+    } aux_free{aux, st};
+    if (adj) {
+        e = hipMallocAsync((void **)&aux, sizeof(float4) * 3 * (size_t)lcap, st);
+        if (e != hipSuccess) return e;
+        adjA.dimg = adj->d_image;
+        adjA.grad = adj->grad;
+        adjA.aux_cont = aux;
+        adjA.aux_nee = aux + lcap;
+        adjA.aux_env = aux + 2 * lcap;
+        adjA.inv_spp = 1.f / (float)p->spp;
+        adjA.npix = (uint32_t)npix;
+    }
     PassArgs P;
     make_cam_dev(cam, &P.cam);
     for (int k = 0; k < 3; ++k) {
@@ -996,110 +1073,117 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
         P.sample = (uint32_t)(p->sample_offset + s0);
         const int ns = std::min(cs, p->spp - s0);
         const int64_t total = npix * ns;
-        e = hipMemsetAsync(rb->counts, 0, sizeof(int32_t) * (kChunkBlock + kCountStride), st);
-        if (e != hipSuccess) return e;
-        // iterations until every path of the chunk has ended; each path takes
-        // at most max_depth + 1 iterations once generated
-        const int64_t max_iter = (int64_t)(p->max_depth + 2) * (total / pool + 2);
-        int64_t it = 0;
-        int64_t left = 0, gen = 0;  // paths carried into this iteration, paths generated (host copies)
-        for (;; ++it) {
-            if (it > max_iter) return hipErrorUnknown;  // a path outlived its depth: internal error
-            int32_t *c = rb->counts + kCountStride * (it & 1);        // input queue's counters
-            int32_t *cn = rb->counts + kCountStride * ((it + 1) & 1); // output queue's counters
-            Queue qin = rb->q[it & 1], qout = rb->q[(it + 1) & 1];
-            Overflow ov{rb->ovf, c + 3};
-            // queue length of this iteration, known on the host: launches are sized to it
-            const int64_t n_new = std::min(pool - left, total - gen);
-            const int64_t n_it = left + n_new;
-            const unsigned gn = (unsigned)std::max<int64_t>(1, (n_it + 255) / 256);
-            const unsigned gq = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n_it + kBlock - 1) / kBlock,
-                                                                                  kPersistBlocks));
-            const bool sorted = n_it >= kSortMin;
-            const int32_t *order = sorted ? (const int32_t *)rb->sval : nullptr;
-            hipLaunchKernelGGL(k_regen, dim3((unsigned)std::max<int64_t>(1, (n_new + 255) / 256)), dim3(256), 0, st,
-                               P, pool, total, (const int32_t *)c, (const int32_t *)chunk_cnt, qin, rb->L);
-            hipLaunchKernelGGL(k_regen_commit, dim3(1), dim3(1), 0, st, pool, total, c, cn, chunk_cnt);
-            P.nrc.n_qry = c + 6;
-            if (it > 0 && n_new == 0 && n_it <= ctx->tail_paths) {
-                // few paths left and none to generate: they run to the end in one kernel
-                timed(8, [&] {
-                    hipLaunchKernelGGL(k_tail, dim3((unsigned)std::max<int64_t>(1, (n_it + 31) / 32)),
-                                       dim3(kBlock), 0, st, Sc[1], P, qin, (const int32_t *)c, rb->L, ctx->stats,
-                                       ctx->err);
-                });
-                if (p->nrc_mode == 1 || p->nrc_mode == 2) {
-                    timed(6, [&] {
-                        e = nrc_forward(ctx, n_it, c + 6, rb->qry, kNrcRecordFloats, 2, box, nullptr, rb->L,
-                                        nrc_scale);
+        // with an adjoint the chunk is traced twice: forward, then the replay
+        for (int pass = 0; pass < (adj ? 2 : 1); ++pass) {
+            P.adj = pass == 1 ? adjA : AdjArgs{};
+            e = hipMemsetAsync(rb->counts, 0, sizeof(int32_t) * (kChunkBlock + kCountStride), st);
+            if (e != hipSuccess) return e;
+            // iterations until every path of the chunk has ended; each path takes
+            // at most max_depth + 1 iterations once generated
+            const int64_t max_iter = (int64_t)(p->max_depth + 2) * (total / pool + 2);
+            int64_t it = 0;
+            int64_t left = 0, gen = 0;  // paths carried into this iteration, paths generated (host copies)
+            for (;; ++it) {
+                if (it > max_iter) return hipErrorUnknown;  // a path outlived its depth: internal error
+                int32_t *c = rb->counts + kCountStride * (it & 1);        // input queue's counters
+                int32_t *cn = rb->counts + kCountStride * ((it + 1) & 1); // output queue's counters
+                Queue qin = rb->q[it & 1], qout = rb->q[(it + 1) & 1];
+                Overflow ov{rb->ovf, c + 3};
+                // queue length of this iteration, known on the host: launches are sized to it
+                const int64_t n_new = std::min(pool - left, total - gen);
+                const int64_t n_it = left + n_new;
+                const unsigned gn = (unsigned)std::max<int64_t>(1, (n_it + 255) / 256);
+                const unsigned gq = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n_it + kBlock - 1) / kBlock,
+                                                                                      kPersistBlocks));
+                const bool sorted = n_it >= kSortMin;
+                const int32_t *order = sorted ? (const int32_t *)rb->sval : nullptr;
+                hipLaunchKernelGGL(k_regen, dim3((unsigned)std::max<int64_t>(1, (n_new + 255) / 256)), dim3(256), 0, st,
+                                   P, pool, total, (const int32_t *)c, (const int32_t *)chunk_cnt, qin, rb->L);
+                hipLaunchKernelGGL(k_regen_commit, dim3(1), dim3(1), 0, st, pool, total, c, cn, chunk_cnt);
+                P.nrc.n_qry = c + 6;
+                if (!adj && it > 0 && n_new == 0 && n_it <= ctx->tail_paths) {
+                    // few paths left and none to generate: they run to the end in one kernel
+                    timed(8, [&] {
+                        hipLaunchKernelGGL(k_tail, dim3((unsigned)std::max<int64_t>(1, (n_it + 31) / 32)),
+                                           dim3(kBlock), 0, st, Sc[1], P, qin, (const int32_t *)c, rb->L, ctx->stats,
+                                           ctx->err);
                     });
-                    if (e != hipSuccess) return e;
-                    hipLaunchKernelGGL(k_nrc_count, dim3(1), dim3(1), 0, st, (const int32_t *)(c + 6),
-                                       ctx->stats + 3);
+                    if (p->nrc_mode == 1 || p->nrc_mode == 2) {
+                        timed(6, [&] {
+                            e = nrc_forward(ctx, n_it, c + 6, rb->qry, kNrcRecordFloats, 2, box, nullptr, rb->L,
+                                            nrc_scale);
+                        });
+                        if (e != hipSuccess) return e;
+                        hipLaunchKernelGGL(k_nrc_count, dim3(1), dim3(1), 0, st, (const int32_t *)(c + 6),
+                                           ctx->stats + 3);
+                    }
+                    break;
                 }
-                break;
-            }
-            // order the queue so each wave's rays are coherent
-            if (sorted)
-                timed(5, [&] {
-                    hipLaunchKernelGGL(k_sort_keys, dim3(gn), dim3(256), 0, st, P, qin, (const int32_t *)c, n_it,
-                                       rb->skey, rb->sval);
-                    radix_sort(rb->skey, rb->sval, rb->skey2, rb->sval2, n_it, st);
-                });
-            timed(0, [&] {
-                hipLaunchKernelGGL((k_collide<kEventsMain, false>), dim3(gq), dim3(kBlock), 0, st, Sc[0], P, qin,
-                                   (const int32_t *)c, order, c + 4, rb->hits, ctx->stats, ov, ctx->err);
-            });
-            timed(1, [&] {
-                hipLaunchKernelGGL((k_collide<kEventsWide, true>), dim3(gw), dim3(kBlock), 0, st, Sc[1], P, qin,
-                                   (const int32_t *)c, order, c + 4, rb->hits, ctx->stats, ov, ctx->err);
-            });
-            timed(4, [&] {
-                hipLaunchKernelGGL(k_shade, dim3(gq), dim3(kBlock), 0, st, S, P, qin, (const int32_t *)c,
-                                   (const int2 *)rb->hits, qout, cn, rb->nee, c + 1, rb->env, c + 2, rb->L);
-            });
-            if (S.n_emit > 0 && p->mis_mode != 1) {
-                // light queue (at most n_it records) sorted like the path queue
+                // order the queue so each wave's rays are coherent
                 if (sorted)
                     timed(5, [&] {
-                        const Queue lq{rb->nee.a, rb->nee.b, rb->nee.c, nullptr};
-                        hipLaunchKernelGGL(k_sort_keys, dim3(gn), dim3(256), 0, st, P, lq, (const int32_t *)(c + 1),
-                                           n_it, rb->skey, rb->sval);
+                        hipLaunchKernelGGL(k_sort_keys, dim3(gn), dim3(256), 0, st, P, qin, (const int32_t *)c, n_it,
+                                           rb->skey, rb->sval);
                         radix_sort(rb->skey, rb->sval, rb->skey2, rb->sval2, n_it, st);
                     });
-                timed(2, [&] {
-                    hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, st, c + 3, 0);
-                    hipLaunchKernelGGL((k_light<kEventsMain, false>), dim3(gq), dim3(kBlock), 0, st, Sc[2], rb->nee,
-                                       (const int32_t *)(c + 1), order, c + 5, rb->L, ctx->stats, ov, ctx->err);
-                    hipLaunchKernelGGL((k_light<kEventsWide, true>), dim3(gw), dim3(kBlock), 0, st, Sc[2], rb->nee,
-                                       (const int32_t *)(c + 1), order, c + 5, rb->L, ctx->stats, ov, ctx->err);
+                timed(0, [&] {
+                    hipLaunchKernelGGL((k_collide<kEventsMain, false>), dim3(gq), dim3(kBlock), 0, st, Sc[0], P, qin,
+                                       (const int32_t *)c, order, c + 4, rb->hits, ctx->stats, ov, ctx->err);
                 });
-            }
-            if (P.has_env && p->mis_mode != 1)
-                timed(3, [&] {
-                    hipLaunchKernelGGL(k_env, dim3(gq), dim3(kBlock), 0, st, Sc[3], rb->env,
-                                       (const int32_t *)(c + 2), rb->L, ctx->stats, ctx->err);
+                timed(1, [&] {
+                    hipLaunchKernelGGL((k_collide<kEventsWide, true>), dim3(gw), dim3(kBlock), 0, st, Sc[1], P, qin,
+                                       (const int32_t *)c, order, c + 4, rb->hits, ctx->stats, ov, ctx->err);
                 });
-            if (p->nrc_mode == 1 || p->nrc_mode == 2) {
-                // cached radiance of the paths that ended in the cache this iteration
-                timed(6, [&] {
-                    e = nrc_forward(ctx, n_it, c + 6, rb->qry, kNrcRecordFloats, 2, box, nullptr, rb->L, nrc_scale);
+                timed(4, [&] {
+                    hipLaunchKernelGGL(k_shade, dim3(gq), dim3(kBlock), 0, st, S, P, qin, (const int32_t *)c,
+                                       (const int2 *)rb->hits, qout, cn, rb->nee, c + 1, rb->env, c + 2, rb->L);
                 });
+                if (S.n_emit > 0 && p->mis_mode != 1) {
+                    // light queue (at most n_it records) sorted like the path queue
+                    if (sorted)
+                        timed(5, [&] {
+                            const Queue lq{rb->nee.a, rb->nee.b, rb->nee.c, nullptr};
+                            hipLaunchKernelGGL(k_sort_keys, dim3(gn), dim3(256), 0, st, P, lq, (const int32_t *)(c + 1),
+                                               n_it, rb->skey, rb->sval);
+                            radix_sort(rb->skey, rb->sval, rb->skey2, rb->sval2, n_it, st);
+                        });
+                    timed(2, [&] {
+                        hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, st, c + 3, 0);
+                        hipLaunchKernelGGL((k_light<kEventsMain, false>), dim3(gq), dim3(kBlock), 0, st, Sc[2], rb->nee,
+                                           (const int32_t *)(c + 1), order, c + 5, rb->L, ctx->stats, ov, P.adj,
+                                           ctx->err);
+                        hipLaunchKernelGGL((k_light<kEventsWide, true>), dim3(gw), dim3(kBlock), 0, st, Sc[2], rb->nee,
+                                           (const int32_t *)(c + 1), order, c + 5, rb->L, ctx->stats, ov, P.adj,
+                                           ctx->err);
+                    });
+                }
+                if (P.has_env && p->mis_mode != 1)
+                    timed(3, [&] {
+                        hipLaunchKernelGGL(k_env, dim3(gq), dim3(kBlock), 0, st, Sc[3], rb->env,
+                                           (const int32_t *)(c + 2), rb->L, ctx->stats, P.adj, ctx->err);
+                    });
+                if (p->nrc_mode == 1 || p->nrc_mode == 2) {
+                    // cached radiance of the paths that ended in the cache this iteration
+                    timed(6, [&] {
+                        e = nrc_forward(ctx, n_it, c + 6, rb->qry, kNrcRecordFloats, 2, box, nullptr, rb->L, nrc_scale);
+                    });
+                    if (e != hipSuccess) return e;
+                    hipLaunchKernelGGL(k_nrc_count, dim3(1), dim3(1), 0, st, (const int32_t *)(c + 6), ctx->stats + 3);
+                }
+                // continue while paths remain in the next queue or wait to be generated
+                e = hipMemcpyAsync(rb->host, cn, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(rb->host + 1, chunk_cnt, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+                if (e == hipSuccess) e = hipStreamSynchronize(st);
                 if (e != hipSuccess) return e;
-                hipLaunchKernelGGL(k_nrc_count, dim3(1), dim3(1), 0, st, (const int32_t *)(c + 6), ctx->stats + 3);
+                left = rb->host[0];
+                gen = rb->host[1];
+                if (left == 0 && gen >= total) break;
             }
-            // continue while paths remain in the next queue or wait to be generated
-            e = hipMemcpyAsync(rb->host, cn, sizeof(int32_t), hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(rb->host + 1, chunk_cnt, sizeof(int32_t), hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess) e = hipStreamSynchronize(st);
-            if (e != hipSuccess) return e;
-            left = rb->host[0];
-            gen = rb->host[1];
-            if (left == 0 && gen >= total) break;
+            if (pass == 0 && sum)
+                hipLaunchKernelGGL(k_accum, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, st, npix, ns, rb->L,
+                                   sum, sumsq);
         }
-        hipLaunchKernelGGL(k_accum, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, st, npix, ns, rb->L, sum,
-                           sumsq);
         if (p->nrc_mode == 1) {
             // targets of this chunk's records, the optimisation steps, new training-path probability
             timed(7, [&] {

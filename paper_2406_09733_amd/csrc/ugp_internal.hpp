@@ -109,8 +109,14 @@ hipError_t launch_exp(ugp_ctx ctx, int64_t n, const float *rays, const int32_t *
                       float *T, int32_t *prim_out, float *t_out);
 
 // render.hip
-hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p, float *sum,
-                  float *sumsq);
+// Albedo adjoint of a render (path replay): d_image = dLoss/d(mean image)
+// [h][w][3]; grad [n][3] += dLoss/dalbedo by original index.
+struct RenderAdjoint {
+    const float *d_image;
+    float *grad;
+};
+hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p, float *sum, float *sumsq,
+                  const RenderAdjoint *adj = nullptr);
 struct CamDev;
 // the device camera (origin, forward, right and up scaled to the field of view)
 void make_cam_dev(const ugp_camera *cam, CamDev *out);

@@ -127,6 +127,20 @@ __device__ inline V3 phase_eval_local(int mat, V3 alb, float rough, V3 wo, V3 wi
               (alb.z + (1.f - alb.z) * sch) * k);
 }
 
+// (d f_c / d albedo_c) / f_c of the phase function above, per channel, for
+// the pair (wo, wi): f is linear in the albedo -- the diffuse lobe is
+// albedo/pi cos_i, the glossy lobe's Schlick term is F0 + (1 - F0) m with
+// m = (1 - wi.h)^5 -- so a path term's derivative is the term times this
+// ratio.  A channel whose f is zero (a diffuse one of zero albedo) reports 0.
+__device__ inline V3 phase_albedo_ratio(int mat, V3 alb, V3 wo, V3 wi) {
+    auto r = [](float num, float den) __attribute__((always_inline)) { return den > 0.f ? num / den : 0.f; };
+    if (mat == 0) return v3(r(1.f, alb.x), r(1.f, alb.y), r(1.f, alb.z));
+    const V3 h = normalize(wo + wi);
+    const float m = pow5(1.f - fmaxf(0.f, dot(wi, h)));
+    return v3(r(1.f - m, alb.x + (1.f - alb.x) * m), r(1.f - m, alb.y + (1.f - alb.y) * m),
+              r(1.f - m, alb.z + (1.f - alb.z) * m));
+}
+
 // local frame sample: returns wi, weight f/pdf; pdf 0 = no sample
 __device__ inline V3 phase_sample_local(int mat, V3 alb, float rough, V3 wo, float u1, float u2,
                                         V3 &wgt, float &pdf) {

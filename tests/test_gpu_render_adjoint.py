@@ -1,0 +1,188 @@
+"""GPU tests of the albedo adjoint of the path tracer (ugp_render_albedo_grad,
+path replay): against central differences of the GPU's own render with the
+same random numbers (no sampling decision depends on the albedo, so the
+image is a polynomial in each primitive's albedo and the difference is
+exact up to float rounding), against FP64 central differences of the
+oracle's render, through the autograd function, and an albedo fit.
+
+Tolerances:
+  vs GPU differences     |g.u - fd| <= 2e-3 |g| + 2e-4 |loss| / h   (float sums
+                          of the two images; h the step)
+  vs oracle differences  |g.u - fd| <= 3e-2 |g| + 2e-5               (FP64 paths may
+                          take another decision than float ones near a margin)
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2406_09733_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    import paper_2406_09733_amd as P
+    return P.Context(0)
+
+
+def _scene():
+    sc = scenes.tiny_random(seed=3)
+    rng = np.random.default_rng(12)
+    n = sc["mean"].shape[0]
+    sc["material"] = (rng.uniform(0, 1, n) < 0.5).astype(np.int32)  # half glossy
+    sc["roughness"] = rng.uniform(0.1, 1.0, n).astype(np.float32)
+    sc["density"] = (np.asarray(sc["density"]) * 6.0).astype(np.float32)
+    return sc
+
+
+CAM = dict(scenes.camera("tiny_random"), width=48, height=48)
+PARAMS = {"spp": 4, "max_depth": 4, "seed": 9, "env_radiance": (0.3, 0.3, 0.3)}
+
+
+def _weights(seed=2):
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, (48, 48, 3)).astype(np.float32)
+
+
+def _gpu_loss(ctx, torch, sc, w):
+    ctx.build_bvh(sc)
+    s, _ = ctx.render(CAM, dict(PARAMS, want_sumsq=False))
+    ctx.sync()
+    img = s.cpu().numpy().astype(np.float64) / PARAMS["spp"]
+    return float(np.sum(w.astype(np.float64) * img))
+
+
+def _grad(ctx, torch, sc, w):
+    ctx.build_bvh(sc)
+    g = torch.zeros((sc["mean"].shape[0], 3), device="cuda", dtype=torch.float32)
+    s = torch.zeros((48, 48, 3), device="cuda", dtype=torch.float32)
+    ctx.render_albedo_grad(CAM, PARAMS, torch.tensor(w, device="cuda"), g, s)
+    ctx.sync()
+    return g.cpu().numpy().astype(np.float64), s.cpu().numpy()
+
+
+def _probe_prims(g, k=8, seed=0):
+    mag = np.abs(g).sum(1)
+    top = list(np.argsort(-mag)[:6])
+    rest = np.where(mag > 0)[0]
+    rng = np.random.default_rng(seed)
+    return top + [int(x) for x in rng.choice(np.setdiff1d(rest, top), 2, replace=False)]
+
+
+def test_albedo_gradient_vs_gpu_differences(ctx, torch):
+    _say("albedo adjoint vs central differences of the GPU render (same random numbers)")
+    sc = _scene()
+    w = _weights()
+    g, s = _grad(ctx, torch, sc, w)
+    s_ref, _ = ctx.render(CAM, dict(PARAMS, want_sumsq=False))
+    ctx.sync()
+    assert np.array_equal(s, s_ref.cpu().numpy())  # the forward pass is ugp_render's
+    L0 = _gpu_loss(ctx, torch, sc, w)
+    rng = np.random.default_rng(1)
+    h = 0.02
+    for k in _probe_prims(g):
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        vals = []
+        for sgn in (1, -1):
+            s2 = dict(sc)
+            a = np.asarray(sc["albedo"], np.float32).copy()
+            a[k] = (a[k] + sgn * h * u).astype(np.float32)
+            s2["albedo"] = a
+            vals.append(_gpu_loss(ctx, torch, s2, w))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        gu = float(g[k] @ u)
+        tol = 2e-3 * np.linalg.norm(g[k]) + 2e-4 * abs(L0) / h
+        _say(f"  prim {k} (material {int(sc['material'][k])}): g.u {gu:.6e} fd {fd:.6e} |diff| {abs(gu - fd):.2e}"
+             f" tol {tol:.2e}")
+        assert abs(gu - fd) <= tol
+
+
+def test_albedo_gradient_vs_oracle_differences(ctx, orc, torch):
+    _say("albedo adjoint vs FP64 central differences of the oracle's render")
+    sc = _scene()
+    w = _weights(3)
+    g, _ = _grad(ctx, torch, sc, w)
+
+    def oracle_loss(s2):
+        s, _, _ = orc.Scene(s2).render(CAM, PARAMS)
+        return float(np.sum(w.reshape(-1, 3).astype(np.float64) * s / PARAMS["spp"]))
+
+    rng = np.random.default_rng(4)
+    h = 0.02
+    for k in _probe_prims(g, seed=1)[:6]:
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        vals = []
+        for sgn in (1, -1):
+            s2 = dict(sc)
+            a = np.asarray(sc["albedo"], np.float64).copy()
+            a[k] = a[k] + sgn * h * u
+            s2["albedo"] = a.astype(np.float32)
+            vals.append((a[k].astype(np.float32).astype(np.float64), oracle_loss(s2)))
+        # the quotient along the float32 albedos actually used
+        du = vals[0][0] - vals[1][0]
+        fd = (vals[0][1] - vals[1][1])
+        gu = float(g[k] @ du)
+        _say(f"  prim {k}: g.du {gu:.6e} oracle difference {fd:.6e}")
+        assert abs(gu - fd) <= 3e-2 * np.linalg.norm(g[k]) * np.linalg.norm(du) + 2e-5
+
+
+def test_autograd_render_and_albedo_fit(ctx, torch):
+    from paper_2406_09733_amd import autograd as A
+    _say("autograd render: fit albedos to an image")
+    sc = _scene()
+    truth = {k: torch.tensor(np.asarray(v), device="cuda") for k, v in sc.items() if k != "bounds"}
+    # common random numbers: the target and every iterate use the same seed,
+    # so the loss measures the albedo error alone (no Monte Carlo floor)
+    rp = dict(PARAMS, spp=8, seed=50)
+    target = A.render(ctx, truth, CAM, rp).detach()
+    rng = np.random.default_rng(6)
+    a0 = np.clip(np.asarray(sc["albedo"]) + rng.uniform(-0.3, 0.3, (sc["mean"].shape[0], 3)), 0.05, 0.95)
+    params = dict(truth)
+    params["albedo"] = torch.tensor(a0.astype(np.float32), device="cuda", requires_grad=True)
+    opt = torch.optim.Adam([params["albedo"]], lr=0.03)
+    losses = []
+    for it in range(40):
+        img = A.render(ctx, params, CAM, rp)
+        loss = ((img - target) ** 2).mean()
+        opt.zero_grad()
+        loss.backward()
+        opt.step()
+        with torch.no_grad():
+            params["albedo"].clamp_(0.01, 0.99)
+        losses.append(float(loss.item()))
+    _say(f"  image loss {losses[0]:.4e} -> {np.mean(losses[-5:]):.4e}")
+    assert np.mean(losses[-5:]) < 0.05 * losses[0]
+    # the primitives that the image sees most recover their albedo
+    g, _ = _grad(ctx, torch, sc, np.ones((48, 48, 3), np.float32))
+    seen = np.argsort(-np.abs(g).sum(1))[:20]
+    err0 = np.abs(a0[seen] - np.asarray(sc["albedo"])[seen]).mean()
+    err1 = np.abs(params["albedo"].detach().cpu().numpy()[seen] - np.asarray(sc["albedo"])[seen]).mean()
+    _say(f"  albedo error of the 20 most visible primitives {err0:.3f} -> {err1:.3f}")
+    assert err1 < 0.5 * err0
+
+
+def test_albedo_gradient_rejects_the_cache(ctx, torch):
+    import paper_2406_09733_amd as P
+    sc = _scene()
+    ctx.build_bvh(sc)
+    g = torch.zeros((sc["mean"].shape[0], 3), device="cuda", dtype=torch.float32)
+    d = torch.zeros((48, 48, 3), device="cuda", dtype=torch.float32)
+    with pytest.raises(P.UGPError) as e:
+        ctx.render_albedo_grad(CAM, dict(PARAMS, nrc_mode=3), d, g)
+    assert e.value.code == 5
