@@ -372,6 +372,47 @@ def rf_render_bench(args):
     print(json.dumps(res), flush=True)
 
 
+def albedo_grad_bench(args):
+    """Cost of the albedo adjoint (ugp_render_albedo_grad, path replay)
+    against the plain render it differentiates: the 100K mixed scene, one
+    view of 256x256 at 64 spp, depth 8 (the differentiable-fitting
+    workload's view).  Prints one JSON line: ms per render, ms per adjoint
+    (forward + replay), and camera paths/s of the adjoint."""
+    import numpy as np
+    import torch
+
+    import paper_2406_09733_amd as P
+    from paper_2406_09733_amd import scenes
+
+    sc = scenes.mixed_100k()
+    cam = dict(scenes.camera("mixed_100k"), width=256, height=256)
+    rp = {"spp": 64, "max_depth": 8, "seed": 5, "env_radiance": (0.2, 0.2, 0.2), "want_sumsq": False}
+    ctx = P.Context(0)
+    ctx.build_bvh(sc)
+    d = torch.tensor(np.random.default_rng(1).uniform(-1, 1, (256, 256, 3)).astype(np.float32), device="cuda")
+    g = torch.zeros((sc["mean"].shape[0], 3), device="cuda", dtype=torch.float32)
+    ctx.render(cam, rp)
+    ctx.render_albedo_grad(cam, rp, d, g)
+    ctx.sync()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.render(cam, rp)
+    ctx.sync()
+    t_fwd = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.render_albedo_grad(cam, rp, d, g)
+    ctx.sync()
+    t_adj = (time.perf_counter() - t0) / reps
+    paths = 256 * 256 * rp["spp"]
+    res = {"metric": "albedo adjoint (path replay) ms per 256x256 view at 64 spp, 100K mixed scene",
+           "value": round(1e3 * t_adj, 2), "unit": "ms", "higher_is_better": False,
+           "render_ms": round(1e3 * t_fwd, 2), "adjoint_over_render": round(t_adj / t_fwd, 3),
+           "adjoint_paths_per_s": round(paths / t_adj, 1), "depth": rp["max_depth"], "spp": rp["spp"]}
+    print(json.dumps(res), flush=True)
+
+
 def query_bench(args):
     """Per-ray query rates on the room (5.5M primitives): linear-model
     transmittance and free-flight sampling (the ordered sweep) against the
@@ -442,6 +483,7 @@ def main():
     ap.add_argument("--fit", action="store_true", help="run the transmittance-optimisation benchmark instead")
     ap.add_argument("--rf", action="store_true", help="run the radiance-field rendering benchmark instead")
     ap.add_argument("--queries", action="store_true", help="run the per-ray query benchmark instead")
+    ap.add_argument("--albedo-grad", action="store_true", help="run the albedo-adjoint benchmark instead")
     ap.add_argument("--rf-frames", type=int, default=40)
     ap.add_argument("--fit-steps", type=int, default=50)
     ap.add_argument("--fit-lr", default="5e-5,1e-2,2e-3,1e-2",
@@ -468,6 +510,9 @@ def main():
         return
     if args.queries:
         query_bench(args)
+        return
+    if args.albedo_grad:
+        albedo_grad_bench(args)
         return
 
     import numpy as np
