@@ -326,7 +326,8 @@ def transmittance_fit(args):
     lr = tuple(float(x) for x in args.fit_lr.split(","))
     fit.fit_transmittance(ctx, warm, cams, target, iters=1, lr=lr)
     out = fit.fit_transmittance(ctx, params, cams, target, iters=args.fit_steps, lr=lr,
-                                on_step=lambda it: log(f"[fit] step {it}") if it % 10 == 0 else None)
+                                on_step=lambda it: log(f"[fit] step {it}") if it % 10 == 0 else None,
+                                rebuild_every=args.fit_rebuild_every)
     ls = out["loss"]
     rays = args.fit_steps * sum(c["width"] * c["height"] for c in cams)
     res = {"metric": "transmittance-fit steps/s (Sec. 7.2) on the 100K mixed scene",
@@ -334,6 +335,7 @@ def transmittance_fit(args):
            "ms_per_step": round(1e3 * out["seconds"] / args.fit_steps, 2),
            "rays_per_s": round(rays / out["seconds"], 1), "primitives": n, "views": len(cams),
            "resolution": "256x256", "steps": args.fit_steps, "lr_mean_logscale_rotation_density": lr,
+           "rebuild_every": args.fit_rebuild_every,
            "loss_first": ls[0], "loss_last": ls[-1], "loss_ratio": round(ls[-1] / ls[0], 4),
            "loss_curve": [round(x, 7) for x in ls[:: max(1, len(ls) // 20)]]}
     print(json.dumps(res), flush=True)
@@ -486,6 +488,8 @@ def main():
     ap.add_argument("--albedo-grad", action="store_true", help="run the albedo-adjoint benchmark instead")
     ap.add_argument("--rf-frames", type=int, default=40)
     ap.add_argument("--fit-steps", type=int, default=50)
+    ap.add_argument("--fit-rebuild-every", type=int, default=1,
+                    help="new hierarchy every N fit steps, refitted in between (1: rebuild every step)")
     ap.add_argument("--fit-lr", default="5e-5,1e-2,2e-3,1e-2",
                     help="Adam rates of the means, log scales, rotations and densities")
     ap.add_argument("--exposure", type=float, default=0.0,

@@ -142,6 +142,21 @@ ugp_status ugp_set_stream(ugp_ctx ctx, void *hip_stream);
  * Synchronises the stream once (to size the tree).  n >= 1. */
 ugp_status ugp_build_bvh(ugp_ctx ctx, const ugp_scene *scene, float cutoff_eps);
 
+/* New parameters for the same n primitives without a new hierarchy: the
+ * records are packed again and every box of the built hierarchy is refitted
+ * bottom-up, keeping its topology and the slab layout of each primitive (cut
+ * primitives keep their slab count and axis, which still cover the new
+ * ellipsoid).  Queries and renders then give the new scene's results; only
+ * the hierarchy's quality (node visits per ray) can degrade as primitives
+ * move, so a caller rebuilds from time to time.  For optimisation loops that
+ * move primitives a little per step (Sec. 7.2 rebuilds its structure every
+ * iteration).  scene->n must equal the built scene's n
+ * (UGP_ERR_INVALID_ARGUMENT); invalid parameters (as ugp_build_bvh) return
+ * UGP_ERR_INVALID_ARGUMENT and leave the scene unchanged; UGP_ERR_NO_SCENE
+ * before a build.  The emitter list and the scene bounds are updated.
+ * Synchronises the stream (validation, emitter count). */
+ugp_status ugp_refit_bvh(ugp_ctx ctx, const ugp_scene *scene);
+
 /* Transmittance along each ray (Sec. 4 eq. transmittance, Sec. 5.3):
  * F = 1/2 sum_k I_k(a_k, b_k) over every primitive k != exclude[i] whose
  * cut-off ellipsoid meets [t0, t1] in the chord [a_k, b_k], with I_k the

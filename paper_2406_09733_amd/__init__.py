@@ -73,7 +73,7 @@ class _Stats(C.Structure):
                 ("ms_nrc_train", C.c_double), ("nrc_loss", C.c_float), ("ms_tail", C.c_double)]
 
 
-EXPORTS = ["ugp_create", "ugp_destroy", "ugp_set_stream", "ugp_build_bvh", "ugp_transmittance",
+EXPORTS = ["ugp_create", "ugp_destroy", "ugp_set_stream", "ugp_build_bvh", "ugp_refit_bvh", "ugp_transmittance",
            "ugp_sample_collision", "ugp_saturation", "ugp_emitter_query", "ugp_render", "ugp_render_albedo_grad", "ugp_sync",
            "ugp_set_profiling", "ugp_set_path_pool", "ugp_set_tail_paths", "ugp_get_render_stats", "ugp_trace_counts", "ugp_status_string",
            "ugp_nrc_num_params", "ugp_nrc_set_weights", "ugp_nrc_get_weights", "ugp_nrc_encode",
@@ -94,6 +94,7 @@ def lib():
         L.ugp_destroy.argtypes = [vp]
         L.ugp_set_stream.argtypes = [vp, vp]
         L.ugp_build_bvh.argtypes = [vp, C.POINTER(_Scene), C.c_float]
+        L.ugp_refit_bvh.argtypes = [vp, C.POINTER(_Scene)]
         L.ugp_transmittance.argtypes = [vp, i64, vp, vp, vp, vp]
         L.ugp_sample_collision.argtypes = [vp, i64, vp, vp, vp, vp, vp]
         L.ugp_saturation.argtypes = [vp, i64, vp, vp, vp]
@@ -199,6 +200,15 @@ class Context:
     # ---- scene -----------------------------------------------------------
     def build_bvh(self, scene: dict, cutoff_eps: float = 0.01):
         """ugp_build_bvh: pack the primitives and build the hierarchy."""
+        return self._scene_call(scene, lambda s: ("ugp_build_bvh", lib().ugp_build_bvh(self.h, C.byref(s),
+                                                                                        float(cutoff_eps))))
+
+    def refit_bvh(self, scene: dict):
+        """ugp_refit_bvh: new parameters for the built scene's primitives (same
+        n), the hierarchy refitted in its topology."""
+        return self._scene_call(scene, lambda s: ("ugp_refit_bvh", lib().ugp_refit_bvh(self.h, C.byref(s))))
+
+    def _scene_call(self, scene: dict, call):
         torch = self.torch
         n = int(np.asarray(scene["mean"]).shape[0]) if not torch.is_tensor(scene["mean"]) else scene["mean"].shape[0]
         t = {
@@ -213,7 +223,7 @@ class Context:
         }
         s = _Scene(n, *[t[k].data_ptr() for k in ("mean", "scale", "rotation", "density", "albedo",
                                                   "roughness", "emission", "material")])
-        _check("ugp_build_bvh", lib().ugp_build_bvh(self.h, C.byref(s), float(cutoff_eps)))
+        _check(*call(s))
         self.n = n
         self._scene_t, self._scene_s = t, s  # the parameters the hierarchy was built from
         self.build_id = getattr(self, "build_id", 0) + 1

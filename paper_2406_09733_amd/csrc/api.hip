@@ -159,6 +159,17 @@ ugp_status ugp_build_bvh(ugp_ctx ctx, const ugp_scene *s, float eps) {
     return from_hip(ugp::build_scene(ctx, s, eps));
 }
 
+ugp_status ugp_refit_bvh(ugp_ctx ctx, const ugp_scene *s) {
+    if (!ctx || !s) return UGP_ERR_INVALID_ARGUMENT;
+    if (!s->mean || !s->scale || !s->rotation || !s->density || !s->albedo || !s->roughness ||
+        !s->emission || !s->material)
+        return UGP_ERR_INVALID_ARGUMENT;
+    if (ctx->scene.n == 0) return UGP_ERR_NO_SCENE;
+    if (s->n != ctx->scene.n) return UGP_ERR_INVALID_ARGUMENT;
+    DeviceGuard g(ctx->device);
+    return from_hip(ugp::refit_scene(ctx, s));
+}
+
 ugp_status ugp_transmittance(ugp_ctx ctx, int64_t n, const float *rays, const int32_t *exclude, float *T,
                              float *F) {
     if (!query_args_ok(ctx, n, rays) || (n > 0 && !T)) return UGP_ERR_INVALID_ARGUMENT;

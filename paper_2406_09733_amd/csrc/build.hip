@@ -299,6 +299,26 @@ __global__ void k_pack(PackIn in, float *boxes, float4 *cold_tmp, float *mtmp, u
 // sqrt(r^2 - min y_L^2) spanned by A_a, A_b (A = R S), widened by a small
 // margin so that a chord entry computed with the float M falls inside the
 // box of the slab that owns it; it is clipped to the whole box.
+__device__ __forceinline__ void slab_box(const PackIn &in, int64_t k, const double R[3][3], int i, int m, int L,
+                                         const float *boxes, float *out) {
+    const double s[3] = {in.scale[3 * k], in.scale[3 * k + 1], in.scale[3 * k + 2]};
+    const int a = (L + 1) % 3, b = (L + 2) % 3;
+    const double r = in.r * (1.0 + 1e-5), dl = 1e-4 * in.r;
+    const double v0 = fmax(-r, -in.r + 2.0 * in.r * i / m - dl);
+    const double v1 = fmin(r, -in.r + 2.0 * in.r * (i + 1) / m + dl);
+    const double rho = (v0 <= 0.0 && v1 >= 0.0) ? r : sqrt(fmax(0.0, r * r - fmin(v0 * v0, v1 * v1)));
+    for (int d = 0; d < 3; ++d) {
+        const double mu = in.mean[3 * k + d];
+        const double AL = R[d][L] * s[L], Aa = R[d][a] * s[a], Ab = R[d][b] * s[b];
+        const double c0 = AL * v0, c1 = AL * v1;
+        const double cs = rho * sqrt(Aa * Aa + Ab * Ab);
+        const double lo = fmax(mu + fmin(c0, c1) - cs, (double)boxes[6 * k + d]);
+        const double hi = fmin(mu + fmax(c0, c1) + cs, (double)boxes[6 * k + 3 + d]);
+        out[d] = round_down(lo);
+        out[3 + d] = round_up(hi);
+    }
+}
+
 __global__ void k_refs(PackIn in, const int32_t *pieces, const int32_t *roff, const float *boxes, float *rbox,
                        int32_t *rprim, int32_t *rinfo) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -317,23 +337,9 @@ __global__ void k_refs(PackIn in, const int32_t *pieces, const int32_t *roff, co
     int L = 0;
     if (s[1] > s[L]) L = 1;
     if (s[2] > s[L]) L = 2;
-    const int a = (L + 1) % 3, b = (L + 2) % 3;
-    const double r = in.r * (1.0 + 1e-5), dl = 1e-4 * in.r;
     for (int i = 0; i < m; ++i) {
-        const double v0 = fmax(-r, -in.r + 2.0 * in.r * i / m - dl);
-        const double v1 = fmin(r, -in.r + 2.0 * in.r * (i + 1) / m + dl);
-        const double rho = (v0 <= 0.0 && v1 >= 0.0) ? r : sqrt(fmax(0.0, r * r - fmin(v0 * v0, v1 * v1)));
         const int64_t j = j0 + i;
-        for (int d = 0; d < 3; ++d) {
-            const double mu = in.mean[3 * k + d];
-            const double AL = R[d][L] * s[L], Aa = R[d][a] * s[a], Ab = R[d][b] * s[b];
-            const double c0 = AL * v0, c1 = AL * v1;
-            const double cs = rho * sqrt(Aa * Aa + Ab * Ab);
-            const double lo = fmax(mu + fmin(c0, c1) - cs, (double)boxes[6 * k + d]);
-            const double hi = fmin(mu + fmax(c0, c1) + cs, (double)boxes[6 * k + 3 + d]);
-            rbox[6 * j + d] = round_down(lo);
-            rbox[6 * j + 3 + d] = round_up(hi);
-        }
+        slab_box(in, k, R, i, m, L, boxes, rbox + 6 * j);
         rprim[j] = (int32_t)k;
         rinfo[j] = i | (m << 8) | (L << 16);
     }
@@ -588,6 +594,17 @@ __global__ void k_collapse_greedy(const float4 *nodes, const int32_t *fin, const
 
 // hot record of leaf i (reference sorted_ref[i]); inv[o] = the leaf of the
 // first slab of primitive o
+// the hot record of a leaf: primitive o, slab info (slab | count << 8 | long axis << 16)
+__device__ __forceinline__ void write_hot(const PackIn &in, const float *mtmp, int64_t o, int info, float4 *h) {
+    const float *M = mtmp + 9 * o;
+    h[0] = make_float4(in.mean[3 * o], in.mean[3 * o + 1], in.mean[3 * o + 2], in.dens[o]);
+    h[1] = make_float4(M[0], M[1], M[2], M[3]);
+    h[2] = make_float4(M[4], M[5], M[6], M[7]);
+    // largest row norm of M, 1 / min(s): bounds how M magnifies an offset
+    const float smin = fminf(in.scale[3 * o], fminf(in.scale[3 * o + 1], in.scale[3 * o + 2]));
+    h[3] = make_float4(M[8], __int_as_float((int)o), 1.0f / smin, __int_as_float(info));
+}
+
 __global__ void k_scatter(int64_t nr, const int32_t *sorted_ref, const int32_t *rprim, const int32_t *rinfo,
                           PackIn in, const float *mtmp, float4 *hot, int32_t *inv) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -595,14 +612,59 @@ __global__ void k_scatter(int64_t nr, const int32_t *sorted_ref, const int32_t *
     const int32_t j = sorted_ref[i];
     const int64_t o = rprim[j];
     const int info = rinfo[j];
-    const float *M = mtmp + 9 * o;
-    hot[4 * i] = make_float4(in.mean[3 * o], in.mean[3 * o + 1], in.mean[3 * o + 2], in.dens[o]);
-    hot[4 * i + 1] = make_float4(M[0], M[1], M[2], M[3]);
-    hot[4 * i + 2] = make_float4(M[4], M[5], M[6], M[7]);
-    // largest row norm of M, 1 / min(s): bounds how M magnifies an offset
-    const float smin = fminf(in.scale[3 * o], fminf(in.scale[3 * o + 1], in.scale[3 * o + 2]));
-    hot[4 * i + 3] = make_float4(M[8], __int_as_float((int)o), 1.0f / smin, __int_as_float(info));
+    write_hot(in, mtmp, o, info, hot + 4 * i);
     if ((info & 255) == 0) inv[o] = (int32_t)i;
+}
+
+// Refit, leaves: each leaf keeps its primitive and slab (the layout of the
+// build: slab count and long axis as recorded) and takes the new parameters'
+// record and box.  Slabs of a fixed count along a fixed axis still cover the
+// ellipsoid, whatever its new shape; only their tightness changes.
+__global__ void k_refit_leaves(int64_t nr, PackIn in, const float *mtmp, const float *boxes, float4 *hot,
+                               float *lbox) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    const float4 h3 = hot[4 * i + 3];
+    const int64_t o = __float_as_int(h3.y);
+    const int info = __float_as_int(h3.w);
+    write_hot(in, mtmp, o, info, hot + 4 * i);
+    const int m = (info >> 8) & 255;
+    if (m <= 1) {
+        for (int c = 0; c < 6; ++c) lbox[6 * i + c] = boxes[6 * o + c];
+    } else {
+        double R[3][3];
+        quat_to_R(in, o, R);
+        slab_box(in, o, R, info & 255, m, (info >> 16) & 3, boxes, lbox + 6 * i);
+    }
+}
+
+// Refit, one level of 4-wide nodes [q0, q1): every child box from its leaf's
+// box or from the union of its node's four (already refitted) child boxes.
+__global__ void k_refit_nodes(int32_t q0, int32_t q1, float4 *nodes4, const float *lbox) {
+    const int64_t q = q0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= q1) return;
+    float4 *nd = nodes4 + 8 * q;
+    const float4 rf = nd[6];
+    const int32_t ref[4] = {__float_as_int(rf.x), __float_as_int(rf.y), __float_as_int(rf.z), __float_as_int(rf.w)};
+    float lo[3][4], hi[3][4];
+    for (int c = 0; c < 4; ++c) {
+        float b[6] = {3.0e38f, 3.0e38f, 3.0e38f, -3.0e38f, -3.0e38f, -3.0e38f};
+        if (ref[c] != kEmptySlot && ref[c] < 0) {
+            for (int k = 0; k < 6; ++k) b[k] = lbox[6 * (int64_t)~ref[c] + k];
+        } else if (ref[c] != kEmptySlot) {
+            const float4 *ch = nodes4 + 8 * (int64_t)ref[c];
+            for (int k = 0; k < 3; ++k) {
+                const float4 l = ch[k], h = ch[3 + k];
+                b[k] = fminf(fminf(l.x, l.y), fminf(l.z, l.w));
+                b[3 + k] = fmaxf(fmaxf(h.x, h.y), fmaxf(h.z, h.w));
+            }
+        }
+        for (int k = 0; k < 3; ++k) { lo[k][c] = b[k]; hi[k][c] = b[3 + k]; }
+    }
+    for (int k = 0; k < 3; ++k) {
+        nd[k] = make_float4(lo[k][0], lo[k][1], lo[k][2], lo[k][3]);
+        nd[3 + k] = make_float4(hi[k][0], hi[k][1], hi[k][2], hi[k][3]);
+    }
 }
 
 __global__ void k_compact(int64_t n, const int32_t *flag, const int32_t *pos, int32_t *out) {
@@ -636,6 +698,8 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
     sc.n = n;
     const double r = sqrt(-2.0 * log((double)eps));
     sc.r2 = (float)(r * r);
+    sc.r_cut = r;
+    std::vector<int32_t> levels4{0, 1};  // level L of the 4-wide nodes: [levels4[L], levels4[L + 1])
     PackIn in{n, s->mean, s->scale, s->rotation, s->density, s->albedo, s->roughness, s->emission,
               s->material, r};
     float *boxes = nullptr, *rbox = nullptr;
@@ -645,6 +709,7 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
     int32_t *pc_node = nullptr, *pc_leaf = nullptr, *pieces = nullptr, *roff = nullptr, *rprim = nullptr,
             *rinfo = nullptr;
     int32_t *emit_flag = nullptr, *emit_pos = nullptr, *depth = nullptr;
+    uint32_t *berr = nullptr;  // the build's own validation flags (not the context's query errors)
     hipError_t e = hipSuccess;
     uint32_t h_err = 0;
     int32_t h_depth = 0, h_nemit = 0, h_last_flag = 0, h_roff_last = 0, h_pieces_last = 0;
@@ -661,16 +726,17 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
     UGP_CHECK(hipMallocAsync((void **)&emit_flag, sizeof(int32_t) * n, st));
     UGP_CHECK(hipMallocAsync((void **)&emit_pos, sizeof(int32_t) * n, st));
     UGP_CHECK(hipMallocAsync((void **)&depth, sizeof(int32_t), st));
-    UGP_CHECK(hipMemsetAsync(ctx->err, 0, sizeof(uint32_t), st));
+    UGP_CHECK(hipMallocAsync((void **)&berr, sizeof(uint32_t), st));
+    UGP_CHECK(hipMemsetAsync(berr, 0, sizeof(uint32_t), st));
     UGP_CHECK(hipMemsetAsync(depth, 0, sizeof(int32_t), st));
     hipLaunchKernelGGL(k_init_bounds, dim3(1), dim3(64), 0, st, bounds);
     hipLaunchKernelGGL(k_pack, dim3(blocks(n)), dim3(kThreads), 0, st, in, boxes, sc.cold, mtmp, bounds, pieces,
-                       ctx->err);
+                       berr);
     UGP_CHECK(hipGetLastError());
     UGP_CHECK(exclusive_scan(pieces, roff, n, st));
     UGP_CHECK(hipMemcpyAsync(&h_roff_last, roff + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st));
     UGP_CHECK(hipMemcpyAsync(&h_pieces_last, pieces + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    UGP_CHECK(hipMemcpyAsync(&h_err, ctx->err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    UGP_CHECK(hipMemcpyAsync(&h_err, berr, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     UGP_CHECK(hipStreamSynchronize(st));
     if (h_err & 8u) {
         e = hipErrorInvalidValue;
@@ -708,12 +774,12 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
         UGP_CHECK(hipMemsetAsync(pc_leaf, 0, sizeof(int32_t) * nr, st));
         UGP_CHECK(hipMemsetAsync(pc_node, 0, sizeof(int32_t) * ni, st));
         hipLaunchKernelGGL(k_validate_refs, dim3(blocks(nr - 1)), dim3(kThreads), 0, st, nr, sc.nodes, pc_node,
-                           pc_leaf, ctx->err);
+                           pc_leaf, berr);
         hipLaunchKernelGGL(k_validate_counts, dim3(blocks(nr)), dim3(kThreads), 0, st, nr, pc_node, pc_leaf,
-                           ctx->err);
+                           berr);
         hipLaunchKernelGGL(k_refit, dim3(blocks(nr)), dim3(kThreads), 0, st, nr, vals, rbox, sc.nodes, pnode,
-                           pleaf, flags, (const uint32_t *)ctx->err);
-        hipLaunchKernelGGL(k_depth, dim3(blocks(nr)), dim3(kThreads), 0, st, nr, pnode, pleaf, depth, ctx->err);
+                           pleaf, flags, (const uint32_t *)berr);
+        hipLaunchKernelGGL(k_depth, dim3(blocks(nr)), dim3(kThreads), 0, st, nr, pnode, pleaf, depth, berr);
     }
     hipLaunchKernelGGL(k_scatter, dim3(blocks(nr)), dim3(kThreads), 0, st, nr, vals, (const int32_t *)rprim,
                        (const int32_t *)rinfo, in, mtmp, sc.hot, sc.inv);
@@ -723,7 +789,7 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
     UGP_CHECK(hipMemcpyAsync(&h_nemit, emit_pos + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st));
     UGP_CHECK(hipMemcpyAsync(&h_last_flag, emit_flag + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st));
     UGP_CHECK(hipMemcpyAsync(&h_depth, depth, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    UGP_CHECK(hipMemcpyAsync(&h_err, ctx->err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    UGP_CHECK(hipMemcpyAsync(&h_err, berr, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     {
         float rootb[12];
         if (nr > 1) UGP_CHECK(hipMemcpyAsync(rootb, sc.nodes, sizeof(float) * 12, hipMemcpyDeviceToHost, st));
@@ -772,8 +838,11 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
                                (const float4 *)sc.nodes, (const int32_t *)fin, (const int32_t *)fout, nf, gin,
                                gout, cnt, cnt + 1, big);
             UGP_CHECK(hipGetLastError());
-            UGP_CHECK(hipMemcpyAsync(&nf, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            int32_t h_cnt[2] = {0, 0};
+            UGP_CHECK(hipMemcpyAsync(h_cnt, cnt, sizeof(h_cnt), hipMemcpyDeviceToHost, st));
             UGP_CHECK(hipStreamSynchronize(st));
+            nf = h_cnt[0];
+            levels4.push_back(h_cnt[1]);
             std::swap(fin, gin);
             std::swap(fout, gout);
             if (++levels > 4096) {
@@ -815,18 +884,109 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
     hipFreeAsync(pnode, st); hipFreeAsync(pleaf, st); hipFreeAsync(flags, st);
     hipFreeAsync(pc_node, st); hipFreeAsync(pc_leaf, st); hipFreeAsync(pieces, st); hipFreeAsync(roff, st);
     hipFreeAsync(rprim, st); hipFreeAsync(rinfo, st);
-    hipFreeAsync(emit_flag, st); hipFreeAsync(emit_pos, st); hipFreeAsync(depth, st);
+    hipFreeAsync(emit_flag, st); hipFreeAsync(emit_pos, st); hipFreeAsync(depth, st); hipFreeAsync(berr, st);
     UGP_CHECK(hipStreamSynchronize(st));
     free_scene(ctx->scene);
     ctx->scene = sc;
+    ctx->node_levels = sc.n_nodes4 > 0 ? levels4 : std::vector<int32_t>{};
     return hipSuccess;
 fail:
     hipStreamSynchronize(st);
     hipFree(boxes); hipFree(rbox); hipFree(mtmp); hipFree(bounds); hipFree(keys); hipFree(tk);
     hipFree(vals); hipFree(tv); hipFree(pnode); hipFree(pleaf); hipFree(flags);
     hipFree(pc_node); hipFree(pc_leaf); hipFree(pieces); hipFree(roff); hipFree(rprim); hipFree(rinfo);
-    hipFree(emit_flag); hipFree(emit_pos); hipFree(depth);
+    hipFree(emit_flag); hipFree(emit_pos); hipFree(depth); hipFree(berr);
     free_scene(sc);
+    return e == hipSuccess ? hipErrorUnknown : e;
+}
+
+hipError_t refit_scene(ugp_ctx ctx, const ugp_scene *s) {
+    hipStream_t st = ctx->stream;
+    SceneDev &sc = ctx->scene;
+    const int64_t n = s->n, nr = sc.n_refs;
+    PackIn in{n, s->mean, s->scale, s->rotation, s->density, s->albedo, s->roughness, s->emission,
+              s->material, sc.r_cut};
+    float *boxes = nullptr, *mtmp = nullptr, *lbox = nullptr;
+    float4 *cold = nullptr;
+    uint32_t *bounds = nullptr;
+    int32_t *pieces = nullptr, *emit_flag = nullptr, *emit_pos = nullptr;
+    uint32_t *berr = nullptr;
+    hipError_t e = hipSuccess;
+    uint32_t h_err = 0;
+    int32_t h_nemit = 0, h_last_flag = 0;
+    float rootb[24];
+    const std::vector<int32_t> &lv = ctx->node_levels;
+    // pack into temporaries and validate: on bad parameters the scene is left as it was
+    UGP_CHECK(hipMallocAsync((void **)&boxes, sizeof(float) * 6 * n, st));
+    UGP_CHECK(hipMallocAsync((void **)&mtmp, sizeof(float) * 9 * n, st));
+    UGP_CHECK(hipMallocAsync((void **)&cold, sizeof(float4) * 3 * n, st));
+    UGP_CHECK(hipMallocAsync((void **)&bounds, sizeof(uint32_t) * 8, st));
+    UGP_CHECK(hipMallocAsync((void **)&pieces, sizeof(int32_t) * n, st));
+    UGP_CHECK(hipMallocAsync((void **)&lbox, sizeof(float) * 6 * nr, st));
+    UGP_CHECK(hipMallocAsync((void **)&emit_flag, sizeof(int32_t) * n, st));
+    UGP_CHECK(hipMallocAsync((void **)&emit_pos, sizeof(int32_t) * n, st));
+    UGP_CHECK(hipMallocAsync((void **)&berr, sizeof(uint32_t), st));
+    UGP_CHECK(hipMemsetAsync(berr, 0, sizeof(uint32_t), st));
+    hipLaunchKernelGGL(k_init_bounds, dim3(1), dim3(64), 0, st, bounds);
+    hipLaunchKernelGGL(k_pack, dim3(blocks(n)), dim3(kThreads), 0, st, in, boxes, cold, mtmp, bounds, pieces,
+                       berr);
+    UGP_CHECK(hipGetLastError());
+    UGP_CHECK(hipMemcpyAsync(&h_err, berr, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    UGP_CHECK(hipStreamSynchronize(st));
+    if (h_err & 8u) {
+        e = hipErrorInvalidValue;
+        goto fail;
+    }
+    // records and leaf boxes, then the 4-wide nodes from the deepest level up
+    UGP_CHECK(hipMemcpyAsync(sc.cold, cold, sizeof(float4) * 3 * n, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_refit_leaves, dim3(blocks(nr)), dim3(kThreads), 0, st, nr, in, (const float *)mtmp,
+                       (const float *)boxes, sc.hot, lbox);
+    for (int64_t L = (int64_t)lv.size() - 2; L >= 0; --L)
+        if (lv[L + 1] > lv[L])
+            hipLaunchKernelGGL(k_refit_nodes, dim3(blocks(lv[L + 1] - lv[L])), dim3(kThreads), 0, st, lv[L],
+                               lv[L + 1], sc.nodes, (const float *)lbox);
+    UGP_CHECK(hipGetLastError());
+    // emitters and the scene bounds
+    hipLaunchKernelGGL(k_emit_flags, dim3(blocks(n)), dim3(kThreads), 0, st, n, (const float4 *)sc.cold, emit_flag);
+    UGP_CHECK(hipGetLastError());
+    UGP_CHECK(exclusive_scan(emit_flag, emit_pos, n, st));
+    UGP_CHECK(hipMemcpyAsync(&h_nemit, emit_pos + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    UGP_CHECK(hipMemcpyAsync(&h_last_flag, emit_flag + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    if (sc.n_nodes4 > 0)
+        UGP_CHECK(hipMemcpyAsync(rootb, sc.nodes, sizeof(float) * 24, hipMemcpyDeviceToHost, st));
+    else
+        UGP_CHECK(hipMemcpyAsync(rootb, lbox, sizeof(float) * 6, hipMemcpyDeviceToHost, st));
+    UGP_CHECK(hipStreamSynchronize(st));
+    h_nemit += h_last_flag;
+    if (h_nemit != sc.n_emit) {
+        hipFree(sc.emit);
+        sc.emit = nullptr;
+        sc.n_emit = 0;
+        if (h_nemit > 0) UGP_CHECK(hipMalloc((void **)&sc.emit, sizeof(int32_t) * h_nemit));
+    }
+    if (h_nemit > 0) {
+        hipLaunchKernelGGL(k_compact, dim3(blocks(n)), dim3(kThreads), 0, st, n, emit_flag, emit_pos, sc.emit);
+        UGP_CHECK(hipGetLastError());
+    }
+    sc.n_emit = h_nemit;
+    for (int c = 0; c < 3; ++c) {
+        if (sc.n_nodes4 > 0) {  // the root's four child boxes (lo.c[4] at 4 c, hi.c[4] at 12 + 4 c)
+            sc.lo[c] = std::min(std::min(rootb[4 * c], rootb[4 * c + 1]), std::min(rootb[4 * c + 2], rootb[4 * c + 3]));
+            sc.hi[c] = std::max(std::max(rootb[12 + 4 * c], rootb[12 + 4 * c + 1]),
+                                std::max(rootb[12 + 4 * c + 2], rootb[12 + 4 * c + 3]));
+        } else {
+            sc.lo[c] = rootb[c];
+            sc.hi[c] = rootb[3 + c];
+        }
+    }
+    hipFreeAsync(boxes, st); hipFreeAsync(mtmp, st); hipFreeAsync(cold, st); hipFreeAsync(bounds, st);
+    hipFreeAsync(pieces, st); hipFreeAsync(lbox, st); hipFreeAsync(emit_flag, st); hipFreeAsync(emit_pos, st);
+    hipFreeAsync(berr, st);
+    return hipSuccess;
+fail:
+    hipStreamSynchronize(st);
+    hipFree(boxes); hipFree(mtmp); hipFree(cold); hipFree(bounds); hipFree(pieces); hipFree(lbox);
+    hipFree(emit_flag); hipFree(emit_pos); hipFree(berr);
     return e == hipSuccess ? hipErrorUnknown : e;
 }
 

@@ -28,6 +28,7 @@ struct SceneDev {
     int64_t n_refs = 0;    // leaves (references) of the hierarchy
     int32_t root = 0;      // ref of the root (a leaf ref when n == 1)
     float r2 = 0.f;        // squared Mahalanobis radius of the cut-off ellipsoid
+    double r_cut = 0.0;    // that radius in full precision (for a refit)
     float4 *hot = nullptr;
     float4 *cold = nullptr;
     float4 *nodes = nullptr;
@@ -81,6 +82,7 @@ struct ugp_ctx_s {
     int64_t tail_paths = 65536;  // live paths at or below which a chunk's last bounces run in one kernel
     // event pairs of the last render, by category: 0 collide main, 1 collide wide, 2 light, 3 env,
     // 4 shade, 5 ray sort
+    std::vector<int32_t> node_levels;  // 4-wide nodes of level L: [node_levels[L], node_levels[L + 1])
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<int, int>> ev_used;  // (category, index of the start event)
     bool ev_cat_valid = false;
@@ -90,6 +92,8 @@ namespace ugp {
 
 // build.hip
 hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps);
+// new parameters for the same n primitives in the built hierarchy's topology
+hipError_t refit_scene(ugp_ctx ctx, const ugp_scene *s);
 // device-wide exclusive scan of int32, and a stable LSD radix sort of
 // (uint32 key, int32 value) pairs (4 passes of 8 bits; result in keys / vals,
 // tk / tv are scratch of the same size)

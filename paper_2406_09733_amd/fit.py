@@ -4,8 +4,9 @@ of the accumulated free-flight CDF (eq. accum_cdf) over several views.
 
 Every step runs in the HIP library: camera rays (``ugp_camera_rays``), the
 CDF, loss and gradient (``ugp_accum_cdf``), the Adam update with its clamps
-(``ugp_fit_adam``) and the hierarchy rebuild after the primitives moved
-(``ugp_build_bvh``).  This module only sequences the calls.
+(``ugp_fit_adam``) and the hierarchy update after the primitives moved
+(``ugp_build_bvh``, or ``ugp_refit_bvh`` between rebuilds).  This module
+only sequences the calls.
 """
 from __future__ import annotations
 
@@ -31,14 +32,24 @@ def reference_images(ctx, scene: dict, cams: list, seed: int = 0, samples: int =
     return acc / samples
 
 
+def _update_hierarchy(ctx, params: dict, it: int, rebuild_every: int):
+    # the primitives moved: a new hierarchy every rebuild_every steps, a refit
+    # of the last one in between
+    if rebuild_every <= 1 or (it - 1) % rebuild_every == 0:
+        ctx.build_bvh(params)
+    else:
+        ctx.refit_bvh(params)
+
+
 def fit_transmittance(ctx, params: dict, cams: list, target, iters: int, lr=(1e-4, 1e-2, 2e-5, 1e-4),
-                      min_scale: float = 1e-6, seed: int = 1, on_step=None) -> dict:
+                      min_scale: float = 1e-6, seed: int = 1, on_step=None, rebuild_every: int = 1) -> dict:
     """Optimise params (device float32 tensors mean, scale, rotation, density,
     updated in place; plus albedo, roughness, emission, material for the
     hierarchy build) for `iters` Adam steps with rates lr = (means, log
     scales, rotations, densities).  Loss: mean over the views' pixels of
     (C - target)^2, one jittered ray per pixel per step, all views in one
-    batch.  Returns the loss of every step and the wall time."""
+    batch.  The hierarchy is rebuilt every `rebuild_every` steps and refitted
+    in between.  Returns the loss of every step and the wall time."""
     import torch
     n = params["mean"].shape[0]
     dev = params["mean"].device
@@ -50,7 +61,7 @@ def fit_transmittance(ctx, params: dict, cams: list, target, iters: int, lr=(1e-
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for it in range(1, iters + 1):
-        ctx.build_bvh(params)  # the primitives moved: rebuild the hierarchy
+        _update_hierarchy(ctx, params, it, rebuild_every)
         grad.zero_()
         loss = torch.zeros(1, device=dev, dtype=torch.float32)
         rays = view_rays(ctx, cams, seed, it)
@@ -76,7 +87,7 @@ def reference_rf_images(ctx, scene: dict, cams: list, seed: int = 0, samples: in
 
 
 def fit_radiance_field(ctx, params: dict, cams: list, target, iters: int, lr=(1e-4, 1e-2, 2e-5, 1e-4, 1e-2),
-                       min_scale: float = 1e-6, seed: int = 1, on_step=None) -> dict:
+                       min_scale: float = 1e-6, seed: int = 1, on_step=None, rebuild_every: int = 1) -> dict:
     """Image-based radiance-field reconstruction (Sec. 8): Adam on the mean
     over the views' pixels of |L - target|^2 with L of eq. rf, one jittered
     ray per pixel per step, every parameter of every primitive including its
@@ -93,7 +104,7 @@ def fit_radiance_field(ctx, params: dict, cams: list, target, iters: int, lr=(1e
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for it in range(1, iters + 1):
-        ctx.build_bvh(params)
+        _update_hierarchy(ctx, params, it, rebuild_every)
         grad.zero_()
         loss = torch.zeros(1, device=dev, dtype=torch.float32)
         ctx.rf_render(view_rays(ctx, cams, seed, it), target=target, want_L=False, loss_scale=1.0 / npix,

@@ -52,6 +52,7 @@ def test_host_side_argument_checks(L):
     # none of these reach the device
     assert L.ugp_create(0, None, None) == 1
     assert L.ugp_build_bvh(None, None, C.c_float(0.01)) == 1
+    assert L.ugp_refit_bvh(None, None) == 1
     assert L.ugp_transmittance(None, 1, None, None, None, None) == 1
     assert L.ugp_sample_collision(None, 1, None, None, None, None, None) == 1
     assert L.ugp_render(None, None, None, None, None) == 1
