@@ -460,42 +460,46 @@ __global__ void k_validate_counts(int64_t n, const int32_t *pc_node, const int32
     if (i < n - 1 && pc_node[i] != (i == 0 ? 0 : 1)) atomicOr(err, 16u);
 }
 
-__device__ __forceinline__ void write_child_box(float4 *nodes, int32_t p, bool left, const float b[6]) {
-    float *nd = reinterpret_cast<float *>(nodes + 4 * (int64_t)p);
-    const int o = left ? 0 : 6;
-    for (int i = 0; i < 6; ++i)
-        __hip_atomic_store(&nd[o + i], b[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Boxes of the binary radix tree, level by level from the deepest: launch L
+// fills the two child boxes of every node at depth L from its leaves' boxes
+// or from its internal children's boxes (filled by the launch before), so
+// kernel boundaries order the levels and no node waits on another thread.
+// (A climb from each leaf with a flag per node needs device-wide fences at
+// every step, and each fence writes back and invalidates the per-XCD L2.)
+__global__ void k_node_depth(int64_t ni, const int32_t *parent_node, int32_t *ndepth, int32_t *maxd,
+                             uint32_t *err) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ni || (*err & 16u)) return;
+    int d = 0;
+    for (int32_t p = (int32_t)i; p != 0; p = parent_node[p]) {
+        if (++d > 4096) {  // a cycle: not a tree
+            atomicOr(err, 16u);
+            return;
+        }
+    }
+    ndepth[i] = d;
+    atomicMax(maxd, d);
 }
 
-__global__ void k_refit(int64_t n, const int32_t *sorted_orig, const float *boxes, float4 *nodes,
-                        const int32_t *parent_node, const int32_t *parent_leaf, int32_t *flags,
-                        const uint32_t *err) {
+__global__ void k_refit_level(int64_t ni, int32_t level, const int32_t *ndepth, const int32_t *sorted_orig,
+                              const float *boxes, float4 *nodes) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || (*err & 16u)) return;
-    float b[6];
-    const int32_t o = sorted_orig[i];
-    for (int c = 0; c < 6; ++c) b[c] = boxes[6 * (int64_t)o + c];
-    int32_t child = ~(int32_t)i;
-    int32_t p = parent_leaf[i];
-    while (true) {
-        const float4 n3 = nodes[4 * (int64_t)p + 3];
-        const bool left = __float_as_int(n3.x) == child;
-        write_child_box(nodes, p, left, b);
-        __threadfence();
-        const int old = __hip_atomic_fetch_add(&flags[p], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (old == 0) return;  // the sibling will finish this node
-        __threadfence();
-        const float *nd = reinterpret_cast<const float *>(nodes + 4 * (int64_t)p);
-        float v[12];
-        for (int c = 0; c < 12; ++c)
-            v[c] = __hip_atomic_load(&nd[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        for (int c = 0; c < 3; ++c) {
-            b[c] = fminf(v[c], v[6 + c]);
-            b[3 + c] = fmaxf(v[3 + c], v[9 + c]);
+    if (i >= ni || ndepth[i] != level) return;
+    float *nd = reinterpret_cast<float *>(nodes + 4 * i);
+    const int32_t ref[2] = {__float_as_int(nd[12]), __float_as_int(nd[13])};
+    for (int side = 0; side < 2; ++side) {
+        float b[6];
+        if (ref[side] < 0) {
+            const float *lb = boxes + 6 * (int64_t)sorted_orig[~ref[side]];
+            for (int c = 0; c < 6; ++c) b[c] = lb[c];
+        } else {
+            const float *cn = reinterpret_cast<const float *>(nodes + 4 * (int64_t)ref[side]);
+            for (int c = 0; c < 3; ++c) {
+                b[c] = fminf(cn[c], cn[6 + c]);
+                b[3 + c] = fmaxf(cn[3 + c], cn[9 + c]);
+            }
         }
-        if (p == 0) return;
-        child = p;
-        p = parent_node[p];
+        for (int c = 0; c < 6; ++c) nd[6 * side + c] = b[c];
     }
 }
 
@@ -710,6 +714,8 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
             *rinfo = nullptr;
     int32_t *emit_flag = nullptr, *emit_pos = nullptr, *depth = nullptr;
     uint32_t *berr = nullptr;  // the build's own validation flags (not the context's query errors)
+    int32_t *maxd = nullptr;   // deepest internal node of the radix tree
+    int32_t h_maxd = 0;
     hipError_t e = hipSuccess;
     uint32_t h_err = 0;
     int32_t h_depth = 0, h_nemit = 0, h_last_flag = 0, h_roff_last = 0, h_pieces_last = 0;
@@ -727,6 +733,7 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
     UGP_CHECK(hipMallocAsync((void **)&emit_pos, sizeof(int32_t) * n, st));
     UGP_CHECK(hipMallocAsync((void **)&depth, sizeof(int32_t), st));
     UGP_CHECK(hipMallocAsync((void **)&berr, sizeof(uint32_t), st));
+    UGP_CHECK(hipMallocAsync((void **)&maxd, sizeof(int32_t), st));
     UGP_CHECK(hipMemsetAsync(berr, 0, sizeof(uint32_t), st));
     UGP_CHECK(hipMemsetAsync(depth, 0, sizeof(int32_t), st));
     hipLaunchKernelGGL(k_init_bounds, dim3(1), dim3(64), 0, st, bounds);
@@ -777,8 +784,21 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
                            pc_leaf, berr);
         hipLaunchKernelGGL(k_validate_counts, dim3(blocks(nr)), dim3(kThreads), 0, st, nr, pc_node, pc_leaf,
                            berr);
-        hipLaunchKernelGGL(k_refit, dim3(blocks(nr)), dim3(kThreads), 0, st, nr, vals, rbox, sc.nodes, pnode,
-                           pleaf, flags, (const uint32_t *)berr);
+        // node depths (into `flags`), then the boxes level by level
+        UGP_CHECK(hipMemsetAsync(maxd, 0, sizeof(int32_t), st));
+        hipLaunchKernelGGL(k_node_depth, dim3(blocks(nr - 1)), dim3(kThreads), 0, st, nr - 1, (const int32_t *)pnode,
+                           flags, maxd, berr);
+        UGP_CHECK(hipMemcpyAsync(&h_maxd, maxd, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        UGP_CHECK(hipMemcpyAsync(&h_err, berr, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        UGP_CHECK(hipStreamSynchronize(st));
+        if (h_err & 16u) {
+            e = hipErrorUnknown;
+            goto fail;
+        }
+        for (int32_t L = h_maxd; L >= 0; --L)
+            hipLaunchKernelGGL(k_refit_level, dim3(blocks(nr - 1)), dim3(kThreads), 0, st, nr - 1, L,
+                               (const int32_t *)flags, (const int32_t *)vals, (const float *)rbox, sc.nodes);
+        UGP_CHECK(hipGetLastError());
         hipLaunchKernelGGL(k_depth, dim3(blocks(nr)), dim3(kThreads), 0, st, nr, pnode, pleaf, depth, berr);
     }
     hipLaunchKernelGGL(k_scatter, dim3(blocks(nr)), dim3(kThreads), 0, st, nr, vals, (const int32_t *)rprim,
@@ -885,6 +905,7 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
     hipFreeAsync(pc_node, st); hipFreeAsync(pc_leaf, st); hipFreeAsync(pieces, st); hipFreeAsync(roff, st);
     hipFreeAsync(rprim, st); hipFreeAsync(rinfo, st);
     hipFreeAsync(emit_flag, st); hipFreeAsync(emit_pos, st); hipFreeAsync(depth, st); hipFreeAsync(berr, st);
+    hipFreeAsync(maxd, st);
     UGP_CHECK(hipStreamSynchronize(st));
     free_scene(ctx->scene);
     ctx->scene = sc;
@@ -895,7 +916,7 @@ fail:
     hipFree(boxes); hipFree(rbox); hipFree(mtmp); hipFree(bounds); hipFree(keys); hipFree(tk);
     hipFree(vals); hipFree(tv); hipFree(pnode); hipFree(pleaf); hipFree(flags);
     hipFree(pc_node); hipFree(pc_leaf); hipFree(pieces); hipFree(roff); hipFree(rprim); hipFree(rinfo);
-    hipFree(emit_flag); hipFree(emit_pos); hipFree(depth); hipFree(berr);
+    hipFree(emit_flag); hipFree(emit_pos); hipFree(depth); hipFree(berr); hipFree(maxd);
     free_scene(sc);
     return e == hipSuccess ? hipErrorUnknown : e;
 }
