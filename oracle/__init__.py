@@ -76,6 +76,14 @@ def lib():
         L.orc_phase_eval.argtypes = [C.c_int, vp, C.c_double, vp, vp, vp, vp, vp]
         L.orc_phase_sample.argtypes = [C.c_int, vp, C.c_double, vp, vp, C.c_double, C.c_double,
                                        vp, vp, vp]
+        L.orc_sggx_phase_quad.argtypes = [vp, vp, vp, C.c_int, C.c_int]
+        L.orc_sggx_phase_quad.restype = C.c_double
+        L.orc_sggx_pdf_approx.argtypes = [vp, vp]
+        L.orc_sggx_pdf_approx.restype = C.c_double
+        L.orc_sggx_eval_n.argtypes = [vp, C.c_int64, vp, vp, C.c_int, vp]
+        L.orc_sggx_sample_vndf_n.argtypes = [vp, vp, C.c_int64, vp, vp]
+        L.orc_sggx_phase_est_n.argtypes = [vp, vp, vp, C.c_int64, vp, vp]
+        L.orc_scene_set_sggx.argtypes = [vp, vp]
         L.orc_render.argtypes = [vp, C.POINTER(_Camera), C.POINTER(_Params), C.c_int64, vp,
                                  C.c_int, vp, vp]
         L.orc_render.restype = C.c_int64
@@ -152,6 +160,14 @@ class Scene:
             raise ValueError("oracle rejected the scene")
         self.h = h
         self.n = n
+        mats = self._keep["material"].reshape(-1)
+        if scene.get("sggx") is not None:
+            g = np.ascontiguousarray(scene["sggx"], dtype=np.float32).reshape(n, 6)
+            self._keep["sggx"] = g
+            if n and lib().orc_scene_set_sggx(self.h, _addr(g)) != 0:
+                raise ValueError("oracle rejected the SGGX matrices (not positive definite)")
+        elif n and bool((mats == 2).any()):
+            raise ValueError("material 2 (SGGX microflakes) needs scene['sggx']")
         self.use_bvh = 0
         if bvh:
             lib().orc_scene_build_bvh(self.h)
@@ -371,6 +387,71 @@ def phase_sample(mat, albedo, rough, normal, wo, u1, u2):
     lib().orc_phase_sample(int(mat), _addr(a), float(rough), _addr(n), _addr(o), float(u1),
                            float(u2), _addr(wi), _addr(w), _addr(pdf))
     return wi, w, float(pdf[0])
+
+
+# ---------------------------------------------------------------------------
+# SGGX microflake phase function with a Lambertian base (per unit albedo)
+# ---------------------------------------------------------------------------
+def _s6(s6):
+    return np.ascontiguousarray(s6, dtype=np.float64).reshape(6)
+
+
+def sggx_sigma(s6, w) -> np.ndarray:
+    """projected area sigma(w) for directions w [n,3]"""
+    v = np.ascontiguousarray(w, dtype=np.float64).reshape(-1, 3)
+    out = np.zeros(v.shape[0]); s = _s6(s6)
+    lib().orc_sggx_eval_n(_addr(s), v.shape[0], None, _addr(v), 0, _addr(out))
+    return out
+
+
+def sggx_D(s6, nrm) -> np.ndarray:
+    """normal distribution D(n) for unit normals [n,3]"""
+    v = np.ascontiguousarray(nrm, dtype=np.float64).reshape(-1, 3)
+    out = np.zeros(v.shape[0]); s = _s6(s6)
+    lib().orc_sggx_eval_n(_addr(s), v.shape[0], None, _addr(v), 1, _addr(out))
+    return out
+
+
+def sggx_vndf(s6, wo, nrm) -> np.ndarray:
+    """visible normal distribution D_wo(n) for unit normals [n,3]"""
+    v = np.ascontiguousarray(nrm, dtype=np.float64).reshape(-1, 3)
+    o = np.ascontiguousarray(wo, dtype=np.float64).reshape(3)
+    out = np.zeros(v.shape[0]); s = _s6(s6)
+    lib().orc_sggx_eval_n(_addr(s), v.shape[0], _addr(o), _addr(v), 2, _addr(out))
+    return out
+
+
+def sggx_sample_vndf(s6, wo, u) -> np.ndarray:
+    """visible normals from uniforms u [n,2] -> [n,3]"""
+    uu = np.ascontiguousarray(u, dtype=np.float64).reshape(-1, 2)
+    o = np.ascontiguousarray(wo, dtype=np.float64).reshape(3)
+    out = np.zeros((uu.shape[0], 3)); s = _s6(s6)
+    lib().orc_sggx_sample_vndf_n(_addr(s), _addr(o), uu.shape[0], _addr(uu), _addr(out))
+    return out
+
+
+def sggx_phase_est(s6, wo, wi, u) -> np.ndarray:
+    """stochastic estimates of f_p(wi, wo) / albedo from uniforms u [n,4]"""
+    uu = np.ascontiguousarray(u, dtype=np.float64).reshape(-1, 4)
+    o = np.ascontiguousarray(wo, dtype=np.float64).reshape(3)
+    i = np.ascontiguousarray(wi, dtype=np.float64).reshape(3)
+    out = np.zeros(uu.shape[0]); s = _s6(s6)
+    lib().orc_sggx_phase_est_n(_addr(s), _addr(o), _addr(i), uu.shape[0], _addr(uu), _addr(out))
+    return out
+
+
+def sggx_phase_quad(s6, wo, wi, nz: int = 400, nphi: int = 800) -> float:
+    """f_p(wi, wo) / albedo by midpoint quadrature over the sphere of normals"""
+    o = np.ascontiguousarray(wo, dtype=np.float64).reshape(3)
+    i = np.ascontiguousarray(wi, dtype=np.float64).reshape(3)
+    s = _s6(s6)
+    return lib().orc_sggx_phase_quad(_addr(s), _addr(o), _addr(i), int(nz), int(nphi))
+
+
+def sggx_pdf_approx(wo, wi) -> float:
+    o = np.ascontiguousarray(wo, dtype=np.float64).reshape(3)
+    i = np.ascontiguousarray(wi, dtype=np.float64).reshape(3)
+    return lib().orc_sggx_pdf_approx(_addr(o), _addr(i))
 
 
 # ---------------------------------------------------------------------------

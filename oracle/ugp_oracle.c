@@ -125,7 +125,8 @@ struct orc_scene {
     double *alb;   /* [n][3] */
     double *rough; /* [n] */
     double *emis;  /* [n][3] */
-    int32_t *mat;  /* [n] 0 Lambert, 1 GGX */
+    int32_t *mat;  /* [n] 0 Lambert, 1 GGX (delta NDF), 2 Lambert microflakes with an SGGX NDF */
+    double *sggx;  /* [n][6] SGGX matrix (xx, yy, zz, xy, xz, yz), world frame; NULL if none */
     double *lo, *hi;  /* [n][3] axis-aligned box of the cut-off ellipsoid */
     double *rsph;  /* [n] radius of the bounding sphere, r * max(s) */
     int64_t *emitters;
@@ -206,6 +207,7 @@ void orc_scene_destroy(orc_scene *S) {
     if (!S) return;
     free(S->mu); free(S->M); free(S->d); free(S->nrm); free(S->alb); free(S->rough);
     free(S->emis); free(S->mat); free(S->lo); free(S->hi); free(S->rsph); free(S->emitters);
+    free(S->sggx);
     free(S->nodes); free(S->perm);
     free(S);
 }
@@ -900,6 +902,221 @@ void orc_phase_sample(int mat, const double alb[3], double rough, const double n
 }
 
 /* ------------------------------------------------------------------------- */
+/* SGGX microflake phase function (Sec. 4.2, eq. vndf and eq. phase_function) */
+/* with a Lambertian base BSDF.  The NDF of a symmetric positive-definite S   */
+/* (Heitz et al. 2015) is D(n) = 1 / (pi sqrt(det S) (n^T S^-1 n)^2); the     */
+/* projected area is sigma(w) = sqrt(w^T S w); the visible NDF is             */
+/* D_wo(n) = <wo.n> D(n) / sigma(wo).  f_p(wi, wo) = int D_wo(n) f(wi; n) dn  */
+/* with the cosine-weighted Lambert f(wi; n) = albedo/pi <wi.n>.  Functions  */
+/* below are per unit albedo.                                                 */
+/* ------------------------------------------------------------------------- */
+
+static void sggx_full(const double s6[6], double S[3][3]) {
+    S[0][0] = s6[0]; S[1][1] = s6[1]; S[2][2] = s6[2];
+    S[0][1] = S[1][0] = s6[3]; S[0][2] = S[2][0] = s6[4]; S[1][2] = S[2][1] = s6[5];
+}
+
+/* inverse and determinant of a symmetric 3x3 (cofactors) */
+static double inv3(const double A[3][3], double Ai[3][3]) {
+    double c00 = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+    double c01 = A[1][2] * A[2][0] - A[1][0] * A[2][2];
+    double c02 = A[1][0] * A[2][1] - A[1][1] * A[2][0];
+    double det = A[0][0] * c00 + A[0][1] * c01 + A[0][2] * c02;
+    double id = 1.0 / det;
+    Ai[0][0] = c00 * id; Ai[1][0] = c01 * id; Ai[2][0] = c02 * id;
+    Ai[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) * id;
+    Ai[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) * id;
+    Ai[2][1] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) * id;
+    Ai[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) * id;
+    Ai[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) * id;
+    Ai[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) * id;
+    return det;
+}
+
+static double quad_form(const double A[3][3], const double v[3]) {
+    double r = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) r += v[i] * A[i][j] * v[j];
+    return r;
+}
+
+double orc_sggx_sigma(const double s6[6], const double w[3]) {
+    double S[3][3];
+    sggx_full(s6, S);
+    return sqrt(fmax(0.0, quad_form(S, w)));
+}
+
+double orc_sggx_D(const double s6[6], const double n[3]) {
+    double S[3][3], Si[3][3];
+    sggx_full(s6, S);
+    double det = inv3(S, Si);
+    double q = quad_form(Si, n);
+    return 1.0 / (M_PI * sqrt(det) * q * q);
+}
+
+double orc_sggx_vndf(const double s6[6], const double wo[3], const double n[3]) {
+    double c = dot3(wo, n);
+    if (c <= 0.0) return 0.0;
+    return c * orc_sggx_D(s6, n) / orc_sggx_sigma(s6, wo);
+}
+
+/* A visible normal: the microflakes' normals are those of the ellipsoid
+ * x^T S x = 1 (its projected area along w is proportional to
+ * sqrt(w^T S w)), and the visible ones, weighted by projected area, are the
+ * normals at the front surface above a point uniform in the ellipsoid's
+ * shadow along wo.  The shadow of {B y : |y| <= 1} (B B^T = S^-1) on the
+ * plane of an orthonormal pair (e1, e2) orthogonal to wo is the ellipse of
+ * the 2x2 matrix [e_a^T S^-1 e_b]: a point u uniform in the unit disk maps
+ * to q = L u (L its Cholesky factor); the front surface point is q + s wo
+ * with s the larger root of (q + s wo)^T S (q + s wo) = 1; its normal is
+ * S x normalised. */
+void orc_sggx_sample_vndf(const double s6[6], const double wo[3], double u1, double u2, double n[3]) {
+    double S[3][3], Si[3][3], e1[3], e2[3];
+    sggx_full(s6, S);
+    inv3(S, Si);
+    onb(wo, e1, e2);
+    double s11 = quad_form(Si, e1), s22 = quad_form(Si, e2), s12 = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) s12 += e1[i] * Si[i][j] * e2[j];
+    double l11 = sqrt(s11), l21 = s12 / l11, l22 = sqrt(fmax(0.0, s22 - l21 * l21));
+    double r = sqrt(u1), ph = 2.0 * M_PI * u2;
+    double a = r * cos(ph), b = r * sin(ph);
+    double qa = l11 * a, qb = l21 * a + l22 * b;
+    double q[3];
+    for (int i = 0; i < 3; ++i) q[i] = qa * e1[i] + qb * e2[i];
+    double A = quad_form(S, wo), B = 0.0, Cq = quad_form(S, q) - 1.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) B += q[i] * S[i][j] * wo[j];
+    double sroot = (-B + sqrt(fmax(0.0, B * B - A * Cq))) / A;
+    double x[3];
+    for (int i = 0; i < 3; ++i) x[i] = q[i] + sroot * wo[i];
+    for (int i = 0; i < 3; ++i) n[i] = S[i][0] * x[0] + S[i][1] * x[1] + S[i][2] * x[2];
+    normalize3(n);
+}
+
+/* a direction cosine-distributed about the unit vector m */
+static void cosine_about(const double m[3], double u1, double u2, double w[3]) {
+    double b1[3], b2[3];
+    onb(m, b1, b2);
+    double r = sqrt(u1), ph = 2.0 * M_PI * u2, z = sqrt(fmax(0.0, 1.0 - u1));
+    for (int i = 0; i < 3; ++i) w[i] = r * cos(ph) * b1[i] + r * sin(ph) * b2[i] + z * m[i];
+}
+
+/* The stochastic evaluation of f_p (Sec. 4.2, "Evaluation"): one normal from
+ * the visible NDF and one from the base BSDF's sampling reversed (for the
+ * Lambertian base: cosine-distributed about wi), combined by the one-sample
+ * balance heuristic.  u[0..1] drive the first, u[2..3] the second.  An
+ * unbiased estimate of f_p / albedo. */
+double orc_sggx_phase_est(const double s6[6], const double wo[3], const double wi[3], const double u[4]) {
+    double n1[3], n3[3];
+    orc_sggx_sample_vndf(s6, wo, u[0], u[1], n1);
+    double p1 = orc_sggx_vndf(s6, wo, n1);
+    double f1 = fmax(0.0, dot3(wi, n1)) / M_PI; /* base f(wi; n1), also n1's density about wi */
+    double est = p1 > 0.0 ? f1 * p1 / (p1 + f1) : 0.0;
+    cosine_about(wi, u[2], u[3], n3);
+    double p3 = orc_sggx_vndf(s6, wo, n3);
+    double c3 = fmax(0.0, dot3(n3, wi)) / M_PI;
+    if (c3 > 0.0 && p3 > 0.0) est += p3 * c3 / (c3 + p3);
+    return est;
+}
+
+/* f_p / albedo by quadrature on a (cos theta, phi) midpoint grid: the plain
+ * definition, for checks */
+double orc_sggx_phase_quad(const double s6[6], const double wo[3], const double wi[3], int nz, int nphi) {
+    double acc = 0.0;
+    for (int a = 0; a < nz; ++a) {
+        double z = -1.0 + (a + 0.5) * 2.0 / nz, rr = sqrt(fmax(0.0, 1.0 - z * z));
+        for (int b = 0; b < nphi; ++b) {
+            double ph = (b + 0.5) * 2.0 * M_PI / nphi;
+            double n[3] = {rr * cos(ph), rr * sin(ph), z};
+            acc += orc_sggx_vndf(s6, wo, n) * fmax(0.0, dot3(wi, n)) / M_PI;
+        }
+    }
+    return acc * (2.0 / nz) * (2.0 * M_PI / nphi);
+}
+
+/* The approximate MIS pdf of the Lambertian component (App. B): a
+ * cosine-weighted lobe of the half vector, <wh.wo>/pi. */
+double orc_sggx_pdf_approx(const double wo[3], const double wi[3]) {
+    double h[3] = {wo[0] + wi[0], wo[1] + wi[1], wo[2] + wi[2]};
+    double l = sqrt(dot3(h, h));
+    if (!(l > 0.0)) return 0.0;
+    return fmax(0.0, dot3(h, wo) / l) / M_PI;
+}
+
+/* Copies the matrices; returns 1 (and keeps none) unless every one is finite
+ * and positive definite (Sylvester: leading minors > 0). */
+int orc_scene_set_sggx(orc_scene *S, const float *sggx) {
+    if (!S || !sggx) return 1;
+    for (int64_t k = 0; k < S->n; ++k) {
+        double A[3][3], s6[6];
+        for (int i = 0; i < 6; ++i) s6[i] = sggx[6 * k + i];
+        sggx_full(s6, A);
+        double m2 = A[0][0] * A[1][1] - A[0][1] * A[0][1];
+        double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[1][2]) - A[0][1] * (A[0][1] * A[2][2] - A[1][2] * A[0][2]) +
+                     A[0][2] * (A[0][1] * A[1][2] - A[1][1] * A[0][2]);
+        if (!(A[0][0] > 0.0) || !(m2 > 0.0) || !(det > 0.0) || !isfinite(det)) return 1;
+    }
+    free(S->sggx);
+    S->sggx = (double *)malloc(sizeof(double) * 6 * (size_t)(S->n > 0 ? S->n : 1));
+    for (int64_t i = 0; i < 6 * S->n; ++i) S->sggx[i] = sggx[i];
+    return 0;
+}
+
+/* Phase function of primitive k for (wo, wi): the delta-NDF materials in
+ * closed form with their exact pdf; SGGX microflakes (material 2) by the
+ * stochastic estimate from u[0..3] with the approximate MIS pdf. */
+static void prim_phase_eval(const orc_scene *S, int64_t k, const double wo[3], const double wi[3],
+                            const double u[4], double f[3], double *pdf) {
+    const double *alb = S->alb + 3 * k;
+    if (S->mat[k] == 2) {
+        if (!S->sggx) { f[0] = f[1] = f[2] = 0.0; *pdf = 0.0; return; }
+        double e = orc_sggx_phase_est(S->sggx + 6 * k, wo, wi, u);
+        for (int c = 0; c < 3; ++c) f[c] = alb[c] * e;
+        *pdf = orc_sggx_pdf_approx(wo, wi);
+        return;
+    }
+    orc_phase_eval(S->mat[k], alb, S->rough[k], S->nrm + 3 * k, wo, wi, f, pdf);
+}
+
+/* Sampling the phase function of primitive k (Sec. 4.2, "Importance
+ * Sampling"): for SGGX microflakes a visible normal from (u1, u2), then the
+ * Lambertian base's cosine sampling about it from v[0..1]; the weight is the
+ * albedo and the pdf reported for MIS is the approximate one. */
+static void prim_phase_sample(const orc_scene *S, int64_t k, const double wo[3], double u1, double u2,
+                              const double v[2], double wi[3], double wgt[3], double *pdf) {
+    const double *alb = S->alb + 3 * k;
+    if (S->mat[k] == 2) {
+        double m[3];
+        if (!S->sggx) { *pdf = 0.0; return; }
+        orc_sggx_sample_vndf(S->sggx + 6 * k, wo, u1, u2, m);
+        cosine_about(m, v[0], v[1], wi);
+        for (int c = 0; c < 3; ++c) wgt[c] = alb[c];
+        *pdf = orc_sggx_pdf_approx(wo, wi);
+        return;
+    }
+    orc_phase_sample(S->mat[k], alb, S->rough[k], S->nrm + 3 * k, wo, u1, u2, wi, wgt, pdf);
+}
+
+/* vectorised forms for the checks: n directions or normals in, n values out */
+void orc_sggx_eval_n(const double s6[6], int64_t n, const double *wo, const double *v, int what, double *out) {
+    for (int64_t i = 0; i < n; ++i) {
+        if (what == 0) out[i] = orc_sggx_sigma(s6, v + 3 * i);
+        else if (what == 1) out[i] = orc_sggx_D(s6, v + 3 * i);
+        else out[i] = orc_sggx_vndf(s6, wo, v + 3 * i);
+    }
+}
+
+void orc_sggx_sample_vndf_n(const double s6[6], const double wo[3], int64_t n, const double *u, double *nrm) {
+    for (int64_t i = 0; i < n; ++i) orc_sggx_sample_vndf(s6, wo, u[2 * i], u[2 * i + 1], nrm + 3 * i);
+}
+
+void orc_sggx_phase_est_n(const double s6[6], const double wo[3], const double wi[3], int64_t n, const double *u,
+                          double *out) {
+    for (int64_t i = 0; i < n; ++i) out[i] = orc_sggx_phase_est(s6, wo, wi, u + 4 * i);
+}
+
+/* ------------------------------------------------------------------------- */
 /* Path tracer (Sec. 5, Table tab:highlevel, right column; eq. rte), with     */
 /* next-event estimation to emissive primitives and to a constant environment */
 /* and the balance heuristic between light and phase sampling.                */
@@ -982,8 +1199,12 @@ static void trace_path(const orc_scene *S, const orc_render_params *P, const orc
     }
     if (n_rec) *n_rec = 0;
     for (uint32_t v = 1;; ++v) {
+        double q3[4], q4[4], q5[4];  /* SGGX: light and environment estimates, cosine about the normal */
         rng4(seed, pix, sample, v, 0, u);
         rng4(seed, pix, sample, v, 1, g);
+        rng4(seed, pix, sample, v, 3, q3);
+        rng4(seed, pix, sample, v, 4, q4);
+        rng4(seed, pix, sample, v, 5, q5);
         gather(S, o, w, 0.0, INFINITY, self, 1, H);
         ocoll c;
         collide(S, H, 0.0, INFINITY, u[0], &c);
@@ -1016,7 +1237,6 @@ static void trace_path(const orc_scene *S, const orc_render_params *P, const orc
         if ((int)v == P->max_depth + 1) break;
         double wo[3] = {-w[0], -w[1], -w[2]};
         const double *nrm = S->nrm + 3 * k, *alb = S->alb + 3 * k;
-        int mat = S->mat[k];
         double rough = S->rough[k];
         if (P->nrc_mode != 0) {
             /* cache inputs at this vertex: position, outgoing direction, facet
@@ -1068,7 +1288,7 @@ static void trace_path(const orc_scene *S, const orc_render_params *P, const orc
                 for (int i = 0; i < 3; ++i)
                     wl[i] = sint * cos(ph) * b1[i] + sint * sin(ph) * b2[i] + cost * cdir[i];
                 double f[3], pph;
-                orc_phase_eval(mat, alb, rough, nrm, wo, wl, f, &pph);
+                prim_phase_eval(S, k, wo, wl, q3, f, &pph);
                 ohit he;
                 if ((f[0] > 0.0 || f[1] > 0.0 || f[2] > 0.0) && ray_prim(S, e, x, wl, 0.0, INFINITY, &he)) {
                     double fac = emitter_factor(S, x, wl, 0.0, INFINITY, k, e, 1, H2);
@@ -1086,7 +1306,7 @@ static void trace_path(const orc_scene *S, const orc_render_params *P, const orc
             double ph = 2.0 * M_PI * g[3];
             double wl[3] = {rr * cos(ph), rr * sin(ph), z};
             double f[3], pph;
-            orc_phase_eval(mat, alb, rough, nrm, wo, wl, f, &pph);
+            prim_phase_eval(S, k, wo, wl, q4, f, &pph);
             if (f[0] > 0.0 || f[1] > 0.0 || f[2] > 0.0) {
                 gather(S, x, wl, 0.0, INFINITY, k, 1, H2);
                 double T = fmax(0.0, 1.0 - accumulated_F(S, H2));
@@ -1097,7 +1317,7 @@ static void trace_path(const orc_scene *S, const orc_render_params *P, const orc
         }
         /* continue by phase sampling; spawn at the chord centre, skip self */
         double wi[3], wgt[3], pdf;
-        orc_phase_sample(mat, alb, rough, nrm, wo, g[0], g[1], wi, wgt, &pdf);
+        prim_phase_sample(S, k, wo, g[0], g[1], q5, wi, wgt, &pdf);
         if (!(pdf > 0.0)) break;
         for (int i = 0; i < 3; ++i) beta[i] *= wgt[i];
         if (beta[0] == 0.0 && beta[1] == 0.0 && beta[2] == 0.0) break;

@@ -78,6 +78,24 @@ void orc_phase_sample(int mat, const double alb[3], double rough, const double n
                       const double wo[3], double u1, double u2, double wi[3], double wgt[3],
                       double *pdf);
 
+/* SGGX microflake phase function with a Lambertian base BSDF (Sec. 4.2,
+ * eq. vndf, eq. phase_function, App. B); s6 = (xx, yy, zz, xy, xz, yz) of the
+ * symmetric positive-definite matrix S in the world frame; values per unit
+ * albedo.  what: 0 sigma(v), 1 D(v), 2 D_wo(v). */
+double orc_sggx_sigma(const double s6[6], const double w[3]);
+double orc_sggx_D(const double s6[6], const double n[3]);
+double orc_sggx_vndf(const double s6[6], const double wo[3], const double n[3]);
+void orc_sggx_sample_vndf(const double s6[6], const double wo[3], double u1, double u2, double n[3]);
+double orc_sggx_phase_est(const double s6[6], const double wo[3], const double wi[3], const double u[4]);
+double orc_sggx_phase_quad(const double s6[6], const double wo[3], const double wi[3], int nz, int nphi);
+double orc_sggx_pdf_approx(const double wo[3], const double wi[3]);
+void orc_sggx_eval_n(const double s6[6], int64_t n, const double *wo, const double *v, int what, double *out);
+void orc_sggx_sample_vndf_n(const double s6[6], const double wo[3], int64_t n, const double *u, double *nrm);
+void orc_sggx_phase_est_n(const double s6[6], const double wo[3], const double wi[3], int64_t n,
+                          const double *u, double *out);
+/* per-primitive SGGX matrices [n][6] (copied); material 2 needs them */
+int orc_scene_set_sggx(orc_scene *S, const float *sggx);
+
 int64_t orc_render(const orc_scene *S, const orc_camera *cam, const orc_render_params *p,
                    int64_t n_pix, const int64_t *pixels, int nthreads, double *sum, double *sumsq);
 void orc_path_radiance(const orc_scene *S, const orc_camera *cam, const orc_render_params *p,

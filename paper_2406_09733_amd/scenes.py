@@ -8,7 +8,9 @@ seed and uses numpy's PCG64, so a workload is reproduced exactly from its name.
 Scene dictionaries hold float32 / int32 numpy arrays:
   mean [n,3], scale [n,3] (>0), rotation [n,4] (w,x,y,z quaternion, any norm),
   density [n] (peak value of the Gaussian), albedo [n,3], roughness [n],
-  emission [n,3] (radiance, 0 = not emissive), material [n] (0 diffuse, 1 glossy)
+  emission [n,3] (radiance, 0 = not emissive), material [n] (0 diffuse, 1 glossy,
+  2 SGGX microflakes with a Lambertian base) and, where material 2 occurs,
+  sggx [n,6] (the SGGX matrix: xx, yy, zz, xy, xz, yz)
 and a "bounds" entry (lo, hi) used by camera set-up and the cache's position
 normalisation.
 
@@ -385,6 +387,56 @@ def perturbed(sc: dict, seed: int = 0, pos: float = 0.5, scale: float = 0.25, de
     out["density"] = (sc["density"] * rng.uniform(1 - dens, 1 + dens, n)).astype(np.float32)
     q = sc["rotation"] + rot * rng.normal(size=(n, 4))
     out["rotation"] = (q / np.linalg.norm(q, axis=1, keepdims=True)).astype(np.float32)
+    return out
+
+
+def _quat_axes(q):
+    """columns of the rotation matrices of unit quaternions (w, x, y, z) [n,4] -> [n,3,3]"""
+    w, x, y, z = (q[:, i] for i in range(4))
+    R = np.empty((q.shape[0], 3, 3))
+    R[:, 0, 0] = 1 - 2 * (y * y + z * z); R[:, 0, 1] = 2 * (x * y - w * z); R[:, 0, 2] = 2 * (x * z + w * y)
+    R[:, 1, 0] = 2 * (x * y + w * z); R[:, 1, 1] = 1 - 2 * (x * x + z * z); R[:, 1, 2] = 2 * (y * z - w * x)
+    R[:, 2, 0] = 2 * (x * z - w * y); R[:, 2, 1] = 2 * (y * z + w * x); R[:, 2, 2] = 1 - 2 * (x * x + y * y)
+    return R
+
+
+def with_sggx(sc: dict, seed: int = 0, frac: float = 0.5) -> dict:
+    """A copy of `sc` in which a random `frac` of the primitives are SGGX
+    microflake primitives (material 2) and every primitive carries an SGGX
+    matrix ("sggx" [n,6] = xx, yy, zz, xy, xz, yz).  The matrices are
+    S = V diag(l1, l2, l3) V^T in the primitive's own frame (V = its rotation,
+    axes sorted by scale), of three kinds drawn with equal probability, the
+    three configurations of the paper's phase-function figure:
+      surface-like: normals about the axis of the smallest scale,
+                    eigenvalue 1 there and r^2 on the other two, r ~ U[0.05, 0.5];
+      isotropic   : S = I (a sphere of flakes);
+      fibre-like  : normals orthogonal to the axis of the largest scale,
+                    eigenvalue r^2 there and 1 on the other two, r ~ U[0.05, 0.3].
+    Primitives that keep materials 0 / 1 hold the isotropic matrix."""
+    rng = _rng(seed)
+    n = sc["mean"].shape[0]
+    out = {k: (np.array(v, copy=True) if isinstance(v, np.ndarray) else v) for k, v in sc.items()}
+    q = np.asarray(sc["rotation"], np.float64)
+    q = q / np.linalg.norm(q, axis=1, keepdims=True)
+    R = _quat_axes(q)
+    order = np.argsort(np.asarray(sc["scale"], np.float64), axis=1)  # ascending
+    V = np.take_along_axis(R, order[:, None, :], axis=2)            # columns: smallest .. largest
+    kind = rng.integers(0, 3, n)
+    lam = np.ones((n, 3))
+    r_s = rng.uniform(0.05, 0.5, n)
+    r_f = rng.uniform(0.05, 0.3, n)
+    lam[kind == 0, 1] = r_s[kind == 0] ** 2
+    lam[kind == 0, 2] = r_s[kind == 0] ** 2
+    lam[kind == 2, 2] = r_f[kind == 2] ** 2
+    S = np.einsum("nij,nj,nkj->nik", V, lam, V)
+    S[kind == 1] = np.eye(3)
+    pick = rng.uniform(0, 1, n) < frac
+    out["material"] = np.where(pick, 2, np.asarray(sc["material"])).astype(np.int32)
+    out["sggx"] = np.stack([S[:, 0, 0], S[:, 1, 1], S[:, 2, 2], S[:, 0, 1], S[:, 0, 2], S[:, 1, 2]],
+                           1).astype(np.float32)
+    for k in range(n):
+        if not pick[k]:
+            out["sggx"][k] = (1, 1, 1, 0, 0, 0)
     return out
 
 

@@ -1,0 +1,268 @@
+"""Pins of the oracle's SGGX microflake phase function with a Lambertian base
+BSDF (Sec. 4.2: eq. vndf, eq. phase_function, the improved stochastic
+evaluation, importance sampling by visible normals, and the approximate MIS
+pdf of App. B).
+
+What fixes the values independently of the oracle's code:
+  * S = I is a sphere of Lambertian flakes, whose phase function is the
+    textbook diffuse-sphere law (8/3pi)(sin g + (pi - g) cos g) / (4 pi) in the
+    angle g between the two directions;
+  * the projected area sigma(w) = sqrt(w^T S w) equals the integral of the
+    clamped cosine against D, so a wrong determinant, inverse or exponent in
+    D breaks it; D_wo integrates to 1;
+  * a flat S (one eigenvalue 1, the others -> 0) reduces f_p to the Lambert
+    BSDF times the cosine about that axis (the delta-NDF limit of Sec. 4.2);
+  * the stochastic estimate is unbiased: its mean over many uniforms equals
+    the quadrature of eq. phase_function, and 4 pi times its mean over uniform
+    directions is 1 (a single scattering event with albedo 1 loses nothing);
+  * visible-normal samples have the moments of D_wo computed by quadrature.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2406_09733_amd import scenes
+
+
+def _unit(v):
+    v = np.asarray(v, np.float64)
+    return v / np.linalg.norm(v)
+
+
+def _s6(S):
+    return np.array([S[0, 0], S[1, 1], S[2, 2], S[0, 1], S[0, 2], S[1, 2]])
+
+
+def _rand_spd(rng, lam):
+    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    return q @ np.diag(lam) @ q.T
+
+
+def _sphere_grid(nz, nphi):
+    z = -1 + (np.arange(nz) + 0.5) * 2 / nz
+    ph = (np.arange(nphi) + 0.5) * 2 * np.pi / nphi
+    Z, P = np.meshgrid(z, ph, indexing="ij")
+    r = np.sqrt(1 - Z * Z)
+    n = np.stack([r * np.cos(P), r * np.sin(P), Z], -1).reshape(-1, 3)
+    return n, (2 / nz) * (2 * np.pi / nphi)
+
+
+def _lambert_sphere(g):
+    return (8 / (3 * np.pi)) * (np.sin(g) + (np.pi - g) * np.cos(g)) / (4 * np.pi)
+
+
+def test_isotropic_flakes_follow_the_diffuse_sphere_law(orc):
+    I6 = [1, 1, 1, 0, 0, 0]
+    wo = _unit([0.3, -0.2, 0.9])
+    rng = np.random.default_rng(0)
+    for g in [0.0, 0.4, 1.1, 1.9, 2.6, 3.0]:
+        # a direction at angle g from wo
+        t = _unit(np.cross(wo, [1.0, 0.0, 0.0]))
+        wi = math.cos(g) * wo + math.sin(g) * t
+        ref = _lambert_sphere(g)
+        assert orc.sggx_phase_quad(I6, wo, wi) == pytest.approx(ref, rel=2e-4, abs=1e-6)
+        est = orc.sggx_phase_est(I6, wo, wi, rng.uniform(0, 1, (40000, 4)))
+        se = est.std() / math.sqrt(est.size)
+        assert abs(est.mean() - ref) <= 5 * se + 1e-12, (g, est.mean(), ref, se)
+
+
+def test_projected_area_and_vndf_normalisation(orc):
+    rng = np.random.default_rng(1)
+    nrm, dA = _sphere_grid(600, 1200)
+    for lam in [(1.0, 0.3, 0.05), (1.0, 1.0, 0.2), (0.5, 0.05, 0.05)]:
+        S = _rand_spd(rng, lam)
+        s6 = _s6(S)
+        D = orc.sggx_D(s6, nrm)
+        for _ in range(3):
+            w = _unit(rng.normal(size=3))
+            sig = orc.sggx_sigma(s6, w[None])[0]
+            assert sig == pytest.approx(math.sqrt(w @ S @ w), rel=1e-12)
+            integral = (np.clip(nrm @ w, 0, None) * D).sum() * dA
+            assert integral == pytest.approx(sig, rel=2e-3)
+            vis = orc.sggx_vndf(s6, w, nrm)
+            assert vis.sum() * dA == pytest.approx(1.0, rel=2e-3)
+            assert np.all(vis[nrm @ w < 0] == 0)
+        # D is even in n and invariant under a rotation of both S and n
+        assert np.allclose(orc.sggx_D(s6, -nrm[:50]), D[:50], rtol=1e-12)
+        Q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+        D2 = orc.sggx_D(_s6(Q @ S @ Q.T), nrm[:200] @ Q.T)
+        assert np.allclose(D2, D[:200], rtol=1e-9)
+
+
+def test_flat_limit_is_the_lambert_bsdf_times_cosine(orc):
+    rng = np.random.default_rng(2)
+    n = _unit([0.2, 0.5, -0.8])
+    eps = 1e-6
+    S = np.outer(n, n) + eps * (np.eye(3) - np.outer(n, n))
+    s6 = _s6(S)
+    u = rng.uniform(0, 1, (4000, 4))
+    for _ in range(4):
+        wo = _unit(rng.normal(size=3))
+        wi = _unit(rng.normal(size=3))
+        side = np.sign(wo @ n)
+        ref = max(0.0, side * (wi @ n)) / math.pi
+        est = orc.sggx_phase_est(s6, wo, wi, u)
+        assert est.mean() == pytest.approx(ref, rel=2e-3, abs=2e-4)
+        # visible normals concentrate on the facet normal turned toward wo
+        # (an SGGX of eigenvalue ratio eps spreads like GGX with alpha =
+        # sqrt(eps): P(angle > 1e-2) is about 1%)
+        m = orc.sggx_sample_vndf(s6, wo, u[:, :2])
+        dev = np.linalg.norm(m - side * n, axis=1)
+        assert np.median(dev) < 2e-3 and np.mean(dev < 1e-2) > 0.97
+
+
+def test_estimator_is_unbiased_against_quadrature(orc):
+    rng = np.random.default_rng(3)
+    for lam in [(1.0, 0.2, 0.2), (1.0, 1.0, 0.04), (1.0, 0.5, 0.1)]:
+        S = _rand_spd(rng, lam)
+        s6 = _s6(S)
+        for _ in range(3):
+            wo = _unit(rng.normal(size=3))
+            wi = _unit(rng.normal(size=3))
+            ref = orc.sggx_phase_quad(s6, wo, wi, 800, 1600)
+            est = orc.sggx_phase_est(s6, wo, wi, rng.uniform(0, 1, (40000, 4)))
+            se = est.std() / math.sqrt(est.size)
+            assert abs(est.mean() - ref) <= 5 * se + 2e-4 * ref, (lam, est.mean(), ref, se)
+
+
+def test_single_scattering_conserves_energy(orc):
+    # per unit albedo the phase function integrates to 1 over incident directions
+    rng = np.random.default_rng(4)
+    for lam in [(1.0, 0.1, 0.1), (1.0, 1.0, 0.05)]:
+        s6 = _s6(_rand_spd(rng, lam))
+        wo = _unit(rng.normal(size=3))
+        tot, tot2, m = 0.0, 0.0, 0
+        for _ in range(2000):
+            wi = _unit(rng.normal(size=3))
+            e = orc.sggx_phase_est(s6, wo, wi, rng.uniform(0, 1, (8, 4)))
+            tot += e.sum(); tot2 += (e * e).sum(); m += e.size
+        mean = 4 * math.pi * tot / m
+        se = 4 * math.pi * math.sqrt(max(tot2 / m - (tot / m) ** 2, 0) / m)
+        assert abs(mean - 1.0) <= 5 * se, (mean, se)
+
+
+def test_visible_normal_samples_have_the_vndf_moments(orc):
+    rng = np.random.default_rng(5)
+    nrm, dA = _sphere_grid(600, 1200)
+    for lam in [(1.0, 0.3, 0.05), (1.0, 1.0, 1.0), (1.0, 0.02, 0.02)]:
+        s6 = _s6(_rand_spd(rng, lam))
+        wo = _unit(rng.normal(size=3))
+        m = orc.sggx_sample_vndf(s6, wo, rng.uniform(0, 1, (60000, 2)))
+        assert np.allclose(np.linalg.norm(m, axis=1), 1.0, atol=1e-12)
+        assert np.all(m @ wo >= -1e-12)
+        vis = orc.sggx_vndf(s6, wo, nrm) * dA
+        for h_s, h_q in [(m, nrm), (m[:, [0]] * m[:, [1, 2]], nrm[:, [0]] * nrm[:, [1, 2]]),
+                         (m * m, nrm * nrm)]:
+            ref = (h_q * vis[:, None]).sum(0)
+            se = h_s.std(0) / math.sqrt(h_s.shape[0])
+            assert np.all(np.abs(h_s.mean(0) - ref) <= 5 * se + 2e-3 * np.abs(ref)), (lam, h_s.mean(0), ref)
+
+
+def test_isotropic_sampling_follows_the_diffuse_sphere_law(orc):
+    # directions from visible-normal sampling followed by cosine sampling about
+    # the normal: for S = I their angle g to wo has density f_p(g) 2 pi sin g
+    rng = np.random.default_rng(6)
+    wo = _unit([0.0, 0.6, 0.8])
+    m = orc.sggx_sample_vndf([1, 1, 1, 0, 0, 0], wo, rng.uniform(0, 1, (200000, 2)))
+    # cosine sampling about each normal, written out here
+    u1, u2 = rng.uniform(0, 1, (2, m.shape[0]))
+    a = np.where(np.abs(m[:, [0]]) < 0.9, [[1.0, 0, 0]], [[0, 1.0, 0]])
+    b1 = np.cross(m, a); b1 /= np.linalg.norm(b1, axis=1, keepdims=True)
+    b2 = np.cross(m, b1)
+    r, ph = np.sqrt(u1), 2 * np.pi * u2
+    wi = (r * np.cos(ph))[:, None] * b1 + (r * np.sin(ph))[:, None] * b2 + np.sqrt(1 - u1)[:, None] * m
+    g = np.arccos(np.clip(wi @ wo, -1, 1))
+    edges = np.linspace(0, np.pi, 13)
+    hist = np.histogram(g, edges)[0] / g.size
+    fine = np.linspace(0, np.pi, 120001)
+    dens = _lambert_sphere(fine) * 2 * np.pi * np.sin(fine)
+    cdf = np.concatenate([[0], np.cumsum(0.5 * (dens[1:] + dens[:-1]) * np.diff(fine))])
+    p = np.diff(np.interp(edges, fine, cdf))
+    assert cdf[-1] == pytest.approx(1.0, abs=1e-6)
+    se = np.sqrt(p * (1 - p) / g.size)
+    assert np.all(np.abs(hist - p) <= 5 * se + 1e-4), (hist, p)
+
+
+def test_improved_estimator_beats_visible_normal_sampling_alone(orc):
+    # the internal MIS lowers the variance of the evaluation (the paper's
+    # comparison of its improved and naive stochastic evaluations), here for a
+    # rough surface-like configuration at grazing incidence
+    rng = np.random.default_rng(7)
+    n = _unit([0.0, 0.0, 1.0])
+    s6 = _s6(np.outer(n, n) + 0.3 ** 2 * (np.eye(3) - np.outer(n, n)))
+    wo = _unit([0.3, 0.0, 0.95])
+    wi = _unit([-0.99, 0.05, 0.12])
+    u = rng.uniform(0, 1, (100000, 4))
+    imp = orc.sggx_phase_est(s6, wo, wi, u)
+    m = orc.sggx_sample_vndf(s6, wo, u[:, :2])
+    naive = np.clip(m @ wi, 0, None) / math.pi
+    assert abs(imp.mean() - naive.mean()) <= 5 * math.hypot(imp.std(), naive.std()) / math.sqrt(u.shape[0])
+    assert imp.var() < 0.7 * naive.var(), (imp.var(), naive.var())
+
+
+def test_approximate_mis_pdf(orc):
+    # App. B: the diffuse component's pdf approximated by a cosine lobe of the
+    # half vector, <w_h . w_o> / pi
+    wo = _unit([0.1, 0.2, 0.97])
+    assert orc.sggx_pdf_approx(wo, wo) == pytest.approx(1 / math.pi, rel=1e-14)
+    t = _unit(np.cross(wo, [1.0, 0, 0]))
+    assert orc.sggx_pdf_approx(wo, t) == pytest.approx(math.cos(math.pi / 4) / math.pi, rel=1e-12)
+    assert orc.sggx_pdf_approx(wo, -wo) == 0.0
+
+
+def _sggx_furnace_scene():
+    sc = scenes.with_sggx(scenes.tiny_random(seed=21, n_emit=0), seed=3, frac=1.0)
+    sc["albedo"][:] = 1.0
+    return sc
+
+
+def test_white_furnace_sggx_phase_sampling_is_exact(orc):
+    sc = _sggx_furnace_scene()
+    assert (sc["material"] == 2).all()
+    S = orc.Scene(sc)
+    cam = dict(scenes.camera("tiny_random"), width=16, height=16)
+    s, _, _ = S.render(cam, {"spp": 8, "max_depth": 1000, "seed": 3, "env_radiance": (1, 1, 1),
+                             "mis_mode": 1})
+    assert np.allclose(s / 8, 1.0, rtol=0, atol=1e-12)
+
+
+def test_white_furnace_sggx_with_mis(orc):
+    # light (environment) sampling evaluates the stochastic estimate and
+    # weighs it with the approximate pdf: still an unbiased image of 1
+    sc = _sggx_furnace_scene()
+    S = orc.Scene(sc)
+    cam = dict(scenes.camera("tiny_random"), width=16, height=16)
+    spp = 32
+    s, s2, _ = S.render(cam, {"spp": spp, "max_depth": 1000, "seed": 4, "env_radiance": (1, 1, 1)})
+    mean = s.sum(0) / (s.shape[0] * spp)
+    var = s2.sum(0) / (s.shape[0] * spp) - mean ** 2
+    err = np.sqrt(var / (s.shape[0] * spp))
+    assert np.all(np.abs(mean - 1.0) <= 4 * err + 1e-12), (mean, err)
+
+
+def test_sggx_mis_estimators_agree(orc):
+    sc = scenes.with_sggx(scenes.tiny_random(seed=0, n_emit=200), seed=1, frac=0.7)
+    S = orc.Scene(sc)
+    cam = dict(scenes.camera("tiny_random"), width=24, height=24)
+    spp = 256
+    res = {}
+    for mode in (0, 1, 2):
+        s, s2, _ = S.render(cam, {"spp": spp, "max_depth": 3, "seed": 7 + mode, "mis_mode": mode})
+        npx = s.shape[0]
+        per = s.sum(1) / 3 / spp
+        var = (s2.sum(1) / 3 / spp - per ** 2).mean()
+        res[mode] = (s.sum() / (npx * spp * 3), math.sqrt(max(var, 0) / (npx * spp)))
+    for a in (1, 2):
+        assert abs(res[a][0] - res[0][0]) <= 3 * math.hypot(res[a][1], res[0][1]), res
+
+
+def test_scene_rejects_bad_sggx(orc):
+    sc = scenes.with_sggx(scenes.tiny_random(seed=0, n=50, n_emit=2), seed=1, frac=1.0)
+    sc["sggx"][7] = (1, 1, -1, 0, 0, 0)
+    with pytest.raises(ValueError):
+        orc.Scene(sc)
+    sc2 = scenes.tiny_random(seed=0, n=50, n_emit=2)
+    sc2["material"][3] = 2
+    with pytest.raises(ValueError):
+        orc.Scene(sc2)
