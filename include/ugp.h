@@ -55,13 +55,22 @@ typedef enum {
  *   albedo[n][3]    base colour: Lambert albedo, or GGX F0
  *   roughness[n]    GGX roughness in (0, 1]; alpha = roughness^2
  *   emission[n][3]  emitted radiance (0 = not an emitter)
- *   material[n]     int32: 0 = diffuse (Lambert), 1 = glossy (GGX); the phase
- *                   function is the delta-NDF limit of eq. phase_function with the
- *                   facet normal along the axis of the smallest scale            */
+ *   material[n]     int32: 0 = diffuse (Lambert), 1 = glossy (GGX): the delta-NDF
+ *                   limit of eq. phase_function with the facet normal along the
+ *                   axis of the smallest scale; 2 = SGGX microflakes with a
+ *                   Lambertian base BSDF (Sec. 4.2, eq. vndf and eq.
+ *                   phase_function: stochastic evaluation with internal MIS,
+ *                   visible-normal sampling, the approximate MIS pdf of App. B)
+ *   sggx[n][6]      SGGX matrix S per primitive (xx, yy, zz, xy, xz, yz), world
+ *                   frame, symmetric positive definite; may be NULL when no
+ *                   primitive has material 2.  When given, every row is checked
+ *                   (leading minors > 0, finite) and a bad row fails the build
+ *                   with UGP_ERR_INVALID_ARGUMENT, as does material 2 with NULL. */
 typedef struct {
     int64_t n;
     const float *mean, *scale, *rotation, *density, *albedo, *roughness, *emission;
     const int32_t *material;
+    const float *sggx;
 } ugp_scene;
 
 /* [host] pinhole camera: pixel (i, j), j = 0 at the top, jitter (jx, jy) in
@@ -338,6 +347,20 @@ ugp_status ugp_render_albedo_grad(ugp_ctx ctx, const ugp_camera *cam, const ugp_
 
 /* Waits for the context's stream and reports deferred device-side errors
  * (queue or stack overflow) as UGP_ERR_OVERFLOW, clearing them. */
+/* Test hook of the SGGX phase function (material 2; Sec. 4.2 and App. B), per
+ * unit albedo, for n independent queries (DEVICE arrays, float32):
+ *   sggx[n][6]  S (xx, yy, zz, xy, xz, yz), positive definite
+ *   dirs[n][6]  w_o (unit, pointing away from the primitive), w_i (unit)
+ *   u[n][6]     uniforms in [0,1): u0,u1 pick the visible normal of the
+ *               evaluation, u2,u3 the cosine-sampled normal about w_i; u0,u1 and
+ *               u4,u5 drive the importance sample (visible normal, then cosine
+ *               about it)
+ *   out[n][8]   f_p estimate at (w_i, w_o), approximate MIS pdf at (w_i, w_o),
+ *               the sampled direction (3), its approximate pdf, 2 zeros
+ * Enqueued on the context's stream; no scene is needed. */
+ugp_status ugp_sggx_phase(ugp_ctx ctx, int64_t n, const float *sggx, const float *dirs, const float *u,
+                          float *out);
+
 ugp_status ugp_sync(ugp_ctx ctx);
 
 /* [host] statistics of the last ugp_render call.  A "ray" is one traversal

@@ -83,6 +83,7 @@ def lib():
         L.orc_sggx_eval_n.argtypes = [vp, C.c_int64, vp, vp, C.c_int, vp]
         L.orc_sggx_sample_vndf_n.argtypes = [vp, vp, C.c_int64, vp, vp]
         L.orc_sggx_phase_est_n.argtypes = [vp, vp, vp, C.c_int64, vp, vp]
+        L.orc_sggx_sample_dir_n.argtypes = [vp, vp, C.c_int64, vp, vp]
         L.orc_scene_set_sggx.argtypes = [vp, vp]
         L.orc_render.argtypes = [vp, C.POINTER(_Camera), C.POINTER(_Params), C.c_int64, vp,
                                  C.c_int, vp, vp]
@@ -427,6 +428,16 @@ def sggx_sample_vndf(s6, wo, u) -> np.ndarray:
     o = np.ascontiguousarray(wo, dtype=np.float64).reshape(3)
     out = np.zeros((uu.shape[0], 3)); s = _s6(s6)
     lib().orc_sggx_sample_vndf_n(_addr(s), _addr(o), uu.shape[0], _addr(uu), _addr(out))
+    return out
+
+
+def sggx_sample_dir(s6, wo, u) -> np.ndarray:
+    """importance-sampled incident directions from uniforms u [n,4]: a visible
+    normal from u[:, :2], then cosine sampling about it from u[:, 2:]"""
+    uu = np.ascontiguousarray(u, dtype=np.float64).reshape(-1, 4)
+    o = np.ascontiguousarray(wo, dtype=np.float64).reshape(3)
+    out = np.zeros((uu.shape[0], 3)); s = _s6(s6)
+    lib().orc_sggx_sample_dir_n(_addr(s), _addr(o), uu.shape[0], _addr(uu), _addr(out))
     return out
 
 

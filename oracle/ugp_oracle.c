@@ -1111,6 +1111,15 @@ void orc_sggx_sample_vndf_n(const double s6[6], const double wo[3], int64_t n, c
     for (int64_t i = 0; i < n; ++i) orc_sggx_sample_vndf(s6, wo, u[2 * i], u[2 * i + 1], nrm + 3 * i);
 }
 
+/* importance samples: visible normal from u[0..1], then cosine about it from u[2..3] */
+void orc_sggx_sample_dir_n(const double s6[6], const double wo[3], int64_t n, const double *u, double *wi) {
+    for (int64_t i = 0; i < n; ++i) {
+        double m[3];
+        orc_sggx_sample_vndf(s6, wo, u[4 * i], u[4 * i + 1], m);
+        cosine_about(m, u[4 * i + 2], u[4 * i + 3], wi + 3 * i);
+    }
+}
+
 void orc_sggx_phase_est_n(const double s6[6], const double wo[3], const double wi[3], int64_t n, const double *u,
                           double *out) {
     for (int64_t i = 0; i < n; ++i) out[i] = orc_sggx_phase_est(s6, wo, wi, u + 4 * i);

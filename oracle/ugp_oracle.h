@@ -91,6 +91,7 @@ double orc_sggx_phase_quad(const double s6[6], const double wo[3], const double 
 double orc_sggx_pdf_approx(const double wo[3], const double wi[3]);
 void orc_sggx_eval_n(const double s6[6], int64_t n, const double *wo, const double *v, int what, double *out);
 void orc_sggx_sample_vndf_n(const double s6[6], const double wo[3], int64_t n, const double *u, double *nrm);
+void orc_sggx_sample_dir_n(const double s6[6], const double wo[3], int64_t n, const double *u, double *wi);
 void orc_sggx_phase_est_n(const double s6[6], const double wo[3], const double wi[3], int64_t n,
                           const double *u, double *out);
 /* per-primitive SGGX matrices [n][6] (copied); material 2 needs them */

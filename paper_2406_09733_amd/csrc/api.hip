@@ -333,6 +333,15 @@ ugp_status ugp_fit_adam(ugp_ctx ctx, int64_t n, float *mean, float *scale, float
                                   0.999f, 1e-8f, min_scale));
 }
 
+ugp_status ugp_sggx_phase(ugp_ctx ctx, int64_t n, const float *sggx, const float *dirs, const float *u,
+                          float *out) {
+    if (!ctx || n < 0) return UGP_ERR_INVALID_ARGUMENT;
+    if (n == 0) return UGP_OK;
+    if (!sggx || !dirs || !u || !out) return UGP_ERR_INVALID_ARGUMENT;
+    DeviceGuard g(ctx->device);
+    return from_hip(ugp::sggx_phase(ctx, n, sggx, dirs, u, out));
+}
+
 ugp_status ugp_sync(ugp_ctx ctx) {
     if (!ctx) return UGP_ERR_INVALID_ARGUMENT;
     DeviceGuard g(ctx->device);

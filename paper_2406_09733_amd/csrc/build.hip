@@ -28,6 +28,7 @@
 #include <vector>
 
 #include "ugp_internal.hpp"
+#include "ugp_math.hpp"
 
 namespace ugp {
 namespace {
@@ -217,6 +218,7 @@ struct PackIn {
     int64_t n;
     const float *mean, *scale, *rot, *dens, *alb, *rough, *emis;
     const int32_t *mat;
+    const float *sggx;  // [n][6] or null
     double r;
 };
 
@@ -244,7 +246,7 @@ __device__ __forceinline__ void quat_to_R(const PackIn &in, int64_t k, double R[
 }
 
 __global__ void k_pack(PackIn in, float *boxes, float4 *cold_tmp, float *mtmp, uint32_t *bounds,
-                       int32_t *pieces, uint32_t *err) {
+                       int32_t *pieces, float4 *sggx_out, uint32_t *err) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= in.n) return;
     const double qw = in.rot[4 * k], qx = in.rot[4 * k + 1], qy = in.rot[4 * k + 2], qz = in.rot[4 * k + 3];
@@ -253,8 +255,16 @@ __global__ void k_pack(PackIn in, float *boxes, float4 *cold_tmp, float *mtmp, u
     const double qn = qw * qw + qx * qx + qy * qy + qz * qz;
     const float d = in.dens[k];
     const int m = in.mat[k];
-    bool bad = !(qn > 0.0) || !isfinite(qn) || !(d >= 0.f) || !isfinite(d) || (m != 0 && m != 1);
+    bool bad = !(qn > 0.0) || !isfinite(qn) || !(d >= 0.f) || !isfinite(d) || m < 0 || m > 2 ||
+               (m == 2 && !in.sggx);
     for (int i = 0; i < 3; ++i) bad = bad || !(s[i] > 0.0) || !isfinite(s[i]) || !isfinite(mu[i]);
+    if (in.sggx) {
+        double g[6];
+        for (int i = 0; i < 6; ++i) g[i] = in.sggx[6 * k + i];
+        float4 rec[4];
+        bad = !sggx_prepare(g, rec) || bad;
+        for (int i = 0; i < 4; ++i) sggx_out[4 * k + i] = rec[i];
+    }
     if (bad) {
         atomicOr(err, 8u);
         for (int i = 0; i < 6; ++i) boxes[6 * k + i] = 0.f;
@@ -683,6 +693,7 @@ inline unsigned blocks(int64_t n) { return (unsigned)((n + kThreads - 1) / kThre
 void free_scene(SceneDev &sc) {
     hipFree(sc.hot);
     hipFree(sc.cold);
+    hipFree(sc.sggx);
     hipFree(sc.nodes);
     hipFree(sc.inv);
     hipFree(sc.emit);
@@ -705,7 +716,7 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
     sc.r_cut = r;
     std::vector<int32_t> levels4{0, 1};  // level L of the 4-wide nodes: [levels4[L], levels4[L + 1])
     PackIn in{n, s->mean, s->scale, s->rotation, s->density, s->albedo, s->roughness, s->emission,
-              s->material, r};
+              s->material, s->sggx, r};
     float *boxes = nullptr, *rbox = nullptr;
     float *mtmp = nullptr;
     uint32_t *bounds = nullptr, *keys = nullptr, *tk = nullptr;
@@ -737,8 +748,9 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
     UGP_CHECK(hipMemsetAsync(berr, 0, sizeof(uint32_t), st));
     UGP_CHECK(hipMemsetAsync(depth, 0, sizeof(int32_t), st));
     hipLaunchKernelGGL(k_init_bounds, dim3(1), dim3(64), 0, st, bounds);
+    if (s->sggx) UGP_CHECK(hipMalloc((void **)&sc.sggx, sizeof(float4) * 4 * n));
     hipLaunchKernelGGL(k_pack, dim3(blocks(n)), dim3(kThreads), 0, st, in, boxes, sc.cold, mtmp, bounds, pieces,
-                       berr);
+                       sc.sggx, berr);
     UGP_CHECK(hipGetLastError());
     UGP_CHECK(exclusive_scan(pieces, roff, n, st));
     UGP_CHECK(hipMemcpyAsync(&h_roff_last, roff + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -926,9 +938,9 @@ hipError_t refit_scene(ugp_ctx ctx, const ugp_scene *s) {
     SceneDev &sc = ctx->scene;
     const int64_t n = s->n, nr = sc.n_refs;
     PackIn in{n, s->mean, s->scale, s->rotation, s->density, s->albedo, s->roughness, s->emission,
-              s->material, sc.r_cut};
+              s->material, s->sggx, sc.r_cut};
     float *boxes = nullptr, *mtmp = nullptr, *lbox = nullptr;
-    float4 *cold = nullptr;
+    float4 *cold = nullptr, *sggx = nullptr;
     uint32_t *bounds = nullptr;
     int32_t *pieces = nullptr, *emit_flag = nullptr, *emit_pos = nullptr;
     uint32_t *berr = nullptr;
@@ -949,8 +961,9 @@ hipError_t refit_scene(ugp_ctx ctx, const ugp_scene *s) {
     UGP_CHECK(hipMallocAsync((void **)&berr, sizeof(uint32_t), st));
     UGP_CHECK(hipMemsetAsync(berr, 0, sizeof(uint32_t), st));
     hipLaunchKernelGGL(k_init_bounds, dim3(1), dim3(64), 0, st, bounds);
+    if (s->sggx) UGP_CHECK(hipMallocAsync((void **)&sggx, sizeof(float4) * 4 * n, st));
     hipLaunchKernelGGL(k_pack, dim3(blocks(n)), dim3(kThreads), 0, st, in, boxes, cold, mtmp, bounds, pieces,
-                       berr);
+                       sggx, berr);
     UGP_CHECK(hipGetLastError());
     UGP_CHECK(hipMemcpyAsync(&h_err, berr, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     UGP_CHECK(hipStreamSynchronize(st));
@@ -960,6 +973,14 @@ hipError_t refit_scene(ugp_ctx ctx, const ugp_scene *s) {
     }
     // records and leaf boxes, then the 4-wide nodes from the deepest level up
     UGP_CHECK(hipMemcpyAsync(sc.cold, cold, sizeof(float4) * 3 * n, hipMemcpyDeviceToDevice, st));
+    if (sggx) {
+        if (!sc.sggx) UGP_CHECK(hipMalloc((void **)&sc.sggx, sizeof(float4) * 4 * n));
+        UGP_CHECK(hipMemcpyAsync(sc.sggx, sggx, sizeof(float4) * 4 * n, hipMemcpyDeviceToDevice, st));
+    } else if (sc.sggx) {  // no material 2 any more (validated): drop the records
+        UGP_CHECK(hipStreamSynchronize(st));
+        hipFree(sc.sggx);
+        sc.sggx = nullptr;
+    }
     hipLaunchKernelGGL(k_refit_leaves, dim3(blocks(nr)), dim3(kThreads), 0, st, nr, in, (const float *)mtmp,
                        (const float *)boxes, sc.hot, lbox);
     for (int64_t L = (int64_t)lv.size() - 2; L >= 0; --L)
@@ -1000,13 +1021,14 @@ hipError_t refit_scene(ugp_ctx ctx, const ugp_scene *s) {
             sc.hi[c] = rootb[3 + c];
         }
     }
-    hipFreeAsync(boxes, st); hipFreeAsync(mtmp, st); hipFreeAsync(cold, st); hipFreeAsync(bounds, st);
+    hipFreeAsync(boxes, st); hipFreeAsync(mtmp, st); hipFreeAsync(cold, st); hipFreeAsync(sggx, st);
+    hipFreeAsync(bounds, st);
     hipFreeAsync(pieces, st); hipFreeAsync(lbox, st); hipFreeAsync(emit_flag, st); hipFreeAsync(emit_pos, st);
     hipFreeAsync(berr, st);
     return hipSuccess;
 fail:
     hipStreamSynchronize(st);
-    hipFree(boxes); hipFree(mtmp); hipFree(cold); hipFree(bounds); hipFree(pieces); hipFree(lbox);
+    hipFree(boxes); hipFree(mtmp); hipFree(cold); hipFree(sggx); hipFree(bounds); hipFree(pieces); hipFree(lbox);
     hipFree(emit_flag); hipFree(emit_pos); hipFree(berr);
     return e == hipSuccess ? hipErrorUnknown : e;
 }

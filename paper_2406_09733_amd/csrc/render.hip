@@ -364,6 +364,19 @@ struct ShadeOut {
     float4 r0{}, r1{}, r2{}, r3{}, r4{}, r5{};  // cache query / training record
 };
 
+// Phase function of primitive k at a path vertex for the direction wl
+// (world frame): f (rgb) and the pdf of phase sampling used by MIS.  The
+// SGGX microflakes (material 2) take the stochastic estimate from the four
+// uniforms of gs and the approximate pdf; the delta-NDF materials are exact.
+__device__ __forceinline__ V3 vertex_phase(int mat, const Sggx &sg, const Facet &F, V3 wo, V3 wol, V3 alb,
+                                           float rough, V3 wl, const Rng4 &gs, float &pdf) {
+    if (mat == 2) {
+        pdf = sggx_pdf_approx(wo, wl);
+        return sggx_phase_est(sg, wo, wl, gs.u[0], gs.u[1], gs.u[2], gs.u[3]) * alb;
+    }
+    return phase_eval_local(mat, alb, rough, wol, to_local(F, wl), pdf);
+}
+
 // Shading of one path vertex after its collision `hit` (prim, t bits):
 // emission pick-up (MIS against the light pdf of the previous vertex),
 // environment on escape, one light sample and one environment sample, phase
@@ -437,6 +450,11 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
             const int mat = __float_as_int(c0.w);
             const V3 alb = f3(c1);
             const float rough = c1.w;
+            // SGGX microflakes: their record, and the uniforms of the light and
+            // environment estimates (groups 3, 4) and of the cosine sample about
+            // the visible normal (group 5)
+            Sggx sg{};
+            if (mat == 2) sg = sggx_load(S.sggx + 4 * (int64_t)k);
             // light sample: one emitter, uniform in the cone of its bounding sphere
             if (S.n_emit > 0 && P.mis_mode != 1) {
                 // floor(u * n_emit) in exact integer arithmetic (u has 24 bits)
@@ -463,7 +481,8 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
                     onb(cd, b1, b2);
                     const V3 wl = (sint * cp) * b1 + (sint * sp) * b2 + cost * cd;
                     float pph;
-                    const V3 f = phase_eval_local(mat, alb, rough, wol, to_local(F, wl), pph);
+                    const Rng4 gs = mat == 2 ? path_rng(P, (uint32_t)pix, (uint32_t)v, 3) : Rng4{};
+                    const V3 f = vertex_phase(mat, sg, F, wo, wol, alb, rough, wl, gs, pph);
                     Chord tc;
                     const RayD lr = make_ray(x.x, x.y, x.z, wl.x, wl.y, wl.z, 0.f, __builtin_huge_val());
                     if (nonzero(f) && chord(load_hot(S.hot, es), lr, S.r2, tc)) {
@@ -489,7 +508,8 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
                 sincosf(2.f * kPi * g1.u[3], &sp, &cp);
                 const V3 wl = v3(rr * cp, rr * sp, z);
                 float pph;
-                const V3 f = phase_eval_local(mat, alb, rough, wol, to_local(F, wl), pph);
+                const Rng4 gs = mat == 2 ? path_rng(P, (uint32_t)pix, (uint32_t)v, 4) : Rng4{};
+                const V3 f = vertex_phase(mat, sg, F, wo, wol, alb, rough, wl, gs, pph);
                 if (nonzero(f)) {
                     const float pe = 0.25f * kInvPi;
                     const float w = P.mis_mode == 2 ? 1.f : pe / (pe + pph);
@@ -505,13 +525,21 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
                 }
             }
             // continue by phase sampling from the chord centre, skipping k
-            V3 wgt;
+            V3 wgt, wil, wi;
             float pdf;
-            const V3 wil = phase_sample_local(mat, alb, rough, wol, g1.u[0], g1.u[1], wgt, pdf);
+            if (mat == 2) {
+                const Rng4 g5 = path_rng(P, (uint32_t)pix, (uint32_t)v, 5);
+                wi = sggx_sample(sg, wo, g1.u[0], g1.u[1], g5.u[0], g5.u[1]);
+                wil = wol;  // (the albedo ratio of material 2 does not depend on directions)
+                wgt = alb;
+                pdf = sggx_pdf_approx(wo, wi);
+            } else {
+                wil = phase_sample_local(mat, alb, rough, wol, g1.u[0], g1.u[1], wgt, pdf);
+                wi = to_world(F, wil);
+            }
             if (pdf > 0.f) {
                 beta = mul(beta, wgt);
                 if (nonzero(beta)) {
-                    const V3 wi = to_world(F, wil);
                     out.cont = true;
                     if (P.adj.dimg) {
                         const V3 q = phase_albedo_ratio(mat, alb, wol, wil);
@@ -1228,6 +1256,38 @@ hipError_t render_nrc_records(ugp_ctx ctx, int64_t cap, float *rec_out, float *t
     }
     *count = n;
     return hipSuccess;
+}
+
+// Test hook of the SGGX phase function: per query the record prepared from
+// the six inputs, the stochastic estimate, the approximate pdf, and an
+// importance sample with its approximate pdf (layout in ugp_sggx_phase).
+__global__ __launch_bounds__(256) void k_sggx_phase(int64_t n, const float *sggx, const float *dirs, const float *u,
+                                                    float *out) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        double g6[6];
+        for (int j = 0; j < 6; ++j) g6[j] = sggx[6 * i + j];
+        float4 rec[4];
+        float *o = out + 8 * i;
+        if (!sggx_prepare(g6, rec)) {
+            for (int j = 0; j < 8; ++j) o[j] = __builtin_nanf("");
+            continue;
+        }
+        const Sggx g = sggx_load(rec);
+        const float *d = dirs + 6 * i, *r = u + 6 * i;
+        const V3 wo = v3(d[0], d[1], d[2]), wi = v3(d[3], d[4], d[5]);
+        o[0] = sggx_phase_est(g, wo, wi, r[0], r[1], r[2], r[3]);
+        o[1] = sggx_pdf_approx(wo, wi);
+        const V3 ws = sggx_sample(g, wo, r[0], r[1], r[4], r[5]);
+        o[2] = ws.x; o[3] = ws.y; o[4] = ws.z;
+        o[5] = sggx_pdf_approx(wo, ws);
+        o[6] = 0.f; o[7] = 0.f;
+    }
+}
+
+hipError_t sggx_phase(ugp_ctx ctx, int64_t n, const float *sggx, const float *dirs, const float *u, float *out) {
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_sggx_phase, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, n, sggx, dirs, u, out);
+    return hipGetLastError();
 }
 
 }  // namespace ugp

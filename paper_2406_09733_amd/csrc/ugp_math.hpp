@@ -1,5 +1,5 @@
 // ugp_math.hpp -- device math for libugp: small vectors, the Philox4x32-10
-// counter-based generator, orthonormal frames, the delta-NDF phase functions
+// counter-based generator, orthonormal frames, the delta-NDF and SGGX phase functions
 // and the pinhole camera.  FP32 unless a name says otherwise.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -134,7 +134,7 @@ __device__ inline V3 phase_eval_local(int mat, V3 alb, float rough, V3 wo, V3 wi
 // ratio.  A channel whose f is zero (a diffuse one of zero albedo) reports 0.
 __device__ inline V3 phase_albedo_ratio(int mat, V3 alb, V3 wo, V3 wi) {
     auto r = [](float num, float den) __attribute__((always_inline)) { return den > 0.f ? num / den : 0.f; };
-    if (mat == 0) return v3(r(1.f, alb.x), r(1.f, alb.y), r(1.f, alb.z));
+    if (mat != 1) return v3(r(1.f, alb.x), r(1.f, alb.y), r(1.f, alb.z));  // Lambert and SGGX-Lambert
     const V3 h = normalize(wo + wi);
     const float m = pow5(1.f - fmaxf(0.f, dot(wi, h)));
     return v3(r(1.f - m, alb.x + (1.f - alb.x) * m), r(1.f - m, alb.y + (1.f - alb.y) * m),
@@ -182,6 +182,128 @@ __device__ inline V3 phase_sample_local(int mat, V3 alb, float rough, V3 wo, flo
     wgt = v3((alb.x + (1.f - alb.x) * sch) * k, (alb.y + (1.f - alb.y) * sch) * k,
              (alb.z + (1.f - alb.z) * sch) * k);
     return wi;
+}
+
+// ---------------------------------------------------------------------------
+// SGGX microflakes with a Lambertian base BSDF (material 2; Sec. 4.2, eq. vndf,
+// eq. phase_function; App. B), in the world frame, per unit albedo.
+// S is symmetric positive definite.  The flakes' normals are those of the
+// ellipsoid x^T S x = 1: D(n) = 1 / (pi sqrt(det S) (n^T S^-1 n)^2), projected
+// area sigma(w) = sqrt(w^T S w), visible normals D_wo(n) = <wo.n> D(n) /
+// sigma(wo).  Per primitive a 64-B record, prepared in FP64 from the six
+// float inputs (the inverse of a flat S cancels badly in FP32):
+//   [0] S xx, yy, zz, xy   [1] S xz, yz, S^-1 xx, yy
+//   [2] S^-1 zz, xy, xz, yz   [3] 1 / (pi sqrt(det S)), 0, 0, 0
+// ---------------------------------------------------------------------------
+struct Sggx {
+    float xx, yy, zz, xy, xz, yz;        // S
+    float ixx, iyy, izz, ixy, ixz, iyz;  // S^-1
+    float dn;                            // 1 / (pi sqrt(det S))
+};
+
+// record of s = (xx, yy, zz, xy, xz, yz); false (record zeroed) unless S is
+// finite and positive definite (leading minors > 0)
+__device__ inline bool sggx_prepare(const double s[6], float4 rec[4]) {
+    const double xx = s[0], yy = s[1], zz = s[2], xy = s[3], xz = s[4], yz = s[5];
+    const double axx = yy * zz - yz * yz, ayy = xx * zz - xz * xz, azz = xx * yy - xy * xy;
+    const double axy = xz * yz - xy * zz, axz = xy * yz - xz * yy, ayz = xy * xz - xx * yz;
+    const double det = xx * axx + xy * axy + xz * axz;
+    bool ok = xx > 0.0 && azz > 0.0 && det > 0.0 && isfinite(det);
+    for (int i = 0; i < 6; ++i) ok = ok && isfinite(s[i]);
+    if (!ok) {
+        for (int i = 0; i < 4; ++i) rec[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        return false;
+    }
+    const double id = 1.0 / det;
+    rec[0] = make_float4((float)xx, (float)yy, (float)zz, (float)xy);
+    rec[1] = make_float4((float)xz, (float)yz, (float)(axx * id), (float)(ayy * id));
+    rec[2] = make_float4((float)(azz * id), (float)(axy * id), (float)(axz * id), (float)(ayz * id));
+    rec[3] = make_float4((float)(1.0 / (3.14159265358979323846 * sqrt(det))), 0.f, 0.f, 0.f);
+    return true;
+}
+
+__device__ __forceinline__ Sggx sggx_load(const float4 *rec) {
+    const float4 a = rec[0], b = rec[1], c = rec[2], d = rec[3];
+    return Sggx{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w, d.x};
+}
+__device__ __forceinline__ V3 sggx_S(const Sggx &g, V3 v) {
+    return v3(g.xx * v.x + g.xy * v.y + g.xz * v.z, g.xy * v.x + g.yy * v.y + g.yz * v.z,
+              g.xz * v.x + g.yz * v.y + g.zz * v.z);
+}
+__device__ __forceinline__ V3 sggx_Sinv(const Sggx &g, V3 v) {
+    return v3(g.ixx * v.x + g.ixy * v.y + g.ixz * v.z, g.ixy * v.x + g.iyy * v.y + g.iyz * v.z,
+              g.ixz * v.x + g.iyz * v.y + g.izz * v.z);
+}
+__device__ __forceinline__ float sggx_sigma(const Sggx &g, V3 w) { return sqrtf(fmaxf(0.f, dot(w, sggx_S(g, w)))); }
+// D_wo(n) given sigma(wo)
+__device__ __forceinline__ float sggx_vndf(const Sggx &g, V3 wo, V3 n, float sig_o) {
+    const float c = dot(wo, n);
+    if (!(c > 0.f) || !(sig_o > 0.f)) return 0.f;
+    const float q = dot(n, sggx_Sinv(g, n));
+    return c * (g.dn / (q * q)) / sig_o;
+}
+
+// A visible normal: a point uniform in the ellipsoid's shadow along wo (the
+// ellipse of the 2x2 matrix [e_a^T S^-1 e_b] on the plane (e1, e2) orthogonal
+// to wo, from the unit disk by its Cholesky factor), lifted to the front
+// surface x = q + t wo (larger root of x^T S x = 1); the normal is S x.
+__device__ inline V3 sggx_sample_vndf(const Sggx &g, V3 wo, float u1, float u2) {
+    V3 e1, e2;
+    onb(wo, e1, e2);
+    const V3 i2 = sggx_Sinv(g, e2);
+    const float s11 = dot(e1, sggx_Sinv(g, e1)), s22 = dot(e2, i2), s12 = dot(e1, i2);
+    const float l11 = sqrtf(s11), l21 = s12 / l11, l22 = sqrtf(fmaxf(0.f, s22 - l21 * l21));
+    const float r = sqrtf(u1);
+    float sp, cp;
+    sincosf(2.f * kPi * u2, &sp, &cp);
+    const float a = r * cp, b = r * sp;
+    const V3 q = (l11 * a) * e1 + (l21 * a + l22 * b) * e2;
+    const V3 Sw = sggx_S(g, wo), Sq = sggx_S(g, q);
+    const float A = dot(wo, Sw), B = dot(q, Sw), C = dot(q, Sq) - 1.f;
+    const float disc = sqrtf(fmaxf(0.f, B * B - A * C));
+    const float t = B > 0.f ? -C / (B + disc) : (disc - B) / A;  // the larger root, without cancellation
+    return normalize(Sq + t * Sw);
+}
+
+// a direction cosine-distributed about the unit vector m
+__device__ __forceinline__ V3 cosine_about(V3 m, float u1, float u2) {
+    V3 b1, b2;
+    onb(m, b1, b2);
+    const float r = sqrtf(u1), z = sqrtf(fmaxf(0.f, 1.f - u1));
+    float sp, cp;
+    sincosf(2.f * kPi * u2, &sp, &cp);
+    return (r * cp) * b1 + (r * sp) * b2 + z * m;
+}
+
+// Stochastic evaluation of f_p(wi, wo) / albedo with internal MIS: one normal
+// from the visible NDF (u0, u1) and one from the Lambertian base's sampling
+// reversed, cosine-distributed about wi (u2, u3), each weighted by the
+// one-sample balance heuristic between the two densities.
+__device__ inline float sggx_phase_est(const Sggx &g, V3 wo, V3 wi, float u0, float u1, float u2, float u3) {
+    const float so = sggx_sigma(g, wo);
+    const V3 n1 = sggx_sample_vndf(g, wo, u0, u1);
+    const float p1 = sggx_vndf(g, wo, n1, so);
+    const float f1 = fmaxf(0.f, dot(wi, n1)) * kInvPi;  // base BSDF at n1, also n1's density about wi
+    float est = p1 > 0.f ? f1 * p1 / (p1 + f1) : 0.f;
+    const V3 n3 = cosine_about(wi, u2, u3);
+    const float p3 = sggx_vndf(g, wo, n3, so);
+    const float c3 = fmaxf(0.f, dot(n3, wi)) * kInvPi;
+    if (c3 > 0.f && p3 > 0.f) est += p3 * c3 / (c3 + p3);
+    return est;
+}
+
+// The approximate MIS pdf of the Lambertian component (App. B): <w_h . w_o> / pi.
+__device__ __forceinline__ float sggx_pdf_approx(V3 wo, V3 wi) {
+    const V3 h = wo + wi;
+    const float l2 = dot(h, h);
+    return l2 > 0.f ? fmaxf(0.f, dot(h, wo)) * rsqrtf(l2) * kInvPi : 0.f;
+}
+
+// Importance sampling (Sec. 4.2): a visible normal, then the base BSDF's
+// cosine sampling about it; weight = albedo (the visible-normal sampling is
+// exact), pdf reported for MIS = the approximate one.
+__device__ __forceinline__ V3 sggx_sample(const Sggx &g, V3 wo, float u0, float u1, float v0, float v1) {
+    return cosine_about(sggx_sample_vndf(g, wo, u0, u1), v0, v1);
 }
 
 // Camera set up on the host: origin, forward f, right r' = tan(vfov/2) aspect r,

@@ -164,14 +164,7 @@ def test_isotropic_sampling_follows_the_diffuse_sphere_law(orc):
     # the normal: for S = I their angle g to wo has density f_p(g) 2 pi sin g
     rng = np.random.default_rng(6)
     wo = _unit([0.0, 0.6, 0.8])
-    m = orc.sggx_sample_vndf([1, 1, 1, 0, 0, 0], wo, rng.uniform(0, 1, (200000, 2)))
-    # cosine sampling about each normal, written out here
-    u1, u2 = rng.uniform(0, 1, (2, m.shape[0]))
-    a = np.where(np.abs(m[:, [0]]) < 0.9, [[1.0, 0, 0]], [[0, 1.0, 0]])
-    b1 = np.cross(m, a); b1 /= np.linalg.norm(b1, axis=1, keepdims=True)
-    b2 = np.cross(m, b1)
-    r, ph = np.sqrt(u1), 2 * np.pi * u2
-    wi = (r * np.cos(ph))[:, None] * b1 + (r * np.sin(ph))[:, None] * b2 + np.sqrt(1 - u1)[:, None] * m
+    wi = orc.sggx_sample_dir([1, 1, 1, 0, 0, 0], wo, rng.uniform(0, 1, (200000, 4)))
     g = np.arccos(np.clip(wi @ wo, -1, 1))
     edges = np.linspace(0, np.pi, 13)
     hist = np.histogram(g, edges)[0] / g.size
