@@ -85,6 +85,18 @@ def lib():
         L.orc_sggx_phase_est_n.argtypes = [vp, vp, vp, C.c_int64, vp, vp]
         L.orc_sggx_sample_dir_n.argtypes = [vp, vp, C.c_int64, vp, vp]
         L.orc_scene_set_sggx.argtypes = [vp, vp]
+        L.orc_scene_set_metallic.argtypes = [vp, vp]
+        L.orc_disney_spec_prob.argtypes = [vp, C.c_double]
+        L.orc_disney_spec_prob.restype = C.c_double
+        L.orc_disney_base.argtypes = [vp, C.c_double, C.c_double, vp, vp, vp, vp, vp]
+        L.orc_sggx_disney_est.argtypes = [vp, vp, C.c_double, C.c_double, vp, vp, vp, vp]
+        L.orc_sggx_disney_sample.argtypes = [vp, vp, C.c_double, C.c_double, vp, C.c_double, C.c_double, vp,
+                                             vp, vp]
+        L.orc_sggx_disney_sample.restype = C.c_int
+        L.orc_sggx_roughened.argtypes = [vp, C.c_double, vp]
+        L.orc_sggx_disney_pdf_approx.argtypes = [vp, vp, C.c_double, C.c_double, vp, vp]
+        L.orc_sggx_disney_pdf_approx.restype = C.c_double
+        L.orc_sggx_disney_quad.argtypes = [vp, vp, C.c_double, C.c_double, vp, vp, C.c_int, C.c_int, vp]
         L.orc_render.argtypes = [vp, C.POINTER(_Camera), C.POINTER(_Params), C.c_int64, vp,
                                  C.c_int, vp, vp]
         L.orc_render.restype = C.c_int64
@@ -167,8 +179,13 @@ class Scene:
             self._keep["sggx"] = g
             if n and lib().orc_scene_set_sggx(self.h, _addr(g)) != 0:
                 raise ValueError("oracle rejected the SGGX matrices (not positive definite)")
-        elif n and bool((mats == 2).any()):
-            raise ValueError("material 2 (SGGX microflakes) needs scene['sggx']")
+        elif n and bool((mats >= 2).any()):
+            raise ValueError("materials 2 and 3 (SGGX microflakes) need scene['sggx']")
+        if scene.get("metallic") is not None:
+            mt = np.ascontiguousarray(scene["metallic"], dtype=np.float32).reshape(n)
+            self._keep["metallic"] = mt
+            if n and lib().orc_scene_set_metallic(self.h, _addr(mt)) != 0:
+                raise ValueError("oracle rejected the metallic values (outside [0, 1])")
         self.use_bvh = 0
         if bvh:
             lib().orc_scene_build_bvh(self.h)
@@ -457,6 +474,67 @@ def sggx_phase_quad(s6, wo, wi, nz: int = 400, nphi: int = 800) -> float:
     i = np.ascontiguousarray(wi, dtype=np.float64).reshape(3)
     s = _s6(s6)
     return lib().orc_sggx_phase_quad(_addr(s), _addr(o), _addr(i), int(nz), int(nphi))
+
+
+def _v3(v):
+    return np.ascontiguousarray(v, dtype=np.float64).reshape(3)
+
+
+def disney_spec_prob(c, met) -> float:
+    return lib().orc_disney_spec_prob(_addr(_v3(c)), float(met))
+
+
+def disney_base(c, rough, met, n, wo, wi):
+    """(specular, diffuse) cosine-weighted base BSDF at the flake normal n"""
+    fs = np.zeros(3); fd = np.zeros(3)
+    cc, nn, o, i = _v3(c), _v3(n), _v3(wo), _v3(wi)
+    lib().orc_disney_base(_addr(cc), float(rough), float(met), _addr(nn), _addr(o), _addr(i), _addr(fs), _addr(fd))
+    return fs, fd
+
+
+def sggx_disney_est(s6, c, rough, met, wo, wi, u) -> np.ndarray:
+    """material 3: improved stochastic estimates of f_p (rgb) from uniforms u [n,6]"""
+    uu = np.ascontiguousarray(u, dtype=np.float64).reshape(-1, 6)
+    out = np.zeros((uu.shape[0], 3)); s = _s6(s6)
+    cc, o, i = _v3(c), _v3(wo), _v3(wi)
+    for k in range(uu.shape[0]):
+        lib().orc_sggx_disney_est(_addr(s), _addr(cc), float(rough), float(met), _addr(o), _addr(i),
+                                  _addr(uu[k]), out[k].ctypes.data)
+    return out
+
+
+def sggx_disney_sample(s6, c, rough, met, wo, u):
+    """material 3: importance samples from uniforms u [n,5] (visible normal u0,u1;
+    lobe u2; direction u3,u4) -> (wi [n,3], weight [n,3], ok [n])"""
+    uu = np.ascontiguousarray(u, dtype=np.float64).reshape(-1, 5)
+    wi = np.zeros((uu.shape[0], 3)); w = np.zeros((uu.shape[0], 3)); ok = np.zeros(uu.shape[0], bool)
+    s, cc, o = _s6(s6), _v3(c), _v3(wo)
+    for k in range(uu.shape[0]):
+        v = np.ascontiguousarray(uu[k, 2:5])
+        ok[k] = bool(lib().orc_sggx_disney_sample(_addr(s), _addr(cc), float(rough), float(met), _addr(o),
+                                                  float(uu[k, 0]), float(uu[k, 1]), _addr(v),
+                                                  wi[k].ctypes.data, w[k].ctypes.data))
+    return wi, w, ok
+
+
+def sggx_roughened(s6, rough) -> np.ndarray:
+    out = np.zeros(6); s = _s6(s6)
+    lib().orc_sggx_roughened(_addr(s), float(rough), _addr(out))
+    return out
+
+
+def sggx_disney_pdf_approx(s6, c, rough, met, wo, wi) -> float:
+    s, cc, o, i = _s6(s6), _v3(c), _v3(wo), _v3(wi)
+    return lib().orc_sggx_disney_pdf_approx(_addr(s), _addr(cc), float(rough), float(met), _addr(o), _addr(i))
+
+
+def sggx_disney_quad(s6, c, rough, met, wo, wi, nz: int = 400, nphi: int = 800) -> np.ndarray:
+    """material 3: f_p (rgb) by midpoint quadrature over the sphere of normals"""
+    f = np.zeros(3)
+    s, cc, o, i = _s6(s6), _v3(c), _v3(wo), _v3(wi)
+    lib().orc_sggx_disney_quad(_addr(s), _addr(cc), float(rough), float(met), _addr(o), _addr(i), int(nz),
+                               int(nphi), _addr(f))
+    return f
 
 
 def sggx_pdf_approx(wo, wi) -> float:

@@ -125,8 +125,10 @@ struct orc_scene {
     double *alb;   /* [n][3] */
     double *rough; /* [n] */
     double *emis;  /* [n][3] */
-    int32_t *mat;  /* [n] 0 Lambert, 1 GGX (delta NDF), 2 Lambert microflakes with an SGGX NDF */
+    int32_t *mat;  /* [n] 0 Lambert, 1 GGX (delta NDF), 2 / 3 microflakes with an SGGX NDF and a
+                      Lambertian / Disney-style base BSDF */
     double *sggx;  /* [n][6] SGGX matrix (xx, yy, zz, xy, xz, yz), world frame; NULL if none */
+    double *met;   /* [n] metallic of material 3's base BSDF; NULL = 0 */
     double *lo, *hi;  /* [n][3] axis-aligned box of the cut-off ellipsoid */
     double *rsph;  /* [n] radius of the bounding sphere, r * max(s) */
     int64_t *emitters;
@@ -207,7 +209,7 @@ void orc_scene_destroy(orc_scene *S) {
     if (!S) return;
     free(S->mu); free(S->M); free(S->d); free(S->nrm); free(S->alb); free(S->rough);
     free(S->emis); free(S->mat); free(S->lo); free(S->hi); free(S->rsph); free(S->emitters);
-    free(S->sggx);
+    free(S->sggx); free(S->met);
     free(S->nodes); free(S->perm);
     free(S);
 }
@@ -1044,6 +1046,245 @@ double orc_sggx_pdf_approx(const double wo[3], const double wi[3]) {
     return fmax(0.0, dot3(h, wo) / l) / M_PI;
 }
 
+/* ------------------------------------------------------------------------- */
+/* SGGX microflakes with a Disney-style base BSDF (material 3; Sec. 4.2: a    */
+/* microfacet specular component and a diffuse component with empirical       */
+/* retro-reflection, Burley 2012/2015).  The base BSDF at a flake normal n,   */
+/* cosine-weighted, for base colour c, roughness r (alpha = r^2 for the       */
+/* specular lobe, r itself in the diffuse retro-reflection) and metallic m:   */
+/*   specular: F D G2 / (4 <n.wo>), GGX D and height-correlated Smith G2 in   */
+/*             the frame of n, Schlick F with F0 = 0.04 (1 - m) + c m;        */
+/*   diffuse : (1 - m) c / pi (1 + (F_D90 - 1)(1 - <n.wi>)^5)                 */
+/*             (1 + (F_D90 - 1)(1 - <n.wo>)^5) <n.wi>,                        */
+/*             F_D90 = 1/2 + 2 r <wi.h>^2;                                    */
+/* zero unless wi and wo are both on the side of n.                           */
+/* ------------------------------------------------------------------------- */
+
+static void disney_base(const double c[3], double rough, double met, const double n[3], const double wo[3],
+                        const double wi[3], double fs[3], double fd[3]) {
+    double b1[3], b2[3], lo[3], li[3];
+    for (int k = 0; k < 3; ++k) fs[k] = fd[k] = 0.0;
+    onb(n, b1, b2);
+    to_local(b1, b2, n, wo, lo);
+    to_local(b1, b2, n, wi, li);
+    if (lo[2] <= 0.0 || li[2] <= 0.0) return;
+    double a = ggx_alpha(rough);
+    double h[3] = {lo[0] + li[0], lo[1] + li[1], lo[2] + li[2]};
+    normalize3(h);
+    double D = ggx_D(a, h[2]);
+    double G2 = 1.0 / (1.0 + ggx_lambda(a, lo[2]) + ggx_lambda(a, li[2]));
+    double cd = fmax(0.0, dot3(li, h));
+    double sch = pow(1.0 - cd, 5.0);
+    double fd90 = 0.5 + 2.0 * rough * cd * cd;
+    double rl = 1.0 + (fd90 - 1.0) * pow(1.0 - li[2], 5.0), rv = 1.0 + (fd90 - 1.0) * pow(1.0 - lo[2], 5.0);
+    for (int k = 0; k < 3; ++k) {
+        double F0 = 0.04 * (1.0 - met) + c[k] * met;
+        fs[k] = (F0 + (1.0 - F0) * sch) * D * G2 / (4.0 * lo[2]);
+        fd[k] = (1.0 - met) * c[k] / M_PI * rl * rv * li[2];
+    }
+}
+
+/* probability of choosing the specular lobe when sampling the base BSDF:
+ * weights 1 (specular) and (1 - m) times the base colour's luminance (diffuse) */
+double orc_disney_spec_prob(const double c[3], double met) {
+    double lum = 0.2126 * c[0] + 0.7152 * c[1] + 0.0722 * c[2];
+    return 1.0 / (1.0 + (1.0 - met) * lum);
+}
+
+/* pdf of sampling the base BSDF at n: the lobe mixture of GGX visible-normal
+ * reflection, G1(wo) D / (4 <n.wo>), and cosine sampling, <n.wi> / pi */
+static double disney_base_pdf(double ps, double rough, const double n[3], const double wo[3], const double wi[3]) {
+    double b1[3], b2[3], lo[3], li[3];
+    onb(n, b1, b2);
+    to_local(b1, b2, n, wo, lo);
+    to_local(b1, b2, n, wi, li);
+    if (lo[2] <= 0.0 || li[2] <= 0.0) return 0.0;
+    double a = ggx_alpha(rough);
+    double h[3] = {lo[0] + li[0], lo[1] + li[1], lo[2] + li[2]};
+    normalize3(h);
+    double G1 = 1.0 / (1.0 + ggx_lambda(a, lo[2]));
+    return ps * G1 * ggx_D(a, h[2]) / (4.0 * lo[2]) + (1.0 - ps) * li[2] / M_PI;
+}
+
+/* a normal n about the half vector h with density D(<n.h>) <n.h> (the GGX
+ * normal distribution's own sampling, Walter et al. 2007, with the roles of
+ * normal and half vector exchanged) */
+static void ggx_ndf_about(const double h[3], double a, double u1, double u2, double n[3]) {
+    double b1[3], b2[3];
+    onb(h, b1, b2);
+    double t2 = a * a * u1 / (1.0 - u1);
+    double ct = 1.0 / sqrt(1.0 + t2), st = sqrt(fmax(0.0, 1.0 - ct * ct)), ph = 2.0 * M_PI * u2;
+    for (int i = 0; i < 3; ++i) n[i] = st * cos(ph) * b1[i] + st * sin(ph) * b2[i] + ct * h[i];
+}
+
+/* Improved stochastic evaluation of f_p (Sec. 4.2, "Evaluation"): per lobe,
+ * one normal from the visible NDF (u0, u1) combined by the one-sample balance
+ * heuristic with one normal from the lobe's own sampling reversed -- for the
+ * specular lobe a GGX normal about the half vector (u2, u3), for the diffuse
+ * lobe a normal cosine-distributed about wi (u4, u5).  f[3] = estimate. */
+void orc_sggx_disney_est(const double s6[6], const double c[3], double rough, double met, const double wo[3],
+                         const double wi[3], const double u[6], double f[3]) {
+    double a = ggx_alpha(rough);
+    double n1[3], n2[3], n3[3], fs[3], fd[3], h[3] = {wo[0] + wi[0], wo[1] + wi[1], wo[2] + wi[2]};
+    for (int k = 0; k < 3; ++k) f[k] = 0.0;
+    orc_sggx_sample_vndf(s6, wo, u[0], u[1], n1);
+    double p1 = orc_sggx_vndf(s6, wo, n1);
+    if (p1 > 0.0) {
+        disney_base(c, rough, met, n1, wo, wi, fs, fd);
+        double hl = sqrt(dot3(h, h)), hn = 0.0;
+        if (hl > 0.0) hn = dot3(h, n1) / hl;
+        double pm = hn > 0.0 ? ggx_D(a, hn) * hn : 0.0;
+        double pc = fmax(0.0, dot3(wi, n1)) / M_PI;
+        for (int k = 0; k < 3; ++k) f[k] += fs[k] * p1 / (p1 + pm) + fd[k] * p1 / (p1 + pc);
+    }
+    double hl = sqrt(dot3(h, h));
+    if (hl > 0.0) {
+        for (int i = 0; i < 3; ++i) h[i] /= hl;
+        ggx_ndf_about(h, a, u[2], u[3], n2);
+        double hn = dot3(n2, h);
+        double p2 = hn > 0.0 ? ggx_D(a, hn) * hn : 0.0;
+        double v2 = orc_sggx_vndf(s6, wo, n2);
+        if (p2 > 0.0 && v2 > 0.0) {
+            disney_base(c, rough, met, n2, wo, wi, fs, fd);
+            for (int k = 0; k < 3; ++k) f[k] += v2 * fs[k] / (p2 + v2);
+        }
+    }
+    cosine_about(wi, u[4], u[5], n3);
+    double p3 = fmax(0.0, dot3(n3, wi)) / M_PI;
+    double v3 = orc_sggx_vndf(s6, wo, n3);
+    if (p3 > 0.0 && v3 > 0.0) {
+        disney_base(c, rough, met, n3, wo, wi, fs, fd);
+        for (int k = 0; k < 3; ++k) f[k] += v3 * fd[k] / (p3 + v3);
+    }
+}
+
+/* Importance sampling (Sec. 4.2): a visible normal n (u0, u1), then the base
+ * BSDF at n: the specular lobe with probability ps (GGX visible normals of n,
+ * v1, v2, reflected) else cosine about n (v1, v2), chosen by v0.  Weight =
+ * base f / mixture pdf (zero below n).  Returns 0 when no direction. */
+int orc_sggx_disney_sample(const double s6[6], const double c[3], double rough, double met, const double wo[3],
+                           double u0, double u1, const double v[3], double wi[3], double wgt[3]) {
+    double n[3], b1[3], b2[3], lo[3], li[3], fs[3], fd[3], dummy[3], dp;
+    double ps = orc_disney_spec_prob(c, met);
+    for (int k = 0; k < 3; ++k) wgt[k] = 0.0;
+    orc_sggx_sample_vndf(s6, wo, u0, u1, n);
+    if (v[0] < ps) {
+        onb(n, b1, b2);
+        to_local(b1, b2, n, wo, lo);
+        double one[3] = {1.0, 1.0, 1.0};
+        phase_sample_local(1, one, rough, lo, v[1], v[2], li, dummy, &dp);
+        if (!(dp > 0.0)) { wi[0] = wi[1] = 0.0; wi[2] = 1.0; return 0; }
+        for (int i = 0; i < 3; ++i) wi[i] = li[0] * b1[i] + li[1] * b2[i] + li[2] * n[i];
+    } else {
+        cosine_about(n, v[1], v[2], wi);
+    }
+    double pdf = disney_base_pdf(ps, rough, n, wo, wi);
+    if (!(pdf > 0.0)) return 0;
+    disney_base(c, rough, met, n, wo, wi, fs, fd);
+    for (int k = 0; k < 3; ++k) wgt[k] = (fs[k] + fd[k]) / pdf;
+    return 1;
+}
+
+/* Symmetric eigen-decomposition by cyclic Jacobi rotations: eigenvalues w,
+ * eigenvectors in the columns of V. */
+static void jacobi3(const double A0[3][3], double w[3], double V[3][3]) {
+    double A[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) { A[i][j] = A0[i][j]; V[i][j] = i == j ? 1.0 : 0.0; }
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = fabs(A[0][1]) + fabs(A[0][2]) + fabs(A[1][2]);
+        if (off == 0.0) break;
+        for (int p = 0; p < 2; ++p)
+            for (int q = p + 1; q < 3; ++q) {
+                if (A[p][q] == 0.0) continue;
+                double th = 0.5 * (A[q][q] - A[p][p]) / A[p][q];
+                double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+                for (int k = 0; k < 3; ++k) {  /* A <- A J */
+                    double akp = A[k][p], akq = A[k][q];
+                    A[k][p] = cs * akp - sn * akq; A[k][q] = sn * akp + cs * akq;
+                }
+                for (int k = 0; k < 3; ++k) {  /* A <- J^T A */
+                    double apk = A[p][k], aqk = A[q][k];
+                    A[p][k] = cs * apk - sn * aqk; A[q][k] = sn * apk + cs * aqk;
+                }
+                for (int k = 0; k < 3; ++k) {
+                    double vkp = V[k][p], vkq = V[k][q];
+                    V[k][p] = cs * vkp - sn * vkq; V[k][q] = sn * vkp + cs * vkq;
+                }
+            }
+    }
+    for (int i = 0; i < 3; ++i) w[i] = A[i][i];
+}
+
+/* The roughened SGGX of App. B: eigenvalues (s1 + a^2 s3, s2 + a^2 s3, s3)
+ * for the eigenvalues s1 <= s2 <= s3 of S, same eigenvectors:
+ * S~ = S + a^2 s3 (I - v3 v3^T) with v3 the eigenvector of s3. */
+void orc_sggx_roughened(const double s6[6], double rough, double out6[6]) {
+    double S[3][3], V[3][3], w[3];
+    sggx_full(s6, S);
+    jacobi3(S, w, V);
+    int t = 0;
+    if (w[1] > w[t]) t = 1;
+    if (w[2] > w[t]) t = 2;
+    double a = ggx_alpha(rough), cc = a * a * w[t];
+    double v[3] = {V[0][t], V[1][t], V[2][t]};
+    double R[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) R[i][j] = S[i][j] + cc * ((i == j ? 1.0 : 0.0) - v[i] * v[j]);
+    out6[0] = R[0][0]; out6[1] = R[1][1]; out6[2] = R[2][2];
+    out6[3] = R[0][1]; out6[4] = R[0][2]; out6[5] = R[1][2];
+}
+
+/* Approximate MIS pdf (App. B): ps times the roughened SGGX's visible NDF at
+ * the half vector plus (1 - ps) times <w_h . w_o> / pi. */
+double orc_sggx_disney_pdf_approx(const double s6[6], const double c[3], double rough, double met,
+                                  const double wo[3], const double wi[3]) {
+    double h[3] = {wo[0] + wi[0], wo[1] + wi[1], wo[2] + wi[2]};
+    double l = sqrt(dot3(h, h));
+    if (!(l > 0.0)) return 0.0;
+    for (int i = 0; i < 3; ++i) h[i] /= l;
+    double r6[6];
+    orc_sggx_roughened(s6, rough, r6);
+    double ps = orc_disney_spec_prob(c, met);
+    return ps * orc_sggx_vndf(r6, wo, h) + (1.0 - ps) * fmax(0.0, dot3(h, wo)) / M_PI;
+}
+
+/* f_p of material 3 by quadrature on a (cos theta, phi) midpoint grid of normals */
+void orc_sggx_disney_quad(const double s6[6], const double c[3], double rough, double met, const double wo[3],
+                          const double wi[3], int nz, int nphi, double f[3]) {
+    double acc[3] = {0.0, 0.0, 0.0}, fs[3], fd[3];
+    for (int a = 0; a < nz; ++a) {
+        double z = -1.0 + (a + 0.5) * 2.0 / nz, rr = sqrt(fmax(0.0, 1.0 - z * z));
+        for (int b = 0; b < nphi; ++b) {
+            double ph = (b + 0.5) * 2.0 * M_PI / nphi;
+            double n[3] = {rr * cos(ph), rr * sin(ph), z};
+            double dv = orc_sggx_vndf(s6, wo, n);
+            if (dv <= 0.0) continue;
+            disney_base(c, rough, met, n, wo, wi, fs, fd);
+            for (int k = 0; k < 3; ++k) acc[k] += dv * (fs[k] + fd[k]);
+        }
+    }
+    for (int k = 0; k < 3; ++k) f[k] = acc[k] * (2.0 / nz) * (2.0 * M_PI / nphi);
+}
+
+/* the base BSDF alone at a given normal (for checks): fs, fd */
+void orc_disney_base(const double c[3], double rough, double met, const double n[3], const double wo[3],
+                     const double wi[3], double fs[3], double fd[3]) {
+    disney_base(c, rough, met, n, wo, wi, fs, fd);
+}
+
+/* metallic per primitive (copied; values outside [0, 1] rejected) */
+int orc_scene_set_metallic(orc_scene *S, const float *met) {
+    if (!S || !met) return 1;
+    for (int64_t k = 0; k < S->n; ++k)
+        if (!(met[k] >= 0.0f && met[k] <= 1.0f)) return 1;
+    free(S->met);
+    S->met = (double *)malloc(sizeof(double) * (size_t)(S->n > 0 ? S->n : 1));
+    for (int64_t k = 0; k < S->n; ++k) S->met[k] = met[k];
+    return 0;
+}
+
 /* Copies the matrices; returns 1 (and keeps none) unless every one is finite
  * and positive definite (Sylvester: leading minors > 0). */
 int orc_scene_set_sggx(orc_scene *S, const float *sggx) {
@@ -1067,8 +1308,15 @@ int orc_scene_set_sggx(orc_scene *S, const float *sggx) {
  * closed form with their exact pdf; SGGX microflakes (material 2) by the
  * stochastic estimate from u[0..3] with the approximate MIS pdf. */
 static void prim_phase_eval(const orc_scene *S, int64_t k, const double wo[3], const double wi[3],
-                            const double u[4], double f[3], double *pdf) {
+                            const double u[6], double f[3], double *pdf) {
     const double *alb = S->alb + 3 * k;
+    if (S->mat[k] == 3) {
+        if (!S->sggx) { f[0] = f[1] = f[2] = 0.0; *pdf = 0.0; return; }
+        double met = S->met ? S->met[k] : 0.0;
+        orc_sggx_disney_est(S->sggx + 6 * k, alb, S->rough[k], met, wo, wi, u, f);
+        *pdf = orc_sggx_disney_pdf_approx(S->sggx + 6 * k, alb, S->rough[k], met, wo, wi);
+        return;
+    }
     if (S->mat[k] == 2) {
         if (!S->sggx) { f[0] = f[1] = f[2] = 0.0; *pdf = 0.0; return; }
         double e = orc_sggx_phase_est(S->sggx + 6 * k, wo, wi, u);
@@ -1081,11 +1329,21 @@ static void prim_phase_eval(const orc_scene *S, int64_t k, const double wo[3], c
 
 /* Sampling the phase function of primitive k (Sec. 4.2, "Importance
  * Sampling"): for SGGX microflakes a visible normal from (u1, u2), then the
- * Lambertian base's cosine sampling about it from v[0..1]; the weight is the
- * albedo and the pdf reported for MIS is the approximate one. */
+ * base BSDF's sampling about it from v (Lambertian: cosine from v[0..1], the
+ * weight is the albedo; Disney-style: lobe choice v[0], direction v[1..2],
+ * the weight f / pdf of the base); the pdf reported for MIS is the
+ * approximate one. */
 static void prim_phase_sample(const orc_scene *S, int64_t k, const double wo[3], double u1, double u2,
-                              const double v[2], double wi[3], double wgt[3], double *pdf) {
+                              const double v[3], double wi[3], double wgt[3], double *pdf) {
     const double *alb = S->alb + 3 * k;
+    if (S->mat[k] == 3) {
+        *pdf = 0.0;
+        if (!S->sggx) return;
+        double met = S->met ? S->met[k] : 0.0;
+        if (!orc_sggx_disney_sample(S->sggx + 6 * k, alb, S->rough[k], met, wo, u1, u2, v, wi, wgt)) return;
+        *pdf = orc_sggx_disney_pdf_approx(S->sggx + 6 * k, alb, S->rough[k], met, wo, wi);
+        return;
+    }
     if (S->mat[k] == 2) {
         double m[3];
         if (!S->sggx) { *pdf = 0.0; return; }
@@ -1208,12 +1466,18 @@ static void trace_path(const orc_scene *S, const orc_render_params *P, const orc
     }
     if (n_rec) *n_rec = 0;
     for (uint32_t v = 1;; ++v) {
-        double q3[4], q4[4], q5[4];  /* SGGX: light and environment estimates, cosine about the normal */
+        /* SGGX: uniforms of the light and environment estimates (groups 3, 4,
+           and 6 for material 3's third normal) and of the base BSDF's sample
+           about the visible normal (group 5) */
+        double q3[4], q4[4], q5[4], q6[4], e3[6], e4[6];
         rng4(seed, pix, sample, v, 0, u);
         rng4(seed, pix, sample, v, 1, g);
         rng4(seed, pix, sample, v, 3, q3);
         rng4(seed, pix, sample, v, 4, q4);
         rng4(seed, pix, sample, v, 5, q5);
+        rng4(seed, pix, sample, v, 6, q6);
+        for (int i = 0; i < 4; ++i) { e3[i] = q3[i]; e4[i] = q4[i]; }
+        e3[4] = q6[0]; e3[5] = q6[1]; e4[4] = q6[2]; e4[5] = q6[3];
         gather(S, o, w, 0.0, INFINITY, self, 1, H);
         ocoll c;
         collide(S, H, 0.0, INFINITY, u[0], &c);
@@ -1297,7 +1561,7 @@ static void trace_path(const orc_scene *S, const orc_render_params *P, const orc
                 for (int i = 0; i < 3; ++i)
                     wl[i] = sint * cos(ph) * b1[i] + sint * sin(ph) * b2[i] + cost * cdir[i];
                 double f[3], pph;
-                prim_phase_eval(S, k, wo, wl, q3, f, &pph);
+                prim_phase_eval(S, k, wo, wl, e3, f, &pph);
                 ohit he;
                 if ((f[0] > 0.0 || f[1] > 0.0 || f[2] > 0.0) && ray_prim(S, e, x, wl, 0.0, INFINITY, &he)) {
                     double fac = emitter_factor(S, x, wl, 0.0, INFINITY, k, e, 1, H2);
@@ -1315,7 +1579,7 @@ static void trace_path(const orc_scene *S, const orc_render_params *P, const orc
             double ph = 2.0 * M_PI * g[3];
             double wl[3] = {rr * cos(ph), rr * sin(ph), z};
             double f[3], pph;
-            prim_phase_eval(S, k, wo, wl, q4, f, &pph);
+            prim_phase_eval(S, k, wo, wl, e4, f, &pph);
             if (f[0] > 0.0 || f[1] > 0.0 || f[2] > 0.0) {
                 gather(S, x, wl, 0.0, INFINITY, k, 1, H2);
                 double T = fmax(0.0, 1.0 - accumulated_F(S, H2));

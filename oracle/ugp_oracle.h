@@ -94,8 +94,24 @@ void orc_sggx_sample_vndf_n(const double s6[6], const double wo[3], int64_t n, c
 void orc_sggx_sample_dir_n(const double s6[6], const double wo[3], int64_t n, const double *u, double *wi);
 void orc_sggx_phase_est_n(const double s6[6], const double wo[3], const double wi[3], int64_t n,
                           const double *u, double *out);
-/* per-primitive SGGX matrices [n][6] (copied); material 2 needs them */
+/* per-primitive SGGX matrices [n][6] (copied); materials 2 and 3 need them */
 int orc_scene_set_sggx(orc_scene *S, const float *sggx);
+/* metallic [n] of material 3 (copied; default 0) */
+int orc_scene_set_metallic(orc_scene *S, const float *met);
+/* material 3: SGGX microflakes with a Disney-style base BSDF (diffuse with
+ * retro-reflection + GGX specular, metallic m); c = base colour */
+double orc_disney_spec_prob(const double c[3], double met);
+void orc_disney_base(const double c[3], double rough, double met, const double n[3], const double wo[3],
+                     const double wi[3], double fs[3], double fd[3]);
+void orc_sggx_disney_est(const double s6[6], const double c[3], double rough, double met, const double wo[3],
+                         const double wi[3], const double u[6], double f[3]);
+int orc_sggx_disney_sample(const double s6[6], const double c[3], double rough, double met, const double wo[3],
+                           double u0, double u1, const double v[3], double wi[3], double wgt[3]);
+void orc_sggx_roughened(const double s6[6], double rough, double out6[6]);
+double orc_sggx_disney_pdf_approx(const double s6[6], const double c[3], double rough, double met,
+                                  const double wo[3], const double wi[3]);
+void orc_sggx_disney_quad(const double s6[6], const double c[3], double rough, double met, const double wo[3],
+                          const double wi[3], int nz, int nphi, double f[3]);
 
 int64_t orc_render(const orc_scene *S, const orc_camera *cam, const orc_render_params *p,
                    int64_t n_pix, const int64_t *pixels, int nthreads, double *sum, double *sumsq);

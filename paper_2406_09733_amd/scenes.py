@@ -9,8 +9,9 @@ Scene dictionaries hold float32 / int32 numpy arrays:
   mean [n,3], scale [n,3] (>0), rotation [n,4] (w,x,y,z quaternion, any norm),
   density [n] (peak value of the Gaussian), albedo [n,3], roughness [n],
   emission [n,3] (radiance, 0 = not emissive), material [n] (0 diffuse, 1 glossy,
-  2 SGGX microflakes with a Lambertian base) and, where material 2 occurs,
-  sggx [n,6] (the SGGX matrix: xx, yy, zz, xy, xz, yz)
+  2 / 3 SGGX microflakes with a Lambertian / Disney-style base) and, where
+  material 2 or 3 occurs, sggx [n,6] (the SGGX matrix: xx, yy, zz, xy, xz, yz)
+  and optionally metallic [n] (material 3)
 and a "bounds" entry (lo, hi) used by camera set-up and the cache's position
 normalisation.
 
@@ -400,9 +401,11 @@ def _quat_axes(q):
     return R
 
 
-def with_sggx(sc: dict, seed: int = 0, frac: float = 0.5) -> dict:
+def with_sggx(sc: dict, seed: int = 0, frac: float = 0.5, base: str = "lambert") -> dict:
     """A copy of `sc` in which a random `frac` of the primitives are SGGX
-    microflake primitives (material 2) and every primitive carries an SGGX
+    microflake primitives (material 2 with base "lambert"; material 3 with
+    base "disney", whose primitives then get roughness U[0.05, 1] and every
+    primitive a metallic U[0, 1]) and every primitive carries an SGGX
     matrix ("sggx" [n,6] = xx, yy, zz, xy, xz, yz).  The matrices are
     S = V diag(l1, l2, l3) V^T in the primitive's own frame (V = its rotation,
     axes sorted by scale), of three kinds drawn with equal probability, the
@@ -437,6 +440,12 @@ def with_sggx(sc: dict, seed: int = 0, frac: float = 0.5) -> dict:
     for k in range(n):
         if not pick[k]:
             out["sggx"][k] = (1, 1, 1, 0, 0, 0)
+    if base == "disney":
+        out["material"] = np.where(pick, 3, out["material"]).astype(np.int32)
+        out["roughness"] = np.where(pick, rng.uniform(0.05, 1.0, n), sc["roughness"]).astype(np.float32)
+        out["metallic"] = rng.uniform(0, 1, n).astype(np.float32)
+    elif base != "lambert":
+        raise ValueError(base)
     return out
 
 
