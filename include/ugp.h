@@ -57,20 +57,27 @@ typedef enum {
  *   emission[n][3]  emitted radiance (0 = not an emitter)
  *   material[n]     int32: 0 = diffuse (Lambert), 1 = glossy (GGX): the delta-NDF
  *                   limit of eq. phase_function with the facet normal along the
- *                   axis of the smallest scale; 2 = SGGX microflakes with a
- *                   Lambertian base BSDF (Sec. 4.2, eq. vndf and eq.
- *                   phase_function: stochastic evaluation with internal MIS,
- *                   visible-normal sampling, the approximate MIS pdf of App. B)
+ *                   axis of the smallest scale; 2 / 3 = SGGX microflakes (Sec.
+ *                   4.2, eq. vndf and eq. phase_function: stochastic evaluation
+ *                   with internal MIS, visible-normal sampling, the approximate
+ *                   MIS pdf of App. B) with a Lambertian base BSDF (2) or a
+ *                   Disney-style base (3): a diffuse lobe with retro-reflection,
+ *                   weight 1 - metallic, and a GGX specular lobe (alpha =
+ *                   roughness^2) with Schlick F0 = 0.04 (1 - metallic) +
+ *                   albedo metallic
  *   sggx[n][6]      SGGX matrix S per primitive (xx, yy, zz, xy, xz, yz), world
  *                   frame, symmetric positive definite; may be NULL when no
- *                   primitive has material 2.  When given, every row is checked
- *                   (leading minors > 0, finite) and a bad row fails the build
- *                   with UGP_ERR_INVALID_ARGUMENT, as does material 2 with NULL. */
+ *                   primitive has material 2 or 3.  When given, every row is
+ *                   checked (leading minors > 0, finite) and a bad row fails the
+ *                   build with UGP_ERR_INVALID_ARGUMENT, as do materials 2 and 3
+ *                   with NULL
+ *   metallic[n]     metallic of material 3 in [0, 1] (checked); NULL = 0       */
 typedef struct {
     int64_t n;
     const float *mean, *scale, *rotation, *density, *albedo, *roughness, *emission;
     const int32_t *material;
     const float *sggx;
+    const float *metallic;
 } ugp_scene;
 
 /* [host] pinhole camera: pixel (i, j), j = 0 at the top, jitter (jx, jy) in
@@ -347,19 +354,26 @@ ugp_status ugp_render_albedo_grad(ugp_ctx ctx, const ugp_camera *cam, const ugp_
 
 /* Waits for the context's stream and reports deferred device-side errors
  * (queue or stack overflow) as UGP_ERR_OVERFLOW, clearing them. */
-/* Test hook of the SGGX phase function (material 2; Sec. 4.2 and App. B), per
- * unit albedo, for n independent queries (DEVICE arrays, float32):
+/* Test hook of the SGGX phase functions (materials 2 and 3; Sec. 4.2 and
+ * App. B) for n independent queries (DEVICE arrays, float32):
  *   sggx[n][6]  S (xx, yy, zz, xy, xz, yz), positive definite
+ *   base[n][5]  albedo (rgb), roughness, metallic of a Disney-style base
+ *               (material 3); NULL = Lambertian base of unit albedo (material 2)
  *   dirs[n][6]  w_o (unit, pointing away from the primitive), w_i (unit)
- *   u[n][6]     uniforms in [0,1): u0,u1 pick the visible normal of the
- *               evaluation, u2,u3 the cosine-sampled normal about w_i; u0,u1 and
- *               u4,u5 drive the importance sample (visible normal, then cosine
- *               about it)
- *   out[n][8]   f_p estimate at (w_i, w_o), approximate MIS pdf at (w_i, w_o),
- *               the sampled direction (3), its approximate pdf, 2 zeros
+ *   u[n][12]    uniforms in [0,1): u0..u5 drive the evaluation (u0,u1 the
+ *               visible normal; material 2: u2,u3 a normal cosine-distributed
+ *               about w_i; material 3: u2,u3 a GGX normal about the half
+ *               vector, u4,u5 a normal cosine-distributed about w_i); u6,u7 the
+ *               sample's visible normal, u8..u10 its base-BSDF sample
+ *               (material 2: cosine from u8,u9; material 3: lobe u8, direction
+ *               u9,u10); u11 unused
+ *   out[n][12]  f_p estimate (rgb), approximate MIS pdf at (w_i, w_o), sampled
+ *               direction (3), its weight f/pdf (rgb), its approximate pdf,
+ *               1 if a direction was sampled else 0
+ * A query whose S is not positive definite gets NaN in every output.
  * Enqueued on the context's stream; no scene is needed. */
-ugp_status ugp_sggx_phase(ugp_ctx ctx, int64_t n, const float *sggx, const float *dirs, const float *u,
-                          float *out);
+ugp_status ugp_sggx_phase(ugp_ctx ctx, int64_t n, const float *sggx, const float *base, const float *dirs,
+                          const float *u, float *out);
 
 ugp_status ugp_sync(ugp_ctx ctx);
 

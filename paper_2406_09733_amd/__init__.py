@@ -32,7 +32,8 @@ class UGPError(RuntimeError):
 class _Scene(C.Structure):
     _fields_ = [("n", C.c_int64), ("mean", C.c_void_p), ("scale", C.c_void_p), ("rotation", C.c_void_p),
                 ("density", C.c_void_p), ("albedo", C.c_void_p), ("roughness", C.c_void_p),
-                ("emission", C.c_void_p), ("material", C.c_void_p), ("sggx", C.c_void_p)]
+                ("emission", C.c_void_p), ("material", C.c_void_p), ("sggx", C.c_void_p),
+                ("metallic", C.c_void_p)]
 
 
 class _Camera(C.Structure):
@@ -116,7 +117,7 @@ def lib():
         L.ugp_nrc_records.argtypes = [vp, i64, vp, vp, C.POINTER(C.c_int64)]
         L.ugp_accum_cdf.argtypes = [vp, vp, i64, vp, vp, vp, C.c_float, vp, vp, vp]
         L.ugp_camera_rays.argtypes = [vp, vp, C.c_uint64, i64, vp]
-        L.ugp_sggx_phase.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.ugp_sggx_phase.argtypes = [vp, i64, vp, vp, vp, vp, vp]
         L.ugp_rf_render.argtypes = [vp, vp, i64, vp, vp, vp, C.c_float, vp, vp, vp]
         L.ugp_accum_cdf_backward.argtypes = [vp, vp, i64, vp, vp, vp, vp]
         L.ugp_rf_render_backward.argtypes = [vp, vp, i64, vp, vp, vp, vp]
@@ -222,12 +223,12 @@ class Context:
             "emission": self._dev(scene["emission"], torch.float32, (n, 3)),
             "material": self._dev(scene["material"], torch.int32, (n,)),
         }
-        g = scene.get("sggx")
-        if g is not None:
-            t["sggx"] = self._dev(g, torch.float32, (n, 6))
+        for key, w in (("sggx", 6), ("metallic", None)):
+            if scene.get(key) is not None:
+                t[key] = self._dev(scene[key], torch.float32, (n, w) if w else (n,))
         s = _Scene(n, *[t[k].data_ptr() for k in ("mean", "scale", "rotation", "density", "albedo",
                                                   "roughness", "emission", "material")],
-                   t["sggx"].data_ptr() if "sggx" in t else None)
+                   *[t[k].data_ptr() if k in t else None for k in ("sggx", "metallic")])
         _check(*call(s))
         self.n = n
         self._scene_t, self._scene_s = t, s  # the parameters the hierarchy was built from
@@ -284,17 +285,20 @@ class Context:
         _check("ugp_emitter_query", lib().ugp_emitter_query(self.h, n, _ptr(r), _ptr(e), _ptr(tg), _ptr(out)))
         return out
 
-    def sggx_phase(self, sggx, dirs, u):
-        """ugp_sggx_phase -> float32 [n, 8]: f_p / albedo estimate, approximate
-        pdf, sampled direction (3), its approximate pdf, 2 zeros"""
+    def sggx_phase(self, sggx, dirs, u, base=None):
+        """ugp_sggx_phase -> float32 [n, 12]: f_p estimate (rgb), approximate
+        pdf, sampled direction (3), its weight (rgb), its approximate pdf, ok.
+        base [n, 5] (albedo rgb, roughness, metallic) selects material 3; None
+        the Lambertian base of unit albedo (material 2)."""
         torch = self.torch
         d = self._dev(dirs, torch.float32)
         n = d.shape[0]
         g = self._dev(sggx, torch.float32, (n, 6))
-        uu = self._dev(u, torch.float32, (n, 6))
+        uu = self._dev(u, torch.float32, (n, 12))
+        b = None if base is None else self._dev(base, torch.float32, (n, 5))
         d = d.reshape(n, 6)
-        out = torch.empty((n, 8), device=self.device, dtype=torch.float32)
-        _check("ugp_sggx_phase", lib().ugp_sggx_phase(self.h, n, _ptr(g), _ptr(d), _ptr(uu), _ptr(out)))
+        out = torch.empty((n, 12), device=self.device, dtype=torch.float32)
+        _check("ugp_sggx_phase", lib().ugp_sggx_phase(self.h, n, _ptr(g), _ptr(b), _ptr(d), _ptr(uu), _ptr(out)))
         return out
 
     def trace_counts(self, mode: int, rays, u=None, target=None, exclude=None):

@@ -242,7 +242,7 @@ ugp_status ugp_render_albedo_grad(ugp_ctx ctx, const ugp_camera *cam, const ugp_
     if (!d_image || !grad_albedo) return UGP_ERR_INVALID_ARGUMENT;
     const ugp_status s = render_args(ctx, cam, p);
     if (s != UGP_OK) return s;
-    if (p->nrc_mode != 0) return UGP_ERR_UNSUPPORTED;
+    if (p->nrc_mode != 0 || ctx->scene.has_mat3) return UGP_ERR_UNSUPPORTED;
     DeviceGuard g(ctx->device);
     const ugp::RenderAdjoint adj{d_image, grad_albedo};
     return from_hip(ugp::render(ctx, cam, p, sum, nullptr, &adj));
@@ -333,13 +333,13 @@ ugp_status ugp_fit_adam(ugp_ctx ctx, int64_t n, float *mean, float *scale, float
                                   0.999f, 1e-8f, min_scale));
 }
 
-ugp_status ugp_sggx_phase(ugp_ctx ctx, int64_t n, const float *sggx, const float *dirs, const float *u,
-                          float *out) {
+ugp_status ugp_sggx_phase(ugp_ctx ctx, int64_t n, const float *sggx, const float *base, const float *dirs,
+                          const float *u, float *out) {
     if (!ctx || n < 0) return UGP_ERR_INVALID_ARGUMENT;
     if (n == 0) return UGP_OK;
     if (!sggx || !dirs || !u || !out) return UGP_ERR_INVALID_ARGUMENT;
     DeviceGuard g(ctx->device);
-    return from_hip(ugp::sggx_phase(ctx, n, sggx, dirs, u, out));
+    return from_hip(ugp::sggx_phase(ctx, n, sggx, base, dirs, u, out));
 }
 
 ugp_status ugp_sync(ugp_ctx ctx) {

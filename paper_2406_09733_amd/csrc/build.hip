@@ -219,6 +219,7 @@ struct PackIn {
     const float *mean, *scale, *rot, *dens, *alb, *rough, *emis;
     const int32_t *mat;
     const float *sggx;  // [n][6] or null
+    const float *met;   // [n] or null (0)
     double r;
 };
 
@@ -255,16 +256,20 @@ __global__ void k_pack(PackIn in, float *boxes, float4 *cold_tmp, float *mtmp, u
     const double qn = qw * qw + qx * qx + qy * qy + qz * qz;
     const float d = in.dens[k];
     const int m = in.mat[k];
-    bool bad = !(qn > 0.0) || !isfinite(qn) || !(d >= 0.f) || !isfinite(d) || m < 0 || m > 2 ||
-               (m == 2 && !in.sggx);
+    bool bad = !(qn > 0.0) || !isfinite(qn) || !(d >= 0.f) || !isfinite(d) || m < 0 || m > 3 ||
+               (m >= 2 && !in.sggx);
     for (int i = 0; i < 3; ++i) bad = bad || !(s[i] > 0.0) || !isfinite(s[i]) || !isfinite(mu[i]);
+    const float met = in.met ? in.met[k] : 0.f;
+    bad = bad || !(met >= 0.f && met <= 1.f);
     if (in.sggx) {
         double g[6];
         for (int i = 0; i < 6; ++i) g[i] = in.sggx[6 * k + i];
-        float4 rec[4];
-        bad = !sggx_prepare(g, rec) || bad;
-        for (int i = 0; i < 4; ++i) sggx_out[4 * k + i] = rec[i];
+        const float alb[3] = {in.alb[3 * k], in.alb[3 * k + 1], in.alb[3 * k + 2]};
+        float4 rec[8];
+        bad = !sggx_prepare_prim(g, in.rough[k], met, alb, rec) || bad;
+        for (int i = 0; i < 8; ++i) sggx_out[8 * k + i] = rec[i];
     }
+    if (m == 3) atomicOr(err, 32u);  // (not an error: the scene holds material 3)
     if (bad) {
         atomicOr(err, 8u);
         for (int i = 0; i < 6; ++i) boxes[6 * k + i] = 0.f;
@@ -716,7 +721,7 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
     sc.r_cut = r;
     std::vector<int32_t> levels4{0, 1};  // level L of the 4-wide nodes: [levels4[L], levels4[L + 1])
     PackIn in{n, s->mean, s->scale, s->rotation, s->density, s->albedo, s->roughness, s->emission,
-              s->material, s->sggx, r};
+              s->material, s->sggx, s->metallic, r};
     float *boxes = nullptr, *rbox = nullptr;
     float *mtmp = nullptr;
     uint32_t *bounds = nullptr, *keys = nullptr, *tk = nullptr;
@@ -748,7 +753,7 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
     UGP_CHECK(hipMemsetAsync(berr, 0, sizeof(uint32_t), st));
     UGP_CHECK(hipMemsetAsync(depth, 0, sizeof(int32_t), st));
     hipLaunchKernelGGL(k_init_bounds, dim3(1), dim3(64), 0, st, bounds);
-    if (s->sggx) UGP_CHECK(hipMalloc((void **)&sc.sggx, sizeof(float4) * 4 * n));
+    if (s->sggx) UGP_CHECK(hipMalloc((void **)&sc.sggx, sizeof(float4) * 8 * n));
     hipLaunchKernelGGL(k_pack, dim3(blocks(n)), dim3(kThreads), 0, st, in, boxes, sc.cold, mtmp, bounds, pieces,
                        sc.sggx, berr);
     UGP_CHECK(hipGetLastError());
@@ -761,6 +766,7 @@ hipError_t build_scene(ugp_ctx ctx, const ugp_scene *s, float eps) {
         e = hipErrorInvalidValue;
         goto fail;
     }
+    sc.has_mat3 = (h_err & 32u) != 0;
     nr = (int64_t)h_roff_last + h_pieces_last;
     if (nr >= (int64_t(1) << 31) - 1) {
         e = hipErrorNotSupported;
@@ -938,7 +944,7 @@ hipError_t refit_scene(ugp_ctx ctx, const ugp_scene *s) {
     SceneDev &sc = ctx->scene;
     const int64_t n = s->n, nr = sc.n_refs;
     PackIn in{n, s->mean, s->scale, s->rotation, s->density, s->albedo, s->roughness, s->emission,
-              s->material, s->sggx, sc.r_cut};
+              s->material, s->sggx, s->metallic, sc.r_cut};
     float *boxes = nullptr, *mtmp = nullptr, *lbox = nullptr;
     float4 *cold = nullptr, *sggx = nullptr;
     uint32_t *bounds = nullptr;
@@ -961,7 +967,7 @@ hipError_t refit_scene(ugp_ctx ctx, const ugp_scene *s) {
     UGP_CHECK(hipMallocAsync((void **)&berr, sizeof(uint32_t), st));
     UGP_CHECK(hipMemsetAsync(berr, 0, sizeof(uint32_t), st));
     hipLaunchKernelGGL(k_init_bounds, dim3(1), dim3(64), 0, st, bounds);
-    if (s->sggx) UGP_CHECK(hipMallocAsync((void **)&sggx, sizeof(float4) * 4 * n, st));
+    if (s->sggx) UGP_CHECK(hipMallocAsync((void **)&sggx, sizeof(float4) * 8 * n, st));
     hipLaunchKernelGGL(k_pack, dim3(blocks(n)), dim3(kThreads), 0, st, in, boxes, cold, mtmp, bounds, pieces,
                        sggx, berr);
     UGP_CHECK(hipGetLastError());
@@ -971,12 +977,13 @@ hipError_t refit_scene(ugp_ctx ctx, const ugp_scene *s) {
         e = hipErrorInvalidValue;
         goto fail;
     }
+    sc.has_mat3 = (h_err & 32u) != 0;
     // records and leaf boxes, then the 4-wide nodes from the deepest level up
     UGP_CHECK(hipMemcpyAsync(sc.cold, cold, sizeof(float4) * 3 * n, hipMemcpyDeviceToDevice, st));
     if (sggx) {
-        if (!sc.sggx) UGP_CHECK(hipMalloc((void **)&sc.sggx, sizeof(float4) * 4 * n));
-        UGP_CHECK(hipMemcpyAsync(sc.sggx, sggx, sizeof(float4) * 4 * n, hipMemcpyDeviceToDevice, st));
-    } else if (sc.sggx) {  // no material 2 any more (validated): drop the records
+        if (!sc.sggx) UGP_CHECK(hipMalloc((void **)&sc.sggx, sizeof(float4) * 8 * n));
+        UGP_CHECK(hipMemcpyAsync(sc.sggx, sggx, sizeof(float4) * 8 * n, hipMemcpyDeviceToDevice, st));
+    } else if (sc.sggx) {  // no material 2 or 3 any more (validated): drop the records
         UGP_CHECK(hipStreamSynchronize(st));
         hipFree(sc.sggx);
         sc.sggx = nullptr;

@@ -368,13 +368,36 @@ struct ShadeOut {
 // (world frame): f (rgb) and the pdf of phase sampling used by MIS.  The
 // SGGX microflakes (material 2) take the stochastic estimate from the four
 // uniforms of gs and the approximate pdf; the delta-NDF materials are exact.
-__device__ __forceinline__ V3 vertex_phase(int mat, const Sggx &sg, const Facet &F, V3 wo, V3 wol, V3 alb,
-                                           float rough, V3 wl, const Rng4 &gs, float &pdf) {
+__device__ __forceinline__ V3 vertex_phase(int mat, const Sggx &sg, const Sggx &sgr, const Facet &F, V3 wo, V3 wol,
+                                           V3 alb, float rough, V3 wl, const float u[6], float &pdf) {
+    if (mat == 3) {
+        pdf = sggx_disney_pdf_approx(sgr, sg.ps, wo, wl);
+        return sggx_disney_est(sg, alb, rough, wo, wl, u);
+    }
     if (mat == 2) {
         pdf = sggx_pdf_approx(wo, wl);
-        return sggx_phase_est(sg, wo, wl, gs.u[0], gs.u[1], gs.u[2], gs.u[3]) * alb;
+        return sggx_phase_est(sg, wo, wl, u[0], u[1], u[2], u[3]) * alb;
     }
     return phase_eval_local(mat, alb, rough, wol, to_local(F, wl), pdf);
+}
+
+// uniforms of an SGGX evaluation at vertex v: group g (four), and for
+// material 3 two more from group 6 (its first pair for the light sample,
+// g = 3, its second for the environment sample)
+__device__ __forceinline__ void eval_uniforms(const PassArgs &P, uint32_t q, uint32_t v, uint32_t g, int mat,
+                                              float u[6]) {
+    u[4] = u[5] = 0.f;
+    if (mat < 2) {
+        u[0] = u[1] = u[2] = u[3] = 0.f;
+        return;
+    }
+    const Rng4 a = path_rng(P, q, v, g);
+    u[0] = a.u[0]; u[1] = a.u[1]; u[2] = a.u[2]; u[3] = a.u[3];
+    if (mat == 3) {
+        const Rng4 b = path_rng(P, q, v, 6);
+        u[4] = g == 3 ? b.u[0] : b.u[2];
+        u[5] = g == 3 ? b.u[1] : b.u[3];
+    }
 }
 
 // Shading of one path vertex after its collision `hit` (prim, t bits):
@@ -453,8 +476,9 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
             // SGGX microflakes: their record, and the uniforms of the light and
             // environment estimates (groups 3, 4) and of the cosine sample about
             // the visible normal (group 5)
-            Sggx sg{};
-            if (mat == 2) sg = sggx_load(S.sggx + 4 * (int64_t)k);
+            Sggx sg{}, sgr{};
+            if (mat >= 2) sg = sggx_load(S.sggx + 8 * (int64_t)k);
+            if (mat == 3) sgr = sggx_load(S.sggx + 8 * (int64_t)k + 4);
             // light sample: one emitter, uniform in the cone of its bounding sphere
             if (S.n_emit > 0 && P.mis_mode != 1) {
                 // floor(u * n_emit) in exact integer arithmetic (u has 24 bits)
@@ -481,8 +505,9 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
                     onb(cd, b1, b2);
                     const V3 wl = (sint * cp) * b1 + (sint * sp) * b2 + cost * cd;
                     float pph;
-                    const Rng4 gs = mat == 2 ? path_rng(P, (uint32_t)pix, (uint32_t)v, 3) : Rng4{};
-                    const V3 f = vertex_phase(mat, sg, F, wo, wol, alb, rough, wl, gs, pph);
+                    float ue[6];
+                    eval_uniforms(P, (uint32_t)pix, (uint32_t)v, 3, mat, ue);
+                    const V3 f = vertex_phase(mat, sg, sgr, F, wo, wol, alb, rough, wl, ue, pph);
                     Chord tc;
                     const RayD lr = make_ray(x.x, x.y, x.z, wl.x, wl.y, wl.z, 0.f, __builtin_huge_val());
                     if (nonzero(f) && chord(load_hot(S.hot, es), lr, S.r2, tc)) {
@@ -508,8 +533,9 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
                 sincosf(2.f * kPi * g1.u[3], &sp, &cp);
                 const V3 wl = v3(rr * cp, rr * sp, z);
                 float pph;
-                const Rng4 gs = mat == 2 ? path_rng(P, (uint32_t)pix, (uint32_t)v, 4) : Rng4{};
-                const V3 f = vertex_phase(mat, sg, F, wo, wol, alb, rough, wl, gs, pph);
+                float ue[6];
+                eval_uniforms(P, (uint32_t)pix, (uint32_t)v, 4, mat, ue);
+                const V3 f = vertex_phase(mat, sg, sgr, F, wo, wol, alb, rough, wl, ue, pph);
                 if (nonzero(f)) {
                     const float pe = 0.25f * kInvPi;
                     const float w = P.mis_mode == 2 ? 1.f : pe / (pe + pph);
@@ -533,6 +559,12 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
                 wil = wol;  // (the albedo ratio of material 2 does not depend on directions)
                 wgt = alb;
                 pdf = sggx_pdf_approx(wo, wi);
+            } else if (mat == 3) {  // (no albedo adjoint for material 3: the entry point refuses it)
+                const Rng4 g5 = path_rng(P, (uint32_t)pix, (uint32_t)v, 5);
+                wil = wol;
+                pdf = sggx_disney_sample(sg, alb, rough, wo, g1.u[0], g1.u[1], g5.u[0], g5.u[1], g5.u[2], wi, wgt)
+                          ? sggx_disney_pdf_approx(sgr, sg.ps, wo, wi)
+                          : 0.f;
             } else {
                 wil = phase_sample_local(mat, alb, rough, wol, g1.u[0], g1.u[1], wgt, pdf);
                 wi = to_world(F, wil);
@@ -1258,35 +1290,56 @@ hipError_t render_nrc_records(ugp_ctx ctx, int64_t cap, float *rec_out, float *t
     return hipSuccess;
 }
 
-// Test hook of the SGGX phase function: per query the record prepared from
-// the six inputs, the stochastic estimate, the approximate pdf, and an
-// importance sample with its approximate pdf (layout in ugp_sggx_phase).
-__global__ __launch_bounds__(256) void k_sggx_phase(int64_t n, const float *sggx, const float *dirs, const float *u,
-                                                    float *out) {
+// Test hook of the SGGX phase functions: per query the records prepared from
+// the inputs as the scene pack does, the stochastic estimate, the approximate
+// pdf, and an importance sample with its weight and approximate pdf (layout
+// in ugp_sggx_phase).
+__global__ __launch_bounds__(256) void k_sggx_phase(int64_t n, const float *sggx, const float *base,
+                                                    const float *dirs, const float *u, float *out) {
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         double g6[6];
         for (int j = 0; j < 6; ++j) g6[j] = sggx[6 * i + j];
-        float4 rec[4];
-        float *o = out + 8 * i;
-        if (!sggx_prepare(g6, rec)) {
-            for (int j = 0; j < 8; ++j) o[j] = __builtin_nanf("");
+        const float *b = base ? base + 5 * i : nullptr;
+        const float alb[3] = {b ? b[0] : 1.f, b ? b[1] : 1.f, b ? b[2] : 1.f};
+        const float rough = b ? b[3] : 0.5f, met = b ? b[4] : 0.f;
+        float4 rec[8];
+        float *o = out + 12 * i;
+        if (!sggx_prepare_prim(g6, rough, met, alb, rec)) {
+            for (int j = 0; j < 12; ++j) o[j] = __builtin_nanf("");
             continue;
         }
-        const Sggx g = sggx_load(rec);
-        const float *d = dirs + 6 * i, *r = u + 6 * i;
-        const V3 wo = v3(d[0], d[1], d[2]), wi = v3(d[3], d[4], d[5]);
-        o[0] = sggx_phase_est(g, wo, wi, r[0], r[1], r[2], r[3]);
-        o[1] = sggx_pdf_approx(wo, wi);
-        const V3 ws = sggx_sample(g, wo, r[0], r[1], r[4], r[5]);
-        o[2] = ws.x; o[3] = ws.y; o[4] = ws.z;
-        o[5] = sggx_pdf_approx(wo, ws);
-        o[6] = 0.f; o[7] = 0.f;
+        const Sggx g = sggx_load(rec), gr = sggx_load(rec + 4);
+        const float *d = dirs + 6 * i, *r = u + 12 * i;
+        const V3 wo = v3(d[0], d[1], d[2]), wi = v3(d[3], d[4], d[5]), c = v3(alb[0], alb[1], alb[2]);
+        V3 f, ws, w;
+        float pf, pw;
+        bool ok;
+        if (b) {
+            f = sggx_disney_est(g, c, rough, wo, wi, r);
+            pf = sggx_disney_pdf_approx(gr, g.ps, wo, wi);
+            ok = sggx_disney_sample(g, c, rough, wo, r[6], r[7], r[8], r[9], r[10], ws, w);
+            pw = ok ? sggx_disney_pdf_approx(gr, g.ps, wo, ws) : 0.f;
+        } else {
+            const float e = sggx_phase_est(g, wo, wi, r[0], r[1], r[2], r[3]);
+            f = v3(e, e, e);
+            pf = sggx_pdf_approx(wo, wi);
+            ws = sggx_sample(g, wo, r[6], r[7], r[8], r[9]);
+            w = v3(1.f, 1.f, 1.f);
+            pw = sggx_pdf_approx(wo, ws);
+            ok = true;
+        }
+        if (!ok) ws = w = v3(0.f, 0.f, 0.f);
+        o[0] = f.x; o[1] = f.y; o[2] = f.z; o[3] = pf;
+        o[4] = ws.x; o[5] = ws.y; o[6] = ws.z;
+        o[7] = w.x; o[8] = w.y; o[9] = w.z; o[10] = pw; o[11] = ok ? 1.f : 0.f;
     }
 }
 
-hipError_t sggx_phase(ugp_ctx ctx, int64_t n, const float *sggx, const float *dirs, const float *u, float *out) {
+hipError_t sggx_phase(ugp_ctx ctx, int64_t n, const float *sggx, const float *base, const float *dirs,
+                      const float *u, float *out) {
     const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_sggx_phase, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, n, sggx, dirs, u, out);
+    hipLaunchKernelGGL(k_sggx_phase, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, n, sggx, base, dirs, u,
+                       out);
     return hipGetLastError();
 }
 

@@ -31,7 +31,8 @@ struct SceneDev {
     double r_cut = 0.0;    // that radius in full precision (for a refit)
     float4 *hot = nullptr;
     float4 *cold = nullptr;
-    float4 *sggx = nullptr;  // [4 n] SGGX records (material 2) in original order; null without SGGX input
+    float4 *sggx = nullptr;  // [8 n] SGGX records (materials 2, 3) in original order; null without SGGX input
+    bool has_mat3 = false;   // some primitive has material 3 (no albedo adjoint for it)
     float4 *nodes = nullptr;
     int32_t *inv = nullptr;
     int32_t *emit = nullptr;
@@ -123,7 +124,8 @@ struct RenderAdjoint {
 hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p, float *sum, float *sumsq,
                   const RenderAdjoint *adj = nullptr);
 // SGGX phase-function test hook (queries laid out as in ugp_sggx_phase)
-hipError_t sggx_phase(ugp_ctx ctx, int64_t n, const float *sggx, const float *dirs, const float *u, float *out);
+hipError_t sggx_phase(ugp_ctx ctx, int64_t n, const float *sggx, const float *base, const float *dirs,
+                      const float *u, float *out);
 struct CamDev;
 // the device camera (origin, forward, right and up scaled to the field of view)
 void make_cam_dev(const ugp_camera *cam, CamDev *out);

@@ -190,15 +190,18 @@ __device__ inline V3 phase_sample_local(int mat, V3 alb, float rough, V3 wo, flo
 // S is symmetric positive definite.  The flakes' normals are those of the
 // ellipsoid x^T S x = 1: D(n) = 1 / (pi sqrt(det S) (n^T S^-1 n)^2), projected
 // area sigma(w) = sqrt(w^T S w), visible normals D_wo(n) = <wo.n> D(n) /
-// sigma(wo).  Per primitive a 64-B record, prepared in FP64 from the six
-// float inputs (the inverse of a flat S cancels badly in FP32):
+// sigma(wo).  Per matrix a 64-B record, prepared in FP64 from the six float
+// inputs (the inverse of a flat S cancels badly in FP32):
 //   [0] S xx, yy, zz, xy   [1] S xz, yz, S^-1 xx, yy
-//   [2] S^-1 zz, xy, xz, yz   [3] 1 / (pi sqrt(det S)), 0, 0, 0
+//   [2] S^-1 zz, xy, xz, yz   [3] 1 / (pi sqrt(det S)), metallic, p_spec, 0
+// A primitive holds two: its S, and the roughened S of App. B used by the
+// approximate MIS pdf of material 3 (128 B).
 // ---------------------------------------------------------------------------
 struct Sggx {
     float xx, yy, zz, xy, xz, yz;        // S
     float ixx, iyy, izz, ixy, ixz, iyz;  // S^-1
     float dn;                            // 1 / (pi sqrt(det S))
+    float met, ps;                       // metallic, probability of the specular lobe (material 3)
 };
 
 // record of s = (xx, yy, zz, xy, xz, yz); false (record zeroed) unless S is
@@ -222,9 +225,74 @@ __device__ inline bool sggx_prepare(const double s[6], float4 rec[4]) {
     return true;
 }
 
+// Largest eigenvalue of a symmetric S = (xx, yy, zz, xy, xz, yz) by the
+// trigonometric closed form of the characteristic cubic, and a unit
+// eigenvector of it: the largest cross product of two rows of S - lambda I,
+// or, when the largest eigenvalue is repeated (rows all parallel), a unit
+// vector orthogonal to the largest row (any vector of the eigenspace).
+__device__ inline double sym3_top(const double s[6], double v[3]) {
+    const double xx = s[0], yy = s[1], zz = s[2], xy = s[3], xz = s[4], yz = s[5];
+    const double p1 = xy * xy + xz * xz + yz * yz;
+    const double q = (xx + yy + zz) / 3.0;
+    const double p2 = (xx - q) * (xx - q) + (yy - q) * (yy - q) + (zz - q) * (zz - q) + 2.0 * p1;
+    if (!(p2 > 0.0)) {  // a multiple of I
+        v[0] = 0.0; v[1] = 0.0; v[2] = 1.0;
+        return q;
+    }
+    const double p = sqrt(p2 / 6.0), ip = 1.0 / p;
+    const double bxx = (xx - q) * ip, byy = (yy - q) * ip, bzz = (zz - q) * ip;
+    const double bxy = xy * ip, bxz = xz * ip, byz = yz * ip;
+    double r = 0.5 * (bxx * (byy * bzz - byz * byz) - bxy * (bxy * bzz - byz * bxz) + bxz * (bxy * byz - byy * bxz));
+    r = fmin(1.0, fmax(-1.0, r));
+    const double lam = q + 2.0 * p * cos(acos(r) / 3.0);
+    const double R[3][3] = {{xx - lam, xy, xz}, {xy, yy - lam, yz}, {xz, yz, zz - lam}};
+    double best = -1.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = a + 1; b < 3; ++b) {
+            const double c[3] = {R[a][1] * R[b][2] - R[a][2] * R[b][1], R[a][2] * R[b][0] - R[a][0] * R[b][2],
+                                 R[a][0] * R[b][1] - R[a][1] * R[b][0]};
+            const double l2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+            if (l2 > best) { best = l2; v[0] = c[0]; v[1] = c[1]; v[2] = c[2]; }
+        }
+    double rn = 0.0;
+    int ra = 0;
+    for (int a = 0; a < 3; ++a) {
+        const double l2 = R[a][0] * R[a][0] + R[a][1] * R[a][1] + R[a][2] * R[a][2];
+        if (l2 > rn) { rn = l2; ra = a; }
+    }
+    if (!(best > 1e-24 * rn * rn)) {  // repeated top eigenvalue: orthogonal to the largest row
+        const double *w = R[ra];
+        const int k = fabs(w[0]) <= fabs(w[1]) ? (fabs(w[0]) <= fabs(w[2]) ? 0 : 2) : (fabs(w[1]) <= fabs(w[2]) ? 1 : 2);
+        const double e[3] = {k == 0 ? 1.0 : 0.0, k == 1 ? 1.0 : 0.0, k == 2 ? 1.0 : 0.0};
+        v[0] = w[1] * e[2] - w[2] * e[1]; v[1] = w[2] * e[0] - w[0] * e[2]; v[2] = w[0] * e[1] - w[1] * e[0];
+    }
+    const double n = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    for (int i = 0; i < 3; ++i) v[i] /= n;
+    return lam;
+}
+
+// Both records of a primitive: S, and the roughened S~ = S + a^2 s3 (I - v3
+// v3^T) of App. B (a = GGX alpha of the roughness, s3 the largest eigenvalue
+// of S, v3 its eigenvector); the specular-lobe probability 1 / (1 + (1 - m)
+// luminance(albedo)) and the metallic m ride in the first record.
+__device__ inline bool sggx_prepare_prim(const double s[6], float rough, float met, const float alb[3],
+                                         float4 rec[8]) {
+    bool ok = sggx_prepare(s, rec);
+    double v[3];
+    const double top = ok ? sym3_top(s, v) : 0.0;
+    const double a = (double)ggx_alpha(rough), c = a * a * top;
+    const double r6[6] = {s[0] + c * (1.0 - v[0] * v[0]), s[1] + c * (1.0 - v[1] * v[1]), s[2] + c * (1.0 - v[2] * v[2]),
+                          s[3] - c * v[0] * v[1], s[4] - c * v[0] * v[2], s[5] - c * v[1] * v[2]};
+    ok = ok && sggx_prepare(r6, rec + 4);
+    const double lum = 0.2126 * alb[0] + 0.7152 * alb[1] + 0.0722 * alb[2];
+    rec[3].y = met;
+    rec[3].z = (float)(1.0 / (1.0 + (1.0 - (double)met) * lum));
+    return ok;
+}
+
 __device__ __forceinline__ Sggx sggx_load(const float4 *rec) {
     const float4 a = rec[0], b = rec[1], c = rec[2], d = rec[3];
-    return Sggx{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w, d.x};
+    return Sggx{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w, d.x, d.y, d.z};
 }
 __device__ __forceinline__ V3 sggx_S(const Sggx &g, V3 v) {
     return v3(g.xx * v.x + g.xy * v.y + g.xz * v.z, g.xy * v.x + g.yy * v.y + g.yz * v.z,
@@ -247,6 +315,12 @@ __device__ __forceinline__ float sggx_vndf(const Sggx &g, V3 wo, V3 n, float sig
 // ellipse of the 2x2 matrix [e_a^T S^-1 e_b] on the plane (e1, e2) orthogonal
 // to wo, from the unit disk by its Cholesky factor), lifted to the front
 // surface x = q + t wo (larger root of x^T S x = 1); the normal is S x.
+// The shadow's quadratic form (the Schur complement of S along wo, the
+// inverse of that 2x2 matrix) maps q back to the disk point of radius^2 u1,
+// so the root is t = -B/A + sqrt((1 - u1) / A) with A = wo^T S wo, B =
+// q^T S wo: written so, with 1 - u1 exact in float, neither the
+// discriminant nor S x = (S q - (B/A) S wo) + sqrt((1 - u1)/A) S wo cancels
+// near the shadow's rim.
 __device__ inline V3 sggx_sample_vndf(const Sggx &g, V3 wo, float u1, float u2) {
     V3 e1, e2;
     onb(wo, e1, e2);
@@ -259,10 +333,8 @@ __device__ inline V3 sggx_sample_vndf(const Sggx &g, V3 wo, float u1, float u2) 
     const float a = r * cp, b = r * sp;
     const V3 q = (l11 * a) * e1 + (l21 * a + l22 * b) * e2;
     const V3 Sw = sggx_S(g, wo), Sq = sggx_S(g, q);
-    const float A = dot(wo, Sw), B = dot(q, Sw), C = dot(q, Sq) - 1.f;
-    const float disc = sqrtf(fmaxf(0.f, B * B - A * C));
-    const float t = B > 0.f ? -C / (B + disc) : (disc - B) / A;  // the larger root, without cancellation
-    return normalize(Sq + t * Sw);
+    const float A = dot(wo, Sw), B = dot(q, Sw);
+    return normalize((Sq - (B / A) * Sw) + sqrtf((1.f - u1) / A) * Sw);
 }
 
 // a direction cosine-distributed about the unit vector m
@@ -304,6 +376,131 @@ __device__ __forceinline__ float sggx_pdf_approx(V3 wo, V3 wi) {
 // exact), pdf reported for MIS = the approximate one.
 __device__ __forceinline__ V3 sggx_sample(const Sggx &g, V3 wo, float u0, float u1, float v0, float v1) {
     return cosine_about(sggx_sample_vndf(g, wo, u0, u1), v0, v1);
+}
+
+// ---------------------------------------------------------------------------
+// Material 3: SGGX microflakes with a Disney-style base BSDF (Sec. 4.2: a
+// microfacet specular component and a diffuse component with empirical
+// retro-reflection).  At a flake normal n, cosine-weighted, for base colour
+// c, roughness r (GGX alpha = r^2; r itself in the retro-reflection) and
+// metallic m:
+//   specular fs = F D G2 / (4 <n.wo>), Schlick F0 = 0.04 (1 - m) + c m
+//   diffuse  fd = (1 - m) c / pi (1 + (F_D90 - 1)(1 - <n.wi>)^5)
+//                 (1 + (F_D90 - 1)(1 - <n.wo>)^5) <n.wi>, F_D90 = 1/2 + 2 r <wi.h>^2
+// both zero unless wi and wo lie on n's side.
+// ---------------------------------------------------------------------------
+__device__ inline void disney_base(V3 c, float rough, float met, V3 n, V3 wo, V3 wi, V3 &fs, V3 &fd) {
+    fs = v3(0.f, 0.f, 0.f);
+    fd = fs;
+    const float co = dot(n, wo), ci = dot(n, wi);
+    if (!(co > 0.f) || !(ci > 0.f)) return;
+    const float a = ggx_alpha(rough);
+    const V3 h = normalize(wo + wi);
+    const float D = ggx_D(a, dot(n, h));
+    const float G2 = 1.f / (1.f + ggx_lambda(a, co) + ggx_lambda(a, ci));
+    const float cd = fmaxf(0.f, dot(wi, h));
+    const float sch = pow5(1.f - cd);
+    const float fd90 = 0.5f + 2.f * rough * cd * cd;
+    const float rl = 1.f + (fd90 - 1.f) * pow5(1.f - ci), rv = 1.f + (fd90 - 1.f) * pow5(1.f - co);
+    const float ks = D * G2 / (4.f * co), kd = (1.f - met) * kInvPi * rl * rv * ci;
+    const float f0x = 0.04f * (1.f - met) + c.x * met, f0y = 0.04f * (1.f - met) + c.y * met,
+                f0z = 0.04f * (1.f - met) + c.z * met;
+    fs = v3((f0x + (1.f - f0x) * sch) * ks, (f0y + (1.f - f0y) * sch) * ks, (f0z + (1.f - f0z) * sch) * ks);
+    fd = kd * c;
+}
+
+// a normal about the half vector h with density D(<n.h>) <n.h> (the GGX
+// distribution's own sampling with normal and half vector exchanged)
+__device__ __forceinline__ V3 ggx_ndf_about(V3 h, float a, float u1, float u2) {
+    V3 b1, b2;
+    onb(h, b1, b2);
+    const float t2 = a * a * u1 / (1.f - u1);
+    const float ct = rsqrtf(1.f + t2), st = sqrtf(t2) * ct;
+    float sp, cp;
+    sincosf(2.f * kPi * u2, &sp, &cp);
+    return (st * cp) * b1 + (st * sp) * b2 + ct * h;
+}
+
+// Improved stochastic evaluation of f_p (rgb) for material 3: per lobe, the
+// visible-normal sample n1 (u0, u1) and the lobe's own sampling reversed -- a
+// GGX normal about the half vector (u2, u3) for the specular lobe, a normal
+// cosine-distributed about wi (u4, u5) for the diffuse lobe -- combined by
+// the one-sample balance heuristic.
+__device__ inline V3 sggx_disney_est(const Sggx &g, V3 c, float rough, V3 wo, V3 wi, const float u[6]) {
+    const float a = ggx_alpha(rough), so = sggx_sigma(g, wo);
+    V3 f = v3(0.f, 0.f, 0.f), fs, fd;
+    const V3 hs = wo + wi;
+    const float hl2 = dot(hs, hs);
+    const bool hok = hl2 > 0.f;
+    const V3 h = hok ? rsqrtf(hl2) * hs : v3(0.f, 0.f, 1.f);
+    const V3 n1 = sggx_sample_vndf(g, wo, u[0], u[1]);
+    const float p1 = sggx_vndf(g, wo, n1, so);
+    if (p1 > 0.f) {
+        disney_base(c, rough, g.met, n1, wo, wi, fs, fd);
+        const float hn = hok ? dot(h, n1) : 0.f;
+        const float pm = hn > 0.f ? ggx_D(a, hn) * hn : 0.f;
+        const float pc = fmaxf(0.f, dot(wi, n1)) * kInvPi;
+        f = (p1 / (p1 + pm)) * fs + (p1 / (p1 + pc)) * fd;
+    }
+    if (hok) {
+        const V3 n2 = ggx_ndf_about(h, a, u[2], u[3]);
+        const float hn = dot(n2, h);
+        const float p2 = hn > 0.f ? ggx_D(a, hn) * hn : 0.f;
+        const float q2 = sggx_vndf(g, wo, n2, so);
+        if (p2 > 0.f && q2 > 0.f) {
+            disney_base(c, rough, g.met, n2, wo, wi, fs, fd);
+            f = f + (q2 / (p2 + q2)) * fs;
+        }
+    }
+    const V3 n3 = cosine_about(wi, u[4], u[5]);
+    const float p3 = fmaxf(0.f, dot(n3, wi)) * kInvPi;
+    const float q3 = sggx_vndf(g, wo, n3, so);
+    if (p3 > 0.f && q3 > 0.f) {
+        disney_base(c, rough, g.met, n3, wo, wi, fs, fd);
+        f = f + (q3 / (p3 + q3)) * fd;
+    }
+    return f;
+}
+
+// Importance sampling of material 3: a visible normal n (u0, u1), then the
+// base BSDF at n -- the specular lobe (GGX visible normals of n, reflected)
+// with probability ps, else cosine about n -- chosen by v0, direction from
+// (v1, v2).  wgt = base f / lobe-mixture pdf; false when no direction.
+__device__ inline bool sggx_disney_sample(const Sggx &g, V3 c, float rough, V3 wo, float u0, float u1, float v0,
+                                          float v1, float v2, V3 &wi, V3 &wgt) {
+    wgt = v3(0.f, 0.f, 0.f);
+    const V3 n = sggx_sample_vndf(g, wo, u0, u1);
+    if (v0 < g.ps) {
+        V3 b1, b2, w1;
+        onb(n, b1, b2);
+        float pd;
+        const V3 li = phase_sample_local(1, v3(1.f, 1.f, 1.f), rough, v3(dot(wo, b1), dot(wo, b2), dot(wo, n)), v1,
+                                         v2, w1, pd);
+        if (!(pd > 0.f)) return false;
+        wi = li.x * b1 + li.y * b2 + li.z * n;
+    } else {
+        wi = cosine_about(n, v1, v2);
+    }
+    const float co = dot(n, wo), ci = dot(n, wi);
+    if (!(co > 0.f) || !(ci > 0.f)) return false;
+    const float a = ggx_alpha(rough);
+    const float pdf = g.ps * ggx_D(a, dot(n, normalize(wo + wi))) / ((1.f + ggx_lambda(a, co)) * 4.f * co) +
+                      (1.f - g.ps) * ci * kInvPi;
+    if (!(pdf > 0.f)) return false;
+    V3 fs, fd;
+    disney_base(c, rough, g.met, n, wo, wi, fs, fd);
+    wgt = (1.f / pdf) * (fs + fd);
+    return true;
+}
+
+// Approximate MIS pdf of material 3 (App. B): ps times the roughened SGGX's
+// visible NDF at the half vector plus (1 - ps) <w_h . w_o> / pi.
+__device__ __forceinline__ float sggx_disney_pdf_approx(const Sggx &gr, float ps, V3 wo, V3 wi) {
+    const V3 hs = wo + wi;
+    const float l2 = dot(hs, hs);
+    if (!(l2 > 0.f)) return 0.f;
+    const V3 h = rsqrtf(l2) * hs;
+    return ps * sggx_vndf(gr, wo, h, sggx_sigma(gr, wo)) + (1.f - ps) * fmaxf(0.f, dot(h, wo)) * kInvPi;
 }
 
 // Camera set up on the host: origin, forward f, right r' = tan(vfov/2) aspect r,
