@@ -415,6 +415,48 @@ def albedo_grad_bench(args):
     print(json.dumps(res), flush=True)
 
 
+def sggx_bench(args):
+    """Cost of the SGGX microflake phase functions in the path tracer: the
+    100K mixed scene at 512x512, 16 spp, depth 8, rendered with its own
+    delta-NDF materials, then with half of the primitives SGGX microflakes
+    with a Lambertian base (material 2) and with a Disney-style base
+    (material 3).  One JSON line: ms per frame, Mrays/s and the shading
+    kernels' share per variant (kernel times from HIP events)."""
+    import torch
+
+    import paper_2406_09733_amd as P
+    from paper_2406_09733_amd import scenes
+
+    base_sc = scenes.mixed_100k()
+    cam = dict(scenes.camera("mixed_100k"), width=512, height=512)
+    rp = {"spp": 16, "max_depth": 8, "seed": 1, "env_radiance": (0.2, 0.2, 0.2)}
+    ctx = P.Context(0)
+    out = {}
+    for name, sc in (("delta_ndf", base_sc), ("sggx_lambert", scenes.with_sggx(base_sc, seed=7, frac=0.5)),
+                     ("sggx_disney", scenes.with_sggx(base_sc, seed=7, frac=0.5, base="disney"))):
+        ctx.build_bvh(sc)
+        ctx.set_profiling(0)
+        ctx.render(cam, dict(rp, spp=2, sample_offset=1000))
+        ctx.sync()
+        ctx.set_profiling(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.render(cam, rp)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = ctx.render_stats()
+        ctx.set_profiling(0)
+        kern = st["ms_collide"] + st["ms_collide_wide"] + st["ms_light"] + st["ms_env"] + st["ms_shade"] + st["ms_sort"]
+        out[name] = {"ms_per_frame": round(1e3 * dt, 2), "mrays_per_s": round(st["rays"] / dt / 1e6, 1),
+                     "shade_ms": round(st["ms_shade"], 2), "shade_share": round(st["ms_shade"] / max(kern, 1e-9), 3),
+                     "rays_per_path": round(st["rays"] / max(st["paths"], 1), 3)}
+        log(f"[bench] {name}: {json.dumps(out[name])}")
+    res = {"metric": "path tracing with SGGX microflake primitives, 100K mixed scene 512x512 16 spp depth 8",
+           "value": out["sggx_disney"]["ms_per_frame"], "unit": "ms", "higher_is_better": False,
+           "variants": out, "sggx_fraction": 0.5}
+    print(json.dumps(res), flush=True)
+
+
 def query_bench(args):
     """Per-ray query rates on the room (5.5M primitives): linear-model
     transmittance and free-flight sampling (the ordered sweep) against the
@@ -486,6 +528,7 @@ def main():
     ap.add_argument("--rf", action="store_true", help="run the radiance-field rendering benchmark instead")
     ap.add_argument("--queries", action="store_true", help="run the per-ray query benchmark instead")
     ap.add_argument("--albedo-grad", action="store_true", help="run the albedo-adjoint benchmark instead")
+    ap.add_argument("--sggx", action="store_true", help="run the SGGX phase-function benchmark instead")
     ap.add_argument("--rf-frames", type=int, default=40)
     ap.add_argument("--fit-steps", type=int, default=50)
     ap.add_argument("--fit-rebuild-every", type=int, default=1,
@@ -517,6 +560,9 @@ def main():
         return
     if args.albedo_grad:
         albedo_grad_bench(args)
+        return
+    if args.sggx:
+        sggx_bench(args)
         return
 
     import numpy as np

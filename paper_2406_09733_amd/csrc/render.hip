@@ -23,7 +23,10 @@
 // vertex, group): group 0 = (collision, emitter pick, cone u, cone v), group 1 =
 // (phase u, phase v, environment u, environment v); the camera jitter uses
 // vertex 0, group 0, the choice of radiance-cache training paths vertex 0,
-// group 2.
+// group 2.  At SGGX vertices: groups 3 and 4 drive the stochastic phase
+// evaluations of the light and environment samples (group 6 adds material
+// 3's third normal to each), group 5 the base BSDF's sample after the
+// visible normal.
 //
 // With the radiance cache, a path that is not a training path ends at
 // collision nrc_terminate_after + 1: after its emission pick-up, its
