@@ -345,15 +345,29 @@ ugp_status ugp_render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_param
  *   grad_albedo  [device] float [scene n][3] by original index, added to
  *   sum_rgb      [device] float [height][width][3] or NULL: the forward pass's
  *                per-pixel sum is added to it (as ugp_render's)
- * p->nrc_mode must be 0 (UGP_ERR_UNSUPPORTED otherwise); other arguments and
- * errors as ugp_render.  A diffuse channel of zero albedo reports a zero
- * gradient (the replay divides the albedo out).
+ * p->nrc_mode must be 0 and the scene may hold no material 3
+ * (UGP_ERR_UNSUPPORTED otherwise); other arguments and errors as ugp_render.
+ * A diffuse channel of zero albedo reports a zero gradient (the replay
+ * divides the albedo out).
  * Temporaries (three float4 per radiance slot) are stream-ordered. */
 ugp_status ugp_render_albedo_grad(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p,
                                   const float *d_image, float *grad_albedo, float *sum_rgb);
 
-/* Waits for the context's stream and reports deferred device-side errors
- * (queue or stack overflow) as UGP_ERR_OVERFLOW, clearing them. */
+/* Roughness adjoint of a render by the same path replay: at every scattering
+ * vertex the radiance that passes through it is weighted by d log f / d
+ * roughness of its phase function at the direction taken there (the glossy
+ * delta-NDF lobe of Sec. 4.2: GGX D and Smith G2 with alpha = roughness^2;
+ * 0 for Lambert and SGGX-Lambert vertices and for roughness <= 0.01, where
+ * alpha is clamped).  Sampling pdfs and MIS weights are held at their values;
+ * the phase sample is an importance sample of f and the MIS weights sum to
+ * one for every roughness, so this is an unbiased estimate of the derivative
+ * of the expected image (the sampled directions themselves move with the
+ * roughness, so it is not the derivative of one estimate).
+ *   grad_roughness [device] float [scene n] by original index, added to
+ * other arguments, errors and restrictions as ugp_render_albedo_grad. */
+ugp_status ugp_render_roughness_grad(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p,
+                                     const float *d_image, float *grad_roughness, float *sum_rgb);
+
 /* Test hook of the SGGX phase functions (materials 2 and 3; Sec. 4.2 and
  * App. B) for n independent queries (DEVICE arrays, float32):
  *   sggx[n][6]  S (xx, yy, zz, xy, xz, yz), positive definite
@@ -375,6 +389,8 @@ ugp_status ugp_render_albedo_grad(ugp_ctx ctx, const ugp_camera *cam, const ugp_
 ugp_status ugp_sggx_phase(ugp_ctx ctx, int64_t n, const float *sggx, const float *base, const float *dirs,
                           const float *u, float *out);
 
+/* Waits for the context's stream and reports deferred device-side errors
+ * (queue or stack overflow) as UGP_ERR_OVERFLOW, clearing them. */
 ugp_status ugp_sync(ugp_ctx ctx);
 
 /* [host] statistics of the last ugp_render call.  A "ray" is one traversal

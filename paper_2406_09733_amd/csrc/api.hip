@@ -244,7 +244,18 @@ ugp_status ugp_render_albedo_grad(ugp_ctx ctx, const ugp_camera *cam, const ugp_
     if (s != UGP_OK) return s;
     if (p->nrc_mode != 0 || ctx->scene.has_mat3) return UGP_ERR_UNSUPPORTED;
     DeviceGuard g(ctx->device);
-    const ugp::RenderAdjoint adj{d_image, grad_albedo};
+    const ugp::RenderAdjoint adj{d_image, grad_albedo, 0};
+    return from_hip(ugp::render(ctx, cam, p, sum, nullptr, &adj));
+}
+
+ugp_status ugp_render_roughness_grad(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p,
+                                     const float *d_image, float *grad_roughness, float *sum) {
+    if (!d_image || !grad_roughness) return UGP_ERR_INVALID_ARGUMENT;
+    const ugp_status s = render_args(ctx, cam, p);
+    if (s != UGP_OK) return s;
+    if (p->nrc_mode != 0 || ctx->scene.has_mat3) return UGP_ERR_UNSUPPORTED;
+    DeviceGuard g(ctx->device);
+    const ugp::RenderAdjoint adj{d_image, grad_roughness, 1};
     return from_hip(ugp::render(ctx, cam, p, sum, nullptr, &adj));
 }
 

@@ -114,15 +114,30 @@ struct AdjArgs {
     float4 *aux_env = nullptr;    // per slot: the same for its environment sample
     float inv_spp = 0.f;
     uint32_t npix = 1;
+    int param = 0;                // 0: albedo (grad [n][3]); 1: roughness (grad [n], channels summed)
 };
 
 __device__ __forceinline__ void adj_grad(const AdjArgs &A, int slot, int k, float x, float y, float z) {
     const float *g = A.dimg + 3 * (int64_t)((uint32_t)slot % A.npix);
     float *dst = A.grad + 3 * (int64_t)k;
     const float gx = g[0] * A.inv_spp * x, gy = g[1] * A.inv_spp * y, gz = g[2] * A.inv_spp * z;
+    if (A.param == 1) {
+        const float t = gx + gy + gz;
+        if (t != 0.f) atomicAdd(A.grad + k, t);
+        return;
+    }
     if (gx != 0.f) atomicAdd(dst, gx);
     if (gy != 0.f) atomicAdd(dst + 1, gy);
     if (gz != 0.f) atomicAdd(dst + 2, gz);
+}
+
+// the ratio (d f / d parameter) / f of the adjoint's parameter at a vertex
+__device__ __forceinline__ V3 adj_ratio(const AdjArgs &A, int mat, V3 alb, float rough, V3 wo, V3 wi) {
+    if (A.param == 1) {
+        const float r = phase_rough_ratio(mat, rough, wo, wi);
+        return v3(r, r, r);
+    }
+    return phase_albedo_ratio(mat, alb, wo, wi);
 }
 
 // radiance c * f collected by the path of `slot`: added in the forward pass
@@ -519,7 +534,7 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
                         const V3 wt = (w / pn) * mul(mul(beta, f), f3(eL));
                         out.do_nee = true;
                         if (P.adj.dimg) {
-                            const V3 q = phase_albedo_ratio(mat, alb, wol, to_local(F, wl));
+                            const V3 q = adj_ratio(P.adj, mat, alb, rough, wol, to_local(F, wl));
                             P.adj.aux_nee[pix] = make_float4(q.x, q.y, q.z, __int_as_float(k));
                         }
                         out.na = make_float4(x.x, x.y, x.z, __int_as_float(e));
@@ -545,7 +560,7 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
                     const V3 wt = (w / pe) * mul(mul(beta, f), v3(P.env[0], P.env[1], P.env[2]));
                     out.do_env = true;
                     if (P.adj.dimg) {
-                        const V3 q = phase_albedo_ratio(mat, alb, wol, to_local(F, wl));
+                        const V3 q = adj_ratio(P.adj, mat, alb, rough, wol, to_local(F, wl));
                         P.adj.aux_env[pix] = make_float4(q.x, q.y, q.z, __int_as_float(k));
                     }
                     out.ea = make_float4(x.x, x.y, x.z, 0.f);
@@ -577,7 +592,7 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
                 if (nonzero(beta)) {
                     out.cont = true;
                     if (P.adj.dimg) {
-                        const V3 q = phase_albedo_ratio(mat, alb, wol, wil);
+                        const V3 q = adj_ratio(P.adj, mat, alb, rough, wol, wil);
                         P.adj.aux_cont[pix] = make_float4(q.x, q.y, q.z, __int_as_float(k));
                     }
                     out.ca = make_float4(x.x, x.y, x.z, pdf);
@@ -1046,6 +1061,7 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
         adjA.aux_env = aux + 2 * lcap;
         adjA.inv_spp = 1.f / (float)p->spp;
         adjA.npix = (uint32_t)npix;
+        adjA.param = adj->param;
     }
     PassArgs P;
     make_cam_dev(cam, &P.cam);

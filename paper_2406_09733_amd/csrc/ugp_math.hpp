@@ -141,6 +141,27 @@ __device__ inline V3 phase_albedo_ratio(int mat, V3 alb, V3 wo, V3 wi) {
               r(1.f - m, alb.z + (1.f - alb.z) * m));
 }
 
+// d log f / d roughness of the phase function above for the pair (wo, wi),
+// the same for every channel: the glossy lobe's D and G2 depend on alpha =
+// roughness^2 (Schlick F does not), the diffuse and SGGX-Lambert lobes not
+// at all; 0 where alpha is clamped (roughness <= 0.01).
+//   d log D / d alpha  = 2/alpha - 4 alpha c_h^2 / (c_h^2 (alpha^2 - 1) + 1)
+//   d log G2 / d alpha = -(dLambda_o + dLambda_i) G2,
+//   dLambda / d alpha  = alpha tan^2 / (2 sqrt(1 + alpha^2 tan^2))
+__device__ inline float phase_rough_ratio(int mat, float rough, V3 wo, V3 wi) {
+    const float a = rough * rough;
+    if (mat != 1 || !(a > 1e-4f) || wo.z <= 0.f || wi.z <= 0.f) return 0.f;
+    const V3 h = normalize(wo + wi);
+    const float c2 = h.z * h.z;
+    const float dlogD = 2.f / a - 4.f * a * c2 / (c2 * (a * a - 1.f) + 1.f);
+    auto dlam = [a](float c) __attribute__((always_inline)) {
+        const float t2 = fmaxf(0.f, 1.f - c * c) / (c * c);
+        return a * t2 / (2.f * sqrtf(1.f + a * a * t2));
+    };
+    const float G2 = 1.f / (1.f + ggx_lambda(a, wo.z) + ggx_lambda(a, wi.z));
+    return 2.f * rough * (dlogD - (dlam(wo.z) + dlam(wi.z)) * G2);
+}
+
 // local frame sample: returns wi, weight f/pdf; pdf 0 = no sample
 __device__ inline V3 phase_sample_local(int mat, V3 alb, float rough, V3 wo, float u1, float u2,
                                         V3 &wgt, float &pdf) {
