@@ -341,6 +341,83 @@ def transmittance_fit(args):
     print(json.dumps(res), flush=True)
 
 
+def shading_fit(args):
+    """Fit of the shading parameters through the path tracer's adjoints: the
+    100K mixed scene rendered from 8 views of 256x256 (depth 4, environment
+    0.3) as targets; a start with every albedo and roughness perturbed
+    (geometry held); Adam on albedo and roughness through autograd.render,
+    one view per step, each view rendered with its target's seed and spp
+    (common random numbers: the loss is zero at the truth and measures the
+    parameter error, not Monte Carlo noise).  Prints one JSON line: steps/s,
+    the image loss of the first and last ten steps and the parameter errors
+    of the primitives the views see most, at the start and the end."""
+    import numpy as np
+    import torch
+
+    import paper_2406_09733_amd as P
+    from paper_2406_09733_amd import autograd as A
+    from paper_2406_09733_amd import scenes
+
+    sc = scenes.mixed_100k()
+    n = sc["mean"].shape[0]
+    cams = scenes.ring_cameras((0.5, 0.5, 0.5), 2.2, n=8, size=256)
+    ctx = P.Context(0)
+    truth = {k: torch.tensor(np.asarray(v), device="cuda") for k, v in sc.items() if k != "bounds"}
+    spp = args.shading_fit_spp
+    rp = {"max_depth": 4, "env_radiance": (0.3, 0.3, 0.3), "spp": spp}
+    targets = [A.render(ctx, truth, c, dict(rp, seed=1000 + i)).detach() for i, c in enumerate(cams)]
+    rng = np.random.default_rng(21)
+    a_true = np.asarray(sc["albedo"], np.float64)
+    r_true = np.asarray(sc["roughness"], np.float64)
+    a0 = np.clip(a_true + rng.uniform(-0.3, 0.3, a_true.shape), 0.02, 0.98)
+    r0 = np.clip(r_true + rng.uniform(-0.3, 0.3, n), 0.05, 1.0)
+    params = dict(truth)
+    params["albedo"] = torch.tensor(a0.astype(np.float32), device="cuda", requires_grad=True)
+    params["roughness"] = torch.tensor(r0.astype(np.float32), device="cuda", requires_grad=True)
+    opt = torch.optim.Adam([params["albedo"], params["roughness"]], lr=0.02)
+    # the primitives the views see most: albedo gradient of a plain sum
+    seen_w = torch.zeros(n, device="cuda")
+    ctx.build_bvh(sc)
+    for c in cams:
+        g = torch.zeros((n, 3), device="cuda")
+        ctx.render_albedo_grad(c, dict(rp, spp=1, seed=7), torch.ones((256, 256, 3), device="cuda"), g)
+        seen_w += g.abs().sum(1)
+    seen = torch.argsort(-seen_w)[:2000].cpu().numpy()
+    glossy = seen[np.asarray(sc["material"])[seen] == 1]
+    steps = args.shading_fit_steps
+    losses = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(steps):
+        v = it % len(cams)
+        img = A.render(ctx, params, cams[v], dict(rp, seed=1000 + v))
+        loss = ((img - targets[v]) ** 2).mean()
+        opt.zero_grad()
+        loss.backward()
+        opt.step()
+        with torch.no_grad():
+            params["albedo"].clamp_(0.01, 0.99)
+            params["roughness"].clamp_(0.05, 1.0)
+        losses.append(float(loss.item()))
+        if it % 40 == 0:
+            log(f"[shading-fit] step {it} loss {losses[-1]:.4e}")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    a1 = params["albedo"].detach().cpu().numpy().astype(np.float64)
+    r1 = params["roughness"].detach().cpu().numpy().astype(np.float64)
+    res = {"metric": "shading fit (albedo + roughness through the path-replay adjoints), 100K mixed scene, "
+                     "8 views of 256x256",
+           "value": round(steps / dt, 3), "unit": "steps/s", "ms_per_step": round(1e3 * dt / steps, 2),
+           "steps": steps, "spp": spp, "max_depth": rp["max_depth"],
+           "loss_first10": float(np.mean(losses[:10])), "loss_last10": float(np.mean(losses[-10:])),
+           "albedo_err_seen": [round(float(np.abs(a0[seen] - a_true[seen]).mean()), 4),
+                               round(float(np.abs(a1[seen] - a_true[seen]).mean()), 4)],
+           "roughness_err_seen_glossy": [round(float(np.abs(r0[glossy] - r_true[glossy]).mean()), 4),
+                                         round(float(np.abs(r1[glossy] - r_true[glossy]).mean()), 4)],
+           "seen_primitives": int(seen.size)}
+    print(json.dumps(res), flush=True)
+
+
 def rf_render_bench(args):
     """Radiance-field rendering (Sec. 8, eq. rf) at the resolution of the
     paper's timings (800x800, one ray per pixel) on a synthetic scene of
@@ -529,6 +606,10 @@ def main():
     ap.add_argument("--queries", action="store_true", help="run the per-ray query benchmark instead")
     ap.add_argument("--albedo-grad", action="store_true", help="run the albedo-adjoint benchmark instead")
     ap.add_argument("--sggx", action="store_true", help="run the SGGX phase-function benchmark instead")
+    ap.add_argument("--shading-fit", action="store_true",
+                    help="run the albedo + roughness fit through the path tracer's adjoints instead")
+    ap.add_argument("--shading-fit-steps", type=int, default=200)
+    ap.add_argument("--shading-fit-spp", type=int, default=8)
     ap.add_argument("--rf-frames", type=int, default=40)
     ap.add_argument("--fit-steps", type=int, default=50)
     ap.add_argument("--fit-rebuild-every", type=int, default=1,
@@ -563,6 +644,9 @@ def main():
         return
     if args.sggx:
         sggx_bench(args)
+        return
+    if args.shading_fit:
+        shading_fit(args)
         return
 
     import numpy as np

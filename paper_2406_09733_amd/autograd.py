@@ -1,7 +1,8 @@
 """torch.autograd functions over the library's differentiable images: the
 accumulated free-flight CDF of each ray (Sec. 7.2, eq. accum_cdf), the
 radiance-field image (Sec. 8, eq. rf), and the path-traced image as a
-function of the primitives' albedo (its shading adjoint by path replay).
+function of the primitives' albedo and roughness (the shading adjoints by
+path replay).
 
 The forward builds the hierarchy of the given parameters and renders with
 ugp_accum_cdf / ugp_rf_render; the backward is the library's
@@ -71,34 +72,47 @@ def rf_render(ugp, params: dict, rays, exclude=None):
 
 class _Render(torch.autograd.Function):
     @staticmethod
-    def forward(fctx, ugp, cam, rparams, fixed, albedo):
-        scene = dict(fixed, albedo=albedo.detach())
+    def forward(fctx, ugp, cam, rparams, fixed, albedo, roughness):
+        scene = dict(fixed, albedo=albedo.detach(), roughness=roughness.detach())
         ugp.build_bvh(scene)
         spp = int(rparams.get("spp", 1))
         s, _ = ugp.render(cam, dict(rparams, want_sumsq=False))
         fctx.ugp, fctx.cam, fctx.rparams, fctx.fixed, fctx.build_id = ugp, cam, rparams, fixed, ugp.build_id
-        fctx.save_for_backward(albedo)
+        fctx.save_for_backward(albedo, roughness)
         return s / spp
 
     @staticmethod
     def backward(fctx, g):
         ugp = fctx.ugp
-        (albedo,) = fctx.saved_tensors
+        albedo, roughness = fctx.saved_tensors
         if ugp.build_id != fctx.build_id:
-            ugp.build_bvh(dict(fctx.fixed, albedo=albedo.detach()))
+            ugp.build_bvh(dict(fctx.fixed, albedo=albedo.detach(), roughness=roughness.detach()))
             fctx.build_id = ugp.build_id
-        grad = torch.zeros((ugp.n, 3), device=ugp.device, dtype=torch.float32)
-        ugp.render_albedo_grad(fctx.cam, fctx.rparams, g.contiguous(), grad)
-        return None, None, None, None, grad
+        ga = gr = None
+        if fctx.needs_input_grad[4]:
+            ga = torch.zeros((ugp.n, 3), device=ugp.device, dtype=torch.float32)
+            ugp.render_albedo_grad(fctx.cam, fctx.rparams, g.contiguous(), ga)
+        if fctx.needs_input_grad[5]:
+            gr = torch.zeros(ugp.n, device=ugp.device, dtype=torch.float32)
+            ugp.render_roughness_grad(fctx.cam, fctx.rparams, g.contiguous(), gr)
+        return None, None, None, None, ga, gr
 
 
 def render(ugp, params: dict, cam: dict, render_params: dict):
     """Mean path-traced image (float32 [H, W, 3], ugp_render's sum / spp),
-    differentiable with respect to params["albedo"] [P, 3] (the other scene
-    fields are held fixed); the backward is ugp_render_albedo_grad with the
-    same camera and render parameters (same seed: the exact derivative of
-    this estimate).  The radiance cache must be off."""
+    differentiable with respect to params["albedo"] [P, 3] and
+    params["roughness"] [P] (the other scene fields are held fixed).  The
+    backward is ugp_render_albedo_grad (the exact derivative of this
+    estimate: same camera, render parameters and seed) and
+    ugp_render_roughness_grad (an unbiased estimate of the derivative of the
+    expected image), each only when its input requires a gradient.  The
+    radiance cache must be off."""
     dev = ugp.device
     albedo = torch.as_tensor(params["albedo"]).to(device=dev, dtype=torch.float32)
-    fixed = {k: params[k] for k in ("mean", "scale", "rotation", "density", "roughness", "emission", "material")}
-    return _Render.apply(ugp, cam, dict(render_params), fixed, albedo)
+    rough = torch.as_tensor(params["roughness"]).to(device=dev, dtype=torch.float32)
+    fixed = {k: params[k] for k in ("mean", "scale", "rotation", "density", "emission", "material")
+             if k in params}
+    for k in ("sggx", "metallic"):
+        if params.get(k) is not None:
+            fixed[k] = params[k]
+    return _Render.apply(ugp, cam, dict(render_params), fixed, albedo, rough)

@@ -171,3 +171,43 @@ def test_roughness_gradient_refusals(ctx, torch):
     with pytest.raises(P.UGPError):
         ctx.render_roughness_grad(cam, {"spp": 1, "max_depth": 2, "seed": 0, "nrc_mode": 2}, d_img,
                                   torch.zeros(200, device="cuda"))
+
+
+def test_autograd_render_roughness_fit(ctx, torch):
+    # gradient descent on the roughness through autograd.render under direct
+    # light by light sampling with common random numbers: there the image is
+    # a smooth function of the roughness and the adjoint is its exact
+    # derivative, so the fit is a deterministic optimisation whose minimum is
+    # the true roughness (with fresh seeds per step the roughness signal of
+    # this scene drowns in the Monte Carlo noise of small renders)
+    from paper_2406_09733_amd import autograd as A
+    _say("autograd render: fit roughness to an image (direct light, light sampling, same seed)")
+    sc = _scene()
+    truth = {k: torch.tensor(np.asarray(v), device="cuda") for k, v in sc.items() if k != "bounds"}
+    rp = dict(DIRECT, seed=50)
+    target = A.render(ctx, truth, CAM, rp).detach()
+    n = sc["mean"].shape[0]
+    r_true = np.asarray(sc["roughness"], np.float64)
+    r0 = np.clip(r_true + np.random.default_rng(7).uniform(-0.3, 0.3, n), 0.1, 0.95)
+    params = dict(truth)
+    params["roughness"] = torch.tensor(r0.astype(np.float32), device="cuda", requires_grad=True)
+    opt = torch.optim.Adam([params["roughness"]], lr=0.02)
+    losses = []
+    for it in range(80):
+        img = A.render(ctx, params, CAM, rp)
+        loss = ((img - target) ** 2).mean()
+        opt.zero_grad()
+        loss.backward()
+        opt.step()
+        with torch.no_grad():
+            params["roughness"].clamp_(0.05, 1.0)
+        losses.append(float(loss.item()))
+    g = _grad(ctx, torch, sc, np.ones((48, 48, 3), np.float32), DIRECT)
+    seen = np.argsort(-np.abs(g))[:20]
+    r1 = params["roughness"].detach().cpu().numpy().astype(np.float64)
+    err0 = np.abs(r0[seen] - r_true[seen]).mean()
+    err1 = np.abs(r1[seen] - r_true[seen]).mean()
+    _say(f"  image loss {losses[0]:.4e} -> {np.mean(losses[-5:]):.4e}; roughness error of the 20 most"
+         f" sensitive primitives {err0:.3f} -> {err1:.3f}")
+    assert np.mean(losses[-5:]) < 0.1 * losses[0]
+    assert err1 < 0.5 * err0
