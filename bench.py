@@ -374,7 +374,8 @@ def shading_fit(args):
     params = dict(truth)
     params["albedo"] = torch.tensor(a0.astype(np.float32), device="cuda", requires_grad=True)
     params["roughness"] = torch.tensor(r0.astype(np.float32), device="cuda", requires_grad=True)
-    opt = torch.optim.Adam([params["albedo"], params["roughness"]], lr=0.02)
+    opt = torch.optim.Adam([{"params": [params["albedo"]], "lr": args.shading_fit_lr[0]},
+                            {"params": [params["roughness"]], "lr": args.shading_fit_lr[1]}])
     # the primitives the views see most: albedo gradient of a plain sum
     seen_w = torch.zeros(n, device="cuda")
     ctx.build_bvh(sc)
@@ -408,7 +409,7 @@ def shading_fit(args):
     res = {"metric": "shading fit (albedo + roughness through the path-replay adjoints), 100K mixed scene, "
                      "8 views of 256x256",
            "value": round(steps / dt, 3), "unit": "steps/s", "ms_per_step": round(1e3 * dt / steps, 2),
-           "steps": steps, "spp": spp, "max_depth": rp["max_depth"],
+           "steps": steps, "spp": spp, "max_depth": rp["max_depth"], "lr_albedo_roughness": args.shading_fit_lr,
            "loss_first10": float(np.mean(losses[:10])), "loss_last10": float(np.mean(losses[-10:])),
            "albedo_err_seen": [round(float(np.abs(a0[seen] - a_true[seen]).mean()), 4),
                                round(float(np.abs(a1[seen] - a_true[seen]).mean()), 4)],
@@ -610,6 +611,8 @@ def main():
                     help="run the albedo + roughness fit through the path tracer's adjoints instead")
     ap.add_argument("--shading-fit-steps", type=int, default=200)
     ap.add_argument("--shading-fit-spp", type=int, default=8)
+    ap.add_argument("--shading-fit-lr", type=lambda v: [float(x) for x in v.split(",")], default=[0.02, 0.005],
+                    help="Adam learning rates: albedo,roughness")
     ap.add_argument("--rf-frames", type=int, default=40)
     ap.add_argument("--fit-steps", type=int, default=50)
     ap.add_argument("--fit-rebuild-every", type=int, default=1,
