@@ -1469,15 +1469,9 @@ static void trace_path(const orc_scene *S, const orc_render_params *P, const orc
         /* SGGX: uniforms of the light and environment estimates (groups 3, 4,
            and 6 for material 3's third normal) and of the base BSDF's sample
            about the visible normal (group 5) */
-        double q3[4], q4[4], q5[4], q6[4], e3[6], e4[6];
+        double q3[4] = {0}, q4[4] = {0}, q5[4] = {0}, q6[4] = {0}, e3[6], e4[6];
         rng4(seed, pix, sample, v, 0, u);
         rng4(seed, pix, sample, v, 1, g);
-        rng4(seed, pix, sample, v, 3, q3);
-        rng4(seed, pix, sample, v, 4, q4);
-        rng4(seed, pix, sample, v, 5, q5);
-        rng4(seed, pix, sample, v, 6, q6);
-        for (int i = 0; i < 4; ++i) { e3[i] = q3[i]; e4[i] = q4[i]; }
-        e3[4] = q6[0]; e3[5] = q6[1]; e4[4] = q6[2]; e4[5] = q6[3];
         gather(S, o, w, 0.0, INFINITY, self, 1, H);
         ocoll c;
         collide(S, H, 0.0, INFINITY, u[0], &c);
@@ -1509,6 +1503,14 @@ static void trace_path(const orc_scene *S, const orc_render_params *P, const orc
         }
         if ((int)v == P->max_depth + 1) break;
         double wo[3] = {-w[0], -w[1], -w[2]};
+        if (S->mat[k] >= 2) {  /* drawn only where an SGGX phase function uses them */
+            rng4(seed, pix, sample, v, 3, q3);
+            rng4(seed, pix, sample, v, 4, q4);
+            rng4(seed, pix, sample, v, 5, q5);
+            rng4(seed, pix, sample, v, 6, q6);
+        }
+        for (int i = 0; i < 4; ++i) { e3[i] = q3[i]; e4[i] = q4[i]; }
+        e3[4] = q6[0]; e3[5] = q6[1]; e4[4] = q6[2]; e4[5] = q6[3];
         const double *nrm = S->nrm + 3 * k, *alb = S->alb + 3 * k;
         double rough = S->rough[k];
         if (P->nrc_mode != 0) {
