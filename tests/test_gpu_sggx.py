@@ -211,6 +211,35 @@ def test_render_parity_sggx_disney_needles(ctx, orc, torch):
     assert d <= 3 * se + 1e-6
 
 
+@pytest.mark.parametrize("base", ["lambert", "disney"])
+def test_render_parity_sggx_mixed_full_size_sampled(ctx, orc, torch, base):
+    # the 100K mixed scene at its full configuration (512x512, 16 spp, depth
+    # 8) with half of the primitives SGGX: the GPU renders every pixel, the
+    # oracle 400 sampled pixels (same counter-based random numbers per pixel)
+    _say(f"render parity mixed_100k with SGGX ({base}) at 512x512, 16 spp, depth 8, 400 sampled pixels")
+    sc = scenes.with_sggx(scenes.mixed_100k(), seed=7, frac=0.5, base=base)
+    cam = dict(scenes.camera("mixed_100k"), width=512, height=512)
+    p = {"spp": 16, "max_depth": 8, "seed": 1, "env_radiance": (0.2, 0.2, 0.2)}
+    ctx.build_bvh(sc)
+    s, s2 = ctx.render(cam, p)
+    ctx.sync()
+    pix = np.sort(np.random.default_rng(11).choice(512 * 512, 400, replace=False))
+    s_ref, s2_ref, _ = orc.Scene(sc).render(cam, p, pixels=pix)
+    spp = p["spp"]
+    s = _np(s).reshape(-1, 3)[pix].astype(np.float64)
+    s2 = _np(s2).reshape(-1, 3)[pix].astype(np.float64)
+    m, m_ref = s / spp, s_ref / spp
+    v = np.maximum(s2 / spp - m ** 2, 0) / spp
+    v_ref = np.maximum(s2_ref / spp - m_ref ** 2, 0) / spp
+    z = np.abs(m - m_ref) / np.sqrt(v + v_ref + 1e-12)
+    frac = float((z > 3).mean())
+    gse = np.sqrt((v + v_ref).sum()) / m.size
+    _say(f"  mean gpu {m.mean():.6f} oracle {m_ref.mean():.6f} se {gse:.2e}; beyond 3 sigma {frac:.4f};"
+         f" identical pixels {(np.abs(m - m_ref) < 1e-4).mean():.3f}")
+    assert frac <= 0.01
+    assert abs(m.mean() - m_ref.mean()) <= 3 * gse + 1e-6
+
+
 def test_render_furnace_sggx(ctx, torch):
     _say("furnace with SGGX primitives")
     sc = scenes.with_sggx(scenes.tiny_random(seed=21, n_emit=0), seed=3, frac=1.0)
