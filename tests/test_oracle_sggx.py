@@ -259,3 +259,33 @@ def test_scene_rejects_bad_sggx(orc):
     sc2["material"][3] = 2
     with pytest.raises(ValueError):
         orc.Scene(sc2)
+
+
+def test_sggx_scene_generator_recipe():
+    # the generator's matrices: positive definite, the three kinds of the
+    # paper's phase-function figure in the primitive's own frame, identity
+    # for the primitives that keep a delta-NDF material
+    sc = scenes.tiny_random(seed=0, n=600, n_emit=5)
+    out = scenes.with_sggx(sc, seed=1, frac=0.5)
+    g = np.asarray(out["sggx"], np.float64)
+    S = np.stack([np.stack([g[:, 0], g[:, 3], g[:, 4]], 1), np.stack([g[:, 3], g[:, 1], g[:, 5]], 1),
+                  np.stack([g[:, 4], g[:, 5], g[:, 2]], 1)], 1)
+    lam = np.linalg.eigvalsh(S)
+    assert np.all(lam > 0)
+    mat = np.asarray(out["material"])
+    assert set(np.unique(mat)) <= {0, 2} and 200 < (mat == 2).sum() < 400
+    assert np.allclose(S[mat != 2], np.eye(3), atol=1e-6)
+    # top eigenvalue 1 (surface-like, fibre-like, isotropic); surface-like
+    # normals along the smallest-scale axis
+    assert np.allclose(lam[:, 2], 1.0, atol=1e-5)
+    q = np.asarray(sc["rotation"], np.float64)
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    from scipy.spatial.transform import Rotation
+    R = Rotation.from_quat(q[:, [1, 2, 3, 0]]).as_matrix()
+    smin = R[np.arange(600), :, np.argmin(np.asarray(sc["scale"]), 1)]
+    surf = (mat == 2) & (lam[:, 1] < 0.3) & (lam[:, 0] < 0.3)
+    assert surf.sum() > 30
+    top = np.linalg.eigh(S[surf])[1][:, :, 2]
+    assert np.allclose(np.abs(np.einsum("ni,ni->n", top, smin[surf])), 1.0, atol=1e-5)
+    d = scenes.with_sggx(sc, seed=1, frac=0.5, base="disney")
+    assert set(np.unique(d["material"])) <= {0, 3} and np.all((d["metallic"] >= 0) & (d["metallic"] < 1))
