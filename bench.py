@@ -13,17 +13,25 @@ paper_2406_09733_amd/scenes.py); inputs are resident in HBM before timing.
 
 Besides the JSON line's throughput it reports:
   roofline     the dominant kernel (the collision kernel): algorithmic bytes
-               per launch (4-wide BVH node records 128 B, primitive records 64 B,
-               re-read records 64 B; per ray the 48-B path record, its 4-B sort
-               index and the 8-B hit record) divided by its mean launch
-               duration from HIP events recorded around every launch during
-               the timed run, against 8 TB/s HBM; `traffic` is the HBM bytes
-               per launch of this run: HBM bytes per collision ray measured
-               with rocprofv3 counters (the summary under profiles/) times the
-               collision rays per launch, reported only while the kernel
-               sources still hash to the value recorded there;
+               per launch divided by its mean launch duration from HIP events
+               recorded around every launch during the timed run, against
+               8 TB/s HBM.  Algorithmic bytes per collision ray = 64 n_node +
+               64 n_prim + 32 (a node visit reads two child boxes' worth, a
+               primitive chord test one 64-B record, the ray 32 B), with
+               n_node and n_prim the measured means of an instrumented pass.
+               `traffic` is the HBM bytes per launch of this run: HBM bytes per
+               collision ray measured with rocprofv3 counters (the summary
+               under profiles/) times the collision rays per launch, reported
+               only while the kernel sources still hash to the value recorded
+               there.  `layout_model` gives the bytes of this build's own
+               layout (128-B 4-wide nodes, re-read records, the path record)
+               for comparison;
   cpu_baseline the FP64 CPU oracle on a bounded pixel subset of the same
-               workload, on this host's cores.
+               workload, on this host's cores and on one core, with the CPU model;
+  time_to_rmse the second half of the metric, bounded: plain, cached,
+               untrained-cache and cache-free-termination tracers at
+               480x270 (1/16 of the pixels of 1920x1080) against a
+               4096-spp plain reference, at exposure 1 (see time_to_rmse).
 
 With --time-to-rmse it instead runs the second half of the metric on the same
 scene: progressive renders of the plain tracer and of the neural-cache tracer
@@ -47,6 +55,10 @@ if ROOT not in sys.path:
 
 METRIC = "Mrays/s at 5.5M prims; time-to-RMSE 0.01, plain vs neural-cache tracer"
 HBM_PEAK_GBS = 8000.0
+# algorithmic bytes of the method (per node visit, per primitive chord test,
+# per ray) and, separately, of this build's layout (4-wide 128-B nodes,
+# re-read records, 48-B path record + 4-B sort index + 8-B hit)
+ALG_NODE_B, ALG_PRIM_B, ALG_RAY_B = 64, 64, 32
 NODE_B, PRIM_B, PATH_B = 128, 64, 60
 COUNTERS = os.path.join(ROOT, "profiles", "k_collide_room_5p5m_hbm_counters.md")
 
@@ -86,7 +98,7 @@ def cpu_baseline(sc, cam, params, target_s: float):
     S = oracle.Scene(sc)
     log(f"[cpu] oracle scene + BVH ready in {time.perf_counter() - t0:.1f}s")
     npix = cam["width"] * cam["height"]
-    nthreads = os.cpu_count() or 1
+    nthreads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1))
     p = dict(params, spp=1, sample_offset=0)
     # calibrate on a small subset, then size the timed subset to ~target_s
     stride = max(1, npix // 512)
@@ -100,9 +112,31 @@ def cpu_baseline(sc, cam, params, target_s: float):
     t0 = time.perf_counter()
     _, _, rays = S.render(cam, dict(p, sample_offset=1), pixels=pix, nthreads=nthreads)
     dt = time.perf_counter() - t0
-    return {"value": rays / dt / 1e6, "unit": "Mrays/s", "cores": nthreads, "kind": "oracle",
+    rate = rays / dt / 1e6
+    # one core, on a subset sized to about a third of the time
+    want1 = max(64, int(len(pix) * (target_s / 3) / (dt * nthreads)))
+    stride1 = max(1, npix // want1)
+    pix1 = np.arange(0, npix, stride1, dtype=np.int64)
+    t0 = time.perf_counter()
+    _, _, rays1 = S.render(cam, dict(p, sample_offset=2), pixels=pix1, nthreads=1)
+    dt1 = time.perf_counter() - t0
+    return {"value": rate, "unit": "Mrays/s", "cores": nthreads, "kind": "oracle",
             "sample": f"every {stride}th pixel of 1920x1080 ({len(pix)} camera paths), 1 spp, "
-                      f"max depth {params['max_depth']}, {rays} rays in {dt:.1f}s"}
+                      f"max depth {params['max_depth']}, {rays} rays in {dt:.1f}s",
+            "cpu_model": _cpu_model(), "value_1_core": rays1 / dt1 / 1e6,
+            "sample_1_core": f"every {stride1}th pixel ({len(pix1)} camera paths), {rays1} rays in {dt1:.1f}s"}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def _rmse(img, ref, k=1.0):
@@ -681,8 +715,11 @@ def main():
     ctx.sync()
     log(f"[bench] counters: {json.dumps(cnt)}")
     coll_rays_c = max(cnt["collision_rays"], 1)
-    bytes_per_coll_ray = (NODE_B * cnt["cat_nodes"][0] + PRIM_B * cnt["cat_prims"][0] +
-                          PRIM_B * cnt["cat_reloads"][0]) / coll_rays_c + PATH_B
+    n_node = cnt["cat_nodes"][0] / coll_rays_c
+    n_prim = cnt["cat_prims"][0] / coll_rays_c
+    n_reload = cnt["cat_reloads"][0] / coll_rays_c
+    alg_bytes_per_ray = ALG_NODE_B * n_node + ALG_PRIM_B * n_prim + ALG_RAY_B
+    layout_bytes_per_ray = NODE_B * n_node + PRIM_B * (n_prim + n_reload) + PATH_B
 
     # warm-up then timed passes (kernel durations from HIP events)
     ctx.set_profiling(1)
@@ -712,19 +749,26 @@ def main():
         f"shade {st['ms_shade']:.1f}, sort {st['ms_sort']:.1f}")
 
     launches = max(st["launches_collide"], 1)
-    achieved = (bytes_per_coll_ray * st["collision_rays"] / launches) / (st["ms_collide"] / launches * 1e-3) / 1e9
+    rays_per_launch = st["collision_rays"] / launches
+    launch_s = st["ms_collide"] / launches * 1e-3
+    achieved = alg_bytes_per_ray * rays_per_launch / launch_s / 1e9
     traffic = measured_traffic()
     if traffic is not None:
-        traffic *= st["collision_rays"] / launches  # HBM bytes per launch of this run
+        traffic *= rays_per_launch  # HBM bytes per launch of this run
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic / 1e9, 3),
                 "traffic_unit": "GB per launch",
-                "kernel": "k_collide (main)", "bytes_per_ray": round(bytes_per_coll_ray, 1),
-                "nodes_per_ray": round(cnt["cat_nodes"][0] / coll_rays_c, 2),
-                "prims_per_ray": round(cnt["cat_prims"][0] / coll_rays_c, 2),
-                "reloads_per_ray": round(cnt["cat_reloads"][0] / coll_rays_c, 2),
-                "mean_launch_ms": round(st["ms_collide"] / launches, 4), "launches": launches}
+                "kernel": "k_collide (main)",
+                "bytes_per_ray": round(alg_bytes_per_ray, 1),
+                "bytes_formula": "64 n_node + 64 n_prim + 32 per collision ray",
+                "nodes_per_ray": round(n_node, 2), "prims_per_ray": round(n_prim, 2),
+                "rays_per_launch": round(rays_per_launch, 1),
+                "mean_launch_ms": round(st["ms_collide"] / launches, 4), "launches": launches,
+                "traffic_gbs": None if traffic is None else round(traffic / launch_s / 1e9, 1),
+                "layout_model": {"bytes_per_ray": round(layout_bytes_per_ray, 1),
+                                 "reloads_per_ray": round(n_reload, 2),
+                                 "gbs": round(layout_bytes_per_ray * rays_per_launch / launch_s / 1e9, 1)}}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -16,7 +16,12 @@
  *    has consumed them (torch's caching allocator on the same stream does this).
  *  - Rays are float32 [n][8] = (origin.xyz, direction.xyz, t0, t1), direction of
  *    unit length, t1 may be +inf.  The ray is x(t) = origin + t * direction,
- *    t in [t0, t1] (Sec. 4.1 "Ray Integral").
+ *    t in [t0, t1] (Sec. 4.1 "Ray Integral").  The per-ray queries validate
+ *    each ray on the device (the host never reads the data): a non-finite
+ *    origin, direction or t0, a NaN t1, or a direction whose length differs
+ *    from 1 by more than 1e-3 makes that ray's outputs NaN (primitive -1)
+ *    without tracing it, leaves every other ray's results unchanged, and is
+ *    reported once by the next ugp_sync as UGP_ERR_INVALID_ARGUMENT.
  *  - Primitive indices in and out are the caller's original indices
  *    (0 .. n-1 in the order the scene was given); -1 means "none".
  *  - Problems a host check can see (NULL required pointer, bad sizes, eps
@@ -389,8 +394,11 @@ ugp_status ugp_render_roughness_grad(ugp_ctx ctx, const ugp_camera *cam, const u
 ugp_status ugp_sggx_phase(ugp_ctx ctx, int64_t n, const float *sggx, const float *base, const float *dirs,
                           const float *u, float *out);
 
-/* Waits for the context's stream and reports deferred device-side errors
- * (queue or stack overflow) as UGP_ERR_OVERFLOW, clearing them. */
+/* Waits for the context's stream and reports deferred device-side errors,
+ * clearing them: UGP_ERR_INVALID_ARGUMENT if a query since the last sync was
+ * given a ray that failed the device's validation (see the ray convention
+ * above), else UGP_ERR_OVERFLOW after a queue, stack or event-buffer
+ * overflow. */
 ugp_status ugp_sync(ugp_ctx ctx);
 
 /* [host] statistics of the last ugp_render call.  A "ray" is one traversal

@@ -49,6 +49,9 @@ def _apply(ugp, params: dict, rays, exclude, rgb: bool):
     dev = ugp.device
     f32 = lambda k: torch.as_tensor(params[k]).to(device=dev, dtype=torch.float32)
     fixed = {k: params[k] for k in ("albedo", "roughness", "material")}
+    for k in ("sggx", "metallic"):
+        if params.get(k) is not None:
+            fixed[k] = params[k]
     rays = torch.as_tensor(rays).to(device=dev, dtype=torch.float32).contiguous()
     if exclude is not None:
         exclude = torch.as_tensor(exclude).to(device=dev, dtype=torch.int32).contiguous()

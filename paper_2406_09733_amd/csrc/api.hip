@@ -363,7 +363,7 @@ ugp_status ugp_sync(ugp_ctx ctx) {
     if (e != hipSuccess) return from_hip(e);
     if (h) {
         hipMemset(ctx->err, 0, sizeof(uint32_t));
-        return UGP_ERR_OVERFLOW;
+        return (h & ugp::kErrRay) ? UGP_ERR_INVALID_ARGUMENT : UGP_ERR_OVERFLOW;
     }
     return UGP_OK;
 }

@@ -104,7 +104,12 @@ __global__ __launch_bounds__(kBlock) void k_cdf(SceneDev S, int64_t n, const flo
     __shared__ int stack[kStackSize * kBlock];
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     float l2 = 0.f;
-    if (i < n) {
+    // a ray that failed validation in the saturation sweep has a NaN t_sat:
+    // NaN outputs, no loss or gradient
+    const bool bad = i < n && isnan(tsat[i]);
+    if (bad && out)
+        for (int k = 0; k < (RGB ? 3 : 1); ++k) out[(RGB ? 3 : 1) * i + k] = __builtin_nanf("");
+    if (i < n && !bad) {
         const RayD r = load_ray(rays, i);
         const int ex = excl ? excl[i] : -1;
         const double tcl = tsat[i];

@@ -15,6 +15,11 @@ __global__ __launch_bounds__(kBlock) void k_transmittance(SceneDev S, int64_t n,
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const RayD r = load_ray(rays, i);
+    if (!ray_ok(r, err)) {
+        T[i] = __builtin_nanf("");
+        if (F) F[i] = __builtin_nanf("");
+        return;
+    }
     TraceCount tc;
     const float f = transmittance_F(S, r, excl ? excl[i] : -1, F == nullptr, stack, err, tc);
     T[i] = fmaxf(0.f, 1.f - f);
@@ -33,6 +38,10 @@ __global__ __launch_bounds__(kBlock) void k_exp_transmittance(SceneDev S, int64_
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const RayD r = load_ray(rays, i);
+    if (!ray_ok(r, err)) {
+        T[i] = __builtin_nanf("");
+        return;
+    }
     const int ex = excl ? excl[i] : -1;
     const float hi = r.t1 < 3.0e38 ? (float)r.t1 : kInf;
     TraceCount tc;
@@ -74,6 +83,11 @@ __global__ __launch_bounds__(kBlock) void k_exp_sample(SceneDev S, int64_t n, co
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const RayD r = load_ray(rays, i);
+    if (!ray_ok(r, err)) {
+        prim_out[i] = -1;
+        t_out[i] = __builtin_nanf("");
+        return;
+    }
     const int ex = excl ? excl[i] : -1;
     const float t1f = r.t1 < 3.0e38 ? (float)r.t1 : kInf;
     TraceCount tc;
@@ -129,8 +143,9 @@ struct SweepArgs {
     int32_t *ovf_count;
     int32_t *counts;     // optional [n][4] per-ray traversal counters
     double *td_out;      // optional: saturate mode, t_sat in full precision
-    float4 *ovf_state;   // optional [kOvfStateSlots][kOvfStateVecs]: the main pass's
+    float4 *ovf_state;   // optional [ovf_slots][kOvfStateVecs]: the main pass's
                          // state of the first overflowed rays, resumed by the wide pass
+    int64_t ovf_slots;   // overflowed rays with a saved state (the rest restart)
 };
 
 // An overflow happens at the end of a round that began with a full buffer of
@@ -208,10 +223,21 @@ __device__ __forceinline__ int write_out(const SweepArgs &A, int64_t i, const Sw
     return -1;
 }
 
+// outputs of a ray that failed validation
+__device__ __forceinline__ void write_invalid(const SweepArgs &A, int64_t i) {
+    if (A.prim_out) A.prim_out[i] = -1;
+    if (A.f_out) A.f_out[i] = __builtin_nanf("");
+    if (A.td_out) A.td_out[i] = __builtin_nan("");
+}
+
 template <int K>
 __device__ __forceinline__ void run_sweep(const SceneDev &S, const SweepArgs &A, int64_t i, int *stack,
                                           uint32_t *err, bool wide) {
     RayD r = load_ray(A.rays, i);
+    if (!ray_ok(r, err)) {
+        write_invalid(A, i);
+        return;
+    }
     const int ex = A.excl ? A.excl[i] : -1;
     int target = -1;
     float entry = -__builtin_huge_valf();
@@ -275,8 +301,10 @@ __global__ __launch_bounds__(kBlock, 2) void k_sweep_persist(SceneDev S, SweepAr
                 ex = A.excl ? A.excl[ray] : -1;
                 target = -1;
                 entry = -kInf;
-                bool ok = true;
-                if (A.mode == kModeEmitter) {
+                // the wide pass takes only rays the main pass validated
+                bool ok = LIST || ray_ok(r, err);
+                if (!ok) write_invalid(A, ray);
+                if (ok && A.mode == kModeEmitter) {
                     target = A.target[ray];
                     ok = emitter_ray(S, r, target, ex, entry);
                     if (!ok) A.f_out[ray] = 0.f;
@@ -286,7 +314,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_sweep_persist(SceneDev S, SweepAr
                     i = ray;
                     sweep_start(st, so, r, A.mode);
                     if constexpr (LIST)
-                        if (A.ovf_state && j < kOvfStateSlots)
+                        if (A.ovf_state && j < A.ovf_slots)
                             load_state(A.ovf_state + j * kOvfStateVecs, st, S, r, tc);
                 }
             } else {
@@ -298,11 +326,17 @@ __global__ __launch_bounds__(kBlock, 2) void k_sweep_persist(SceneDev S, SweepAr
         if (i >= 0 && sweep_round<K>(S, r, ex, A.mode, u, target, entry, st, so, stack, spill, susp, err, tc)) {
             const int slot = write_out(A, i, so, err, LIST);
             if constexpr (!LIST)
-                if (slot >= 0 && slot < kOvfStateSlots && A.ovf_state)
+                if (slot >= 0 && slot < A.ovf_slots && A.ovf_state)
                     save_state(A.ovf_state + (int64_t)slot * kOvfStateVecs, st);
             i = -1;
         }
     }
+}
+
+// clears the sweep's three counters (a kernel rather than a memset node, so
+// that a caller may capture the launches in a graph)
+__global__ void k_zero_counters(int32_t *c) {
+    if (threadIdx.x < 3) c[threadIdx.x] = 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_sweep_wide(SceneDev S, SweepArgs A, uint32_t *err) {
@@ -334,22 +368,21 @@ hipError_t launch_exp(ugp_ctx ctx, int64_t n, const float *rays, const int32_t *
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(ugp_ctx ctx, int mode, int64_t n, const float *rays, const int32_t *excl,
-                        const float *u, const int32_t *target, int32_t *prim_out, float *f_out,
-                        int32_t *counts, double *td_out) {
-    // [0] overflow count, [1] main-pass work counter, [2] wide-pass work
-    // counter, [3..] overflow list; then (16-B aligned) the resumable states
-    // of the first kOvfStateSlots overflowed rays (not with counts: the wide
-    // pass then starts each ray again and adds its own counts)
-    const size_t list_bytes = (sizeof(int32_t) * (size_t)(n + 3) + 15) & ~(size_t)15;
-    const size_t state_bytes = counts ? 0 : sizeof(float4) * kOvfStateVecs * (size_t)std::min(n, kOvfStateSlots);
-    char *mem = (char *)ctx_scratch(ctx, list_bytes + state_bytes);
-    if (!mem) return hipErrorOutOfMemory;
+// The sweep's working memory: [0] overflow count, [1] main-pass work counter,
+// [2] wide-pass work counter, [3..3+n) overflow list; then (16-B aligned) the
+// resumable states of the first `slots` overflowed rays (none with counts:
+// the wide pass then starts each ray again and adds its own counts).
+static size_t sweep_list_bytes(int64_t n) { return (sizeof(int32_t) * (size_t)(n + 3) + 15) & ~(size_t)15; }
+
+static hipError_t launch_sweep_in(ugp_ctx ctx, int mode, int64_t n, const float *rays, const int32_t *excl,
+                                  const float *u, const int32_t *target, int32_t *prim_out, float *f_out,
+                                  int32_t *counts, double *td_out, char *mem, int64_t slots) {
+    const size_t list_bytes = sweep_list_bytes(n);
     int32_t *buf = (int32_t *)mem;
-    hipError_t e = hipMemsetAsync(buf, 0, sizeof(int32_t) * 3, ctx->stream);
-    if (e != hipSuccess) return e;
-    float4 *state = counts ? nullptr : (float4 *)(mem + list_bytes);
-    SweepArgs A{mode, n, rays, excl, u, target, prim_out, f_out, buf + 3, buf, counts, td_out, state};
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, ctx->stream, buf);
+    float4 *state = (counts || slots == 0) ? nullptr : (float4 *)(mem + list_bytes);
+    SweepArgs A{mode, n, rays, excl, u, target, prim_out, f_out, buf + 3, buf, counts, td_out, state,
+                state ? slots : 0};
     const unsigned g = (unsigned)((n + kBlock - 1) / kBlock);
     const unsigned gp = std::min<unsigned>(g, 4096u);
     if (counts) {
@@ -362,6 +395,16 @@ hipError_t launch_sweep(ugp_ctx ctx, int mode, int64_t n, const float *rays, con
                            ctx->scene, A, buf + 2, ctx->err);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_sweep(ugp_ctx ctx, int mode, int64_t n, const float *rays, const int32_t *excl,
+                        const float *u, const int32_t *target, int32_t *prim_out, float *f_out,
+                        int32_t *counts, double *td_out) {
+    const int64_t slots = counts ? 0 : std::min(n, kOvfStateSlots);
+    const size_t bytes = sweep_list_bytes(n) + sizeof(float4) * kOvfStateVecs * (size_t)slots;
+    char *mem = (char *)ctx_scratch(ctx, bytes);
+    if (!mem) return hipErrorOutOfMemory;
+    return launch_sweep_in(ctx, mode, n, rays, excl, u, target, prim_out, f_out, counts, td_out, mem, slots);
 }
 
 }  // namespace ugp

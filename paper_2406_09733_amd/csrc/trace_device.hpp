@@ -64,6 +64,20 @@ __device__ __forceinline__ RayD load_ray(const float *rays, int64_t i) {
     return make_ray(a.x, a.y, a.z, a.w, b.x, b.y, b.z, (double)b.w);
 }
 
+// Validation of a caller's ray, which only the device sees: a finite origin
+// and direction, a direction of length within 1e-3 of 1, a finite t0 and a t1
+// that is not NaN (+inf is allowed).  A ray that fails sets kErrRay in the
+// error word (ugp_sync reports it as an invalid argument) and the query
+// writes NaN (or "no primitive") for it without traversing.
+__device__ __forceinline__ bool ray_ok(const RayD &r, uint32_t *err) {
+    const bool fin = isfinite(r.ox) && isfinite(r.oy) && isfinite(r.oz) && isfinite(r.dx) && isfinite(r.dy) &&
+                     isfinite(r.dz) && isfinite(r.t0) && !isnan(r.t1);
+    const double len = sqrt((double)r.dx * r.dx + (double)r.dy * r.dy + (double)r.dz * r.dz);
+    const bool ok = fin && fabs(len - 1.0) <= 1e-3;
+    if (!ok) atomicOr(err, kErrRay);
+    return ok;
+}
+
 // ---------------------------------------------------------------------------
 // Chord of the cut-off ellipsoid and the closed-form ray integral
 // (Sec. 4.1 eqs. ray_integral / cutoff_threshold, App. A).

@@ -43,8 +43,9 @@ struct SceneDev {
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};  // bounds of the primitive boxes
 };
 
-// Device error word bits (deferred errors reported by ugp_sync)
-enum : uint32_t { kErrStack = 1u, kErrEvents = 2u, kErrQueue = 4u };
+// Device error word bits (deferred errors reported by ugp_sync): buffer
+// overflows, and a caller's ray that failed validation (ray_ok)
+enum : uint32_t { kErrStack = 1u, kErrEvents = 2u, kErrQueue = 4u, kErrRay = 8u };
 
 // Sweep modes of the ordered traversal
 enum SweepMode : int { kModeCollide = 0, kModeSaturate = 1, kModeEmitter = 2 };

@@ -180,3 +180,29 @@ def test_autograd_backward_after_another_build(ctx, torch):
     assert live.sum() > 10
     assert np.all(_close_rows(got[live], ref[live], 0) <= 1e-5)
     assert np.all(got[~live] == 0)
+
+
+def test_autograd_on_a_scene_with_sggx_primitives(ctx, torch):
+    # the SGGX matrices and metallic values ride along as fixed fields, so the
+    # hierarchy rebuilt for the image accepts material 3 primitives; the
+    # transmittance image does not depend on the phase function
+    from paper_2406_09733_amd import autograd as A
+    _say("autograd accum_cdf on a scene with Disney-base SGGX primitives")
+    sa = _dense_tiny()
+    sg = scenes.with_sggx(sa, seed=3, frac=0.5, base="disney")
+    rays = scenes.probe_rays(sa, 1024, seed=234, aimed_frac=1.0, finite_frac=0.2)
+    w = torch.tensor(np.random.default_rng(6).uniform(0.0, 1.0, rays.shape[0]), device="cuda",
+                     dtype=torch.float32)
+    pa = _params(torch, sa)
+    (A.accum_cdf(ctx, pa, rays) * w).sum().backward()
+    pg = _params(torch, sg)
+    pg["sggx"] = torch.tensor(sg["sggx"], device="cuda")
+    pg["metallic"] = torch.tensor(sg["metallic"], device="cuda")
+    pg["material"] = torch.tensor(sg["material"], device="cuda")
+    (A.accum_cdf(ctx, pg, rays) * w).sum().backward()
+    ref, got = _rows(pa), _rows(pg)
+    live = np.abs(ref).max(axis=1) > 0
+    assert live.sum() > 10
+    # float atomics add in any order
+    assert np.all(_close_rows(got[live], ref[live], 0) <= 1e-5)
+    assert np.all(got[~live] == 0)

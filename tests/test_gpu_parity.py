@@ -49,7 +49,9 @@ def _np(t):
 
 
 def _rel_ok(got, ref, rtol=1e-5, floor=1e-3, atol=0.0):
-    return np.abs(got - ref) <= rtol * np.maximum(np.abs(ref), floor) + atol
+    # equal infinities (t_sat = t1 = inf) compare equal; inf - inf is not taken
+    with np.errstate(invalid="ignore"):
+        return (got == ref) | (np.abs(got - ref) <= rtol * np.maximum(np.abs(ref), floor) + atol)
 
 
 ATOL_SUM = 5e-7  # 4 ulp of 1.0 in float32
@@ -105,13 +107,17 @@ def test_saturation_parity(ctx, built, name):
     ts = _np(ctx.saturation(rays, ex)).astype(np.float64)
     ctx.sync()
     t1 = rays[:, 7].astype(np.float64)
-    same = (ts == t1) == (ts_ref == t1)
-    if same.mean() <= 0.999:
-        F_end, _ = S.transmittance(rays, ex)
-        bad = np.where(~same)[0][:8]
+    # the saturation status is decided by F_end >= 1 (reading C20): rays whose
+    # oracle F_end lies within the F bar of 1 may go either way, no others
+    F_end, _ = S.transmittance(rays, ex)
+    near = np.abs(F_end - 1.0) <= 1e-5 * np.maximum(F_end, 1e-3) + ATOL_SUM
+    same = (ts < t1) == (ts_ref < t1)
+    if not np.all(same | near):
+        bad = np.where(~(same | near))[0][:8]
         _say("  disagreeing rays:", [(int(i), float(ts[i]), float(ts_ref[i]), float(t1[i]), float(F_end[i]))
                                      for i in bad])
-    assert same.mean() > 0.999
+    _say(f"  status differs on {int((~same).sum())} rays, all within the F bar of 1: {bool(np.all(same | near))}")
+    assert np.all(same | near)
     sat = (ts_ref < t1) & (ts < t1)
     close = _rel_ok(ts, ts_ref)
     resid = np.abs(S.F_at(rays[sat], ts[sat], ex[sat]) - 1.0) <= 2e-5
@@ -299,6 +305,36 @@ def test_render_parity_mixed(ctx, orc, torch):
     assert d <= 3 * se + 1e-6
 
 
+def test_render_parity_mixed_full_size_sampled(ctx, orc, torch):
+    # the mixed scene at its full configuration (512x512, 16 spp, depth 8):
+    # the GPU renders every pixel, the oracle 400 sampled pixels with the same
+    # counter-based random numbers
+    _say("render parity mixed_100k at 512x512, 16 spp, depth 8, 400 sampled pixels")
+    sc = scenes.mixed_100k()
+    cam = scenes.camera("mixed_100k")
+    rs = scenes.render_settings("mixed_100k")
+    p = {"spp": rs["spp"], "max_depth": rs["max_depth"], "seed": rs["seed"]}
+    _build(ctx, sc)
+    s, s2 = ctx.render(cam, p)
+    ctx.sync()
+    pix = np.sort(np.random.default_rng(13).choice(512 * 512, 400, replace=False))
+    s_ref, s2_ref, _ = orc.Scene(sc).render(cam, p, pixels=pix)
+    spp = p["spp"]
+    s = _np(s).reshape(-1, 3)[pix].astype(np.float64)
+    s2 = _np(s2).reshape(-1, 3)[pix].astype(np.float64)
+    m, m_ref = s / spp, s_ref / spp
+    v = np.maximum(s2 / spp - m ** 2, 0) / spp
+    v_ref = np.maximum(s2_ref / spp - m_ref ** 2, 0) / spp
+    z = np.abs(m - m_ref) / np.sqrt(v + v_ref + 1e-12)
+    frac = float((z > 3).mean())
+    gse = np.sqrt((v + v_ref).sum()) / m.size
+    _say(f"  mean gpu {m.mean():.6f} oracle {m_ref.mean():.6f} se {gse:.2e}; beyond 3 sigma {frac:.4f};"
+         f" identical pixels {(np.abs(m - m_ref) < 1e-4).mean():.3f}")
+    assert frac <= 0.01
+    assert abs(m.mean() - m_ref.mean()) <= 3 * gse + 1e-6
+    assert m_ref.mean() > 0
+
+
 def test_render_parity_needles(ctx, orc, torch):
     # long primitives cut into slabs by the hierarchy, many overlapping
     _say("render parity needles 96x96 4 spp depth 6")
@@ -360,3 +396,53 @@ def test_render_tail_kernel_matches_wavefront(ctx, torch, mode):
     for s, q in out[1:]:
         assert torch.equal(s, out[0][0]) and torch.equal(q, out[0][1])
     assert float(out[0][0].sum()) > 0
+
+
+def test_invalid_rays_are_reported_once(ctx, torch):
+    # a NaN origin and a direction of length 1.01: those two rays get NaN (or
+    # "no primitive") without being traced, ugp_sync reports an invalid
+    # argument once, and every other ray's result is bit-identical to the
+    # clean batch's
+    import paper_2406_09733_amd as P
+    _say("device-side validation of ray inputs")
+    sc = scenes.needles()
+    _build(ctx, sc)
+    n = 3000
+    rays = scenes.probe_rays(sc, n, seed=105)
+    u = np.random.default_rng(10).uniform(0, 1, n).astype(np.float32)
+    tgt = np.random.default_rng(11).integers(0, sc["mean"].shape[0], n).astype(np.int32)
+    bad_rays = rays.copy()
+    bad_rays[5, 1] = np.nan
+    bad_rays[77, 3:6] *= 1.01
+    bad_rays[901, 6] = np.inf  # t0 must be finite
+    bad = np.zeros(n, bool)
+    bad[[5, 77, 901]] = True
+    queries = {
+        "transmittance": lambda r: ctx.transmittance(r, want_F=True),
+        "sample_collision": lambda r: ctx.sample_collision(r, u),
+        "saturation": lambda r: (ctx.saturation(r),),
+        "emitter_query": lambda r: (ctx.emitter_query(r, tgt),),
+        "exp_transmittance": lambda r: (ctx.exp_transmittance(r),),
+        "exp_sample_collision": lambda r: ctx.exp_sample_collision(r, 3),
+        "accum_cdf": lambda r: (ctx.accum_cdf(r),),
+    }
+    for name, fn in queries.items():
+        clean = [_np(x) for x in fn(rays)]
+        ctx.sync()
+        got = [_np(x) for x in fn(bad_rays)]
+        with pytest.raises(P.UGPError) as e:
+            ctx.sync()
+        assert e.value.code == 1, name
+        ctx.sync()  # reported once, then cleared
+        for c, g in zip(clean, got):
+            assert np.array_equal(c[~bad], g[~bad], equal_nan=True), name
+            if g.dtype == np.int32:
+                assert np.all(g[bad] == -1), name
+            else:
+                assert np.all(np.isnan(g[bad])), name
+        _say(f"  {name}: invalid rays flagged, others unchanged")
+    # a valid ray of length exactly within the 1e-3 bar passes
+    ok = rays.copy()
+    ok[:, 3:6] *= 1.0009
+    ctx.transmittance(ok)
+    ctx.sync()
