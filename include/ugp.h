@@ -206,6 +206,30 @@ ugp_status ugp_sample_collision(ugp_ctx ctx, int64_t n_rays, const float *rays,
                                 const int32_t *exclude, const float *u, int32_t *prim_out,
                                 float *t_out);
 
+/* Allocation-free variant of ugp_sample_collision, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Arguments, results and errors as
+ * ugp_sample_collision, except:
+ *  - n_rays at most UGP_NOALLOC_MAX_RAYS; a larger n_rays returns
+ *    UGP_ERR_INVALID_ARGUMENT and enqueues nothing.
+ *  - The call allocates nothing (no hipMalloc, hipFree, stream-ordered or
+ *    library allocation; no memset node).  Its working memory (the list of
+ *    rays that overflow the 16-entry buffer and the saved states they resume
+ *    from) is one fixed 32 MiB buffer per GPU, a device array of the library
+ *    that each GPU it runs on holds until the process ends; its address is
+ *    taken in ugp_create.  Overflowing rays beyond the first ones whose saved
+ *    states fit (at least 58,000) restart in the 64-entry pass instead of
+ *    resuming (the same result up to float rounding of t).  UGP_ERR_DEVICE if
+ *    the buffer is unavailable.
+ *  - Every call on one GPU shares that buffer and the previous call's
+ *    contents remain in it (each call clears what must start at zero): calls
+ *    that overlap on one GPU -- other streams, contexts or threads -- race, and
+ *    the caller serialises them. */
+#define UGP_NOALLOC_MAX_RAYS 4194304
+ugp_status ugp_sample_collision_noalloc(ugp_ctx ctx, int64_t n_rays, const float *rays,
+                                        const int32_t *exclude, const float *u, int32_t *prim_out,
+                                        float *t_out);
+
 /* Saturating distance per ray: smallest t in [t0, t1] with F(t) = 1 (Sec. 4,
  * below eq. free_flight_pdf), or t1 when F(t1) < 1.  tsat_out float [n]. */
 ugp_status ugp_saturation(ugp_ctx ctx, int64_t n_rays, const float *rays,

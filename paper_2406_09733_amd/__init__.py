@@ -19,6 +19,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libugp.so")
 _lib = None
 
+NOALLOC_MAX_RAYS = 4194304  # UGP_NOALLOC_MAX_RAYS
+
 STATUS = {0: "ok", 1: "invalid argument", 2: "out of device memory", 3: "device error",
           4: "no scene has been built", 5: "unsupported", 6: "a per-ray buffer overflowed"}
 
@@ -75,7 +77,7 @@ class _Stats(C.Structure):
 
 
 EXPORTS = ["ugp_create", "ugp_destroy", "ugp_set_stream", "ugp_build_bvh", "ugp_refit_bvh", "ugp_transmittance",
-           "ugp_sample_collision", "ugp_saturation", "ugp_emitter_query", "ugp_render", "ugp_render_albedo_grad",
+           "ugp_sample_collision", "ugp_sample_collision_noalloc", "ugp_saturation", "ugp_emitter_query", "ugp_render", "ugp_render_albedo_grad",
            "ugp_render_roughness_grad", "ugp_sync",
            "ugp_set_profiling", "ugp_set_path_pool", "ugp_set_tail_paths", "ugp_get_render_stats", "ugp_trace_counts", "ugp_status_string",
            "ugp_nrc_num_params", "ugp_nrc_set_weights", "ugp_nrc_get_weights", "ugp_nrc_encode",
@@ -99,6 +101,7 @@ def lib():
         L.ugp_refit_bvh.argtypes = [vp, C.POINTER(_Scene)]
         L.ugp_transmittance.argtypes = [vp, i64, vp, vp, vp, vp]
         L.ugp_sample_collision.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+        L.ugp_sample_collision_noalloc.argtypes = [vp, i64, vp, vp, vp, vp, vp]
         L.ugp_saturation.argtypes = [vp, i64, vp, vp, vp]
         L.ugp_emitter_query.argtypes = [vp, i64, vp, vp, vp, vp]
         L.ugp_render.argtypes = [vp, C.POINTER(_Camera), C.POINTER(_Params), vp, vp]
@@ -266,6 +269,24 @@ class Context:
         t = self.torch.empty(n, device=self.device, dtype=self.torch.float32)
         _check("ugp_sample_collision",
                lib().ugp_sample_collision(self.h, n, _ptr(r), _ptr(e), _ptr(uu), _ptr(prim), _ptr(t)))
+        return prim, t
+
+    def sample_collision_noalloc(self, rays, u, exclude=None, prim=None, t=None):
+        """ugp_sample_collision_noalloc -> (prim int32, t float32): the
+        allocation-free variant (the library allocates nothing; the outputs
+        are the caller's, allocated here unless given)"""
+        r = self._rays(rays)
+        n = r.shape[0]
+        e = self._excl(exclude, n)
+        uu = self._dev(u, self.torch.float32, (n,))
+        if prim is None:
+            prim = self.torch.empty(n, device=self.device, dtype=self.torch.int32)
+        if t is None:
+            t = self.torch.empty(n, device=self.device, dtype=self.torch.float32)
+        assert prim.dtype == self.torch.int32 and prim.numel() == n and prim.is_contiguous()
+        assert t.dtype == self.torch.float32 and t.numel() == n and t.is_contiguous()
+        _check("ugp_sample_collision_noalloc",
+               lib().ugp_sample_collision_noalloc(self.h, n, _ptr(r), _ptr(e), _ptr(uu), _ptr(prim), _ptr(t)))
         return prim, t
 
     def saturation(self, rays, exclude=None):

@@ -124,6 +124,9 @@ ugp_status ugp_create(int device, void *hip_stream, ugp_ctx *out) {
     }
     hipMemset(c->err, 0, sizeof(uint32_t));
     hipMemset(c->stats, 0, sizeof(int64_t) * 8);
+    // address of this device's copy of the allocation-free query's buffer
+    // (a failure here only disables ugp_sample_collision_noalloc)
+    (void)ugp::noalloc_init(device);
     *out = c;
     return UGP_OK;
 }
@@ -186,6 +189,18 @@ ugp_status ugp_sample_collision(ugp_ctx ctx, int64_t n, const float *rays, const
     if (n == 0) return UGP_OK;
     DeviceGuard g(ctx->device);
     return from_hip(ugp::launch_sweep(ctx, ugp::kModeCollide, n, rays, exclude, u, nullptr, prim, t));
+}
+
+ugp_status ugp_sample_collision_noalloc(ugp_ctx ctx, int64_t n, const float *rays, const int32_t *exclude,
+                                        const float *u, int32_t *prim, float *t) {
+    if (!query_args_ok(ctx, n, rays) || (n > 0 && (!u || !prim || !t))) return UGP_ERR_INVALID_ARGUMENT;
+    if (n > UGP_NOALLOC_MAX_RAYS) return UGP_ERR_INVALID_ARGUMENT;
+    if (ctx->scene.n == 0) return UGP_ERR_NO_SCENE;
+    if (n == 0) return UGP_OK;
+    DeviceGuard g(ctx->device);
+    const hipError_t e = ugp::launch_sweep_noalloc(ctx, ugp::kModeCollide, n, rays, exclude, u, nullptr, prim, t);
+    if (e == hipErrorNotInitialized) return UGP_ERR_DEVICE;
+    return from_hip(e);
 }
 
 ugp_status ugp_saturation(ugp_ctx ctx, int64_t n, const float *rays, const int32_t *exclude, float *tsat) {

@@ -3,6 +3,8 @@
 // the emitter (light-sampling) query.  One lane per ray, one wave64 per block,
 // the traversal stack in LDS.  Rays whose event buffer overflows in the main
 // (register) sweep are queued and re-run by a wide sweep.
+#include <mutex>
+
 #include "trace_device.hpp"
 
 namespace ugp {
@@ -405,6 +407,57 @@ hipError_t launch_sweep(ugp_ctx ctx, int mode, int64_t n, const float *rays, con
     char *mem = (char *)ctx_scratch(ctx, bytes);
     if (!mem) return hipErrorOutOfMemory;
     return launch_sweep_in(ctx, mode, n, rays, excl, u, target, prim_out, f_out, counts, td_out, mem, slots);
+}
+
+// ---------------------------------------------------------------------------
+// Working memory of the allocation-free collision query: one fixed buffer per
+// GPU in a file-scope device array, held until the process ends.  Host code
+// never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol): it uses the device address that
+// hipGetSymbolAddress returns, taken once per device with that device current.
+// Every call on one GPU shares the buffer, so calls that overlap on a GPU race.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kNoAllocBytes = size_t(32) << 20;
+static_assert(sizeof(int32_t) * (size_t)(kNoAllocMaxRays + 3) + 16 + (size_t(1) << 20) <= kNoAllocBytes,
+              "the overflow list of the largest call leaves room for resumable states");
+static_assert(kNoAllocMaxRays == UGP_NOALLOC_MAX_RAYS, "the header states the library's limit");
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kMaxDevices] = {};
+hipError_t g_noalloc_status[kMaxDevices] = {};
+bool g_noalloc_done[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_done[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));  // the caller made `device` current
+        g_noalloc_status[device] = e;
+        g_noalloc_ptr[device] = e == hipSuccess ? ptr : nullptr;
+        g_noalloc_done[device] = true;
+    }
+    return g_noalloc_status[device];
+}
+
+hipError_t launch_sweep_noalloc(ugp_ctx ctx, int mode, int64_t n, const float *rays, const int32_t *excl,
+                                const float *u, const int32_t *target, int32_t *prim_out, float *f_out) {
+    if (n > kNoAllocMaxRays) return hipErrorInvalidValue;
+    void *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_noalloc_mu);
+        if (ctx->device >= 0 && ctx->device < kMaxDevices && g_noalloc_done[ctx->device])
+            base = g_noalloc_ptr[ctx->device];
+    }
+    if (!base) return hipErrorNotInitialized;
+    const size_t list_bytes = sweep_list_bytes(n);
+    const int64_t slots = std::min<int64_t>(
+        n, (int64_t)((kNoAllocBytes - list_bytes) / (sizeof(float4) * kOvfStateVecs)));
+    return launch_sweep_in(ctx, mode, n, rays, excl, u, target, prim_out, f_out, nullptr, nullptr,
+                           (char *)base, slots);
 }
 
 }  // namespace ugp

@@ -111,6 +111,14 @@ hipError_t launch_sweep(ugp_ctx ctx, int mode, int64_t n, const float *rays, con
                         const float *u, const int32_t *target, int32_t *prim_out, float *f_out,
                         int32_t *counts = nullptr, double *td_out = nullptr);
 
+// allocation-free sweep: the working memory is a fixed per-GPU device array
+// (at most kNoAllocMaxRays rays per call); noalloc_init takes its address once
+// per device, with that device current
+constexpr int64_t kNoAllocMaxRays = int64_t(1) << 22;
+hipError_t noalloc_init(int device);
+hipError_t launch_sweep_noalloc(ugp_ctx ctx, int mode, int64_t n, const float *rays, const int32_t *excl,
+                                const float *u, const int32_t *target, int32_t *prim_out, float *f_out);
+
 // exponential variant: T = exp(-sum I_k) (sample = false) or decomposition-tracking samples
 hipError_t launch_exp(ugp_ctx ctx, int64_t n, const float *rays, const int32_t *excl, bool sample, uint64_t seed,
                       float *T, int32_t *prim_out, float *t_out);
