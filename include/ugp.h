@@ -244,6 +244,22 @@ ugp_status ugp_saturation(ugp_ctx ctx, int64_t n_rays, const float *rays,
 ugp_status ugp_emitter_query(ugp_ctx ctx, int64_t n_rays, const float *rays,
                              const int32_t *exclude, const int32_t *target, float *out);
 
+/* Test hook of the ray integral (Sec. 4.1 eq. ray_integral; App. A closed
+ * form): for each ray i and primitive prim[i] (original index), the integral
+ * of that primitive's cut-off kernel over the part of its chord inside
+ * [t0, t1], I = d sqrt(pi/(2A)) exp(-rho^2/2) [erf tau_b - erf tau_a]
+ * (erfc differences in the tails); 0 where the ray misses it.  Computed by the
+ * same device code as the queries above.  I_out float [n].  A prim[i] outside
+ * [0, n) gives NaN and is reported by ugp_sync as an invalid argument. */
+ugp_status ugp_ray_integral(ugp_ctx ctx, int64_t n_rays, const float *rays, const int32_t *prim,
+                            float *I_out);
+
+/* Test hook of the counter-based generator every random number of the path
+ * tracer is drawn from: Philox4x32-10 (Salmon et al., SC'11) of counters
+ * uint32 [n][4] under key (key low 32 bits, key high 32 bits); out uint32
+ * [n][4].  No scene is needed. */
+ugp_status ugp_philox(ugp_ctx ctx, int64_t n, const uint32_t *counters, uint64_t key, uint32_t *out);
+
 /* ---- Exponential variant (App. D; eq. exp_ff) ----------------------------
  * The same Gaussians read as a heterogeneous exponential medium, sigma_t =
  * sum_k G_k (the comparison variant of the paper's linear-vs-exponential

@@ -106,6 +106,7 @@ def lib():
                                        vp, C.c_int, vp]
         L.orc_path_records.restype = C.c_int
         L.orc_philox4x32_10.argtypes = [vp, vp, vp]
+        L.orc_philox4x32_10_batch.argtypes = [C.c_int64, vp, vp, vp]
         L.orc_nrc_num_params.restype = C.c_int
         L.orc_nrc_encode.argtypes = [C.c_int64, vp, vp, vp, vp]
         L.orc_nrc_forward.argtypes = [C.c_int64, vp, vp, vp]
@@ -123,8 +124,13 @@ def _addr(a):
 
 
 def philox4x32_10(ctr, key) -> np.ndarray:
+    """Philox4x32-10 of one counter [4] or of counters [n, 4] under key [2]"""
     c = np.ascontiguousarray(ctr, dtype=np.uint32)
     k = np.ascontiguousarray(key, dtype=np.uint32)
+    if c.ndim == 2:
+        out = np.zeros_like(c)
+        lib().orc_philox4x32_10_batch(c.shape[0], _addr(c), _addr(k), _addr(out))
+        return out
     out = np.zeros(4, dtype=np.uint32)
     lib().orc_philox4x32_10(_addr(c), _addr(k), _addr(out))
     return out

@@ -40,6 +40,7 @@ typedef struct {
 } orc_render_params;
 
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+void orc_philox4x32_10_batch(int64_t n, const uint32_t *ctr, const uint32_t key[2], uint32_t *out);
 void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
 
 int orc_scene_create(int64_t n, const float *mean, const float *scale, const float *rotation,

@@ -83,7 +83,8 @@ EXPORTS = ["ugp_create", "ugp_destroy", "ugp_set_stream", "ugp_build_bvh", "ugp_
            "ugp_nrc_num_params", "ugp_nrc_set_weights", "ugp_nrc_get_weights", "ugp_nrc_encode",
            "ugp_nrc_forward", "ugp_nrc_train_step", "ugp_nrc_records", "ugp_exp_transmittance",
            "ugp_exp_sample_collision", "ugp_accum_cdf", "ugp_rf_render", "ugp_accum_cdf_backward",
-           "ugp_rf_render_backward", "ugp_camera_rays", "ugp_fit_adam", "ugp_sggx_phase"]
+           "ugp_rf_render_backward", "ugp_camera_rays", "ugp_fit_adam", "ugp_sggx_phase", "ugp_ray_integral",
+           "ugp_philox"]
 
 
 def lib():
@@ -103,6 +104,8 @@ def lib():
         L.ugp_sample_collision.argtypes = [vp, i64, vp, vp, vp, vp, vp]
         L.ugp_sample_collision_noalloc.argtypes = [vp, i64, vp, vp, vp, vp, vp]
         L.ugp_saturation.argtypes = [vp, i64, vp, vp, vp]
+        L.ugp_ray_integral.argtypes = [vp, i64, vp, vp, vp]
+        L.ugp_philox.argtypes = [vp, i64, vp, C.c_uint64, vp]
         L.ugp_emitter_query.argtypes = [vp, i64, vp, vp, vp, vp]
         L.ugp_render.argtypes = [vp, C.POINTER(_Camera), C.POINTER(_Params), vp, vp]
         L.ugp_render_albedo_grad.argtypes = [vp, C.POINTER(_Camera), C.POINTER(_Params), vp, vp, vp]
@@ -288,6 +291,26 @@ class Context:
         _check("ugp_sample_collision_noalloc",
                lib().ugp_sample_collision_noalloc(self.h, n, _ptr(r), _ptr(e), _ptr(uu), _ptr(prim), _ptr(t)))
         return prim, t
+
+    def ray_integral(self, rays, prim):
+        """ugp_ray_integral -> I float32 [n]: the integral of primitive prim[i]'s
+        kernel along ray i's clipped chord (test hook)"""
+        r = self._rays(rays)
+        n = r.shape[0]
+        pr = self._dev(prim, self.torch.int32, (n,))
+        out = self.torch.empty(n, device=self.device, dtype=self.torch.float32)
+        _check("ugp_ray_integral", lib().ugp_ray_integral(self.h, n, _ptr(r), _ptr(pr), _ptr(out)))
+        return out
+
+    def philox(self, counters, key: int):
+        """ugp_philox -> uint32 words [n, 4] (as int32 storage) of Philox4x32-10
+        of counters [n, 4] under key (test hook)"""
+        c = self.torch.as_tensor(np.ascontiguousarray(np.asarray(counters, np.uint32)).view(np.int32))
+        c = c.to(self.device).contiguous()
+        assert c.ndim == 2 and c.shape[1] == 4
+        out = self.torch.empty_like(c)
+        _check("ugp_philox", lib().ugp_philox(self.h, c.shape[0], _ptr(c), int(key), _ptr(out)))
+        return out
 
     def saturation(self, rays, exclude=None):
         """ugp_saturation -> t_sat float32"""

@@ -203,6 +203,21 @@ ugp_status ugp_sample_collision_noalloc(ugp_ctx ctx, int64_t n, const float *ray
     return from_hip(e);
 }
 
+ugp_status ugp_ray_integral(ugp_ctx ctx, int64_t n, const float *rays, const int32_t *prim, float *I_out) {
+    if (!query_args_ok(ctx, n, rays) || (n > 0 && (!prim || !I_out))) return UGP_ERR_INVALID_ARGUMENT;
+    if (ctx->scene.n == 0) return UGP_ERR_NO_SCENE;
+    if (n == 0) return UGP_OK;
+    DeviceGuard g(ctx->device);
+    return from_hip(ugp::launch_ray_integral(ctx, n, rays, prim, I_out));
+}
+
+ugp_status ugp_philox(ugp_ctx ctx, int64_t n, const uint32_t *counters, uint64_t key, uint32_t *out) {
+    if (!ctx || n < 0 || (n > 0 && (!counters || !out))) return UGP_ERR_INVALID_ARGUMENT;
+    if (n == 0) return UGP_OK;
+    DeviceGuard g(ctx->device);
+    return from_hip(ugp::launch_philox(ctx, n, counters, key, out));
+}
+
 ugp_status ugp_saturation(ugp_ctx ctx, int64_t n, const float *rays, const int32_t *exclude, float *tsat) {
     if (!query_args_ok(ctx, n, rays) || (n > 0 && !tsat)) return UGP_ERR_INVALID_ARGUMENT;
     if (ctx->scene.n == 0) return UGP_ERR_NO_SCENE;

@@ -132,6 +132,39 @@ __global__ __launch_bounds__(kBlock) void k_exp_sample(SceneDev S, int64_t n, co
     t_out[i] = bk >= 0 ? (float)best : __builtin_nanf("");
 }
 
+// Test hook of the ray integral (Sec. 4.1 eq. ray_integral, App. A): the
+// kernel's integral I_k over the ray's clipped chord of primitive k, computed
+// by the same chord() the sweeps use (on k's first reference; the chord is
+// the primitive's whatever slab holds it).  A missed primitive gives 0.
+__global__ void k_ray_integral(SceneDev S, int64_t n, const float *rays, const int32_t *prim, float *I,
+                               uint32_t *err) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const RayD r = load_ray(rays, i);
+    if (!ray_ok(r, err)) {
+        I[i] = __builtin_nanf("");
+        return;
+    }
+    const int k = prim[i];
+    if (k < 0 || k >= S.n) {
+        atomicOr(err, kErrRay);
+        I[i] = __builtin_nanf("");
+        return;
+    }
+    Chord c;
+    I[i] = chord(load_hot(S.hot, S.inv[k]), r, S.r2, c) ? 2.f * c.W : 0.f;
+}
+
+// Test hook of the counter-based generator: Philox4x32-10 of counters
+// [n][4] under one key, the function every random number of the renderer
+// comes from.
+__global__ void k_philox(int64_t n, const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint4 c = reinterpret_cast<const uint4 *>(ctr)[i];
+    reinterpret_cast<uint4 *>(out)[i] = philox4x32_10(c, k0, k1);
+}
+
 struct SweepArgs {
     int mode;
     int64_t n;
@@ -355,6 +388,19 @@ hipError_t launch_transmittance(ugp_ctx ctx, int64_t n, const float *rays, const
     const unsigned g = (unsigned)((n + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_transmittance, dim3(g), dim3(kBlock), 0, ctx->stream, ctx->scene, n, rays, excl, T,
                        F, ctx->err);
+    return hipGetLastError();
+}
+
+hipError_t launch_ray_integral(ugp_ctx ctx, int64_t n, const float *rays, const int32_t *prim, float *I) {
+    const unsigned g = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_ray_integral, dim3(g), dim3(256), 0, ctx->stream, ctx->scene, n, rays, prim, I, ctx->err);
+    return hipGetLastError();
+}
+
+hipError_t launch_philox(ugp_ctx ctx, int64_t n, const uint32_t *ctr, uint64_t key, uint32_t *out) {
+    const unsigned g = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_philox, dim3(g), dim3(256), 0, ctx->stream, n, ctr, (uint32_t)key, (uint32_t)(key >> 32),
+                       out);
     return hipGetLastError();
 }
 

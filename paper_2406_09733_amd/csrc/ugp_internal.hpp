@@ -119,6 +119,10 @@ hipError_t noalloc_init(int device);
 hipError_t launch_sweep_noalloc(ugp_ctx ctx, int mode, int64_t n, const float *rays, const int32_t *excl,
                                 const float *u, const int32_t *target, int32_t *prim_out, float *f_out);
 
+// test hooks: the ray integral of given primitives, Philox4x32-10 of given counters
+hipError_t launch_ray_integral(ugp_ctx ctx, int64_t n, const float *rays, const int32_t *prim, float *I);
+hipError_t launch_philox(ugp_ctx ctx, int64_t n, const uint32_t *ctr, uint64_t key, uint32_t *out);
+
 // exponential variant: T = exp(-sum I_k) (sample = false) or decomposition-tracking samples
 hipError_t launch_exp(ugp_ctx ctx, int64_t n, const float *rays, const int32_t *excl, bool sample, uint64_t seed,
                       float *T, int32_t *prim_out, float *t_out);

@@ -366,3 +366,71 @@ def test_render_training_records_parity(ctx, torch, orc):
     assert len(rec) > 500
     assert ok >= 0.99 * total
     c2.close()
+
+
+def test_trained_cache_gains_over_untrained_and_termination(torch):
+    # On the room at 160x90 (its configuration's depth 12, exposure 1): a
+    # cache trained online on the tracer's own records (2048 spp of training,
+    # 16 Adam steps on 262,144 records per chunk) leaves a smaller error against a converged plain
+    # reference than the same network untrained and than ending paths after two
+    # scattering events with nothing added, at equal spp (1024) and on the same
+    # random numbers (identical path prefixes: the images differ only in what
+    # the cache adds).  Error = the bias, estimated over pixels whose reference
+    # is below 0.9: mean (t - r)^2 minus the variance of t (from its per-pixel
+    # sums of squares) minus the variance of the reference r (from its two
+    # halves), which leaves mean (E t - E r)^2.  The clamped RMSE at exposure 1
+    # with the reference's noise removed (the benchmark's criterion) is
+    # reported beside it.
+    import paper_2406_09733_amd as P
+    from paper_2406_09733_amd import scenes
+    _say("trained cache vs untrained cache vs termination on the room at 160x90")
+    sc = scenes.room_5p5m()
+    ctx = P.Context(0)
+    ctx.build_bvh(sc)
+    cam = dict(scenes.camera("room_5p5m"), width=160, height=90)
+    base = {"max_depth": 12, "seed": 2}
+    halves = []
+    for h in range(2):
+        s, _ = ctx.render(cam, dict(base, spp=4096, sample_offset=4096 * h))
+        halves.append(s.double() / 4096)
+    ctx.sync()
+    a, b = halves
+    r = 0.5 * (a + b)
+    var_r = (a - b) ** 2 / 4
+    rng = np.random.default_rng(0)
+    from oracle import NRC_LAYERS
+    w0 = np.concatenate([rng.uniform(-1, 1, o * i) * np.sqrt(6.0 / i) for (o, i) in NRC_LAYERS]).astype(np.float32)
+    nrc = {"nrc_terminate_after": 2, "nrc_train_records": 262144, "nrc_lr": 1e-2, "nrc_train_steps": 16,
+           "nrc_target_clamp": 0.0}
+    ctx.nrc_set_weights(w0)
+    for k in range(16):
+        ctx.render(cam, dict(base, seed=5, spp=128, sample_offset=128 * k, want_sumsq=False, nrc_mode=1, **nrc))
+    ctx.sync()
+    spp = 1024
+    test = {"seed": 9, "spp": spp}
+
+    def err(mode, weights=None):
+        if weights is not None:
+            ctx.nrc_set_weights(weights)
+        # (nrc_radiance_scale 0 keeps the radiance unit the training set;
+        # setting weights clears it to 1)
+        s, s2 = ctx.render(cam, dict(base, **test, nrc_mode=mode, **nrc))
+        ctx.sync()
+        t = s.double() / spp
+        var_t = torch.clamp(s2.double() / spp - t * t, min=0) / spp
+        live = r.max(dim=2, keepdim=True).values.expand_as(r) < 0.9
+        bias2 = float(((t - r) ** 2 - var_t - var_r)[live].mean())
+        mse_c = float(((t.clamp(0, 1) - r.clamp(0, 1)) ** 2).mean())
+        noise_c = float(((a.clamp(0, 1) - b.clamp(0, 1)) ** 2 / 4).mean())
+        return bias2, max(0.0, mse_c - noise_c) ** 0.5
+
+    e_trained = err(2)  # the weights and unit the training left
+    e_term = err(3)
+    e_untrained = err(2, w0)
+    _say(f"  bias^2 (unsaturated pixels): trained {e_trained[0]:.3e}, untrained {e_untrained[0]:.3e}, "
+         f"termination {e_term[0]:.3e}")
+    _say(f"  clamped RMSE at exposure 1, reference noise removed: trained {e_trained[1]:.4f}, "
+         f"untrained {e_untrained[1]:.4f}, termination {e_term[1]:.4f}")
+    assert e_trained[0] < e_term[0] and e_trained[0] < e_untrained[0]
+    assert e_trained[1] < e_term[1] and e_trained[1] < e_untrained[1]
+    ctx.close()

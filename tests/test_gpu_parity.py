@@ -446,3 +446,52 @@ def test_invalid_rays_are_reported_once(ctx, torch):
     ok[:, 3:6] *= 1.0009
     ctx.transmittance(ok)
     ctx.sync()
+
+
+@pytest.mark.parametrize("name", ["tiny_random", "mixed_100k", "needles"])
+def test_ray_integral_parity(ctx, built, name):
+    # the closed-form integral of one primitive along a ray (App. A) against
+    # the oracle's, for rays aimed near the primitive (some clipped by t0, t1)
+    sc, S, _ = built[name]
+    _say("ray integral parity", name)
+    _build(ctx, sc)
+    n = 2048
+    rng = np.random.default_rng(106)
+    k = rng.integers(0, sc["mean"].shape[0], n).astype(np.int32)
+    mu = sc["mean"][k].astype(np.float64)
+    smax = sc["scale"][k].max(1).astype(np.float64)
+    o = mu + rng.normal(size=(n, 3)) * 0.3
+    w = mu + rng.normal(size=(n, 3)) * smax[:, None] - o
+    w /= np.linalg.norm(w, axis=1, keepdims=True)
+    dist = np.linalg.norm(mu - o, axis=1)
+    t0 = np.where(rng.uniform(size=n) < 0.3, dist + rng.normal(size=n) * smax, 0.0)
+    t1 = np.where(rng.uniform(size=n) < 0.3, dist + rng.normal(size=n) * smax, np.inf)
+    t1 = np.maximum(t1, t0)
+    rays = np.concatenate([o, w, t0[:, None], t1[:, None]], 1).astype(np.float32)
+    got = _np(ctx.ray_integral(rays, k)).astype(np.float64)
+    ctx.sync()
+    ref = np.array([S.ray_integral(int(k[i]), rays[i], float(rays[i, 6]), float(rays[i, 7])) for i in range(n)])
+    ok = _rel_ok(got, ref, atol=2 * ATOL_SUM)
+    _say(f"  nonzero {float((ref > 0).mean()):.3f}, max rel err {np.max(np.abs(got - ref) / np.maximum(ref, 1e-3)):.2e}")
+    assert ok.all(), (np.where(~ok)[0][:10], got[~ok][:5], ref[~ok][:5])
+    assert (ref > 0).mean() > 0.1  # thin needles are often missed
+
+
+def test_philox_matches_the_oracle_bit_for_bit(ctx, orc):
+    # 10^6 counters: the renderer's (pixel, sample, vertex, group) pattern and
+    # random words, under three keys
+    _say("Philox4x32-10: GPU vs oracle on 10^6 counters")
+    rng = np.random.default_rng(107)
+    n = 1 << 20
+    c = np.empty((n, 4), np.uint32)
+    half = n // 2
+    idx = np.arange(half, dtype=np.uint64)
+    c[:half, 0] = (idx % 1920 * 1080).astype(np.uint32)
+    c[:half, 1] = (idx // 2073600 + idx % 64).astype(np.uint32)
+    c[:half, 2] = (idx % 13).astype(np.uint32)
+    c[:half, 3] = (idx % 7).astype(np.uint32)
+    c[half:] = rng.integers(0, 2 ** 32, (n - half, 4), dtype=np.uint64).astype(np.uint32)
+    for key in (0, 2, (1 << 40) + 7):
+        got = ctx.philox(c, key).cpu().numpy().view(np.uint32)
+        ref = orc.philox4x32_10(c, [key & 0xFFFFFFFF, key >> 32])
+        assert np.array_equal(got, ref), (key, np.where((got != ref).any(1))[0][:5])

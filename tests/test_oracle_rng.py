@@ -35,3 +35,11 @@ def test_philox_uniform_statistics(orc):
     u = np.array(u)
     assert abs(u.mean() - 0.5) < 4 * np.sqrt(1 / 12 / u.size)
     assert abs(u.var() - 1 / 12) < 0.01
+
+
+def test_philox_batch_equals_single_calls(orc):
+    rng = np.random.default_rng(3)
+    c = rng.integers(0, 2 ** 32, (257, 4), dtype=np.uint64).astype(np.uint32)
+    got = orc.philox4x32_10(c, [5, 9])
+    for i in (0, 1, 100, 256):
+        assert got[i].tolist() == orc.philox4x32_10(c[i], [5, 9]).tolist()
