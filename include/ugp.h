@@ -413,6 +413,29 @@ ugp_status ugp_render_albedo_grad(ugp_ctx ctx, const ugp_camera *cam, const ugp_
 ugp_status ugp_render_roughness_grad(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p,
                                      const float *d_image, float *grad_roughness, float *sum_rgb);
 
+/* Density adjoint of a render (the derivative of the expected image with
+ * respect to every primitive's peak density d), by the same path replay.
+ * Densities enter only through the free-flight distribution (Sec. 4.1 eq.
+ * sampling_overlaps: a collision selects primitive k with probability
+ * W_k = 1/2 I_k(a_k, min(b_k, t_sat)) and escapes with probability
+ * T = 1 - F) and through the weights of light samples (the emitter factor
+ * W_k, eq. rte) and environment samples (T); scatter points, directions,
+ * throughputs and MIS weights do not depend on them.  So each collision adds
+ * the radiance its path collects from there on times d log W_k / d d_j (or
+ * d log T / d d_j on an escape), and each light or environment sample adds
+ * its contribution's derivative: I_j is linear in d_j, and t_sat moves by
+ * -(W_j(t_sat) / d_j) / F'(t_sat) with F' = 1/2 sum G (eq. free_flight_pdf).
+ * The result is an unbiased estimate of the derivative of the expected image
+ * (a score-function estimate: not the derivative of one estimate, whose
+ * discrete choices do not move with d).  Each collision and sample is traced
+ * again, up to three times (t_sat, F', the terms).
+ *   grad_density [device] float [scene n] by original index, added to (no
+ *                gradient for primitives of zero density)
+ * p->nrc_mode must be 0 (UGP_ERR_UNSUPPORTED); other arguments and errors as
+ * ugp_render_albedo_grad; every material is supported. */
+ugp_status ugp_render_density_grad(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p,
+                                   const float *d_image, float *grad_density, float *sum_rgb);
+
 /* Test hook of the SGGX phase functions (materials 2 and 3; Sec. 4.2 and
  * App. B) for n independent queries (DEVICE arrays, float32):
  *   sggx[n][6]  S (xx, yy, zz, xy, xz, yz), positive definite

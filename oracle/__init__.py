@@ -97,6 +97,7 @@ def lib():
         L.orc_sggx_disney_pdf_approx.argtypes = [vp, vp, C.c_double, C.c_double, vp, vp]
         L.orc_sggx_disney_pdf_approx.restype = C.c_double
         L.orc_sggx_disney_quad.argtypes = [vp, vp, C.c_double, C.c_double, vp, vp, C.c_int, C.c_int, vp]
+        L.orc_camera_rays.argtypes = [C.POINTER(_Camera), C.c_uint64, C.c_uint32, vp]
         L.orc_render.argtypes = [vp, C.POINTER(_Camera), C.POINTER(_Params), C.c_int64, vp,
                                  C.c_int, vp, vp]
         L.orc_render.restype = C.c_int64
@@ -351,6 +352,16 @@ class Scene:
         n = lib().orc_path_records(self.h, C.byref(c), C.byref(p), int(pixel), int(sample), _addr(rec),
                                    int(max_rec), _addr(L))
         return L, rec[:min(n, max_rec)]
+
+
+def camera_rays(cam: dict, seed: int, sample: int) -> np.ndarray:
+    """float32 [height * width, 8]: the oracle's camera rays of one sample of
+    every pixel, jittered as its path tracer jitters them."""
+    n = int(cam["width"]) * int(cam["height"])
+    out = np.zeros((n, 8), dtype=np.float32)
+    c = make_camera(cam)
+    lib().orc_camera_rays(C.byref(c), int(seed), int(sample), _addr(out))
+    return out
 
 
 def make_camera(cam: dict) -> _Camera:

@@ -1444,6 +1444,25 @@ static void camera_ray(const orc_camera *cam, int64_t px, int64_t py, double jx,
     normalize3(w);
 }
 
+/* The camera rays of one sample of every pixel (the jitter of vertex 0,
+ * group 0, as the path tracer draws it), rounded to float [npix][8] =
+ * (origin, direction, t0 = 0, t1 = inf). */
+void orc_camera_rays(const orc_camera *cam, uint64_t seed, uint32_t sample, float *rays) {
+    const int64_t npix = (int64_t)cam->width * cam->height;
+    for (int64_t i = 0; i < npix; ++i) {
+        double u[4], o[3], w[3];
+        rng4(seed, (uint32_t)i, sample, 0, 0, u);
+        camera_ray(cam, i % cam->width, i / cam->width, u[0], u[1], o, w);
+        float *r = rays + 8 * i;
+        for (int k = 0; k < 3; ++k) {
+            r[k] = (float)o[k];
+            r[3 + k] = (float)w[k];
+        }
+        r[6] = 0.f;
+        r[7] = (float)INFINITY;
+    }
+}
+
 /* Radiance of one camera path (vertex v = 1, 2, ...: collide, pick up
  * emission, stop after max_depth scattering events, else NEE and phase
  * sampling). */

@@ -114,6 +114,7 @@ double orc_sggx_disney_pdf_approx(const double s6[6], const double c[3], double 
 void orc_sggx_disney_quad(const double s6[6], const double c[3], double rough, double met, const double wo[3],
                           const double wi[3], int nz, int nphi, double f[3]);
 
+void orc_camera_rays(const orc_camera *cam, uint64_t seed, uint32_t sample, float *rays);
 int64_t orc_render(const orc_scene *S, const orc_camera *cam, const orc_render_params *p,
                    int64_t n_pix, const int64_t *pixels, int nthreads, double *sum, double *sumsq);
 void orc_path_radiance(const orc_scene *S, const orc_camera *cam, const orc_render_params *p,

@@ -75,47 +75,57 @@ def rf_render(ugp, params: dict, rays, exclude=None):
 
 class _Render(torch.autograd.Function):
     @staticmethod
-    def forward(fctx, ugp, cam, rparams, fixed, albedo, roughness):
-        scene = dict(fixed, albedo=albedo.detach(), roughness=roughness.detach())
+    def forward(fctx, ugp, cam, rparams, bparams, fixed, albedo, roughness, density):
+        scene = dict(fixed, albedo=albedo.detach(), roughness=roughness.detach(), density=density.detach())
         ugp.build_bvh(scene)
         spp = int(rparams.get("spp", 1))
         s, _ = ugp.render(cam, dict(rparams, want_sumsq=False))
-        fctx.ugp, fctx.cam, fctx.rparams, fctx.fixed, fctx.build_id = ugp, cam, rparams, fixed, ugp.build_id
-        fctx.save_for_backward(albedo, roughness)
+        fctx.ugp, fctx.cam, fctx.rparams, fctx.fixed, fctx.build_id = ugp, cam, bparams, fixed, ugp.build_id
+        fctx.save_for_backward(albedo, roughness, density)
         return s / spp
 
     @staticmethod
     def backward(fctx, g):
         ugp = fctx.ugp
-        albedo, roughness = fctx.saved_tensors
+        albedo, roughness, density = fctx.saved_tensors
         if ugp.build_id != fctx.build_id:
-            ugp.build_bvh(dict(fctx.fixed, albedo=albedo.detach(), roughness=roughness.detach()))
+            ugp.build_bvh(dict(fctx.fixed, albedo=albedo.detach(), roughness=roughness.detach(),
+                               density=density.detach()))
             fctx.build_id = ugp.build_id
-        ga = gr = None
-        if fctx.needs_input_grad[4]:
+        ga = gr = gd = None
+        if fctx.needs_input_grad[5]:
             ga = torch.zeros((ugp.n, 3), device=ugp.device, dtype=torch.float32)
             ugp.render_albedo_grad(fctx.cam, fctx.rparams, g.contiguous(), ga)
-        if fctx.needs_input_grad[5]:
+        if fctx.needs_input_grad[6]:
             gr = torch.zeros(ugp.n, device=ugp.device, dtype=torch.float32)
             ugp.render_roughness_grad(fctx.cam, fctx.rparams, g.contiguous(), gr)
-        return None, None, None, None, ga, gr
+        if fctx.needs_input_grad[7]:
+            gd = torch.zeros(ugp.n, device=ugp.device, dtype=torch.float32)
+            ugp.render_density_grad(fctx.cam, fctx.rparams, g.contiguous(), gd)
+        return None, None, None, None, None, ga, gr, gd
 
 
-def render(ugp, params: dict, cam: dict, render_params: dict):
+def render(ugp, params: dict, cam: dict, render_params: dict, backward_params: dict | None = None):
     """Mean path-traced image (float32 [H, W, 3], ugp_render's sum / spp),
-    differentiable with respect to params["albedo"] [P, 3] and
-    params["roughness"] [P] (the other scene fields are held fixed).  The
-    backward is ugp_render_albedo_grad (the exact derivative of this
-    estimate: same camera, render parameters and seed) and
-    ugp_render_roughness_grad (an unbiased estimate of the derivative of the
-    expected image), each only when its input requires a gradient.  The
-    radiance cache must be off."""
+    differentiable with respect to params["albedo"] [P, 3],
+    params["roughness"] [P] and params["density"] [P] (the other scene fields
+    are held fixed).  The backward is ugp_render_albedo_grad (the exact
+    derivative of this estimate: same camera, render parameters and seed),
+    ugp_render_roughness_grad and ugp_render_density_grad (unbiased estimates
+    of the derivative of the expected image), each only when its input
+    requires a gradient.  The radiance cache must be off.  backward_params
+    overrides render parameters of the backward pass only: another seed there
+    makes the gradient estimate independent of this image's noise (the
+    gradient of a loss that multiplies the two, such as |image - target|^2,
+    is otherwise biased by their correlation; the exact albedo derivative
+    then is of another estimate)."""
     dev = ugp.device
     albedo = torch.as_tensor(params["albedo"]).to(device=dev, dtype=torch.float32)
     rough = torch.as_tensor(params["roughness"]).to(device=dev, dtype=torch.float32)
-    fixed = {k: params[k] for k in ("mean", "scale", "rotation", "density", "emission", "material")
-             if k in params}
+    dens = torch.as_tensor(params["density"]).to(device=dev, dtype=torch.float32)
+    fixed = {k: params[k] for k in ("mean", "scale", "rotation", "emission", "material") if k in params}
     for k in ("sggx", "metallic"):
         if params.get(k) is not None:
             fixed[k] = params[k]
-    return _Render.apply(ugp, cam, dict(render_params), fixed, albedo, rough)
+    bparams = dict(render_params, **(backward_params or {}))
+    return _Render.apply(ugp, cam, dict(render_params), bparams, fixed, albedo, rough, dens)

@@ -289,6 +289,16 @@ ugp_status ugp_render_roughness_grad(ugp_ctx ctx, const ugp_camera *cam, const u
     return from_hip(ugp::render(ctx, cam, p, sum, nullptr, &adj));
 }
 
+ugp_status ugp_render_density_grad(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p,
+                                   const float *d_image, float *grad_density, float *sum) {
+    if (!d_image || !grad_density) return UGP_ERR_INVALID_ARGUMENT;
+    const ugp_status s = render_args(ctx, cam, p);
+    if (s != UGP_OK) return s;
+    if (p->nrc_mode != 0) return UGP_ERR_UNSUPPORTED;
+    DeviceGuard g(ctx->device);
+    const ugp::RenderAdjoint adj{d_image, grad_density, 2};
+    return from_hip(ugp::render(ctx, cam, p, sum, nullptr, &adj));
+}
 
 ugp_status ugp_exp_transmittance(ugp_ctx ctx, int64_t n, const float *rays, const int32_t *exclude, float *T_out) {
     if (!query_args_ok(ctx, n, rays) || (n > 0 && !T_out)) return UGP_ERR_INVALID_ARGUMENT;

@@ -395,6 +395,31 @@ __global__ __launch_bounds__(64) void k_nrc_wgrad(int64_t n_host, const int32_t 
             }
 }
 
+// Weight gradient of every layer from its record-slice partials ([slice][layer
+// params] per layer): grad[p] = sum over the nb slices, in a fixed order --
+// row y of a block sums slices y, y + 16, y + 32, ... in turn, then the 16
+// rows are added in row order.  64 parameters x 16 rows per block, one launch
+// for all layers (the slices are independent loads, summed 16 at a time).
+__global__ __launch_bounds__(1024) void k_nrc_reduce_grad(int nb, const float *part, float *grad) {
+    __shared__ float red[16][64];
+    const int x = threadIdx.x & 63, y = threadIdx.x >> 6;
+    const int p = blockIdx.x * 64 + x;
+    float s = 0.f;
+    if (p < kNParam) {
+        const int l = p < kMOff[1] ? 0 : p < kMOff[2] ? 1 : p < kMOff[3] ? 2 : p < kMOff[4] ? 3 : 4;
+        const int np = (l == 4 ? kNParam : kMOff[l + 1]) - kMOff[l];
+        const float *base = part + (int64_t)nb * kMOff[l] + (p - kMOff[l]);
+        for (int b = y; b < nb; b += 16) s += base[(int64_t)b * np];
+    }
+    red[y][x] = s;
+    __syncthreads();
+    if (y == 0 && p < kNParam) {
+        float t = 0.f;
+        for (int k = 0; k < 16; ++k) t += red[k][x];
+        grad[p] = t;
+    }
+}
+
 // out[p] = sum over b < nblocks of part[b][p], in block order
 __global__ void k_nrc_reduce(int nblocks, int np, const float *part, float *out) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -668,11 +693,8 @@ static hipError_t train_step_impl(ugp_ctx ctx, int64_t n, const int32_t *n_dev, 
                            (const __bf16 *)s->act[l], rpb, s->part + (int64_t)nb * kMOff[l]);
     hipLaunchKernelGGL((k_nrc_wgrad<32, 3, 64>), dim3(nb), dim3(64), 0, st, n, n_dev, (const __bf16 *)s->delta[4],
                        (const __bf16 *)s->act[4], rpb, s->part + (int64_t)nb * kMOff[4]);
-    for (int l = 0; l < 5; ++l) {
-        const int np = (l == 0 ? kNH * kNIn : l < 4 ? kNH * kNH : kNOut * kNH);
-        hipLaunchKernelGGL(k_nrc_reduce, dim3((np + 255) / 256), dim3(256), 0, st, nb, np,
-                           (const float *)(s->part + (int64_t)nb * kMOff[l]), s->grad + kMOff[l]);
-    }
+    hipLaunchKernelGGL(k_nrc_reduce_grad, dim3((kNParam + 63) / 64), dim3(1024), 0, st, nb, (const float *)s->part,
+                       s->grad);
     if (grad_out) {
         e = hipMemcpyAsync(grad_out, s->grad, sizeof(float) * kNParam, hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return e;

@@ -114,7 +114,8 @@ struct AdjArgs {
     float4 *aux_env = nullptr;    // per slot: the same for its environment sample
     float inv_spp = 0.f;
     uint32_t npix = 1;
-    int param = 0;                // 0: albedo (grad [n][3]); 1: roughness (grad [n], channels summed)
+    int param = 0;                // 0: albedo (grad [n][3]); 1: roughness (grad [n], channels summed);
+                                  // 2: density (grad [n]; the shading ratios and aux_* are not used)
 };
 
 __device__ __forceinline__ void adj_grad(const AdjArgs &A, int slot, int k, float x, float y, float z) {
@@ -432,7 +433,7 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
     V3 beta = f3(C);
     const Rng4 g0 = path_rng(P, (uint32_t)pix, (uint32_t)v, 0);
     const Rng4 g1 = path_rng(P, (uint32_t)pix, (uint32_t)v, 1);
-    if (P.adj.dimg && v >= 2) {
+    if (P.adj.aux_cont && v >= 2) {
         // replay: what is left to collect went through the previous vertex's continuation
         const float4 a = P.adj.aux_cont[pix], R = L[pix];
         adj_grad(P.adj, pix, __float_as_int(a.w), a.x * R.x, a.y * R.y, a.z * R.z);
@@ -533,7 +534,7 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
                         const float4 eL = S.cold[3 * e + 2];
                         const V3 wt = (w / pn) * mul(mul(beta, f), f3(eL));
                         out.do_nee = true;
-                        if (P.adj.dimg) {
+                        if (P.adj.aux_nee) {
                             const V3 q = adj_ratio(P.adj, mat, alb, rough, wol, to_local(F, wl));
                             P.adj.aux_nee[pix] = make_float4(q.x, q.y, q.z, __int_as_float(k));
                         }
@@ -559,7 +560,7 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
                     const float w = P.mis_mode == 2 ? 1.f : pe / (pe + pph);
                     const V3 wt = (w / pe) * mul(mul(beta, f), v3(P.env[0], P.env[1], P.env[2]));
                     out.do_env = true;
-                    if (P.adj.dimg) {
+                    if (P.adj.aux_env) {
                         const V3 q = adj_ratio(P.adj, mat, alb, rough, wol, to_local(F, wl));
                         P.adj.aux_env[pix] = make_float4(q.x, q.y, q.z, __int_as_float(k));
                     }
@@ -591,7 +592,7 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
                 beta = mul(beta, wgt);
                 if (nonzero(beta)) {
                     out.cont = true;
-                    if (P.adj.dimg) {
+                    if (P.adj.aux_cont) {
                         const V3 q = adj_ratio(P.adj, mat, alb, rough, wol, wil);
                         P.adj.aux_cont[pix] = make_float4(q.x, q.y, q.z, __int_as_float(k));
                     }
@@ -777,6 +778,160 @@ __device__ __forceinline__ SweepOut tail_sweep(const SceneDev &S, const RayD &r,
     if (so.status != 0) so = tail_sweep_wide(S, r, excl, mode, u, target, stop_a, stack, err, tc);
     if (so.status != 0) atomicOr(err, kErrEvents);
     return so;
+}
+
+// ---------------------------------------------------------------------------
+// Density adjoint of the path tracer (score function).  The densities change
+// no sampling decision's inputs other than the free-flight distribution: a
+// collision selects primitive k with probability W_k = 1/2 I_k(a_k, min(b_k,
+// t_sat)) or escapes with probability T = 1 - F (eq. sampling_overlaps), while
+// throughputs, emission pick-ups, directions, scatter points (chord centres)
+// and light-sampling densities do not depend on them.  So the derivative of
+// the expected image is the expectation, per path, of
+//   sum over collisions v: L_v * d log P_v / d d_j
+// (P_v the probability of the outcome drawn at v, L_v the radiance the path
+// collects from v on), plus the derivatives of the two estimator weights
+// that do depend on densities: the emitter factor W_k of a light sample
+// (emission rides on the free-flight probability, eq. rte) and the
+// transmittance of an environment sample.  I_j is linear in d_j, so at a
+// fixed t_sat d W_j / d d_j = W_j / d_j; t_sat moves by
+// d t_sat / d d_j = -(W_j(t_sat) / d_j) / F'(t_sat), F' = 1/2 sum G.  The MIS
+// weights do not depend on densities.  In the replay the path's slot holds
+// L_v when its collision v is processed (nothing of v is collected yet).
+// Primitives of zero density get no gradient (W_j / d_j is not formed).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float dens_weight(const AdjArgs &A, int slot, float x, float y, float z) {
+    const float *g = A.dimg + 3 * (int64_t)((uint32_t)slot % A.npix);
+    return A.inv_spp * (g[0] * x + g[1] * y + g[2] * z);
+}
+
+// every primitive j != excl whose clipped chord starts before hi: fn(record, chord)
+template <class Fn>
+__device__ __forceinline__ void dens_chords(const SceneDev &S, const RayD &r, int excl, float hi, int *stack,
+                                            uint32_t *err, TraceCount &tc, Fn &&fn) {
+    int spill[kStackSpill];
+    TravState ts;
+    trav_begin(ts, S);
+    traverse(S, r, r.t0, [&]() __attribute__((always_inline)) { return hi; }, stack, spill, ts, 0, err, tc,
+             [&](int p) __attribute__((always_inline)) {
+                 const HotRec h = load_hot(S.hot, p);
+                 return h.orig != excl && !surely_missed(h, r, S.r2);
+             },
+             [&](int p) __attribute__((always_inline)) {
+                 const HotRec h = load_hot(S.hot, p);
+                 Chord c;
+                 if (chord(h, r, S.r2, c, true) && c.own) fn(h, c);
+                 return false;
+             });
+}
+
+// the t_sat terms of a primitive k straddling t_sat whose weight (or
+// factor) enters with coefficient w: grad[j] -= w (1/2 G_k(t_sat)) / F'(t_sat)
+// * W_j(t_sat) / d_j for every j entering before t_sat (k included)
+__device__ __forceinline__ void dens_tsat_terms(const SceneDev &S, const RayD &r, int excl, double tsat, float gk,
+                                                float w, float *grad, int *stack, uint32_t *err, TraceCount &tc) {
+    const float hi = (float)tsat * (1.f + 1e-6f) + 1e-30f;
+    float Fp = 0.f;
+    dens_chords(S, r, excl, hi, stack, err, tc, [&](const HotRec &, const Chord &c) { Fp += half_kernel_at(c, tsat); });
+    if (!(Fp > 0.f) || gk == 0.f) return;
+    const float coef = w * gk / Fp;
+    dens_chords(S, r, excl, hi, stack, err, tc, [&](const HotRec &h, const Chord &c) {
+        const float wj = half_integral_to(c, tsat);
+        if (wj > 0.f && h.d > 0.f) atomicAdd(grad + h.orig, -coef * wj / h.d);
+    });
+}
+
+// escape (or an environment sample's transmittance T = 1 - F over the whole
+// ray): grad[j] -= w W_j / d_j for every j on the ray, w already divided by T
+// for an escape (d log T / d d_j = -(W_j / d_j) / T)
+__device__ __forceinline__ void dens_all(const SceneDev &S, const RayD &r, int excl, float w, bool log_T,
+                                         float *grad, int *stack, uint32_t *err, TraceCount &tc) {
+    if (log_T) {
+        float F = 0.f;
+        dens_chords(S, r, excl, kInf, stack, err, tc, [&](const HotRec &, const Chord &c) { F += c.W; });
+        const float T = 1.f - F;
+        if (!(T > 0.f)) return;
+        w /= T;
+    }
+    dens_chords(S, r, excl, kInf, stack, err, tc, [&](const HotRec &h, const Chord &c) {
+        if (c.W > 0.f && h.d > 0.f) atomicAdd(grad + h.orig, -w * c.W / h.d);
+    });
+}
+
+// collisions of the path queue (before their shading collects anything)
+__global__ __launch_bounds__(kBlock) void k_dens_collide(SceneDev S, PassArgs P, Queue q, const int32_t *n_in,
+                                                         const int2 *hits, const float4 *L, uint32_t *err) {
+    __shared__ int stack[kStackSize * kBlock];
+    const int n = *n_in;
+    TraceCount tc;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const float4 A = q.a[i], B = q.b[i], C = q.c[i];
+        const int slot = __float_as_int(C.w) & kPixMask;
+        const float4 Rv = L[slot];
+        const float w = dens_weight(P.adj, slot, Rv.x, Rv.y, Rv.z);
+        if (w == 0.f) continue;
+        const int excl = __float_as_int(B.w), k = hits[i].x;
+        const RayD r = make_ray(A.x, A.y, A.z, B.x, B.y, B.z, 0.f, __builtin_huge_val());
+        if (k < 0) {
+            dens_all(S, r, excl, w, true, P.adj.grad, stack, err, tc);
+            continue;
+        }
+        const HotRec hk = load_hot(S.hot, S.inv[k]);
+        Chord ck;
+        if (!chord(hk, r, S.r2, ck) || !(hk.d > 0.f)) continue;
+        atomicAdd(P.adj.grad + k, w / hk.d);
+        const SweepOut so = tail_sweep(S, r, excl, kModeSaturate, 0.f, -1, -kInf, stack, err, tc);
+        if (so.status == 0 && so.td < ck.bd) {  // k straddles t_sat
+            const float wk = half_integral_to(ck, so.td);
+            if (wk > 0.f)
+                dens_tsat_terms(S, r, excl, so.td, half_kernel_at(ck, so.td), w / wk, P.adj.grad, stack, err, tc);
+        }
+    }
+}
+
+// light samples: the emitter factor W_k of target k along the ray clipped at
+// its exit, times the sample's weight
+__global__ __launch_bounds__(kBlock) void k_dens_light(SceneDev S, LightQueue q, const int32_t *n_in, AdjArgs adj,
+                                                       uint32_t *err) {
+    __shared__ int stack[kStackSize * kBlock];
+    const int n = *n_in;
+    TraceCount tc;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const float4 A = q.a[i], B = q.b[i], C = q.c[i];
+        const float w = dens_weight(adj, __float_as_int(C.w), C.x, C.y, C.z);
+        if (w == 0.f) continue;
+        const int target = __float_as_int(A.w), excl = __float_as_int(B.w);
+        RayD r = make_ray(A.x, A.y, A.z, B.x, B.y, B.z, 0.f, __builtin_huge_val());
+        const HotRec hk = load_hot(S.hot, S.inv[target]);
+        Chord ck;
+        if (!chord(hk, r, S.r2, ck) || !(hk.d > 0.f)) continue;
+        r.t1 = ck.bd;
+        const SweepOut so = tail_sweep(S, r, excl, kModeSaturate, 0.f, -1, -kInf, stack, err, tc);
+        if (so.status != 0) continue;
+        const float wk = half_integral_to(ck, so.td);
+        if (!(wk > 0.f)) continue;  // hidden by primitives in front: factor 0
+        atomicAdd(adj.grad + target, w * wk / hk.d);
+        if (so.td < ck.bd)
+            dens_tsat_terms(S, r, excl, so.td, half_kernel_at(ck, so.td), w, adj.grad, stack, err, tc);
+    }
+}
+
+// environment samples: T = 1 - F along the whole ray, times the sample's weight
+__global__ __launch_bounds__(kBlock) void k_dens_env(SceneDev S, LightQueue q, const int32_t *n_in, AdjArgs adj,
+                                                     uint32_t *err) {
+    __shared__ int stack[kStackSize * kBlock];
+    const int n = *n_in;
+    TraceCount tc;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const float4 A = q.a[i], B = q.b[i], C = q.c[i];
+        const float w = dens_weight(adj, __float_as_int(C.w), C.x, C.y, C.z);
+        if (w == 0.f) continue;
+        const RayD r = make_ray(A.x, A.y, A.z, B.x, B.y, B.z, 0.f, __builtin_huge_val());
+        float F = 0.f;
+        dens_chords(S, r, __float_as_int(B.w), kInf, stack, err, tc, [&](const HotRec &, const Chord &c) { F += c.W; });
+        if (!(F < 1.f)) continue;  // T = 0: the sample added nothing, and nothing nearby
+        dens_all(S, r, __float_as_int(B.w), w, false, adj.grad, stack, err, tc);
+    }
 }
 
 __device__ __forceinline__ void add_radiance(float4 *L, int pix, float x, float y, float z, float f) {
@@ -1052,13 +1207,15 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
         }
     } aux_free{aux, st};
     if (adj) {
-        e = hipMallocAsync((void **)&aux, sizeof(float4) * 3 * (size_t)lcap, st);
-        if (e != hipSuccess) return e;
+        if (adj->param != 2) {  // the shading adjoints' per-slot ratios
+            e = hipMallocAsync((void **)&aux, sizeof(float4) * 3 * (size_t)lcap, st);
+            if (e != hipSuccess) return e;
+            adjA.aux_cont = aux;
+            adjA.aux_nee = aux + lcap;
+            adjA.aux_env = aux + 2 * lcap;
+        }
         adjA.dimg = adj->d_image;
         adjA.grad = adj->grad;
-        adjA.aux_cont = aux;
-        adjA.aux_nee = aux + lcap;
-        adjA.aux_env = aux + 2 * lcap;
         adjA.inv_spp = 1.f / (float)p->spp;
         adjA.npix = (uint32_t)npix;
         adjA.param = adj->param;
@@ -1213,6 +1370,9 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
                     hipLaunchKernelGGL((k_collide<kEventsWide, true>), dim3(gw), dim3(kBlock), 0, st, Sc[1], P, qin,
                                        (const int32_t *)c, order, c + 4, rb->hits, ctx->stats, ov, ctx->err);
                 });
+                if (P.adj.dimg && P.adj.param == 2)
+                    hipLaunchKernelGGL(k_dens_collide, dim3(gq), dim3(kBlock), 0, st, S, P, qin, (const int32_t *)c,
+                                       (const int2 *)rb->hits, (const float4 *)rb->L, ctx->err);
                 timed(4, [&] {
                     hipLaunchKernelGGL(k_shade, dim3(gq), dim3(kBlock), 0, st, S, P, qin, (const int32_t *)c,
                                        (const int2 *)rb->hits, qout, cn, rb->nee, c + 1, rb->env, c + 2, rb->L);
@@ -1235,12 +1395,18 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
                                            (const int32_t *)(c + 1), order, c + 5, rb->L, ctx->stats, ov, P.adj,
                                            ctx->err);
                     });
+                    if (P.adj.dimg && P.adj.param == 2)
+                        hipLaunchKernelGGL(k_dens_light, dim3(gq), dim3(kBlock), 0, st, S, rb->nee,
+                                           (const int32_t *)(c + 1), P.adj, ctx->err);
                 }
                 if (P.has_env && p->mis_mode != 1)
                     timed(3, [&] {
                         hipLaunchKernelGGL(k_env, dim3(gq), dim3(kBlock), 0, st, Sc[3], rb->env,
                                            (const int32_t *)(c + 2), rb->L, ctx->stats, P.adj, ctx->err);
                     });
+                if (P.has_env && p->mis_mode != 1 && P.adj.dimg && P.adj.param == 2)
+                    hipLaunchKernelGGL(k_dens_env, dim3(gq), dim3(kBlock), 0, st, S, rb->env, (const int32_t *)(c + 2),
+                                       P.adj, ctx->err);
                 if (p->nrc_mode == 1 || p->nrc_mode == 2) {
                     // cached radiance of the paths that ended in the cache this iteration
                     timed(6, [&] {

@@ -133,7 +133,7 @@ hipError_t launch_exp(ugp_ctx ctx, int64_t n, const float *rays, const int32_t *
 struct RenderAdjoint {
     const float *d_image;
     float *grad;
-    int param = 0;  // 0: albedo, grad [n][3]; 1: roughness, grad [n]
+    int param = 0;  // 0: albedo, grad [n][3]; 1: roughness, grad [n]; 2: density, grad [n]
 };
 hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p, float *sum, float *sumsq,
                   const RenderAdjoint *adj = nullptr);

@@ -87,3 +87,30 @@ def test_mis_estimators_agree(orc):
     for a in (1, 2):
         d = abs(res[a][0] - res[0][0])
         assert d <= 3 * math.hypot(res[a][1], res[0][1]), res
+
+
+def test_oracle_camera_rays(orc):
+    # the camera rays the oracle's path tracer starts from: the pinhole at the
+    # camera origin, unit directions, the central pixel's ray within half a
+    # pixel of the viewing direction, jitter inside each pixel
+    import math
+    cam = {"origin": (0.5, 0.5, -1.0), "target": (0.5, 0.5, 0.5), "up": (0.0, 1.0, 0.0), "vfov_deg": 45.0,
+           "width": 9, "height": 7}
+    r = orc.camera_rays(cam, 3, 0)
+    assert r.shape == (63, 8)
+    assert np.allclose(r[:, :3], (0.5, 0.5, -1.0))
+    assert np.allclose(np.linalg.norm(r[:, 3:6], axis=1), 1.0, atol=1e-6)
+    assert np.all(r[:, 6] == 0) and np.all(np.isinf(r[:, 7]))
+    th = math.tan(math.radians(22.5))
+    # image-plane coordinates of each ray (forward +z, right -x, up +y)
+    sx = -r[:, 3] / r[:, 5] / (th * 9 / 7)
+    sy = r[:, 4] / r[:, 5] / th
+    px = np.arange(63) % 9
+    py = np.arange(63) // 9
+    fx = (sx + 1) / 2 * 9 - px       # jitter in [0, 1)
+    fy = (1 - sy) / 2 * 7 - py
+    assert np.all((fx > -1e-5) & (fx < 1 + 1e-5)) and np.all((fy > -1e-5) & (fy < 1 + 1e-5))
+    c = r[31, 3:6]
+    assert np.degrees(np.arccos(c[2])) < 45.0 / 7
+    # another sample jitters differently
+    assert not np.allclose(orc.camera_rays(cam, 3, 1), r)
