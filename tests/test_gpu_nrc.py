@@ -18,11 +18,20 @@ a rounding error uniform in +-u|x| with variance (u x)^2 / 3:
   fused encoding  the forward pass on raw inputs equals the forward pass on
                   the GPU's own features bit for bit
   loss            |dL| <= 6 sigma_L + 1e-5 L, sigma_L from sigma_y through dL/dy
-  gradient        per layer ||dg|| <= 0.08 ||g|| and cosine > 0.995: about a
-                  dozen roundings lie between the loss and each weight
-                  (~12 u = 2.3%), plus ReLU units whose pre-activation lies
-                  within rounding of zero and switch (the CPU emulation
-                  reaches 5.1% on 33 records)
+  gradient        per element against an emulation of the kernels' bf16
+                  arithmetic (tests/nrc_emul.py: the same roundings of
+                  activations, loss gradient and back-propagated errors;
+                  FP64 sums, pinned to the oracle with rounding off):
+                  |dg| <= 2^-9 (|g| + 0.02 max|g| of its layer), except for
+                  at most 2% of a layer's elements (at most 8x the bar: a
+                  ReLU unit whose pre-activation is within float32 rounding
+                  of zero switches and moves a row), and normwise within
+                  2^-9 of the emulation; and against
+                  the exact FP64 gradient of the oracle per layer
+                  ||dg|| <= 0.08 ||g|| and cosine > 0.995 (about a dozen
+                  roundings lie between the loss and each weight, ~12 u =
+                  2.3%, plus ReLU units whose pre-activation lies within
+                  rounding of zero and switch)
   Adam            the master weights after each step equal the oracle's Adam
                   step on the kernel's gradient to float32 rounding
 """
@@ -166,13 +175,33 @@ def test_train_step_parity(ctx, torch, orc, n):
     sl = loss_sigma(yref, tgt.astype(np.float64), forward_sigma(W, feat))
     _say(f"  loss gpu {loss:.6f} oracle {lref:.6f} (|d| / sigma {abs(loss - lref) / sl:.2f})")
     assert abs(loss - lref) <= 6 * sl + 1e-5 * lref
+    # per element against the emulation of the kernels' bf16 arithmetic (the
+    # same roundings at the same points; sums in FP64 instead of FP32):
+    # |dg| <= 2^-9 (|g| + 0.02 max|g| of the layer), and normwise against the
+    # exact FP64 gradient of the oracle
+    import nrc_emul
+    _, gem = nrc_emul.train_grad(W, feat, tgt.astype(np.float64))
     off = 0
     for l, (o, i) in enumerate(NRC_LAYERS):
-        a, b = g[off:off + o * i], gref[off:off + o * i]
+        a, b, e = g[off:off + o * i], gref[off:off + o * i], gem[off:off + o * i]
         off += o * i
         rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
         cos = a @ b / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-30)
-        _say(f"  layer {l}: normwise rel err {rel:.3e}, cosine {cos:.6f}")
+        tol = U * (np.abs(e) + 0.02 * np.abs(e).max()) + 1e-12
+        ratio = np.abs(a - e) / tol
+        worst, beyond = float(ratio.max()), int((ratio > 1.0).sum())
+        _say(f"  layer {l}: vs bf16 emulation worst |dg|/bar {worst:.3f}, {beyond} of {ratio.size} beyond (max rel "
+             f"{np.max(np.abs(a - e) / (np.abs(e) + 1e-30 + 0.02 * np.abs(e).max())):.2e}); "
+             f"vs FP64 normwise {rel:.3e}, cosine {cos:.6f}")
+        # a ReLU unit whose pre-activation lies within float32 rounding of
+        # zero can switch between the matrix-core sum and the emulation's FP64
+        # sum, which moves a row of the layer's gradient (up to 96 elements) by
+        # that record's terms; a bf16 rounding that lands on the other side
+        # moves single terms by an ulp: at most 2% of a layer's elements may
+        # exceed the bar, by a bounded factor, and normwise the layer stays
+        # within the bar's 2^-9
+        assert beyond <= max(2, ratio.size // 50) and worst <= 8.0
+        assert np.linalg.norm(a - e) <= U * np.linalg.norm(e)
         assert rel <= 0.08 and cos > 0.995
     # Adam on the master weights: one step from zero moments
     Wn = ctx.nrc_get_weights().cpu().numpy().astype(np.float64)

@@ -122,3 +122,17 @@ def test_adam_matches_torch(orc):
         p.grad = torch.tensor(g)
         opt.step()
     assert np.allclose(Wc, p.detach().numpy(), rtol=1e-12, atol=1e-15)
+
+
+def test_bf16_emulation_without_rounding_is_the_oracle(orc):
+    # the test helper that emulates the kernels' bf16 arithmetic computes the
+    # oracle's FP64 loss and gradient when its rounding is switched off
+    import nrc_emul
+    rng = np.random.default_rng(8)
+    W = np.concatenate([rng.uniform(-1, 1, o * i) * np.sqrt(6.0 / i) for (o, i) in orc.NRC_LAYERS])
+    feat = rng.uniform(-1, 1, (97, 96))
+    tgt = rng.uniform(0, 2, (97, 3))
+    l_ref, g_ref = orc.nrc_loss_grad(W, feat, tgt)
+    l, g = nrc_emul.train_grad(W, feat, tgt, rounding=False)
+    assert abs(l - l_ref) <= 1e-12 * abs(l_ref)
+    assert np.allclose(g, g_ref, rtol=1e-10, atol=1e-14)
