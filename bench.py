@@ -379,6 +379,109 @@ def transmittance_fit(args):
     print(json.dumps(res), flush=True)
 
 
+def radiance_fit(args):
+    """Differentiable fitting at the shape of the fitting workload: a target of
+    the 100K mixed scene rendered by the plain tracer from 8 cameras on a ring
+    of radius 1.5 around (0.5, 0.5, 0.5) at heights +-0.3 (alternating),
+    256x256, 64 spp, depth 4, environment 0.3; a start of 200,000 primitives
+    as in the 1K random scene (means U[0,1]^3, random rotations, densities
+    U[0.5, 5]) with albedo 0.5 and roughness 0.5 (seed 4), its scales
+    (log-uniform [0.005, 0.05] there) multiplied by (1000 / 200000)^(1/3) so
+    that the start overlaps as the 1K scene does (0.9 primitives per point;
+    at the 1K scene's scales 200K primitives overlap 176-fold, beyond the
+    sweep's 64 entries).  Stage A fits the geometry (means, scales,
+    rotations, densities) to the target's transmittance images with the
+    accumulated free-flight CDF (Sec. 7.2; its Adam with clamps); stage B fits
+    albedo, roughness and density to the target radiance images through the
+    path tracer's adjoints (autograd.render, one view of 64 spp per step, the
+    backward on another seed).  One JSON line: steps/s of each stage, the
+    losses, and the image error of all views (at 64 spp) before and after."""
+    import numpy as np
+    import torch
+
+    import paper_2406_09733_amd as P
+    from paper_2406_09733_amd import autograd as A
+    from paper_2406_09733_amd import fit, scenes
+
+    target_sc = scenes.mixed_100k()
+    cams = []
+    for k in range(8):
+        a = 2 * np.pi * k / 8
+        h = 0.3 if k % 2 == 0 else -0.3
+        o = np.array([0.5, 0.5, 0.5]) + 1.5 * np.array([np.cos(a), h, np.sin(a)])
+        cams.append({"origin": tuple(o.tolist()), "target": (0.5, 0.5, 0.5), "up": (0.0, 1.0, 0.0),
+                     "vfov_deg": 45.0, "width": 256, "height": 256})
+    rp = {"max_depth": 4, "env_radiance": (0.3, 0.3, 0.3), "spp": 64}
+    ctx = P.Context(0)
+    t0 = time.perf_counter()
+    truth = {k: torch.tensor(np.asarray(v), device="cuda") for k, v in target_sc.items() if k != "bounds"}
+    with torch.no_grad():
+        targets = [A.render(ctx, truth, c, dict(rp, seed=900 + i)).detach() for i, c in enumerate(cams)]
+    cdf_target = fit.reference_images(ctx, target_sc, cams, seed=3, samples=16)
+    torch.cuda.synchronize()
+    log(f"[radiance-fit] targets rendered in {time.perf_counter() - t0:.1f}s")
+    init = scenes.tiny_random(seed=4, n=200_000, n_emit=0)
+    init["scale"] = (init["scale"] * (1000.0 / 200_000) ** (1.0 / 3.0)).astype(np.float32)
+    init["albedo"][:] = 0.5
+    init["roughness"][:] = 0.5
+    params = {k: torch.tensor(np.asarray(init[k]), device="cuda").contiguous()
+              for k in ("mean", "scale", "rotation", "density", "albedo", "roughness", "emission", "material")}
+
+    def image_error():
+        with torch.no_grad():
+            e = [float(((A.render(ctx, params, c, dict(rp, seed=700 + i)) - targets[i]) ** 2).mean())
+                 for i, c in enumerate(cams)]
+        return float(np.mean(e))
+
+    err0 = image_error()
+    log(f"[radiance-fit] start: image error {err0:.4e}")
+    # stage A: geometry from the transmittance images (Sec. 7.2)
+    outA = fit.fit_transmittance(ctx, params, cams, cdf_target, iters=args.fit_steps_geometry,
+                                 lr=(5e-5, 1e-2, 2e-3, 1e-2), rebuild_every=1,
+                                 on_step=lambda it: log(f"[radiance-fit] geometry step {it}") if it % 10 == 0 else None)
+    errA = image_error()
+    log(f"[radiance-fit] after the geometry stage: image error {errA:.4e}")
+    # stage B: albedo, roughness and density through the path tracer
+    alb = params["albedo"].clone().requires_grad_(True)
+    rough = params["roughness"].clone().requires_grad_(True)
+    logd = torch.log(params["density"].clamp(min=1e-4)).requires_grad_(True)
+    opt = torch.optim.Adam([{"params": [alb], "lr": 0.02}, {"params": [rough], "lr": 0.01},
+                            {"params": [logd], "lr": 0.02}])
+    lossesB = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(args.fit_steps_appearance):
+        v = it % len(cams)
+        cur = dict(params, albedo=alb, roughness=rough, density=torch.exp(logd))
+        img = A.render(ctx, cur, cams[v], dict(rp, seed=2000 + it), backward_params={"seed": 50000 + it})
+        loss = ((img - targets[v]) ** 2).mean()
+        opt.zero_grad()
+        loss.backward()
+        opt.step()
+        with torch.no_grad():
+            alb.clamp_(0.01, 0.99)
+            rough.clamp_(0.05, 1.0)
+        lossesB.append(float(loss.item()))
+        if it % 10 == 0:
+            log(f"[radiance-fit] appearance step {it} loss {lossesB[-1]:.4e}")
+    torch.cuda.synchronize()
+    tB = time.perf_counter() - t0
+    with torch.no_grad():
+        params["albedo"], params["roughness"], params["density"] = alb.detach(), rough.detach(), torch.exp(logd).detach()
+    errB = image_error()
+    lsA = outA["loss"]
+    res = {"metric": "differentiable fitting: 200K random primitives to 8 views of the 100K mixed scene at 256x256",
+           "value": round(args.fit_steps_appearance / tB, 3), "unit": "appearance steps/s", "higher_is_better": True,
+           "primitives": int(params["mean"].shape[0]), "target_primitives": int(target_sc["mean"].shape[0]),
+           "views": len(cams), "resolution": "256x256", "spp": rp["spp"], "max_depth": rp["max_depth"],
+           "stage_a": {"steps": args.fit_steps_geometry, "steps_per_s": round(args.fit_steps_geometry / outA["seconds"], 3),
+                       "loss_first": lsA[0], "loss_last": lsA[-1]},
+           "stage_b": {"steps": args.fit_steps_appearance, "ms_per_step": round(1e3 * tB / args.fit_steps_appearance, 1),
+                       "loss_first5": float(np.mean(lossesB[:5])), "loss_last5": float(np.mean(lossesB[-5:]))},
+           "image_error": {"start": round(err0, 6), "after_geometry": round(errA, 6), "after_appearance": round(errB, 6)}}
+    print(json.dumps(res), flush=True)
+
+
 def shading_fit(args):
     """Fit of the shading parameters through the path tracer's adjoints: the
     100K mixed scene rendered from 8 views of 256x256 (depth 4, environment
@@ -646,6 +749,10 @@ def main():
     ap.add_argument("--queries", action="store_true", help="run the per-ray query benchmark instead")
     ap.add_argument("--albedo-grad", action="store_true", help="run the albedo-adjoint benchmark instead")
     ap.add_argument("--sggx", action="store_true", help="run the SGGX phase-function benchmark instead")
+    ap.add_argument("--radiance-fit", action="store_true",
+                    help="run the differentiable-fitting benchmark (200K primitives, 8 views) instead")
+    ap.add_argument("--fit-steps-geometry", type=int, default=50, help="geometry (transmittance) steps")
+    ap.add_argument("--fit-steps-appearance", type=int, default=40, help="appearance (path-traced) steps")
     ap.add_argument("--shading-fit", action="store_true",
                     help="run the albedo + roughness fit through the path tracer's adjoints instead")
     ap.add_argument("--shading-fit-steps", type=int, default=200)
@@ -687,6 +794,9 @@ def main():
         return
     if args.shading_fit:
         shading_fit(args)
+        return
+    if args.radiance_fit:
+        radiance_fit(args)
         return
 
     import numpy as np
