@@ -73,6 +73,10 @@ def lib():
         L.orc_exp_sample.argtypes = [vp, C.c_int64, vp, vp, C.c_uint64, C.c_int, vp, vp, vp]
         L.orc_sample_collision.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_int, vp, vp, vp, vp, vp]
         L.orc_emitter_query.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_int, vp]
+        L.orc_light_pdf.argtypes = [vp, C.c_int64, vp, vp]
+        L.orc_light_pdf.restype = C.c_double
+        L.orc_light_dir.argtypes = [vp, C.c_int64, vp, vp, vp]
+        L.orc_light_dir.restype = C.c_int
         L.orc_phase_eval.argtypes = [C.c_int, vp, C.c_double, vp, vp, vp, vp, vp]
         L.orc_phase_sample.argtypes = [C.c_int, vp, C.c_double, vp, vp, C.c_double, C.c_double,
                                        vp, vp, vp]
@@ -320,6 +324,22 @@ class Scene:
         ub = self.use_bvh if use_bvh is None else int(use_bvh)
         lib().orc_emitter_query(self.h, n, _addr(r), _addr(e), _addr(tg), ub, _addr(L))
         return L
+
+    def light_pdf(self, k: int, x, w) -> float:
+        """Solid-angle pdf of the path tracer's light sample toward emissive
+        primitive k from x in direction w (times the choice 1/n_emit)."""
+        xx = np.ascontiguousarray(x, dtype=np.float64)
+        ww = np.ascontiguousarray(w, dtype=np.float64)
+        return float(lib().orc_light_pdf(self.h, int(k), _addr(xx), _addr(ww)))
+
+    def light_dir(self, j: int, x, u):
+        """Light-sampled direction from x toward emitter slot j (the j-th
+        emissive primitive in index order) from four uniforms, or None."""
+        xx = np.ascontiguousarray(x, dtype=np.float64)
+        uu = np.ascontiguousarray(u, dtype=np.float64)
+        w = np.zeros(3)
+        ok = lib().orc_light_dir(self.h, int(j), _addr(xx), _addr(uu), _addr(w))
+        return w if ok else None
 
     def render(self, cam: dict, params: dict, pixels=None, nthreads: int | None = None):
         c = make_camera(cam)

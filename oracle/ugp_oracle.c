@@ -135,8 +135,8 @@ struct orc_scene {
     double *sggx;  /* [n][6] SGGX matrix (xx, yy, zz, xy, xz, yz), world frame; NULL if none */
     double *met;   /* [n] metallic of material 3's base BSDF; NULL = 0 */
     double *lo, *hi;  /* [n][3] axis-aligned box of the cut-off ellipsoid */
-    double *rsph;  /* [n] radius of the bounding sphere, r * max(s) */
     int64_t *emitters;
+    double *emA;   /* [n_emit][9] row-major R S of emitter slot j (unit frame -> world offset) */
     int64_t n_emit;
     /* acceleration structure: a plain median-split BVH, used only to find the
        candidate set; results are independent of it (checked against brute force) */
@@ -168,8 +168,8 @@ int orc_scene_create(int64_t n, const float *mean, const float *scale, const flo
     S->mat = (int32_t *)malloc(sizeof(int32_t) * nn);
     S->lo = (double *)malloc(sizeof(double) * 3 * nn);
     S->hi = (double *)malloc(sizeof(double) * 3 * nn);
-    S->rsph = (double *)malloc(sizeof(double) * nn);
     S->emitters = (int64_t *)malloc(sizeof(int64_t) * nn);
+    S->emA = (double *)malloc(sizeof(double) * 9 * nn);
     S->n_emit = 0;
     for (int64_t k = 0; k < n; ++k) {
         double qw = rotation[4 * k + 0], qx = rotation[4 * k + 1], qy = rotation[4 * k + 2],
@@ -187,8 +187,6 @@ int orc_scene_create(int64_t n, const float *mean, const float *scale, const flo
         if (s[1] < s[m]) m = 1;
         if (s[2] < s[m]) m = 2;
         for (int j = 0; j < 3; ++j) S->nrm[3 * k + j] = R[j][m];
-        double smax = fmax(s[0], fmax(s[1], s[2]));
-        S->rsph[k] = S->r * smax;
         for (int j = 0; j < 3; ++j) {
             double h2 = 0.0;
             for (int i = 0; i < 3; ++i) h2 += (R[j][i] * s[i]) * (R[j][i] * s[i]);
@@ -203,9 +201,14 @@ int orc_scene_create(int64_t n, const float *mean, const float *scale, const flo
         S->d[k] = density[k];
         S->rough[k] = roughness[k];
         S->mat[k] = material[k];
-        if (S->emis[3 * k] > 0.0 || S->emis[3 * k + 1] > 0.0 || S->emis[3 * k + 2] > 0.0)
+        if (S->emis[3 * k] > 0.0 || S->emis[3 * k + 1] > 0.0 || S->emis[3 * k + 2] > 0.0) {
+            double *A = S->emA + 9 * S->n_emit;
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) A[3 * i + j] = R[i][j] * s[j];
             S->emitters[S->n_emit++] = k;
+        }
     }
+    if (S->n_emit > 0) S->emA = (double *)realloc(S->emA, sizeof(double) * 9 * (size_t)S->n_emit);
     *out = S;
     return 0;
 }
@@ -213,7 +216,7 @@ int orc_scene_create(int64_t n, const float *mean, const float *scale, const flo
 void orc_scene_destroy(orc_scene *S) {
     if (!S) return;
     free(S->mu); free(S->M); free(S->d); free(S->nrm); free(S->alb); free(S->rough);
-    free(S->emis); free(S->mat); free(S->lo); free(S->hi); free(S->rsph); free(S->emitters);
+    free(S->emis); free(S->mat); free(S->lo); free(S->hi); free(S->emitters); free(S->emA);
     free(S->sggx); free(S->met);
     free(S->nodes); free(S->perm);
     free(S);
@@ -1398,17 +1401,64 @@ void orc_sggx_phase_est_n(const double s6[6], const double wo[3], const double w
 void orc_nrc_encode(int64_t n, const float *in, const double lo[3], const double hi[3], double *feat);
 static void nrc_predict(const double *W, const float in[16], const double box[6], double y[3]);
 
-/* NEE cone pdf of emitter k seen from x: uniform over the cone subtending k's
- * bounding sphere, times the uniform emitter-choice probability; 0 when x is
- * inside the sphere. */
-static double nee_pdf(const orc_scene *S, int64_t k, const double x[3]) {
-    double c[3] = {S->mu[3 * k] - x[0], S->mu[3 * k + 1] - x[1], S->mu[3 * k + 2] - x[2]};
-    double d2 = dot3(c, c), rs = S->rsph[k];
-    if (d2 <= rs * rs) return 0.0;
-    double sin2 = rs * rs / d2;
-    double cosm = sqrt(fmax(0.0, 1.0 - sin2));
-    double omc = sin2 / (1.0 + cosm);
-    return 1.0 / ((double)S->n_emit * 2.0 * M_PI * omc);
+/* Light sampling (reading C12): pick an emissive primitive uniformly, draw a
+ * point y of its untruncated Gaussian N(mu_k, Sigma_k), Sigma_k = (R S)(R S)^T,
+ * and aim at it from x.  The direction's solid-angle density is the density
+ * of y integrated along the ray, int_0^inf N(x + t w) t^2 dt.  In the unit
+ * frame of k (x' = M (x - mu), w' = M w, a = |w'|) the point x + t w maps to
+ * x' + t w', on a line that passes the centre at distance rho, at signed
+ * position s = s0 + a t along it (s0 = x'.w' / a), so |x' + t w'|^2 =
+ * rho^2 + s^2; the density of y is |det M| (2 pi)^(-3/2) exp(-|M (y - mu)|^2/2), so
+ *   p(w) = |det M| exp(-rho^2/2) / ((2 pi)^(3/2) a^3) K(s0),
+ *   K(s0) = int_{s0}^inf exp(-s^2/2) (s - s0)^2 ds
+ *         = (1 + s0^2) sqrt(pi/2) erfc(s0/sqrt 2) - s0 exp(-s0^2/2).
+ * Returned times the uniform emitter-choice probability. */
+static double nee_pdf(const orc_scene *S, int64_t k, const double x[3], const double w[3]) {
+    const double *M = S->M + 9 * k, *mu = S->mu + 3 * k;
+    double c[3] = {x[0] - mu[0], x[1] - mu[1], x[2] - mu[2]}, xp[3], wp[3];
+    for (int i = 0; i < 3; ++i) {
+        xp[i] = M[3 * i] * c[0] + M[3 * i + 1] * c[1] + M[3 * i + 2] * c[2];
+        wp[i] = M[3 * i] * w[0] + M[3 * i + 1] * w[1] + M[3 * i + 2] * w[2];
+    }
+    double a = sqrt(dot3(wp, wp));
+    if (!(a > 0.0)) return 0.0;
+    double s0 = dot3(xp, wp) / a;
+    double perp[3];
+    for (int i = 0; i < 3; ++i) perp[i] = xp[i] - s0 * wp[i] / a;
+    double rho2 = dot3(perp, perp);
+    double K = (1.0 + s0 * s0) * sqrt(M_PI / 2.0) * erfc(s0 / sqrt(2.0)) - s0 * exp(-0.5 * s0 * s0);
+    double detM = M[0] * (M[4] * M[8] - M[5] * M[7]) - M[1] * (M[3] * M[8] - M[5] * M[6]) +
+                  M[2] * (M[3] * M[7] - M[4] * M[6]);
+    double p = fabs(detM) * exp(-0.5 * rho2) * fmax(K, 0.0) / (pow(2.0 * M_PI, 1.5) * a * a * a);
+    return p / (double)S->n_emit;
+}
+
+/* The light-sampled direction from x toward emitter slot j: y = mu + (R S) n
+ * with n three standard normals from the uniforms u[0..3] (Box-Muller);
+ * returns 0 when y coincides with x. */
+static int nee_dir(const orc_scene *S, int64_t j, const double x[3], const double u[4], double w[3]) {
+    int64_t e = S->emitters[j];
+    const double *A = S->emA + 9 * j, *mu = S->mu + 3 * e;
+    double r1 = sqrt(-2.0 * log(1.0 - u[0])), r2 = sqrt(-2.0 * log(1.0 - u[2]));
+    double n[3] = {r1 * cos(2.0 * M_PI * u[1]), r1 * sin(2.0 * M_PI * u[1]), r2 * cos(2.0 * M_PI * u[3])};
+    double y[3];
+    for (int i = 0; i < 3; ++i) y[i] = mu[i] + A[3 * i] * n[0] + A[3 * i + 1] * n[1] + A[3 * i + 2] * n[2];
+    for (int i = 0; i < 3; ++i) w[i] = y[i] - x[i];
+    double l = sqrt(dot3(w, w));
+    if (!(l > 0.0)) return 0;
+    for (int i = 0; i < 3; ++i) w[i] /= l;
+    return 1;
+}
+
+/* exported for the tests: light pdf of primitive k and the light-sampled
+ * direction toward emitter slot j */
+double orc_light_pdf(const orc_scene *S, int64_t k, const double *x, const double *w) {
+    return nee_pdf(S, k, x, w);
+}
+
+int orc_light_dir(const orc_scene *S, int64_t j, const double *x, const double *u, double *w) {
+    if (j < 0 || j >= S->n_emit) return 0;
+    return nee_dir(S, j, x, u, w);
 }
 
 typedef struct {
@@ -1518,7 +1568,7 @@ static void trace_path(const orc_scene *S, const orc_render_params *P, const orc
             double wt;
             if (v == 1) wt = 1.0;
             else {
-                double pn = nee_pdf(S, k, x_prev);
+                double pn = nee_pdf(S, k, x_prev, w);
                 if (P->mis_mode == 1) wt = 1.0;
                 else if (P->mis_mode == 2) wt = (pn > 0.0) ? 0.0 : 1.0;
                 else wt = p_prev / (p_prev + pn);
@@ -1564,37 +1614,27 @@ static void trace_path(const orc_scene *S, const orc_render_params *P, const orc
                 ++*n_rec;
             }
         }
-        /* NEE to one emissive primitive */
+        /* NEE to one emissive primitive: uniform pick (group 0), a point of its
+           Gaussian to aim at (group 7) */
         if (S->n_emit > 0 && P->mis_mode != 1) {
             int64_t j = (int64_t)(u[1] * (double)S->n_emit);
             if (j >= S->n_emit) j = S->n_emit - 1;
             int64_t e = S->emitters[j];
-            double pn = nee_pdf(S, e, x);
-            if (pn > 0.0) {
-                double cdir[3] = {S->mu[3 * e] - x[0], S->mu[3 * e + 1] - x[1], S->mu[3 * e + 2] - x[2]};
-                double d2 = dot3(cdir, cdir), rs = S->rsph[e];
-                double dist = sqrt(d2);
-                for (int i = 0; i < 3; ++i) cdir[i] /= dist;
-                double sin2m = rs * rs / d2;
-                double cosm = sqrt(fmax(0.0, 1.0 - sin2m));
-                double omc = sin2m / (1.0 + cosm);
-                double one_m_cos = u[2] * omc;
-                double cost = 1.0 - one_m_cos;
-                double sint = sqrt(fmax(0.0, one_m_cos * (2.0 - one_m_cos)));
-                double ph = 2.0 * M_PI * u[3];
-                double b1[3], b2[3], wl[3];
-                onb(cdir, b1, b2);
-                for (int i = 0; i < 3; ++i)
-                    wl[i] = sint * cos(ph) * b1[i] + sint * sin(ph) * b2[i] + cost * cdir[i];
+            double q7[4], wl[3];
+            rng4(seed, pix, sample, v, 7, q7);
+            if (e != k && nee_dir(S, j, x, q7, wl)) {
                 double f[3], pph;
                 prim_phase_eval(S, k, wo, wl, e3, f, &pph);
                 ohit he;
                 if ((f[0] > 0.0 || f[1] > 0.0 || f[2] > 0.0) && ray_prim(S, e, x, wl, 0.0, INFINITY, &he)) {
-                    double fac = emitter_factor(S, x, wl, 0.0, INFINITY, k, e, 1, H2);
-                    ++*rays;
-                    double wt = (P->mis_mode == 2) ? 1.0 : pn / (pn + pph);
-                    for (int i = 0; i < 3; ++i)
-                        L[i] += beta[i] * f[i] * S->emis[3 * e + i] * fac * wt / pn;
+                    double pn = nee_pdf(S, e, x, wl);
+                    if (pn > 0.0) {
+                        double fac = emitter_factor(S, x, wl, 0.0, INFINITY, k, e, 1, H2);
+                        ++*rays;
+                        double wt = (P->mis_mode == 2) ? 1.0 : pn / (pn + pph);
+                        for (int i = 0; i < 3; ++i)
+                            L[i] += beta[i] * f[i] * S->emis[3 * e + i] * fac * wt / pn;
+                    }
                 }
             }
         }

@@ -72,6 +72,12 @@ void orc_sample_collision(const orc_scene *S, int64_t n, const float *rays, cons
                           double *F_out, double *tsat_out, double *margin_out);
 void orc_emitter_query(const orc_scene *S, int64_t n, const float *rays, const int32_t *exclude,
                        const int32_t *target, int use_bvh, double *L_out);
+/* light sampling of the path tracer: solid-angle pdf of direction w from x
+ * toward emissive primitive k (times the uniform choice 1/n_emit), and the
+ * direction toward a Gaussian point of emitter slot j from uniforms u[4]
+ * (returns 0 if none) */
+double orc_light_pdf(const orc_scene *S, int64_t k, const double *x, const double *w);
+int orc_light_dir(const orc_scene *S, int64_t j, const double *x, const double *u, double *w);
 
 void orc_phase_eval(int mat, const double alb[3], double rough, const double nrm[3],
                     const double wo[3], const double wi[3], double f[3], double *pdf);

@@ -20,8 +20,9 @@
 // accumulation into sum / sum of squares runs pixel by pixel in sample order
 // and the image does not depend on how paths were scheduled.
 // Random numbers: Philox4x32-10 keyed by the seed, counter (pixel, sample,
-// vertex, group): group 0 = (collision, emitter pick, cone u, cone v), group 1 =
-// (phase u, phase v, environment u, environment v); the camera jitter uses
+// vertex, group): group 0 = (collision, emitter pick, -, -), group 1 =
+// (phase u, phase v, environment u, environment v), group 7 = the light
+// sample's point (three normals by Box-Muller); the camera jitter uses
 // vertex 0, group 0, the choice of radiance-cache training paths vertex 0,
 // group 2.  At SGGX vertices: groups 3 and 4 drive the stochastic phase
 // evaluations of the light and environment samples (group 6 adds material
@@ -186,17 +187,68 @@ __device__ __forceinline__ Rng4 path_rng(const PassArgs &P, uint32_t q, uint32_t
     return rng4(P.seed, q % P.npix, P.sample + q / P.npix, v, g);
 }
 
-// light pdf of emitter k (original index) seen from x: uniform cone over its
-// bounding sphere, times the uniform emitter choice; 0 inside the sphere
-__device__ __forceinline__ float nee_pdf(const SceneDev &S, int k, V3 x) {
-    const float4 h0 = S.hot[4 * S.inv[k]];
-    const float rs = S.cold[3 * k + 2].w;
-    const V3 c = v3(h0.x - x.x, h0.y - x.y, h0.z - x.z);
-    const float d2 = dot(c, c);
-    if (d2 <= rs * rs) return 0.f;
-    const float sin2 = rs * rs / d2;
-    const float omc = sin2 / (1.f + sqrtf(fmaxf(0.f, 1.f - sin2)));
-    return 1.f / ((float)S.n_emit * 2.f * kPi * omc);
+// Light sampling: an emissive primitive picked uniformly, then a point y of
+// its untruncated Gaussian N(mu, Sigma) to aim at.  The direction's
+// solid-angle pdf is the density of y integrated along the ray,
+// int_0^inf N(x + t w) t^2 dt.  In the primitive's unit frame (x' = M (x -
+// mu), w' = M w, a = |w'|) the ray passes the centre at distance rho, at
+// signed position s = s0 + a t (s0 = x'.w' / a), so the integral is
+//   |det M| exp(-rho^2/2) K(s0) / ((2 pi)^(3/2) a^3),
+//   K(s0) = (1 + s0^2) sqrt(pi/2) erfc(s0/sqrt 2) - s0 exp(-s0^2/2),
+// evaluated in double from the primitive's record, times the uniform choice.
+__device__ double light_pdf(const HotRec &h, int n_emit, V3 x, V3 w) {
+    const double c[3] = {(double)x.x - h.mx, (double)x.y - h.my, (double)x.z - h.mz};
+    const double wd[3] = {w.x, w.y, w.z};
+    double xp[3], wp[3];
+    for (int i = 0; i < 3; ++i) {
+        const double m0 = h.m[3 * i], m1 = h.m[3 * i + 1], m2 = h.m[3 * i + 2];
+        xp[i] = m0 * c[0] + m1 * c[1] + m2 * c[2];
+        wp[i] = m0 * wd[0] + m1 * wd[1] + m2 * wd[2];
+    }
+    const double a2 = wp[0] * wp[0] + wp[1] * wp[1] + wp[2] * wp[2];
+    if (!(a2 > 0.0)) return 0.0;
+    const double a = sqrt(a2);
+    const double s0 = (xp[0] * wp[0] + xp[1] * wp[1] + xp[2] * wp[2]) / a;
+    double rho2 = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        const double q = xp[i] - s0 * wp[i] / a;
+        rho2 += q * q;
+    }
+    const double K = (1.0 + s0 * s0) * 1.2533141373155003 * erfc(s0 * 0.7071067811865476) - s0 * exp(-0.5 * s0 * s0);
+    const double det = (double)h.m[0] * ((double)h.m[4] * h.m[8] - (double)h.m[5] * h.m[7]) -
+                       (double)h.m[1] * ((double)h.m[3] * h.m[8] - (double)h.m[5] * h.m[6]) +
+                       (double)h.m[2] * ((double)h.m[3] * h.m[7] - (double)h.m[4] * h.m[6]);
+    return fabs(det) * exp(-0.5 * rho2) * fmax(K, 0.0) / (15.749609945653303 * a2 * a) / (double)n_emit;
+}
+
+// The light sample's direction from x toward primitive record h: y = mu + A n
+// with A = M^-1 (= R S, by the adjugate in double) and n three standard
+// normals from the uniforms u (Box-Muller); false when y coincides with x.
+__device__ bool light_dir(const HotRec &h, V3 x, const Rng4 &u, V3 &w) {
+    double m[9];
+    for (int i = 0; i < 9; ++i) m[i] = h.m[i];
+    const double det = m[0] * (m[4] * m[8] - m[5] * m[7]) - m[1] * (m[3] * m[8] - m[5] * m[6]) +
+                       m[2] * (m[3] * m[7] - m[4] * m[6]);
+    if (!(fabs(det) > 0.0)) return false;
+    const double id = 1.0 / det;
+    const double A[9] = {(m[4] * m[8] - m[5] * m[7]) * id, (m[2] * m[7] - m[1] * m[8]) * id,
+                         (m[1] * m[5] - m[2] * m[4]) * id, (m[5] * m[6] - m[3] * m[8]) * id,
+                         (m[0] * m[8] - m[2] * m[6]) * id, (m[2] * m[3] - m[0] * m[5]) * id,
+                         (m[3] * m[7] - m[4] * m[6]) * id, (m[1] * m[6] - m[0] * m[7]) * id,
+                         (m[0] * m[4] - m[1] * m[3]) * id};
+    const double r1 = sqrt(-2.0 * log(1.0 - (double)u.u[0])), r2 = sqrt(-2.0 * log(1.0 - (double)u.u[2]));
+    double s1, c1, s3, c3;
+    sincos(6.283185307179586 * (double)u.u[1], &s1, &c1);
+    sincos(6.283185307179586 * (double)u.u[3], &s3, &c3);
+    const double n[3] = {r1 * c1, r1 * s1, r2 * c3};
+    double d[3];
+    const double mu[3] = {h.mx, h.my, h.mz}, xs[3] = {x.x, x.y, x.z};
+    for (int i = 0; i < 3; ++i) d[i] = mu[i] + A[3 * i] * n[0] + A[3 * i + 1] * n[1] + A[3 * i + 2] * n[2] - xs[i];
+    const double l2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (!(l2 > 0.0)) return false;
+    const double il = 1.0 / sqrt(l2);
+    w = v3((float)(d[0] * il), (float)(d[1] * il), (float)(d[2] * il));
+    return true;
 }
 
 // Refill the free slots of the input queue with new camera paths of the
@@ -458,7 +510,7 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
         if (nonzero(Le)) {
             float w = 1.f;
             if (v > 1) {
-                const float pn = nee_pdf(S, k, o);
+                const float pn = (float)light_pdf(load_hot(S.hot, S.inv[k]), S.n_emit, o, d);
                 if (P.mis_mode == 2) w = pn > 0.f ? 0.f : 1.f;
                 else if (P.mis_mode == 0) w = p_prev / (p_prev + pn);
             }
@@ -498,38 +550,25 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
             Sggx sg{}, sgr{};
             if (mat >= 2) sg = sggx_load(S.sggx + 8 * (int64_t)k);
             if (mat == 3) sgr = sggx_load(S.sggx + 8 * (int64_t)k + 4);
-            // light sample: one emitter, uniform in the cone of its bounding sphere
+            // light sample: one emitter picked uniformly, aimed at a point of its
+            // Gaussian (uniforms of group 7)
             if (S.n_emit > 0 && P.mis_mode != 1) {
                 // floor(u * n_emit) in exact integer arithmetic (u has 24 bits)
                 int j = (int)(((uint64_t)(g0.u[1] * 16777216.f) * (uint64_t)S.n_emit) >> 24);
                 j = min(j, S.n_emit - 1);
                 const int e = S.emit[j];
-                const int es = S.inv[e];
-                const float4 eh = S.hot[4 * es];
-                const float rs = S.cold[3 * e + 2].w;
-                V3 cd = v3(eh.x - x.x, eh.y - x.y, eh.z - x.z);
-                const float d2 = dot(cd, cd);
-                if (d2 > rs * rs) {
-                    cd = rsqrtf(d2) * cd;
-                    const float sin2 = rs * rs / d2;
-                    const float cosm = sqrtf(fmaxf(0.f, 1.f - sin2));
-                    const float omc = sin2 / (1.f + cosm);
-                    const float pn = 1.f / ((float)S.n_emit * 2.f * kPi * omc);
-                    const float omcos = g0.u[2] * omc;
-                    const float cost = 1.f - omcos;
-                    const float sint = sqrtf(fmaxf(0.f, omcos * (2.f - omcos)));
-                    float sp, cp;
-                    sincosf(2.f * kPi * g0.u[3], &sp, &cp);
-                    V3 b1, b2;
-                    onb(cd, b1, b2);
-                    const V3 wl = (sint * cp) * b1 + (sint * sp) * b2 + cost * cd;
+                const HotRec eh = load_hot(S.hot, S.inv[e]);
+                V3 wl;
+                if (e != k && light_dir(eh, x, path_rng(P, (uint32_t)pix, (uint32_t)v, 7), wl)) {
                     float pph;
                     float ue[6];
                     eval_uniforms(P, (uint32_t)pix, (uint32_t)v, 3, mat, ue);
                     const V3 f = vertex_phase(mat, sg, sgr, F, wo, wol, alb, rough, wl, ue, pph);
                     Chord tc;
                     const RayD lr = make_ray(x.x, x.y, x.z, wl.x, wl.y, wl.z, 0.f, __builtin_huge_val());
-                    if (nonzero(f) && chord(load_hot(S.hot, es), lr, S.r2, tc)) {
+                    const float pn = nonzero(f) && chord(eh, lr, S.r2, tc) ? (float)light_pdf(eh, S.n_emit, x, wl)
+                                                                           : 0.f;
+                    if (pn > 0.f) {
                         const float w = P.mis_mode == 2 ? 1.f : pn / (pn + pph);
                         const float4 eL = S.cold[3 * e + 2];
                         const V3 wt = (w / pn) * mul(mul(beta, f), f3(eL));
