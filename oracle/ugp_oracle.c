@@ -1412,7 +1412,10 @@ static void nrc_predict(const double *W, const float in[16], const double box[6]
  *   p(w) = |det M| exp(-rho^2/2) / ((2 pi)^(3/2) a^3) K(s0),
  *   K(s0) = int_{s0}^inf exp(-s^2/2) (s - s0)^2 ds
  *         = (1 + s0^2) sqrt(pi/2) erfc(s0/sqrt 2) - s0 exp(-s0^2/2).
- * Returned times the uniform emitter-choice probability. */
+ * Returned times the uniform emitter-choice probability.  From a point inside
+ * the emitter's cut-off ellipsoid no light sample is taken toward it (pdf 0):
+ * there the directions that leave a flat emitter's plane would have a density
+ * far below their share of its emission, and phase sampling covers them. */
 static double nee_pdf(const orc_scene *S, int64_t k, const double x[3], const double w[3]) {
     const double *M = S->M + 9 * k, *mu = S->mu + 3 * k;
     double c[3] = {x[0] - mu[0], x[1] - mu[1], x[2] - mu[2]}, xp[3], wp[3];
@@ -1420,6 +1423,7 @@ static double nee_pdf(const orc_scene *S, int64_t k, const double x[3], const do
         xp[i] = M[3 * i] * c[0] + M[3 * i + 1] * c[1] + M[3 * i + 2] * c[2];
         wp[i] = M[3 * i] * w[0] + M[3 * i + 1] * w[1] + M[3 * i + 2] * w[2];
     }
+    if (dot3(xp, xp) <= S->r * S->r) return 0.0;
     double a = sqrt(dot3(wp, wp));
     if (!(a > 0.0)) return 0.0;
     double s0 = dot3(xp, wp) / a;
@@ -1435,10 +1439,17 @@ static double nee_pdf(const orc_scene *S, int64_t k, const double x[3], const do
 
 /* The light-sampled direction from x toward emitter slot j: y = mu + (R S) n
  * with n three standard normals from the uniforms u[0..3] (Box-Muller);
- * returns 0 when y coincides with x. */
+ * returns 0 when x is inside the emitter's cut-off ellipsoid or y coincides
+ * with x. */
 static int nee_dir(const orc_scene *S, int64_t j, const double x[3], const double u[4], double w[3]) {
     int64_t e = S->emitters[j];
-    const double *A = S->emA + 9 * j, *mu = S->mu + 3 * e;
+    const double *A = S->emA + 9 * j, *mu = S->mu + 3 * e, *M = S->M + 9 * e;
+    double c[3] = {x[0] - mu[0], x[1] - mu[1], x[2] - mu[2]}, q2 = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        double xi = M[3 * i] * c[0] + M[3 * i + 1] * c[1] + M[3 * i + 2] * c[2];
+        q2 += xi * xi;
+    }
+    if (q2 <= S->r * S->r) return 0;
     double r1 = sqrt(-2.0 * log(1.0 - u[0])), r2 = sqrt(-2.0 * log(1.0 - u[2]));
     double n[3] = {r1 * cos(2.0 * M_PI * u[1]), r1 * sin(2.0 * M_PI * u[1]), r2 * cos(2.0 * M_PI * u[3])};
     double y[3];

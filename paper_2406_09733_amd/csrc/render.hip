@@ -196,7 +196,21 @@ __device__ __forceinline__ Rng4 path_rng(const PassArgs &P, uint32_t q, uint32_t
 //   |det M| exp(-rho^2/2) K(s0) / ((2 pi)^(3/2) a^3),
 //   K(s0) = (1 + s0^2) sqrt(pi/2) erfc(s0/sqrt 2) - s0 exp(-s0^2/2),
 // evaluated in double from the primitive's record, times the uniform choice.
-__device__ double light_pdf(const HotRec &h, int n_emit, V3 x, V3 w) {
+// From a point inside the emitter's cut-off ellipsoid (|x'| <= r) no light
+// sample is taken toward it (pdf 0): the directions that leave a flat
+// emitter's plane would get a density far below their share of its emission,
+// and phase sampling covers them.
+__device__ bool inside_cut(const HotRec &h, double r2, V3 x) {
+    const double c[3] = {(double)x.x - h.mx, (double)x.y - h.my, (double)x.z - h.mz};
+    double q2 = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        const double xi = h.m[3 * i] * c[0] + h.m[3 * i + 1] * c[1] + h.m[3 * i + 2] * c[2];
+        q2 += xi * xi;
+    }
+    return q2 <= r2;
+}
+
+__device__ double light_pdf(const HotRec &h, int n_emit, double r2, V3 x, V3 w) {
     const double c[3] = {(double)x.x - h.mx, (double)x.y - h.my, (double)x.z - h.mz};
     const double wd[3] = {w.x, w.y, w.z};
     double xp[3], wp[3];
@@ -205,6 +219,7 @@ __device__ double light_pdf(const HotRec &h, int n_emit, V3 x, V3 w) {
         xp[i] = m0 * c[0] + m1 * c[1] + m2 * c[2];
         wp[i] = m0 * wd[0] + m1 * wd[1] + m2 * wd[2];
     }
+    if (xp[0] * xp[0] + xp[1] * xp[1] + xp[2] * xp[2] <= r2) return 0.0;
     const double a2 = wp[0] * wp[0] + wp[1] * wp[1] + wp[2] * wp[2];
     if (!(a2 > 0.0)) return 0.0;
     const double a = sqrt(a2);
@@ -510,7 +525,7 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
         if (nonzero(Le)) {
             float w = 1.f;
             if (v > 1) {
-                const float pn = (float)light_pdf(load_hot(S.hot, S.inv[k]), S.n_emit, o, d);
+                const float pn = (float)light_pdf(load_hot(S.hot, S.inv[k]), S.n_emit, S.r_cut * S.r_cut, o, d);
                 if (P.mis_mode == 2) w = pn > 0.f ? 0.f : 1.f;
                 else if (P.mis_mode == 0) w = p_prev / (p_prev + pn);
             }
@@ -559,15 +574,16 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
                 const int e = S.emit[j];
                 const HotRec eh = load_hot(S.hot, S.inv[e]);
                 V3 wl;
-                if (e != k && light_dir(eh, x, path_rng(P, (uint32_t)pix, (uint32_t)v, 7), wl)) {
+                const double r2 = S.r_cut * S.r_cut;
+                if (e != k && !inside_cut(eh, r2, x) && light_dir(eh, x, path_rng(P, (uint32_t)pix, (uint32_t)v, 7), wl)) {
                     float pph;
                     float ue[6];
                     eval_uniforms(P, (uint32_t)pix, (uint32_t)v, 3, mat, ue);
                     const V3 f = vertex_phase(mat, sg, sgr, F, wo, wol, alb, rough, wl, ue, pph);
                     Chord tc;
                     const RayD lr = make_ray(x.x, x.y, x.z, wl.x, wl.y, wl.z, 0.f, __builtin_huge_val());
-                    const float pn = nonzero(f) && chord(eh, lr, S.r2, tc) ? (float)light_pdf(eh, S.n_emit, x, wl)
-                                                                           : 0.f;
+                    const float pn =
+                        nonzero(f) && chord(eh, lr, S.r2, tc) ? (float)light_pdf(eh, S.n_emit, r2, x, wl) : 0.f;
                     if (pn > 0.f) {
                         const float w = P.mis_mode == 2 ? 1.f : pn / (pn + pph);
                         const float4 eL = S.cold[3 * e + 2];

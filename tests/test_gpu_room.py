@@ -238,3 +238,28 @@ def test_room_cached_render_parity_sampled(room):
     assert share > 0.1
     assert frac <= 0.01
     assert abs(m.mean() - m_ref.mean()) <= 3 * gse + 1e-6
+
+
+def test_room_light_phase_and_mis_estimates_agree(room):
+    # light sampling only, phase sampling only and their balance heuristic
+    # estimate the same image; the room's emitters are flat (thin axis 1/100)
+    # and seen at every angle, where a wrong light-sample pdf shows as a bias
+    sc, ctx, S = room
+    _say("room: light-only, phase-only and MIS images at 240x135, depth 3, 256 spp")
+    cam = dict(scenes.camera("room_5p5m"), width=240, height=135)
+    spp = 256
+    res = {}
+    for mode in (0, 1, 2):
+        s, s2 = ctx.render(cam, {"spp": spp, "max_depth": 3, "seed": 40 + mode, "mis_mode": mode})
+        s, s2 = _np(s).astype(np.float64), _np(s2).astype(np.float64)
+        mean_pix = s / spp
+        var_pix = np.maximum(s2 / spp - mean_pix ** 2, 0.0)
+        # the channels of a pixel share their paths: the variance of their
+        # mean is at most the mean of their variances
+        res[mode] = (float(mean_pix.mean()), float(np.sqrt(var_pix.mean() / (spp * (mean_pix.size // 3)))))
+    ctx.sync()
+    _say("  " + ", ".join(f"mode {m}: {v[0]:.5f} +- {v[1]:.5f}" for m, v in res.items()))
+    for a in (1, 2):
+        assert abs(res[a][0] - res[0][0]) <= 4 * np.hypot(res[a][1], res[0][1]), res
+    # each estimate resolves the image mean to better than 2%
+    assert all(v[1] < 0.02 * v[0] for v in res.values())

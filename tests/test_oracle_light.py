@@ -5,8 +5,9 @@ density of y integrated along the ray, int_0^inf N(x + t w) t^2 dt; the
 oracle evaluates it in closed form.
 
 * the closed form against adaptive quadrature of that integral, with Sigma
-  from scipy's rotation of the quaternion (outside, near and inside the
-  cut-off ellipsoid; toward, across and away from the centre);
+  from scipy's rotation of the quaternion (near and far outside the cut-off
+  ellipsoid; toward, across and away from the centre), and 0 from inside it
+  (no light sample is taken toward an emitter from within its support);
 * the pdf integrates to 1 over the sphere of directions;
 * the sampled directions follow the pdf (chi-square over solid-angle bins),
   and the points behind them are Gaussian (the directions toward the mean of
@@ -63,7 +64,7 @@ def test_light_pdf_matches_its_integral_definition(orc):
     n_emit = sc["mean"].shape[0]
     rng = np.random.default_rng(7)
     worst = 0.0
-    checked = 0
+    checked = inside = 0
     for k in range(n_emit):
         mu, s, R, Sigma, _ = indep.prim(sc, k)
         for dist in (0.05, 0.5, 2.0, 8.0):  # in units of the largest scale: inside .. far
@@ -74,8 +75,13 @@ def test_light_pdf_matches_its_integral_definition(orc):
                 for w in (c, c + 0.5 * float(np.max(s)) / max(np.linalg.norm(mu - x), 1e-3) * rng.normal(size=3),
                           rng.normal(size=3)):
                     w = w / np.linalg.norm(w)
-                    ref = _pdf_quad(sc, k, x, w)
                     got = S.light_pdf(k, x, w) * n_emit
+                    if indep.mahal2(sc, k, x) <= indep.R_CUT ** 2:
+                        # no light sample from inside the cut-off ellipsoid
+                        assert got == 0.0
+                        inside += 1
+                        continue
+                    ref = _pdf_quad(sc, k, x, w)
                     # relative agreement wherever the density is not
                     # vanishingly small (far behind the emitter both forms
                     # lose relative precision in the exp(-s^2/2) tail)
@@ -84,7 +90,7 @@ def test_light_pdf_matches_its_integral_definition(orc):
                         checked += 1
                     else:
                         assert got <= 1e-25
-    assert checked > 150
+    assert checked > 120 and inside > 30
     assert worst < 1e-7, worst
 
 
@@ -98,6 +104,7 @@ def test_light_pdf_integrates_to_one(orc, dist):
     for k in (0, 1, 4):
         mu, s, R, Sigma, _ = indep.prim(sc, k)
         x = mu + dist * np.array([0.3, 0.8, -0.52]) / np.linalg.norm([0.3, 0.8, -0.52])
+        assert indep.mahal2(sc, k, x) > indep.R_CUT ** 2
         c = (mu - x) / np.linalg.norm(mu - x)
         b1 = np.cross(c, [1.0, 0.0, 0.0] if abs(c[0]) < 0.9 else [0.0, 1.0, 0.0])
         b1 /= np.linalg.norm(b1)
@@ -132,6 +139,7 @@ def test_light_directions_follow_the_pdf(orc):
     k = 0
     mu, s, R, Sigma, _ = indep.prim(sc, k)
     x = mu + 0.3 * np.array([0.6, 0.0, 0.8])
+    assert indep.mahal2(sc, k, x) > indep.R_CUT ** 2
     c = (mu - x) / np.linalg.norm(mu - x)
     b1 = np.cross(c, [0.0, 1.0, 0.0])
     b1 /= np.linalg.norm(b1)
@@ -181,3 +189,46 @@ def test_light_points_are_gaussian(orc):
     off = W[:, :2] / W[:, 2:3] * D / float(s[0])
     for col in off.T:
         assert stats.kstest(col, "norm").pvalue > 1e-3
+
+
+def _panel_and_floor():
+    # a panel of overlapping flat emitters (thin axis 1/100) 1 above a floor
+    # of flat diffuse primitives, both facing each other
+    g = np.arange(12) * 0.05 - 0.275
+    px, pz = np.meshgrid(g, g)
+    fg = np.arange(16) * 0.12 - 0.9
+    fx, fz = np.meshgrid(fg, fg)
+    n_p, n_f = px.size, fx.size
+    mean = np.concatenate([np.stack([px.ravel(), np.full(n_p, 1.0), pz.ravel()], 1),
+                           np.stack([fx.ravel(), np.zeros(n_f), fz.ravel()], 1)])
+    s_p, s_f = 0.04, 0.1
+    scale = np.concatenate([np.tile([s_p, s_p, s_p / 100], (n_p, 1)), np.tile([s_f, s_f, s_f / 100], (n_f, 1))])
+    q = np.tile([np.cos(np.pi / 4), np.sin(np.pi / 4), 0.0, 0.0], (n_p + n_f, 1))  # thin axis -> y
+    alpha = 0.8
+    dens = 2 * alpha / (np.sqrt(2 * np.pi) * scale[:, 2])
+    emis = np.zeros((n_p + n_f, 3))
+    emis[:n_p] = 4.0
+    return {"mean": mean.astype(np.float32), "scale": scale.astype(np.float32), "rotation": q.astype(np.float32),
+            "density": dens.astype(np.float32), "albedo": np.full((n_p + n_f, 3), 0.7, np.float32),
+            "roughness": np.full(n_p + n_f, 0.5, np.float32), "emission": emis.astype(np.float32),
+            "material": np.zeros(n_p + n_f, np.int32)}
+
+
+@pytest.mark.slow
+def test_mis_estimators_agree_with_overlapping_flat_emitters(orc):
+    # paths scatter inside the panel's overlapping emitters and on the floor:
+    # light-only, phase-only and MIS estimates of the image agree
+    sc = _panel_and_floor()
+    S = orc.Scene(sc)
+    cam = {"origin": (0.0, 0.5, -2.0), "target": (0.0, 0.55, 0.0), "up": (0, 1, 0), "vfov_deg": 50.0,
+           "width": 24, "height": 24}
+    spp = 192
+    res = {}
+    for mode in (0, 1, 2):
+        s, s2, _ = S.render(cam, {"spp": spp, "max_depth": 2, "seed": 70 + mode, "mis_mode": mode})
+        per = s / spp
+        var = np.maximum(s2 / spp - per ** 2, 0.0)
+        res[mode] = (float(per.mean()), float(np.sqrt(var.mean() / (spp * s.shape[0]))))
+    for a in (1, 2):
+        assert abs(res[a][0] - res[0][0]) <= 4 * np.hypot(res[a][1], res[0][1]), res
+    assert all(v[1] < 0.03 * v[0] for v in res.values()), res
