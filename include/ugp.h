@@ -436,6 +436,17 @@ ugp_status ugp_render_roughness_grad(ugp_ctx ctx, const ugp_camera *cam, const u
 ugp_status ugp_render_density_grad(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p,
                                    const float *d_image, float *grad_density, float *sum_rgb);
 
+/* The albedo, roughness and density adjoints above from one forward pass and
+ * one replay of the same paths (the three calls each trace and replay the
+ * paths again): each gradient pointer is a [device] buffer laid out as in its
+ * own call, added to, or NULL when that gradient is not wanted; at least one
+ * must be given (else UGP_ERR_INVALID_ARGUMENT).  The restrictions of every
+ * requested adjoint apply (UGP_ERR_UNSUPPORTED); the results equal the
+ * separate calls' on the same parameters up to the order of floating-point
+ * atomic additions. */
+ugp_status ugp_render_grads(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p, const float *d_image,
+                            float *grad_albedo, float *grad_roughness, float *grad_density, float *sum_rgb);
+
 /* Test hook of the SGGX phase functions (materials 2 and 3; Sec. 4.2 and
  * App. B) for n independent queries (DEVICE arrays, float32):
  *   sggx[n][6]  S (xx, yy, zz, xy, xz, yz), positive definite

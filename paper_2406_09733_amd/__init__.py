@@ -78,7 +78,7 @@ class _Stats(C.Structure):
 
 EXPORTS = ["ugp_create", "ugp_destroy", "ugp_set_stream", "ugp_build_bvh", "ugp_refit_bvh", "ugp_transmittance",
            "ugp_sample_collision", "ugp_sample_collision_noalloc", "ugp_saturation", "ugp_emitter_query", "ugp_render", "ugp_render_albedo_grad",
-           "ugp_render_roughness_grad", "ugp_render_density_grad", "ugp_sync",
+           "ugp_render_roughness_grad", "ugp_render_density_grad", "ugp_render_grads", "ugp_sync",
            "ugp_set_profiling", "ugp_set_path_pool", "ugp_set_tail_paths", "ugp_get_render_stats", "ugp_trace_counts", "ugp_status_string",
            "ugp_nrc_num_params", "ugp_nrc_set_weights", "ugp_nrc_get_weights", "ugp_nrc_encode",
            "ugp_nrc_forward", "ugp_nrc_train_step", "ugp_nrc_records", "ugp_exp_transmittance",
@@ -111,6 +111,7 @@ def lib():
         L.ugp_render_albedo_grad.argtypes = [vp, C.POINTER(_Camera), C.POINTER(_Params), vp, vp, vp]
         L.ugp_render_roughness_grad.argtypes = [vp, C.POINTER(_Camera), C.POINTER(_Params), vp, vp, vp]
         L.ugp_render_density_grad.argtypes = [vp, C.POINTER(_Camera), C.POINTER(_Params), vp, vp, vp]
+        L.ugp_render_grads.argtypes = [vp, C.POINTER(_Camera), C.POINTER(_Params), vp, vp, vp, vp, vp]
         L.ugp_sync.argtypes = [vp]
         L.ugp_set_profiling.argtypes = [vp, C.c_int]
         L.ugp_set_path_pool.argtypes = [vp, C.c_int64]
@@ -517,6 +518,27 @@ class Context:
         _check("ugp_render_roughness_grad", lib().ugp_render_roughness_grad(self.h, C.byref(c), C.byref(p),
                                                                             _ptr(d), _ptr(grad), _ptr(sum_rgb)))
         return grad
+
+    def render_grads(self, cam: dict, params: dict, d_image, grad_albedo=None, grad_roughness=None,
+                     grad_density=None, sum_rgb=None):
+        """ugp_render_grads: the albedo ([n_prims, 3]), roughness ([n_prims])
+        and density ([n_prims]) gradients that are given (float32, added to)
+        from one forward pass and one replay; sum_rgb as in
+        render_albedo_grad.  Returns (grad_albedo, grad_roughness,
+        grad_density)."""
+        torch = self.torch
+        W, H = int(cam["width"]), int(cam["height"])
+        d = self._dev(d_image, torch.float32, (H, W, 3))
+        for g, shape in ((grad_albedo, (self.n, 3)), (grad_roughness, (self.n,)), (grad_density, (self.n,))):
+            if g is not None:
+                assert g.dtype == torch.float32 and tuple(g.shape) == shape and g.is_contiguous()
+        if sum_rgb is not None:
+            assert sum_rgb.dtype == torch.float32 and tuple(sum_rgb.shape) == (H, W, 3) and sum_rgb.is_contiguous()
+        c = _camera(cam)
+        p = _render_params(params)
+        _check("ugp_render_grads", lib().ugp_render_grads(self.h, C.byref(c), C.byref(p), _ptr(d), _ptr(grad_albedo),
+                                                          _ptr(grad_roughness), _ptr(grad_density), _ptr(sum_rgb)))
+        return grad_albedo, grad_roughness, grad_density
 
     def render_density_grad(self, cam: dict, params: dict, d_image, grad, sum_rgb=None):
         """ugp_render_density_grad: grad (float32 [n_prims]) += an unbiased

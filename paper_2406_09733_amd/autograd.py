@@ -92,16 +92,16 @@ class _Render(torch.autograd.Function):
             ugp.build_bvh(dict(fctx.fixed, albedo=albedo.detach(), roughness=roughness.detach(),
                                density=density.detach()))
             fctx.build_id = ugp.build_id
+        # every wanted gradient from one forward pass and one replay
         ga = gr = gd = None
         if fctx.needs_input_grad[5]:
             ga = torch.zeros((ugp.n, 3), device=ugp.device, dtype=torch.float32)
-            ugp.render_albedo_grad(fctx.cam, fctx.rparams, g.contiguous(), ga)
         if fctx.needs_input_grad[6]:
             gr = torch.zeros(ugp.n, device=ugp.device, dtype=torch.float32)
-            ugp.render_roughness_grad(fctx.cam, fctx.rparams, g.contiguous(), gr)
         if fctx.needs_input_grad[7]:
             gd = torch.zeros(ugp.n, device=ugp.device, dtype=torch.float32)
-            ugp.render_density_grad(fctx.cam, fctx.rparams, g.contiguous(), gd)
+        if ga is not None or gr is not None or gd is not None:
+            ugp.render_grads(fctx.cam, fctx.rparams, g.contiguous(), ga, gr, gd)
         return None, None, None, None, None, ga, gr, gd
 
 
@@ -109,11 +109,11 @@ def render(ugp, params: dict, cam: dict, render_params: dict, backward_params: d
     """Mean path-traced image (float32 [H, W, 3], ugp_render's sum / spp),
     differentiable with respect to params["albedo"] [P, 3],
     params["roughness"] [P] and params["density"] [P] (the other scene fields
-    are held fixed).  The backward is ugp_render_albedo_grad (the exact
-    derivative of this estimate: same camera, render parameters and seed),
-    ugp_render_roughness_grad and ugp_render_density_grad (unbiased estimates
-    of the derivative of the expected image), each only when its input
-    requires a gradient.  The radiance cache must be off.  backward_params
+    are held fixed).  The backward is one ugp_render_grads call for the
+    inputs that require a gradient: the albedo adjoint (the exact derivative
+    of this estimate: same camera, render parameters and seed) and the
+    roughness and density adjoints (unbiased estimates of the derivative of
+    the expected image).  The radiance cache must be off.  backward_params
     overrides render parameters of the backward pass only: another seed there
     makes the gradient estimate independent of this image's noise (the
     gradient of a loss that multiplies the two, such as |image - target|^2,

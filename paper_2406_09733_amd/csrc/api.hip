@@ -267,37 +267,37 @@ ugp_status ugp_render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_param
     return from_hip(ugp::render(ctx, cam, p, sum, sumsq));
 }
 
-ugp_status ugp_render_albedo_grad(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p,
-                                  const float *d_image, float *grad_albedo, float *sum) {
-    if (!d_image || !grad_albedo) return UGP_ERR_INVALID_ARGUMENT;
+ugp_status ugp_render_grads(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p, const float *d_image,
+                            float *grad_albedo, float *grad_roughness, float *grad_density, float *sum) {
+    if (!d_image || !(grad_albedo || grad_roughness || grad_density)) return UGP_ERR_INVALID_ARGUMENT;
     const ugp_status s = render_args(ctx, cam, p);
     if (s != UGP_OK) return s;
-    if (p->nrc_mode != 0 || ctx->scene.has_mat3) return UGP_ERR_UNSUPPORTED;
+    // the radiance cache is refused by every adjoint, material 3 by the shading ones
+    if (p->nrc_mode != 0 || ((grad_albedo || grad_roughness) && ctx->scene.has_mat3)) return UGP_ERR_UNSUPPORTED;
     DeviceGuard g(ctx->device);
-    const ugp::RenderAdjoint adj{d_image, grad_albedo, 0};
+    ugp::RenderAdjoint adj{d_image};
+    adj.grad_albedo = grad_albedo;
+    adj.grad_roughness = grad_roughness;
+    adj.grad_density = grad_density;
     return from_hip(ugp::render(ctx, cam, p, sum, nullptr, &adj));
+}
+
+ugp_status ugp_render_albedo_grad(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p,
+                                  const float *d_image, float *grad_albedo, float *sum) {
+    if (!grad_albedo) return UGP_ERR_INVALID_ARGUMENT;
+    return ugp_render_grads(ctx, cam, p, d_image, grad_albedo, nullptr, nullptr, sum);
 }
 
 ugp_status ugp_render_roughness_grad(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p,
                                      const float *d_image, float *grad_roughness, float *sum) {
-    if (!d_image || !grad_roughness) return UGP_ERR_INVALID_ARGUMENT;
-    const ugp_status s = render_args(ctx, cam, p);
-    if (s != UGP_OK) return s;
-    if (p->nrc_mode != 0 || ctx->scene.has_mat3) return UGP_ERR_UNSUPPORTED;
-    DeviceGuard g(ctx->device);
-    const ugp::RenderAdjoint adj{d_image, grad_roughness, 1};
-    return from_hip(ugp::render(ctx, cam, p, sum, nullptr, &adj));
+    if (!grad_roughness) return UGP_ERR_INVALID_ARGUMENT;
+    return ugp_render_grads(ctx, cam, p, d_image, nullptr, grad_roughness, nullptr, sum);
 }
 
 ugp_status ugp_render_density_grad(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p,
                                    const float *d_image, float *grad_density, float *sum) {
-    if (!d_image || !grad_density) return UGP_ERR_INVALID_ARGUMENT;
-    const ugp_status s = render_args(ctx, cam, p);
-    if (s != UGP_OK) return s;
-    if (p->nrc_mode != 0) return UGP_ERR_UNSUPPORTED;
-    DeviceGuard g(ctx->device);
-    const ugp::RenderAdjoint adj{d_image, grad_density, 2};
-    return from_hip(ugp::render(ctx, cam, p, sum, nullptr, &adj));
+    if (!grad_density) return UGP_ERR_INVALID_ARGUMENT;
+    return ugp_render_grads(ctx, cam, p, d_image, nullptr, nullptr, grad_density, sum);
 }
 
 ugp_status ugp_exp_transmittance(ugp_ctx ctx, int64_t n, const float *rays, const int32_t *exclude, float *T_out) {

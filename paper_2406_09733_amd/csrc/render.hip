@@ -109,33 +109,35 @@ struct NrcArgs {
 // light and environment samples' terms when they are collected.
 struct AdjArgs {
     const float *dimg = nullptr;  // dLoss / d(mean image) [npix][3]; null: forward pass
-    float *grad = nullptr;        // [n_prims][3], original index, added to
-    float4 *aux_cont = nullptr;   // per slot: (albedo ratio of the continuation, primitive bits)
-    float4 *aux_nee = nullptr;    // per slot: the same for this vertex's light sample
-    float4 *aux_env = nullptr;    // per slot: the same for its environment sample
+    float *grad_alb = nullptr;    // [n_prims][3], original index, added to (null: not wanted)
+    float *grad_rough = nullptr;  // [n_prims], channels summed
+    float *grad_dens = nullptr;   // [n_prims]
+    // per slot, for the albedo [0] and roughness [1] adjoints: (ratio, primitive
+    // bits) of the vertex's continuation [.][0], light sample [.][1] and
+    // environment sample [.][2]; null where that adjoint is not wanted
+    float4 *aux[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
     float inv_spp = 0.f;
     uint32_t npix = 1;
-    int param = 0;                // 0: albedo (grad [n][3]); 1: roughness (grad [n], channels summed);
-                                  // 2: density (grad [n]; the shading ratios and aux_* are not used)
 };
 
-__device__ __forceinline__ void adj_grad(const AdjArgs &A, int slot, int k, float x, float y, float z) {
+// the shading adjoint `which` (0 albedo, 1 roughness) of primitive k
+__device__ __forceinline__ void adj_grad(const AdjArgs &A, int which, int slot, int k, float x, float y, float z) {
     const float *g = A.dimg + 3 * (int64_t)((uint32_t)slot % A.npix);
-    float *dst = A.grad + 3 * (int64_t)k;
     const float gx = g[0] * A.inv_spp * x, gy = g[1] * A.inv_spp * y, gz = g[2] * A.inv_spp * z;
-    if (A.param == 1) {
+    if (which == 1) {
         const float t = gx + gy + gz;
-        if (t != 0.f) atomicAdd(A.grad + k, t);
+        if (t != 0.f) atomicAdd(A.grad_rough + k, t);
         return;
     }
+    float *dst = A.grad_alb + 3 * (int64_t)k;
     if (gx != 0.f) atomicAdd(dst, gx);
     if (gy != 0.f) atomicAdd(dst + 1, gy);
     if (gz != 0.f) atomicAdd(dst + 2, gz);
 }
 
-// the ratio (d f / d parameter) / f of the adjoint's parameter at a vertex
-__device__ __forceinline__ V3 adj_ratio(const AdjArgs &A, int mat, V3 alb, float rough, V3 wo, V3 wi) {
-    if (A.param == 1) {
+// the ratio (d f / d parameter) / f of adjoint `which` at a vertex
+__device__ __forceinline__ V3 adj_ratio(int which, int mat, V3 alb, float rough, V3 wo, V3 wi) {
+    if (which == 1) {
         const float r = phase_rough_ratio(mat, rough, wo, wi);
         return v3(r, r, r);
     }
@@ -145,10 +147,10 @@ __device__ __forceinline__ V3 adj_ratio(const AdjArgs &A, int mat, V3 alb, float
 // radiance c * f collected by the path of `slot`: added in the forward pass
 // (one explicit fma per channel, the same in every kernel that collects, so
 // that the per-path sums do not depend on which kernel traced the path); in
-// the replay subtracted, and with aux (the collecting vertex's ratio and
-// primitive) its albedo adjoint added
+// the replay subtracted, and for a light (kind 1) or environment (kind 2)
+// sample the shading adjoints added from the collecting vertex's ratios
 __device__ __forceinline__ void collect(const AdjArgs &A, float4 *L, int slot, float cx, float cy, float cz,
-                                        float f, const float4 *aux) {
+                                        float f, int kind) {
     float4 l = L[slot];
     if (!A.dimg) {
         l.x = fmaf(cx, f, l.x); l.y = fmaf(cy, f, l.y); l.z = fmaf(cz, f, l.z);
@@ -157,9 +159,12 @@ __device__ __forceinline__ void collect(const AdjArgs &A, float4 *L, int slot, f
     }
     l.x = fmaf(-cx, f, l.x); l.y = fmaf(-cy, f, l.y); l.z = fmaf(-cz, f, l.z);
     L[slot] = l;
-    if (aux) {
-        const float4 a = aux[slot];
-        adj_grad(A, slot, __float_as_int(a.w), a.x * (cx * f), a.y * (cy * f), a.z * (cz * f));
+    if (kind < 1) return;
+    for (int w = 0; w < 2; ++w) {
+        if (A.aux[w][kind]) {
+            const float4 a = A.aux[w][kind][slot];
+            adj_grad(A, w, slot, __float_as_int(a.w), a.x * (cx * f), a.y * (cy * f), a.z * (cz * f));
+        }
     }
 }
 
@@ -500,10 +505,15 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
     V3 beta = f3(C);
     const Rng4 g0 = path_rng(P, (uint32_t)pix, (uint32_t)v, 0);
     const Rng4 g1 = path_rng(P, (uint32_t)pix, (uint32_t)v, 1);
-    if (P.adj.aux_cont && v >= 2) {
+    if (P.adj.dimg && v >= 2) {
         // replay: what is left to collect went through the previous vertex's continuation
-        const float4 a = P.adj.aux_cont[pix], R = L[pix];
-        adj_grad(P.adj, pix, __float_as_int(a.w), a.x * R.x, a.y * R.y, a.z * R.z);
+        const float4 R = L[pix];
+        for (int w = 0; w < 2; ++w) {
+            if (P.adj.aux[w][0]) {
+                const float4 a = P.adj.aux[w][0][pix];
+                adj_grad(P.adj, w, pix, __float_as_int(a.w), a.x * R.x, a.y * R.y, a.z * R.z);
+            }
+        }
     }
     V3 Lc = v3(0.f, 0.f, 0.f);  // radiance picked up here: Lw * Lc
     float Lw = 0.f;
@@ -589,9 +599,11 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
                         const float4 eL = S.cold[3 * e + 2];
                         const V3 wt = (w / pn) * mul(mul(beta, f), f3(eL));
                         out.do_nee = true;
-                        if (P.adj.aux_nee) {
-                            const V3 q = adj_ratio(P.adj, mat, alb, rough, wol, to_local(F, wl));
-                            P.adj.aux_nee[pix] = make_float4(q.x, q.y, q.z, __int_as_float(k));
+                        for (int aw = 0; aw < 2; ++aw) {
+                            if (P.adj.aux[aw][1]) {
+                                const V3 q = adj_ratio(aw, mat, alb, rough, wol, to_local(F, wl));
+                                P.adj.aux[aw][1][pix] = make_float4(q.x, q.y, q.z, __int_as_float(k));
+                            }
                         }
                         out.na = make_float4(x.x, x.y, x.z, __int_as_float(e));
                         out.nb = make_float4(wl.x, wl.y, wl.z, __int_as_float(k));
@@ -615,9 +627,11 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
                     const float w = P.mis_mode == 2 ? 1.f : pe / (pe + pph);
                     const V3 wt = (w / pe) * mul(mul(beta, f), v3(P.env[0], P.env[1], P.env[2]));
                     out.do_env = true;
-                    if (P.adj.aux_env) {
-                        const V3 q = adj_ratio(P.adj, mat, alb, rough, wol, to_local(F, wl));
-                        P.adj.aux_env[pix] = make_float4(q.x, q.y, q.z, __int_as_float(k));
+                    for (int aw = 0; aw < 2; ++aw) {
+                        if (P.adj.aux[aw][2]) {
+                            const V3 q = adj_ratio(aw, mat, alb, rough, wol, to_local(F, wl));
+                            P.adj.aux[aw][2][pix] = make_float4(q.x, q.y, q.z, __int_as_float(k));
+                        }
                     }
                     out.ea = make_float4(x.x, x.y, x.z, 0.f);
                     out.eb = make_float4(wl.x, wl.y, wl.z, __int_as_float(k));
@@ -647,9 +661,11 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
                 beta = mul(beta, wgt);
                 if (nonzero(beta)) {
                     out.cont = true;
-                    if (P.adj.aux_cont) {
-                        const V3 q = adj_ratio(P.adj, mat, alb, rough, wol, wil);
-                        P.adj.aux_cont[pix] = make_float4(q.x, q.y, q.z, __int_as_float(k));
+                    for (int aw = 0; aw < 2; ++aw) {
+                        if (P.adj.aux[aw][0]) {
+                            const V3 q = adj_ratio(aw, mat, alb, rough, wol, wil);
+                            P.adj.aux[aw][0][pix] = make_float4(q.x, q.y, q.z, __int_as_float(k));
+                        }
                     }
                     out.ca = make_float4(x.x, x.y, x.z, pdf);
                     out.cb = make_float4(wi.x, wi.y, wi.z, __int_as_float(k));
@@ -658,7 +674,7 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
             }
         }
     }
-    if (Lw != 0.f && (Lc.x != 0.f || Lc.y != 0.f || Lc.z != 0.f)) collect(P.adj, L, pix, Lc.x, Lc.y, Lc.z, Lw, nullptr);
+    if (Lw != 0.f && (Lc.x != 0.f || Lc.y != 0.f || Lc.z != 0.f)) collect(P.adj, L, pix, Lc.x, Lc.y, Lc.z, Lw, 0);
 }
 
 // Shading of every live path after its collision: emission pick-up (MIS
@@ -725,7 +741,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_light(SceneDev S, LightQueue q, c
             }
             return;
         }
-        if (so.t > 0.f) collect(adj, L, pix, C.x, C.y, C.z, so.t, adj.aux_nee);
+        if (so.t > 0.f) collect(adj, L, pix, C.x, C.y, C.z, so.t, 1);
     };
     if (WIDE) {
         for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock)
@@ -769,7 +785,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_light(SceneDev S, LightQueue q, c
                     ovf.idx[slot] = (int32_t)i;
                 } else if (so.t > 0.f) {
                     const float4 C = q.c[i];
-                    collect(adj, L, __float_as_int(C.w), C.x, C.y, C.z, so.t, adj.aux_nee);
+                    collect(adj, L, __float_as_int(C.w), C.x, C.y, C.z, so.t, 1);
                 }
                 i = -1;
             }
@@ -790,7 +806,7 @@ __global__ __launch_bounds__(kBlock) void k_env(SceneDev S, LightQueue q, const 
         const RayD r = make_ray(A.x, A.y, A.z, B.x, B.y, B.z, 0.f, __builtin_huge_val());
         const float F = transmittance_F(S, r, excl, true, stack, err, tc);
         const float T = fmaxf(0.f, 1.f - F);
-        if (T > 0.f) collect(adj, L, pix, C.x, C.y, C.z, T, adj.aux_env);
+        if (T > 0.f) collect(adj, L, pix, C.x, C.y, C.z, T, 2);
     }
     flush_counts(S, tc);
 }
@@ -928,18 +944,18 @@ __global__ __launch_bounds__(kBlock) void k_dens_collide(SceneDev S, PassArgs P,
         const int excl = __float_as_int(B.w), k = hits[i].x;
         const RayD r = make_ray(A.x, A.y, A.z, B.x, B.y, B.z, 0.f, __builtin_huge_val());
         if (k < 0) {
-            dens_all(S, r, excl, w, true, P.adj.grad, stack, err, tc);
+            dens_all(S, r, excl, w, true, P.adj.grad_dens, stack, err, tc);
             continue;
         }
         const HotRec hk = load_hot(S.hot, S.inv[k]);
         Chord ck;
         if (!chord(hk, r, S.r2, ck) || !(hk.d > 0.f)) continue;
-        atomicAdd(P.adj.grad + k, w / hk.d);
+        atomicAdd(P.adj.grad_dens + k, w / hk.d);
         const SweepOut so = tail_sweep(S, r, excl, kModeSaturate, 0.f, -1, -kInf, stack, err, tc);
         if (so.status == 0 && so.td < ck.bd) {  // k straddles t_sat
             const float wk = half_integral_to(ck, so.td);
             if (wk > 0.f)
-                dens_tsat_terms(S, r, excl, so.td, half_kernel_at(ck, so.td), w / wk, P.adj.grad, stack, err, tc);
+                dens_tsat_terms(S, r, excl, so.td, half_kernel_at(ck, so.td), w / wk, P.adj.grad_dens, stack, err, tc);
         }
     }
 }
@@ -965,9 +981,9 @@ __global__ __launch_bounds__(kBlock) void k_dens_light(SceneDev S, LightQueue q,
         if (so.status != 0) continue;
         const float wk = half_integral_to(ck, so.td);
         if (!(wk > 0.f)) continue;  // hidden by primitives in front: factor 0
-        atomicAdd(adj.grad + target, w * wk / hk.d);
+        atomicAdd(adj.grad_dens + target, w * wk / hk.d);
         if (so.td < ck.bd)
-            dens_tsat_terms(S, r, excl, so.td, half_kernel_at(ck, so.td), w, adj.grad, stack, err, tc);
+            dens_tsat_terms(S, r, excl, so.td, half_kernel_at(ck, so.td), w, adj.grad_dens, stack, err, tc);
     }
 }
 
@@ -985,7 +1001,7 @@ __global__ __launch_bounds__(kBlock) void k_dens_env(SceneDev S, LightQueue q, c
         float F = 0.f;
         dens_chords(S, r, __float_as_int(B.w), kInf, stack, err, tc, [&](const HotRec &, const Chord &c) { F += c.W; });
         if (!(F < 1.f)) continue;  // T = 0: the sample added nothing, and nothing nearby
-        dens_all(S, r, __float_as_int(B.w), w, false, adj.grad, stack, err, tc);
+        dens_all(S, r, __float_as_int(B.w), w, false, adj.grad_dens, stack, err, tc);
     }
 }
 
@@ -1251,7 +1267,8 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
     if (e != hipSuccess) return e;
     RenderBuffers *rb = ctx->rb;
     hipStream_t st = ctx->stream;
-    // albedo adjoint: the replay's per-slot ratios (three float4 per radiance slot)
+    // shading adjoints: the replay's per-slot ratios (three float4 per
+    // radiance slot for each of albedo and roughness that is wanted)
     AdjArgs adjA;
     float4 *aux = nullptr;
     struct AuxFree {
@@ -1262,18 +1279,23 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
         }
     } aux_free{aux, st};
     if (adj) {
-        if (adj->param != 2) {  // the shading adjoints' per-slot ratios
-            e = hipMallocAsync((void **)&aux, sizeof(float4) * 3 * (size_t)lcap, st);
+        const int nsh = (adj->grad_albedo ? 1 : 0) + (adj->grad_roughness ? 1 : 0);
+        if (nsh > 0) {
+            e = hipMallocAsync((void **)&aux, sizeof(float4) * 3 * (size_t)nsh * (size_t)lcap, st);
             if (e != hipSuccess) return e;
-            adjA.aux_cont = aux;
-            adjA.aux_nee = aux + lcap;
-            adjA.aux_env = aux + 2 * lcap;
+            float4 *next = aux;
+            for (int w = 0; w < 2; ++w) {
+                if (!(w == 0 ? adj->grad_albedo : adj->grad_roughness)) continue;
+                for (int kind = 0; kind < 3; ++kind) adjA.aux[w][kind] = next + (int64_t)kind * lcap;
+                next += 3 * lcap;
+            }
         }
         adjA.dimg = adj->d_image;
-        adjA.grad = adj->grad;
+        adjA.grad_alb = adj->grad_albedo;
+        adjA.grad_rough = adj->grad_roughness;
+        adjA.grad_dens = adj->grad_density;
         adjA.inv_spp = 1.f / (float)p->spp;
         adjA.npix = (uint32_t)npix;
-        adjA.param = adj->param;
     }
     PassArgs P;
     make_cam_dev(cam, &P.cam);
@@ -1425,7 +1447,7 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
                     hipLaunchKernelGGL((k_collide<kEventsWide, true>), dim3(gw), dim3(kBlock), 0, st, Sc[1], P, qin,
                                        (const int32_t *)c, order, c + 4, rb->hits, ctx->stats, ov, ctx->err);
                 });
-                if (P.adj.dimg && P.adj.param == 2)
+                if (P.adj.dimg && P.adj.grad_dens != nullptr)
                     hipLaunchKernelGGL(k_dens_collide, dim3(gq), dim3(kBlock), 0, st, S, P, qin, (const int32_t *)c,
                                        (const int2 *)rb->hits, (const float4 *)rb->L, ctx->err);
                 timed(4, [&] {
@@ -1450,7 +1472,7 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
                                            (const int32_t *)(c + 1), order, c + 5, rb->L, ctx->stats, ov, P.adj,
                                            ctx->err);
                     });
-                    if (P.adj.dimg && P.adj.param == 2)
+                    if (P.adj.dimg && P.adj.grad_dens != nullptr)
                         hipLaunchKernelGGL(k_dens_light, dim3(gq), dim3(kBlock), 0, st, S, rb->nee,
                                            (const int32_t *)(c + 1), P.adj, ctx->err);
                 }
@@ -1459,7 +1481,7 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
                         hipLaunchKernelGGL(k_env, dim3(gq), dim3(kBlock), 0, st, Sc[3], rb->env,
                                            (const int32_t *)(c + 2), rb->L, ctx->stats, P.adj, ctx->err);
                     });
-                if (P.has_env && p->mis_mode != 1 && P.adj.dimg && P.adj.param == 2)
+                if (P.has_env && p->mis_mode != 1 && P.adj.dimg && P.adj.grad_dens != nullptr)
                     hipLaunchKernelGGL(k_dens_env, dim3(gq), dim3(kBlock), 0, st, S, rb->env, (const int32_t *)(c + 2),
                                        P.adj, ctx->err);
                 if (p->nrc_mode == 1 || p->nrc_mode == 2) {

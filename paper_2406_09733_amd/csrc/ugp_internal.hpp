@@ -132,8 +132,9 @@ hipError_t launch_exp(ugp_ctx ctx, int64_t n, const float *rays, const int32_t *
 // [h][w][3]; grad [n][3] += dLoss/dalbedo by original index.
 struct RenderAdjoint {
     const float *d_image;
-    float *grad;
-    int param = 0;  // 0: albedo, grad [n][3]; 1: roughness, grad [n]; 2: density, grad [n]
+    float *grad_albedo = nullptr;     // [n][3], or null: not wanted
+    float *grad_roughness = nullptr;  // [n], or null
+    float *grad_density = nullptr;    // [n], or null
 };
 hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p, float *sum, float *sumsq,
                   const RenderAdjoint *adj = nullptr);

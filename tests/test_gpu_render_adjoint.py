@@ -186,3 +186,41 @@ def test_albedo_gradient_rejects_the_cache(ctx, torch):
     with pytest.raises(P.UGPError) as e:
         ctx.render_albedo_grad(CAM, dict(PARAMS, nrc_mode=3), d, g)
     assert e.value.code == 5
+
+
+def test_combined_adjoints_equal_the_separate_calls(ctx, torch):
+    # ugp_render_grads: albedo, roughness and density gradients from one
+    # forward pass and one replay equal the three separate calls (each its own
+    # forward pass and replay of the same paths), up to the order of float
+    # atomic additions; the forward image is the same bit for bit
+    import paper_2406_09733_amd as P
+    sc = _scene()
+    ctx.build_bvh(sc)
+    n = sc["mean"].shape[0]
+    d = torch.tensor(_weights(), device="cuda")
+    p = dict(PARAMS, mis_mode=0)
+    z3 = lambda: torch.zeros((n, 3), device="cuda", dtype=torch.float32)
+    z1 = lambda: torch.zeros(n, device="cuda", dtype=torch.float32)
+    zi = lambda: torch.zeros((48, 48, 3), device="cuda", dtype=torch.float32)
+    ga, gr, gd = z3(), z1(), z1()
+    sa, sr, sd = zi(), zi(), zi()
+    ctx.render_albedo_grad(CAM, p, d, ga, sa)
+    ctx.render_roughness_grad(CAM, p, d, gr, sr)
+    ctx.render_density_grad(CAM, p, d, gd, sd)
+    ca, cr, cd, sc_ = z3(), z1(), z1(), zi()
+    ctx.render_grads(CAM, p, d, ca, cr, cd, sc_)
+    # two of the three at once
+    pa, pd = z3(), z1()
+    ctx.render_grads(CAM, p, d, grad_albedo=pa, grad_density=pd)
+    ctx.sync()
+    for s in (sa, sr, sd):
+        assert torch.equal(s, sc_)
+    for sep, comb in ((ga, ca), (gr, cr), (gd, cd), (ga, pa), (gd, pd)):
+        a, b = sep.cpu().numpy().astype(np.float64), comb.cpu().numpy().astype(np.float64)
+        scale = np.abs(a).max()
+        assert scale > 0
+        err = float(np.abs(a - b).max())
+        _say(f"  combined vs separate: max |diff| {err:.3e} of max |g| {scale:.3e}")
+        assert err <= 5e-5 * scale
+    with pytest.raises(P.UGPError):
+        ctx.render_grads(CAM, p, d)  # no gradient asked for
