@@ -929,13 +929,45 @@ __device__ __forceinline__ void dens_all(const SceneDev &S, const RayD &r, int e
     });
 }
 
-// collisions of the path queue (before their shading collects anything)
+// The rays of the collisions whose t_sat the density adjoint needs (a primitive
+// was selected and the pixel's loss weight is not zero), in the queue's traced
+// order j, for the saturation query; the others get an empty range.
+__global__ void k_dens_rays(PassArgs P, Queue q, const int32_t *n_in, int64_t n, const int32_t *order,
+                            const int2 *hits, const float4 *L, float *rays, int32_t *excl) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    float *r = rays + 8 * j;
+    bool need = false;
+    float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = make_float4(0.f, 0.f, 1.f, __int_as_float(-1));
+    if (j < *n_in) {
+        const int64_t i = order ? (int64_t)order[j] : j;
+        A = q.a[i];
+        B = q.b[i];
+        const int slot = __float_as_int(q.c[i].w) & kPixMask;
+        const float4 Rv = L[slot];
+        need = hits[i].x >= 0 && dens_weight(P.adj, slot, Rv.x, Rv.y, Rv.z) != 0.f;
+    }
+    if (!need) {
+        A = make_float4(0.f, 0.f, 0.f, 0.f);
+        B = make_float4(0.f, 0.f, 1.f, B.w);
+    }
+    r[0] = A.x; r[1] = A.y; r[2] = A.z;
+    r[3] = B.x; r[4] = B.y; r[5] = B.z;
+    r[6] = 0.f;
+    r[7] = need ? __builtin_huge_valf() : 0.f;
+    excl[j] = __float_as_int(B.w);
+}
+
+// collisions of the path queue (before their shading collects anything);
+// tsat[j] is the saturation query's t_sat of the entry traced j-th
 __global__ __launch_bounds__(kBlock) void k_dens_collide(SceneDev S, PassArgs P, Queue q, const int32_t *n_in,
-                                                         const int2 *hits, const float4 *L, uint32_t *err) {
+                                                         const int32_t *order, const int2 *hits, const float4 *L,
+                                                         const double *tsat, uint32_t *err) {
     __shared__ int stack[kStackSize * kBlock];
     const int n = *n_in;
     TraceCount tc;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = order ? (int64_t)order[j] : j;
         const float4 A = q.a[i], B = q.b[i], C = q.c[i];
         const int slot = __float_as_int(C.w) & kPixMask;
         const float4 Rv = L[slot];
@@ -951,11 +983,11 @@ __global__ __launch_bounds__(kBlock) void k_dens_collide(SceneDev S, PassArgs P,
         Chord ck;
         if (!chord(hk, r, S.r2, ck) || !(hk.d > 0.f)) continue;
         atomicAdd(P.adj.grad_dens + k, w / hk.d);
-        const SweepOut so = tail_sweep(S, r, excl, kModeSaturate, 0.f, -1, -kInf, stack, err, tc);
-        if (so.status == 0 && so.td < ck.bd) {  // k straddles t_sat
-            const float wk = half_integral_to(ck, so.td);
+        const double td = tsat[j];  // NaN where the query overflowed (reported by ugp_sync)
+        if (td < ck.bd) {  // k straddles t_sat
+            const float wk = half_integral_to(ck, td);
             if (wk > 0.f)
-                dens_tsat_terms(S, r, excl, so.td, half_kernel_at(ck, so.td), w / wk, P.adj.grad_dens, stack, err, tc);
+                dens_tsat_terms(S, r, excl, td, half_kernel_at(ck, td), w / wk, P.adj.grad_dens, stack, err, tc);
         }
     }
 }
@@ -1278,6 +1310,17 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
             if (p) hipFreeAsync(p, s);
         }
     } aux_free{aux, st};
+    char *dens_mem = nullptr;
+    struct DensFree {
+        char *&p;
+        hipStream_t s;
+        ~DensFree() {
+            if (p) hipFreeAsync(p, s);
+        }
+    } dens_free{dens_mem, st};
+    double *dens_td = nullptr;
+    float *dens_rays = nullptr;
+    int32_t *dens_excl = nullptr;
     if (adj) {
         const int nsh = (adj->grad_albedo ? 1 : 0) + (adj->grad_roughness ? 1 : 0);
         if (nsh > 0) {
@@ -1289,6 +1332,14 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
                 for (int kind = 0; kind < 3; ++kind) adjA.aux[w][kind] = next + (int64_t)kind * lcap;
                 next += 3 * lcap;
             }
+        }
+        if (adj->grad_density) {  // the density adjoint's saturation queries: rays, exclusions, t_sat
+            e = hipMallocAsync((void **)&dens_mem, (sizeof(float) * 8 + sizeof(int32_t) + sizeof(double)) * (size_t)pool,
+                               st);
+            if (e != hipSuccess) return e;
+            dens_td = (double *)dens_mem;
+            dens_rays = (float *)(dens_td + pool);
+            dens_excl = (int32_t *)(dens_rays + 8 * pool);
         }
         adjA.dimg = adj->d_image;
         adjA.grad_alb = adj->grad_albedo;
@@ -1447,9 +1498,17 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
                     hipLaunchKernelGGL((k_collide<kEventsWide, true>), dim3(gw), dim3(kBlock), 0, st, Sc[1], P, qin,
                                        (const int32_t *)c, order, c + 4, rb->hits, ctx->stats, ov, ctx->err);
                 });
-                if (P.adj.dimg && P.adj.grad_dens != nullptr)
+                if (P.adj.dimg && P.adj.grad_dens != nullptr) {
+                    // t_sat of the collisions by the persistent saturation query
+                    hipLaunchKernelGGL(k_dens_rays, dim3(gn), dim3(256), 0, st, P, qin, (const int32_t *)c, n_it,
+                                       order, (const int2 *)rb->hits, (const float4 *)rb->L, dens_rays, dens_excl);
+                    e = launch_sweep(ctx, kModeSaturate, n_it, dens_rays, dens_excl, nullptr, nullptr, nullptr,
+                                     nullptr, nullptr, dens_td);
+                    if (e != hipSuccess) return e;
                     hipLaunchKernelGGL(k_dens_collide, dim3(gq), dim3(kBlock), 0, st, S, P, qin, (const int32_t *)c,
-                                       (const int2 *)rb->hits, (const float4 *)rb->L, ctx->err);
+                                       order, (const int2 *)rb->hits, (const float4 *)rb->L, (const double *)dens_td,
+                                       ctx->err);
+                }
                 timed(4, [&] {
                     hipLaunchKernelGGL(k_shade, dim3(gq), dim3(kBlock), 0, st, S, P, qin, (const int32_t *)c,
                                        (const int2 *)rb->hits, qout, cn, rb->nee, c + 1, rb->env, c + 2, rb->L);
