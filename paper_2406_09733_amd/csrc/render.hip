@@ -992,14 +992,51 @@ __global__ __launch_bounds__(kBlock) void k_dens_collide(SceneDev S, PassArgs P,
     }
 }
 
+// The light samples' rays clipped at their target's exit, in traced order,
+// for the density adjoint's saturation query (an empty range where the
+// pixel's loss weight is zero or the ray misses its target)
+__global__ void k_dens_light_rays(SceneDev S, LightQueue q, const int32_t *n_in, int64_t n, const int32_t *order,
+                                  AdjArgs adj, float *rays, int32_t *excl) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    float *r = rays + 8 * j;
+    float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = make_float4(0.f, 0.f, 1.f, __int_as_float(-1));
+    float t1 = 0.f;
+    if (j < *n_in) {
+        const int64_t i = order ? (int64_t)order[j] : j;
+        const float4 C = q.c[i];
+        A = q.a[i];
+        B = q.b[i];
+        const HotRec hk = load_hot(S.hot, S.inv[__float_as_int(A.w)]);
+        Chord ck;
+        if (dens_weight(adj, __float_as_int(C.w), C.x, C.y, C.z) != 0.f && hk.d > 0.f &&
+            chord(hk, make_ray(A.x, A.y, A.z, B.x, B.y, B.z, 0.f, __builtin_huge_val()), S.r2, ck))
+            t1 = (float)ck.bd;
+    }
+    if (!(t1 > 0.f)) {
+        A = make_float4(0.f, 0.f, 0.f, 0.f);
+        B = make_float4(0.f, 0.f, 1.f, B.w);
+        t1 = 0.f;
+    }
+    r[0] = A.x; r[1] = A.y; r[2] = A.z;
+    r[3] = B.x; r[4] = B.y; r[5] = B.z;
+    r[6] = 0.f;
+    r[7] = t1;
+    excl[j] = __float_as_int(B.w);
+}
+
 // light samples: the emitter factor W_k of target k along the ray clipped at
-// its exit, times the sample's weight
-__global__ __launch_bounds__(kBlock) void k_dens_light(SceneDev S, LightQueue q, const int32_t *n_in, AdjArgs adj,
+// its exit, times the sample's weight; tsat[j] is the saturation query's
+// t_sat of the sample traced j-th (its range's end, rounded to float, when
+// the ray does not saturate before the exit)
+__global__ __launch_bounds__(kBlock) void k_dens_light(SceneDev S, LightQueue q, const int32_t *n_in,
+                                                       const int32_t *order, AdjArgs adj, const double *tsat,
                                                        uint32_t *err) {
     __shared__ int stack[kStackSize * kBlock];
     const int n = *n_in;
     TraceCount tc;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = order ? (int64_t)order[j] : j;
         const float4 A = q.a[i], B = q.b[i], C = q.c[i];
         const float w = dens_weight(adj, __float_as_int(C.w), C.x, C.y, C.z);
         if (w == 0.f) continue;
@@ -1009,13 +1046,14 @@ __global__ __launch_bounds__(kBlock) void k_dens_light(SceneDev S, LightQueue q,
         Chord ck;
         if (!chord(hk, r, S.r2, ck) || !(hk.d > 0.f)) continue;
         r.t1 = ck.bd;
-        const SweepOut so = tail_sweep(S, r, excl, kModeSaturate, 0.f, -1, -kInf, stack, err, tc);
-        if (so.status != 0) continue;
-        const float wk = half_integral_to(ck, so.td);
+        double td = tsat[j];
+        if (!(td == td)) continue;  // the query overflowed (reported by ugp_sync)
+        const bool sat = td < (double)(float)ck.bd;  // saturates before the target's exit
+        if (!sat) td = ck.bd;
+        const float wk = half_integral_to(ck, td);
         if (!(wk > 0.f)) continue;  // hidden by primitives in front: factor 0
         atomicAdd(adj.grad_dens + target, w * wk / hk.d);
-        if (so.td < ck.bd)
-            dens_tsat_terms(S, r, excl, so.td, half_kernel_at(ck, so.td), w, adj.grad_dens, stack, err, tc);
+        if (sat) dens_tsat_terms(S, r, excl, td, half_kernel_at(ck, td), w, adj.grad_dens, stack, err, tc);
     }
 }
 
@@ -1531,9 +1569,16 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
                                            (const int32_t *)(c + 1), order, c + 5, rb->L, ctx->stats, ov, P.adj,
                                            ctx->err);
                     });
-                    if (P.adj.dimg && P.adj.grad_dens != nullptr)
+                    if (P.adj.dimg && P.adj.grad_dens != nullptr) {
+                        // t_sat of the light samples (at most n_it) by the persistent saturation query
+                        hipLaunchKernelGGL(k_dens_light_rays, dim3(gn), dim3(256), 0, st, S, rb->nee,
+                                           (const int32_t *)(c + 1), n_it, order, P.adj, dens_rays, dens_excl);
+                        e = launch_sweep(ctx, kModeSaturate, n_it, dens_rays, dens_excl, nullptr, nullptr, nullptr,
+                                         nullptr, nullptr, dens_td);
+                        if (e != hipSuccess) return e;
                         hipLaunchKernelGGL(k_dens_light, dim3(gq), dim3(kBlock), 0, st, S, rb->nee,
-                                           (const int32_t *)(c + 1), P.adj, ctx->err);
+                                           (const int32_t *)(c + 1), order, P.adj, (const double *)dens_td, ctx->err);
+                    }
                 }
                 if (P.has_env && p->mis_mode != 1)
                     timed(3, [&] {
