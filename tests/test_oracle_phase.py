@@ -95,3 +95,47 @@ def test_phase_sample_histogram_matches_pdf(orc):
         m = exp > 20
         chi2 = (((hist - exp) ** 2) / exp)[m].sum()
         assert chi2 < 40, (mat, chi2)
+
+
+def _ggx_slope_pdf(a, x, y):
+    # the GGX (Trowbridge-Reitz) distribution of microfacet slopes of roughness a
+    return 1.0 / (np.pi * a * a * (1.0 + (x * x + y * y) / (a * a)) ** 2)
+
+
+def _smith_lambda_by_definition(a, cos_t):
+    # Smith's Lambda from its definition over the slope distribution:
+    # Lambda = (1/mu) int_mu^inf (q - mu) P2(q) dq, mu = cot(theta), with the
+    # marginal P2(q) = int P22(q, y) dy taken by quadrature too
+    from scipy import integrate
+    mu = cos_t / np.sqrt(max(0.0, 1.0 - cos_t * cos_t))
+    P2 = lambda q: integrate.quad(lambda y: _ggx_slope_pdf(a, q, y), -np.inf, np.inf, epsabs=0, epsrel=1e-12)[0]
+    val = integrate.quad(lambda q: (q - mu) * P2(q), mu, np.inf, epsabs=0, epsrel=1e-10, limit=200)[0]
+    return val / mu
+
+
+def test_ggx_form_against_the_microfacet_definitions(orc):
+    # With albedo 1 (Schlick F = 1) the glossy delta-NDF phase function is
+    # D(h) G2(w_o, w_i) / (4 cos_o) and its sampling pdf G1(w_o) D(h) / (4
+    # cos_o).  Here D comes from the slope distribution (D(h) = P22(slope)
+    # / cos^4 theta_h), G1 = 1/(1 + Lambda(w_o)) and the height-correlated
+    # G2 = 1/(1 + Lambda(w_o) + Lambda(w_i)) with Lambda integrated from its
+    # definition, so a wrong exponent, a dropped term or the uncorrelated
+    # form G1 G1 fails it
+    rng = np.random.default_rng(21)
+    nrm = np.array([0.0, 0.0, 1.0])
+    for _ in range(12):
+        rough = rng.uniform(0.3, 1.0)
+        a = rough * rough
+        wo, wi = _rand_dir(rng), _rand_dir(rng)
+        wo[2], wi[2] = abs(wo[2]) + 0.05, abs(wi[2]) + 0.05
+        wo /= np.linalg.norm(wo)
+        wi /= np.linalg.norm(wi)
+        f, pdf = orc.phase_eval(1, np.ones(3), rough, nrm, wo, wi)
+        h = wo + wi
+        h /= np.linalg.norm(h)
+        D = _ggx_slope_pdf(a, -h[0] / h[2], -h[1] / h[2]) / h[2] ** 4
+        lo, li = _smith_lambda_by_definition(a, wo[2]), _smith_lambda_by_definition(a, wi[2])
+        f_ref = D / (1.0 + lo + li) / (4.0 * wo[2])
+        pdf_ref = D / (1.0 + lo) / (4.0 * wo[2])
+        assert np.allclose(f, f_ref, rtol=1e-7), (f, f_ref)
+        assert pdf == pytest.approx(pdf_ref, rel=1e-7)
