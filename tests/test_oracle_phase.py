@@ -139,3 +139,32 @@ def test_ggx_form_against_the_microfacet_definitions(orc):
         pdf_ref = D / (1.0 + lo) / (4.0 * wo[2])
         assert np.allclose(f, f_ref, rtol=1e-7), (f, f_ref)
         assert pdf == pytest.approx(pdf_ref, rel=1e-7)
+
+
+def test_ggx_fresnel_limits(orc):
+    # Schlick's Fresnel with F0 = albedo: at w_i = w_o (half vector along both,
+    # normal incidence on the microfacet) the reflectance is the albedo, so
+    # f(albedo) / f(1) = albedo; at grazing microfacet incidence (w_i = -w_o
+    # mirrored about a half vector nearly perpendicular to w_o) it tends to 1
+    rng = np.random.default_rng(22)
+    nrm = np.array([0.0, 0.0, 1.0])
+    for _ in range(6):
+        alb = rng.uniform(0.05, 0.9, 3)
+        w = _rand_dir(rng)
+        w[2] = abs(w[2]) + 0.1
+        w /= np.linalg.norm(w)
+        f1, _ = orc.phase_eval(1, np.ones(3), 0.6, nrm, w, w)
+        fa, _ = orc.phase_eval(1, alb, 0.6, nrm, w, w)
+        assert np.allclose(fa / f1, alb, rtol=1e-12)
+    # nearly opposite directions in the upper hemisphere: w_i . h -> 0
+    wo = np.array([np.sin(1.5), 0.0, np.cos(1.5)])
+    wi = np.array([-np.sin(1.5), 1e-3, np.cos(1.5)])
+    wi /= np.linalg.norm(wi)
+    f1, _ = orc.phase_eval(1, np.ones(3), 0.8, nrm, wo, wi)
+    fa, _ = orc.phase_eval(1, np.full(3, 0.2), 0.8, nrm, wo, wi)
+    h = (wo + wi) / np.linalg.norm(wo + wi)
+    c = float(wi @ h)
+    assert c < 0.08
+    # reflectance rises from 0.2 toward 1: above 0.2 + 0.8 * 0.92^5 = 0.727
+    # there, and below 1
+    assert np.all(fa / f1 > 0.72) and np.all(fa / f1 < 1.0)
