@@ -313,3 +313,23 @@ def test_albedo_adjoint_refuses_disney_base(ctx, torch):
     with pytest.raises(P.UGPError):
         ctx.render_albedo_grad(cam, {"spp": 1, "max_depth": 2, "seed": 0}, d_img,
                                torch.zeros((200, 3), device="cuda"))
+
+
+def test_combined_adjoints_on_a_disney_base(ctx, torch):
+    # the density adjoint supports every material; the shading adjoints
+    # refuse material 3, alone or together with the density one
+    import paper_2406_09733_amd as P
+    sc = scenes.with_sggx(scenes.tiny_random(n=200, n_emit=5), seed=0, frac=0.5, base="disney")
+    ctx.build_bvh(sc)
+    cam = dict(scenes.camera("tiny_random"), width=16, height=16)
+    p = {"spp": 2, "max_depth": 2, "seed": 0}
+    d_img = torch.ones((16, 16, 3), device="cuda")
+    gd = torch.zeros(200, device="cuda")
+    ctx.render_grads(cam, p, d_img, grad_density=gd)
+    ctx.sync()
+    assert bool(torch.isfinite(gd).all()) and float(gd.abs().sum()) > 0
+    for kw in ({"grad_albedo": torch.zeros((200, 3), device="cuda")},
+               {"grad_roughness": torch.zeros(200, device="cuda")},
+               {"grad_albedo": torch.zeros((200, 3), device="cuda"), "grad_density": torch.zeros(200, device="cuda")}):
+        with pytest.raises(P.UGPError):
+            ctx.render_grads(cam, p, d_img, **kw)
