@@ -365,7 +365,10 @@ ugp_status ugp_trace_counts(ugp_ctx ctx, int mode, int64_t n_rays, const float *
 
 /* Path tracing (Sec. 5 table tab:highlevel, eq. rte) with next-event
  * estimation to emissive primitives and to the environment and the balance
- * heuristic against phase sampling.  Adds, per pixel, the sum over this call's
+ * heuristic against phase sampling.  A light sample picks an emissive
+ * primitive uniformly and aims at a point drawn from its untruncated Gaussian
+ * (the solid-angle pdf in closed form; none is taken from inside the emitter's
+ * cut-off ellipsoid).  Adds, per pixel, the sum over this call's
  * samples of the path radiance to sum_rgb [height][width][3] and of its square
  * to sumsq_rgb (or NULL).  The samples are traced in chunks of
  * max(1, min(spp, 2^25 / pixels)) samples of every pixel, all paths of a
