@@ -83,7 +83,12 @@ constexpr int64_t kChunkPaths = int64_t(1) << 25;  // paths of a chunk (radiance
 // [0] paths in the queue, [1] light samples, [2] environment samples,
 // [3] overflow, [4] collision work, [5] light work, [6] cache queries;
 // then the chunk block: [0] paths generated, [1] training records appended
-constexpr int kCountStride = 8;
+// Queue counters, each on a 256-B line of its own: the shading kernel appends
+// to three of them once per wave, and atomics on one line serialise (with the
+// eight counters of both blocks sharing a line, k_shade took 80% longer).
+constexpr int kCtrSpread = 64;
+__host__ __device__ constexpr int ctr(int k) { return k * kCtrSpread; }
+constexpr int kCountStride = ctr(8);
 constexpr int kChunkBlock = 2 * kCountStride;
 constexpr int64_t kSortMin = 16384;  // queues shorter than this are traced unsorted
 
@@ -300,8 +305,8 @@ __global__ void k_regen_commit(int64_t pool, int64_t total, int32_t *cnt_in, int
     const int64_t n_new = pool - n_in < total - gen ? pool - n_in : total - gen;
     cnt_in[0] = (int32_t)(n_in + n_new);
     chunk[0] = (int32_t)(gen + n_new);
-    for (int k = 1; k < kCountStride; ++k) cnt_in[k] = 0;
-    for (int k = 0; k < kCountStride; ++k) cnt_out[k] = 0;
+    for (int k = 1; k < 8; ++k) cnt_in[ctr(k)] = 0;
+    for (int k = 0; k < 8; ++k) cnt_out[ctr(k)] = 0;
 }
 
 __device__ __forceinline__ int wave_append(bool want, int32_t *counter) {
@@ -1433,7 +1438,7 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
         P.nrc.frac = rb->frac;
         if (p->nrc_mode == 1) {
             P.nrc.rec = rb->rec;
-            P.nrc.n_rec = chunk_cnt + 1;
+            P.nrc.n_rec = chunk_cnt + ctr(1);
             P.nrc.rec_cap = p->nrc_train_records;
         }
     }
@@ -1490,7 +1495,7 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
                 int32_t *c = rb->counts + kCountStride * (it & 1);        // input queue's counters
                 int32_t *cn = rb->counts + kCountStride * ((it + 1) & 1); // output queue's counters
                 Queue qin = rb->q[it & 1], qout = rb->q[(it + 1) & 1];
-                Overflow ov{rb->ovf, c + 3};
+                Overflow ov{rb->ovf, c + ctr(3)};
                 // queue length of this iteration, known on the host: launches are sized to it
                 const int64_t n_new = std::min(pool - left, total - gen);
                 const int64_t n_it = left + n_new;
@@ -1502,7 +1507,7 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
                 hipLaunchKernelGGL(k_regen, dim3((unsigned)std::max<int64_t>(1, (n_new + 255) / 256)), dim3(256), 0, st,
                                    P, pool, total, (const int32_t *)c, (const int32_t *)chunk_cnt, qin, rb->L);
                 hipLaunchKernelGGL(k_regen_commit, dim3(1), dim3(1), 0, st, pool, total, c, cn, chunk_cnt);
-                P.nrc.n_qry = c + 6;
+                P.nrc.n_qry = c + ctr(6);
                 if (!adj && it > 0 && n_new == 0 && n_it <= ctx->tail_paths) {
                     // few paths left and none to generate: they run to the end in one kernel
                     timed(8, [&] {
@@ -1512,11 +1517,11 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
                     });
                     if (p->nrc_mode == 1 || p->nrc_mode == 2) {
                         timed(6, [&] {
-                            e = nrc_forward(ctx, n_it, c + 6, rb->qry, kNrcRecordFloats, 2, box, nullptr, rb->L,
+                            e = nrc_forward(ctx, n_it, c + ctr(6), rb->qry, kNrcRecordFloats, 2, box, nullptr, rb->L,
                                             nrc_scale);
                         });
                         if (e != hipSuccess) return e;
-                        hipLaunchKernelGGL(k_nrc_count, dim3(1), dim3(1), 0, st, (const int32_t *)(c + 6),
+                        hipLaunchKernelGGL(k_nrc_count, dim3(1), dim3(1), 0, st, (const int32_t *)(c + ctr(6)),
                                            ctx->stats + 3);
                     }
                     break;
@@ -1530,11 +1535,11 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
                     });
                 timed(0, [&] {
                     hipLaunchKernelGGL((k_collide<kEventsMain, false>), dim3(gq), dim3(kBlock), 0, st, Sc[0], P, qin,
-                                       (const int32_t *)c, order, c + 4, rb->hits, ctx->stats, ov, ctx->err);
+                                       (const int32_t *)c, order, c + ctr(4), rb->hits, ctx->stats, ov, ctx->err);
                 });
                 timed(1, [&] {
                     hipLaunchKernelGGL((k_collide<kEventsWide, true>), dim3(gw), dim3(kBlock), 0, st, Sc[1], P, qin,
-                                       (const int32_t *)c, order, c + 4, rb->hits, ctx->stats, ov, ctx->err);
+                                       (const int32_t *)c, order, c + ctr(4), rb->hits, ctx->stats, ov, ctx->err);
                 });
                 if (P.adj.dimg && P.adj.grad_dens != nullptr) {
                     // t_sat of the collisions by the persistent saturation query
@@ -1549,52 +1554,52 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
                 }
                 timed(4, [&] {
                     hipLaunchKernelGGL(k_shade, dim3(gq), dim3(kBlock), 0, st, S, P, qin, (const int32_t *)c,
-                                       (const int2 *)rb->hits, qout, cn, rb->nee, c + 1, rb->env, c + 2, rb->L);
+                                       (const int2 *)rb->hits, qout, cn, rb->nee, c + ctr(1), rb->env, c + ctr(2), rb->L);
                 });
                 if (S.n_emit > 0 && p->mis_mode != 1) {
                     // light queue (at most n_it records) sorted like the path queue
                     if (sorted)
                         timed(5, [&] {
                             const Queue lq{rb->nee.a, rb->nee.b, rb->nee.c, nullptr};
-                            hipLaunchKernelGGL(k_sort_keys, dim3(gn), dim3(256), 0, st, P, lq, (const int32_t *)(c + 1),
+                            hipLaunchKernelGGL(k_sort_keys, dim3(gn), dim3(256), 0, st, P, lq, (const int32_t *)(c + ctr(1)),
                                                n_it, rb->skey, rb->sval);
                             radix_sort(rb->skey, rb->sval, rb->skey2, rb->sval2, n_it, st);
                         });
                     timed(2, [&] {
-                        hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, st, c + 3, 0);
+                        hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, st, c + ctr(3), 0);
                         hipLaunchKernelGGL((k_light<kEventsMain, false>), dim3(gq), dim3(kBlock), 0, st, Sc[2], rb->nee,
-                                           (const int32_t *)(c + 1), order, c + 5, rb->L, ctx->stats, ov, P.adj,
+                                           (const int32_t *)(c + ctr(1)), order, c + ctr(5), rb->L, ctx->stats, ov, P.adj,
                                            ctx->err);
                         hipLaunchKernelGGL((k_light<kEventsWide, true>), dim3(gw), dim3(kBlock), 0, st, Sc[2], rb->nee,
-                                           (const int32_t *)(c + 1), order, c + 5, rb->L, ctx->stats, ov, P.adj,
+                                           (const int32_t *)(c + ctr(1)), order, c + ctr(5), rb->L, ctx->stats, ov, P.adj,
                                            ctx->err);
                     });
                     if (P.adj.dimg && P.adj.grad_dens != nullptr) {
                         // t_sat of the light samples (at most n_it) by the persistent saturation query
                         hipLaunchKernelGGL(k_dens_light_rays, dim3(gn), dim3(256), 0, st, S, rb->nee,
-                                           (const int32_t *)(c + 1), n_it, order, P.adj, dens_rays, dens_excl);
+                                           (const int32_t *)(c + ctr(1)), n_it, order, P.adj, dens_rays, dens_excl);
                         e = launch_sweep(ctx, kModeSaturate, n_it, dens_rays, dens_excl, nullptr, nullptr, nullptr,
                                          nullptr, nullptr, dens_td);
                         if (e != hipSuccess) return e;
                         hipLaunchKernelGGL(k_dens_light, dim3(gq), dim3(kBlock), 0, st, S, rb->nee,
-                                           (const int32_t *)(c + 1), order, P.adj, (const double *)dens_td, ctx->err);
+                                           (const int32_t *)(c + ctr(1)), order, P.adj, (const double *)dens_td, ctx->err);
                     }
                 }
                 if (P.has_env && p->mis_mode != 1)
                     timed(3, [&] {
                         hipLaunchKernelGGL(k_env, dim3(gq), dim3(kBlock), 0, st, Sc[3], rb->env,
-                                           (const int32_t *)(c + 2), rb->L, ctx->stats, P.adj, ctx->err);
+                                           (const int32_t *)(c + ctr(2)), rb->L, ctx->stats, P.adj, ctx->err);
                     });
                 if (P.has_env && p->mis_mode != 1 && P.adj.dimg && P.adj.grad_dens != nullptr)
-                    hipLaunchKernelGGL(k_dens_env, dim3(gq), dim3(kBlock), 0, st, S, rb->env, (const int32_t *)(c + 2),
+                    hipLaunchKernelGGL(k_dens_env, dim3(gq), dim3(kBlock), 0, st, S, rb->env, (const int32_t *)(c + ctr(2)),
                                        P.adj, ctx->err);
                 if (p->nrc_mode == 1 || p->nrc_mode == 2) {
                     // cached radiance of the paths that ended in the cache this iteration
                     timed(6, [&] {
-                        e = nrc_forward(ctx, n_it, c + 6, rb->qry, kNrcRecordFloats, 2, box, nullptr, rb->L, nrc_scale);
+                        e = nrc_forward(ctx, n_it, c + ctr(6), rb->qry, kNrcRecordFloats, 2, box, nullptr, rb->L, nrc_scale);
                     });
                     if (e != hipSuccess) return e;
-                    hipLaunchKernelGGL(k_nrc_count, dim3(1), dim3(1), 0, st, (const int32_t *)(c + 6), ctx->stats + 3);
+                    hipLaunchKernelGGL(k_nrc_count, dim3(1), dim3(1), 0, st, (const int32_t *)(c + ctr(6)), ctx->stats + 3);
                 }
                 // continue while paths remain in the next queue or wait to be generated
                 e = hipMemcpyAsync(rb->host, cn, sizeof(int32_t), hipMemcpyDeviceToHost, st);
@@ -1613,15 +1618,15 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
         if (p->nrc_mode == 1) {
             // targets of this chunk's records, the optimisation steps, new training-path probability
             timed(7, [&] {
-                e = nrc_targets(ctx, p->nrc_train_records, chunk_cnt + 1, rb->rec, rb->L, rb->targets);
+                e = nrc_targets(ctx, p->nrc_train_records, chunk_cnt + ctr(1), rb->rec, rb->L, rb->targets);
                 if (e == hipSuccess)
-                    e = nrc_train_render(ctx, p->nrc_train_records, chunk_cnt + 1, rb->rec, box, rb->targets,
+                    e = nrc_train_render(ctx, p->nrc_train_records, chunk_cnt + ctr(1), rb->rec, box, rb->targets,
                                          p->nrc_lr > 0.f ? p->nrc_lr : 1e-2f, std::max(1, p->nrc_train_steps),
                                          p->nrc_target_clamp, rb->loss);
-                if (e == hipSuccess) e = nrc_adapt(ctx, chunk_cnt + 1, p->nrc_train_records, rb->frac);
+                if (e == hipSuccess) e = nrc_adapt(ctx, chunk_cnt + ctr(1), p->nrc_train_records, rb->frac);
             });
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k_nrc_count, dim3(1), dim3(1), 0, st, (const int32_t *)(chunk_cnt + 1),
+            hipLaunchKernelGGL(k_nrc_count, dim3(1), dim3(1), 0, st, (const int32_t *)(chunk_cnt + ctr(1)),
                                ctx->stats + 4);
         }
         e = hipGetLastError();
@@ -1642,7 +1647,7 @@ hipError_t render_nrc_records(ugp_ctx ctx, int64_t cap, float *rec_out, float *t
     hipError_t e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) return e;
     int32_t appended = 0;
-    e = hipMemcpy(&appended, rb->counts + ctx->last_nrc_counts + 1, sizeof(int32_t), hipMemcpyDeviceToHost);
+    e = hipMemcpy(&appended, rb->counts + ctx->last_nrc_counts + ctr(1), sizeof(int32_t), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return e;
     int64_t n = std::min<int64_t>((int64_t)appended, ctx->last_nrc_cap);
     n = std::min<int64_t>(n, cap);
