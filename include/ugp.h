@@ -116,12 +116,19 @@ typedef struct {
  *                    targets (path radiance - radiance so far) / throughput
  *                    drive nrc_train_steps Adam steps (as ugp_nrc_train_step)
  *                    after every chunk of samples (see ugp_render) and f is
- *                    rescaled toward nrc_train_records records per chunk;
+ *                    rescaled toward nrc_train_records records per chunk.
+ *                    Up to 4 x nrc_train_records records of a chunk are
+ *                    kept and ordered by path (a fixed shuffle of the paths,
+ *                    each path's records in vertex order), and the first
+ *                    nrc_train_records of them are trained on, so the
+ *                    training and every later image repeat exactly from
+ *                    run to run (as long as no chunk attempts more than
+ *                    that: ugp_render_stats.nrc_records);
  *                  2 infer only (every path ends in the cache);
  *                  3 end paths at nrc_terminate_after + 1 and add nothing
  *   nrc_terminate_after  scattering events before a cached path ends (>= 1)
  *   nrc_train_records    records used per training step, 1 .. 1 << 20 (mode 1);
- *                  f starts at min(1, nrc_train_records / (2 paths of a chunk))
+ *                  f starts at min(1, nrc_train_records / (8 paths of a chunk))
  *   nrc_lr         Adam learning rate of the cache (0 = 1e-2)
  *   nrc_box        lo[3], hi[3] of the cache's position encoding; hi <= lo on
  *                  any axis = the scene bounds
@@ -501,7 +508,7 @@ typedef struct {
        (level 2, else -1) */
     int64_t cat_nodes[4], cat_prims[4], cat_reloads[4];
     int64_t nrc_queries;     /* paths that ended in the radiance cache */
-    int64_t nrc_records;     /* training records appended (before the per-pass cap) */
+    int64_t nrc_records;     /* training records attempted, summed over chunks (before the caps) */
     double ms_nrc_infer;     /* duration of the cache inference launches (level >= 1, else -1) */
     double ms_nrc_train;     /* ... of the cache training steps */
     float nrc_loss;          /* loss of the last training step (NaN if none) */
@@ -517,8 +524,7 @@ ugp_status ugp_set_profiling(ugp_ctx ctx, int level);
 /* Path slots of later ugp_render calls: 0 (the default) keeps every path of
  * a chunk in flight (up to 2^25); a smaller pool (>= 64) bounds the render
  * buffers to about 230 B per slot and refills slots with new camera paths as
- * paths end, at some cost in throughput.  Results do not depend on it
- * (except the cache training of nrc_mode 1, whose record order does).
+ * paths end, at some cost in throughput.  Results do not depend on it.
  * Buffers already allocated are kept.  [host] call, no device work. */
 ugp_status ugp_set_path_pool(ugp_ctx ctx, int64_t slots);
 
@@ -526,8 +532,7 @@ ugp_status ugp_set_path_pool(ugp_ctx ctx, int64_t slots);
  * chunk (once no path is left to generate, from the second bounce on) in one
  * kernel, one lane following its path to the end, instead of one wavefront
  * launch per bounce; 0 disables it.  Default 65536.  Results do not depend on
- * it (except the cache training of nrc_mode 1, whose record order does).
- * [host] call, no device work. */
+ * it.  [host] call, no device work. */
 ugp_status ugp_set_tail_paths(ugp_ctx ctx, int64_t paths);
 
 /* Statistics of the last ugp_render call (synchronises the stream). */
@@ -580,8 +585,9 @@ ugp_status ugp_nrc_train_step(ugp_ctx ctx, int64_t n, const float *x, int32_t x_
 /* The training records of the last sample pass of the last ugp_render call
  * with nrc_mode 1: records_out float [cap][24] (inputs[16], throughput[3],
  * path index as int32 bits, radiance before the vertex's scattered light[3],
- * vertex index) and targets_out float [cap][3] (or NULL), in no particular
- * order; *count_out [host] = records written (<= cap).  The path index is
+ * vertex index) and targets_out float [cap][3] (or NULL), in the order
+ * they were trained on (by path, see nrc_mode 1); *count_out [host] =
+ * records written (<= cap).  The path index is
  * pixel + pixels x (sample - first sample of its chunk), see ugp_render.
  * Synchronises. */
 ugp_status ugp_nrc_records(ugp_ctx ctx, int64_t cap, float *records_out, float *targets_out,

@@ -35,7 +35,9 @@
 // paths run to max_depth and record, at every scattering vertex, the cache
 // inputs, the throughput and the radiance gathered so far; after the chunk the
 // record's target is (path radiance - radiance so far) / throughput, and the
-// optimisation steps are taken on the chunk's records.
+// optimisation steps are taken on the chunk's records, ordered by path (a
+// fixed shuffle of the path slots) so that training, and with it every later
+// image, is the same from run to run.
 #include <algorithm>
 
 #include "trace_device.hpp"
@@ -68,15 +70,24 @@ struct RenderBuffers {
     int32_t *host = nullptr;    // pinned: [paths left in the next queue, paths generated]
     float *qry = nullptr;       // radiance-cache queries (kNrcRecordFloats per path)
     void *block = nullptr;
-    // radiance-cache training state (grown on demand)
+    // radiance-cache training state (grown on demand): records are appended
+    // to `staged` (kRecStage x rec_cap of them) in whatever order the waves
+    // reach them, then ordered by path into `rec` (rec_cap)
     int64_t rec_cap = 0;
-    float *rec = nullptr, *targets = nullptr, *frac = nullptr, *loss = nullptr;
+    float *staged = nullptr, *rec = nullptr, *targets = nullptr, *frac = nullptr, *loss = nullptr;
+    uint32_t *rkey = nullptr, *rkey2 = nullptr;  // record-sort keys (and scratch), kRecStage x rec_cap
+    int32_t *rval = nullptr, *rval2 = nullptr;   // record-sort permutation (and scratch)
     void *nrc_block = nullptr;
 };
 
 namespace {
 
 constexpr int kPersistBlocks = 4096;
+// training records staged per chunk, in multiples of the records a chunk
+// trains on: the training set does not depend on the order of appends as long
+// as a chunk attempts at most this many (the training-path probability is
+// adapted toward one multiple and starts at an eighth of a path's worth)
+constexpr int64_t kRecStage = 4;
 constexpr int64_t kPoolPaths = int64_t(1) << 25;   // path slots of the pool
 constexpr int64_t kChunkPaths = int64_t(1) << 25;  // paths of a chunk (radiance slots)
 // iteration counters, two blocks used alternately (input / output queue):
@@ -95,7 +106,7 @@ constexpr int64_t kSortMin = 16384;  // queues shorter than this are traced unso
 struct NrcArgs {
     int mode;              // 0 off, 1 infer + train, 2 infer, 3 terminate only
     int term;              // scattering events before a cached path ends
-    float *rec;            // training records [rec_cap][kNrcRecordFloats]
+    float *rec;            // staged training records [rec_cap][kNrcRecordFloats]
     int32_t *n_rec;        // records appended (may exceed rec_cap: the excess is dropped)
     int32_t rec_cap;
     float *qry;            // cache queries [paths][kNrcRecordFloats]
@@ -1280,6 +1291,44 @@ namespace {
 
 __global__ void k_set_float(float *p, float v) { *p = v; }
 
+// a bijection of [0, 2^25) (multiplications by odd constants and xor-shifts
+// within 25 bits), so that paths of nearby slots scatter over the key range
+__device__ __forceinline__ uint32_t slot_mix(uint32_t x) {
+    constexpr uint32_t m = (1u << 25) - 1u;
+    x = (x * 0x9E3779B1u) & m;
+    x ^= x >> 12;
+    x = (x * 0x85EBCA77u) & m;
+    x ^= x >> 13;
+    return x;
+}
+
+// sort keys of the staged records: the mixed path slot (radiance slots are
+// below 2^25), all ones past the staged count; the values are staging indices
+__global__ void k_rec_keys(const int32_t *n_dev, int64_t stage, const float *staged, uint32_t *keys,
+                           int32_t *vals) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= stage) return;
+    const int64_t n = (int64_t)*n_dev < stage ? (int64_t)*n_dev : stage;
+    keys[i] = i < n ? slot_mix((uint32_t)__float_as_int(staged[kNrcRecordFloats * i + 19]) & ((1u << 25) - 1u))
+                    : 0xFFFFFFFFu;
+    vals[i] = (int32_t)i;
+}
+
+// the first min(staged, cap) records in key order.  The sort is stable and a
+// path's records are staged in vertex order (each is appended one bounce
+// after the last), so the order, and which records fill the cap, depends
+// only on which paths were training paths.
+__global__ void k_rec_gather(const int32_t *n_dev, int64_t cap, const int32_t *order, const float *staged,
+                             float *rec) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = (int64_t)*n_dev < cap ? (int64_t)*n_dev : cap;
+    if (j >= n) return;
+    const float4 *src = reinterpret_cast<const float4 *>(staged + (int64_t)kNrcRecordFloats * order[j]);
+    float4 *dst = reinterpret_cast<float4 *>(rec + (int64_t)kNrcRecordFloats * j);
+#pragma unroll
+    for (int k = 0; k < kNrcRecordFloats / 4; ++k) dst[k] = src[k];
+}
+
 // radiance-cache buffers of a render: queries for every pixel, training
 // records and targets for rec_cap records, the training-path probability
 hipError_t ensure_nrc_buffers(ugp_ctx ctx, int64_t npix, int64_t rec_cap, bool *fresh) {
@@ -1296,11 +1345,18 @@ hipError_t ensure_nrc_buffers(ugp_ctx ctx, int64_t npix, int64_t rec_cap, bool *
         rb->nrc_block = nullptr;
         rb->rec_cap = 0;
         const int64_t cap = rec_cap < 1024 ? 1024 : rec_cap;
-        const size_t bytes = sizeof(float) * (size_t)cap * (kNrcRecordFloats + 3) + 2 * 256;
+        const size_t stage = (size_t)(kRecStage * cap);
+        const size_t bytes = sizeof(float) * (stage + (size_t)cap) * kNrcRecordFloats +
+                             sizeof(float) * 3 * (size_t)cap + 4 * sizeof(uint32_t) * stage + 2 * 256;
         e = hipMalloc(&rb->nrc_block, bytes);
         if (e != hipSuccess) return e;
-        rb->rec = (float *)rb->nrc_block;
+        rb->staged = (float *)rb->nrc_block;
+        rb->rec = rb->staged + stage * kNrcRecordFloats;
         rb->targets = rb->rec + (size_t)cap * kNrcRecordFloats;
+        rb->rkey = (uint32_t *)(rb->targets + 3 * (size_t)cap);
+        rb->rkey2 = rb->rkey + stage;
+        rb->rval = (int32_t *)(rb->rkey2 + stage);
+        rb->rval2 = rb->rval + stage;
         rb->frac = (float *)((char *)rb->nrc_block + bytes - 2 * 256);
         rb->loss = rb->frac + 64;
         rb->rec_cap = cap;
@@ -1429,17 +1485,17 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
         if (e != hipSuccess) return e;
         if (p->nrc_mode == 1 && (fresh || ctx->nrc_frac_pixels != lcap)) {
             // a training path is chosen with probability frac; frac starts at
-            // records / (2 paths of a chunk) and is adapted after every chunk
-            const float f0 = std::min(1.0f, (float)p->nrc_train_records / (2.0f * (float)lcap));
+            // records / (8 paths of a chunk) and is adapted after every chunk
+            const float f0 = std::min(1.0f, (float)p->nrc_train_records / (8.0f * (float)lcap));
             hipLaunchKernelGGL(k_set_float, dim3(1), dim3(1), 0, st, rb->frac, f0);
             ctx->nrc_frac_pixels = lcap;
         }
         P.nrc.qry = rb->qry;
         P.nrc.frac = rb->frac;
         if (p->nrc_mode == 1) {
-            P.nrc.rec = rb->rec;
+            P.nrc.rec = rb->staged;
             P.nrc.n_rec = chunk_cnt + ctr(1);
-            P.nrc.rec_cap = p->nrc_train_records;
+            P.nrc.rec_cap = (int32_t)(kRecStage * p->nrc_train_records);
         }
     }
     e = hipMemsetAsync(ctx->stats, 0, sizeof(int64_t) * 8, st);
@@ -1616,9 +1672,23 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
                                    sum, sumsq);
         }
         if (p->nrc_mode == 1) {
-            // targets of this chunk's records, the optimisation steps, new training-path probability
+            // this chunk's records in path order, their targets, the optimisation
+            // steps, new training-path probability
             timed(7, [&] {
-                e = nrc_targets(ctx, p->nrc_train_records, chunk_cnt + ctr(1), rb->rec, rb->L, rb->targets);
+                const int64_t stage = kRecStage * p->nrc_train_records;
+                const int32_t *n_att = chunk_cnt + ctr(1);
+                hipLaunchKernelGGL(k_rec_keys, dim3((unsigned)((stage + 255) / 256)), dim3(256), 0, st, n_att, stage,
+                                   (const float *)rb->staged, rb->rkey, rb->rval);
+                e = radix_sort(rb->rkey, rb->rval, rb->rkey2, rb->rval2, stage, st);
+                if (e == hipSuccess) {
+                    hipLaunchKernelGGL(k_rec_gather,
+                                       dim3((unsigned)((p->nrc_train_records + 255) / 256)), dim3(256), 0, st, n_att,
+                                       (int64_t)p->nrc_train_records, (const int32_t *)rb->rval,
+                                       (const float *)rb->staged, rb->rec);
+                    e = hipGetLastError();
+                }
+                if (e == hipSuccess)
+                    e = nrc_targets(ctx, p->nrc_train_records, chunk_cnt + ctr(1), rb->rec, rb->L, rb->targets);
                 if (e == hipSuccess)
                     e = nrc_train_render(ctx, p->nrc_train_records, chunk_cnt + ctr(1), rb->rec, box, rb->targets,
                                          p->nrc_lr > 0.f ? p->nrc_lr : 1e-2f, std::max(1, p->nrc_train_steps),
