@@ -562,7 +562,10 @@ const char *ugp_status_string(ugp_status s);
  * ------------------------------------------------------------------------ */
 int32_t ugp_nrc_num_params(void);
 /* Set the float32 master weights (device [P]) and reset the Adam moments and
- * step count.  The first call allocates the cache state. */
+ * step count, the radiance unit (the next training sets it) and the
+ * training-path probability of nrc_mode 1 (the next such render starts it
+ * afresh), so that renders from the same weights repeat exactly.  The first
+ * call allocates the cache state. */
 ugp_status ugp_nrc_set_weights(ugp_ctx ctx, const float *weights);
 /* Copy the float32 master weights to weights_out (device [P]).
  * UGP_ERR_INVALID_ARGUMENT if the cache has no state yet. */

@@ -243,8 +243,6 @@ ugp_status ugp_trace_counts(ugp_ctx ctx, int mode, int64_t n, const float *rays,
     if (ctx->scene.n == 0) return UGP_ERR_NO_SCENE;
     if (n == 0) return UGP_OK;
     DeviceGuard g(ctx->device);
-    float *scratch = (float *)ugp::ctx_scratch(ctx, 0);
-    (void)scratch;
     float *fo = nullptr;
     int32_t *po = nullptr;
     if (hipMallocAsync((void **)&fo, sizeof(float) * n, ctx->stream) != hipSuccess) return UGP_ERR_OUT_OF_MEMORY;

@@ -584,6 +584,7 @@ hipError_t nrc_set_weights(ugp_ctx ctx, const float *w) {
     e = hipMemsetAsync(s->scale, 0, sizeof(float), ctx->stream);  // radiance unit: set by the next training
     if (e != hipSuccess) return e;
     s->step = 0;
+    ctx->nrc_frac_pixels = 0;  // the next training render starts the training-path probability afresh
     hipLaunchKernelGGL(k_nrc_publish, dim3((kWfSize + 255) / 256), dim3(256), 0, ctx->stream, (const float *)s->master,
                        s->wf, s->wb);
     return hipGetLastError();

@@ -402,8 +402,9 @@ def test_cached_renders_repeat_exactly(torch):
     # reach them; the renderer orders a chunk's records by path before it
     # trains, so runs from the same weights give the same records, weights and
     # images bit for bit -- also with a bounded path pool and no tail kernel
-    # (other append orders), and when a chunk attempts more records than it
-    # trains on (the cap then keeps the same paths).  The room at 64x36, depth
+    # (other append orders), when a chunk attempts more records than it
+    # trains on (the cap then keeps the same paths), and in a context that
+    # trained before and was given the initial weights again.  The room at 64x36, depth
     # 30: a closed scene, so a training path records many vertices and the
     # first call attempts more than the cap.
     import paper_2406_09733_amd as P
@@ -417,24 +418,27 @@ def test_cached_renders_repeat_exactly(torch):
     p = {"max_depth": 30, "seed": 4, "spp": 4, "nrc_mode": 1, "nrc_terminate_after": 2, "nrc_train_records": cap,
          "nrc_train_steps": 4}
 
-    def run(pool, tail):
+    def run(pool, tail, again=False):
         ctx = P.Context(0)
         ctx.build_bvh(sc)
         ctx.set_path_pool(pool)
         ctx.set_tail_paths(tail)
-        ctx.nrc_set_weights(w0)
-        imgs, att = [], []
-        for k in range(3):
-            s, _ = ctx.render(cam, dict(p, sample_offset=4 * k))
-            att.append(int(ctx.render_stats()["nrc_records"]))
-            imgs.append(_np(s).copy())
+        for _ in range(2 if again else 1):
+            # setting the weights again restarts the training state (Adam,
+            # radiance unit, training-path probability)
+            ctx.nrc_set_weights(w0)
+            imgs, att = [], []
+            for k in range(3):
+                s, _ = ctx.render(cam, dict(p, sample_offset=4 * k))
+                att.append(int(ctx.render_stats()["nrc_records"]))
+                imgs.append(_np(s).copy())
         rec, tgt = ctx.nrc_records(cap)
         out = imgs, att, _np(ctx.nrc_get_weights()).copy(), _np(rec).copy(), _np(tgt).copy()
         ctx.close()
         return out
 
     a = run(0, 65536)
-    b = run(0, 65536)
+    b = run(0, 65536, again=True)
     c = run(64 * 36, 0)
     _say(f"  records attempted per call: {a[1]} (cap {cap}); kept in the last: {len(a[3])}")
     assert a[1] == b[1] == c[1]
