@@ -42,7 +42,8 @@ class _Params(C.Structure):
     _fields_ = [("spp", C.c_int32), ("max_depth", C.c_int32), ("seed", C.c_uint64),
                 ("sample_offset", C.c_int64), ("env_radiance", C.c_double * 3),
                 ("mis_mode", C.c_int32), ("nrc_mode", C.c_int32), ("nrc_terminate_after", C.c_int32),
-                ("nrc_train_frac", C.c_double), ("nrc_weights", C.c_void_p), ("nrc_box", C.c_double * 6)]
+                ("nrc_train_frac", C.c_double), ("nrc_weights", C.c_void_p), ("nrc_box", C.c_double * 6),
+                ("transport", C.c_int32)]
 
 
 def _p(a, ct):
@@ -409,6 +410,7 @@ def make_params(p: dict) -> _Params:
     q.nrc_mode = int(p.get("nrc_mode", 0))
     q.nrc_terminate_after = int(p.get("nrc_terminate_after", 2))
     q.nrc_train_frac = float(p.get("nrc_train_frac", 0.0))
+    q.transport = int(p.get("transport", 0))
     if q.nrc_mode in (1, 2):
         W = np.ascontiguousarray(p["nrc_weights"], dtype=np.float64)
         assert W.shape == (nrc_num_params(),)

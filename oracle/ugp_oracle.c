@@ -617,14 +617,64 @@ static double exp_uniform(uint64_t seed, int64_t i, int64_t k) {
     return (double)(x[0] >> 8) * (1.0 / 16777216.0);
 }
 
+/* Where the uniform of primitive k comes from in one decomposition-tracking
+ * query: ray i of a per-ray query (exp_uniform), or vertex v of a path of the
+ * exponential render mode -- counter (pixel, sample, v, 16 + 2k + which)
+ * under the path tracer's key, first word, which = 0 for the path's next
+ * collision and 1 for its light sample. */
+typedef struct {
+    int path;
+    uint64_t seed;
+    int64_t i;
+    uint32_t pix, sample, v, which;
+} exp_key;
+
+static double exp_u(const exp_key *q, int64_t k) {
+    if (!q->path) return exp_uniform(q->seed, q->i, k);
+    double u[4];
+    rng4(q->seed, q->pix, q->sample, q->v, (uint32_t)(16 + 2 * k + q->which), u);
+    return u[0];
+}
+
 /* Free-flight sampling of the exponential variant by analog decomposition
  * tracking (App. D, after Kutz et al. 2017): every Gaussian the ray meets
  * draws its own exponential free flight y_k = -ln(1 - u_k); it collides where
  * its optical depth from the chord entry reaches y_k, t_k = I_k^-1(y_k; a_k),
  * if y_k is below its whole chord's depth; the ray collides at the nearest
- * t_k, else escapes (prim -1, t NaN).  The inversion here is a bisection on
- * the monotone I_k(a_k, t).  margin: the smallest of |y_k - I_k(a_k, b_k)| / y_k
+ * t_k, else escapes (returns -1).  The inversion here is a bisection on the
+ * monotone I_k(a_k, t).  margin: the smallest of |y_k - I_k(a_k, b_k)| / y_k
  * and, when two collide, the relative gap of the two nearest t_k. */
+static int64_t exp_track(const orc_scene *S, const hitvec *H, const exp_key *q, double *t_out,
+                         double *margin_out) {
+    double best = INFINITY, second = INFINITY, margin = INFINITY;
+    int64_t bk = -1;
+    for (int64_t j = 0; j < H->n; ++j) {
+        const ohit *h = &H->v[j];
+        const double y = -log1p(-exp_u(q, h->k));
+        const double total = seg_integral(S, h, h->a, h->b);
+        margin = fmin(margin, fabs(y - total) / fmax(y, 1e-30));
+        if (!(y < total)) continue;
+        double lo = h->a, hi = h->b;
+        for (int it = 0; it < 200 && hi - lo > 1e-15 * fmax(1.0, fabs(hi)); ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (seg_integral(S, h, h->a, mid) < y) lo = mid;
+            else hi = mid;
+        }
+        const double t = 0.5 * (lo + hi);
+        if (t < best) {
+            second = best;
+            best = t;
+            bk = h->k;
+        } else if (t < second) {
+            second = t;
+        }
+    }
+    if (second < INFINITY) margin = fmin(margin, (second - best) / fmax(fabs(best), 1e-30));
+    *t_out = bk >= 0 ? best : NAN;
+    if (margin_out) *margin_out = margin;
+    return bk;
+}
+
 void orc_exp_sample(const orc_scene *S, int64_t n, const float *rays, const int32_t *exclude, uint64_t seed,
                     int use_bvh, int32_t *prim_out, double *t_out, double *margin_out) {
     hitvec H = {0};
@@ -632,33 +682,8 @@ void orc_exp_sample(const orc_scene *S, int64_t n, const float *rays, const int3
         const float *r = rays + 8 * i;
         double o[3] = {r[0], r[1], r[2]}, w[3] = {r[3], r[4], r[5]};
         gather(S, o, w, r[6], r[7], exclude ? exclude[i] : -1, use_bvh, &H);
-        double best = INFINITY, second = INFINITY, margin = INFINITY;
-        int64_t bk = -1;
-        for (int64_t j = 0; j < H.n; ++j) {
-            const ohit *h = &H.v[j];
-            const double y = -log1p(-exp_uniform(seed, i, h->k));
-            const double total = seg_integral(S, h, h->a, h->b);
-            margin = fmin(margin, fabs(y - total) / fmax(y, 1e-30));
-            if (!(y < total)) continue;
-            double lo = h->a, hi = h->b;
-            for (int it = 0; it < 200 && hi - lo > 1e-15 * fmax(1.0, fabs(hi)); ++it) {
-                const double mid = 0.5 * (lo + hi);
-                if (seg_integral(S, h, h->a, mid) < y) lo = mid;
-                else hi = mid;
-            }
-            const double t = 0.5 * (lo + hi);
-            if (t < best) {
-                second = best;
-                best = t;
-                bk = h->k;
-            } else if (t < second) {
-                second = t;
-            }
-        }
-        if (second < INFINITY) margin = fmin(margin, (second - best) / fmax(fabs(best), 1e-30));
-        prim_out[i] = (int32_t)bk;
-        t_out[i] = bk >= 0 ? best : NAN;
-        if (margin_out) margin_out[i] = margin;
+        const exp_key q = {0, seed, i, 0, 0, 0, 0};
+        prim_out[i] = (int32_t)exp_track(S, &H, &q, &t_out[i], margin_out ? &margin_out[i] : NULL);
     }
     free(H.v);
 }
@@ -1559,7 +1584,13 @@ static void trace_path(const orc_scene *S, const orc_render_params *P, const orc
         rng4(seed, pix, sample, v, 1, g);
         gather(S, o, w, 0.0, INFINITY, self, 1, H);
         ocoll c;
-        collide(S, H, 0.0, INFINITY, u[0], &c);
+        if (P->transport == 1) {
+            /* exponential variant: the nearest of the Gaussians' own free flights */
+            const exp_key q = {1, seed, 0, pix, sample, v, 0};
+            c.prim = exp_track(S, H, &q, &c.t_hit, NULL);
+        } else {
+            collide(S, H, 0.0, INFINITY, u[0], &c);
+        }
         ++*rays;
         if (c.prim < 0) {
             if (env) {
@@ -1640,7 +1671,18 @@ static void trace_path(const orc_scene *S, const orc_render_params *P, const orc
                 if ((f[0] > 0.0 || f[1] > 0.0 || f[2] > 0.0) && ray_prim(S, e, x, wl, 0.0, INFINITY, &he)) {
                     double pn = nee_pdf(S, e, x, wl);
                     if (pn > 0.0) {
-                        double fac = emitter_factor(S, x, wl, 0.0, INFINITY, k, e, 1, H2);
+                        double fac;
+                        if (P->transport == 1) {
+                            /* exponential variant: one decomposition-tracking draw along the
+                             * segment to e's chord exit scores 1 if e is hit first, an
+                             * unbiased estimate of the probability that it is */
+                            gather(S, x, wl, 0.0, he.b, -1, 1, H2);
+                            const exp_key q = {1, seed, 0, pix, sample, v, 1};
+                            double th;
+                            fac = exp_track(S, H2, &q, &th, NULL) == e ? 1.0 : 0.0;
+                        } else {
+                            fac = emitter_factor(S, x, wl, 0.0, INFINITY, k, e, 1, H2);
+                        }
                         ++*rays;
                         double wt = (P->mis_mode == 2) ? 1.0 : pn / (pn + pph);
                         for (int i = 0; i < 3; ++i)
@@ -1658,21 +1700,33 @@ static void trace_path(const orc_scene *S, const orc_render_params *P, const orc
             double f[3], pph;
             prim_phase_eval(S, k, wo, wl, e4, f, &pph);
             if (f[0] > 0.0 || f[1] > 0.0 || f[2] > 0.0) {
-                gather(S, x, wl, 0.0, INFINITY, k, 1, H2);
-                double T = fmax(0.0, 1.0 - accumulated_F(S, H2));
+                double T;
+                if (P->transport == 1) {
+                    /* exponential variant: exp of the optical depth, nothing excluded */
+                    gather(S, x, wl, 0.0, INFINITY, -1, 1, H2);
+                    double depth = 0.0;
+                    for (int64_t j = 0; j < H2->n; ++j) depth += seg_integral(S, &H2->v[j], H2->v[j].a, H2->v[j].b);
+                    T = exp(-depth);
+                } else {
+                    gather(S, x, wl, 0.0, INFINITY, k, 1, H2);
+                    T = fmax(0.0, 1.0 - accumulated_F(S, H2));
+                }
                 ++*rays;
                 double wt = (P->mis_mode == 2) ? 1.0 : p_env / (p_env + pph);
                 for (int i = 0; i < 3; ++i) L[i] += beta[i] * f[i] * T * P->env_radiance[i] * wt / p_env;
             }
         }
-        /* continue by phase sampling; spawn at the chord centre, skip self */
+        /* continue by phase sampling from the collision point */
         double wi[3], wgt[3], pdf;
         prim_phase_sample(S, k, wo, g[0], g[1], q5, wi, wgt, &pdf);
         if (!(pdf > 0.0)) break;
         for (int i = 0; i < 3; ++i) beta[i] *= wgt[i];
         if (beta[0] == 0.0 && beta[1] == 0.0 && beta[2] == 0.0) break;
         for (int i = 0; i < 3; ++i) { o[i] = x[i]; w[i] = wi[i]; x_prev[i] = x[i]; }
-        self = k;
+        /* the linear model's scatter point is the chord centre, and the
+         * primitive is skipped from there; an exponential medium scatters
+         * inside the Gaussian, whose rest still attenuates */
+        self = P->transport == 1 ? -1 : k;
         p_prev = pdf;
     }
 }

@@ -37,6 +37,11 @@ typedef struct {
     double nrc_train_frac;
     const double *nrc_weights;
     double nrc_box[6];
+    /* transport model: 0 linear transmittance (Sec. 4); 1 the exponential
+     * variant (App. D): collisions and light samples by analog decomposition
+     * tracking, environment samples by exp(-sum I_k), no primitive excluded
+     * from a path's next segment */
+    int32_t transport;
 } orc_render_params;
 
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
