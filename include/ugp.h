@@ -139,7 +139,19 @@ typedef struct {
  *                  current unit, which the first training after
  *                  ugp_nrc_set_weights sets to the mean of its targets
  *   nrc_target_clamp  training targets (in that unit) are clamped at this
- *                  value in the loss (0 = no clamp)                           */
+ *                  value in the loss (0 = no clamp)
+ *   transport      0 the paper's linear transmittance; 1 its exponential
+ *                  variant (App. D, eq. exp_ff; the baseline of the paper's
+ *                  comparison of transmittance models): the Gaussians as a
+ *                  medium with sigma_t = sum_k G_k, a path's collisions and
+ *                  light samples drawn by analog decomposition tracking (the
+ *                  uniform of Gaussian k at vertex v: the path's generator
+ *                  with group 16 + 2k, or 17 + 2k for the light sample), a
+ *                  light sample scoring if its target is hit first along the
+ *                  segment to the target's chord exit, environment samples
+ *                  weighted by exp(-sum_k I_k), and no primitive skipped after
+ *                  a scatter (it happens inside the Gaussian).  Requires
+ *                  nrc_mode 0; no adjoint entry point takes it (UGP_ERR_UNSUPPORTED). */
 typedef struct {
     int32_t spp, max_depth;
     uint64_t seed;
@@ -152,6 +164,7 @@ typedef struct {
     int32_t nrc_train_steps;
     float nrc_radiance_scale;
     float nrc_target_clamp;
+    int32_t transport;
 } ugp_render_params;
 
 /* Create a context on `device` that enqueues on `hip_stream` (a hipStream_t;
@@ -400,7 +413,7 @@ ugp_status ugp_render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_param
  *   grad_albedo  [device] float [scene n][3] by original index, added to
  *   sum_rgb      [device] float [height][width][3] or NULL: the forward pass's
  *                per-pixel sum is added to it (as ugp_render's)
- * p->nrc_mode must be 0 and the scene may hold no material 3
+ * p->nrc_mode and p->transport must be 0 and the scene may hold no material 3
  * (UGP_ERR_UNSUPPORTED otherwise); other arguments and errors as ugp_render.
  * A diffuse channel of zero albedo reports a zero gradient (the replay
  * divides the albedo out).
@@ -441,8 +454,9 @@ ugp_status ugp_render_roughness_grad(ugp_ctx ctx, const ugp_camera *cam, const u
  * again, up to three times (t_sat, F', the terms).
  *   grad_density [device] float [scene n] by original index, added to (no
  *                gradient for primitives of zero density)
- * p->nrc_mode must be 0 (UGP_ERR_UNSUPPORTED); other arguments and errors as
- * ugp_render_albedo_grad; every material is supported. */
+ * p->nrc_mode and p->transport must be 0 (UGP_ERR_UNSUPPORTED); other
+ * arguments and errors as ugp_render_albedo_grad; every material is
+ * supported. */
 ugp_status ugp_render_density_grad(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p,
                                    const float *d_image, float *grad_density, float *sum_rgb);
 

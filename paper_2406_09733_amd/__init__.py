@@ -60,7 +60,7 @@ class _Params(C.Structure):
                 ("nrc_mode", C.c_int32), ("nrc_terminate_after", C.c_int32),
                 ("nrc_train_records", C.c_int32), ("nrc_lr", C.c_float), ("nrc_box", C.c_float * 6),
                 ("nrc_train_steps", C.c_int32), ("nrc_radiance_scale", C.c_float),
-                ("nrc_target_clamp", C.c_float)]
+                ("nrc_target_clamp", C.c_float), ("transport", C.c_int32)]
 
 
 class _Stats(C.Structure):
@@ -174,6 +174,7 @@ def _render_params(params: dict):
     p.nrc_train_steps = int(params.get("nrc_train_steps", 1))
     p.nrc_radiance_scale = float(params.get("nrc_radiance_scale", 0.0))
     p.nrc_target_clamp = float(params.get("nrc_target_clamp", 0.0))
+    p.transport = int(params.get("transport", 0))
     return p
 
 

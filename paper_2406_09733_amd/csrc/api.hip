@@ -82,7 +82,10 @@ ugp_status render_args(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_para
     if (!(p->nrc_target_clamp >= 0.f) || !std::isfinite(p->nrc_target_clamp)) return UGP_ERR_INVALID_ARGUMENT;
     for (int k = 0; k < 6; ++k)
         if (!std::isfinite(p->nrc_box[k])) return UGP_ERR_INVALID_ARGUMENT;
+    if (p->transport < 0 || p->transport > 1) return UGP_ERR_INVALID_ARGUMENT;
     if (ctx->scene.n == 0) return UGP_ERR_NO_SCENE;
+    // the exponential variant is rendered without the radiance cache
+    if (p->transport == 1 && p->nrc_mode != 0) return UGP_ERR_UNSUPPORTED;
     return UGP_OK;
 }
 
@@ -270,8 +273,10 @@ ugp_status ugp_render_grads(ugp_ctx ctx, const ugp_camera *cam, const ugp_render
     if (!d_image || !(grad_albedo || grad_roughness || grad_density)) return UGP_ERR_INVALID_ARGUMENT;
     const ugp_status s = render_args(ctx, cam, p);
     if (s != UGP_OK) return s;
-    // the radiance cache is refused by every adjoint, material 3 by the shading ones
-    if (p->nrc_mode != 0 || ((grad_albedo || grad_roughness) && ctx->scene.has_mat3)) return UGP_ERR_UNSUPPORTED;
+    // the radiance cache and the exponential variant are refused by every
+    // adjoint, material 3 by the shading ones
+    if (p->nrc_mode != 0 || p->transport != 0 || ((grad_albedo || grad_roughness) && ctx->scene.has_mat3))
+        return UGP_ERR_UNSUPPORTED;
     DeviceGuard g(ctx->device);
     ugp::RenderAdjoint adj{d_image};
     adj.grad_albedo = grad_albedo;

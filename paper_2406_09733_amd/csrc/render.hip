@@ -194,6 +194,7 @@ struct PassArgs {
     int mis_mode;
     float env[3];
     int has_env;
+    int transport;           // 0 linear transmittance, 1 the exponential variant
     NrcArgs nrc;
     AdjArgs adj;
 };
@@ -622,7 +623,9 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
                             }
                         }
                         out.na = make_float4(x.x, x.y, x.z, __int_as_float(e));
-                        out.nb = make_float4(wl.x, wl.y, wl.z, __int_as_float(k));
+                        // the linear model skips k on the light ray; the exponential
+                        // variant skips nothing and keys the ray's draws by the vertex
+                        out.nb = make_float4(wl.x, wl.y, wl.z, __int_as_float(P.transport ? v : k));
                         out.nc = make_float4(wt.x, wt.y, wt.z, __int_as_float(pix));
                     }
                 }
@@ -650,11 +653,13 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
                         }
                     }
                     out.ea = make_float4(x.x, x.y, x.z, 0.f);
-                    out.eb = make_float4(wl.x, wl.y, wl.z, __int_as_float(k));
+                    out.eb = make_float4(wl.x, wl.y, wl.z, __int_as_float(P.transport ? -1 : k));
                     out.ec = make_float4(wt.x, wt.y, wt.z, __int_as_float(pix));
                 }
             }
-            // continue by phase sampling from the chord centre, skipping k
+            // continue by phase sampling from the collision point, skipping k in
+            // the linear model (an exponential medium scatters inside the
+            // Gaussian, whose rest still attenuates)
             V3 wgt, wil, wi;
             float pdf;
             if (mat == 2) {
@@ -684,7 +689,7 @@ __device__ __forceinline__ void shade_one(const SceneDev &S, const PassArgs &P, 
                         }
                     }
                     out.ca = make_float4(x.x, x.y, x.z, pdf);
-                    out.cb = make_float4(wi.x, wi.y, wi.z, __int_as_float(k));
+                    out.cb = make_float4(wi.x, wi.y, wi.z, __int_as_float(P.transport ? -1 : k));
                     out.cc = make_float4(beta.x, beta.y, beta.z, __int_as_float(pbits));
                 }
             }
@@ -823,6 +828,85 @@ __global__ __launch_bounds__(kBlock) void k_env(SceneDev S, LightQueue q, const 
         const float F = transmittance_F(S, r, excl, true, stack, err, tc);
         const float T = fmaxf(0.f, 1.f - F);
         if (T > 0.f) collect(adj, L, pix, C.x, C.y, C.z, T, 2);
+    }
+    flush_counts(S, tc);
+}
+
+// ---------------------------------------------------------------------------
+// The exponential variant (App. D) as a render mode, for the paper's comparison
+// of transmittance models: a path's next collision and its light samples are
+// drawn by analog decomposition tracking (exp_track), with the uniform of
+// Gaussian k at vertex v from the path's generator, group 16 + 2k (collision)
+// or 17 + 2k (light sample); environment samples take T = exp(-depth).  One
+// ray per lane (no windowed sweep is needed).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_collide_exp(SceneDev S, PassArgs P, Queue qin, const int32_t *n_in,
+                                                        const int32_t *order, int2 *hits, int64_t *stats,
+                                                        uint32_t *err) {
+    __shared__ int stack[kStackSize * kBlock];
+    const int n = *n_in;
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd((unsigned long long *)&stats[0], (unsigned long long)n);
+    TraceCount tc;
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = order ? (int64_t)order[j] : j;
+        const float4 A = qin.a[i], B = qin.b[i], C = qin.c[i];
+        const uint32_t pix = (uint32_t)(__float_as_int(C.w) & kPixMask), v = (uint32_t)qin.v[i];
+        const RayD r = make_ray(A.x, A.y, A.z, B.x, B.y, B.z, 0.f, __builtin_huge_val());
+        double t;
+        const int k = exp_track(
+            S, r, __float_as_int(B.w),
+            [&](int q) __attribute__((always_inline)) {
+                return (double)path_rng(P, pix, v, 16u + 2u * (uint32_t)q).u[0];
+            },
+            stack, err, tc, t);
+        hits[i] = make_int2(k, __float_as_int(k >= 0 ? (float)t : 0.f));
+    }
+    flush_counts(S, tc);
+}
+
+// light samples: one decomposition-tracking draw along the segment to the
+// target's chord exit scores the sample if the target is hit first (an
+// unbiased estimate of the probability that it is)
+__global__ __launch_bounds__(kBlock) void k_light_exp(SceneDev S, PassArgs P, LightQueue q, const int32_t *n_in,
+                                                      const int32_t *order, float4 *L, int64_t *stats,
+                                                      uint32_t *err) {
+    __shared__ int stack[kStackSize * kBlock];
+    const int n = *n_in;
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd((unsigned long long *)&stats[1], (unsigned long long)n);
+    TraceCount tc;
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = order ? (int64_t)order[j] : j;
+        const float4 A = q.a[i], B = q.b[i];
+        const int target = __float_as_int(A.w);
+        RayD r = make_ray(A.x, A.y, A.z, B.x, B.y, B.z, 0.f, __builtin_huge_val());
+        Chord c;
+        if (!chord(load_hot(S.hot, S.inv[target]), r, S.r2, c)) continue;
+        r.t1 = c.bd;
+        const float4 C = q.c[i];
+        const uint32_t pix = (uint32_t)__float_as_int(C.w), v = (uint32_t)__float_as_int(B.w);
+        double t;
+        const int k = exp_track(
+            S, r, -1,
+            [&](int p) __attribute__((always_inline)) {
+                return (double)path_rng(P, pix, v, 17u + 2u * (uint32_t)p).u[0];
+            },
+            stack, err, tc, t);
+        if (k == target) collect(P.adj, L, (int)pix, C.x, C.y, C.z, 1.f, 1);
+    }
+    flush_counts(S, tc);
+}
+
+__global__ __launch_bounds__(kBlock) void k_env_exp(SceneDev S, PassArgs P, LightQueue q, const int32_t *n_in,
+                                                    float4 *L, int64_t *stats, uint32_t *err) {
+    __shared__ int stack[kStackSize * kBlock];
+    const int n = *n_in;
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd((unsigned long long *)&stats[2], (unsigned long long)n);
+    TraceCount tc;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const float4 A = q.a[i], B = q.b[i], C = q.c[i];
+        const RayD r = make_ray(A.x, A.y, A.z, B.x, B.y, B.z, 0.f, __builtin_huge_val());
+        const float T = expf(-exp_depth(S, r, __float_as_int(B.w), stack, err, tc));
+        if (T > 0.f) collect(P.adj, L, __float_as_int(C.w), C.x, C.y, C.z, T, 2);
     }
     flush_counts(S, tc);
 }
@@ -1460,6 +1544,7 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
     P.mis_mode = p->mis_mode;
     P.env[0] = p->env_radiance[0]; P.env[1] = p->env_radiance[1]; P.env[2] = p->env_radiance[2];
     P.has_env = (P.env[0] > 0.f || P.env[1] > 0.f || P.env[2] > 0.f) ? 1 : 0;
+    P.transport = p->transport;
     int32_t *chunk_cnt = rb->counts + kChunkBlock;  // [0] paths generated, [1] records appended
     // radiance cache: modes 1 and 2 need the network; records only in mode 1
     P.nrc = NrcArgs{p->nrc_mode, p->nrc_terminate_after, nullptr, nullptr, 0, nullptr, nullptr, nullptr};
@@ -1564,7 +1649,7 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
                                    P, pool, total, (const int32_t *)c, (const int32_t *)chunk_cnt, qin, rb->L);
                 hipLaunchKernelGGL(k_regen_commit, dim3(1), dim3(1), 0, st, pool, total, c, cn, chunk_cnt);
                 P.nrc.n_qry = c + ctr(6);
-                if (!adj && it > 0 && n_new == 0 && n_it <= ctx->tail_paths) {
+                if (!adj && !P.transport && it > 0 && n_new == 0 && n_it <= ctx->tail_paths) {
                     // few paths left and none to generate: they run to the end in one kernel
                     timed(8, [&] {
                         hipLaunchKernelGGL(k_tail, dim3((unsigned)std::max<int64_t>(1, (n_it + 31) / 32)),
@@ -1589,14 +1674,23 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
                                            rb->skey, rb->sval);
                         radix_sort(rb->skey, rb->sval, rb->skey2, rb->sval2, n_it, st);
                     });
-                timed(0, [&] {
-                    hipLaunchKernelGGL((k_collide<kEventsMain, false>), dim3(gq), dim3(kBlock), 0, st, Sc[0], P, qin,
-                                       (const int32_t *)c, order, c + ctr(4), rb->hits, ctx->stats, ov, ctx->err);
-                });
-                timed(1, [&] {
-                    hipLaunchKernelGGL((k_collide<kEventsWide, true>), dim3(gw), dim3(kBlock), 0, st, Sc[1], P, qin,
-                                       (const int32_t *)c, order, c + ctr(4), rb->hits, ctx->stats, ov, ctx->err);
-                });
+                if (P.transport) {
+                    timed(0, [&] {
+                        hipLaunchKernelGGL(k_collide_exp, dim3(gq), dim3(kBlock), 0, st, Sc[0], P, qin,
+                                           (const int32_t *)c, order, rb->hits, ctx->stats, ctx->err);
+                    });
+                } else {
+                    timed(0, [&] {
+                        hipLaunchKernelGGL((k_collide<kEventsMain, false>), dim3(gq), dim3(kBlock), 0, st, Sc[0], P,
+                                           qin, (const int32_t *)c, order, c + ctr(4), rb->hits, ctx->stats, ov,
+                                           ctx->err);
+                    });
+                    timed(1, [&] {
+                        hipLaunchKernelGGL((k_collide<kEventsWide, true>), dim3(gw), dim3(kBlock), 0, st, Sc[1], P,
+                                           qin, (const int32_t *)c, order, c + ctr(4), rb->hits, ctx->stats, ov,
+                                           ctx->err);
+                    });
+                }
                 if (P.adj.dimg && P.adj.grad_dens != nullptr) {
                     // t_sat of the collisions by the persistent saturation query
                     hipLaunchKernelGGL(k_dens_rays, dim3(gn), dim3(256), 0, st, P, qin, (const int32_t *)c, n_it,
@@ -1621,6 +1715,12 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
                                                n_it, rb->skey, rb->sval);
                             radix_sort(rb->skey, rb->sval, rb->skey2, rb->sval2, n_it, st);
                         });
+                    if (P.transport)
+                        timed(2, [&] {
+                            hipLaunchKernelGGL(k_light_exp, dim3(gq), dim3(kBlock), 0, st, Sc[2], P, rb->nee,
+                                               (const int32_t *)(c + ctr(1)), order, rb->L, ctx->stats, ctx->err);
+                        });
+                    else
                     timed(2, [&] {
                         hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, st, c + ctr(3), 0);
                         hipLaunchKernelGGL((k_light<kEventsMain, false>), dim3(gq), dim3(kBlock), 0, st, Sc[2], rb->nee,
@@ -1643,8 +1743,12 @@ hipError_t render(ugp_ctx ctx, const ugp_camera *cam, const ugp_render_params *p
                 }
                 if (P.has_env && p->mis_mode != 1)
                     timed(3, [&] {
-                        hipLaunchKernelGGL(k_env, dim3(gq), dim3(kBlock), 0, st, Sc[3], rb->env,
-                                           (const int32_t *)(c + ctr(2)), rb->L, ctx->stats, P.adj, ctx->err);
+                        if (P.transport)
+                            hipLaunchKernelGGL(k_env_exp, dim3(gq), dim3(kBlock), 0, st, Sc[3], P, rb->env,
+                                               (const int32_t *)(c + ctr(2)), rb->L, ctx->stats, ctx->err);
+                        else
+                            hipLaunchKernelGGL(k_env, dim3(gq), dim3(kBlock), 0, st, Sc[3], rb->env,
+                                               (const int32_t *)(c + ctr(2)), rb->L, ctx->stats, P.adj, ctx->err);
                     });
                 if (P.has_env && p->mis_mode != 1 && P.adj.dimg && P.adj.grad_dens != nullptr)
                     hipLaunchKernelGGL(k_dens_env, dim3(gq), dim3(kBlock), 0, st, S, rb->env, (const int32_t *)(c + ctr(2)),

@@ -29,10 +29,8 @@ __global__ __launch_bounds__(kBlock) void k_transmittance(SceneDev S, int64_t n,
 }
 
 // ---------------------------------------------------------------------------
-// Exponential variant (App. D; eq. exp_ff): the same Gaussians as an
-// exponential medium with sigma_t = sum_k G_k.  Optical depth of a ray: the
-// sum of the ray integrals I_k = pref [erf tau_b - erf tau_a] of the clipped
-// chords (the full integral; the linear model's free-flight weight is half).
+// Exponential variant (App. D; eq. exp_ff), per ray: T = exp(-depth) and
+// decomposition tracking (exp_depth, exp_track).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_exp_transmittance(SceneDev S, int64_t n, const float *rays,
                                                               const int32_t *excl, float *T, uint32_t *err) {
@@ -44,34 +42,12 @@ __global__ __launch_bounds__(kBlock) void k_exp_transmittance(SceneDev S, int64_
         T[i] = __builtin_nanf("");
         return;
     }
-    const int ex = excl ? excl[i] : -1;
-    const float hi = r.t1 < 3.0e38 ? (float)r.t1 : kInf;
     TraceCount tc;
-    int spill[kStackSpill];
-    TravState ts;
-    trav_begin(ts, S);
-    float depth = 0.f;
-    traverse(S, r, r.t0, [&]() __attribute__((always_inline)) { return hi; }, stack, spill, ts, 0, err, tc,
-             [&](int p) __attribute__((always_inline)) {
-                 const HotRec h = load_hot(S.hot, p);
-                 return h.orig != ex && !surely_missed(h, r, S.r2);
-             },
-             [&](int p) __attribute__((always_inline)) {
-                 const HotRec h = load_hot(S.hot, p);
-                 Chord c;
-                 if (chord(h, r, S.r2, c, true) && c.own) depth += 2.f * c.W;
-                 return false;
-             });
-    T[i] = expf(-depth);
+    T[i] = expf(-exp_depth(S, r, excl ? excl[i] : -1, stack, err, tc));
 }
 
-// Analog decomposition tracking (App. D, after Kutz et al. 2017): each
-// Gaussian the ray meets draws y_k = -ln(1 - u_k) (u_k: Philox4x32-10 with
-// counter (ray index, k, 0) and key seed; top 24 bits of the first word) and
-// collides where its optical depth from the chord entry reaches y_k, if it
-// does before the chord exit; the nearest such point wins.  The inverse of
-// the erf closed form is taken in FP64, through erfc in the tails.  The
-// traversal is cut at the nearest collision found so far.
+// the uniform of Gaussian k on ray i: Philox4x32-10 with counter (ray index,
+// k, 0) and key seed; top 24 bits of the first word
 __device__ __forceinline__ double exp_uniform(uint64_t seed, int64_t i, int k) {
     const uint4 x = philox4x32_10(make_uint4((uint32_t)i, (uint32_t)((uint64_t)i >> 32), (uint32_t)k, 0u),
                                   (uint32_t)seed, (uint32_t)(seed >> 32));
@@ -90,46 +66,13 @@ __global__ __launch_bounds__(kBlock) void k_exp_sample(SceneDev S, int64_t n, co
         t_out[i] = __builtin_nanf("");
         return;
     }
-    const int ex = excl ? excl[i] : -1;
-    const float t1f = r.t1 < 3.0e38 ? (float)r.t1 : kInf;
     TraceCount tc;
-    int spill[kStackSpill];
-    TravState ts;
-    trav_begin(ts, S);
-    double best = __builtin_huge_val();
-    int bk = -1;
-    traverse(S, r, r.t0, [&]() __attribute__((always_inline)) { return fminf(t1f, (float)best); }, stack, spill,
-             ts, 0, err, tc,
-             [&](int p) __attribute__((always_inline)) {
-                 const HotRec h = load_hot(S.hot, p);
-                 return h.orig != ex && !surely_missed(h, r, S.r2);
-             },
-             [&](int p) __attribute__((always_inline)) {
-                 const HotRec h = load_hot(S.hot, p);
-                 Chord c;
-                 if (!chord(h, r, S.r2, c, true) || !c.own || !((double)c.a < best)) return false;
-                 const double y = -log1p(-exp_uniform(seed, i, h.orig));
-                 const double pref = c.pref, ta = c.ta, tb = c.tb;
-                 // I(a, t) = pref [erf tau(t) - erf ta]; collide if y < I(a, b)
-                 double tau;
-                 if (ta >= 0.0) {
-                     const double q = erfc(ta) - y / pref;  // erfc tau
-                     if (!(q > erfc(tb))) return false;
-                     tau = erfcinv(q);
-                 } else {
-                     const double e = erf(ta) + y / pref;   // erf tau
-                     if (!(e < erf(tb))) return false;
-                     tau = e <= 0.0 ? -erfcinv(1.0 + e) : erfcinv(1.0 - e);
-                 }
-                 const double t = c.tc + tau / (double)c.s;
-                 if (t < best) {
-                     best = t;
-                     bk = h.orig;
-                 }
-                 return false;
-             });
+    double t;
+    const int bk = exp_track(S, r, excl ? excl[i] : -1,
+                             [&](int k) __attribute__((always_inline)) { return exp_uniform(seed, i, k); }, stack,
+                             err, tc, t);
     prim_out[i] = bk;
-    t_out[i] = bk >= 0 ? (float)best : __builtin_nanf("");
+    t_out[i] = bk >= 0 ? (float)t : __builtin_nanf("");
 }
 
 // Test hook of the ray integral (Sec. 4.1 eq. ray_integral, App. A): the

@@ -451,6 +451,85 @@ __device__ inline float transmittance_F(const SceneDev &S, const RayD &r, int ex
 }
 
 // ---------------------------------------------------------------------------
+// Exponential variant (App. D; eq. exp_ff): the same Gaussians read as a
+// heterogeneous exponential medium with sigma_t = sum_k G_k.
+//
+// Optical depth of a ray: the sum of the ray integrals I_k = pref [erf tau_b -
+// erf tau_a] of the clipped chords (the full integral; the linear model's
+// free-flight weight is half of it).
+// ---------------------------------------------------------------------------
+__device__ inline float exp_depth(const SceneDev &S, const RayD &r, int excl, int *stack, uint32_t *err,
+                                  TraceCount &tc) {
+    const float hi = r.t1 < 3.0e38 ? (float)r.t1 : kInf;
+    int spill[kStackSpill];
+    TravState ts;
+    trav_begin(ts, S);
+    float depth = 0.f;
+    traverse(S, r, r.t0, [&]() __attribute__((always_inline)) { return hi; }, stack, spill, ts, 0, err, tc,
+             [&](int p) __attribute__((always_inline)) {
+                 const HotRec h = load_hot(S.hot, p);
+                 return h.orig != excl && !surely_missed(h, r, S.r2);
+             },
+             [&](int p) __attribute__((always_inline)) {
+                 const HotRec h = load_hot(S.hot, p);
+                 Chord c;
+                 if (chord(h, r, S.r2, c, true) && c.own) depth += 2.f * c.W;
+                 return false;
+             });
+    return depth;
+}
+
+// Analog decomposition tracking (App. D, after Kutz et al. 2017): each
+// Gaussian k the ray meets draws y_k = -ln(1 - u_k) (u_k = uni(k), k the
+// original index) and collides where its optical depth from the chord entry
+// reaches y_k, if it does before the chord exit; the nearest such point wins.
+// The inverse of the erf closed form is taken in FP64, through erfc in the
+// tails.  The traversal is cut at the nearest collision found so far.
+// Returns the original index (or -1, escape) and its distance in t.
+template <class UniFn>
+__device__ inline int exp_track(const SceneDev &S, const RayD &r, int excl, UniFn &&uni, int *stack, uint32_t *err,
+                                TraceCount &tc, double &t) {
+    const float t1f = r.t1 < 3.0e38 ? (float)r.t1 : kInf;
+    int spill[kStackSpill];
+    TravState ts;
+    trav_begin(ts, S);
+    double best = __builtin_huge_val();
+    int bk = -1;
+    traverse(S, r, r.t0, [&]() __attribute__((always_inline)) { return fminf(t1f, (float)best); }, stack, spill,
+             ts, 0, err, tc,
+             [&](int p) __attribute__((always_inline)) {
+                 const HotRec h = load_hot(S.hot, p);
+                 return h.orig != excl && !surely_missed(h, r, S.r2);
+             },
+             [&](int p) __attribute__((always_inline)) {
+                 const HotRec h = load_hot(S.hot, p);
+                 Chord c;
+                 if (!chord(h, r, S.r2, c, true) || !c.own || !((double)c.a < best)) return false;
+                 const double y = -log1p(-uni(h.orig));
+                 const double pref = c.pref, ta = c.ta, tb = c.tb;
+                 // I(a, t) = pref [erf tau(t) - erf ta]; collide if y < I(a, b)
+                 double tau;
+                 if (ta >= 0.0) {
+                     const double q = erfc(ta) - y / pref;  // erfc tau
+                     if (!(q > erfc(tb))) return false;
+                     tau = erfcinv(q);
+                 } else {
+                     const double e = erf(ta) + y / pref;   // erf tau
+                     if (!(e < erf(tb))) return false;
+                     tau = e <= 0.0 ? -erfcinv(1.0 + e) : erfcinv(1.0 - e);
+                 }
+                 const double tk = c.tc + tau / (double)c.s;
+                 if (tk < best) {
+                     best = tk;
+                     bk = h.orig;
+                 }
+                 return false;
+             });
+    t = best;
+    return bk;
+}
+
+// ---------------------------------------------------------------------------
 // Ordered sweep: primitive-level free-flight sampling (Sec. 5.2), the
 // saturating distance and the emitter query.
 //
