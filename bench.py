@@ -5,7 +5,8 @@ one MI355X, reported as traversal queries per second (Mrays/s).
 One step = one sample pass over the whole hot path: camera rays for every
 pixel of the 1920x1080 image, then per vertex (max depth 12) primitive-level
 free-flight sampling, emission pick-up, next-event estimation (emitter query
-along a sampled cone direction) and phase sampling, then accumulation.  A
+toward a point drawn from the emitter's Gaussian) and phase sampling, then
+accumulation.  A
 "ray" is one traversal query (collision, emitter or environment query).
 
 The scene, camera and seeds are synthetic and fixed (see
@@ -41,6 +42,11 @@ cache trains online, 16 Adam steps per render call of 128 samples per pixel)
 against a 4096-spp plain reference, RMSE over all pixels and channels of the
 images clamped to [0, 1] with the reference's own noise removed, against
 wall time.  It prints one JSON line of its own (see time_to_rmse).
+
+Other modes, each printing one JSON line of its own: --queries (per-ray query
+rates), --sggx (SGGX phase functions), --transport (the linear model against
+its exponential variant as renders), --fit, --radiance-fit, --shading-fit,
+--rf and --albedo-grad (differentiation).
 """
 from __future__ import annotations
 
@@ -678,6 +684,51 @@ def sggx_bench(args):
     print(json.dumps(res), flush=True)
 
 
+def transport_bench(args):
+    """The paper's comparison of transmittance models as renders: the 100K
+    mixed scene (512x512, 16 spp, depth 8) and the room (480x270, 4 spp,
+    depth 12) rendered with the linear model and with its exponential
+    variant (decomposition tracking, App. D).  One JSON line: ms per frame,
+    Mrays/s, collision and light-sample kernel times and the image mean per
+    scene and model (kernel times from HIP events)."""
+    import torch
+
+    import paper_2406_09733_amd as P
+    from paper_2406_09733_amd import scenes
+
+    ctx = P.Context(0)
+    out = {}
+    for name, sc, cam, rp in (
+            ("mixed_100k", scenes.mixed_100k(), dict(scenes.camera("mixed_100k"), width=512, height=512),
+             {"spp": 16, "max_depth": 8, "seed": 1, "env_radiance": (0.2, 0.2, 0.2)}),
+            ("room_5p5m", scenes.room_5p5m(), dict(scenes.camera("room_5p5m"), width=480, height=270),
+             {"spp": 4, "max_depth": 12, "seed": 1})):
+        ctx.build_bvh(sc)
+        for tr, model in ((0, "linear"), (1, "exponential")):
+            p = dict(rp, transport=tr)
+            ctx.set_profiling(0)
+            ctx.render(cam, dict(p, spp=1, sample_offset=1000))
+            ctx.sync()
+            ctx.set_profiling(1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s, _ = ctx.render(cam, p)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            st = ctx.render_stats()
+            ctx.set_profiling(0)
+            r = {"ms_per_frame": round(1e3 * dt, 2), "mrays_per_s": round(st["rays"] / dt / 1e6, 1),
+                 "collide_ms": round(st["ms_collide"] + st["ms_collide_wide"] + st["ms_tail"], 2),
+                 "light_ms": round(st["ms_light"], 2), "rays_per_path": round(st["rays"] / max(st["paths"], 1), 3),
+                 "image_mean": round(float(s.mean()) / p["spp"], 5)}
+            out[f"{name}_{model}"] = r
+            log(f"[bench] {name} {model}: {json.dumps(r)}")
+    res = {"metric": "path tracing under the linear model and its exponential variant (App. D)",
+           "value": out["room_5p5m_exponential"]["mrays_per_s"], "unit": "Mrays/s", "higher_is_better": True,
+           "runs": out}
+    print(json.dumps(res), flush=True)
+
+
 def query_bench(args):
     """Per-ray query rates on the room (5.5M primitives): linear-model
     transmittance and free-flight sampling (the ordered sweep) against the
@@ -753,6 +804,8 @@ def main():
     ap.add_argument("--queries", action="store_true", help="run the per-ray query benchmark instead")
     ap.add_argument("--albedo-grad", action="store_true", help="run the albedo-adjoint benchmark instead")
     ap.add_argument("--sggx", action="store_true", help="run the SGGX phase-function benchmark instead")
+    ap.add_argument("--transport", action="store_true",
+                    help="render two scenes under the linear model and its exponential variant instead")
     ap.add_argument("--radiance-fit", action="store_true",
                     help="run the differentiable-fitting benchmark (200K primitives, 8 views) instead")
     ap.add_argument("--fit-steps-geometry", type=int, default=50, help="geometry (transmittance) steps")
@@ -792,6 +845,9 @@ def main():
         return
     if args.albedo_grad:
         albedo_grad_bench(args)
+        return
+    if args.transport:
+        transport_bench(args)
         return
     if args.sggx:
         sggx_bench(args)
