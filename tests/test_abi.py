@@ -70,3 +70,32 @@ def test_create_without_gpu_reports_device_error(L):
         pytest.skip("a GPU is present")
     h = C.c_void_p()
     assert L.ugp_create(0, None, C.byref(h)) == 3
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    # every struct the binding passes by pointer has the header's field names,
+    # offsets and size (a C program built against include/ugp.h prints them)
+    import shutil
+    import subprocess
+    import paper_2406_09733_amd as P
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"ugp_scene": P._Scene, "ugp_camera": P._Camera, "ugp_render_params": P._Params,
+               "ugp_render_stats": P._Stats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ugp.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == C.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)

@@ -43,3 +43,34 @@ def test_philox_batch_equals_single_calls(orc):
     got = orc.philox4x32_10(c, [5, 9])
     for i in (0, 1, 100, 256):
         assert got[i].tolist() == orc.philox4x32_10(c[i], [5, 9]).tolist()
+
+
+def test_oracle_binding_structs_match_its_header(tmp_path):
+    # the oracle's camera and render parameters as the binding lays them out
+    # equal the C header's (a C program built against oracle/ugp_oracle.h)
+    import ctypes as C
+    import os
+    import shutil
+    import subprocess
+    import oracle as O
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    structs = {"orc_camera": O._Camera, "orc_render_params": O._Params}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ugp_oracle.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(root, "oracle"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == C.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
