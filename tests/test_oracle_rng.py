@@ -2,6 +2,7 @@
 import os
 
 import numpy as np
+import pytest
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
 
@@ -49,7 +50,6 @@ def test_oracle_binding_structs_match_its_header(tmp_path):
     # the oracle's camera and render parameters as the binding lays them out
     # equal the C header's (a C program built against oracle/ugp_oracle.h)
     import ctypes as C
-    import os
     import shutil
     import subprocess
     import oracle as O
