@@ -209,6 +209,20 @@ def test_room_render_parity_sampled(room):
     assert m_ref.mean() > 0
 
 
+def test_room_exp_render_parity_sampled(room):
+    # the exponential variant as a render mode (decomposition tracking) on the
+    # benchmark's workload: 1920x1080, 64 spp, depth 12, 400 sampled pixels
+    sc, ctx, S = room
+    _say("room exponential render parity: 1920x1080, 64 spp, depth 12, 400 sampled pixels")
+    cam = scenes.camera("room_5p5m")
+    rs = scenes.render_settings("room_5p5m")
+    p = {"spp": rs["spp"], "max_depth": rs["max_depth"], "seed": rs["seed"] + 1, "transport": 1}
+    m, m_ref, frac, gse = _sampled(ctx, S, cam, p, _pixels(33))
+    assert frac <= 0.01
+    assert abs(m.mean() - m_ref.mean()) <= 3 * gse + 1e-6
+    assert m_ref.mean() > 0
+
+
 def test_room_cached_render_parity_sampled(room):
     # paths end in a fixed (random-weight) cache after two scattering events;
     # the output layer is scaled by 512 (exact in bf16) so that the cache
