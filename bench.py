@@ -824,9 +824,8 @@ def main():
                     help="Adam rates of the means, log scales, rotations and densities")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path shards by "
-              "pixels with no communication beyond a final image reduction; see DESIGN.md)",
-              file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path would shard by "
+              "pixels, with no communication beyond a final image reduction)", file=sys.stderr)
         sys.exit(2)
     if args.copy_probe:
         copy_probe(args.copy_probe)

@@ -1,7 +1,7 @@
 """GPU parity: libugp (FP32 kernels, FP64 ray-frame transform) against the FP64
 CPU oracle on identical seeded inputs, through the C ABI.
 
-Tolerances ("Parity bar"):
+Tolerances:
   T                    |dT| <= 1e-5
   F, I, emitter factor |dx| <= 1e-5 max(|x|, 1e-3) + 5e-7   (5e-7 = 4 ulp of 1.0 in
                        float32: these are float sums / differences of erf values of
