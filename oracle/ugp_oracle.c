@@ -1549,9 +1549,12 @@ void orc_camera_rays(const orc_camera *cam, uint64_t seed, uint32_t sample, floa
     }
 }
 
-/* Radiance of one camera path (vertex v = 1, 2, ...: collide, pick up
- * emission, stop after max_depth scattering events, else NEE and phase
- * sampling). */
+/* Radiance of one camera path (Sec. 5 table tab:highlevel, eq. rte; vertex
+ * v = 1, 2, ...: collide, pick up emission, stop after max_depth scattering
+ * events, else NEE and phase sampling).  transport 1 runs the same loop in
+ * the exponential variant (App. D): decomposition tracking for collisions and
+ * light samples, exp(-sum I_k) for environment samples, no primitive skipped
+ * after a scatter. */
 static void trace_path(const orc_scene *S, const orc_render_params *P, const orc_camera *cam,
                        uint32_t pix, uint32_t sample, hitvec *H, hitvec *H2, double L[3],
                        int64_t *rays, double *rec, int max_rec, int *n_rec) {
