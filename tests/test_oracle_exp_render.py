@@ -136,3 +136,19 @@ def test_exp_and_linear_models_differ(orc):
     me, se_e = _mean_radiance(S, dict(EXP, spp=1, max_depth=0, seed=5), 3000)
     ml, se_l = _mean_radiance(S, dict(spp=1, max_depth=0, seed=5), 3000)
     assert np.all(np.abs(me - ml) > 5 * np.hypot(se_e, se_l))
+
+
+def test_exp_scatter_keeps_the_gaussian(orc):
+    # one dense Gaussian of albedo 1 in a unit environment, one scattering
+    # event, phase sampling only: the linear model skips the primitive after
+    # its scatter, so every path escapes carrying exactly 1; the exponential
+    # variant scatters inside the Gaussian, whose rest still attenuates the
+    # second flight, so some paths end there and the mean falls below 1
+    sc = _prims([[0.5, 0.52, 0.5]], [[0.2, 0.2, 0.2]], [[1, 0, 0, 0]], [6.0], [[0, 0, 0]])
+    sc["albedo"][:] = 1.0
+    S = orc.Scene(sc)
+    p = {"spp": 1, "max_depth": 1, "seed": 8, "env_radiance": (1, 1, 1), "mis_mode": 1}
+    lin = np.array([S.path_radiance(_PIN, p, 0, i) for i in range(400)])
+    assert np.allclose(lin, 1.0, rtol=0, atol=1e-12)
+    m, se = _mean_radiance(S, dict(EXP, **p), 3000)
+    assert np.all(m < 1.0 - 10 * se), (m, se)
